@@ -1,0 +1,650 @@
+/*
+ * ckc_oracle.c — the reference checker for index programs.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * compared against; it is used by the tests, by the smoke check and by the
+ * benchmark's CPU-baseline leg, and by nothing else.  It shares no code,
+ * header, table or helper with the library: it decodes the IR bytes itself and
+ * defines its own constants.
+ *
+ * What it computes is the plain definition of the result the paper's fuzzing
+ * pipeline produces for one kernel launch under AddressSanitizer and AFL++
+ * coverage (Section 4: the kernel is translated so that every GPU thread runs
+ * on the CPU and every memory access is checked; Section 2.1: a coverage map
+ * is filled while the program runs):
+ *
+ *   for every input, in order
+ *     for every thread of the chosen thread set, in global-thread-id order
+ *       run the program sequentially, check every access against the
+ *       allocation it names, count every site visit.
+ *
+ * The thread sets are the whole grid (what the paper runs for kernels that
+ * are not affine-access, Section 5.1), the corner threads of the PREX Theorem
+ * (Section 5.1.1), the boundary-blocks-plus-one-interior set, and the block
+ * order of the PREX runtime algorithm (Section 5.1.2, Algorithm 1).
+ *
+ * Readings where the paper is silent (each one is listed with its reason in
+ * the design notes of the repository):
+ *   - bounds are exact per allocation (the paper contrasts redzone tripwires
+ *     with base-and-bounds checking in Section 7.1); a violation is recorded
+ *     and execution continues (record-and-continue, so that "first violation
+ *     per access" is defined);
+ *   - a violating LOAD reads 0;
+ *   - integer arithmetic wraps at its width; division by zero gives 0 and is
+ *     counted as an arithmetic fault; INT_MIN / -1 = INT_MIN;
+ *   - the first violation of an access is the one with the smallest
+ *     (global thread id, outer iteration, inner iteration), packed into a
+ *     64-bit key;
+ *   - coverage is one saturating (at 255) hit counter per program site,
+ *     the LLVM-PCGuard style the paper fuzzes with (Section 7.1).
+ *
+ * Build: gcc -O2 -shared -fPIC -pthread ckc_oracle.c -o libckc_oracle.so
+ */
+#include <limits.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- IR constants, decoded independently of the library ---------------- */
+enum {
+  O_CONST = 1, O_SCALAR = 2, O_SPECIAL = 3,
+  O_ADD = 8, O_SUB, O_MUL, O_DIVS, O_DIVU, O_REMS, O_REMU, O_AND, O_OR, O_XOR,
+  O_SHL, O_SHRA, O_SHRL, O_MINS, O_MAXS, O_MINU, O_MAXU,
+  O_CMPEQ, O_CMPNE, O_CMPLTS, O_CMPLES, O_CMPLTU, O_CMPLEU,
+  O_SELECT = 31, O_SEXT = 32, O_ZEXT = 33, O_TRUNC = 34,
+  O_ACCESS = 48, O_LOAD = 49,
+  O_IF = 56, O_ELSE = 57, O_ENDIF = 58, O_LOOP = 59, O_ENDLOOP = 60
+};
+#define NOSITE 0xFFFFu
+#define NOREG 0xFFFFu
+
+/* violation kinds */
+#define K_OVER 1u
+#define K_UNDER 2u
+#define K_FREED 4u
+#define K_NULL 8u
+#define A_FREED 1u
+
+/* thread-set modes */
+#define M_FULL 0u
+#define M_CORNERS 1u
+#define M_BOUNDARY 2u
+#define M_PREX 3u
+
+#define E_OK 0
+#define E_INVALID (-1)
+#define E_IR (-2)
+#define E_RANGE (-3)
+
+typedef struct { uint64_t base, size_bytes; const void* data; uint32_t flags, pad; } or_alloc;
+typedef struct { uint64_t first_key; int64_t index; uint64_t count; uint32_t kinds, first_kind; } or_record;
+typedef struct { uint64_t lanes, accesses_checked, hang_lanes, arith_faults; uint32_t flags, pad; } or_status;
+
+typedef struct {
+  uint8_t op, w;
+  uint16_t dst, a, b, c, d, s0, s1;
+  int32_t alt;  /* IF: its ELSE (or -1); */
+  int32_t end;  /* IF/ELSE: its ENDIF; LOOP: its ENDLOOP */
+  int32_t depth; /* loop depth of the instruction itself (LOOP: depth it opens) */
+} or_ins;
+
+typedef struct {
+  int n_instr, n_consts, n_scalars, n_slots, n_accesses, n_sites, n_regs;
+  const int64_t* consts; /* points into a private copy */
+  uint16_t* site_ids;
+  or_ins* ins;
+  int max_depth;
+  uint8_t* load_slot; /* slot used by some LOAD */
+  int64_t* const_copy;
+} or_prog;
+
+static uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+static uint32_t rd32(const uint8_t* p) { return (uint32_t)rd16(p) | ((uint32_t)rd16(p + 2) << 16); }
+static int64_t rd64(const uint8_t* p) { return (int64_t)((uint64_t)rd32(p) | ((uint64_t)rd32(p + 4) << 32)); }
+
+static void prog_free(or_prog* P) {
+  free(P->site_ids); free(P->ins); free(P->load_slot); free(P->const_copy);
+  memset(P, 0, sizeof *P);
+}
+
+static int is_binary(int op) { return op >= O_ADD && op <= O_CMPLEU; }
+
+/* Decode and validate the byte format (include/ckc_ir.h describes it; this is
+ * an independent reading of that description). */
+static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
+  memset(P, 0, sizeof *P);
+  if (!ir || n < 32) return E_IR;
+  if (rd32(ir) != 0x31434B43u || rd16(ir + 4) != 1) return E_IR;
+  P->n_instr = rd16(ir + 6); P->n_consts = rd16(ir + 8); P->n_scalars = rd16(ir + 10);
+  P->n_slots = rd16(ir + 12); P->n_accesses = rd16(ir + 14); P->n_sites = rd16(ir + 16);
+  P->n_regs = rd16(ir + 18);
+  for (int i = 20; i < 32; i++) if (ir[i]) return E_IR;
+  if (P->n_scalars > 16 || P->n_slots > 16 || P->n_accesses > 1024 || P->n_sites > 4096 ||
+      P->n_instr > 4096 || P->n_consts > 4096) return E_IR;
+  size_t site_bytes = ((size_t)P->n_sites * 2 + 7) / 8 * 8;
+  size_t need = 32 + (size_t)P->n_consts * 8 + site_bytes + (size_t)P->n_instr * 16;
+  if (need != n) return E_IR;
+  const uint8_t* pc = ir + 32;
+  P->const_copy = (int64_t*)calloc(P->n_consts + 1, 8);
+  for (int i = 0; i < P->n_consts; i++) P->const_copy[i] = rd64(pc + 8 * i);
+  P->consts = P->const_copy;
+  const uint8_t* ps = pc + 8 * P->n_consts;
+  P->site_ids = (uint16_t*)calloc(P->n_sites + 1, 2);
+  for (int i = 0; i < P->n_sites; i++) P->site_ids[i] = rd16(ps + 2 * i);
+  const uint8_t* pi = ps + site_bytes;
+  P->ins = (or_ins*)calloc(P->n_instr + 1, sizeof(or_ins));
+  P->load_slot = (uint8_t*)calloc(17, 1);
+  for (int i = 0; i < P->n_instr; i++) {
+    const uint8_t* q = pi + 16 * i;
+    or_ins* I = &P->ins[i];
+    I->op = q[0]; I->w = q[1]; I->dst = rd16(q + 2); I->a = rd16(q + 4); I->b = rd16(q + 6);
+    I->c = rd16(q + 8); I->d = rd16(q + 10); I->s0 = rd16(q + 12); I->s1 = rd16(q + 14);
+    I->alt = -1; I->end = -1;
+  }
+
+  /* site ids unique; every site index and access id used at most once */
+  int rc = E_IR;
+  uint8_t* seen_id = (uint8_t*)calloc(65536, 1);
+  uint8_t* site_used = (uint8_t*)calloc(P->n_sites + 1, 1);
+  uint8_t* acc_used = (uint8_t*)calloc(P->n_accesses + 1, 1);
+  int32_t* def_scope = (int32_t*)malloc(sizeof(int32_t) * (P->n_regs + 1));
+  uint8_t* scope_open = (uint8_t*)calloc(P->n_instr + 2, 1);
+  int32_t stack[64]; int sp = 0; int loop_depth = 0; int n_scopes = 1;
+  for (int r = 0; r < P->n_regs; r++) def_scope[r] = -1;
+  for (int i = 0; i < P->n_sites; i++) { if (seen_id[P->site_ids[i]]) goto out; seen_id[P->site_ids[i]] = 1; }
+  scope_open[0] = 1;
+  int32_t scope_stack[64]; int ssp = 0; scope_stack[ssp++] = 0;
+
+#define USE(r) do { if ((r) >= P->n_regs || def_scope[(r)] < 0 || !scope_open[def_scope[(r)]]) goto out; } while (0)
+#define DEF(r) do { if ((r) >= P->n_regs || def_scope[(r)] != -1) goto out; def_scope[(r)] = scope_stack[ssp - 1]; } while (0)
+#define SITE(s) do { if ((s) != NOSITE) { if ((s) >= P->n_sites || site_used[(s)]) goto out; site_used[(s)] = 1; } } while (0)
+#define WIDTH(wv) do { if ((wv) != 32 && (wv) != 64) goto out; } while (0)
+
+  for (int i = 0; i < P->n_instr; i++) {
+    or_ins* I = &P->ins[i];
+    I->depth = loop_depth;
+    switch (I->op) {
+      case O_CONST: WIDTH(I->w); if (I->a >= P->n_consts) goto out; DEF(I->dst); break;
+      case O_SCALAR: WIDTH(I->w); if (I->a >= P->n_scalars) goto out; DEF(I->dst); break;
+      case O_SPECIAL: if (I->a > 11) goto out; DEF(I->dst); break;
+      case O_SELECT: WIDTH(I->w); USE(I->a); USE(I->b); USE(I->c); DEF(I->dst); break;
+      case O_SEXT: case O_ZEXT: case O_TRUNC: USE(I->a); DEF(I->dst); break;
+      case O_ACCESS:
+      case O_LOAD:
+        WIDTH(I->w); USE(I->a);
+        if (I->b >= P->n_accesses || acc_used[I->b]) goto out;
+        acc_used[I->b] = 1;
+        if (I->c >= P->n_slots) goto out;
+        if (I->op == O_ACCESS) { if (I->d > 7) goto out; }
+        else { if (I->d != 2 && I->d != 3) goto out; P->load_slot[I->c] = 1; DEF(I->dst); }
+        SITE(I->s0);
+        break;
+      case O_IF:
+        USE(I->a); SITE(I->s0); SITE(I->s1);
+        if (sp >= 16) goto out;
+        stack[sp++] = i;
+        scope_open[n_scopes] = 1; scope_stack[ssp++] = n_scopes++;
+        break;
+      case O_ELSE:
+        if (sp == 0 || P->ins[stack[sp - 1]].op != O_IF || P->ins[stack[sp - 1]].alt >= 0) goto out;
+        P->ins[stack[sp - 1]].alt = i;
+        scope_open[scope_stack[--ssp]] = 0;
+        scope_open[n_scopes] = 1; scope_stack[ssp++] = n_scopes++;
+        break;
+      case O_ENDIF: {
+        if (sp == 0 || P->ins[stack[sp - 1]].op != O_IF) goto out;
+        int f = stack[--sp];
+        P->ins[f].end = i;
+        if (P->ins[f].alt >= 0) P->ins[P->ins[f].alt].end = i;
+        scope_open[scope_stack[--ssp]] = 0;
+        break;
+      }
+      case O_LOOP:
+        WIDTH(I->w); USE(I->a); USE(I->b); USE(I->c); SITE(I->s0); SITE(I->s1);
+        if (sp >= 16 || loop_depth >= 2) goto out;
+        stack[sp++] = i; loop_depth++;
+        if (loop_depth > P->max_depth) P->max_depth = loop_depth;
+        scope_open[n_scopes] = 1; scope_stack[ssp++] = n_scopes++;
+        DEF(I->dst);
+        break;
+      case O_ENDLOOP: {
+        if (sp == 0 || P->ins[stack[sp - 1]].op != O_LOOP) goto out;
+        int f = stack[--sp];
+        P->ins[f].end = i; I->end = f; loop_depth--;
+        scope_open[scope_stack[--ssp]] = 0;
+        break;
+      }
+      default:
+        if (!is_binary(I->op)) goto out;
+        WIDTH(I->w); USE(I->a); USE(I->b); DEF(I->dst);
+        break;
+    }
+    if (ssp > 60) goto out;
+  }
+  if (sp != 0) goto out;
+  for (int a = 0; a < P->n_accesses; a++) if (!acc_used[a]) goto out;
+  rc = E_OK;
+out:
+#undef USE
+#undef DEF
+#undef SITE
+#undef WIDTH
+  free(seen_id); free(site_used); free(acc_used); free(def_scope); free(scope_open);
+  if (rc != E_OK) prog_free(P);
+  return rc;
+}
+
+/* ---- integer semantics (wrap at width w; see the IR description) -------- */
+static uint64_t narrow(uint64_t v, int w) { return w == 32 ? (uint64_t)(int64_t)(int32_t)(uint32_t)v : v; }
+
+static uint64_t alu(int op, int w, uint64_t x, uint64_t y, uint64_t* faults) {
+  x = narrow(x, w); y = narrow(y, w);
+  uint64_t mask = w == 32 ? 0xFFFFFFFFull : ~0ull;
+  uint64_t ux = x & mask, uy = y & mask; /* unsigned views */
+  int64_t sx = (int64_t)x, sy = (int64_t)y; /* signed views (already sign-extended) */
+  int64_t smin = w == 32 ? (int64_t)INT32_MIN : INT64_MIN;
+  unsigned sh = (unsigned)(uy & (uint64_t)(w - 1));
+  uint64_t r = 0;
+  switch (op) {
+    case O_ADD: r = ux + uy; break;
+    case O_SUB: r = ux - uy; break;
+    case O_MUL: r = ux * uy; break;
+    case O_DIVS:
+      if (sy == 0) { (*faults)++; r = 0; }
+      else if (sx == smin && sy == -1) r = (uint64_t)smin;
+      else r = (uint64_t)(sx / sy);
+      break;
+    case O_REMS:
+      if (sy == 0) { (*faults)++; r = 0; }
+      else if (sx == smin && sy == -1) r = 0;
+      else r = (uint64_t)(sx % sy);
+      break;
+    case O_DIVU: if (uy == 0) { (*faults)++; r = 0; } else r = ux / uy; break;
+    case O_REMU: if (uy == 0) { (*faults)++; r = 0; } else r = ux % uy; break;
+    case O_AND: r = ux & uy; break;
+    case O_OR: r = ux | uy; break;
+    case O_XOR: r = ux ^ uy; break;
+    case O_SHL: r = ux << sh; break;
+    case O_SHRA: r = (uint64_t)(sx >> sh); break;
+    case O_SHRL: r = ux >> sh; break;
+    case O_MINS: r = (uint64_t)(sx < sy ? sx : sy); break;
+    case O_MAXS: r = (uint64_t)(sx > sy ? sx : sy); break;
+    case O_MINU: r = ux < uy ? ux : uy; break;
+    case O_MAXU: r = ux > uy ? ux : uy; break;
+    case O_CMPEQ: r = ux == uy; break;
+    case O_CMPNE: r = ux != uy; break;
+    case O_CMPLTS: r = sx < sy; break;
+    case O_CMPLES: r = sx <= sy; break;
+    case O_CMPLTU: r = ux < uy; break;
+    case O_CMPLEU: r = ux <= uy; break;
+  }
+  return narrow(r, w);
+}
+
+/* Trip count of LOOP start,end,step at width w, as an exact integer,
+ * saturated at UINT64_MAX ("never ends"). */
+static uint64_t trip_count(int64_t s, int64_t e, int64_t step) {
+  if (step >= 0) {
+    if (!(s < e)) return 0;
+    if (step == 0) return UINT64_MAX;
+    uint64_t span = (uint64_t)e - (uint64_t)s; /* exact: e > s */
+    return span / (uint64_t)step + (span % (uint64_t)step != 0);
+  } else {
+    if (!(s > e)) return 0;
+    uint64_t span = (uint64_t)s - (uint64_t)e;
+    uint64_t mag = (uint64_t)0 - (uint64_t)step;
+    return span / mag + (span % mag != 0);
+  }
+}
+
+/* ---- one thread --------------------------------------------------------- */
+typedef struct {
+  const or_prog* P;
+  const int64_t* scalars;
+  const uint32_t* launch; /* gx gy gz bx by bz */
+  const or_alloc* table;
+  uint32_t tid[3], bid[3];
+  uint64_t gtid;
+  unsigned L1, L2;
+  uint64_t cap[2];
+  uint64_t* regs;
+  uint64_t iter[2];
+  int stopped;
+  or_record* rec;  /* this input's records [n_accesses] */
+  uint64_t* cnt;   /* this input's site counters [n_sites] */
+  or_status* st;
+  uint8_t* acc_seen; /* [n_accesses]: executed at least once in this input */
+} thr;
+
+static void visit(thr* t, uint16_t s) { if (s != NOSITE) t->cnt[s]++; }
+
+/* Check one access (the allocation-table check of an ASan-style detector). */
+static uint32_t check_kind(const or_alloc* a, int64_t idx, unsigned log2e) {
+  if (a->base == 0) return K_NULL;
+  if (a->flags & A_FREED) return K_FREED;
+  if (idx < 0) return K_UNDER;
+  uint64_t n_elems = a->size_bytes >> log2e;
+  if ((uint64_t)idx >= n_elems) return K_OVER;
+  return 0;
+}
+
+static void record(thr* t, int acc, uint32_t kind, int64_t idx) {
+  or_record* R = &t->rec[acc];
+  uint64_t key = (t->gtid << (t->L1 + t->L2)) | (t->iter[0] << t->L2) | t->iter[1];
+  R->count++;
+  R->kinds |= kind;
+  if (key < R->first_key) { R->first_key = key; R->index = idx; R->first_kind = kind; }
+}
+
+static void exec_range(thr* t, int pc, int end);
+
+static void exec_one_loop(thr* t, int pc) {
+  const or_ins* I = &t->P->ins[pc];
+  int w = I->w;
+  int64_t s = (int64_t)narrow(t->regs[I->a], w);
+  int64_t e = (int64_t)narrow(t->regs[I->b], w);
+  int64_t st = (int64_t)narrow(t->regs[I->c], w);
+  uint64_t n = trip_count(s, e, st);
+  int d = I->depth; /* 0 for a depth-1 loop */
+  uint64_t cap = t->cap[d];
+  uint64_t run = n < cap ? n : cap;
+  for (uint64_t k = 0; k < run && !t->stopped; k++) {
+    t->regs[I->dst] = narrow((uint64_t)s + k * (uint64_t)st, w);
+    t->iter[d] = k;
+    visit(t, I->s0);
+    exec_range(t, pc + 1, I->end);
+  }
+  t->iter[d] = 0;
+  if (t->stopped) return;
+  if (n > cap) { t->stopped = 1; t->st->hang_lanes++; return; }
+  visit(t, I->s1);
+}
+
+static void exec_range(thr* t, int pc, int end) {
+  const or_prog* P = t->P;
+  uint64_t* R = t->regs;
+  while (pc < end && !t->stopped) {
+    const or_ins* I = &P->ins[pc];
+    switch (I->op) {
+      case O_CONST: R[I->dst] = narrow((uint64_t)P->consts[I->a], I->w); break;
+      case O_SCALAR: R[I->dst] = narrow((uint64_t)t->scalars[I->a], I->w); break;
+      case O_SPECIAL: {
+        uint32_t v;
+        int k = I->a;
+        if (k < 3) v = t->tid[k];
+        else if (k < 6) v = t->bid[k - 3];
+        else if (k < 9) v = t->launch[3 + (k - 6)];
+        else v = t->launch[k - 9];
+        R[I->dst] = (uint64_t)v;
+        break;
+      }
+      case O_SELECT: R[I->dst] = narrow(R[I->a] != 0 ? R[I->b] : R[I->c], I->w); break;
+      case O_SEXT: case O_TRUNC: R[I->dst] = narrow(R[I->a], 32); break;
+      case O_ZEXT: R[I->dst] = R[I->a] & 0xFFFFFFFFull; break;
+      case O_ACCESS:
+      case O_LOAD: {
+        int64_t idx = (int64_t)narrow(R[I->a], I->w);
+        unsigned log2e = I->op == O_ACCESS ? (I->d & 3u) : I->d;
+        const or_alloc* A = &t->table[I->c];
+        uint32_t kind = check_kind(A, idx, log2e);
+        t->st->accesses_checked++;
+        t->acc_seen[I->b] = 1;
+        visit(t, I->s0);
+        if (kind) record(t, I->b, kind, idx);
+        if (I->op == O_LOAD) {
+          uint64_t v = 0;
+          if (!kind) {
+            if (log2e == 2) v = (uint64_t)(int64_t)((const int32_t*)A->data)[idx];
+            else v = (uint64_t)((const int64_t*)A->data)[idx];
+          }
+          R[I->dst] = v;
+        }
+        break;
+      }
+      case O_IF: {
+        int taken = R[I->a] != 0;
+        if (taken) {
+          visit(t, I->s0);
+          exec_range(t, pc + 1, I->alt >= 0 ? I->alt : I->end);
+        } else {
+          visit(t, I->s1);
+          if (I->alt >= 0) exec_range(t, I->alt + 1, I->end);
+        }
+        pc = I->end; /* continue after ENDIF */
+        break;
+      }
+      case O_LOOP:
+        exec_one_loop(t, pc);
+        pc = I->end;
+        break;
+      case O_ELSE: case O_ENDIF: case O_ENDLOOP:
+        break; /* reached only as range ends */
+      default:
+        R[I->dst] = alu(I->op, I->w, R[I->a], R[I->b], &t->st->arith_faults);
+        break;
+    }
+    pc++;
+  }
+}
+
+static void run_thread(thr* t, uint64_t blin, uint32_t tlin) {
+  const uint32_t* L = t->launch;
+  uint32_t gx = L[0], gy = L[1], bx = L[3], by = L[4];
+  uint64_t bsize = (uint64_t)L[3] * L[4] * L[5];
+  t->bid[0] = (uint32_t)(blin % gx);
+  t->bid[1] = (uint32_t)((blin / gx) % gy);
+  t->bid[2] = (uint32_t)(blin / ((uint64_t)gx * gy));
+  t->tid[0] = tlin % bx;
+  t->tid[1] = (tlin / bx) % by;
+  t->tid[2] = tlin / (bx * by);
+  t->gtid = blin * bsize + tlin;
+  memset(t->regs, 0, sizeof(uint64_t) * (t->P->n_regs + 1));
+  t->iter[0] = t->iter[1] = 0;
+  t->stopped = 0;
+  t->st->lanes++;
+  exec_range(t, 0, t->P->n_instr);
+}
+
+/* A block is a boundary block when one of its coordinates is first or last
+ * along its grid dimension. */
+static int is_boundary_block(const uint32_t* L, uint64_t blin) {
+  uint32_t gx = L[0], gy = L[1], gz = L[2];
+  uint32_t x = (uint32_t)(blin % gx), y = (uint32_t)((blin / gx) % gy), z = (uint32_t)(blin / ((uint64_t)gx * gy));
+  return x == 0 || x == gx - 1 || y == 0 || y == gy - 1 || z == 0 || z == gz - 1;
+}
+
+/* One input under the chosen thread set. */
+static void run_input(thr* t, uint32_t mode) {
+  const uint32_t* L = t->launch;
+  uint64_t nblocks = (uint64_t)L[0] * L[1] * L[2];
+  uint32_t bsize = L[3] * L[4] * L[5];
+  if (nblocks == 0 || bsize == 0) return;
+  if (mode == M_FULL) {
+    /* The whole grid: what the paper executes for kernels that are not
+     * affine-access (Section 5.1, fall-back to all blocks and threads). */
+    for (uint64_t b = 0; b < nblocks; b++)
+      for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, b, tl);
+  } else if (mode == M_CORNERS) {
+    /* The PREX Theorem's representative threads {first, last thread} x
+     * {first, last block} (Section 5.1.1), taken per dimension: every vertex
+     * of the box of block and thread coordinates. */
+    uint32_t lo_hi[6][2];
+    int cnt[6];
+    for (int d = 0; d < 6; d++) {
+      lo_hi[d][0] = 0; lo_hi[d][1] = L[d] - 1;
+      cnt[d] = L[d] == 1 ? 1 : 2;
+    }
+    int tot = 1;
+    for (int d = 0; d < 6; d++) tot *= cnt[d];
+    /* Enumerate vertices in global-thread-id order: block coordinates
+     * outermost (z, y, x), then thread coordinates (z, y, x). */
+    for (int v = 0; v < tot; v++) {
+      uint32_t c[6];
+      int rem = v;
+      int order[6] = {2, 1, 0, 5, 4, 3}; /* bz by bx tz ty tx (gx..gz = 0..2, bx..bz = 3..5) */
+      int div = tot;
+      for (int o = 0; o < 6; o++) {
+        int d = order[o];
+        div /= cnt[d];
+        int digit = rem / div;
+        rem %= div;
+        c[d] = lo_hi[d][digit];
+      }
+      uint64_t blin = c[0] + (uint64_t)L[0] * (c[1] + (uint64_t)L[1] * c[2]);
+      uint32_t tlin = c[3] + L[3] * (c[4] + L[4] * c[5]);
+      run_thread(t, blin, tlin);
+    }
+  } else if (mode == M_BOUNDARY) {
+    /* Every block on the faces of the grid plus the middle block, all of
+     * their threads (the blocks the PREX runtime prioritises, Section 5.1.2,
+     * plus one interior representative). */
+    uint64_t centre = (uint64_t)(L[0] / 2) + (uint64_t)L[0] * ((L[1] / 2) + (uint64_t)L[1] * (L[2] / 2));
+    for (uint64_t b = 0; b < nblocks; b++)
+      if (is_boundary_block(L, b) || b == centre)
+        for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, b, tl);
+  } else if (mode == M_PREX) {
+    /* Algorithm 1 (PREX runtime): blocks are taken from both ends of the
+     * block order inward, head then tail, and the sweep stops before a new
+     * pair once every memory-access instruction of the program has executed
+     * (the runtime's "coverage is 100%") or a violation has been seen.  A
+     * single middle block (head == tail) runs once. */
+    uint64_t head = 0, tail = nblocks - 1;
+    for (;;) {
+      if (head > tail) break;
+      int covered = 1, bug = 0;
+      for (int a = 0; a < t->P->n_accesses; a++) if (!t->acc_seen[a]) { covered = 0; break; }
+      for (int a = 0; a < t->P->n_accesses; a++) if (t->rec[a].count) { bug = 1; break; }
+      if (covered || bug) break;
+      for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, head, tl);
+      if (tail != head)
+        for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, tail, tl);
+      head++;
+      if (tail == 0) break;
+      tail--;
+    }
+  }
+}
+
+/* ---- batch driver ------------------------------------------------------- */
+typedef struct {
+  const or_prog* P;
+  uint32_t n_inputs;
+  const uint32_t* launch;
+  const int64_t* scalars;
+  const or_alloc* tables;     /* concatenated */
+  const uint64_t* table_off;  /* [n_inputs] first entry of each input's table */
+  uint32_t mode;
+  unsigned L1, L2;
+  uint64_t cap[2];
+  or_record* recs;
+  uint64_t* counts;
+  or_status* st;
+  int nthreads, me;
+} job_t;
+
+static void* worker(void* arg) {
+  job_t* J = (job_t*)arg;
+  const or_prog* P = J->P;
+  thr t;
+  memset(&t, 0, sizeof t);
+  t.P = P;
+  t.regs = (uint64_t*)calloc(P->n_regs + 1, 8);
+  t.acc_seen = (uint8_t*)calloc(P->n_accesses + 1, 1);
+  t.L1 = J->L1; t.L2 = J->L2; t.cap[0] = J->cap[0]; t.cap[1] = J->cap[1];
+  int64_t zero_scalars[16] = {0};
+  for (uint32_t i = (uint32_t)J->me; i < J->n_inputs; i += (uint32_t)J->nthreads) {
+    t.launch = J->launch + 6 * (size_t)i;
+    t.scalars = P->n_scalars ? J->scalars + (size_t)P->n_scalars * i : zero_scalars;
+    t.table = J->tables + J->table_off[i];
+    t.rec = J->recs + (size_t)P->n_accesses * i;
+    t.cnt = J->counts + (size_t)P->n_sites * i;
+    t.st = J->st + i;
+    memset(t.acc_seen, 0, P->n_accesses + 1);
+    run_input(&t, J->mode);
+  }
+  free(t.regs);
+  free(t.acc_seen);
+  return NULL;
+}
+
+/* Public entry: check n_inputs inputs of one program.
+ *   launch   [n_inputs][6]  gx gy gz bx by bz
+ *   scalars  [n_inputs][n_scalars]
+ *   tables   concatenated allocation tables; input i's table starts at
+ *            table_off[i] and has table_len[i] >= n_slots entries
+ *   mode     0 whole grid, 1 corner threads, 2 boundary blocks, 3 PREX sweep
+ *   cap_log2 trip caps 2^cap_log2[d] for loops at depth d+1
+ *   recs     [n_inputs][n_accesses] out; counts [n_inputs][n_sites] out (u64);
+ *   maps     [n_inputs][65536] out or NULL; st [n_inputs] out
+ * Returns 0, or a negative code (-1 invalid arguments, -2 bad IR, -3 key range). */
+int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint32_t* launch,
+               const int64_t* scalars, const or_alloc* tables, const uint64_t* table_off,
+               const uint32_t* table_len, uint32_t mode, const uint32_t* cap_log2,
+               or_record* recs, uint64_t* counts, uint8_t* maps, or_status* st, int nthreads) {
+  or_prog P;
+  int rc = prog_decode(ir, ir_bytes, &P);
+  if (rc) return rc;
+  if (mode > M_PREX || cap_log2[0] > 32 || cap_log2[1] > 32) { prog_free(&P); return E_INVALID; }
+  unsigned L1 = P.max_depth >= 1 ? cap_log2[0] : 0;
+  unsigned L2 = P.max_depth >= 2 ? cap_log2[1] : 0;
+  for (uint32_t i = 0; i < n_inputs; i++) {
+    const uint32_t* L = launch + 6 * (size_t)i;
+    if (table_len[i] < (uint32_t)P.n_slots) { prog_free(&P); return E_INVALID; }
+    for (int s = 0; s < P.n_slots; s++) {
+      const or_alloc* A = tables + table_off[i] + s;
+      if (P.load_slot[s] && A->base != 0 && !(A->flags & A_FREED) && A->data == NULL && A->size_bytes > 0) {
+        prog_free(&P); return E_INVALID;
+      }
+    }
+    unsigned __int128 nthr = (unsigned __int128)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
+    if ((uint64_t)L[3] * L[4] * L[5] > 1024 || (uint64_t)L[0] * L[1] * L[2] > 0xFFFFFFFFull) { prog_free(&P); return E_INVALID; }
+    if (nthr > 0 && L1 + L2 > 0) {
+      unsigned __int128 lim = (unsigned __int128)1 << (64 - L1 - L2);
+      if (nthr > lim) { prog_free(&P); return E_RANGE; }
+    }
+  }
+  for (size_t k = 0; k < (size_t)n_inputs * P.n_accesses; k++) {
+    recs[k].first_key = UINT64_MAX; recs[k].index = 0; recs[k].count = 0; recs[k].kinds = 0; recs[k].first_kind = 0;
+  }
+  memset(counts, 0, sizeof(uint64_t) * (size_t)n_inputs * P.n_sites);
+  memset(st, 0, sizeof(or_status) * n_inputs);
+  if (nthreads < 1) nthreads = 1;
+  if ((uint32_t)nthreads > n_inputs && n_inputs > 0) nthreads = (int)n_inputs;
+  job_t* jobs = (job_t*)calloc(nthreads, sizeof(job_t));
+  pthread_t* th = (pthread_t*)calloc(nthreads, sizeof(pthread_t));
+  for (int k = 0; k < nthreads; k++) {
+    job_t* J = &jobs[k];
+    J->P = &P; J->n_inputs = n_inputs; J->launch = launch; J->scalars = scalars;
+    J->tables = tables; J->table_off = table_off; J->mode = mode; J->L1 = L1; J->L2 = L2;
+    J->cap[0] = 1ull << cap_log2[0]; J->cap[1] = 1ull << cap_log2[1];
+    J->recs = recs; J->counts = counts; J->st = st; J->nthreads = nthreads; J->me = k;
+  }
+  if (nthreads == 1) worker(&jobs[0]);
+  else {
+    for (int k = 0; k < nthreads; k++) pthread_create(&th[k], NULL, worker, &jobs[k]);
+    for (int k = 0; k < nthreads; k++) pthread_join(th[k], NULL);
+  }
+  if (maps) {
+    memset(maps, 0, (size_t)n_inputs * 65536);
+    for (uint32_t i = 0; i < n_inputs; i++)
+      for (int s = 0; s < P.n_sites; s++) {
+        uint64_t c = counts[(size_t)i * P.n_sites + s];
+        maps[(size_t)i * 65536 + P.site_ids[s]] = (uint8_t)(c > 255 ? 255 : c);
+      }
+  }
+  free(jobs); free(th);
+  prog_free(&P);
+  return E_OK;
+}
+
+/* Decode-only entry: 0 if the IR is well formed, else -2.  Fills
+ * n_accesses/n_sites/max_depth when out != NULL. */
+int ckco_validate(const uint8_t* ir, size_t ir_bytes, int32_t* out) {
+  or_prog P;
+  int rc = prog_decode(ir, ir_bytes, &P);
+  if (rc) return rc;
+  if (out) { out[0] = P.n_accesses; out[1] = P.n_sites; out[2] = P.max_depth; out[3] = P.n_slots; }
+  prog_free(&P);
+  return E_OK;
+}

@@ -1,0 +1,301 @@
+"""Seeded synthetic workloads: index programs plus per-input launch shapes,
+scalars and allocation tables.
+
+The paper measures on third-party CUDA benchmark suites and on its own
+memory-safety benchmark (Section 7.1); none of them is available here, so these
+generators stand in for them with the access *shapes* the paper discusses:
+affine kernels such as vector addition (Listing 1, Listing 3) and stencils, and
+indirect kernels whose indices come from loaded index arrays (the paper's
+graph kernels, for which PREX falls back to the whole grid, Section 7.3).
+
+Families (each in an int32 and an int64 form):
+  F1  1-D affine kernel: four accesses A[gid-1], A[gid], B[gid+1], B[gid+2]
+  F2  2-D 9-point stencil: centre read, an 8-iteration neighbour loop with a
+      halo radius and a row-stride scalar, centre write
+  F3  CSR SpMV gather: guarded row, two row_ptr loads, a loop over the row's
+      nonzeros loading col_idx[j] and touching val[j] and x[col], then y[row]
+
+Only numpy's PCG64 generator is used; nothing here performs the checking
+arithmetic.  A workload is a plain record of arrays that both the oracle
+wrapper and the GPU binding consume.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .ir import Program
+
+# allocation-table entry (32 bytes; layout shared by the C-ABI's ckc_alloc):
+# the ``data`` field holds a 1-based index into ``Workload.data`` here (0 = no
+# data); consumers replace it with a host or device address.
+ALLOC_DTYPE = np.dtype([("base", "<u8"), ("size_bytes", "<u8"), ("data", "<u8"),
+                        ("flags", "<u4"), ("pad", "<u4")])
+ALLOC_FREED = 1
+
+MODE_FULL, MODE_CORNERS, MODE_BOUNDARY, MODE_PREX = 0, 1, 2, 3
+DEFAULT_CAP_LOG2 = (20, 12)
+I64_BASE = 1 << 32  # base offset of the int64 variants (no memory behind it)
+LOGICAL_BASE = 0x7F00_0000_0000  # nonzero logical base for live allocations
+
+
+@dataclass
+class Workload:
+    name: str
+    ir: bytes
+    launch: np.ndarray          # [n, 6] uint32: gx gy gz bx by bz
+    scalars: np.ndarray         # [n, n_scalars] int64
+    tables: np.ndarray          # [n_tables, n_slots] ALLOC_DTYPE
+    table_idx: np.ndarray       # [n] uint32: table of each input
+    data: list = field(default_factory=list)  # arrays referenced by tables["data"]
+    mode: int = MODE_FULL
+    cap_log2: tuple = DEFAULT_CAP_LOG2
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_inputs(self) -> int:
+        return int(self.launch.shape[0])
+
+    def subset(self, idx) -> "Workload":
+        """The same workload restricted to inputs ``idx`` (tables kept whole)."""
+        idx = np.asarray(idx)
+        return Workload(self.name, self.ir, self.launch[idx].copy(), self.scalars[idx].copy(),
+                        self.tables, self.table_idx[idx].copy(), self.data, self.mode,
+                        self.cap_log2, dict(self.meta))
+
+
+def alloc(size_bytes: int, data_ref: int = 0, base: int = LOGICAL_BASE, flags: int = 0):
+    return (base, size_bytes, data_ref, flags, 0)
+
+
+# ---------------------------------------------------------------------------
+# programs
+# ---------------------------------------------------------------------------
+def _gid_x(p: Program, w: int):
+    return p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), w), p.special("tid.x"), w)
+
+
+def f1_program(w: int = 32) -> bytes:
+    """F1: gid = bid.x*bdim.x + tid.x; reads A[gid-1], A[gid]; writes B[gid+1],
+    B[gid+2] (the index form of the vector kernels of Listings 1 and 3).  The
+    int64 form adds scalar 0 (a base offset) to every index."""
+    p = Program(n_scalars=1 if w == 64 else 0, n_slots=2)
+    gid = _gid_x(p, w)
+    if w == 64:
+        gid = p.add(gid, p.scalar(0, 64), 64)
+    for slot, off, write in ((0, -1, False), (0, 0, False), (1, 1, True), (1, 2, True)):
+        p.access(slot, p.add(gid, p.const(off, w), w), elem=4, write=write)
+    return p.to_bytes()
+
+
+def f2_program(w: int = 32) -> bytes:
+    """F2: 2-D 9-point stencil.  Scalars: 0 = row stride S, 1 = radius r
+    (2 = base offset in the int64 form).  base = y*S + x; read in[base];
+    for k in 0..7: j = k + (k > 3); read in[base + ((j/3)-1)*r*S + ((j%3)-1)*r];
+    write out[base]."""
+    p = Program(n_scalars=3 if w == 64 else 2, n_slots=2)
+    x = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), w), p.special("tid.x"), w)
+    y = p.add(p.mul(p.special("bid.y"), p.special("bdim.y"), w), p.special("tid.y"), w)
+    S = p.scalar(0, w)
+    r = p.scalar(1, w)
+    base = p.add(p.mul(y, S, w), x, w)
+    if w == 64:
+        base = p.add(base, p.scalar(2, 64), 64)
+    p.access(0, base, elem=4)
+    with p.loop(0, 8, 1, w=w) as k:
+        j = p.add(k, p.cmplts(p.const(3, w), k, w), w)
+        dy = p.mul(p.sub(p.divs(j, p.const(3, w), w), p.const(1, w), w), r, w)
+        dx = p.mul(p.sub(p.rems(j, p.const(3, w), w), p.const(1, w), w), r, w)
+        p.access(0, p.add(base, p.add(p.mul(dy, S, w), dx, w), w), elem=4)
+    p.access(1, base, elem=4, write=True)
+    return p.to_bytes()
+
+
+def f3_program(w: int = 32) -> bytes:
+    """F3: CSR SpMV gather.  Slots 0 row_ptr, 1 col_idx (int32, real data),
+    2 val, 3 x, 4 y (fp32, addresses only).  Scalar 0 = nrows (1 = base offset
+    added to the val/x/y indices in the int64 form)."""
+    p = Program(n_scalars=2 if w == 64 else 1, n_slots=5)
+    r = _gid_x(p, w)
+    nrows = p.scalar(0, w)
+    with p.if_(p.cmplts(r, nrows, w)):
+        rp0 = p.load(0, r, elem=4, w=w)
+        rp1 = p.load(0, p.add(r, p.const(1, w), w), elem=4, w=w)
+        off = p.scalar(1, 64) if w == 64 else None
+        with p.loop(rp0, rp1, 1, w=w) as j:
+            c = p.load(1, j, elem=4, w=w)
+            jj = p.add(j, off, 64) if w == 64 else j
+            cc = p.add(c, off, 64) if w == 64 else c
+            p.access(2, jj, elem=4, w=w)
+            p.access(3, cc, elem=4, w=w)
+        rr = p.add(r, off, 64) if w == 64 else r
+        p.access(4, rr, elem=4, write=True, w=w)
+    return p.to_bytes()
+
+
+PROGRAMS = {("F1", 32): f1_program, ("F1", 64): f1_program, ("F2", 32): f2_program,
+            ("F2", 64): f2_program, ("F3", 32): f3_program, ("F3", 64): f3_program}
+
+
+def program(family: str, w: int) -> bytes:
+    return PROGRAMS[(family, w)](w)
+
+
+# ---------------------------------------------------------------------------
+# CSR generator (power-law row lengths, corrupted copies of col_idx)
+# ---------------------------------------------------------------------------
+def powerlaw_row_lengths(rng, nrows: int, ncols: int, mean: int = 16, alpha: float = 2.1):
+    """Row lengths L = min(ncols, max(1, floor(s*w))) with w = (1-u)^(-1/(alpha-1))
+    (a Pareto law with density exponent alpha); s is bisected to the largest
+    value with sum(L) <= mean*nrows and the remaining deficit is added one
+    nonzero at a time to the first rows that are below ncols."""
+    u = rng.random(nrows)
+    w = (1.0 - u) ** (-1.0 / (alpha - 1.0))
+    target = mean * nrows
+
+    def total(s):
+        return int(np.minimum(ncols, np.maximum(1, np.floor(s * w))).sum())
+
+    lo, hi = 0.0, float(mean) * 4
+    while total(hi) < target:
+        hi *= 2
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if total(mid) <= target:
+            lo = mid
+        else:
+            hi = mid
+    L = np.minimum(ncols, np.maximum(1, np.floor(lo * w))).astype(np.int64)
+    deficit = target - int(L.sum())
+    if deficit > 0:
+        open_rows = np.nonzero(L < ncols)[0][:deficit]
+        L[open_rows] += 1
+    assert int(L.sum()) == target
+    return L
+
+
+def csr_structure(seed: int, nrows: int, ncols: int, mean: int = 16):
+    rng = np.random.default_rng(seed)
+    L = powerlaw_row_lengths(rng, nrows, ncols, mean)
+    row_ptr = np.zeros(nrows + 1, dtype=np.int64)
+    np.cumsum(L, out=row_ptr[1:])
+    assert row_ptr[-1] < 2**31
+    col = rng.integers(0, ncols, size=int(row_ptr[-1]), dtype=np.int64).astype(np.int32)
+    return rng, row_ptr.astype(np.int32), col
+
+
+def corrupt_copy(rng, col: np.ndarray, ncols: int, frac: float = 0.001):
+    """A copy of ``col`` with round(frac*nnz) positions (without replacement)
+    replaced by values uniform in [-64, ncols+64)."""
+    out = col.copy()
+    k = int(round(frac * col.size))
+    if k:
+        pos = rng.choice(col.size, size=k, replace=False)
+        out[pos] = rng.integers(-64, ncols + 64, size=k, dtype=np.int64).astype(np.int32)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# configurations
+# ---------------------------------------------------------------------------
+def config1(seed: int = 1001, n_inputs: int = 256, g_range=(32, 80), block: int = 256,
+            n_range=(8192, 16384), w: int = 32) -> Workload:
+    """Plain 1-D affine check: G ~ U{g_range} blocks of ``block`` threads,
+    n ~ U{n_range} int32 elements per allocation."""
+    rng = np.random.default_rng(seed)
+    G = rng.integers(g_range[0], g_range[1] + 1, size=n_inputs)
+    n = rng.integers(n_range[0], n_range[1] + 1, size=n_inputs)
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    launch[:, 0] = G
+    launch[:, 1:3] = 1
+    launch[:, 3] = block
+    launch[:, 4:6] = 1
+    extra = I64_BASE if w == 64 else 0
+    tables = np.zeros((n_inputs, 2), ALLOC_DTYPE)
+    for i in range(n_inputs):
+        sz = (int(n[i]) + extra) * 4
+        tables[i] = [alloc(sz), alloc(sz, base=LOGICAL_BASE + (1 << 36))]
+    scalars = np.full((n_inputs, 1), extra, np.int64) if w == 64 else np.zeros((n_inputs, 0), np.int64)
+    return Workload(f"config1_f1_i{w}", f1_program(w), launch, scalars, tables,
+                    np.arange(n_inputs, dtype=np.uint32), [], MODE_FULL,
+                    meta=dict(seed=seed, G=G, n=n, block=block))
+
+
+def config2(seed: int = 1002, n_inputs: int = 4096, g0: int = 128, hw0: int = 2048,
+            delta: int = 3, block=(16, 16), mode: int = MODE_FULL, w: int = 32) -> Workload:
+    """2-D 9-point stencil: grid (g0+d1) x (g0+d2) blocks of 16x16 threads over
+    an H x W fp32 pair of allocations with H = hw0+d3, W = hw0+d4 (d ~ U{-delta..delta}),
+    radius r ~ U{1, 2}, row stride S = W."""
+    rng = np.random.default_rng(seed)
+    d = rng.integers(-delta, delta + 1, size=(n_inputs, 4))
+    r = rng.integers(1, 3, size=n_inputs)
+    gx, gy = g0 + d[:, 0], g0 + d[:, 1]
+    H, W = hw0 + d[:, 2], hw0 + d[:, 3]
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    launch[:, 0], launch[:, 1], launch[:, 2] = gx, gy, 1
+    launch[:, 3], launch[:, 4], launch[:, 5] = block[0], block[1], 1
+    extra = I64_BASE if w == 64 else 0
+    ns = 3 if w == 64 else 2
+    scalars = np.zeros((n_inputs, ns), np.int64)
+    scalars[:, 0], scalars[:, 1] = W, r
+    if w == 64:
+        scalars[:, 2] = extra
+    tables = np.zeros((n_inputs, 2), ALLOC_DTYPE)
+    for i in range(n_inputs):
+        sz = (int(H[i]) * int(W[i]) + extra) * 4
+        tables[i] = [alloc(sz), alloc(sz, base=LOGICAL_BASE + (1 << 36))]
+    return Workload(f"config2_f2_i{w}", f2_program(w), launch, scalars, tables,
+                    np.arange(n_inputs, dtype=np.uint32), [], mode,
+                    meta=dict(seed=seed, H=H, W=W, r=r, gx=gx, gy=gy))
+
+
+def config3(seed: int = 1003, n_inputs: int = 64, log2_rows: int = 20, mean: int = 16,
+            frac: float = 0.001, block: int = 256, w: int = 32) -> Workload:
+    """CSR gather: nrows = ncols = 2^log2_rows, power-law rows with mean
+    ``mean`` nonzeros, one corrupted copy of col_idx per input."""
+    nrows = ncols = 1 << log2_rows
+    rng, row_ptr, col = csr_structure(seed, nrows, ncols, mean)
+    nnz = int(row_ptr[-1])
+    data = [row_ptr]
+    for _ in range(n_inputs):
+        data.append(corrupt_copy(rng, col, ncols, frac))
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    launch[:, 0] = (nrows + block - 1) // block
+    launch[:, 1:3] = 1
+    launch[:, 3] = block
+    launch[:, 4:6] = 1
+    extra = I64_BASE if w == 64 else 0
+    ns = 2 if w == 64 else 1
+    scalars = np.zeros((n_inputs, ns), np.int64)
+    scalars[:, 0] = nrows
+    if w == 64:
+        scalars[:, 1] = extra
+    tables = np.zeros((n_inputs, 5), ALLOC_DTYPE)
+    for i in range(n_inputs):
+        tables[i] = [alloc((nrows + 1) * 4, 1, LOGICAL_BASE),
+                     alloc(nnz * 4, 2 + i, LOGICAL_BASE + (1 << 36)),
+                     alloc((nnz + extra) * 4, 0, LOGICAL_BASE + (2 << 36)),
+                     alloc((ncols + extra) * 4, 0, LOGICAL_BASE + (3 << 36)),
+                     alloc((nrows + extra) * 4, 0, LOGICAL_BASE + (4 << 36))]
+    return Workload(f"config3_f3_i{w}", f3_program(w), launch, scalars, tables,
+                    np.arange(n_inputs, dtype=np.uint32), data, MODE_FULL,
+                    meta=dict(seed=seed, nrows=nrows, ncols=ncols, nnz=nnz))
+
+
+def mini(name: str, **kw) -> Workload:
+    """Reduced forms of the configurations: small enough for the oracle to
+    finish in seconds, still spanning many tiles and a ragged tail."""
+    if name == "config1":
+        base = dict(n_inputs=24, g_range=(2, 9), block=64, n_range=(100, 600))
+        base.update(kw)
+        return config1(**base)
+    if name == "config2":
+        base = dict(n_inputs=12, g0=6, hw0=90, delta=3, block=(16, 16))
+        base.update(kw)
+        return config2(**base)
+    if name == "config3":
+        base = dict(n_inputs=6, log2_rows=11, mean=16, frac=0.01)
+        base.update(kw)
+        return config3(**base)
+    raise KeyError(name)
