@@ -1,0 +1,213 @@
+/*
+ * ckc.h — C-ABI of libckc: GPU-native checking of index programs on AMD
+ * MI355X (gfx950).
+ *
+ * The library runs the hot path of coverage-guided kernel fuzzing with an
+ * address sanitizer (the method of the paper, Sections 4 and 5): for many
+ * inputs of one or more kernels it evaluates every memory-access index of
+ * every thread of the launch grid (or of a representative subset of threads,
+ * the PREX idea of Section 5.1), checks each index against the allocation it
+ * names, records the first violation of every (input, access), and builds a
+ * 64 KiB saturating coverage map per input (the AFL++ map of Section 2.1).
+ * Programs are given in the index-program IR of ckc_ir.h.
+ *
+ * Conventions for every entry point:
+ *   - the return value is CKC_OK (0), CKC_NOT_READY (1) or a negative error;
+ *     no call aborts, and no C++ exception crosses the ABI;
+ *   - ckc_last_error() returns a message for the calling thread's last failed
+ *     call (valid until that thread's next call);
+ *   - a context may be used by one thread at a time;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory of the context's device.
+ */
+#ifndef CKC_H
+#define CKC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ckc_ir.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ckc_status_code {
+  CKC_OK = 0,
+  CKC_NOT_READY = 1,   /* results not yet available (ckc_read_results without CKC_WAIT) */
+  CKC_E_INVALID = -1,  /* bad argument, id, size or combination */
+  CKC_E_IR = -2,       /* IR bytes malformed or outside the supported limits */
+  CKC_E_RANGE = -3,    /* a first-violation key would not fit in 64 bits */
+  CKC_E_NOMEM = -4,    /* device or host allocation failed */
+  CKC_E_HIP = -5,      /* a HIP runtime call failed */
+  CKC_E_BUSY = -6      /* object still referenced by unread jobs */
+};
+
+/* thread-set modes (ckc_batch.mode) */
+enum ckc_mode {
+  CKC_FULL = 0,         /* every thread of the grid (Section 5.1: the fall-back for
+                           kernels that are not affine-access) */
+  CKC_REP_CORNERS = 1,  /* the vertices of the (grid x block) coordinate box: the
+                           first/last thread of the first/last block of the PREX
+                           Theorem (Section 5.1.1), per dimension */
+  CKC_REP_BOUNDARY = 2  /* every block with a coordinate first or last along its grid
+                           dimension, plus the middle block, all of their threads */
+};
+
+/* violation kinds (ckc_record.kinds / first_kind) */
+enum ckc_kind { CKC_KIND_OVER = 1, CKC_KIND_UNDER = 2, CKC_KIND_FREED = 4, CKC_KIND_NULL = 8 };
+
+/* program classes (ckc_prog_info.cls), from the load-time analysis */
+enum ckc_prog_class {
+  CKC_CLS_AFFINE = 1,     /* every access index is affine in the thread and block
+                             coordinates with thread-invariant coefficients
+                             (Section 5.1.1's affine-access definition) */
+  CKC_CLS_GUARDED = 2,    /* some access sits under thread-dependent control flow */
+  CKC_CLS_INDIRECT = 4,   /* some index depends on a loaded value */
+  CKC_CLS_I64 = 8,        /* some access index has width 64 */
+  CKC_CLS_UNIFORM = 16,   /* control flow is thread-invariant and every index is
+                             affine: evaluated as a per-input access trace */
+  CKC_CLS_EXPANDED = 32   /* one loop is evaluated one lane per iteration */
+};
+
+typedef struct ckc_ctx_s* ckc_ctx;
+
+/* One context per HIP device.  Creates the context's stream-independent
+ * state; no kernel runs.  Errors: CKC_E_INVALID (no such device), CKC_E_HIP. */
+int ckc_init(int hip_device, ckc_ctx* out);
+/* Waits for outstanding work, frees every program, table and job. */
+void ckc_shutdown(ckc_ctx ctx);
+/* Message of the calling thread's last failed call ("" if none). */
+const char* ckc_last_error(void);
+
+/* ---- programs (Section 5.1.1 affine analysis, Section 5.2 pruning) ------ */
+typedef struct ckc_prog_info {
+  uint32_t n_accesses, n_sites, n_slots, n_scalars;
+  uint32_t max_loop_depth;
+  uint32_t cls;            /* ckc_prog_class bits */
+  uint32_t n_instr_live;   /* instructions left after removing those that feed no
+                              index, guard or loop bound */
+  uint32_t n_regs_phys;    /* registers after allocation */
+} ckc_prog_info;
+
+/* Per-access result of the load-time analysis.  coef[] describes the index
+ * as sum_d coef[d]*coord[d] + coef[6] over coord = (tid.x, tid.y, tid.z,
+ * bid.x, bid.y, bid.z) when the access is affine: each entry is encoded as
+ * kind << 32 | value with kind 0 = zero, 1 = the constant `value`, 2 = the
+ * uniform IR register `value` (a SPECIAL, SCALAR or CONST result), 3 = a
+ * thread-invariant expression. */
+typedef struct ckc_access_info {
+  uint32_t access_id, slot, log2_elem, width;
+  uint32_t affine;        /* 1 if the index is affine in the coordinates */
+  uint32_t guarded;       /* 1 if under thread-dependent control flow */
+  uint32_t indirect;      /* 1 if the index depends on a loaded value */
+  uint32_t loop_depth;
+  uint64_t coef[7];
+} ckc_access_info;        /* 88 bytes */
+
+/* Host-only analysis of IR bytes (no device needed): validation, pruning,
+ * classification.  info and acc (n_accesses entries) may be NULL.
+ * Errors: CKC_E_IR with a message naming the offending instruction. */
+int ckc_analyze_ir(const void* ir, size_t ir_bytes, ckc_prog_info* info, ckc_access_info* acc,
+                   uint32_t acc_capacity);
+
+/* Validates, analyses and lowers the program, and uploads its device form
+ * once.  ir: host bytes in the ckc_ir.h layout (copied).  *prog_id receives a
+ * nonzero id.  info may be NULL.  Errors: CKC_E_IR, CKC_E_NOMEM, CKC_E_HIP. */
+int ckc_load_program(ckc_ctx ctx, const void* ir, size_t ir_bytes, uint32_t* prog_id,
+                     ckc_prog_info* info);
+/* CKC_E_BUSY while an unread job uses the program. */
+int ckc_unload_program(ckc_ctx ctx, uint32_t prog_id);
+
+/* ---- allocation tables (the analogue of the heap the paper's translated
+ *      kernels run against, Section 4.1) -------------------------------- */
+#define CKC_ALLOC_FREED 1u
+typedef struct ckc_alloc {
+  uint64_t base;        /* logical address; 0 = NULL allocation */
+  uint64_t size_bytes;  /* bounds; metadata only unless data != NULL */
+  const void* data;     /* device pointer to size_bytes bytes; required for slots
+                           read by LOAD; borrowed: must stay valid until every job
+                           using the table has been read */
+  uint32_t flags;       /* CKC_ALLOC_FREED */
+  uint32_t pad;
+} ckc_alloc;            /* 32 bytes */
+
+/* Copies n (1..16) host entries into a device-resident table.  *table_id
+ * receives a nonzero id.  Errors: CKC_E_INVALID, CKC_E_NOMEM. */
+int ckc_put_alloc_table(ckc_ctx ctx, const ckc_alloc* entries, uint32_t n, uint32_t* table_id);
+/* CKC_E_BUSY while an unread job uses the table. */
+int ckc_free_alloc_table(ckc_ctx ctx, uint32_t table_id);
+
+/* ---- checking ----------------------------------------------------------- */
+enum ckc_batch_flags { CKC_DENSE_MAP = 2 };  /* also build the dense 64 KiB maps */
+
+typedef struct ckc_batch {
+  uint32_t prog_id;
+  uint32_t n_inputs;
+  const uint32_t* launch;    /* host [n_inputs][6]: gx gy gz bx by bz (copied) */
+  const int64_t* scalars;    /* host [n_inputs][n_scalars] (copied); NULL if n_scalars = 0 */
+  const uint32_t* table_ids; /* host [n_inputs] (copied) */
+  uint32_t mode;             /* ckc_mode */
+  uint32_t flags;            /* ckc_batch_flags */
+  uint32_t loop_cap_log2[2]; /* trip caps 2^k for loops at depth 1 and 2 (k <= 32);
+                                0,0 selects the defaults 20, 12 */
+} ckc_batch;
+
+typedef struct ckc_launch_opts {
+  uint32_t tile;       /* lanes per tile (multiple of 64, <= 1024); 0 = default */
+  uint32_t wg_size;    /* threads per workgroup (64..1024); 0 = default */
+  uint32_t n_wg;       /* persistent workgroups; 0 = default */
+  uint32_t force_generic; /* 1: evaluate every program with the general interpreter */
+  void* hip_stream;    /* hipStream_t; NULL = the context's own stream */
+} ckc_launch_opts;
+
+/* Checks every input of every descriptor in one job (one planning pass and
+ * one persistent evaluation over all of them).  Host arrays are copied before
+ * the call returns; the work is queued on the stream and the call returns
+ * without waiting.  Launch limits: block <= 1024 threads, grid < 2^32 blocks.
+ * Errors: CKC_E_INVALID (ids, sizes, missing LOAD data), CKC_E_RANGE (key
+ * bits: log2(threads per input) + cap bits of the depths used > 64),
+ * CKC_E_NOMEM, CKC_E_HIP. */
+int ckc_check_batch(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_descs,
+                    const ckc_launch_opts* opts, uint64_t* job);
+
+typedef struct ckc_record {
+  uint64_t first_key;   /* smallest (gtid << (L1+L2) | i1 << L2 | i2) that violated;
+                           UINT64_MAX if none */
+  int64_t index;        /* index value at first_key */
+  uint64_t count;       /* violating executions */
+  uint32_t kinds;       /* OR of ckc_kind bits */
+  uint32_t first_kind;  /* kind at first_key */
+} ckc_record;           /* 32 bytes */
+
+typedef struct ckc_input_status {
+  uint64_t lanes;            /* threads executed */
+  uint64_t accesses_checked; /* ACCESS and LOAD executions */
+  uint64_t hang_lanes;       /* threads stopped by a loop trip cap */
+  uint64_t arith_faults;     /* divisions by zero */
+  uint32_t flags, pad;
+} ckc_input_status;          /* 40 bytes */
+
+enum ckc_read_flags { CKC_WAIT = 1, CKC_DST_DEVICE = 2 };
+
+/* Copies a job's results out and releases the job.  Inputs are numbered in
+ * descriptor order.  recs: [sum over inputs of n_accesses]; maps: [inputs][65536]
+ * or NULL (requires CKC_DENSE_MAP); st: [inputs] or NULL.  With CKC_DST_DEVICE
+ * the three pointers are device pointers (device-to-device copies on the
+ * job's stream).  Without CKC_WAIT returns CKC_NOT_READY while the job runs.
+ * Errors: CKC_E_INVALID (unknown job), CKC_E_HIP. */
+int ckc_read_results(ckc_ctx ctx, uint64_t job, ckc_record* recs, uint8_t* maps,
+                     ckc_input_status* st, uint32_t flags);
+
+/* Number of inputs and records of a job (for sizing result buffers). */
+int ckc_job_sizes(ckc_ctx ctx, uint64_t job, uint64_t* n_inputs, uint64_t* n_records);
+
+/* Device timing of the job's evaluation kernels in milliseconds (HIP events on
+ * the job's stream, valid after the job completed): [0] planning, [1] main
+ * evaluation, [2] expanded-loop evaluation, [3] finishing (records, maps). */
+int ckc_job_timing(ckc_ctx ctx, uint64_t job, float* ms4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKC_H */

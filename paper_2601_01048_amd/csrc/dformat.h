@@ -1,0 +1,109 @@
+// dformat.h — the lowered (device) form of a loaded index program and the
+// per-job descriptors the evaluation kernels read.  Shared by the host runtime
+// and the HIP kernels of libckc; plain C layout, no HIP types.
+#pragma once
+#include <stdint.h>
+
+namespace ckc {
+
+constexpr int NREG = 32;          // physical registers per lane (64-bit each)
+constexpr int MAX_DINSTR = 1024;  // lowered instructions per program
+constexpr int MAX_DCONST = 256;   // constants per program
+constexpr int MAX_SLOTS = 16;
+constexpr int MAX_CLASSES = 4;    // distinct coefficient vectors in a trace
+constexpr int MAX_LIVEIN = 6;     // registers carried into an expanded loop body
+constexpr int MAX_SITES_LDS = 1024; // sites counted in LDS by the interpreter
+constexpr uint32_t NOSITE = 0xFFFFu;
+constexpr uint32_t DEAD = 0x40000000u;  // "disabled depth" of a stopped lane
+
+// Lowered instruction (16 bytes).  Register fields are physical registers.
+struct dins {
+  uint8_t op;     // IR opcode (ckc_ir_op numbering)
+  uint8_t w;      // 32 / 64
+  uint8_t dst, a;
+  uint8_t b, c;
+  uint8_t slot;   // ACCESS/LOAD: slot
+  uint8_t fl;     // ACCESS/LOAD: log2_elem; IF/LOOP: DI_* flags
+  uint16_t s0, s1;
+  uint16_t x;     // CONST: const index; SCALAR: scalar; SPECIAL: source;
+                  // ACCESS/LOAD: access id; LOOP: depth (0/1)
+  uint16_t jmp;   // IF: ELSE or ENDIF; ELSE: ENDIF; LOOP: ENDLOOP; ENDLOOP: LOOP
+};
+static_assert(sizeof(dins) == 16, "dins layout");
+
+enum : uint8_t {
+  DI_NOSKIP = 1,    // IF/LOOP: never skip the region (holds the expanded loop)
+  DI_EXPAND = 2,    // LOOP: evaluated one lane per iteration
+  DI_HASELSE = 4    // IF: jmp points at an ELSE
+};
+
+// Per-access facts used by the fix-up pass.
+struct daccess {
+  uint16_t pc;        // instruction index
+  uint16_t depth;     // enclosing loops
+  int16_t loop_pc[2]; // pcs of the enclosing LOOPs, outermost first (-1 if none)
+};
+
+// Program blob header; followed in memory by dins[n_instr], int64 consts,
+// daccess[n_accesses], uint16 site_ids[n_sites] (each region 16-byte aligned).
+struct dprog {
+  uint32_t n_instr, n_consts, n_accesses, n_sites;
+  uint32_t n_slots, n_scalars, max_depth, cls;
+  uint32_t n_regs;
+  int32_t expand_pc;          // LOOP lowered with DI_EXPAND, or -1
+  uint32_t n_livein;
+  uint32_t trace_cap;         // entries reserved per input for the trace path (0 = none)
+  uint8_t livein[MAX_LIVEIN]; // physical registers read by the expanded body
+  uint8_t load_slots;         // unused
+  uint8_t pad0;
+  uint32_t off_instr, off_consts, off_access, off_sites;  // byte offsets from the header
+  uint32_t total_bytes;
+  uint32_t pad1[3];
+};
+
+// One input of a job (the global input list concatenates the descriptors).
+struct dinput {
+  uint64_t prog;          // device address of the dprog blob
+  uint64_t table;         // device address of the ckc_alloc[] table
+  uint64_t lanes;         // threads in the thread set
+  uint64_t tile_begin[2]; // first tile in the trace / generic tile spaces
+  uint64_t rec_base;      // first record of this input
+  uint64_t cnt_base;      // first site counter of this input
+  uint64_t trace;         // device address of this input's trace (0 = none)
+  uint32_t launch[6];
+  uint32_t mode;
+  uint32_t L1, L2;        // key bits of depth-1 / depth-2 iteration ordinals
+  uint32_t cap_log2[2];
+  uint32_t path;          // 0 = trace evaluator, 1 = generic interpreter (set by planning)
+  uint32_t n_tiles[2];
+  uint32_t pad[3];
+};
+
+constexpr int MAX_SCALARS = 16;
+
+// Trace of a uniform-control program for one input: every thread performs the
+// same access sequence; each access index is base[class](thread) + off.
+struct dtrace_entry {
+  int64_t off;          // constant part (wrapped at the access width)
+  uint64_t keylo;       // i1 << L2 | i2 of this dynamic access
+  uint64_t bound;       // element count, clamped to 2^63 (2^31 for width 32)
+  uint32_t acc;         // access id
+  uint8_t cls;          // coefficient class
+  uint8_t w;            // 32 / 64
+  uint8_t dead_kind;    // NULL/FREED kind when the slot is dead, else 0
+  uint8_t pad;
+};
+static_assert(sizeof(dtrace_entry) == 32, "trace entry layout");
+
+struct dtrace_head {
+  uint32_t n_entries;
+  uint32_t n_classes;
+  uint32_t overflow;    // 1 if the trace did not fit (input falls back)
+  uint32_t hang;        // 1 if every thread stops at the end of the trace
+  int64_t coef[MAX_CLASSES][6];  // per class: tid.xyz, bid.xyz coefficients
+  uint8_t cls_w[MAX_CLASSES];
+  uint32_t pad[3];
+};
+// followed by dtrace_entry[trace_cap]
+
+}  // namespace ckc

@@ -1,0 +1,732 @@
+// loader.cpp — host-side loading of index programs: validation, pruning,
+// uniformity and affine-access analysis, register allocation and lowering to
+// the device form of dformat.h.  Pure host code (no HIP calls), so it is
+// tested on machines without a GPU through ckc_analyze_ir().
+//
+// The analysis follows the paper's compile-time passes, applied to the IR:
+//   * pruning keeps only what feeds an index, a branch or a loop bound
+//     (AXIPrune's MathElimination, Section 5.2, Algorithm 2);
+//   * an access is affine when its index is sum_d T_d * coord_d + b with
+//     thread-invariant T and b (the affine-access definition of Section 5.1.1);
+//     the coefficient vector reported per access is a row of the paper's T.
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ckc.h"
+#include "dformat.h"
+#include "loader.h"
+
+namespace ckc {
+namespace {
+
+struct Ins {
+  uint8_t op, w;
+  uint16_t dst, a, b, c, d, s0, s1;
+  int alt = -1, end = -1, depth = 0;  // IF: ELSE; IF/ELSE: ENDIF; LOOP<->ENDLOOP
+  int parent = -1;                    // innermost enclosing IF/ELSE/LOOP pc
+  bool live = false;
+};
+
+bool is_binary(int op) { return op >= CKC_OP_ADD && op <= CKC_OP_CMPLEU; }
+bool is_divrem(int op) {
+  return op == CKC_OP_DIVS || op == CKC_OP_DIVU || op == CKC_OP_REMS || op == CKC_OP_REMU;
+}
+
+// Symbolic component of an affine form: zero, a known constant, a uniform IR
+// register, or some other thread-invariant expression.
+struct Comp {
+  uint8_t kind = 0;  // 0 zero, 1 const, 2 reg, 3 expr
+  int64_t v = 0;
+};
+struct Form {
+  bool affine = false;
+  int k = 0;  // valid modulo 2^k (0 = exact integer)
+  Comp c[7];
+};
+
+int64_t wrapw(int64_t v, int w) { return w == 32 ? (int64_t)(int32_t)(uint32_t)(uint64_t)v : v; }
+
+Comp cadd(Comp x, Comp y, int w) {
+  if (x.kind == 0) return y;
+  if (y.kind == 0) return x;
+  if (x.kind == 1 && y.kind == 1) return Comp{1, wrapw((int64_t)((uint64_t)x.v + (uint64_t)y.v), w)};
+  return Comp{3, 0};
+}
+Comp cneg(Comp x, int w) {
+  if (x.kind == 0) return x;
+  if (x.kind == 1) return Comp{1, wrapw((int64_t)(0 - (uint64_t)x.v), w)};
+  return Comp{3, 0};
+}
+Comp cmul(Comp x, Comp u, int w) {  // u: the uniform factor
+  if (x.kind == 0 || u.kind == 0) return Comp{};
+  if (x.kind == 1 && x.v == 1) return u;
+  if (u.kind == 1 && u.v == 1) return x;
+  if (x.kind == 1 && u.kind == 1) return Comp{1, wrapw((int64_t)((uint64_t)x.v * (uint64_t)u.v), w)};
+  return Comp{3, 0};
+}
+
+struct Analyzer {
+  std::string err;
+  const uint8_t* ir = nullptr;
+  size_t n = 0;
+  int n_instr = 0, n_consts = 0, n_scalars = 0, n_slots = 0, n_accesses = 0, n_sites = 0,
+      n_regs = 0;
+  std::vector<int64_t> consts;
+  std::vector<uint16_t> site_ids;
+  std::vector<Ins> ins;
+  std::vector<int> def_pc;      // per virtual register
+  std::vector<char> uni;        // uniform register
+  std::vector<char> ctrl_var;   // per pc: under thread-dependent control
+  std::vector<Form> form;
+  std::vector<char> indirect;
+  int max_depth = 0;
+
+  bool fail(int pc, const char* what) {
+    err = pc >= 0 ? ("instruction " + std::to_string(pc) + ": " + what) : std::string(what);
+    return false;
+  }
+
+  static uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+
+  bool decode() {
+    if (!ir || n < sizeof(ckc_ir_header)) return fail(-1, "IR shorter than its header");
+    ckc_ir_header h;
+    std::memcpy(&h, ir, sizeof h);
+    if (h.magic != CKC_IR_MAGIC) return fail(-1, "bad magic");
+    if (h.version != CKC_IR_VERSION) return fail(-1, "unsupported IR version");
+    if (h.reserved[0] || h.reserved[1] || h.reserved[2]) return fail(-1, "reserved header bytes not zero");
+    n_instr = h.n_instr; n_consts = h.n_consts; n_scalars = h.n_scalars; n_slots = h.n_slots;
+    n_accesses = h.n_accesses; n_sites = h.n_sites; n_regs = h.n_regs;
+    if (n_instr > (int)CKC_IR_MAX_INSTR || n_consts > (int)CKC_IR_MAX_CONSTS ||
+        n_scalars > (int)CKC_IR_MAX_SCALARS || n_slots > (int)CKC_IR_MAX_SLOTS ||
+        n_accesses > (int)CKC_IR_MAX_ACCESSES || n_sites > (int)CKC_IR_MAX_SITES)
+      return fail(-1, "header count above the supported limit");
+    size_t site_bytes = ((size_t)n_sites * 2 + 7) / 8 * 8;
+    size_t need = sizeof(ckc_ir_header) + (size_t)n_consts * 8 + site_bytes + (size_t)n_instr * 16;
+    if (need != n) return fail(-1, "byte count does not match the header");
+    const uint8_t* p = ir + sizeof(ckc_ir_header);
+    consts.resize(n_consts);
+    for (int i = 0; i < n_consts; i++) std::memcpy(&consts[i], p + 8 * i, 8);
+    p += 8 * (size_t)n_consts;
+    site_ids.resize(n_sites);
+    for (int i = 0; i < n_sites; i++) site_ids[i] = rd16(p + 2 * i);
+    p += site_bytes;
+    ins.resize(n_instr);
+    for (int i = 0; i < n_instr; i++) {
+      const uint8_t* q = p + 16 * (size_t)i;
+      Ins& I = ins[i];
+      I.op = q[0]; I.w = q[1];
+      I.dst = rd16(q + 2); I.a = rd16(q + 4); I.b = rd16(q + 6); I.c = rd16(q + 8);
+      I.d = rd16(q + 10); I.s0 = rd16(q + 12); I.s1 = rd16(q + 14);
+    }
+    return true;
+  }
+
+  // Structure, SSA and scoping rules of ckc_ir.h.
+  bool validate() {
+    std::vector<char> id_seen(65536, 0), site_used(n_sites, 0), acc_used(n_accesses, 0);
+    for (int i = 0; i < n_sites; i++) {
+      if (id_seen[site_ids[i]]) return fail(-1, "duplicate coverage-map id");
+      id_seen[site_ids[i]] = 1;
+    }
+    def_pc.assign(n_regs, -1);
+    std::vector<int> def_scope(n_regs, -1);
+    std::vector<char> scope_open(1, 1);
+    std::vector<int> scope_stack{0}, ctl;
+    int loop_depth = 0;
+    auto use = [&](int pc, unsigned r) {
+      if ((int)r >= n_regs || def_scope[r] < 0 || !scope_open[def_scope[r]])
+        return fail(pc, "register used before definition or outside its scope");
+      return true;
+    };
+    auto def = [&](int pc, unsigned r) {
+      if ((int)r >= n_regs || def_scope[r] != -1) return fail(pc, "register defined twice or out of range");
+      def_scope[r] = scope_stack.back();
+      def_pc[r] = pc;
+      return true;
+    };
+    auto site = [&](int pc, unsigned s) {
+      if (s == CKC_IR_NO_SITE) return true;
+      if ((int)s >= n_sites || site_used[s]) return fail(pc, "site index out of range or reused");
+      site_used[s] = 1;
+      return true;
+    };
+    auto width = [&](int pc, int w) { return (w == 32 || w == 64) ? true : fail(pc, "width must be 32 or 64"); };
+    auto open_scope = [&]() {
+      scope_open.push_back(1);
+      scope_stack.push_back((int)scope_open.size() - 1);
+    };
+    auto close_scope = [&]() {
+      scope_open[scope_stack.back()] = 0;
+      scope_stack.pop_back();
+    };
+    for (int i = 0; i < n_instr; i++) {
+      Ins& I = ins[i];
+      I.depth = loop_depth;
+      I.parent = ctl.empty() ? -1 : ctl.back();
+      switch (I.op) {
+        case CKC_OP_CONST:
+          if (!width(i, I.w)) return false;
+          if (I.a >= n_consts) return fail(i, "constant index out of range");
+          if (!def(i, I.dst)) return false;
+          break;
+        case CKC_OP_SCALAR:
+          if (!width(i, I.w)) return false;
+          if (I.a >= n_scalars) return fail(i, "scalar index out of range");
+          if (!def(i, I.dst)) return false;
+          break;
+        case CKC_OP_SPECIAL:
+          if (I.a > 11) return fail(i, "unknown special source");
+          if (!def(i, I.dst)) return false;
+          break;
+        case CKC_OP_SELECT:
+          if (!width(i, I.w) || !use(i, I.a) || !use(i, I.b) || !use(i, I.c) || !def(i, I.dst)) return false;
+          break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC:
+          if (!use(i, I.a) || !def(i, I.dst)) return false;
+          break;
+        case CKC_OP_ACCESS:
+        case CKC_OP_LOAD:
+          if (!width(i, I.w) || !use(i, I.a)) return false;
+          if (I.b >= n_accesses || acc_used[I.b]) return fail(i, "access id out of range or reused");
+          acc_used[I.b] = 1;
+          if (I.c >= n_slots) return fail(i, "allocation slot out of range");
+          if (I.op == CKC_OP_ACCESS) {
+            if (I.d > 7) return fail(i, "bad ACCESS flags");
+          } else {
+            if (I.d != 2 && I.d != 3) return fail(i, "LOAD element must be 4 or 8 bytes");
+            if (!def(i, I.dst)) return false;
+          }
+          if (!site(i, I.s0)) return false;
+          break;
+        case CKC_OP_IF:
+          if (!use(i, I.a) || !site(i, I.s0) || !site(i, I.s1)) return false;
+          if (ctl.size() >= CKC_IR_MAX_NEST) return fail(i, "nesting deeper than 16");
+          ctl.push_back(i);
+          open_scope();
+          break;
+        case CKC_OP_ELSE:
+          if (ctl.empty() || ins[ctl.back()].op != CKC_OP_IF || ins[ctl.back()].alt >= 0)
+            return fail(i, "ELSE without an open IF");
+          ins[ctl.back()].alt = i;
+          I.parent = ctl.back();
+          close_scope();
+          open_scope();
+          ctl.back() = i;  // else-arm instructions hang off the ELSE
+          break;
+        case CKC_OP_ENDIF: {
+          if (ctl.empty() || (ins[ctl.back()].op != CKC_OP_IF && ins[ctl.back()].op != CKC_OP_ELSE))
+            return fail(i, "ENDIF without an open IF");
+          int t = ctl.back();
+          ctl.pop_back();
+          int f = ins[t].op == CKC_OP_ELSE ? ins[t].parent : t;
+          ins[f].end = i;
+          if (ins[f].alt >= 0) ins[ins[f].alt].end = i;
+          I.parent = f;
+          close_scope();
+          break;
+        }
+        case CKC_OP_LOOP:
+          if (!width(i, I.w) || !use(i, I.a) || !use(i, I.b) || !use(i, I.c)) return false;
+          if (!site(i, I.s0) || !site(i, I.s1)) return false;
+          if (ctl.size() >= CKC_IR_MAX_NEST) return fail(i, "nesting deeper than 16");
+          if (loop_depth >= (int)CKC_IR_MAX_LOOP_DEPTH) return fail(i, "loops nested deeper than 2");
+          ctl.push_back(i);
+          loop_depth++;
+          if (loop_depth > max_depth) max_depth = loop_depth;
+          open_scope();
+          if (!def(i, I.dst)) return false;
+          break;
+        case CKC_OP_ENDLOOP: {
+          if (ctl.empty() || ins[ctl.back()].op != CKC_OP_LOOP) return fail(i, "ENDLOOP without an open LOOP");
+          int f = ctl.back();
+          ctl.pop_back();
+          ins[f].end = i;
+          I.end = f;
+          I.parent = f;
+          loop_depth--;
+          close_scope();
+          break;
+        }
+        default:
+          if (!is_binary(I.op)) return fail(i, "unknown opcode");
+          if (!width(i, I.w) || !use(i, I.a) || !use(i, I.b) || !def(i, I.dst)) return false;
+          break;
+      }
+    }
+    if (!ctl.empty()) return fail(-1, "unclosed IF or LOOP");
+    for (int a = 0; a < n_accesses; a++)
+      if (!acc_used[a]) return fail(-1, "an access id is never used");
+    return true;
+  }
+
+  // Pruning: keep accesses, control flow, divisions (they count faults) and
+  // everything that feeds them; one backward pass suffices because every
+  // definition precedes its uses.
+  void prune() {
+    std::vector<char> reg_live(n_regs, 0);
+    for (int i = n_instr - 1; i >= 0; i--) {
+      Ins& I = ins[i];
+      bool root = I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD || I.op >= CKC_OP_IF || is_divrem(I.op);
+      bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF;
+      I.live = root || (defines && I.dst < n_regs && reg_live[I.dst]);
+      if (!I.live) continue;
+      auto mark = [&](uint16_t r) { if (r < n_regs) reg_live[r] = 1; };
+      switch (I.op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
+        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP:
+          break;
+        case CKC_OP_SELECT: case CKC_OP_LOOP: mark(I.a); mark(I.b); mark(I.c); break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
+        case CKC_OP_LOAD: case CKC_OP_IF: mark(I.a); break;
+        default: mark(I.a); mark(I.b); break;
+      }
+    }
+  }
+
+  bool reg_used(int r) const {
+    for (int i = def_pc[r] + 1; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live) continue;
+      switch (I.op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
+        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
+        case CKC_OP_SELECT: case CKC_OP_LOOP:
+          if (I.a == r || I.b == r || I.c == r) return true;
+          break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
+        case CKC_OP_LOAD: case CKC_OP_IF:
+          if (I.a == r) return true;
+          break;
+        default:
+          if (I.a == r || I.b == r) return true;
+      }
+    }
+    return false;
+  }
+
+  // Uniformity (thread-invariance) of values and control, and the affine
+  // form of every value over (tid.xyz, bid.xyz).
+  void classify() {
+    uni.assign(n_regs, 0);
+    indirect.assign(n_regs, 0);
+    form.assign(n_regs, Form{});
+    ctrl_var.assign(n_instr, 0);
+    std::vector<char> cvar_stack{0};
+    auto uform = [&](int r, int pc) {  // form of a uniform register
+      Form f;
+      f.affine = true;
+      f.k = 0;
+      const Ins& I = ins[pc];
+      if (I.op == CKC_OP_CONST) f.c[6] = Comp{1, wrapw(consts[I.a], I.w)};
+      else if (I.op == CKC_OP_SCALAR || I.op == CKC_OP_SPECIAL) f.c[6] = Comp{2, r};
+      else f.c[6] = Comp{3, 0};
+      return f;
+    };
+    auto usable = [&](int r, int w) {
+      const Form& f = form[r];
+      return f.affine && (uni[r] || f.k == 0 || f.k >= w);
+    };
+    for (int i = 0; i < n_instr; i++) {
+      Ins& I = ins[i];
+      // control context of this instruction
+      ctrl_var[i] = cvar_stack.back();
+      if (I.op == CKC_OP_ELSE || I.op == CKC_OP_ENDIF || I.op == CKC_OP_ENDLOOP) {
+        cvar_stack.pop_back();
+        if (I.op == CKC_OP_ELSE) cvar_stack.push_back(cvar_stack.back() || !uni[ins[I.parent].a]);
+        ctrl_var[i] = cvar_stack.back();
+        continue;
+      }
+      if (I.op == CKC_OP_IF) {
+        cvar_stack.push_back(cvar_stack.back() || !uni[I.a]);
+        continue;
+      }
+      int r = I.dst;
+      switch (I.op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR:
+          uni[r] = 1; form[r] = uform(r, i);
+          break;
+        case CKC_OP_SPECIAL:
+          if (I.a >= 6) { uni[r] = 1; form[r] = uform(r, i); }
+          else {
+            Form f; f.affine = true; f.k = 0; f.c[I.a] = Comp{1, 1};
+            form[r] = f;
+          }
+          break;
+        case CKC_OP_LOAD:
+          uni[r] = uni[I.a];
+          if (uni[r]) form[r] = uform(r, i);
+          else indirect[r] = 1;
+          break;
+        case CKC_OP_LOOP: {
+          bool u = uni[I.a] && uni[I.b] && uni[I.c];
+          uni[r] = u;
+          if (u) form[r] = uform(r, i);
+          cvar_stack.push_back(cvar_stack.back() || !u);
+          break;
+        }
+        case CKC_OP_ACCESS:
+          break;
+        default: {
+          bool u = uni[I.a] && (I.op == CKC_OP_SEXT || I.op == CKC_OP_ZEXT || I.op == CKC_OP_TRUNC ||
+                                (uni[I.b] && (I.op != CKC_OP_SELECT || uni[I.c])));
+          uni[r] = u;
+          indirect[r] = indirect[I.a] || (I.op != CKC_OP_SEXT && I.op != CKC_OP_ZEXT &&
+                                          I.op != CKC_OP_TRUNC && indirect[I.b]) ||
+                        (I.op == CKC_OP_SELECT && indirect[I.c]);
+          if (u) { form[r] = uform(r, i); break; }
+          Form f;
+          int w = I.w;
+          if ((I.op == CKC_OP_ADD || I.op == CKC_OP_SUB) && usable(I.a, w) && usable(I.b, w)) {
+            f.affine = true; f.k = w;
+            for (int d = 0; d < 7; d++)
+              f.c[d] = cadd(form[I.a].c[d], I.op == CKC_OP_SUB ? cneg(form[I.b].c[d], w) : form[I.b].c[d], w);
+          } else if ((I.op == CKC_OP_MUL || I.op == CKC_OP_SHL) && usable(I.a, w) && usable(I.b, w) &&
+                     (uni[I.a] || uni[I.b])) {
+            int v = uni[I.b] ? I.a : I.b, u2 = uni[I.b] ? I.b : I.a;
+            if (I.op == CKC_OP_SHL && !uni[I.b]) { form[r] = f; break; }  // varying shift amount
+            Comp factor = form[u2].c[6];
+            if (I.op == CKC_OP_SHL)
+              factor = factor.kind == 1 ? Comp{1, wrapw((int64_t)(1ull << ((uint64_t)factor.v & (w - 1))), w)}
+                                        : Comp{3, 0};
+            f.affine = true; f.k = w;
+            for (int d = 0; d < 7; d++) f.c[d] = cmul(form[v].c[d], factor, w);
+          } else if (I.op == CKC_OP_TRUNC && form[I.a].affine) {
+            f = form[I.a];
+            f.k = 32;
+          }
+          form[r] = f;
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------------
+  // register allocation (linear scan over live values)
+  std::vector<int> phys;  // per virtual register, -1 if none
+  int n_phys = 0;
+
+  bool allocate() {
+    std::vector<int> last(n_regs, -1);
+    auto touch = [&](int r, int pc) {
+      if (r >= n_regs) return;
+      // a use inside loops that do not contain the definition keeps the value
+      // alive to the end of the outermost such loop
+      int end = pc;
+      for (int p = ins[pc].parent; p >= 0; p = ins[p].parent) {
+        const Ins& P = ins[p];
+        if (P.op == CKC_OP_LOOP && def_pc[r] < p) end = std::max(end, P.end);
+      }
+      last[r] = std::max(last[r], end);
+    };
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live) continue;
+      switch (I.op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
+        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
+        case CKC_OP_SELECT: case CKC_OP_LOOP: touch(I.a, i); touch(I.b, i); touch(I.c, i); break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
+        case CKC_OP_LOAD: case CKC_OP_IF: touch(I.a, i); break;
+        default: touch(I.a, i); touch(I.b, i); break;
+      }
+    }
+    // a loop counter lives through its whole body
+    for (int i = 0; i < n_instr; i++)
+      if (ins[i].live && ins[i].op == CKC_OP_LOOP) last[ins[i].dst] = std::max(last[ins[i].dst], ins[i].end);
+    phys.assign(n_regs, -1);
+    std::vector<int> busy_until(NREG, -1);
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live) continue;
+      bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF ? true : I.op == CKC_OP_LOOP;
+      if (!defines || I.dst >= n_regs) continue;
+      int r = I.dst;
+      int end = last[r] < 0 ? i : last[r];
+      int got = -1;
+      for (int p = 0; p < NREG; p++)
+        if (busy_until[p] < i) { got = p; break; }
+      // operands whose interval ends exactly here may share the register
+      if (got < 0) {
+        for (int p = 0; p < NREG; p++)
+          if (busy_until[p] == i) { got = p; break; }
+      }
+      if (got < 0) return fail(i, "program needs more than 32 live registers");
+      phys[r] = got;
+      busy_until[got] = end;
+      n_phys = std::max(n_phys, got + 1);
+    }
+    return true;
+  }
+
+  // ------------------------------------------------------------------------
+  // lowering
+  int expand_pc = -1;
+  std::vector<int> livein;
+
+  bool body_has_loop(int lp) const {
+    for (int i = lp + 1; i < ins[lp].end; i++)
+      if (ins[i].live && ins[i].op == CKC_OP_LOOP) return true;
+    return false;
+  }
+
+  void choose_expansion(bool uniform_prog) {
+    if (uniform_prog) return;
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live || I.op != CKC_OP_LOOP || I.depth != 0) continue;
+      if (uni[I.dst]) continue;  // uniform trip count: nothing to balance
+      if (body_has_loop(i)) continue;
+      // registers read by the body and defined before the loop
+      std::vector<int> li;
+      for (int j = i + 1; j < I.end; j++) {
+        const Ins& J = ins[j];
+        if (!J.live) continue;
+        uint16_t ops[3] = {CKC_IR_NO_REG, CKC_IR_NO_REG, CKC_IR_NO_REG};
+        switch (J.op) {
+          case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
+          case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
+          case CKC_OP_SELECT: ops[0] = J.a; ops[1] = J.b; ops[2] = J.c; break;
+          case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
+          case CKC_OP_LOAD: case CKC_OP_IF: ops[0] = J.a; break;
+          default: ops[0] = J.a; ops[1] = J.b; break;
+        }
+        for (uint16_t r : ops) {
+          if (r >= n_regs || r == I.dst || def_pc[r] >= i) continue;
+          int p = phys[r];
+          bool have = false;
+          for (int q : li) have |= q == p;
+          if (!have) li.push_back(p);
+        }
+      }
+      if ((int)li.size() > MAX_LIVEIN) continue;
+      expand_pc = i;
+      livein = li;
+      return;
+    }
+  }
+
+  std::vector<uint8_t> lower(uint32_t cls, uint32_t trace_cap, int* n_live_out) {
+    std::vector<int> newpc(n_instr, -1);
+    int m = 0;
+    for (int i = 0; i < n_instr; i++)
+      if (ins[i].live) newpc[i] = m++;
+    *n_live_out = m;
+    std::vector<int> cmap(n_consts, -1);
+    std::vector<int64_t> dconsts;
+    std::vector<dins> out(m);
+    std::vector<daccess> acc(n_accesses);
+    // IFs enclosing the expanded loop are never skipped
+    std::vector<char> noskip(n_instr, 0);
+    if (expand_pc >= 0)
+      for (int p = ins[expand_pc].parent; p >= 0; p = ins[p].parent) {
+        noskip[p] = 1;
+        if (ins[p].op == CKC_OP_ELSE) noskip[ins[p].parent] = 1;
+      }
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live) continue;
+      dins D;
+      std::memset(&D, 0, sizeof D);
+      D.op = I.op;
+      D.w = I.w;
+      D.s0 = I.s0; D.s1 = I.s1;
+      auto P = [&](uint16_t r) -> uint8_t { return r < n_regs && phys[r] >= 0 ? (uint8_t)phys[r] : 0; };
+      switch (I.op) {
+        case CKC_OP_CONST: {
+          if (cmap[I.a] < 0) { cmap[I.a] = (int)dconsts.size(); dconsts.push_back(consts[I.a]); }
+          D.dst = P(I.dst); D.x = (uint16_t)cmap[I.a];
+          break;
+        }
+        case CKC_OP_SCALAR: case CKC_OP_SPECIAL: D.dst = P(I.dst); D.x = I.a; D.w = I.op == CKC_OP_SPECIAL ? 64 : I.w; break;
+        case CKC_OP_SELECT: D.dst = P(I.dst); D.a = P(I.a); D.b = P(I.b); D.c = P(I.c); break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: D.dst = P(I.dst); D.a = P(I.a); break;
+        case CKC_OP_ACCESS: case CKC_OP_LOAD: {
+          D.a = P(I.a); D.slot = (uint8_t)I.c; D.x = I.b;
+          D.fl = (uint8_t)(I.op == CKC_OP_ACCESS ? (I.d & 3) : I.d);
+          D.dst = I.op == CKC_OP_LOAD ? P(I.dst) : 0;
+          daccess& A = acc[I.b];
+          A.pc = (uint16_t)newpc[i];
+          A.depth = (uint16_t)I.depth;
+          A.loop_pc[0] = A.loop_pc[1] = -1;
+          int lv = I.depth;
+          for (int p = I.parent; p >= 0; p = ins[p].parent)
+            if (ins[p].op == CKC_OP_LOOP) A.loop_pc[--lv] = (int16_t)newpc[p];
+          break;
+        }
+        case CKC_OP_IF:
+          D.a = P(I.a);
+          D.jmp = (uint16_t)newpc[I.alt >= 0 ? I.alt : I.end];
+          D.fl = (uint8_t)((noskip[i] ? DI_NOSKIP : 0) | (I.alt >= 0 ? DI_HASELSE : 0));
+          break;
+        case CKC_OP_ELSE: D.jmp = (uint16_t)newpc[I.end]; D.fl = noskip[I.parent] ? DI_NOSKIP : 0; break;
+        case CKC_OP_ENDIF: break;
+        case CKC_OP_LOOP:
+          D.dst = P(I.dst); D.a = P(I.a); D.b = P(I.b); D.c = P(I.c);
+          D.x = (uint16_t)I.depth;
+          D.jmp = (uint16_t)newpc[I.end];
+          D.fl = (uint8_t)(i == expand_pc ? (DI_EXPAND | DI_NOSKIP) : 0);
+          break;
+        case CKC_OP_ENDLOOP: D.jmp = (uint16_t)newpc[I.end]; D.x = (uint16_t)ins[I.end].depth; break;
+        default: D.dst = P(I.dst); D.a = P(I.a); D.b = P(I.b); break;
+      }
+      out[newpc[i]] = D;
+    }
+    auto al = [](uint32_t v) { return (v + 15u) & ~15u; };
+    dprog h;
+    std::memset(&h, 0, sizeof h);
+    h.n_instr = (uint32_t)m;
+    h.n_consts = (uint32_t)dconsts.size();
+    h.n_accesses = (uint32_t)n_accesses;
+    h.n_sites = (uint32_t)n_sites;
+    h.n_slots = (uint32_t)n_slots;
+    h.n_scalars = (uint32_t)n_scalars;
+    h.max_depth = (uint32_t)max_depth;
+    h.cls = cls;
+    h.n_regs = (uint32_t)n_phys;
+    h.expand_pc = expand_pc >= 0 ? newpc[expand_pc] : -1;
+    h.n_livein = (uint32_t)livein.size();
+    for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
+    h.trace_cap = trace_cap;
+    h.off_instr = al(sizeof(dprog));
+    h.off_consts = al(h.off_instr + 16u * m);
+    h.off_access = al(h.off_consts + 8u * h.n_consts);
+    h.off_sites = al(h.off_access + (uint32_t)sizeof(daccess) * n_accesses);
+    h.total_bytes = al(h.off_sites + 2u * n_sites);
+    std::vector<uint8_t> blob(h.total_bytes, 0);
+    std::memcpy(blob.data(), &h, sizeof h);
+    if (m) std::memcpy(blob.data() + h.off_instr, out.data(), 16u * m);
+    if (!dconsts.empty()) std::memcpy(blob.data() + h.off_consts, dconsts.data(), 8u * dconsts.size());
+    if (n_accesses) std::memcpy(blob.data() + h.off_access, acc.data(), sizeof(daccess) * n_accesses);
+    if (n_sites) std::memcpy(blob.data() + h.off_sites, site_ids.data(), 2u * n_sites);
+    return blob;
+  }
+
+  // Static upper bound of the per-thread access count of a uniform program,
+  // when every loop around an access has constant bounds; else 0 (unknown).
+  uint64_t static_trace_len() const {
+    auto cval = [&](uint16_t r, int w, int64_t* v) {
+      int p = def_pc[r];
+      if (p < 0 || ins[p].op != CKC_OP_CONST) return false;
+      *v = wrapw(consts[ins[p].a], w);
+      return true;
+    };
+    uint64_t total = 0;
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live || (I.op != CKC_OP_ACCESS && I.op != CKC_OP_LOAD)) continue;
+      uint64_t mult = 1;
+      for (int p = I.parent; p >= 0; p = ins[p].parent) {
+        const Ins& L = ins[p];
+        if (L.op != CKC_OP_LOOP) continue;
+        int64_t s, e, st;
+        if (!cval(L.a, L.w, &s) || !cval(L.b, L.w, &e) || !cval(L.c, L.w, &st)) return 0;
+        uint64_t n = 0;
+        if (st > 0 && s < e) n = ((uint64_t)e - (uint64_t)s + (uint64_t)st - 1) / (uint64_t)st;
+        else if (st < 0 && s > e) n = ((uint64_t)s - (uint64_t)e + (0 - (uint64_t)st) - 1) / (0 - (uint64_t)st);
+        else if (st == 0 && s < e) return 0;
+        mult *= n;
+        if (mult > (1u << 20)) return 0;
+      }
+      total += mult;
+      if (total > (1u << 20)) return 0;
+    }
+    return total;
+  }
+};
+
+}  // namespace
+
+int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
+  Analyzer A;
+  A.ir = (const uint8_t*)ir;
+  A.n = ir_bytes;
+  if (!A.decode() || !A.validate()) {
+    out->err = A.err;
+    return CKC_E_IR;
+  }
+  A.prune();
+  A.classify();
+  if (!A.allocate()) {
+    out->err = A.err;
+    return CKC_E_IR;
+  }
+  // per-access facts and the program class
+  out->acc.assign(A.n_accesses, ckc_access_info{});
+  bool all_affine = true, any_guard = false, any_ind = false, any64 = false;
+  for (int i = 0; i < A.n_instr; i++) {
+    const Ins& I = A.ins[i];
+    if (I.op != CKC_OP_ACCESS && I.op != CKC_OP_LOAD) continue;
+    ckc_access_info& ai = out->acc[I.b];
+    ai.access_id = I.b;
+    ai.slot = I.c;
+    ai.log2_elem = I.op == CKC_OP_ACCESS ? (I.d & 3u) : I.d;
+    ai.width = I.w;
+    const Form& f = A.form[I.a];
+    bool aff = f.affine && (A.uni[I.a] || f.k == 0 || f.k >= I.w);
+    ai.affine = aff;
+    ai.guarded = A.ctrl_var[i];
+    ai.indirect = A.indirect[I.a];
+    ai.loop_depth = I.depth;
+    for (int d = 0; d < 7; d++)
+      ai.coef[d] = aff ? ((uint64_t)f.c[d].kind << 32) | (uint32_t)f.c[d].v : (3ull << 32);
+    all_affine &= aff;
+    any_guard |= (bool)ai.guarded;
+    any_ind |= (bool)ai.indirect;
+    any64 |= I.w == 64;
+  }
+  // uniform-trace eligibility: thread-invariant control, affine indices, and
+  // every live thread-dependent value that is used is affine
+  bool any_var_ctrl = false, var_ok = true;
+  for (int i = 0; i < A.n_instr; i++) {
+    const Ins& I = A.ins[i];
+    if (!I.live) continue;
+    if (I.op == CKC_OP_IF && !A.uni[I.a]) any_var_ctrl = true;
+    if (I.op == CKC_OP_LOOP && !A.uni[I.dst]) any_var_ctrl = true;
+    bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF;
+    if (defines && I.dst < A.n_regs && !A.uni[I.dst]) {
+      if (is_divrem(I.op)) var_ok = false;
+      else if (!A.form[I.dst].affine && A.reg_used(I.dst)) var_ok = false;
+    }
+  }
+  bool uniform_prog = all_affine && !any_var_ctrl && var_ok;
+  uint32_t cls = (all_affine ? CKC_CLS_AFFINE : 0) | (any_guard ? CKC_CLS_GUARDED : 0) |
+                 (any_ind ? CKC_CLS_INDIRECT : 0) | (any64 ? CKC_CLS_I64 : 0) |
+                 (uniform_prog ? CKC_CLS_UNIFORM : 0);
+  A.choose_expansion(uniform_prog);
+  if (A.expand_pc >= 0) cls |= CKC_CLS_EXPANDED;
+  uint32_t trace_cap = 0;
+  if (uniform_prog) {
+    uint64_t s = A.static_trace_len();
+    trace_cap = s ? (uint32_t)std::min<uint64_t>(s, 4096) : 256;
+    if (trace_cap == 0) trace_cap = 1;
+  }
+  int n_live = 0;
+  out->blob = A.lower(cls, trace_cap, &n_live);
+  if (n_live > MAX_DINSTR) {
+    out->err = "program has more than 1024 instructions after pruning";
+    return CKC_E_IR;
+  }
+  const dprog* h = (const dprog*)out->blob.data();
+  if (h->n_consts > (uint32_t)MAX_DCONST) {
+    out->err = "program uses more than 256 constants";
+    return CKC_E_IR;
+  }
+  std::memset(&out->info, 0, sizeof out->info);
+  out->info.n_accesses = A.n_accesses;
+  out->info.n_sites = A.n_sites;
+  out->info.n_slots = A.n_slots;
+  out->info.n_scalars = A.n_scalars;
+  out->info.max_loop_depth = A.max_depth;
+  out->info.cls = cls;
+  out->info.n_instr_live = n_live;
+  out->info.n_regs_phys = A.n_phys;
+  out->load_slots = 0;
+  for (int i = 0; i < A.n_instr; i++)
+    if (A.ins[i].op == CKC_OP_LOAD) out->load_slots |= 1u << A.ins[i].c;
+  return CKC_OK;
+}
+
+}  // namespace ckc

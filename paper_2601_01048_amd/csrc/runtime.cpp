@@ -1,0 +1,417 @@
+// runtime.cpp — the C-ABI of libckc (include/ckc.h): contexts, programs,
+// allocation tables, jobs.  Host code; every step of a check runs in the
+// kernels of kernels.hip, queued on one HIP stream per job.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ckc.h"
+#include "dformat.h"
+#include "kernels.h"
+#include "loader.h"
+
+using namespace ckc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHECK(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return fail(CKC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));         \
+  } while (0)
+
+struct Program {
+  void* dblob = nullptr;
+  Loaded L;
+  int busy = 0;
+};
+
+struct Table {
+  void* dptr = nullptr;
+  std::vector<ckc_alloc> host;
+  int busy = 0;
+};
+
+struct Job {
+  hipStream_t stream = nullptr;
+  std::vector<void*> bufs;
+  dinput* d_inputs = nullptr;
+  ckc_record* d_recs = nullptr;
+  uint32_t* d_counts = nullptr;
+  ckc_input_status* d_status = nullptr;
+  uint8_t* d_maps = nullptr;
+  uint64_t n_inputs = 0, n_records = 0;
+  std::vector<uint32_t> progs, tables;
+  hipEvent_t ev[5] = {};
+  bool dense = false;
+};
+
+}  // namespace
+
+struct ckc_ctx_s {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  uint32_t next_prog = 1, next_table = 1;
+  uint64_t next_job = 1;
+  std::map<uint32_t, Program> progs;
+  std::map<uint32_t, Table> tables;
+  std::map<uint64_t, Job> jobs;
+  int n_cu = 256;
+};
+
+namespace {
+
+int set_device(ckc_ctx c) {
+  HIPCHECK(hipSetDevice(c->dev));
+  return CKC_OK;
+}
+
+void free_job(ckc_ctx c, Job& J) {
+  for (void* p : J.bufs) hipFree(p);
+  J.bufs.clear();
+  for (auto& e : J.ev)
+    if (e) hipEventDestroy(e);
+  for (uint32_t p : J.progs) {
+    auto it = c->progs.find(p);
+    if (it != c->progs.end()) it->second.busy--;
+  }
+  for (uint32_t t : J.tables) {
+    auto it = c->tables.find(t);
+    if (it != c->tables.end()) it->second.busy--;
+  }
+}
+
+template <class T>
+int dalloc(Job& J, T** out, size_t count) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(CKC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  J.bufs.push_back(p);
+  *out = (T*)p;
+  return CKC_OK;
+}
+
+unsigned bits_of(uint64_t n) {  // bits needed for values 0..n-1
+  unsigned b = 0;
+  while (b < 64 && (n - 1) >> b) b++;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ckc_last_error(void) { return g_err.c_str(); }
+
+int ckc_init(int hip_device, ckc_ctx* out) {
+  if (!out) return fail(CKC_E_INVALID, "out is NULL");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n)
+    return fail(CKC_E_INVALID, "no such HIP device");
+  ckc_ctx c = new (std::nothrow) ckc_ctx_s;
+  if (!c) return fail(CKC_E_NOMEM, "context");
+  c->dev = hip_device;
+  hipError_t e = hipSetDevice(hip_device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(CKC_E_HIP, std::string("context stream: ") + hipGetErrorString(e));
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  *out = c;
+  return CKC_OK;
+}
+
+void ckc_shutdown(ckc_ctx c) {
+  if (!c) return;
+  hipSetDevice(c->dev);
+  for (auto& kv : c->jobs) {
+    if (kv.second.stream) hipStreamSynchronize(kv.second.stream);
+    free_job(c, kv.second);
+  }
+  c->jobs.clear();
+  for (auto& kv : c->progs) hipFree(kv.second.dblob);
+  for (auto& kv : c->tables) hipFree(kv.second.dptr);
+  if (c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int ckc_analyze_ir(const void* ir, size_t ir_bytes, ckc_prog_info* info, ckc_access_info* acc,
+                   uint32_t acc_capacity) {
+  Loaded L;
+  int rc = analyze_program(ir, ir_bytes, &L);
+  if (rc != CKC_OK) return fail(rc, L.err);
+  if (info) *info = L.info;
+  if (acc) {
+    uint32_t n = std::min<uint32_t>(acc_capacity, (uint32_t)L.acc.size());
+    std::memcpy(acc, L.acc.data(), n * sizeof(ckc_access_info));
+  }
+  return CKC_OK;
+}
+
+int ckc_load_program(ckc_ctx c, const void* ir, size_t ir_bytes, uint32_t* prog_id, ckc_prog_info* info) {
+  if (!c || !prog_id) return fail(CKC_E_INVALID, "NULL argument");
+  Program P;
+  int rc = analyze_program(ir, ir_bytes, &P.L);
+  if (rc != CKC_OK) return fail(rc, P.L.err);
+  if ((rc = set_device(c))) return rc;
+  hipError_t e = hipMalloc(&P.dblob, P.L.blob.size());
+  if (e != hipSuccess) return fail(CKC_E_NOMEM, "program upload");
+  e = hipMemcpy(P.dblob, P.L.blob.data(), P.L.blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(P.dblob);
+    return fail(CKC_E_HIP, std::string("program upload: ") + hipGetErrorString(e));
+  }
+  uint32_t id = c->next_prog++;
+  if (info) *info = P.L.info;
+  c->progs.emplace(id, std::move(P));
+  *prog_id = id;
+  return CKC_OK;
+}
+
+int ckc_unload_program(ckc_ctx c, uint32_t prog_id) {
+  if (!c) return fail(CKC_E_INVALID, "NULL context");
+  auto it = c->progs.find(prog_id);
+  if (it == c->progs.end()) return fail(CKC_E_INVALID, "unknown program id");
+  if (it->second.busy) return fail(CKC_E_BUSY, "program used by an unread job");
+  set_device(c);
+  hipFree(it->second.dblob);
+  c->progs.erase(it);
+  return CKC_OK;
+}
+
+int ckc_put_alloc_table(ckc_ctx c, const ckc_alloc* entries, uint32_t n, uint32_t* table_id) {
+  if (!c || !entries || !table_id) return fail(CKC_E_INVALID, "NULL argument");
+  if (n == 0 || n > CKC_IR_MAX_SLOTS) return fail(CKC_E_INVALID, "a table holds 1..16 entries");
+  int rc;
+  if ((rc = set_device(c))) return rc;
+  Table T;
+  T.host.assign(entries, entries + n);
+  T.host.resize(MAX_SLOTS, ckc_alloc{0, 0, nullptr, 0, 0});
+  hipError_t e = hipMalloc(&T.dptr, sizeof(ckc_alloc) * MAX_SLOTS);
+  if (e != hipSuccess) return fail(CKC_E_NOMEM, "table");
+  e = hipMemcpy(T.dptr, T.host.data(), sizeof(ckc_alloc) * MAX_SLOTS, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(T.dptr);
+    return fail(CKC_E_HIP, std::string("table upload: ") + hipGetErrorString(e));
+  }
+  T.host.resize(n);
+  uint32_t id = c->next_table++;
+  c->tables.emplace(id, std::move(T));
+  *table_id = id;
+  return CKC_OK;
+}
+
+int ckc_free_alloc_table(ckc_ctx c, uint32_t table_id) {
+  if (!c) return fail(CKC_E_INVALID, "NULL context");
+  auto it = c->tables.find(table_id);
+  if (it == c->tables.end()) return fail(CKC_E_INVALID, "unknown table id");
+  if (it->second.busy) return fail(CKC_E_BUSY, "table used by an unread job");
+  set_device(c);
+  hipFree(it->second.dptr);
+  c->tables.erase(it);
+  return CKC_OK;
+}
+
+int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts* opts,
+                    uint64_t* job) {
+  if (!c || !descs || !job || n_descs == 0) return fail(CKC_E_INVALID, "NULL argument or no descriptor");
+  ckc_launch_opts O;
+  std::memset(&O, 0, sizeof O);
+  if (opts) O = *opts;
+  // ---- validate and build the input list on the host (copies only) ----
+  std::vector<dinput> hin;
+  std::vector<int64_t> hsc;
+  uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
+  for (uint32_t k = 0; k < n_descs; k++) {
+    const ckc_batch& B = descs[k];
+    auto pit = c->progs.find(B.prog_id);
+    if (pit == c->progs.end()) return fail(CKC_E_INVALID, "descriptor " + std::to_string(k) + ": unknown program");
+    if (B.n_inputs && (!B.launch || !B.table_ids)) return fail(CKC_E_INVALID, "descriptor arrays missing");
+    const Program& P = pit->second;
+    const dprog* h = (const dprog*)P.L.blob.data();
+    if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, "scalars missing");
+    if (B.mode > CKC_REP_BOUNDARY) return fail(CKC_E_INVALID, "unknown mode");
+    uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
+    if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
+    if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, "loop cap above 2^32");
+    unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
+    for (uint32_t i = 0; i < B.n_inputs; i++) {
+      const uint32_t* L = B.launch + 6 * (size_t)i;
+      uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
+      if (bs > 1024) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": block above 1024 threads");
+      if (nb > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": grid of 2^32 blocks or more");
+      uint64_t nthr = nb * bs;
+      if (nthr > 1 && bits_of(nthr) + L1 + L2 > 64)
+        return fail(CKC_E_RANGE, "input " + std::to_string(i) + ": first-violation key needs more than 64 bits");
+      auto tit = c->tables.find(B.table_ids[i]);
+      if (tit == c->tables.end()) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": unknown table");
+      const Table& T = tit->second;
+      if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": table has fewer slots than the program");
+      for (uint32_t s = 0; s < h->n_slots; s++) {
+        const ckc_alloc& A = T.host[s];
+        if ((P.L.load_slots >> s & 1u) && A.base != 0 && !(A.flags & CKC_ALLOC_FREED) && A.size_bytes > 0 &&
+            A.data == nullptr)
+          return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": slot " + std::to_string(s) + " is loaded but has no data");
+      }
+      dinput d;
+      std::memset(&d, 0, sizeof d);
+      d.prog = (uint64_t)(uintptr_t)P.dblob;
+      d.table = (uint64_t)(uintptr_t)T.dptr;
+      for (int q = 0; q < 6; q++) d.launch[q] = L[q];
+      d.mode = B.mode;
+      d.L1 = L1;
+      d.L2 = L2;
+      d.cap_log2[0] = c0;
+      d.cap_log2[1] = c1;
+      d.rec_base = n_records;
+      d.cnt_base = n_counts;
+      n_records += h->n_accesses;
+      n_counts += h->n_sites;
+      if ((h->cls & CKC_CLS_UNIFORM) && !O.force_generic) {
+        d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
+        trace_bytes += sizeof(dtrace_head) + (uint64_t)h->trace_cap * sizeof(dtrace_entry);
+      }
+      hin.push_back(d);
+      for (uint32_t s = 0; s < MAX_SCALARS; s++)
+        hsc.push_back(s < h->n_scalars ? B.scalars[(size_t)i * h->n_scalars + s] : 0);
+      n_inputs++;
+    }
+  }
+  if (n_inputs == 0) return fail(CKC_E_INVALID, "no inputs");
+  if (n_inputs > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "too many inputs");
+  int rc;
+  if ((rc = set_device(c))) return rc;
+  Job J;
+  J.n_inputs = n_inputs;
+  J.n_records = n_records;
+  J.stream = O.hip_stream ? (hipStream_t)O.hip_stream : c->stream;
+  J.dense = false;
+  for (uint32_t k = 0; k < n_descs; k++) J.dense |= (descs[k].flags & CKC_DENSE_MAP) != 0;
+  int64_t* d_sc = nullptr;
+  jobstate* d_js = nullptr;
+  uint8_t* d_tr = nullptr;
+  if ((rc = dalloc(J, &J.d_inputs, n_inputs)) || (rc = dalloc(J, &d_sc, hsc.size())) ||
+      (rc = dalloc(J, &J.d_recs, n_records)) || (rc = dalloc(J, &J.d_counts, n_counts)) ||
+      (rc = dalloc(J, &J.d_status, n_inputs)) || (rc = dalloc(J, &d_js, 1)) ||
+      (rc = dalloc(J, &d_tr, trace_bytes)) ||
+      (J.dense && (rc = dalloc(J, &J.d_maps, n_inputs * 65536)))) {
+    free_job(c, J);
+    return rc;
+  }
+  for (auto& d : hin)
+    if (d.trace) d.trace = (uint64_t)(uintptr_t)(d_tr + (d.trace - 1));
+  auto bail = [&](int code) {
+    hipStreamSynchronize(J.stream);
+    free_job(c, J);
+    return code;
+  };
+  hipError_t e = hipMemcpyAsync(J.d_inputs, hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, J.stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sc, hsc.data(), sizeof(int64_t) * hsc.size(), hipMemcpyHostToDevice, J.stream);
+  for (int q = 0; q < 5 && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
+  if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e)));
+  KArgs a;
+  a.inputs = J.d_inputs;
+  a.scalars = d_sc;
+  a.n_inputs = (uint32_t)n_inputs;
+  a.force_generic = O.force_generic;
+  a.recs = J.d_recs;
+  a.counts = J.d_counts;
+  a.status = J.d_status;
+  a.maps = J.d_maps;
+  a.js = d_js;
+  uint32_t wg_trace = O.n_wg ? O.n_wg : (uint32_t)c->n_cu * 8;
+  uint32_t wg_gen = O.n_wg ? O.n_wg : (uint32_t)c->n_cu * 2;
+  e = hipEventRecord(J.ev[0], J.stream);
+  if (e == hipSuccess) e = launch_plan(a, J.stream);
+  if (e == hipSuccess) e = launch_scan(a, J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
+  if (e == hipSuccess) e = launch_eval_trace(a, wg_trace, J.stream);
+  if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
+  if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
+  if (e == hipSuccess) e = launch_finish(a, J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
+  if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));
+  for (uint32_t k = 0; k < n_descs; k++) {
+    J.progs.push_back(descs[k].prog_id);
+    c->progs[descs[k].prog_id].busy++;
+    for (uint32_t i = 0; i < descs[k].n_inputs; i++) {
+      J.tables.push_back(descs[k].table_ids[i]);
+      c->tables[descs[k].table_ids[i]].busy++;
+    }
+  }
+  uint64_t id = c->next_job++;
+  c->jobs.emplace(id, std::move(J));
+  *job = id;
+  return CKC_OK;
+}
+
+int ckc_job_sizes(ckc_ctx c, uint64_t job, uint64_t* n_inputs, uint64_t* n_records) {
+  if (!c) return fail(CKC_E_INVALID, "NULL context");
+  auto it = c->jobs.find(job);
+  if (it == c->jobs.end()) return fail(CKC_E_INVALID, "unknown job");
+  if (n_inputs) *n_inputs = it->second.n_inputs;
+  if (n_records) *n_records = it->second.n_records;
+  return CKC_OK;
+}
+
+int ckc_job_timing(ckc_ctx c, uint64_t job, float* ms4) {
+  if (!c || !ms4) return fail(CKC_E_INVALID, "NULL argument");
+  auto it = c->jobs.find(job);
+  if (it == c->jobs.end()) return fail(CKC_E_INVALID, "unknown job");
+  Job& J = it->second;
+  set_device(c);
+  HIPCHECK(hipEventSynchronize(J.ev[4]));
+  HIPCHECK(hipEventElapsedTime(&ms4[0], J.ev[0], J.ev[1]));
+  HIPCHECK(hipEventElapsedTime(&ms4[1], J.ev[1], J.ev[2]));
+  HIPCHECK(hipEventElapsedTime(&ms4[2], J.ev[2], J.ev[3]));
+  HIPCHECK(hipEventElapsedTime(&ms4[3], J.ev[3], J.ev[4]));
+  return CKC_OK;
+}
+
+int ckc_read_results(ckc_ctx c, uint64_t job, ckc_record* recs, uint8_t* maps, ckc_input_status* st,
+                     uint32_t flags) {
+  if (!c) return fail(CKC_E_INVALID, "NULL context");
+  auto it = c->jobs.find(job);
+  if (it == c->jobs.end()) return fail(CKC_E_INVALID, "unknown job");
+  Job& J = it->second;
+  int rc;
+  if ((rc = set_device(c))) return rc;
+  if (!(flags & CKC_WAIT)) {
+    hipError_t q = hipEventQuery(J.ev[4]);
+    if (q == hipErrorNotReady) return CKC_NOT_READY;
+    if (q != hipSuccess) return fail(CKC_E_HIP, std::string("job: ") + hipGetErrorString(q));
+  }
+  if (maps && !J.dense) return fail(CKC_E_INVALID, "maps requested but the job was not run with CKC_DENSE_MAP");
+  hipMemcpyKind kind = (flags & CKC_DST_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  hipError_t e = hipSuccess;
+  if (recs) e = hipMemcpyAsync(recs, J.d_recs, sizeof(ckc_record) * J.n_records, kind, J.stream);
+  if (e == hipSuccess && maps) e = hipMemcpyAsync(maps, J.d_maps, J.n_inputs * 65536, kind, J.stream);
+  if (e == hipSuccess && st) e = hipMemcpyAsync(st, J.d_status, sizeof(ckc_input_status) * J.n_inputs, kind, J.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(J.stream);
+  if (e != hipSuccess) return fail(CKC_E_HIP, std::string("readback: ") + hipGetErrorString(e));
+  free_job(c, J);
+  c->jobs.erase(it);
+  return CKC_OK;
+}
+
+}  // extern "C"

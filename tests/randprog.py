@@ -1,0 +1,139 @@
+"""Random well-formed index programs for differential tests (GPU library vs
+oracle).  Programs mix every opcode, both widths, guards, nested loops with
+small or huge trip counts, and loads from a small data array, so that guarded,
+indirect, capped and faulting paths are all exercised."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2601_01048_amd.gen.ir import BINARY, Program
+from paper_2601_01048_amd.gen import workloads as W
+
+SPECIALS = ["tid.x", "tid.y", "tid.z", "bid.x", "bid.y", "bid.z", "bdim.x", "bdim.y", "bdim.z",
+            "gdim.x", "gdim.y", "gdim.z"]
+
+
+class _Gen:
+    def __init__(self, rng, n_scalars, n_slots, budget, loads=True, uniform_only=False):
+        self.rng = rng
+        self.p = Program(n_scalars=n_scalars, n_slots=n_slots)
+        self.scopes = [[]]
+        self.budget = budget
+        self.loads = loads
+        self.uniform_only = uniform_only
+        self.n_scalars = n_scalars
+        self.n_slots = n_slots
+
+    def vis(self):
+        return [r for s in self.scopes for r in s]
+
+    def val(self):
+        v = self.vis()
+        if not v or self.rng.random() < 0.2:
+            return self.leaf()
+        return v[int(self.rng.integers(len(v)))]
+
+    def leaf(self):
+        r = self.rng.random()
+        p = self.p
+        if r < 0.35:
+            names = SPECIALS[6:] if self.uniform_only else SPECIALS
+            x = p.special(names[int(self.rng.integers(len(names)))])
+        elif r < 0.6 and self.n_scalars:
+            x = p.scalar(int(self.rng.integers(self.n_scalars)), int(self.rng.choice([32, 64])))
+        else:
+            c = int(self.rng.choice([0, 1, -1, 2, 3, 5, 7, 31, 32, 63, 64, -(1 << 31), (1 << 31) - 1,
+                                     1 << 33, -(1 << 63), int(self.rng.integers(-100, 100))]))
+            x = p.const(c, int(self.rng.choice([32, 64])))
+        self.scopes[-1].append(x)
+        return x
+
+    def stmt(self, loop_depth, nest):
+        rng, p = self.rng, self.p
+        self.budget -= 1
+        r = rng.random()
+        w = int(rng.choice([32, 64]))
+        if r < 0.45:
+            op = BINARY[int(rng.integers(len(BINARY)))]
+            if self.uniform_only and op in ("MUL", "SHL"):
+                op = "ADD"
+            x = p.op(op, self.val(), self.val(), w)
+        elif r < 0.5:
+            x = p.select(self.val(), self.val(), self.val(), w)
+        elif r < 0.55:
+            x = [p.sext, p.zext, p.trunc][int(rng.integers(3))](self.val())
+        elif r < 0.75:
+            slot = int(rng.integers(self.n_slots))
+            p.access(slot, self.val(), elem=int(rng.choice([1, 2, 4, 8])), write=bool(rng.random() < 0.5),
+                     w=w, site=bool(rng.random() < 0.9))
+            return
+        elif r < 0.82 and self.loads:
+            idx = p.op("REMU", self.val(), p.const(int(rng.integers(40, 90)), w), w)
+            x = p.load(0, idx, elem=4, w=w)
+        elif r < 0.9 and nest < 4:
+            with p.if_(self.val(), site_t=bool(rng.random() < 0.9), site_f=bool(rng.random() < 0.9)):
+                self.scopes.append([])
+                self.block(loop_depth, nest + 1, int(rng.integers(1, 5)))
+                self.scopes.pop()
+                if rng.random() < 0.4:
+                    p.else_()
+                    self.scopes.append([])
+                    self.block(loop_depth, nest + 1, int(rng.integers(1, 4)))
+                    self.scopes.pop()
+            return
+        elif loop_depth < 2 and nest < 4:
+            start = self.val()
+            if rng.random() < 0.8:
+                end = p.op("ADD", start, p.const(int(rng.integers(-2, 7)), w), w)
+            else:
+                end = self.val()  # arbitrary: may be huge (capped) or empty
+            step = p.const(int(rng.choice([1, 1, 2, -1, 3])), w)
+            with p.loop(start, end, step, w=w, site_iter=bool(rng.random() < 0.9),
+                        site_exit=bool(rng.random() < 0.9)) as k:
+                self.scopes.append([k])
+                self.block(loop_depth + 1, nest + 1, int(rng.integers(1, 5)))
+                self.scopes.pop()
+            return
+        else:
+            x = self.leaf()
+            return
+        self.scopes[-1].append(x)
+
+    def block(self, loop_depth, nest, n):
+        for _ in range(n):
+            if self.budget <= 0:
+                break
+            self.stmt(loop_depth, nest)
+
+
+def random_program(rng, n_scalars=2, n_slots=3, budget=40, loads=True, uniform_only=False) -> bytes:
+    g = _Gen(rng, n_scalars, n_slots, budget, loads, uniform_only)
+    g.block(0, 0, budget)
+    # at least one access so the program checks something
+    g.p.access(int(rng.integers(n_slots)), g.val(), elem=4)
+    return g.p.to_bytes()
+
+
+def random_workload(rng, ir: bytes, n_inputs=4, n_scalars=2, n_slots=3, mode=W.MODE_FULL,
+                    cap=(4, 3)) -> W.Workload:
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    for i in range(n_inputs):
+        launch[i] = [rng.integers(1, 4), rng.integers(1, 3), rng.integers(1, 3),
+                     rng.integers(1, 9), rng.integers(1, 4), rng.integers(1, 3)]
+    scalars = rng.integers(-5, 40, size=(n_inputs, n_scalars)).astype(np.int64)
+    scalars[rng.random(scalars.shape) < 0.1] = (1 << 40) + 3
+    data = [rng.integers(-10, 70, size=64).astype(np.int32)]
+    tables = np.zeros((n_inputs, n_slots), W.ALLOC_DTYPE)
+    for i in range(n_inputs):
+        for s in range(n_slots):
+            base = W.LOGICAL_BASE + (s << 36)
+            flags = 0
+            u = rng.random()
+            if s > 0 and u < 0.08:
+                base = 0
+            elif s > 0 and u < 0.16:
+                flags = W.ALLOC_FREED
+            size = 64 * 4 if s == 0 else int(rng.integers(0, 200))
+            tables[i, s] = (base, size, 1 if s == 0 else 0, flags, 0)
+    return W.Workload("rand", ir, launch, scalars, tables, np.arange(n_inputs, dtype=np.uint32), data,
+                      mode, tuple(cap))

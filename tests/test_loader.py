@@ -1,0 +1,136 @@
+"""Host-side tests of the library (no GPU): the C-ABI loads and exports every
+declared symbol, the load-time analysis classifies programs and reproduces the
+paper's affine decomposition of Listing 1, pruning removes instructions that
+feed no index, and malformed IR is rejected without crashing, in agreement with
+the oracle's own decoder."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import kernels as K
+from oracle import oracle as O
+from paper_2601_01048_amd import ckc
+from paper_2601_01048_amd.gen import workloads as W
+from paper_2601_01048_amd.gen.ir import Program
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _have_lib():
+    return os.path.exists(ckc.LIB)
+
+
+pytestmark = pytest.mark.skipif(not _have_lib(), reason="libckc.so not built")
+
+
+def test_exports_every_declared_symbol():
+    decl = set()
+    for h in ("ckc.h",):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        decl |= set(re.findall(r"\b(ckc_[a-z_]+)\s*\(", txt))
+    lib = ckc.lib()
+    assert decl, "no declarations found"
+    for name in sorted(decl):
+        assert hasattr(lib, name), name
+
+
+def test_listing1_affine_decomposition():
+    """Section 5.1.1: the seven accesses of Listing 1 use two indices,
+    threadIdx.x and blockIdx.x*blockDim.x + threadIdx.x, with
+    T = [[1, 0], [1, blockDim.x]] over (threadIdx.x, blockIdx.x) and b = 0."""
+    info, acc = ckc.analyze(K.listing1_program())
+    assert info["n_accesses"] == 7
+    assert info["cls"] & ckc.CLS["AFFINE"] and not info["cls"] & ckc.CLS["GUARDED"]
+    bdim_reg = 4  # register defined by SPECIAL bdim.x in listing1_program
+    rows = set()
+    for a in acc:
+        assert a["affine"] and not a["guarded"] and not a["indirect"]
+        c = a["coef"]
+        assert c[0] == (1, 1)                      # tid.x coefficient 1
+        assert c[1] == c[2] == c[4] == c[5] == (0, 0)
+        assert c[6] == (1, 0)                      # b = 0
+        rows.add(c[3])
+    assert rows == {(0, 0), (2, bdim_reg)}          # bid.x: 0 or blockDim.x
+
+
+def test_program_classes():
+    def cls(ir):
+        return {k for k, v in ckc.CLS.items() if ckc.analyze(ir)[0]["cls"] & v}
+    assert cls(W.f1_program()) == {"AFFINE", "UNIFORM"}
+    assert cls(W.f2_program(64)) == {"AFFINE", "UNIFORM", "I64"}
+    assert cls(W.f3_program()) == {"GUARDED", "INDIRECT", "EXPANDED"}
+    assert cls(K.listing3_program()) == {"AFFINE", "GUARDED"}
+    # thread-dependent product: not affine
+    p = Program(n_scalars=0, n_slots=1)
+    t = p.special("tid.x")
+    p.access(0, p.mul(t, t, 32))
+    assert "AFFINE" not in cls(p.to_bytes())
+    # sign extension of a thread-dependent 32-bit value into a 64-bit index
+    p = Program(n_scalars=0, n_slots=1)
+    g = p.add(p.special("tid.x"), p.const(5, 32), 32)
+    p.access(0, p.sext(g), w=64)
+    assert "AFFINE" not in cls(p.to_bytes())
+
+
+def test_pruning_keeps_only_index_slice():
+    """Arithmetic that feeds no index, guard or loop bound is removed
+    (MathElimination of Algorithm 2); divisions stay because they count
+    arithmetic faults."""
+    p = Program(n_scalars=1, n_slots=1)
+    t = p.special("tid.x")
+    junk = p.mul(p.add(t, 3, 32), p.const(7, 32), 32)
+    p.xor(junk, t, 32)                         # dead
+    p.divs(t, p.scalar(0, 32), 32)              # dead value, kept for faults
+    p.access(0, p.add(t, 1, 32))
+    info, _ = ckc.analyze(p.to_bytes())
+    # live: tid.x, scalar, divs, const 1, add, access
+    assert info["n_instr_live"] == 6
+
+
+def test_register_limit():
+    p = Program(n_scalars=0, n_slots=1)
+    t = p.special("tid.x")
+    for k in range(40):  # each value dies at its access: registers are reused
+        p.access(0, p.add(t, p.const(k, 32), 32))
+    # 40 values plus tid.x live at once: over the 32-register file
+    p2 = Program(n_scalars=0, n_slots=1)
+    t2 = p2.special("tid.x")
+    vs = [p2.add(t2, k, 32) for k in range(40)]
+    acc = vs[0]
+    for v in vs[1:]:
+        acc = p2.add(acc, v, 32)
+    p2.access(0, acc)
+    with pytest.raises(ckc.CkcError) as e:
+        ckc.analyze(p2.to_bytes())
+    assert e.value.code == -2
+    ckc.analyze(p.to_bytes())  # sequential uses fit
+
+
+def test_malformed_ir_agrees_with_oracle():
+    rng = np.random.default_rng(9)
+    for base in (W.f3_program(), W.f2_program(), K.listing3_program()):
+        for _ in range(400):
+            b = bytearray(base)
+            for _ in range(int(rng.integers(1, 4))):
+                b[int(rng.integers(32, len(b)))] = int(rng.integers(0, 256))
+            b = bytes(b)
+            try:
+                O.validate(b)
+                ok_oracle = True
+            except O.OracleError:
+                ok_oracle = False
+            try:
+                ckc.analyze(b)
+                ok_lib = True
+            except ckc.CkcError as e:
+                assert e.code == -2
+                ok_lib = False
+            assert ok_oracle == ok_lib, b.hex()
+
+
+def test_truncated_and_garbage_ir():
+    for b in (b"", b"\x00" * 8, W.f1_program()[:-16], b"CKC1" + b"\xff" * 60):
+        with pytest.raises(ckc.CkcError):
+            ckc.analyze(b)
