@@ -446,12 +446,16 @@ static void run_thread(thr* t, uint64_t blin, uint32_t tlin) {
   exec_range(t, 0, t->P->n_instr);
 }
 
-/* A block is a boundary block when one of its coordinates is first or last
- * along its grid dimension. */
+/* A block is a boundary block when, along some grid dimension of extent at
+ * least 2, its coordinate is the first or the last one.  A dimension of extent
+ * 1 has no boundary of its own (otherwise every block of a 2-D grid would be a
+ * boundary block): the set is the perimeter of the grid in the dimensions it
+ * actually spans. */
 static int is_boundary_block(const uint32_t* L, uint64_t blin) {
   uint32_t gx = L[0], gy = L[1], gz = L[2];
   uint32_t x = (uint32_t)(blin % gx), y = (uint32_t)((blin / gx) % gy), z = (uint32_t)(blin / ((uint64_t)gx * gy));
-  return x == 0 || x == gx - 1 || y == 0 || y == gy - 1 || z == 0 || z == gz - 1;
+  return (gx >= 2 && (x == 0 || x == gx - 1)) || (gy >= 2 && (y == 0 || y == gy - 1)) ||
+         (gz >= 2 && (z == 0 || z == gz - 1));
 }
 
 /* One input under the chosen thread set. */

@@ -55,7 +55,9 @@ def threads(launch, mode="full"):
         out = []
         for b in range(nb):
             x, y, z = b % gx, (b // gx) % gy, b // (gx * gy)
-            if x in (0, gx - 1) or y in (0, gy - 1) or z in (0, gz - 1) or b == centre:
+            face = ((gx > 1 and x in (0, gx - 1)) or (gy > 1 and y in (0, gy - 1))
+                    or (gz > 1 and z in (0, gz - 1)))
+            if face or b == centre:
                 out.extend(coords(b, t) for t in range(bs))
         return out
     raise ValueError(mode)

@@ -298,6 +298,20 @@ def test_representative_sets_are_subsets(mode):
     assert_subset(O.check(wl, mode=mode), O.check(wl, mode=W.MODE_FULL))
 
 
+def test_boundary_set_sizes():
+    """The boundary set is the perimeter of the grid in the dimensions it spans
+    plus its middle block: a 128 x 128 grid gives 128*4 - 4 + 1 = 509 blocks;
+    a grid of extent 1 or 2 in every spanned dimension is all boundary."""
+    p = Program(n_scalars=0, n_slots=1)
+    p.access(0, p.special("tid.x"), w=64)
+    ir = p.to_bytes()
+    for g, blocks in (((128, 128, 1), 509), ((1, 1, 1), 1), ((5, 1, 1), 3), ((2, 2, 2), 8),
+                      ((4, 4, 4), 4 * 4 * 4 - 2 * 2 * 2 + 1), ((3, 1, 7), 3 * 7 - 1 * 5 + 1)):
+        wl = K.simple_workload(ir, [list(g) + [2, 1, 1]], [[(LB, 8, 0, 0, 0)]], mode=W.MODE_BOUNDARY)
+        assert int(O.check(wl)["status"]["lanes"][0]) == 2 * blocks, g
+        assert len(brute.threads(wl.launch[0], "boundary")) == 2 * blocks, g
+
+
 def test_corners_miss_guarded_bug():
     """Listing 3 is why the Theorem needs unguarded accesses: the corner
     threads miss the bug at id = N-1 unless it is a corner."""
