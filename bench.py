@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Throughput of the checking hot path on one MI355X.
+
+Workload: the 2-D 9-point stencil configuration -- 4096 seeded inputs, each a
+grid of (128 +- 3)^2 blocks of 16 x 16 threads over an (2048 +- 3)^2 int32-indexed
+pair of allocations, halo radius 1 or 2 -- checked over the whole grid (every
+thread of every input).  One step = one ckc_check_batch (thread sets and
+traces, evaluation, first-violation replay, dense 64 KiB maps) plus
+ckc_read_results into device buffers; program and allocation tables are
+resident before the timed region.
+
+Prints one JSON line: checked thread-accesses/s (value), inputs/s, the
+roofline of the dominant kernel (timed with HIP events on the job's stream)
+and the oracle's throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2601_01048_amd import ckc  # noqa: E402
+from paper_2601_01048_amd.gen import workloads as W  # noqa: E402
+
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz
+PEAK_INT_OPS = 256 * 64 * 2.4e9
+# algorithmic work of one checked access on the affine path: form the index
+# (per-thread base + per-access offset) and one unsigned bound compare
+OPS_PER_ACCESS = 2
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rep", action="store_true", help="skip the representative-thread line")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="inputs in the oracle sample")
+    return ap.parse_args()
+
+
+def run_steps(ctx, dw, out, mode, steps):
+    """Runs `steps` checks; returns per-step (kernel timing list)."""
+    timings = []
+    for _ in range(steps):
+        job = ctx.check([dw.desc(mode=mode, dense=True)])
+        timings.append(ctx.timing(job))
+        ctx.read_device(job, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr())
+    return timings
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload shards by "
+              "input with no communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    wl = W.config2(mode=W.MODE_FULL)
+    n = wl.n_inputs
+    with ckc.Context(0) as ctx:
+        dw = ckc.DeviceWorkload(ctx, wl)
+        n_acc = dw.info["n_accesses"]
+        out = dict(recs=torch.empty(n * n_acc * 32, dtype=torch.uint8, device="cuda"),
+                   maps=torch.empty(n * 65536, dtype=torch.uint8, device="cuda"),
+                   st=torch.empty(n * 40, dtype=torch.uint8, device="cuda"))
+        run_steps(ctx, dw, out, W.MODE_FULL, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tim = run_steps(ctx, dw, out, W.MODE_FULL, args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
+        accesses = int(st["accesses_checked"].sum())
+        step_s = (t1 - t0) / args.steps
+        kern = np.array(tim)  # [steps, 4] ms: plan, trace eval, interpreter, finish
+        eval_ms = float(kern[:, 1].mean())
+        result = {
+            "metric": "checked thread-accesses/sec",
+            "value": accesses / step_s,
+            "unit": "accesses/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": step_s * 1e3,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "int32",
+            "data": "synthetic",
+            "config": {
+                "workload": "2-D 9-point stencil, 4096 inputs, grid (128+-3)^2 x 16x16 threads, "
+                            "(2048+-3)^2 allocations, radius 1-2, whole grid (FULL)",
+                "inputs": n,
+                "threads_per_batch": int(st["lanes"].sum()),
+                "accesses_per_batch": accesses,
+                "seed": 1002,
+            },
+            "inputs_per_s": n / step_s,
+            "kernel_ms": {"plan": float(kern[:, 0].mean()), "eval_trace": eval_ms,
+                          "interpreter": float(kern[:, 2].mean()), "finish": float(kern[:, 3].mean())},
+        }
+        achieved = OPS_PER_ACCESS * accesses / (eval_ms * 1e-3)
+        result["roofline"] = {
+            "bound": "alu",
+            "kernel": "eval_trace_kernel",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_INT_OPS / 1e12,
+            "unit": "Tops/s (int32)",
+            "frac": achieved / PEAK_INT_OPS,
+            "traffic": None,
+        }
+        if not args.no_rep:
+            run_steps(ctx, dw, out, W.MODE_BOUNDARY, 1)
+            torch.cuda.synchronize()
+            r0 = time.perf_counter()
+            rt = run_steps(ctx, dw, out, W.MODE_BOUNDARY, max(2, args.steps // 2))
+            torch.cuda.synchronize()
+            r1 = time.perf_counter()
+            rst = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
+            rs = (r1 - r0) / len(rt)
+            result["rep_boundary"] = {"inputs_per_s": n / rs, "ms_per_step": rs * 1e3,
+                                      "accesses_per_s": int(rst["accesses_checked"].sum()) / rs,
+                                      "lanes_per_batch": int(rst["lanes"].sum()),
+                                      "speedup_inputs_per_s_vs_full": step_s / rs}
+        dw.close()
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        k = min(args.cpu_sample, n)
+        cores = min(16, os.cpu_count() or 1)
+        sub = wl.subset(np.arange(k))
+        c0 = time.perf_counter()
+        o = O.check(sub, nthreads=cores, maps=False)
+        c1 = time.perf_counter()
+        acc_cpu = int(o["status"]["accesses_checked"].sum())
+        result["cpu_baseline"] = {"value": acc_cpu / (c1 - c0), "unit": "accesses/s", "cores": cores,
+                                  "kind": "oracle",
+                                  "sample": f"first {k} of {n} inputs of the same workload (FULL), "
+                                            f"{acc_cpu} accesses in {c1 - c0:.2f} s"}
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

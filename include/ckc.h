@@ -202,9 +202,10 @@ int ckc_read_results(ckc_ctx ctx, uint64_t job, ckc_record* recs, uint8_t* maps,
 /* Number of inputs and records of a job (for sizing result buffers). */
 int ckc_job_sizes(ckc_ctx ctx, uint64_t job, uint64_t* n_inputs, uint64_t* n_records);
 
-/* Device timing of the job's evaluation kernels in milliseconds (HIP events on
- * the job's stream, valid after the job completed): [0] planning, [1] main
- * evaluation, [2] expanded-loop evaluation, [3] finishing (records, maps). */
+/* Device timing of the job's kernels in milliseconds (HIP events on the job's
+ * stream; waits for the job): [0] planning (thread sets, traces, tile scan),
+ * [1] trace evaluator, [2] interpreter, [3] finishing (first-violation replay,
+ * status, dense maps).  Call before ckc_read_results releases the job. */
 int ckc_job_timing(ckc_ctx ctx, uint64_t job, float* ms4);
 
 #ifdef __cplusplus

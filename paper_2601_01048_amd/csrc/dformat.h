@@ -76,10 +76,12 @@ struct dinput {
   uint32_t cap_log2[2];
   uint32_t path;          // 0 = trace evaluator, 1 = generic interpreter (set by planning)
   uint32_t n_tiles[2];
-  uint32_t pad[3];
+  uint32_t tv;            // trace path layout: 0 = lane tiles, 1 = block-major wavefront jobs
+  uint32_t pad[2];
 };
 
 constexpr int MAX_SCALARS = 16;
+constexpr uint32_t LPB = 4;  // blocks per wavefront job of the block-major trace path
 
 // Trace of a uniform-control program for one input: every thread performs the
 // same access sequence; each access index is base[class](thread) + off.

@@ -172,58 +172,90 @@ __device__ __forceinline__ void thr_from(const uint32_t* L, uint64_t blin, uint3
   th.gtid = blin * bsz + tlin;
 }
 
-// Blocks of the boundary set (every block with a first/last coordinate, plus
-// the middle block when it is interior) that precede block `blin`.
+// The boundary thread set: every block that, along some grid dimension of
+// extent >= 2, sits at the first or last coordinate, plus the middle block
+// (gx/2, gy/2, gz/2) when it is not such a block; all threads of those blocks.
+// Blocks are taken in block order.  Structure used below: the set is made of
+// whole "face" slabs (z first/last), and in the other slabs of whole face rows
+// (y first/last) and, in the other rows, the first and last block (x) -- plus
+// the middle block in its own slab and row.
 struct BSet {
   uint32_t gx, gy, gz, cx, cy, cz;
-  bool centre;
-  uint64_t mbase;  // blocks of a non-face slab, centre not counted
+  uint32_t centre;      // 1 if the middle block is interior (an extra member)
+  uint32_t per_row;     // set blocks of a non-face row without the middle block
+  uint32_t face_rows;   // face rows of a non-face slab
+  uint64_t gxy;
+  uint64_t mbase;       // set blocks of a non-face slab without the middle block
 };
 __device__ __forceinline__ BSet bset(const uint32_t* L) {
   BSet s;
   s.gx = L[0]; s.gy = L[1]; s.gz = L[2];
   s.cx = s.gx / 2; s.cy = s.gy / 2; s.cz = s.gz / 2;
-  s.centre = s.gx >= 3 && s.gy >= 3 && s.gz >= 3;
-  uint64_t per_row = s.gx <= 2 ? s.gx : 2;
-  s.mbase = s.gy <= 2 ? (uint64_t)s.gx * s.gy : 2ull * s.gx + (uint64_t)(s.gy - 2) * per_row;
+  s.centre = (s.gx == 1 || s.gx >= 3) && (s.gy == 1 || s.gy >= 3) && (s.gz == 1 || s.gz >= 3);
+  s.per_row = s.gx >= 2 ? 2u : 0u;
+  s.face_rows = s.gy >= 2 ? 2u : 0u;
+  s.gxy = (uint64_t)s.gx * s.gy;
+  s.mbase = (uint64_t)s.face_rows * s.gx + (uint64_t)(s.gy - s.face_rows) * s.per_row;
   return s;
 }
-__device__ __forceinline__ uint64_t bset_before(const BSet& s, uint64_t blin) {
-  uint64_t gxy = (uint64_t)s.gx * s.gy;
-  uint32_t z = (uint32_t)(blin / gxy);
-  uint32_t rem = (uint32_t)(blin - (uint64_t)z * gxy);
-  uint32_t y = rem / s.gx, x = rem - y * s.gx;
-  uint64_t c = 0;
-  if (z > 0) c += gxy + (uint64_t)(z - 1) * s.mbase + ((s.centre && s.cz < z) ? 1 : 0);
-  bool face = z == 0 || z == s.gz - 1;
-  if (face || s.gy <= 2) {
-    c += (uint64_t)y * s.gx;
-    return c + x;
-  }
-  uint64_t per_row = s.gx <= 2 ? s.gx : 2;
-  if (y > 0) c += s.gx + (uint64_t)(y - 1) * per_row + ((s.centre && z == s.cz && s.cy < y) ? 1 : 0);
-  bool full = y == 0 || y == s.gy - 1 || s.gx <= 2;
-  if (full) return c + x;
-  c += (x > 0 ? 1 : 0) + ((s.centre && y == s.cy && z == s.cz && s.cx < x) ? 1 : 0);
-  return c;
-}
 __device__ __forceinline__ uint64_t bset_size(const uint32_t* L) {
-  uint64_t nb = (uint64_t)L[0] * L[1] * L[2];
+  const uint64_t nb = (uint64_t)L[0] * L[1] * L[2];
   uint64_t inner = 1;
-  for (int d = 0; d < 3; d++) inner *= L[d] >= 2 ? (uint64_t)(L[d] - 2) : 0ull;
-  bool centre = L[0] >= 3 && L[1] >= 3 && L[2] >= 3;
-  return nb - inner + (centre ? 1 : 0);
+  for (int d = 0; d < 3; d++) inner *= L[d] >= 2 ? (uint64_t)(L[d] - 2) : 1ull;
+  const BSet s = bset(L);
+  return nb - inner + s.centre;
 }
-// k-th block of the boundary set in block order.
-__device__ __forceinline__ uint64_t bset_block(const uint32_t* L, uint64_t k) {
-  BSet s = bset(L);
-  uint64_t lo = 0, hi = (uint64_t)L[0] * L[1] * L[2] - 1;
-  while (lo < hi) {  // largest b with before(b) <= k
-    uint64_t mid = lo + (hi - lo + 1) / 2;
-    if (bset_before(s, mid) <= k) lo = mid;
-    else hi = mid - 1;
+// Position k (0-based) of a middle-section list in which each of `n` groups
+// holds `per` items, except group `cg` (if has_c) which holds one more.
+// Returns the group and the index inside it.
+__device__ __forceinline__ void split_groups(uint64_t k, uint64_t per, uint32_t n, bool has_c, uint32_t cg,
+                                             uint32_t& grp, uint64_t& idx) {
+  if (!has_c) {
+    grp = per ? (uint32_t)(k / per) : 0u;
+    idx = per ? k - (uint64_t)grp * per : k;
+    return;
   }
-  return lo;
+  const uint64_t before = (uint64_t)cg * per;
+  if (k < before) { grp = (uint32_t)(k / per); idx = k - (uint64_t)grp * per; return; }
+  if (k < before + per + 1) { grp = cg; idx = k - before; return; }
+  const uint64_t k2 = k - before - per - 1;
+  const uint32_t g2 = per ? (uint32_t)(k2 / per) : 0u;
+  grp = cg + 1 + g2;
+  idx = per ? k2 - (uint64_t)g2 * per : k2;
+  (void)n;
+}
+// Block index of the k-th member of the boundary set (k < bset_size).
+__device__ __forceinline__ uint64_t bset_block(const uint32_t* L, uint64_t k) {
+  const BSet s = bset(L);
+  const bool zf = s.gz >= 2;
+  if (zf && k < s.gxy) return k;  // first face slab
+  const uint64_t k1 = zf ? k - s.gxy : k;
+  const uint32_t zoff = zf ? 1u : 0u;
+  const uint32_t nmid = zf ? s.gz - 2 : 1u;
+  const uint64_t mid_total = (uint64_t)nmid * s.mbase + s.centre;
+  if (k1 >= mid_total) return (uint64_t)(s.gz - 1) * s.gxy + (k1 - mid_total);  // last face slab
+  uint32_t zi;
+  uint64_t r;
+  split_groups(k1, s.mbase, nmid, s.centre != 0, s.cz - zoff, zi, r);
+  const uint32_t z = zoff + zi;
+  const bool cslab = s.centre && z == s.cz;
+  const bool yf = s.gy >= 2;
+  const uint64_t zbase = (uint64_t)z * s.gxy;
+  if (yf && r < s.gx) return zbase + r;  // first face row
+  const uint64_t r1 = yf ? r - s.gx : r;
+  const uint32_t yoff = yf ? 1u : 0u;
+  const uint32_t nmid_rows = yf ? s.gy - 2 : 1u;
+  const uint64_t mid_rows_total = (uint64_t)nmid_rows * s.per_row + (cslab ? 1 : 0);
+  if (r1 >= mid_rows_total) return zbase + (uint64_t)(s.gy - 1) * s.gx + (r1 - mid_rows_total);
+  uint32_t yi;
+  uint64_t rr;
+  split_groups(r1, s.per_row, nmid_rows, cslab, s.cy - yoff, yi, rr);
+  const uint32_t y = yoff + yi;
+  const bool crow = cslab && y == s.cy;
+  uint32_t x;
+  if (s.gx >= 2) x = rr == 0 ? 0u : (crow && rr == 1) ? s.cx : s.gx - 1;
+  else x = 0;  // only the middle block
+  return zbase + (uint64_t)y * s.gx + x;
 }
 
 __device__ __forceinline__ uint64_t set_lanes(uint32_t mode, const uint32_t* L) {
@@ -533,8 +565,20 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
   }
   if (j == 0) {
     uint64_t tiles = (lanes + TILE - 1) / TILE;
+    uint32_t tv = 0;
+    const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
+    if (path == 0 && in.mode != CKC_REP_CORNERS && bs % 64u == 0 &&
+        ((const dtrace_head*)in.trace)->n_classes == 1) {
+      // block-major jobs: (64-thread slice position, group of LPB set blocks)
+      const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
+                                               : bset_size(in.launch);
+      const uint64_t jobs = (uint64_t)(bs / 64u) * ((nsb + LPB - 1) / LPB);
+      tiles = (jobs + 3) / 4;
+      tv = 1;
+    }
     in.lanes = lanes;
     in.path = path;
+    in.tv = tv;
     in.n_tiles[0] = path == 0 ? (uint32_t)tiles : 0;
     in.n_tiles[1] = path == 1 ? (uint32_t)tiles : 0;
   }
@@ -593,51 +637,255 @@ __device__ __forceinline__ uint32_t find_input(const dinput* in, uint32_t n, uin
 // ---------------------------------------------------------------------------
 // trace evaluator
 // ---------------------------------------------------------------------------
+// Unsigned 32-bit division by a runtime divisor d >= 1 with a precomputed
+// multiplier (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): m = floor(2^32 (2^s - d) / d) + 1, s = ceil(log2 d),
+// q = (mulhi(n, m) + n) >> s, the sum taken in 64 bits.
+struct UDiv {
+  uint32_t m, s;
+};
+__device__ __forceinline__ UDiv udiv_make(uint32_t d) {
+  const uint32_t s = 32u - (uint32_t)__clz((int)(d - 1u));
+  const uint64_t m = ((1ull << 32) * ((1ull << s) - d)) / d + 1ull;
+  return UDiv{(uint32_t)m, s};
+}
+__device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv D) {
+  return (uint32_t)(((uint64_t)__umulhi(n, D.m) + n) >> D.s);
+}
+
+// Read-only job data is read through the constant address space so that
+// wavefront-uniform loads become scalar loads.
+typedef const __attribute__((address_space(4))) dtrace_entry c_entry;
+typedef const __attribute__((address_space(4))) dtrace_head c_head;
+typedef const __attribute__((address_space(4))) dinput c_input;
+typedef const __attribute__((address_space(4))) jobstate c_jobstate;
+
+__device__ __forceinline__ uint32_t find_input_c(c_input* in, uint32_t n, uint32_t path, uint64_t t) {
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (in[mid].tile_begin[path] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Rare path of one trace entry: some lane of the wavefront violates.
+__device__ __noinline__ void trace_violation(ckc_record* rec, uint32_t bad, uint64_t gtid, uint32_t Lsum,
+                                             uint64_t keylo) {
+  merge_violation(rec, bad, (gtid << Lsum) | keylo);
+}
+
+// Checks of a trace whose entries all use one coefficient class of width W:
+// per entry one add and one unsigned compare against the clamped bound.
+template <int W>
+__device__ __forceinline__ void trace_entries_1(c_entry* te, uint32_t ne, uint64_t base, bool act,
+                                                ckc_record* rec, uint64_t gtid, uint32_t Lsum) {
+  for (uint32_t e = 0; e < ne; e++) {
+    const int64_t off = te[e].off;
+    const uint64_t bound = te[e].bound;
+    const uint32_t dead = te[e].dead_kind;
+    uint32_t bad;
+    if (W == 32) {
+      const uint32_t v = (uint32_t)base + (uint32_t)off;
+      bad = v >= (uint32_t)bound ? (((int32_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+    } else {
+      const uint64_t v = base + (uint64_t)off;
+      bad = v >= bound ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+    }
+    if (dead) bad = dead;
+    bad = act ? bad : 0u;
+    if (__ballot(bad != 0)) trace_violation(rec + te[e].acc, bad, gtid, Lsum, te[e].keylo);
+  }
+}
+
+// Block-major checks of one wavefront job: this lane's thread position
+// (tlin) in up to LPB set blocks; tpart is the thread part of the index base,
+// bp[j] the block parts (wavefront-uniform).  Per entry: one add for the
+// thread part, then one add and one compare per block.
+template <int W>
+__device__ __forceinline__ void trace_blocks(c_entry* te, uint32_t ne, uint64_t tpart, const uint64_t* bp,
+                                             const uint64_t* gb, uint32_t nvalid, uint32_t tlin,
+                                             ckc_record* rec, uint32_t Lsum) {
+  for (uint32_t e = 0; e < ne; e++) {
+    const int64_t off = te[e].off;
+    const uint64_t bound = te[e].bound;
+    const uint32_t dead = te[e].dead_kind;
+    uint64_t m = 0;
+    uint32_t bad[LPB];
+#pragma unroll
+    for (uint32_t j = 0; j < LPB; j++) {
+      if (W == 32) {
+        const uint32_t v = (uint32_t)tpart + (uint32_t)off + (uint32_t)bp[j];
+        bad[j] = v >= (uint32_t)bound ? (((int32_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+      } else {
+        const uint64_t v = tpart + (uint64_t)off + bp[j];
+        bad[j] = v >= bound ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+      }
+      if (dead) bad[j] = dead;
+      if (j >= nvalid) bad[j] = 0;
+      m |= __ballot(bad[j] != 0);
+    }
+    if (m) {
+      const uint32_t acc = te[e].acc;
+      const uint64_t keylo = te[e].keylo;
+#pragma unroll
+      for (uint32_t j = 0; j < LPB; j++)
+        if (__ballot(bad[j] != 0)) trace_violation(rec + acc, bad[j], gb[j] + tlin, Lsum, keylo);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
-  const uint64_t total = a.js->total_tiles[0];
+  c_jobstate* js = (c_jobstate*)a.js;
+  c_input* ins = (c_input*)a.inputs;
+  const uint64_t total = js->total_tiles[0];
   if (total == 0) return;
   const uint64_t G = gridDim.x;
   const uint64_t t_begin = total * blockIdx.x / G, t_end = total * (blockIdx.x + 1) / G;
   if (t_begin >= t_end) return;
-  uint32_t i = find_input(a.inputs, a.n_inputs, 0, t_begin);
+  const uint32_t tid = threadIdx.x;
+  uint32_t i = find_input_c(ins, a.n_inputs, 0, t_begin);
+  uint32_t cur = 0xFFFFFFFFu;
+  // per-input state (wavefront-uniform)
+  uint32_t L[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t bs = 1, gxy = 1, bxy = 1, mode = 0, Lsum = 0, ncls = 0, ne = 0, w0 = 32;
+  UDiv dbs{1, 0}, dgx{1, 0}, dgxy{1, 0}, dbx{1, 0}, dbxy{1, 0}, dspb{1, 0};
+  uint64_t lanes = 0, tb = 0, blin0 = 0, nsb = 0;
+  uint32_t tlin0 = 0, tv = 0;
+  int64_t k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0, k5 = 0;
+  c_head* th = nullptr;
+  c_entry* te = nullptr;
+  ckc_record* rec = nullptr;
+  uint64_t cur_end = 0;
   for (uint64_t t = t_begin; t < t_end; t++) {
-    while (a.inputs[i].n_tiles[0] == 0 || t >= a.inputs[i].tile_begin[0] + a.inputs[i].n_tiles[0]) i++;
-    const dinput& in = a.inputs[i];
-    const dtrace_head* th = (const dtrace_head*)in.trace;
-    const dtrace_entry* te = (const dtrace_entry*)(th + 1);
-    const uint64_t l = (t - in.tile_begin[0]) * TILE + threadIdx.x;
-    const bool act = l < in.lanes;
-    Thr T;
-    decode_lane(in.mode, in.launch, act ? l : 0, T);
-    uint64_t coord[6] = {T.t[0], T.t[1], T.t[2], T.b[0], T.b[1], T.b[2]};
-    const uint32_t ncls = ufirst(th->n_classes);
+    if (t >= cur_end || cur == 0xFFFFFFFFu) {
+      while (ins[i].n_tiles[0] == 0 || t >= ins[i].tile_begin[0] + ins[i].n_tiles[0]) i++;
+      cur_end = ins[i].tile_begin[0] + ins[i].n_tiles[0];
+    }
+    if (i != cur) {
+      cur = i;
+      for (int q = 0; q < 6; q++) L[q] = ins[i].launch[q];
+      bs = L[3] * L[4] * L[5];
+      gxy = L[0] * L[1];
+      bxy = L[3] * L[4];
+      dbs = udiv_make(bs); dgx = udiv_make(L[0]); dgxy = udiv_make(gxy);
+      dbx = udiv_make(L[3]); dbxy = udiv_make(bxy);
+      dspb = udiv_make(bs >= 64 ? bs / 64u : 1u);
+      mode = ins[i].mode;
+      Lsum = ins[i].L1 + ins[i].L2;
+      lanes = ins[i].lanes;
+      tb = ins[i].tile_begin[0];
+      th = (c_head*)ins[i].trace;
+      te = (c_entry*)(th + 1);
+      rec = a.recs + ins[i].rec_base;
+      ncls = th->n_classes;
+      ne = th->n_entries;
+      w0 = th->cls_w[0];
+      tv = ins[i].tv;
+      nsb = mode == CKC_FULL ? (uint64_t)L[0] * L[1] * L[2] : bset_size(L);
+      k0 = th->coef[0][0]; k1 = th->coef[0][1]; k2 = th->coef[0][2];
+      k3 = th->coef[0][3]; k4 = th->coef[0][4]; k5 = th->coef[0][5];
+      const uint64_t l0 = (t - tb) * TILE;
+      blin0 = l0 / bs;
+      tlin0 = (uint32_t)(l0 - blin0 * bs);
+    }
+    if (tv == 1) {
+      // ---- block-major wavefront job ----
+      const uint32_t wv = ufirst(tid >> 6);
+      const uint64_t job = (t - tb) * 4 + wv;
+      const uint32_t spb = bs / 64u;
+      const uint64_t g = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, dspb) : job / spb;
+      const uint32_t o = (uint32_t)(job - g * spb);
+      if (g * LPB >= nsb) continue;  // past the last group (whole wavefront)
+      const uint32_t tlin = o * 64u + (tid & 63u);
+      const uint32_t tz = udiv(tlin, dbxy), tr = tlin - tz * bxy;
+      const uint32_t ty = udiv(tr, dbx);
+      const uint32_t tx = tr - ty * L[3];
+      uint64_t tpart = 0;
+      if (k0 == 1) tpart += tx; else if (k0 != 0) tpart += (uint64_t)k0 * tx;
+      if (k1 == 1) tpart += ty; else if (k1 != 0) tpart += (uint64_t)k1 * ty;
+      if (k2 == 1) tpart += tz; else if (k2 != 0) tpart += (uint64_t)k2 * tz;
+      uint64_t bp[LPB], gb[LPB];
+      const uint64_t left = nsb - g * LPB;
+      const uint32_t nvalid = left < LPB ? (uint32_t)left : LPB;
+#pragma unroll
+      for (uint32_t jj = 0; jj < LPB; jj++) {
+        const uint64_t k = g * LPB + jj;
+        const uint32_t blin = jj < nvalid ? (uint32_t)(mode == CKC_FULL ? k : bset_block(L, k)) : 0u;
+        const uint32_t bz = udiv(blin, dgxy), brem = blin - bz * gxy;
+        const uint32_t by = udiv(brem, dgx), bx = brem - by * L[0];
+        bp[jj] = (uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz;
+        gb[jj] = (uint64_t)blin * bs;
+      }
+      if (w0 == 32) trace_blocks<32>(te, ne, tpart, bp, gb, nvalid, tlin, rec, Lsum);
+      else trace_blocks<64>(te, ne, tpart, bp, gb, nvalid, tlin, rec, Lsum);
+      continue;
+    }
+    const uint64_t l = (t - tb) * TILE + tid;
+    const bool act = l < lanes;
+    uint32_t c6[6];
+    uint64_t gtid;
+    if (mode == CKC_FULL) {
+      // consecutive lanes are consecutive threads: block carry by division
+      const uint32_t u = tlin0 + tid;
+      const uint32_t q = udiv(u, dbs);
+      const uint32_t tlin = u - q * bs;
+      uint32_t blin = (uint32_t)blin0 + q;
+      if (bs % 64u == 0) blin = ufirst(blin);  // one block per wavefront
+      const uint32_t z = udiv(blin, dgxy), r = blin - z * gxy;
+      const uint32_t y = udiv(r, dgx);
+      c6[3] = r - y * L[0]; c6[4] = y; c6[5] = z;
+      const uint32_t tz = udiv(tlin, dbxy), tr = tlin - tz * bxy;
+      const uint32_t ty = udiv(tr, dbx);
+      c6[0] = tr - ty * L[3]; c6[1] = ty; c6[2] = tz;
+      gtid = (uint64_t)blin * bs + tlin;
+      // next tile
+      tlin0 += TILE;
+      const uint32_t qn = udiv(tlin0, dbs);
+      blin0 += qn;
+      tlin0 -= qn * bs;
+    } else {
+      Thr T;
+      decode_lane(mode, L, act ? l : 0, T);
+      c6[0] = T.t[0]; c6[1] = T.t[1]; c6[2] = T.t[2]; c6[3] = T.b[0]; c6[4] = T.b[1]; c6[5] = T.b[2];
+      gtid = T.gtid;
+    }
+    // base of each coefficient class: sum of coefficient x coordinate, skipping
+    // zero coefficients (uniform branches)
     uint64_t base[MAX_CLASSES];
 #pragma unroll
     for (int c = 0; c < MAX_CLASSES; c++) {
       uint64_t b = 0;
       if ((uint32_t)c < ncls) {
 #pragma unroll
-        for (int d = 0; d < 6; d++) b += (uint64_t)th->coef[c][d] * coord[d];
+        for (int d = 0; d < 6; d++) {
+          const int64_t k = th->coef[c][d];
+          if (k == 1) b += c6[d];
+          else if (k != 0) b += (uint64_t)k * c6[d];
+        }
       }
       base[c] = b;
     }
-    const uint32_t ne = ufirst(th->n_entries);
-    const uint32_t Lsum = in.L1 + in.L2;
-    ckc_record* rec = a.recs + in.rec_base;
-    for (uint32_t e = 0; e < ne; e++) {
-      const dtrace_entry E = te[e];
-      uint64_t b = E.cls == 0 ? base[0] : E.cls == 1 ? base[1] : E.cls == 2 ? base[2] : base[3];
-      uint64_t v = b + (uint64_t)E.off;
-      uint32_t bad;
-      if (E.w == 32) {
-        uint32_t v32 = (uint32_t)v;
-        bad = (v32 >= (uint32_t)E.bound) ? (((int32_t)v32 < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
-      } else {
-        bad = (v >= E.bound) ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+    if (ncls == 1) {
+      if (w0 == 32) trace_entries_1<32>(te, ne, base[0], act, rec, gtid, Lsum);
+      else trace_entries_1<64>(te, ne, base[0], act, rec, gtid, Lsum);
+    } else {
+      for (uint32_t e = 0; e < ne; e++) {
+        const uint32_t c = te[e].cls;
+        const uint64_t b = c == 0 ? base[0] : c == 1 ? base[1] : c == 2 ? base[2] : base[3];
+        const uint64_t v = b + (uint64_t)te[e].off;
+        uint32_t bad;
+        if (te[e].w == 32) {
+          const uint32_t v32 = (uint32_t)v;
+          bad = v32 >= (uint32_t)te[e].bound ? (((int32_t)v32 < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+        } else {
+          bad = v >= te[e].bound ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+        }
+        if (te[e].dead_kind) bad = te[e].dead_kind;
+        bad = act ? bad : 0u;
+        if (__ballot(bad != 0)) trace_violation(rec + te[e].acc, bad, gtid, Lsum, te[e].keylo);
       }
-      if (E.dead_kind) bad = E.dead_kind;
-      bad = act ? bad : 0u;
-      if (__ballot(bad != 0)) merge_violation(rec + E.acc, bad, (T.gtid << Lsum) | E.keylo);
     }
   }
 }

@@ -49,7 +49,7 @@ struct Table {
 
 struct Job {
   hipStream_t stream = nullptr;
-  std::vector<void*> bufs;
+  std::vector<std::pair<size_t, void*>> bufs;  // (bytes, device pointer)
   dinput* d_inputs = nullptr;
   ckc_record* d_recs = nullptr;
   uint32_t* d_counts = nullptr;
@@ -72,6 +72,9 @@ struct ckc_ctx_s {
   std::map<uint32_t, Table> tables;
   std::map<uint64_t, Job> jobs;
   int n_cu = 256;
+  // device buffers of finished jobs, reused by later jobs of similar size
+  std::multimap<size_t, void*> pool;
+  size_t pool_bytes = 0;
 };
 
 namespace {
@@ -81,8 +84,17 @@ int set_device(ckc_ctx c) {
   return CKC_OK;
 }
 
+constexpr size_t POOL_LIMIT = 16ull << 30;  // bytes kept for reuse per context
+
 void free_job(ckc_ctx c, Job& J) {
-  for (void* p : J.bufs) hipFree(p);
+  for (auto& b : J.bufs) {
+    if (c->pool_bytes + b.first <= POOL_LIMIT) {
+      c->pool.emplace(b.first, b.second);
+      c->pool_bytes += b.first;
+    } else {
+      hipFree(b.second);
+    }
+  }
   J.bufs.clear();
   for (auto& e : J.ev)
     if (e) hipEventDestroy(e);
@@ -97,12 +109,27 @@ void free_job(ckc_ctx c, Job& J) {
 }
 
 template <class T>
-int dalloc(Job& J, T** out, size_t count) {
+int dalloc(ckc_ctx c, Job& J, T** out, size_t count) {
+  size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  bytes = (bytes + 255) & ~(size_t)255;
   void* p = nullptr;
-  size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) return fail(CKC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  J.bufs.push_back(p);
+  auto it = c->pool.lower_bound(bytes);
+  if (it != c->pool.end() && it->first <= 2 * bytes) {
+    bytes = it->first;
+    p = it->second;
+    c->pool_bytes -= bytes;
+    c->pool.erase(it);
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {  // release pooled buffers and retry once
+      for (auto& kv : c->pool) hipFree(kv.second);
+      c->pool.clear();
+      c->pool_bytes = 0;
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) return fail(CKC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  J.bufs.emplace_back(bytes, p);
   *out = (T*)p;
   return CKC_OK;
 }
@@ -149,6 +176,7 @@ void ckc_shutdown(ckc_ctx c) {
   c->jobs.clear();
   for (auto& kv : c->progs) hipFree(kv.second.dblob);
   for (auto& kv : c->tables) hipFree(kv.second.dptr);
+  for (auto& kv : c->pool) hipFree(kv.second);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -308,11 +336,11 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   int64_t* d_sc = nullptr;
   jobstate* d_js = nullptr;
   uint8_t* d_tr = nullptr;
-  if ((rc = dalloc(J, &J.d_inputs, n_inputs)) || (rc = dalloc(J, &d_sc, hsc.size())) ||
-      (rc = dalloc(J, &J.d_recs, n_records)) || (rc = dalloc(J, &J.d_counts, n_counts)) ||
-      (rc = dalloc(J, &J.d_status, n_inputs)) || (rc = dalloc(J, &d_js, 1)) ||
-      (rc = dalloc(J, &d_tr, trace_bytes)) ||
-      (J.dense && (rc = dalloc(J, &J.d_maps, n_inputs * 65536)))) {
+  if ((rc = dalloc(c, J, &J.d_inputs, n_inputs)) || (rc = dalloc(c, J, &d_sc, hsc.size())) ||
+      (rc = dalloc(c, J, &J.d_recs, n_records)) || (rc = dalloc(c, J, &J.d_counts, n_counts)) ||
+      (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &d_js, 1)) ||
+      (rc = dalloc(c, J, &d_tr, trace_bytes)) ||
+      (J.dense && (rc = dalloc(c, J, &J.d_maps, n_inputs * 65536)))) {
     free_job(c, J);
     return rc;
   }
@@ -344,8 +372,8 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   if (e == hipSuccess) e = launch_scan(a, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
   if (e == hipSuccess) e = launch_eval_trace(a, wg_trace, J.stream);
-  if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
+  if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
   if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
   if (e == hipSuccess) e = launch_finish(a, J.stream);

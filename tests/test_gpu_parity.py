@@ -142,6 +142,29 @@ def test_special_registers(ctx):
             compare(g, o, what=f"specials {mode} {generic}")
 
 
+def test_boundary_shapes(ctx):
+    """Boundary thread sets over many 3-D grid shapes (degenerate dimensions
+    included), for block sizes that take the block-major and the lane-tiled
+    trace layouts and for the interpreter."""
+    rng = np.random.default_rng(7)
+    p = Program(n_scalars=0, n_slots=2)
+    for nm in R.SPECIALS[:6]:
+        p.access(0, p.special(nm), w=64)
+    g = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), 32), p.special("tid.x"), 32)
+    p.access(1, p.add(g, p.mul(p.special("bid.y"), 3, 32), 32))
+    ir = p.to_bytes()
+    launches = []
+    for blk in ((64, 1, 1), (16, 4, 1), (8, 2, 1), (32, 2, 2), (3, 1, 1)):
+        for _ in range(6):
+            launches.append([int(v) for v in rng.integers(1, 6, size=3)] + list(blk))
+    tables = [[(W.LOGICAL_BASE, 8, 0, 0, 0), (W.LOGICAL_BASE, 4 * 200, 0, 0, 0)]] * len(launches)
+    wl = K.simple_workload(ir, launches, tables, mode=W.MODE_BOUNDARY)
+    for mode in (W.MODE_BOUNDARY, W.MODE_FULL, W.MODE_CORNERS):
+        for generic in (False, True):
+            gg, o = both(ctx, wl, mode, generic)
+            compare(gg, o, what=f"boundary shapes mode {mode} generic {generic}")
+
+
 def test_empty_and_degenerate(ctx):
     wl = K.simple_workload(K.listing3_program(), [[0, 1, 1, 32, 1, 1], [1, 1, 1, 1, 1, 1], [3, 0, 1, 4, 1, 1]],
                            [[(W.LOGICAL_BASE, 4, 0, 0, 0)] * 3] * 3, scalars=[[5], [5], [5]])
