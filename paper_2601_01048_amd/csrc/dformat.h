@@ -66,7 +66,7 @@ struct dinput {
   uint64_t prog;          // device address of the dprog blob
   uint64_t table;         // device address of the ckc_alloc[] table
   uint64_t lanes;         // threads in the thread set
-  uint64_t tile_begin[2]; // first tile in the trace / generic tile spaces
+  uint64_t tile_begin[3]; // first tile in each evaluator's tile space (see path)
   uint64_t rec_base;      // first record of this input
   uint64_t cnt_base;      // first site counter of this input
   uint64_t trace;         // device address of this input's trace (0 = none)
@@ -74,14 +74,16 @@ struct dinput {
   uint32_t mode;
   uint32_t L1, L2;        // key bits of depth-1 / depth-2 iteration ordinals
   uint32_t cap_log2[2];
-  uint32_t path;          // 0 = trace evaluator, 1 = generic interpreter (set by planning)
-  uint32_t n_tiles[2];
-  uint32_t tv;            // trace path layout: 0 = lane tiles, 1 = block-major wavefront jobs
+  uint32_t path;          // evaluator, set by planning: PATH_BLOCKS, PATH_GENERIC, PATH_LANES
+  uint32_t n_tiles[3];
   uint32_t pad[2];
 };
+// Evaluators of an input: the trace evaluator in block-major wavefront jobs,
+// the general interpreter, or the trace evaluator over lane tiles.
+enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };
 
 constexpr int MAX_SCALARS = 16;
-constexpr uint32_t LPB = 4;  // blocks per wavefront job of the block-major trace path
+constexpr uint32_t LPB = 8;  // blocks per wavefront job of the block-major trace path
 
 // Trace of a uniform-control program for one input: every thread performs the
 // same access sequence; each access index is base[class](thread) + off.
@@ -104,8 +106,17 @@ struct dtrace_head {
   uint32_t hang;        // 1 if every thread stops at the end of the trace
   int64_t coef[MAX_CLASSES][6];  // per class: tid.xyz, bid.xyz coefficients
   uint8_t cls_w[MAX_CLASSES];
-  uint32_t pad[3];
+  uint32_t any_dead;    // some entry names a NULL or FREED slot
+  uint32_t cap8;        // entry capacity rounded up to a multiple of 8
+  uint32_t pad;
 };
-// followed by dtrace_entry[trace_cap]
+static_assert(sizeof(dtrace_head) % 16 == 0, "trace head alignment");
+// Followed by three arrays of cap8 entries each:
+//   int64 hot64[cap8][2]   (offset, bound) for width-64 checks
+//   uint32 hot32[cap8][2]  (offset, bound) low halves for width-32 checks
+//   dtrace_entry entries[cap8]
+constexpr uint64_t trace_bytes(uint32_t cap) {
+  return sizeof(dtrace_head) + (uint64_t)((cap + 7u) & ~7u) * (16 + 8 + sizeof(dtrace_entry));
+}
 
 }  // namespace ckc

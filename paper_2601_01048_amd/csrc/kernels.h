@@ -11,8 +11,8 @@ namespace ckc {
 constexpr int TILE = 256;  // lanes per tile = threads per evaluation workgroup
 
 struct jobstate {
-  unsigned long long total_tiles[2];  // trace / generic tile spaces
-  unsigned long long next_tile[2];    // dynamic schedule counters
+  unsigned long long total_tiles[3];  // tile space of each evaluator (dinput.path)
+  unsigned long long next_tile[3];    // dynamic schedule counters
 };
 
 struct KArgs {
@@ -30,6 +30,7 @@ struct KArgs {
 hipError_t launch_plan(const KArgs& a, hipStream_t s);
 hipError_t launch_scan(const KArgs& a, hipStream_t s);
 hipError_t launch_eval_trace(const KArgs& a, uint32_t n_wg, hipStream_t s);
+hipError_t launch_eval_trace_lanes(const KArgs& a, uint32_t n_wg, hipStream_t s);
 hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, hipStream_t s);
 hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s);
 hipError_t launch_finish(const KArgs& a, hipStream_t s);

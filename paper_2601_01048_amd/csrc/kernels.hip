@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/ckc.h"
 #include "dformat.h"
 #include "kernels.h"
@@ -345,7 +347,7 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
   uint32_t lo[NREG], hi[NREG];
 #pragma unroll
   for (int r = 0; r < NREG; r++) { lo[r] = 0; hi[r] = 0; }
-  uint32_t n_ent = 0, n_cls = 0, overflow = 0, hang = 0;
+  uint32_t n_ent = 0, n_cls = 0, overflow = 0, hang = 0, any_dead = 0;
   uint64_t acc_per_thread = 0, faults_per_thread = 0;
   __shared__ int64_t cls_coef[MAX_CLASSES][6];
   __shared__ uint32_t cls_w[MAX_CLASSES];
@@ -423,6 +425,9 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
         }
         if (n_ent >= P->trace_cap) { overflow = 1; break; }
         if (j == 0) {
+          const uint32_t cap8 = (P->trace_cap + 7u) & ~7u;
+          int64_t* h64 = (int64_t*)(th + 1);
+          uint32_t* h32 = (uint32_t*)(h64 + 2 * (size_t)cap8);
           dtrace_entry E;
           E.off = off;
           E.keylo = (k[0] << L2) | k[1];
@@ -435,6 +440,11 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
           E.dead_kind = A.base == 0 ? CKC_KIND_NULL : ((A.flags & CKC_ALLOC_FREED) ? CKC_KIND_FREED : 0);
           E.pad = 0;
           te[n_ent] = E;
+          h64[2 * n_ent] = off;
+          h64[2 * n_ent + 1] = (int64_t)E.bound;
+          h32[2 * n_ent] = (uint32_t)off;
+          h32[2 * n_ent + 1] = (uint32_t)E.bound;
+          if (E.dead_kind) any_dead = 1;
         }
         n_ent++;
         acc_per_thread++;
@@ -518,6 +528,8 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
     th->n_classes = n_cls;
     th->overflow = overflow;
     th->hang = hang;
+    th->any_dead = any_dead;
+    th->cap8 = (P->trace_cap + 7u) & ~7u;
     for (uint32_t c = 0; c < n_cls; c++) {
       for (int d = 0; d < 6; d++) th->coef[c][d] = cls_coef[c][d];
       th->cls_w[c] = (uint8_t)cls_w[c];
@@ -554,7 +566,8 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
   uint32_t path = 1;
   if (trace) {
     dtrace_head* th = (dtrace_head*)in.trace;
-    dtrace_entry* te = (dtrace_entry*)(th + 1);
+    const uint32_t cap8 = (P->trace_cap + 7u) & ~7u;
+    dtrace_entry* te = (dtrace_entry*)((uint8_t*)(th + 1) + (size_t)cap8 * 24);
     build_trace(P, in, a.scalars + (size_t)i * MAX_SCALARS, (const ckc_alloc*)in.table, th, te, cnt, st);
     __syncthreads();
     path = th->overflow ? 1 : 0;
@@ -565,61 +578,62 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
   }
   if (j == 0) {
     uint64_t tiles = (lanes + TILE - 1) / TILE;
-    uint32_t tv = 0;
     const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
-    if (path == 0 && in.mode != CKC_REP_CORNERS && bs % 64u == 0 &&
-        ((const dtrace_head*)in.trace)->n_classes == 1) {
-      // block-major jobs: (64-thread slice position, group of LPB set blocks)
-      const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
-                                               : bset_size(in.launch);
-      const uint64_t jobs = (uint64_t)(bs / 64u) * ((nsb + LPB - 1) / LPB);
-      tiles = (jobs + 3) / 4;
-      tv = 1;
+    if (path == 0) {
+      if (in.mode != CKC_REP_CORNERS && bs % 64u == 0 && ((const dtrace_head*)in.trace)->n_classes == 1) {
+        // block-major jobs: (64-thread slice position, group of LPB set blocks)
+        const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
+                                                 : bset_size(in.launch);
+        const uint64_t jobs = (uint64_t)(bs / 64u) * ((nsb + LPB - 1) / LPB);
+        tiles = (jobs + 3) / 4;
+        path = PATH_BLOCKS;
+      } else {
+        path = PATH_LANES;
+      }
     }
     in.lanes = lanes;
     in.path = path;
-    in.tv = tv;
-    in.n_tiles[0] = path == 0 ? (uint32_t)tiles : 0;
-    in.n_tiles[1] = path == 1 ? (uint32_t)tiles : 0;
+    for (uint32_t q = 0; q < 3; q++) in.n_tiles[q] = q == path ? (uint32_t)tiles : 0u;
   }
 }
 
-// Exclusive prefix of per-input tile counts for both evaluators.
+// Exclusive prefix of per-input tile counts for the three evaluators.
 __global__ void __launch_bounds__(1024) scan_kernel(KArgs a) {
-  __shared__ unsigned long long part[2][1024 / 64];
-  __shared__ unsigned long long carry[2];
+  __shared__ unsigned long long part[3][1024 / 64];
+  __shared__ unsigned long long carry[3];
   const uint32_t t = threadIdx.x;
-  if (t < 2) carry[t] = 0;
+  if (t < 3) carry[t] = 0;
   __syncthreads();
   for (uint32_t base = 0; base < a.n_inputs; base += 1024) {
-    uint32_t i = base + t;
-    uint64_t v0 = i < a.n_inputs ? a.inputs[i].n_tiles[0] : 0;
-    uint64_t v1 = i < a.n_inputs ? a.inputs[i].n_tiles[1] : 0;
-    // inclusive wave scan
-    uint64_t s0 = v0, s1 = v1;
-    for (int o = 1; o < 64; o <<= 1) {
-      uint64_t u0 = __shfl_up((unsigned long long)s0, o, 64);
-      uint64_t u1 = __shfl_up((unsigned long long)s1, o, 64);
-      if ((int)lane_id() >= o) { s0 += u0; s1 += u1; }
+    const uint32_t i = base + t;
+    uint64_t v[3], sc[3];
+    for (int p = 0; p < 3; p++) {
+      v[p] = i < a.n_inputs ? a.inputs[i].n_tiles[p] : 0;
+      sc[p] = v[p];
     }
-    if (lane_id() == 63) { part[0][t / 64] = s0; part[1][t / 64] = s1; }
+    for (int o = 1; o < 64; o <<= 1)  // inclusive wavefront scan
+      for (int p = 0; p < 3; p++) {
+        const uint64_t u = __shfl_up((unsigned long long)sc[p], o, 64);
+        if ((int)lane_id() >= o) sc[p] += u;
+      }
+    if (lane_id() == 63)
+      for (int p = 0; p < 3; p++) part[p][t / 64] = sc[p];
     __syncthreads();
-    uint64_t w0 = 0, w1 = 0;
-    for (uint32_t q = 0; q < t / 64; q++) { w0 += part[0][q]; w1 += part[1][q]; }
-    uint64_t c0 = carry[0], c1 = carry[1];
-    if (i < a.n_inputs) {
-      a.inputs[i].tile_begin[0] = c0 + w0 + s0 - v0;
-      a.inputs[i].tile_begin[1] = c1 + w1 + s1 - v1;
+    uint64_t w[3] = {0, 0, 0}, c[3];
+    for (int p = 0; p < 3; p++) {
+      for (uint32_t q = 0; q < t / 64; q++) w[p] += part[p][q];
+      c[p] = carry[p];
     }
+    if (i < a.n_inputs)
+      for (int p = 0; p < 3; p++) a.inputs[i].tile_begin[p] = c[p] + w[p] + sc[p] - v[p];
     __syncthreads();
-    if (t == 1023) { carry[0] = c0 + w0 + s0; carry[1] = c1 + w1 + s1; }
+    if (t == 1023)
+      for (int p = 0; p < 3; p++) carry[p] = c[p] + w[p] + sc[p];
     __syncthreads();
   }
-  if (t == 0) {
-    a.js->total_tiles[0] = carry[0];
-    a.js->total_tiles[1] = carry[1];
-    a.js->next_tile[0] = 0;
-    a.js->next_tile[1] = 0;
+  if (t < 3) {
+    a.js->total_tiles[t] = carry[t];
+    a.js->next_tile[t] = 0;
   }
 }
 
@@ -670,189 +684,406 @@ __device__ __forceinline__ uint32_t find_input_c(c_input* in, uint32_t n, uint32
   return lo;
 }
 
-// Rare path of one trace entry: some lane of the wavefront violates.
-__device__ __noinline__ void trace_violation(ckc_record* rec, uint32_t bad, uint64_t gtid, uint32_t Lsum,
-                                             uint64_t keylo) {
-  merge_violation(rec, bad, (gtid << Lsum) | keylo);
-}
+// Violations found by the trace evaluator are merged per workgroup in LDS (first
+// key, count, kinds per access of the current input) and flushed into the job's
+// records once per input.  Every thread-set decode of this evaluator is
+// increasing in the global thread id along the lanes of a wavefront, and the
+// blocks of a wavefront job are increasing too, so the first violation of a
+// wavefront is its lowest violating lane.
+constexpr uint32_t TR_ACC_LDS = 256;
+struct TraceLds {
+  unsigned long long fk[TR_ACC_LDS];
+  unsigned long long cnt[TR_ACC_LDS];
+  uint32_t kinds[TR_ACC_LDS];
+};
 
-// Checks of a trace whose entries all use one coefficient class of width W:
-// per entry one add and one unsigned compare against the clamped bound.
-template <int W>
-__device__ __forceinline__ void trace_entries_1(c_entry* te, uint32_t ne, uint64_t base, bool act,
-                                                ckc_record* rec, uint64_t gtid, uint32_t Lsum) {
-  for (uint32_t e = 0; e < ne; e++) {
-    const int64_t off = te[e].off;
-    const uint64_t bound = te[e].bound;
-    const uint32_t dead = te[e].dead_kind;
-    uint32_t bad;
-    if (W == 32) {
-      const uint32_t v = (uint32_t)base + (uint32_t)off;
-      bad = v >= (uint32_t)bound ? (((int32_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+__device__ __forceinline__ void tr_note(TraceLds& S, ckc_record* rec, uint32_t acc, bool lds, uint64_t key,
+                                        uint64_t cnt, uint32_t kinds) {
+  if (lane_id() == 0) {
+    if (lds) {
+      atomicMin(&S.fk[acc], (unsigned long long)key);
+      atomicAdd(&S.cnt[acc], (unsigned long long)cnt);
+      atomicOr(&S.kinds[acc], kinds);
     } else {
-      const uint64_t v = base + (uint64_t)off;
-      bad = v >= bound ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
+      atomicMin((unsigned long long*)&rec[acc].first_key, (unsigned long long)key);
+      atomicAdd((unsigned long long*)&rec[acc].count, (unsigned long long)cnt);
+      atomicOr(&rec[acc].kinds, kinds);
     }
-    if (dead) bad = dead;
-    bad = act ? bad : 0u;
-    if (__ballot(bad != 0)) trace_violation(rec + te[e].acc, bad, gtid, Lsum, te[e].keylo);
   }
 }
 
-// Block-major checks of one wavefront job: this lane's thread position
-// (tlin) in up to LPB set blocks; tpart is the thread part of the index base,
-// bp[j] the block parts (wavefront-uniform).  Per entry: one add for the
-// thread part, then one add and one compare per block.
-template <int W>
-__device__ __forceinline__ void trace_blocks(c_entry* te, uint32_t ne, uint64_t tpart, const uint64_t* bp,
-                                             const uint64_t* gb, uint32_t nvalid, uint32_t tlin,
-                                             ckc_record* rec, uint32_t Lsum) {
-  for (uint32_t e = 0; e < ne; e++) {
-    const int64_t off = te[e].off;
-    const uint64_t bound = te[e].bound;
-    const uint32_t dead = te[e].dead_kind;
-    uint64_t m = 0;
-    uint32_t bad[LPB];
+__device__ void tr_flush(TraceLds& S, ckc_record* rec, uint32_t n_acc) {
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < n_acc && q < TR_ACC_LDS; q += TILE) {
+    if (S.cnt[q]) {
+      atomicMin((unsigned long long*)&rec[q].first_key, S.fk[q]);
+      atomicAdd((unsigned long long*)&rec[q].count, S.cnt[q]);
+      atomicOr(&rec[q].kinds, S.kinds[q]);
+      S.fk[q] = ~0ull;
+      S.cnt[q] = 0;
+      S.kinds[q] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// Out-of-line boundary-set decode (keeps its divisions off the FULL path).
+__device__ __forceinline__ uint64_t bset_block_call(uint32_t gx, uint32_t gy, uint32_t gz, uint64_t k) {
+  const uint32_t L[3] = {gx, gy, gz};
+  return bset_block(L, k);
+}
+
+typedef const __attribute__((address_space(4))) int64_t c_i64;
+typedef const __attribute__((address_space(4))) uint32_t c_u32;
+typedef const __attribute__((address_space(4))) dprog c_dprog;
+
+// Violation path of entry e in a block-major job (rare): per block, the mask
+// of violating lanes and of negative indices; the first block with a
+// violation gives the first key at its lowest violating lane.
+template <int W, class BT>
+__device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint32_t e, uint64_t tpart,
+                                                 const BT* bp, const uint32_t* Lg, uint64_t g, uint32_t bs,
+                                                 uint32_t nvalid, uint32_t tlin_lane0, ckc_record* rec,
+                                                 bool lds, uint32_t Lsum) {
+  const int64_t off = te[e].off;
+  const uint64_t bound = te[e].bound;
+  const uint32_t dead = te[e].dead_kind;
+  uint64_t fk = ~0ull, cnt = 0;
+  uint32_t kinds = 0;
+  for (uint32_t j = 0; j < nvalid; j++) {
+    uint64_t badm, underm;
+    if (W == 32) {
+      const uint32_t v = (uint32_t)tpart + (uint32_t)off + (uint32_t)bp[j];
+      badm = __ballot(v >= (uint32_t)bound);
+      underm = __ballot((int32_t)v < 0);
+    } else {
+      const uint64_t v = tpart + (uint64_t)off + (uint64_t)bp[j];
+      badm = __ballot(v >= bound);
+      underm = __ballot((int64_t)v < 0);
+    }
+    if (dead) {
+      badm = ~0ull;
+      kinds |= dead;
+    } else {
+      underm &= badm;
+      kinds |= (underm ? CKC_KIND_UNDER : 0u) | ((badm & ~underm) ? CKC_KIND_OVER : 0u);
+    }
+    if (badm) {
+      if (fk == ~0ull) {
+        // block of member g*LPB + j of the thread set (Lg[6] holds the mode)
+        const uint64_t k = g * LPB + j;
+        const uint64_t blin = Lg[6] == CKC_FULL ? k : bset_block(Lg, k);
+        fk = ((blin * bs + tlin_lane0 + (uint64_t)(__ffsll((unsigned long long)badm) - 1)) << Lsum) |
+             te[e].keylo;
+      }
+      cnt += (uint64_t)__popcll(badm);
+    }
+  }
+  if (cnt) tr_note(S, rec, te[e].acc, lds, fk, cnt, kinds);
+}
+
+// Block-major checks of one wavefront job: this lane's thread position in up to
+// LPB set blocks; tpart is the thread part of the index base, bp[j] the block
+// parts (wavefront-uniform).  Entries come as packed (offset, bound) pairs
+// through scalar loads.  Width 32: an index is in bounds iff its unsigned
+// value is below the bound (clamped to 2^31), so one entry is clean for all
+// blocks iff the unsigned maximum over the blocks is below the bound -- one
+// add per block, a max tree and one compare.
+template <int W, bool ALL, class BT>
+__device__ __forceinline__ bool entry_bad(uint64_t tpart, uint64_t off, uint64_t bnd, const BT* bp,
+                                          uint32_t nvalid) {
+  if (W == 32) {
+    const uint32_t t = (uint32_t)tpart + (uint32_t)off;
+    uint32_t mx = 0;
 #pragma unroll
     for (uint32_t j = 0; j < LPB; j++) {
-      if (W == 32) {
-        const uint32_t v = (uint32_t)tpart + (uint32_t)off + (uint32_t)bp[j];
-        bad[j] = v >= (uint32_t)bound ? (((int32_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
-      } else {
-        const uint64_t v = tpart + (uint64_t)off + bp[j];
-        bad[j] = v >= bound ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
-      }
-      if (dead) bad[j] = dead;
-      if (j >= nvalid) bad[j] = 0;
-      m |= __ballot(bad[j] != 0);
+      const uint32_t v = t + (uint32_t)bp[j];
+      if (ALL || j < nvalid) mx = v > mx ? v : mx;
     }
-    if (m) {
-      const uint32_t acc = te[e].acc;
-      const uint64_t keylo = te[e].keylo;
+    return mx >= (uint32_t)bnd;
+  } else {
+    const uint64_t t = tpart + off;
+    bool x = false;
 #pragma unroll
-      for (uint32_t j = 0; j < LPB; j++)
-        if (__ballot(bad[j] != 0)) trace_violation(rec + acc, bad[j], gb[j] + tlin, Lsum, keylo);
-    }
+    for (uint32_t j = 0; j < LPB; j++)
+      if (ALL || j < nvalid) x |= (t + (uint64_t)bp[j]) >= bnd;
+    return x;
   }
 }
 
+template <int W, bool ALL, bool DEADS, class BT>
+__device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h64, c_u32* h32, uint32_t ne,
+                                             uint64_t tpart, const BT* bp, const uint32_t* Lg, uint64_t g,
+                                             uint32_t bs, uint32_t nvalid, uint32_t tlin_lane0,
+                                             ckc_record* rec, bool lds, uint32_t Lsum) {
+  constexpr uint32_t EB = W == 32 ? 8 : 4;  // entries per scalar-load batch
+  uint32_t e = 0;  // first entry that needs the violation path
+  if (!DEADS) {
+    // fast scan: stop at the first entry with a violating lane
+    const uint32_t neb = ne - ne % EB;
+    bool hit = false;
+    for (uint32_t e0 = 0; e0 < neb && !hit; e0 += EB) {
+      uint64_t off[EB], bnd[EB];
+#pragma unroll
+      for (uint32_t k = 0; k < EB; k++) {
+        if (W == 32) {
+          off[k] = h32[2 * (e0 + k)];
+          bnd[k] = h32[2 * (e0 + k) + 1];
+        } else {
+          off[k] = (uint64_t)h64[2 * (e0 + k)];
+          bnd[k] = (uint64_t)h64[2 * (e0 + k) + 1];
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < EB; k++) {
+        if (!hit && __ballot(entry_bad<W, ALL>(tpart, off[k], bnd[k], bp, nvalid))) {
+          hit = true;
+          e = e0 + k;
+        }
+      }
+      if (!hit) e = e0 + EB;
+    }
+    if (!hit) {
+      for (; e < ne; e++) {
+        uint64_t off, bnd;
+        if (W == 32) {
+          off = h32[2 * e];
+          bnd = h32[2 * e + 1];
+        } else {
+          off = (uint64_t)h64[2 * e];
+          bnd = (uint64_t)h64[2 * e + 1];
+        }
+        if (__ballot(entry_bad<W, ALL>(tpart, off, bnd, bp, nvalid))) break;
+      }
+    }
+    if (e >= ne) return;
+  }
+  // violation path: the remaining entries one by one (one copy of this code)
+  for (; e < ne; e++) {
+    uint64_t off, bnd;
+    if (W == 32) {
+      off = h32[2 * e];
+      bnd = h32[2 * e + 1];
+    } else {
+      off = (uint64_t)h64[2 * e];
+      bnd = (uint64_t)h64[2 * e + 1];
+    }
+    if (DEADS || __ballot(entry_bad<W, false>(tpart, off, bnd, bp, nvalid)))
+      blocks_violation<W>(S, te, e, tpart, bp, Lg, g, bs, nvalid, tlin_lane0, rec, lds, Lsum);
+  }
+}
+
+// Per-input state of the trace evaluator (wavefront-uniform).
+struct TrIn {
+  uint32_t L[7];  // launch dims, then the thread-set mode
+  uint32_t bs, gxy, bxy, mode, Lsum, ne, n_acc;
+  UDiv dgx, dgxy, dbx, dbxy, dspb;
+  uint64_t nsb;
+  c_head* th;     // coefficients are re-read per job (scalar loads)
+  uint32_t any_dead;
+  bool lds;
+  c_entry* te;
+  c_i64* h64;
+  c_u32* h32;
+  ckc_record* rec;
+};
+
+// One block-major wavefront job: slice position o (64 threads) of the blocks
+// g*LPB .. g*LPB+LPB-1 of the set.
+template <int W>
+__device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint64_t g, uint32_t o) {
+  typedef typename std::conditional<W == 32, uint32_t, uint64_t>::type BT;
+  const uint32_t tlin = o * 64u + (threadIdx.x & 63u);
+  const uint32_t tz = udiv(tlin, I.dbxy), tr = tlin - tz * I.bxy;
+  const uint32_t ty = udiv(tr, I.dbx);
+  const uint32_t tx = tr - ty * I.L[3];
+  const int64_t k0 = I.th->coef[0][0], k1 = I.th->coef[0][1], k2 = I.th->coef[0][2];
+  const int64_t k3 = I.th->coef[0][3], k4 = I.th->coef[0][4], k5 = I.th->coef[0][5];
+  uint64_t tpart = 0;
+  if (k0 == 1) tpart += tx; else if (k0 != 0) tpart += (uint64_t)k0 * tx;
+  if (k1 == 1) tpart += ty; else if (k1 != 0) tpart += (uint64_t)k1 * ty;
+  if (k2 == 1) tpart += tz; else if (k2 != 0) tpart += (uint64_t)k2 * tz;
+  BT bp[LPB];
+  const uint64_t left = I.nsb - g * LPB;
+  const uint32_t nvalid = left < LPB ? (uint32_t)left : LPB;
+  if (I.mode == CKC_FULL) {
+    // blocks g*LPB ..: walk x with carries from the first one
+    const uint32_t b0 = (uint32_t)(g * LPB);
+    uint32_t bz = udiv(b0, I.dgxy), brem = b0 - bz * I.gxy;
+    uint32_t by = udiv(brem, I.dgx), bx = brem - by * I.L[0];
+#pragma unroll
+    for (uint32_t jj = 0; jj < LPB; jj++) {
+      bp[jj] = (BT)((uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz);
+      if (++bx == I.L[0]) {
+        bx = 0;
+        if (++by == I.L[1]) { by = 0; ++bz; }
+      }
+    }
+  } else {
+    for (uint32_t jj = 0; jj < LPB; jj++) {
+      const uint32_t blin = jj < nvalid ? (uint32_t)bset_block_call(I.L[0], I.L[1], I.L[2], g * LPB + jj) : 0u;
+      const uint32_t bz = udiv(blin, I.dgxy), brem = blin - bz * I.gxy;
+      const uint32_t by = udiv(brem, I.dgx), bx = brem - by * I.L[0];
+      bp[jj] = (BT)((uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz);
+    }
+  }
+  const uint32_t t0 = o * 64u;
+  if (I.any_dead) {
+    trace_blocks<W, false, true>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+  } else if (nvalid == LPB) {
+    trace_blocks<W, true, false>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+  } else {
+    trace_blocks<W, false, false>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+  }
+}
+
+// Per-lane checks of one lane tile (thread sets without the block-major
+// layout).  The lowest violating lane has the smallest key.
+__device__ __forceinline__ void lanes_violation(TraceLds& S, c_entry* te, uint32_t e, uint64_t v, bool act,
+                                                uint64_t gtid, ckc_record* rec, bool lds, uint32_t Lsum) {
+  const uint32_t w = te[e].w;
+  const uint64_t bound = te[e].bound;
+  const uint32_t dead = te[e].dead_kind;
+  uint64_t badm, underm;
+  if (w == 32) {
+    badm = __ballot(act && (uint32_t)v >= (uint32_t)bound);
+    underm = __ballot(act && (int32_t)(uint32_t)v < 0);
+  } else {
+    badm = __ballot(act && v >= bound);
+    underm = __ballot(act && (int64_t)v < 0);
+  }
+  uint32_t kinds;
+  if (dead) {
+    badm = __ballot(act);
+    kinds = dead;
+  } else {
+    underm &= badm;
+    kinds = (underm ? CKC_KIND_UNDER : 0u) | ((badm & ~underm) ? CKC_KIND_OVER : 0u);
+  }
+  if (!badm) return;
+  const int first = __ffsll((unsigned long long)badm) - 1;
+  const uint64_t key = (readlane64(gtid, first) << Lsum) | te[e].keylo;
+  tr_note(S, rec, te[e].acc, lds, key, (uint64_t)__popcll(badm), kinds);
+}
+
+// Loads the per-input state of the trace evaluator.
+__device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_record* recs, uint64_t& tb,
+                                        uint32_t path, uint32_t& ncls, uint32_t& w0, c_head*& th) {
+  for (int q = 0; q < 6; q++) I.L[q] = ins[i].launch[q];
+  I.L[6] = ins[i].mode;
+  I.bs = I.L[3] * I.L[4] * I.L[5];
+  I.gxy = I.L[0] * I.L[1];
+  I.bxy = I.L[3] * I.L[4];
+  I.dgx = udiv_make(I.L[0]);
+  I.dgxy = udiv_make(I.gxy);
+  I.dbx = udiv_make(I.L[3]);
+  I.dbxy = udiv_make(I.bxy);
+  I.dspb = udiv_make(I.bs >= 64 ? I.bs / 64u : 1u);
+  I.mode = ins[i].mode;
+  I.Lsum = ins[i].L1 + ins[i].L2;
+  I.n_acc = ((c_dprog*)ins[i].prog)->n_accesses;
+  I.lds = I.n_acc <= TR_ACC_LDS;
+  th = (c_head*)ins[i].trace;
+  const uint32_t cap8 = th->cap8;
+  I.h64 = (c_i64*)(th + 1);
+  I.h32 = (c_u32*)(I.h64 + 2 * (size_t)cap8);
+  I.te = (c_entry*)(I.h32 + 2 * (size_t)cap8);
+  I.any_dead = th->any_dead;
+  I.rec = recs + ins[i].rec_base;
+  I.ne = th->n_entries;
+  ncls = th->n_classes;
+  w0 = th->cls_w[0];
+  I.nsb = I.mode == CKC_FULL ? (uint64_t)I.L[0] * I.L[1] * I.L[2] : bset_size(I.L);
+  I.th = th;
+  tb = ins[i].tile_begin[path];
+}
+
+// Trace evaluator, block-major layout: persistent workgroups over a contiguous
+// range of tiles; a tile is four wavefront jobs.
 __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
+  __shared__ TraceLds S;
   c_jobstate* js = (c_jobstate*)a.js;
   c_input* ins = (c_input*)a.inputs;
-  const uint64_t total = js->total_tiles[0];
+  const uint64_t total = js->total_tiles[PATH_BLOCKS];
   if (total == 0) return;
   const uint64_t G = gridDim.x;
   const uint64_t t_begin = total * blockIdx.x / G, t_end = total * (blockIdx.x + 1) / G;
   if (t_begin >= t_end) return;
   const uint32_t tid = threadIdx.x;
-  uint32_t i = find_input_c(ins, a.n_inputs, 0, t_begin);
-  uint32_t cur = 0xFFFFFFFFu;
-  // per-input state (wavefront-uniform)
-  uint32_t L[6] = {0, 0, 0, 0, 0, 0};
-  uint32_t bs = 1, gxy = 1, bxy = 1, mode = 0, Lsum = 0, ncls = 0, ne = 0, w0 = 32;
-  UDiv dbs{1, 0}, dgx{1, 0}, dgxy{1, 0}, dbx{1, 0}, dbxy{1, 0}, dspb{1, 0};
-  uint64_t lanes = 0, tb = 0, blin0 = 0, nsb = 0;
-  uint32_t tlin0 = 0, tv = 0;
-  int64_t k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0, k5 = 0;
+  for (uint32_t q = tid; q < TR_ACC_LDS; q += TILE) {
+    S.fk[q] = ~0ull;
+    S.cnt[q] = 0;
+    S.kinds[q] = 0;
+  }
+  __syncthreads();
+  uint32_t i = find_input_c(ins, a.n_inputs, PATH_BLOCKS, t_begin);
+  uint32_t cur = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint64_t tb = 0, cur_end = 0;
   c_head* th = nullptr;
-  c_entry* te = nullptr;
-  ckc_record* rec = nullptr;
-  uint64_t cur_end = 0;
+  TrIn I;
   for (uint64_t t = t_begin; t < t_end; t++) {
-    if (t >= cur_end || cur == 0xFFFFFFFFu) {
-      while (ins[i].n_tiles[0] == 0 || t >= ins[i].tile_begin[0] + ins[i].n_tiles[0]) i++;
-      cur_end = ins[i].tile_begin[0] + ins[i].n_tiles[0];
-    }
-    if (i != cur) {
+    if (t >= cur_end) {
+      while (ins[i].n_tiles[PATH_BLOCKS] == 0 ||
+             t >= ins[i].tile_begin[PATH_BLOCKS] + ins[i].n_tiles[PATH_BLOCKS])
+        i++;
+      cur_end = ins[i].tile_begin[PATH_BLOCKS] + ins[i].n_tiles[PATH_BLOCKS];
+      if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
       cur = i;
-      for (int q = 0; q < 6; q++) L[q] = ins[i].launch[q];
-      bs = L[3] * L[4] * L[5];
-      gxy = L[0] * L[1];
-      bxy = L[3] * L[4];
-      dbs = udiv_make(bs); dgx = udiv_make(L[0]); dgxy = udiv_make(gxy);
-      dbx = udiv_make(L[3]); dbxy = udiv_make(bxy);
-      dspb = udiv_make(bs >= 64 ? bs / 64u : 1u);
-      mode = ins[i].mode;
-      Lsum = ins[i].L1 + ins[i].L2;
-      lanes = ins[i].lanes;
-      tb = ins[i].tile_begin[0];
-      th = (c_head*)ins[i].trace;
-      te = (c_entry*)(th + 1);
-      rec = a.recs + ins[i].rec_base;
-      ncls = th->n_classes;
-      ne = th->n_entries;
-      w0 = th->cls_w[0];
-      tv = ins[i].tv;
-      nsb = mode == CKC_FULL ? (uint64_t)L[0] * L[1] * L[2] : bset_size(L);
-      k0 = th->coef[0][0]; k1 = th->coef[0][1]; k2 = th->coef[0][2];
-      k3 = th->coef[0][3]; k4 = th->coef[0][4]; k5 = th->coef[0][5];
-      const uint64_t l0 = (t - tb) * TILE;
-      blin0 = l0 / bs;
-      tlin0 = (uint32_t)(l0 - blin0 * bs);
+      tr_load(I, ins, i, a.recs, tb, PATH_BLOCKS, ncls, w0, th);
     }
-    if (tv == 1) {
-      // ---- block-major wavefront job ----
-      const uint32_t wv = ufirst(tid >> 6);
-      const uint64_t job = (t - tb) * 4 + wv;
-      const uint32_t spb = bs / 64u;
-      const uint64_t g = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, dspb) : job / spb;
-      const uint32_t o = (uint32_t)(job - g * spb);
-      if (g * LPB >= nsb) continue;  // past the last group (whole wavefront)
-      const uint32_t tlin = o * 64u + (tid & 63u);
-      const uint32_t tz = udiv(tlin, dbxy), tr = tlin - tz * bxy;
-      const uint32_t ty = udiv(tr, dbx);
-      const uint32_t tx = tr - ty * L[3];
-      uint64_t tpart = 0;
-      if (k0 == 1) tpart += tx; else if (k0 != 0) tpart += (uint64_t)k0 * tx;
-      if (k1 == 1) tpart += ty; else if (k1 != 0) tpart += (uint64_t)k1 * ty;
-      if (k2 == 1) tpart += tz; else if (k2 != 0) tpart += (uint64_t)k2 * tz;
-      uint64_t bp[LPB], gb[LPB];
-      const uint64_t left = nsb - g * LPB;
-      const uint32_t nvalid = left < LPB ? (uint32_t)left : LPB;
-#pragma unroll
-      for (uint32_t jj = 0; jj < LPB; jj++) {
-        const uint64_t k = g * LPB + jj;
-        const uint32_t blin = jj < nvalid ? (uint32_t)(mode == CKC_FULL ? k : bset_block(L, k)) : 0u;
-        const uint32_t bz = udiv(blin, dgxy), brem = blin - bz * gxy;
-        const uint32_t by = udiv(brem, dgx), bx = brem - by * L[0];
-        bp[jj] = (uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz;
-        gb[jj] = (uint64_t)blin * bs;
-      }
-      if (w0 == 32) trace_blocks<32>(te, ne, tpart, bp, gb, nvalid, tlin, rec, Lsum);
-      else trace_blocks<64>(te, ne, tpart, bp, gb, nvalid, tlin, rec, Lsum);
-      continue;
+    const uint32_t wv = ufirst(tid >> 6);
+    const uint64_t job = (t - tb) * 4 + wv;
+    const uint32_t spb = I.bs / 64u;
+    const uint64_t g = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, I.dspb) : job / spb;
+    const uint32_t o = (uint32_t)(job - g * spb);
+    if (g * LPB >= I.nsb) continue;  // past the last group (whole wavefront)
+    if (w0 == 32) block_job<32>(S, I, g, o);
+    else block_job<64>(S, I, g, o);
+  }
+  if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+}
+
+// Trace evaluator over lane tiles (thread sets or traces the block-major
+// layout does not cover): TILE consecutive lanes of the thread set per tile.
+__global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
+  __shared__ TraceLds S;
+  c_jobstate* js = (c_jobstate*)a.js;
+  c_input* ins = (c_input*)a.inputs;
+  const uint64_t total = js->total_tiles[PATH_LANES];
+  if (total == 0) return;
+  const uint64_t G = gridDim.x;
+  const uint64_t t_begin = total * blockIdx.x / G, t_end = total * (blockIdx.x + 1) / G;
+  if (t_begin >= t_end) return;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t q = tid; q < TR_ACC_LDS; q += TILE) {
+    S.fk[q] = ~0ull;
+    S.cnt[q] = 0;
+    S.kinds[q] = 0;
+  }
+  __syncthreads();
+  uint32_t i = find_input_c(ins, a.n_inputs, PATH_LANES, t_begin);
+  uint32_t cur = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint64_t tb = 0, cur_end = 0, lanes = 0;
+  c_head* th = nullptr;
+  TrIn I;
+  for (uint64_t t = t_begin; t < t_end; t++) {
+    if (t >= cur_end) {
+      while (ins[i].n_tiles[PATH_LANES] == 0 ||
+             t >= ins[i].tile_begin[PATH_LANES] + ins[i].n_tiles[PATH_LANES])
+        i++;
+      cur_end = ins[i].tile_begin[PATH_LANES] + ins[i].n_tiles[PATH_LANES];
+      if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+      cur = i;
+      tr_load(I, ins, i, a.recs, tb, PATH_LANES, ncls, w0, th);
+      lanes = ins[i].lanes;
     }
     const uint64_t l = (t - tb) * TILE + tid;
     const bool act = l < lanes;
-    uint32_t c6[6];
-    uint64_t gtid;
-    if (mode == CKC_FULL) {
-      // consecutive lanes are consecutive threads: block carry by division
-      const uint32_t u = tlin0 + tid;
-      const uint32_t q = udiv(u, dbs);
-      const uint32_t tlin = u - q * bs;
-      uint32_t blin = (uint32_t)blin0 + q;
-      if (bs % 64u == 0) blin = ufirst(blin);  // one block per wavefront
-      const uint32_t z = udiv(blin, dgxy), r = blin - z * gxy;
-      const uint32_t y = udiv(r, dgx);
-      c6[3] = r - y * L[0]; c6[4] = y; c6[5] = z;
-      const uint32_t tz = udiv(tlin, dbxy), tr = tlin - tz * bxy;
-      const uint32_t ty = udiv(tr, dbx);
-      c6[0] = tr - ty * L[3]; c6[1] = ty; c6[2] = tz;
-      gtid = (uint64_t)blin * bs + tlin;
-      // next tile
-      tlin0 += TILE;
-      const uint32_t qn = udiv(tlin0, dbs);
-      blin0 += qn;
-      tlin0 -= qn * bs;
-    } else {
-      Thr T;
-      decode_lane(mode, L, act ? l : 0, T);
-      c6[0] = T.t[0]; c6[1] = T.t[1]; c6[2] = T.t[2]; c6[3] = T.b[0]; c6[4] = T.b[1]; c6[5] = T.b[2];
-      gtid = T.gtid;
-    }
-    // base of each coefficient class: sum of coefficient x coordinate, skipping
-    // zero coefficients (uniform branches)
+    Thr T;
+    decode_lane(I.mode, I.L, act ? l : 0, T);
+    const uint32_t c6[6] = {T.t[0], T.t[1], T.t[2], T.b[0], T.b[1], T.b[2]};
+    // base of each coefficient class: sum of coefficient x coordinate,
+    // skipping zero coefficients (uniform branches)
     uint64_t base[MAX_CLASSES];
 #pragma unroll
     for (int c = 0; c < MAX_CLASSES; c++) {
@@ -867,27 +1098,18 @@ __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
       }
       base[c] = b;
     }
-    if (ncls == 1) {
-      if (w0 == 32) trace_entries_1<32>(te, ne, base[0], act, rec, gtid, Lsum);
-      else trace_entries_1<64>(te, ne, base[0], act, rec, gtid, Lsum);
-    } else {
-      for (uint32_t e = 0; e < ne; e++) {
-        const uint32_t c = te[e].cls;
-        const uint64_t b = c == 0 ? base[0] : c == 1 ? base[1] : c == 2 ? base[2] : base[3];
-        const uint64_t v = b + (uint64_t)te[e].off;
-        uint32_t bad;
-        if (te[e].w == 32) {
-          const uint32_t v32 = (uint32_t)v;
-          bad = v32 >= (uint32_t)te[e].bound ? (((int32_t)v32 < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
-        } else {
-          bad = v >= te[e].bound ? (((int64_t)v < 0) ? CKC_KIND_UNDER : CKC_KIND_OVER) : 0u;
-        }
-        if (te[e].dead_kind) bad = te[e].dead_kind;
-        bad = act ? bad : 0u;
-        if (__ballot(bad != 0)) trace_violation(rec + te[e].acc, bad, gtid, Lsum, te[e].keylo);
-      }
+    c_entry* te = I.te;
+    for (uint32_t e = 0; e < I.ne; e++) {
+      const uint32_t c = te[e].cls;
+      const uint64_t b = c == 0 ? base[0] : c == 1 ? base[1] : c == 2 ? base[2] : base[3];
+      const uint64_t v = b + (uint64_t)te[e].off;
+      bool x;
+      if (te[e].w == 32) x = (uint32_t)v >= (uint32_t)te[e].bound;
+      else x = v >= te[e].bound;
+      if (__ballot(act && x) || te[e].dead_kind) lanes_violation(S, te, e, v, act, T.gtid, I.rec, I.lds, I.Lsum);
     }
   }
+  if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1219,7 +1441,7 @@ __device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, const dpr
 __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   __shared__ GenLds S;
   const uint32_t tid = threadIdx.x;
-  const uint64_t total = a.js->total_tiles[1];
+  const uint64_t total = a.js->total_tiles[PATH_GENERIC];
   if (total == 0) return;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
@@ -1227,11 +1449,11 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   uint64_t cur_prog = 0;
   for (;;) {
     __syncthreads();
-    if (tid == 0) S.tile = atomicAdd((unsigned long long*)&a.js->next_tile[1], 1ull);
+    if (tid == 0) S.tile = atomicAdd((unsigned long long*)&a.js->next_tile[PATH_GENERIC], 1ull);
     __syncthreads();
     const uint64_t t = S.tile;
     if (t >= total) break;
-    const uint32_t i = find_input(a.inputs, a.n_inputs, 1, t);
+    const uint32_t i = find_input(a.inputs, a.n_inputs, PATH_GENERIC, t);
     const dinput& in = a.inputs[i];
     const dprog* P = (const dprog*)in.prog;
     if (i != cur) {
@@ -1248,7 +1470,7 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
       cur = i;
       __syncthreads();
     }
-    const uint64_t l = (t - in.tile_begin[1]) * TILE + tid;
+    const uint64_t l = (t - in.tile_begin[PATH_GENERIC]) * TILE + tid;
     const bool act = l < in.lanes;
     Thr T;
     decode_lane(in.mode, in.launch, act ? l : 0, T);
@@ -1352,7 +1574,7 @@ __global__ void __launch_bounds__(256) finish_kernel(KArgs a) {
   const dprog* P = (const dprog*)in.prog;
   uint32_t* cnt = a.counts + in.cnt_base;
   const uint64_t lanes = in.lanes;
-  if (in.path == 0) {
+  if (in.path != PATH_GENERIC) {
     for (uint32_t s = threadIdx.x; s < P->n_sites; s += blockDim.x) {
       uint64_t v = (uint64_t)cnt[s] * lanes;
       cnt[s] = v > 255 ? 255u : (uint32_t)v;
@@ -1392,6 +1614,10 @@ hipError_t launch_scan(const KArgs& a, hipStream_t s) {
 }
 hipError_t launch_eval_trace(const KArgs& a, uint32_t n_wg, hipStream_t s) {
   hipLaunchKernelGGL(eval_trace_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_eval_trace_lanes(const KArgs& a, uint32_t n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(eval_trace_lanes_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, hipStream_t s) {

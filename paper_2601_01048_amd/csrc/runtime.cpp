@@ -315,7 +315,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
       n_counts += h->n_sites;
       if ((h->cls & CKC_CLS_UNIFORM) && !O.force_generic) {
         d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
-        trace_bytes += sizeof(dtrace_head) + (uint64_t)h->trace_cap * sizeof(dtrace_entry);
+        trace_bytes += ckc::trace_bytes(h->trace_cap);
       }
       hin.push_back(d);
       for (uint32_t s = 0; s < MAX_SCALARS; s++)
@@ -372,6 +372,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   if (e == hipSuccess) e = launch_scan(a, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
   if (e == hipSuccess) e = launch_eval_trace(a, wg_trace, J.stream);
+  if (e == hipSuccess) e = launch_eval_trace_lanes(a, wg_gen, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
   if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
