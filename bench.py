@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rep", action="store_true", help="skip the representative-thread line")
     ap.add_argument("--cpu-sample", type=int, default=16, help="inputs in the oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -67,6 +69,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = W.config2(mode=W.MODE_FULL)
     n = wl.n_inputs
     with ckc.Context(0) as ctx:
@@ -112,6 +120,17 @@ def main():
                           "interpreter": float(kern[:, 2].mean()), "finish": float(kern[:, 3].mean())},
         }
         achieved = OPS_PER_ACCESS * accesses / (eval_ms * 1e-3)
+        # HBM bytes per launch from the committed counter runs, valid only for
+        # the kernel source they were taken on
+        traffic = None
+        try:
+            import hashlib
+            rec_t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["eval_trace_kernel"]
+            src = open(os.path.join(ROOT, "paper_2601_01048_amd", "csrc", "kernels.hip"), "rb").read()
+            if hashlib.sha256(src).hexdigest()[:16] == rec_t["kernels_hip_sha256_16"]:
+                traffic = rec_t["traffic_bytes"]
+        except (OSError, KeyError, ValueError):
+            traffic = None
         result["roofline"] = {
             "bound": "alu",
             "kernel": "eval_trace_kernel",
@@ -119,7 +138,7 @@ def main():
             "peak": PEAK_INT_OPS / 1e12,
             "unit": "Tops/s (int32)",
             "frac": achieved / PEAK_INT_OPS,
-            "traffic": None,
+            "traffic": traffic,
         }
         if not args.no_rep:
             run_steps(ctx, dw, out, W.MODE_BOUNDARY, 1)
