@@ -46,7 +46,63 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16, help="inputs in the oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d"],
+                    help="stencil: the benchmark batch; csr / affine1d: the other plain configurations")
     return ap.parse_args()
+
+
+HBM_PEAK = 8.0e12  # bytes/s
+
+
+def bench_other(args):
+    """The CSR gather (64 inputs, 2^20 rows) or the 1-D affine batch (256
+    inputs): same step definition, one JSON line."""
+    import torch
+    if args.workload == "csr":
+        wl = W.config3()
+        desc_w = "CSR SpMV gather, 64 inputs, 2^20 rows, power-law rows (mean 16 nnz), 0.1% corrupted col_idx"
+    else:
+        wl = W.config1()
+        desc_w = "1-D affine kernel, 256 inputs, 32-80 blocks of 256, 4 accesses per thread"
+    n = wl.n_inputs
+    with ckc.Context(0) as ctx:
+        dw = ckc.DeviceWorkload(ctx, wl)
+        n_acc = dw.info["n_accesses"]
+        out = dict(recs=torch.empty(n * n_acc * 32, dtype=torch.uint8, device="cuda"),
+                   maps=torch.empty(n * 65536, dtype=torch.uint8, device="cuda"),
+                   st=torch.empty(n * 40, dtype=torch.uint8, device="cuda"))
+        run_steps(ctx, dw, out, W.MODE_FULL, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tim = run_steps(ctx, dw, out, W.MODE_FULL, args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
+        dw.close()
+    accesses = int(st["accesses_checked"].sum())
+    step_s = (t1 - t0) / args.steps
+    kern = np.array(tim)
+    res = {"metric": "checked thread-accesses/sec", "value": accesses / step_s, "unit": "accesses/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic", "config": {"workload": desc_w, "inputs": n, "accesses_per_batch": accesses},
+           "inputs_per_s": n / step_s,
+           "kernel_ms": {"plan": float(kern[:, 0].mean()), "eval_trace": float(kern[:, 1].mean()),
+                         "interpreter": float(kern[:, 2].mean()), "finish": float(kern[:, 3].mean())}}
+    if args.workload == "csr":
+        nnz, nrows = wl.meta["nnz"], wl.meta["nrows"]
+        alg = n * 4 * (nnz + nrows + 1)  # col_idx per input + row_ptr per input
+        ms = float(kern[:, 2].mean())
+        res["roofline"] = {"bound": "hbm", "kernel": "eval_generic_kernel", "achieved": alg / (ms * 1e-3) / 1e9,
+                           "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": alg / (ms * 1e-3) / HBM_PEAK,
+                           "traffic": None}
+    else:
+        ms = float(kern[:, 1].mean())
+        ach = OPS_PER_ACCESS * accesses / (ms * 1e-3)
+        res["roofline"] = {"bound": "alu", "kernel": "eval_trace_kernel", "achieved": ach / 1e12,
+                           "peak": PEAK_INT_OPS / 1e12, "unit": "Tops/s (int32)", "frac": ach / PEAK_INT_OPS,
+                           "traffic": None}
+    print(json.dumps(res))
 
 
 def run_steps(ctx, dw, out, mode, steps):
@@ -69,6 +125,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.workload != "stencil":
+        bench_other(args)
+        return
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

@@ -31,8 +31,8 @@ hipError_t launch_plan(const KArgs& a, hipStream_t s);
 hipError_t launch_scan(const KArgs& a, hipStream_t s);
 hipError_t launch_eval_trace(const KArgs& a, uint32_t n_wg, hipStream_t s);
 hipError_t launch_eval_trace_lanes(const KArgs& a, uint32_t n_wg, hipStream_t s);
-hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, hipStream_t s);
-hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s);
+hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, uint32_t n_regs, hipStream_t s);
+hipError_t launch_fixup(const KArgs& a, uint64_t n_records, uint32_t n_regs, hipStream_t s);
 hipError_t launch_finish(const KArgs& a, hipStream_t s);
 
 }  // namespace ckc

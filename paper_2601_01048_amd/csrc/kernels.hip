@@ -1115,9 +1115,24 @@ __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
 // ---------------------------------------------------------------------------
 // generic interpreter
 // ---------------------------------------------------------------------------
+// The register file lives in LDS (dynamic shared memory): register r of lane t
+// is R[r * TILE + t], 64 bits, so operands are addressed by wavefront-uniform
+// register numbers without any per-lane indexing.  The lowered bytecode and
+// its constants are read through the scalar cache (constant address space):
+// every instruction field arrives in scalar registers.
+typedef const __attribute__((address_space(4))) dins c_dins;
+typedef const __attribute__((address_space(4))) daccess c_daccess;
+
+// One 16-byte instruction through four scalar loads.
+__device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
+  c_u32* p = (c_u32*)(I + pc);
+  const uint32_t w[4] = {p[0], p[1], p[2], p[3]};
+  dins d;
+  __builtin_memcpy(&d, w, sizeof d);
+  return d;
+}
+
 struct GenLds {
-  dins ins[MAX_DINSTR];
-  int64_t consts[MAX_DCONST];
   ckc_alloc tab[MAX_SLOTS];
   uint32_t sites[MAX_SITES_LDS];
   // expanded loop: one entry per lane of the workgroup
@@ -1127,8 +1142,6 @@ struct GenLds {
   unsigned long long wsum[TILE / 64];
   unsigned long long acc_checked, hangs, faults;
   uint64_t tile;
-  uint32_t input;
-  uint32_t n_instr;
 };
 
 enum { M_MAIN = 0, M_FIX = 1 };
@@ -1146,6 +1159,9 @@ struct Lane {
 
 struct Ctx {
   const dinput* in;
+  c_dprog* P;
+  c_dins* I;
+  c_i64* K;
   const int64_t* sc;
   ckc_record* rec;
   uint32_t* gcnt;          // global site counters (sites beyond the LDS range)
@@ -1171,54 +1187,49 @@ __device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint32_t s, 
   }
 }
 
-// Runs instructions [pc, pc_end) for the wavefront.  MODE M_MAIN checks,
-// counts and records; M_FIX replays one thread (lane 0) towards the target
-// access and stops there.  EXPAND allows the workgroup-wide expanded loop.
+// Register file: two uint32_t[NREG] arrays per lane, indexed only by
+// wavefront-uniform register numbers (VGPR indexing, no scratch).  Reads happen
+// before the opcode switch and the single result write after it, so the arrays
+// never flow through the switch's control-flow joins.
+#define RGET(i) (((uint64_t)hi[(i)] << 32) | lo[(i)])
+#define RPUT(i, v)                  \
+  do {                              \
+    const uint64_t _v = (v);        \
+    lo[(i)] = (uint32_t)_v;         \
+    hi[(i)] = (uint32_t)(_v >> 32); \
+  } while (0)
+
+// Runs the program for the wavefront.  MODE M_MAIN checks, counts and records;
+// M_FIX replays one thread (lane 0) towards the target access and stops there.
 template <int MODE>
-__device__ void run_program(GenLds& S, Ctx& C, Lane& ln, uint32_t* lo, uint32_t* hi, uint32_t n_instr) {
+__device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
+  uint32_t lo[NREG], hi[NREG];
+#pragma unroll
+  for (int q = 0; q < NREG; q++) { lo[q] = 0; hi[q] = 0; }
   // state of the expanded loop (one lane per iteration across the workgroup)
   bool in_x = false;
   uint64_t x_base = 0, x_total = 0;
   uint32_t x_lpc = 0, x_own_dis = 0, x_hang = 0, x_act = 0, x_nlive = 0;
   uint64_t x_own_gtid = 0;
-  const dprog* P = (const dprog*)C.in->prog;
+  c_dprog* P = C.P;
+  c_dins* I = C.I;
+  const uint32_t n_instr = P->n_instr;
   uint32_t pc = 0;
-  // Prepares chunk x_base of the expanded loop at LOOP pc `lpc`: every lane takes
-  // one iteration of some thread of the workgroup ("owner" o).
-  auto x_chunk = [&](uint32_t lpc) {
-    const dins L = S.ins[lpc];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t g = x_base + tid;
-    const bool ga = g < x_total;
-    uint32_t o = 0;
-    if (ga) {  // last o with pref[o] <= g
-      uint32_t l2 = 0, h2 = TILE - 1;
-      while (l2 < h2) {
-        uint32_t m = (l2 + h2 + 1) >> 1;
-        if (S.x_pref[m] <= g) l2 = m; else h2 = m - 1;
-      }
-      o = l2;
-    }
-    const uint64_t kk = ga ? g - S.x_pref[o] : 0;
-    for (uint32_t q = 0; q < x_nlive; q++) RSET(P->livein[q], S.x_live[q][o]);
-    RSET(ufirst(L.dst), narrow(S.x_start[o] + kk * S.x_step[o], ufirst(L.w)));
-    ln.dis = ga ? 0u : 1u;
-    ln.gtid = S.x_gtid[o];
-    ln.k0 = kk;
-    ln.k1 = 0;
-    count_site(S, C, ufirst(L.s0), __ballot(ga));
-  };
   while (pc < n_instr) {
-    const dins D = S.ins[pc];
-    const uint32_t op = ufirst(D.op);
-    const uint32_t w = ufirst(D.w);
+    const dins D = ld_ins(I, pc);
+    const uint32_t op = D.op, w = D.w;
     const uint32_t da = ufirst(D.a), db = ufirst(D.b), dc = ufirst(D.c), dd = ufirst(D.dst);
+    const uint64_t va = RGET(da), vb = RGET(db), vc = RGET(dc);
     const bool act = ln.dis == 0;
+    uint64_t r = 0;
+    uint32_t wreg = 0xFFu;   // register written after the switch
+    uint32_t chunk = 0;      // 1: set up a chunk of the expanded loop; 2: leave it
+    uint32_t npc = pc + 1;
     switch (op) {
-      case CKC_OP_CONST: RSET(dd, narrow((uint64_t)S.consts[ufirst(D.x)], w)); break;
-      case CKC_OP_SCALAR: RSET(dd, narrow((uint64_t)C.sc[ufirst(D.x)], w)); break;
+      case CKC_OP_CONST: r = narrow((uint64_t)C.K[D.x], w); wreg = dd; break;
+      case CKC_OP_SCALAR: r = narrow((uint64_t)C.sc[D.x], w); wreg = dd; break;
       case CKC_OP_SPECIAL: {
-        const uint32_t x = ufirst(D.x);
+        const uint32_t x = D.x;
         uint32_t v;
         switch (x) {
           case 0: v = C.t0; break;
@@ -1229,24 +1240,25 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln, uint32_t* lo, uint32_t*
           case 5: v = C.b2; break;
           default: v = x < 9 ? C.in->launch[3 + x - 6] : C.in->launch[x - 9]; break;
         }
-        RSET(dd, (uint64_t)v);
+        r = v;
+        wreg = dd;
         break;
       }
-      case CKC_OP_SELECT: RSET(dd, narrow(rget(lo, hi, da) != 0 ? rget(lo, hi, db) : rget(lo, hi, dc), w)); break;
-      case CKC_OP_SEXT: case CKC_OP_TRUNC: RSET(dd, narrow(rget(lo, hi, da), 32)); break;
-      case CKC_OP_ZEXT: RSET(dd, rget(lo, hi, da) & 0xFFFFFFFFull); break;
+      case CKC_OP_SELECT: r = narrow(va != 0 ? vb : vc, w); wreg = dd; break;
+      case CKC_OP_SEXT: case CKC_OP_TRUNC: r = narrow(va, 32); wreg = dd; break;
+      case CKC_OP_ZEXT: r = va & 0xFFFFFFFFull; wreg = dd; break;
       case CKC_OP_ACCESS:
       case CKC_OP_LOAD: {
-        const uint32_t slot = ufirst(D.slot), lg = ufirst(D.fl) & 3u, acc = ufirst(D.x);
-        const int64_t idx = (int64_t)narrow(rget(lo, hi, da), w);
+        const uint32_t slot = D.slot, lg = D.fl & 3u, acc = D.x;
+        const int64_t idx = (int64_t)narrow(va, w);
         const ckc_alloc& A = S.tab[slot];
-        uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
+        const uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
         if (MODE == M_MAIN) {
-          uint64_t am = __ballot(act);
+          const uint64_t am = __ballot(act);
           if (lane_id() == 0 && am) atomicAdd(&S.acc_checked, (unsigned long long)__popcll(am));
-          count_site(S, C, ufirst(D.s0), am);
+          count_site(S, C, D.s0, am);
           if (__ballot(kd != 0)) {
-            uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2) | ln.k1;
+            const uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2) | ln.k1;
             merge_violation(C.rec + acc, kd, key);
           }
         } else if (acc == C.tacc) {
@@ -1255,67 +1267,56 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln, uint32_t* lo, uint32_t*
         }
         if (op == CKC_OP_LOAD) {
           uint64_t v = 0;
-          if (act && kd == 0) {
-            v = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx]
-                        : (uint64_t)((const int64_t*)A.data)[idx];
-          }
-          RSET(dd, v);
+          if (act && kd == 0)
+            v = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
+          r = v;
+          wreg = dd;
         }
         break;
       }
       case CKC_OP_IF: {
-        const bool p = rget(lo, hi, da) != 0;
-        const uint32_t fl = ufirst(D.fl);
+        const bool p = va != 0;
         if (MODE == M_MAIN) {
-          count_site(S, C, ufirst(D.s0), __ballot(act && p));
-          count_site(S, C, ufirst(D.s1), __ballot(act && !p));
+          count_site(S, C, D.s0, __ballot(act && p));
+          count_site(S, C, D.s1, __ballot(act && !p));
         }
         ln.dis = act ? (p ? 0u : 1u) : ln.dis + 1;
-        if (!(fl & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) {
-          pc = ufirst(D.jmp);  // ELSE or ENDIF: handled there
-          continue;
-        }
+        if (!(D.fl & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) npc = D.jmp;  // ELSE / ENDIF handle it
         break;
       }
-      case CKC_OP_ELSE: {
+      case CKC_OP_ELSE:
         ln.dis = ln.dis == 1 ? 0u : (ln.dis == 0 ? 1u : ln.dis);
-        if (!(ufirst(D.fl) & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) {
-          pc = ufirst(D.jmp);
-          continue;
-        }
+        if (!(D.fl & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) npc = D.jmp;
         break;
-      }
       case CKC_OP_ENDIF: ln.dis = ln.dis > 0 ? ln.dis - 1 : 0u; break;
       case CKC_OP_LOOP: {
-        const uint32_t d = ufirst(D.x), fl = ufirst(D.fl);
-        const uint32_t endpc = ufirst(D.jmp);
-        const int64_t s = (int64_t)narrow(rget(lo, hi, da), w);
-        const int64_t e = (int64_t)narrow(rget(lo, hi, db), w);
-        const int64_t stp = (int64_t)narrow(rget(lo, hi, dc), w);
+        const uint32_t d = D.x, fl = D.fl, endpc = D.jmp;
+        const int64_t s0 = (int64_t)narrow(va, w), e0 = (int64_t)narrow(vb, w), stp = (int64_t)narrow(vc, w);
         if (MODE == M_FIX) {
           const int32_t me = (int32_t)pc;
-          if (me != C.tloop0 && me != C.tloop1) { pc = endpc + 1; continue; }
+          if (me != C.tloop0 && me != C.tloop1) { npc = endpc + 1; break; }
           const uint64_t kk = me == C.tloop0 ? C.tk0 : C.tk1;
-          RSET(dd, narrow((uint64_t)s + kk * (uint64_t)stp, w));
+          r = narrow((uint64_t)s0 + kk * (uint64_t)stp, w);
+          wreg = dd;
           if (d == 0) ln.k0 = kk; else ln.k1 = kk;
           break;  // into the body for exactly the target iteration
         }
-        const uint64_t nt = act ? trip_count(s, e, stp) : 0;
+        const uint64_t nt = act ? trip_count(s0, e0, stp) : 0;
         const uint64_t cap = d == 0 ? C.cap0 : C.cap1;
         const uint64_t rn = nt < cap ? nt : cap;
         const bool hg = act && nt > cap;
         if (fl & DI_EXPAND) {
           // every wavefront of the workgroup arrives here exactly once per tile
           const uint32_t tid = threadIdx.x;
-          x_nlive = ufirst(P->n_livein);
-          S.x_start[tid] = (uint64_t)s;
+          x_nlive = P->n_livein;
+          S.x_start[tid] = (uint64_t)s0;
           S.x_step[tid] = (uint64_t)stp;
           S.x_gtid[tid] = ln.gtid;
-          for (uint32_t q = 0; q < x_nlive; q++) S.x_live[q][tid] = rget(lo, hi, P->livein[q]);
+          for (uint32_t q = 0; q < x_nlive; q++) S.x_live[q][tid] = RGET(ufirst(P->livein[q]));
           const uint64_t v = act ? rn : 0;
           uint64_t incl = v;
           for (int o = 1; o < 64; o <<= 1) {
-            uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
+            const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
             if ((int)lane_id() >= o) incl += u;
           }
           if (lane_id() == 63) S.wsum[tid / 64] = incl;
@@ -1332,69 +1333,49 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln, uint32_t* lo, uint32_t*
           x_own_gtid = ln.gtid;
           x_hang = hg;
           x_act = act;
-          if (x_total == 0) {
-            pc = endpc;  // ENDLOOP finishes the expansion
-            in_x = true;
-            continue;
-          }
           in_x = true;
-          x_chunk(pc);
-          break;  // body follows
+          if (x_total == 0) { chunk = 2; break; }  // nothing to run: leave at once
+          chunk = 1;
+          break;
         }
-        if (d == 0) { ln.run0 = rn; ln.st0 = (uint64_t)s; ln.sp0 = (uint64_t)stp; ln.k0 = 0; }
-        else { ln.run1 = rn; ln.st1 = (uint64_t)s; ln.sp1 = (uint64_t)stp; ln.k1 = 0; }
+        if (d == 0) { ln.run0 = rn; ln.st0 = (uint64_t)s0; ln.sp0 = (uint64_t)stp; ln.k0 = 0; }
+        else { ln.run1 = rn; ln.st1 = (uint64_t)s0; ln.sp1 = (uint64_t)stp; ln.k1 = 0; }
         ln.hangp = (ln.hangp & ~(1u << d)) | (hg ? (1u << d) : 0u);
         ln.dis = act ? (rn > 0 ? 0u : 1u) : ln.dis + 1;
-        if (__ballot(ln.dis == 0) == 0) {
-          pc = endpc;  // ENDLOOP: exit handling
-          continue;
-        }
-        RSET(dd, narrow((uint64_t)s, w));
-        if (MODE == M_MAIN) count_site(S, C, ufirst(D.s0), __ballot(ln.dis == 0));
+        if (__ballot(ln.dis == 0) == 0) { npc = endpc; break; }  // ENDLOOP: exit handling
+        r = narrow((uint64_t)s0, w);
+        wreg = dd;
+        if (MODE == M_MAIN) count_site(S, C, D.s0, __ballot(ln.dis == 0));
         break;
       }
       case CKC_OP_ENDLOOP: {
         if (MODE == M_FIX) return;  // target not reached in this iteration
-        const uint32_t d = ufirst(D.x);
-        const uint32_t lpc = ufirst(D.jmp);
+        const uint32_t d = D.x, lpc = D.jmp;
         if (in_x && lpc == x_lpc) {
           x_base += TILE;
-          if (x_base < x_total) {
-            x_chunk(lpc);
-            pc = lpc + 1;
-            continue;
-          }
-          // expansion done: back to this lane's own thread
-          in_x = false;
-          for (uint32_t q = 0; q < x_nlive; q++) RSET(P->livein[q], S.x_live[q][threadIdx.x]);
-          ln.gtid = x_own_gtid;
-          ln.k0 = 0;
-          ln.k1 = 0;
-          ln.dis = x_own_dis;
-          if (x_hang) { ln.dis = DEAD; ln.hangs++; }
-          count_site(S, C, ufirst(S.ins[lpc].s1), __ballot(x_act && !x_hang));
-          __syncthreads();
+          chunk = x_base < x_total ? 1u : 2u;
           break;
         }
-        const dins Lp = S.ins[lpc];
-        const uint32_t lw = ufirst(Lp.w), ldst = ufirst(Lp.dst);
+        const dins Lp = ld_ins(I, lpc);
         if (ln.dis == 0) {
-          uint64_t kk = (d == 0 ? ln.k0 : ln.k1) + 1;
+          const uint64_t kk = (d == 0 ? ln.k0 : ln.k1) + 1;
           if (d == 0) ln.k0 = kk; else ln.k1 = kk;
           if (kk == (d == 0 ? ln.run0 : ln.run1)) ln.dis = 1;  // done at this level
         }
         if (__ballot(ln.dis == 0)) {
           const uint64_t kk = d == 0 ? ln.k0 : ln.k1;
-          const uint64_t s0 = d == 0 ? ln.st0 : ln.st1, sp = d == 0 ? ln.sp0 : ln.sp1;
-          if (ln.dis == 0) RSET(ldst, narrow(s0 + kk * sp, lw));
-          if (MODE == M_MAIN) count_site(S, C, ufirst(Lp.s0), __ballot(ln.dis == 0));
-          pc = lpc + 1;
-          continue;
+          const uint64_t sa = d == 0 ? ln.st0 : ln.st1, sp = d == 0 ? ln.sp0 : ln.sp1;
+          wreg = ufirst(Lp.dst);
+          // lanes that left the loop keep their value
+          r = ln.dis == 0 ? narrow(sa + kk * sp, Lp.w) : RGET(wreg);
+          if (MODE == M_MAIN) count_site(S, C, Lp.s0, __ballot(ln.dis == 0));
+          npc = lpc + 1;
+          break;
         }
         // exit: lanes that ran this loop leave it; a capped loop stops its lane
         const bool mine = ln.dis == 1;
         const bool hg = mine && ((ln.hangp >> d) & 1u);
-        if (MODE == M_MAIN) count_site(S, C, ufirst(Lp.s1), __ballot(mine && !hg));
+        if (MODE == M_MAIN) count_site(S, C, Lp.s1, __ballot(mine && !hg));
         if (mine) {
           if (hg) { ln.dis = DEAD; ln.hangs++; }
           else ln.dis = 0;
@@ -1406,21 +1387,60 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln, uint32_t* lo, uint32_t*
       }
       default: {
         uint32_t f = 0;
-        uint64_t r = alu(op, w, rget(lo, hi, da), rget(lo, hi, db), f);
+        r = alu(op, w, va, vb, f);
         if (act) ln.faults += f;
-        RSET(dd, r);
+        wreg = dd;
         break;
       }
     }
-    pc++;
+    if (wreg != 0xFFu) RPUT(wreg, r);
+    if (MODE == M_MAIN && chunk == 1) {
+      // next chunk of the expanded loop: every lane takes one iteration of some
+      // thread of the workgroup (owner o, last o with pref[o] <= g)
+      const dins L = ld_ins(I, x_lpc);
+      const uint32_t tid = threadIdx.x;
+      const uint64_t g = x_base + tid;
+      const bool ga = g < x_total;
+      uint32_t o = 0;
+      if (ga) {
+        uint32_t l2 = 0, h2 = TILE - 1;
+        while (l2 < h2) {
+          const uint32_t m = (l2 + h2 + 1) >> 1;
+          if (S.x_pref[m] <= g) l2 = m; else h2 = m - 1;
+        }
+        o = l2;
+      }
+      const uint64_t kk = ga ? g - S.x_pref[o] : 0;
+      for (uint32_t q = 0; q < x_nlive; q++) RPUT(ufirst(P->livein[q]), S.x_live[q][o]);
+      RPUT(ufirst(L.dst), narrow(S.x_start[o] + kk * S.x_step[o], L.w));
+      ln.dis = ga ? 0u : 1u;
+      ln.gtid = S.x_gtid[o];
+      ln.k0 = kk;
+      ln.k1 = 0;
+      count_site(S, C, L.s0, __ballot(ga));
+      npc = x_lpc + 1;
+    } else if (MODE == M_MAIN && chunk == 2) {
+      // expansion done: back to this lane's own thread
+      in_x = false;
+      for (uint32_t q = 0; q < x_nlive; q++) RPUT(ufirst(P->livein[q]), S.x_live[q][threadIdx.x]);
+      ln.gtid = x_own_gtid;
+      ln.k0 = 0;
+      ln.k1 = 0;
+      ln.dis = x_own_dis;
+      if (x_hang) { ln.dis = DEAD; ln.hangs++; }
+      count_site(S, C, ld_ins(I, x_lpc).s1, __ballot(x_act && !x_hang));
+      __syncthreads();
+      npc = ld_ins(I, x_lpc).jmp + 1;
+    }
+    pc = npc;
   }
 }
 
-__device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, const dprog* P) {
+__device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, uint32_t n_sites) {
   __syncthreads();
   const dinput& in = a.inputs[input];
   uint32_t* cnt = a.counts + in.cnt_base;
-  uint32_t ns = P->n_sites < (uint32_t)MAX_SITES_LDS ? P->n_sites : (uint32_t)MAX_SITES_LDS;
+  const uint32_t ns = n_sites < (uint32_t)MAX_SITES_LDS ? n_sites : (uint32_t)MAX_SITES_LDS;
   for (uint32_t s = threadIdx.x; s < ns; s += TILE) {
     uint32_t c = S.sites[s];
     if (c) {
@@ -1438,6 +1458,30 @@ __device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, const dpr
   __syncthreads();
 }
 
+__device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, const dinput& in, uint32_t i, const Thr& T) {
+  C.in = &in;
+  C.P = (c_dprog*)in.prog;
+  C.I = (c_dins*)((const uint8_t*)in.prog + C.P->off_instr);
+  C.K = (c_i64*)((const uint8_t*)in.prog + C.P->off_consts);
+  C.sc = a.scalars + (size_t)i * MAX_SCALARS;
+  C.rec = a.recs + in.rec_base;
+  C.gcnt = a.counts + in.cnt_base;
+  C.Lsum = in.L1 + in.L2;
+  C.L2 = in.L2;
+  C.cap0 = 1ull << in.cap_log2[0];
+  C.cap1 = 1ull << in.cap_log2[1];
+  C.t0 = T.t[0]; C.t1 = T.t[1]; C.t2 = T.t[2]; C.b0 = T.b[0]; C.b1 = T.b[1]; C.b2 = T.b[2];
+}
+
+__device__ __forceinline__ void lane_init(Lane& ln, bool act, uint64_t gtid) {
+  ln.dis = act ? 0u : DEAD;
+  ln.k0 = ln.k1 = ln.run0 = ln.run1 = ln.st0 = ln.st1 = ln.sp0 = ln.sp1 = 0;
+  ln.hangp = 0;
+  ln.gtid = gtid;
+  ln.faults = 0;
+  ln.hangs = 0;
+}
+
 __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   __shared__ GenLds S;
   const uint32_t tid = threadIdx.x;
@@ -1445,8 +1489,7 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   if (total == 0) return;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
-  uint32_t cur = 0xFFFFFFFFu;
-  uint64_t cur_prog = 0;
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0;
   for (;;) {
     __syncthreads();
     if (tid == 0) S.tile = atomicAdd((unsigned long long*)&a.js->next_tile[PATH_GENERIC], 1ull);
@@ -1455,19 +1498,13 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
     if (t >= total) break;
     const uint32_t i = find_input(a.inputs, a.n_inputs, PATH_GENERIC, t);
     const dinput& in = a.inputs[i];
-    const dprog* P = (const dprog*)in.prog;
     if (i != cur) {
-      if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, (const dprog*)a.inputs[cur].prog);
-      if (in.prog != cur_prog) {
-        const dins* src = prog_ins(P);
-        for (uint32_t q = tid; q < P->n_instr; q += TILE) S.ins[q] = src[q];
-        const int64_t* k = prog_consts(P);
-        for (uint32_t q = tid; q < P->n_consts; q += TILE) S.consts[q] = k[q];
-        cur_prog = in.prog;
-      }
+      if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
       const ckc_alloc* tab = (const ckc_alloc*)in.table;
-      if (tid < P->n_slots) S.tab[tid] = tab[tid];
+      const uint32_t ns = ((c_dprog*)in.prog)->n_slots;
+      if (tid < ns) S.tab[tid] = tab[tid];
       cur = i;
+      cur_sites = ((c_dprog*)in.prog)->n_sites;
       __syncthreads();
     }
     const uint64_t l = (t - in.tile_begin[PATH_GENERIC]) * TILE + tid;
@@ -1475,33 +1512,17 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
     Thr T;
     decode_lane(in.mode, in.launch, act ? l : 0, T);
     Ctx C;
-    C.in = &in;
-    C.sc = a.scalars + (size_t)i * MAX_SCALARS;
-    C.rec = a.recs + in.rec_base;
-    C.gcnt = a.counts + in.cnt_base;
-    C.Lsum = in.L1 + in.L2;
-    C.L2 = in.L2;
-    C.cap0 = 1ull << in.cap_log2[0];
-    C.cap1 = 1ull << in.cap_log2[1];
-    C.t0 = T.t[0]; C.t1 = T.t[1]; C.t2 = T.t[2]; C.b0 = T.b[0]; C.b1 = T.b[1]; C.b2 = T.b[2];
+    ctx_init(C, a, in, i, T);
     Lane ln;
-    ln.dis = act ? 0u : DEAD;
-    ln.k0 = ln.k1 = ln.run0 = ln.run1 = ln.st0 = ln.st1 = ln.sp0 = ln.sp1 = 0;
-    ln.hangp = 0;
-    ln.gtid = T.gtid;
-    ln.faults = 0;
-    ln.hangs = 0;
-    uint32_t lo[NREG], hi[NREG];
-#pragma unroll
-    for (int r = 0; r < NREG; r++) { lo[r] = 0; hi[r] = 0; }
-    run_program<M_MAIN>(S, C, ln, lo, hi, P->n_instr);
+    lane_init(ln, act, T.gtid);
+    run_program<M_MAIN>(S, C, ln);
     uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs);
     if (lane_id() == 0) {
       if (f) atomicAdd(&S.faults, (unsigned long long)f);
       if (h) atomicAdd(&S.hangs, (unsigned long long)h);
     }
   }
-  if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, (const dprog*)a.inputs[cur].prog);
+  if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
 }
 
 // One wavefront per record: replays the thread of first_key up to the access
@@ -1521,10 +1542,6 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   const dinput& in = a.inputs[lo_i];
   const dprog* P = (const dprog*)in.prog;
   const uint32_t acc = (uint32_t)(r - in.rec_base);
-  const dins* src = prog_ins(P);
-  for (uint32_t q = threadIdx.x; q < P->n_instr; q += 64) S.ins[q] = src[q];
-  const int64_t* k = prog_consts(P);
-  for (uint32_t q = threadIdx.x; q < P->n_consts; q += 64) S.consts[q] = k[q];
   const ckc_alloc* tab = (const ckc_alloc*)in.table;
   if (threadIdx.x < P->n_slots) S.tab[threadIdx.x] = tab[threadIdx.x];
   __syncthreads();
@@ -1538,15 +1555,7 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   thr_from(in.launch, gtid / bs, (uint32_t)(gtid % bs), T);
   const daccess A = prog_access(P)[acc];
   Ctx C;
-  C.in = &in;
-  C.sc = a.scalars + (size_t)lo_i * MAX_SCALARS;
-  C.rec = a.recs + in.rec_base;
-  C.gcnt = a.counts + in.cnt_base;
-  C.Lsum = Lsum;
-  C.L2 = in.L2;
-  C.cap0 = 1ull << in.cap_log2[0];
-  C.cap1 = 1ull << in.cap_log2[1];
-  C.t0 = T.t[0]; C.t1 = T.t[1]; C.t2 = T.t[2]; C.b0 = T.b[0]; C.b1 = T.b[1]; C.b2 = T.b[2];
+  ctx_init(C, a, in, lo_i, T);
   C.tacc = acc;
   C.tk0 = i1;
   C.tk1 = i2;
@@ -1554,18 +1563,11 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   C.tloop1 = A.loop_pc[1];
   C.trec = rec;
   Lane ln;
-  ln.dis = lane_id() == 0 ? 0u : DEAD;
-  ln.k0 = ln.k1 = ln.run0 = ln.run1 = ln.st0 = ln.st1 = ln.sp0 = ln.sp1 = 0;
-  ln.hangp = 0;
-  ln.gtid = gtid;
-  ln.faults = 0;
-  ln.hangs = 0;
-  uint32_t lo[NREG], hi[NREG];
-#pragma unroll
-  for (int q = 0; q < NREG; q++) { lo[q] = 0; hi[q] = 0; }
-  run_program<M_FIX>(S, C, ln, lo, hi, P->n_instr);
+  lane_init(ln, lane_id() == 0, gtid);
+  run_program<M_FIX>(S, C, ln);
 }
 
+// ---------------------------------------------------------------------------
 // Per input: trace-path totals from per-thread counts, then the dense map.
 __global__ void __launch_bounds__(256) finish_kernel(KArgs a) {
   const uint32_t i = blockIdx.x;
@@ -1620,12 +1622,14 @@ hipError_t launch_eval_trace_lanes(const KArgs& a, uint32_t n_wg, hipStream_t s)
   hipLaunchKernelGGL(eval_trace_lanes_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, hipStream_t s) {
+hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, uint32_t n_regs, hipStream_t s) {
+  (void)n_regs;
   hipLaunchKernelGGL(eval_generic_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s) {
+hipError_t launch_fixup(const KArgs& a, uint64_t n_records, uint32_t n_regs, hipStream_t s) {
   if (n_records == 0) return hipSuccess;
+  (void)n_regs;
   hipLaunchKernelGGL(fixup_kernel, dim3((uint32_t)n_records), dim3(64), 0, s, a, n_records);
   return hipGetLastError();
 }

@@ -268,6 +268,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   std::vector<dinput> hin;
   std::vector<int64_t> hsc;
   uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
+  uint32_t max_regs = 1;  // interpreter register file rows (LDS)
   for (uint32_t k = 0; k < n_descs; k++) {
     const ckc_batch& B = descs[k];
     auto pit = c->progs.find(B.prog_id);
@@ -281,6 +282,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
     if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, "loop cap above 2^32");
     unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
+    max_regs = std::max(max_regs, h->n_regs);
     for (uint32_t i = 0; i < B.n_inputs; i++) {
       const uint32_t* L = B.launch + 6 * (size_t)i;
       uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
@@ -374,9 +376,9 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   if (e == hipSuccess) e = launch_eval_trace(a, wg_trace, J.stream);
   if (e == hipSuccess) e = launch_eval_trace_lanes(a, wg_gen, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
-  if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, J.stream);
+  if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, max_regs, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
-  if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
+  if (e == hipSuccess) e = launch_fixup(a, n_records, max_regs, J.stream);
   if (e == hipSuccess) e = launch_finish(a, J.stream);
   if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));

@@ -148,11 +148,11 @@ def program(family: str, w: int) -> bytes:
 def powerlaw_row_lengths(rng, nrows: int, ncols: int, mean: int = 16, alpha: float = 2.1):
     """Row lengths L = min(ncols, max(1, floor(s*w))) with w = (1-u)^(-1/(alpha-1))
     (a Pareto law with density exponent alpha); s is bisected to the largest
-    value with sum(L) <= mean*nrows and the remaining deficit is added one
-    nonzero at a time to the first rows that are below ncols."""
+    value with sum(L) <= mean*nrows (at most nrows*ncols) and the remaining
+    deficit is added one nonzero at a time to the first rows below ncols."""
     u = rng.random(nrows)
     w = (1.0 - u) ** (-1.0 / (alpha - 1.0))
-    target = mean * nrows
+    target = min(mean * nrows, nrows * ncols)  # a matrix smaller than mean x nrows is full
 
     def total(s):
         return int(np.minimum(ncols, np.maximum(1, np.floor(s * w))).sum())
@@ -299,3 +299,94 @@ def mini(name: str, **kw) -> Workload:
         base.update(kw)
         return config3(**base)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------------------
+# mixed batches (many small kernels of the three families)
+# ---------------------------------------------------------------------------
+@dataclass
+class MixedBatch:
+    """A list of one-input workloads checked together.  ``kernels[k]`` is a
+    Workload with one input; programs are shared by (family, width)."""
+    name: str
+    kernels: list
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_kernels(self) -> int:
+        return len(self.kernels)
+
+
+def _f1_kernel(rng, T: int, w: int) -> Workload:
+    block = min(256, T)
+    grid = -(-T // block)
+    n = int(rng.integers(-(-9 * T // 10), -(-11 * T // 10) + 1))
+    extra = I64_BASE if w == 64 else 0
+    launch = np.array([[grid, 1, 1, block, 1, 1]], np.uint32)
+    sz = (n + extra) * 4
+    tables = np.array([[alloc(sz), alloc(sz, base=LOGICAL_BASE + (1 << 36))]], ALLOC_DTYPE)
+    scalars = np.full((1, 1), extra, np.int64) if w == 64 else np.zeros((1, 0), np.int64)
+    return Workload(f"f1_i{w}", f1_program(w), launch, scalars, tables, np.zeros(1, np.uint32),
+                    [], MODE_FULL, meta=dict(family="F1", T=T, n=n))
+
+
+def _f2_kernel(rng, T: int, w: int) -> Workload:
+    side = int(np.ceil(np.sqrt(T)))
+    b = min(16, side)
+    g = -(-side // b)
+    H = side + int(rng.integers(-3, 4))
+    W = side + int(rng.integers(-3, 4))
+    H, W = max(H, 1), max(W, 1)
+    r = int(rng.integers(1, 3))
+    extra = I64_BASE if w == 64 else 0
+    launch = np.array([[g, g, 1, b, b, 1]], np.uint32)
+    sc = [W, r] + ([extra] if w == 64 else [])
+    scalars = np.array([sc], np.int64)
+    sz = (H * W + extra) * 4
+    tables = np.array([[alloc(sz), alloc(sz, base=LOGICAL_BASE + (1 << 36))]], ALLOC_DTYPE)
+    return Workload(f"f2_i{w}", f2_program(w), launch, scalars, tables, np.zeros(1, np.uint32),
+                    [], MODE_FULL, meta=dict(family="F2", T=T, H=H, W=W, r=r))
+
+
+def _f3_kernel(seed: int, T: int, w: int, frac: float = 0.001, block: int = 256) -> Workload:
+    nrows = ncols = T
+    rng, row_ptr, col = csr_structure(seed, nrows, ncols, 16)
+    nnz = int(row_ptr[-1])
+    col = corrupt_copy(rng, col, ncols, frac)
+    bs = min(block, nrows)
+    extra = I64_BASE if w == 64 else 0
+    launch = np.array([[-(-nrows // bs), 1, 1, bs, 1, 1]], np.uint32)
+    scalars = np.array([[nrows] + ([extra] if w == 64 else [])], np.int64)
+    tables = np.array([[alloc((nrows + 1) * 4, 1, LOGICAL_BASE),
+                        alloc(nnz * 4, 2, LOGICAL_BASE + (1 << 36)),
+                        alloc((nnz + extra) * 4, 0, LOGICAL_BASE + (2 << 36)),
+                        alloc((ncols + extra) * 4, 0, LOGICAL_BASE + (3 << 36)),
+                        alloc((nrows + extra) * 4, 0, LOGICAL_BASE + (4 << 36))]], ALLOC_DTYPE)
+    return Workload(f"f3_i{w}", f3_program(w), launch, scalars, tables, np.zeros(1, np.uint32),
+                    [row_ptr, col], MODE_FULL, meta=dict(family="F3", T=T, nnz=nnz))
+
+
+def config4(seed: int = 1004, n_kernels: int = 10000, t_max: int = 65536) -> MixedBatch:
+    """Batched mix: family ~ U{F1, F2, F3}, width ~ U{32, 64}, total threads
+    T = floor(exp(U[0, ln t_max])) per kernel.  F1: block min(256, T), grid
+    ceil(T/block), n ~ U{ceil(0.9T)..ceil(1.1T)} elements.  F2: side ceil(sqrt T),
+    block min(16, side)^2, grid ceil(side/b)^2, H, W = side + U{-3..3}, r ~ U{1, 2}.
+    F3: nrows = ncols = T, power-law rows of mean 16 capped at T, 0.1% of col_idx
+    corrupted.  Width-64 kernels add the base offset 2^32 to their indices."""
+    rng = np.random.default_rng(seed)
+    fam = rng.integers(0, 3, size=n_kernels)
+    wid = np.where(rng.integers(0, 2, size=n_kernels) == 1, 64, 32)
+    T = np.floor(np.exp(rng.uniform(0.0, np.log(t_max), size=n_kernels))).astype(np.int64)
+    T = np.maximum(T, 1)
+    seeds = rng.integers(0, 2**62, size=n_kernels)
+    ks = []
+    for k in range(n_kernels):
+        sub = np.random.default_rng(int(seeds[k]))
+        t, w = int(T[k]), int(wid[k])
+        if fam[k] == 0:
+            ks.append(_f1_kernel(sub, t, w))
+        elif fam[k] == 1:
+            ks.append(_f2_kernel(sub, t, w))
+        else:
+            ks.append(_f3_kernel(int(seeds[k]), t, w))
+    return MixedBatch("config4_mixed", ks, meta=dict(seed=seed, T=T, family=fam, width=wid))
