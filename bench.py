@@ -46,8 +46,13 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16, help="inputs in the oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d"],
-                    help="stencil: the benchmark batch; csr / affine1d: the other plain configurations")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched sub-result")
+    ap.add_argument("--no-served", action="store_true", help="skip the served sub-result")
+    ap.add_argument("--served-seconds", type=float, default=35.0,
+                    help="length of the served stream (the first 5 s are warm-up)")
+    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d", "batched", "served"],
+                    help="stencil: the benchmark batch; csr / affine1d: the other plain configurations; "
+                         "batched: 10,000 mixed kernels in one job vs one job per kernel")
     return ap.parse_args()
 
 
@@ -105,6 +110,117 @@ def bench_other(args):
     print(json.dumps(res))
 
 
+def bench_batched(args):
+    """10,000 mixed kernels (F1/F2/F3, int32/int64, 1..65536 threads each) in
+    one job with autotuned launch options and one graph, against one job
+    (seven kernel launches) per kernel."""
+    import torch
+    t_gen = time.perf_counter()
+    mb = W.config4()
+    t_gen = time.perf_counter() - t_gen
+    with ckc.Context(0) as ctx:
+        db = ckc.DeviceBatch(ctx, mb)
+        descs = db.descs()
+        prep = ckc.Context.prepare(descs)
+        n_rec = sum(db.n_accesses(i) for i in range(mb.n_kernels))
+        n = mb.n_kernels
+        out = dict(recs=torch.empty(n_rec * 32, dtype=torch.uint8, device="cuda"),
+                   maps=torch.empty(n * 65536, dtype=torch.uint8, device="cuda"),
+                   st=torch.empty(n * 40, dtype=torch.uint8, device="cuda"))
+        t_tune = time.perf_counter()
+        best, log = ctx.autotune(prep, reps=1)
+        t_tune = time.perf_counter() - t_tune
+        best.use_graph = 1
+        # per-kernel split of the tuned options (events need the non-graph form)
+        split_opts = ckc.launch_opts(best.schedule, best.chunk, best.wg_per_cu)
+        job = ctx.check(prep, opts=split_opts)
+        split = ctx.timing(job)
+        ctx.release(job)
+
+        def step():
+            j = ctx.check(prep, opts=best)
+            ctx.read_device(j, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr())
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
+        accesses = int(st["accesses_checked"].sum())
+        step_s = (t1 - t0) / args.steps
+        # one job per kernel: all queued, then each read back into the same buffers
+        singles = [ckc.Context.prepare([d]) for d in descs]
+        rec_off = np.concatenate([[0], np.cumsum([db.n_accesses(i) for i in range(n)])])
+        for rep in range(2):  # the first pass fills the buffer pool
+            torch.cuda.synchronize()
+            p0 = time.perf_counter()
+            jobs = [ctx.check(sp) for sp in singles]
+            for i, j in enumerate(jobs):
+                ctx.read_device(j, out["recs"].data_ptr() + 32 * int(rec_off[i]),
+                                out["maps"].data_ptr() + 65536 * i, out["st"].data_ptr() + 40 * i)
+            torch.cuda.synchronize()
+            p1 = time.perf_counter()
+        st2 = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
+        assert int(st2["accesses_checked"].sum()) == accesses
+        db.close()
+    per_kernel_s = p1 - p0
+    fam = mb.meta["family"]
+    res = {"metric": "checked thread-accesses/sec", "value": accesses / step_s, "unit": "accesses/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32+int64",
+           "data": "synthetic",
+           "config": {"workload": "batched: 10,000 mixed kernels (F1 1-D affine, F2 stencil, F3 CSR; int32 and "
+                                  "int64), threads per kernel log-uniform in [1, 65536], one job, one graph",
+                      "kernels": n, "threads": int(st["lanes"].sum()), "accesses_per_batch": accesses,
+                      "family_counts": [int((fam == f).sum()) for f in range(3)], "seed": 1004},
+           "kernels_per_s": n / step_s,
+           "per_kernel_launches": {"ms_total": per_kernel_s * 1e3, "kernels_per_s": n / per_kernel_s,
+                                   "accesses_per_s": accesses / per_kernel_s,
+                                   "launches": 7 * n},
+           "speedup_vs_per_kernel": per_kernel_s / step_s,
+           "autotune": {"best": best.as_dict(), "candidates": len(log), "seconds": t_tune,
+                        "best_ms": min(ms for _, ms in log), "worst_ms": max(ms for _, ms in log),
+                        "default_ms": [ms for d, ms in log
+                                       if d["schedule"] == "blocked" and d["wg_per_cu"] == 0][0]},
+           "kernel_ms_tuned_no_graph": {"plan": split[0], "eval_trace": split[1], "interpreter": split[2],
+                                        "finish": split[3]},
+           "generator_s": t_gen}
+    return res
+
+
+def bench_served(args):
+    """Poisson stream of check jobs (2000/s, 1e3..1e7 thread-accesses each,
+    F1/F2/F3 mix, int32/int64) replayed open-loop through the library's
+    request loop (4 streams, continuous batching, 64 GB admission cap)."""
+    from paper_2601_01048_amd import serve
+    warm = 5.0
+    ss = W.config5(duration_s=args.served_seconds)
+    with ckc.Context(0) as ctx:
+        t0 = time.perf_counter()
+        ds = ckc.DeviceStream(ctx, ss)
+        t_setup = time.perf_counter() - t0
+        with ckc.Server(ctx, n_streams=4) as srv:
+            res, lag = serve.replay(srv, ds)
+            st = srv.stats()
+        ds.close()
+    summ = serve.summarize(res, t_from_s=min(warm, args.served_seconds / 2), arrivals=ss.arrivals)
+    offered = float(ss.meta["A"].mean() * ss.meta["rate"])
+    return {"metric": "checked thread-accesses/sec (served) and p50/p99 job latency",
+            "value": summ["accesses_per_s"], "unit": "accesses/s",
+            "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
+            "max_ms": summ["max_ms"], "jobs_per_s": summ["jobs_per_s"],
+            "config": {"workload": "served: Poisson 2000 jobs/s, sizes log-uniform in [1e3, 1e7] thread-accesses, "
+                                   "F1/F2/F3 x int32/int64, resident CSR pool 2^4..2^18 rows, dense maps, "
+                                   "4 streams, 64 GB admission cap",
+                       "jobs": ss.n_jobs, "seconds": args.served_seconds, "warmup_s": warm, "seed": 1005},
+            "offered_accesses_per_s": offered, "window": summ, "server": st, "submit_lag": lag,
+            "setup_s": t_setup}
+
+
 def run_steps(ctx, dw, out, mode, steps):
     """Runs `steps` checks; returns per-step (kernel timing list)."""
     timings = []
@@ -125,6 +241,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)))
+        return
+    if args.workload == "served":
+        print(json.dumps(bench_served(args)))
+        return
     if args.workload != "stencil":
         bench_other(args)
         return
@@ -213,6 +335,15 @@ def main():
                                       "lanes_per_batch": int(rst["lanes"].sum()),
                                       "speedup_inputs_per_s_vs_full": step_s / rs}
         dw.close()
+    if not args.no_batched:
+        b = bench_batched(args)
+        result["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "kernels_per_s",
+                                                "per_kernel_launches", "speedup_vs_per_kernel", "autotune",
+                                                "kernel_ms_tuned_no_graph", "config")}
+    if not args.no_served:
+        sv = bench_served(args)
+        result["served"] = {k: sv[k] for k in ("value", "unit", "p50_ms", "p99_ms", "mean_ms", "jobs_per_s",
+                                                "offered_accesses_per_s", "config", "server")}
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         k = min(args.cpu_sample, n)

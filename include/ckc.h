@@ -153,13 +153,27 @@ typedef struct ckc_batch {
                                 0,0 selects the defaults 20, 12 */
 } ckc_batch;
 
+/* How the persistent evaluators hand out their work items (runs of `chunk`
+ * consecutive 256-lane tiles) to workgroups. */
+enum ckc_schedule {
+  CKC_SCHED_DEFAULT = 0,  /* BLOCKED for the trace evaluators, DYNAMIC for the interpreter */
+  CKC_SCHED_BLOCKED = 1,  /* workgroup g takes one contiguous range of tiles */
+  CKC_SCHED_CYCLIC = 2,   /* workgroup g takes items g, g+G, g+2G, ... */
+  CKC_SCHED_DYNAMIC = 3,  /* items from an atomic counter */
+  CKC_SCHED_LPT = 4       /* DYNAMIC over a tile space that lists the largest inputs first */
+};
+
 typedef struct ckc_launch_opts {
-  uint32_t tile;       /* lanes per tile (multiple of 64, <= 1024); 0 = default */
-  uint32_t wg_size;    /* threads per workgroup (64..1024); 0 = default */
-  uint32_t n_wg;       /* persistent workgroups; 0 = default */
+  uint32_t schedule;      /* ckc_schedule */
+  uint32_t chunk;         /* tiles per work item (1..256); 0 = 1 */
+  uint32_t wg_per_cu;     /* persistent workgroups per compute unit for every evaluator
+                             (1..32); 0 = per-evaluator defaults (8 trace, 2 interpreter) */
   uint32_t force_generic; /* 1: evaluate every program with the general interpreter */
-  void* hip_stream;    /* hipStream_t; NULL = the context's own stream */
-} ckc_launch_opts;
+  uint32_t use_graph;     /* 1: run the job's kernels as one HIP graph (the evaluators as
+                             parallel branches); per-kernel timing is then unavailable */
+  uint32_t pad;
+  void* hip_stream;       /* hipStream_t; NULL = the context's own stream */
+} ckc_launch_opts;        /* 32 bytes; all zeros = defaults */
 
 /* Checks every input of every descriptor in one job (one planning pass and
  * one persistent evaluation over all of them).  Host arrays are copied before
@@ -205,8 +219,84 @@ int ckc_job_sizes(ckc_ctx ctx, uint64_t job, uint64_t* n_inputs, uint64_t* n_rec
 /* Device timing of the job's kernels in milliseconds (HIP events on the job's
  * stream; waits for the job): [0] planning (thread sets, traces, tile scan),
  * [1] trace evaluator, [2] interpreter, [3] finishing (first-violation replay,
- * status, dense maps).  Call before ckc_read_results releases the job. */
+ * status, dense maps).  Jobs run as a graph report -1 in all four.  Call
+ * before ckc_read_results releases the job. */
 int ckc_job_timing(ckc_ctx ctx, uint64_t job, float* ms4);
+/* Device time of the whole job (first kernel start to last kernel end), in
+ * milliseconds; waits for the job.  Errors: CKC_E_INVALID (unknown job). */
+int ckc_job_elapsed(ckc_ctx ctx, uint64_t job, float* ms);
+
+/* ---- autotuning of the persistent launch ---------------------------------- */
+typedef struct ckc_tune_entry {
+  ckc_launch_opts opts;   /* candidate (hip_stream as passed in base) */
+  float ms;               /* best device time over the repetitions */
+  uint32_t pad;
+} ckc_tune_entry;         /* 40 bytes */
+
+/* Times candidate launch options on this very batch and returns the fastest
+ * in *best.  Candidates: every schedule (BLOCKED, CYCLIC, DYNAMIC, LPT) x
+ * chunk {1, 4, 16} x wg_per_cu {defaults, 2, 4, 8, 16}; `base` supplies
+ * force_generic, use_graph and the stream (NULL = defaults).  Each candidate
+ * runs `reps` (>= 1) complete jobs whose results are discarded; results do
+ * not depend on the options, so any candidate may be used.  log (may be
+ * NULL) receives up to log_cap entries in trial order, *n_log their count.
+ * Errors: as ckc_check_batch. */
+int ckc_autotune(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts* base,
+                 uint32_t reps, ckc_launch_opts* best, ckc_tune_entry* log, uint32_t log_cap,
+                 uint32_t* n_log);
+
+/* ---- serving: a request loop with continuous batching ---------------------
+ * A server owns a worker thread that admits submitted check jobs in arrival
+ * order while their device working set fits under a cap, packs the admitted
+ * jobs into one batched check per free stream (jobs that arrive while others
+ * run join the next batch on the next free stream, so batches overlap on the
+ * device), and copies each batch's results to host memory as it completes.
+ * While a server exists, its context must not be used by any other thread
+ * except through the ckc_server_* calls; load programs and put tables first. */
+typedef struct ckc_server_s* ckc_server;
+
+typedef struct ckc_server_config {
+  uint32_t n_streams;       /* concurrent batches (1..16); 0 = 4 */
+  uint32_t max_batch_jobs;  /* jobs per batch (1..65536); 0 = 1024 */
+  uint64_t hbm_cap_bytes;   /* device working set of admitted, unfinished jobs; 0 = 64 GB */
+  ckc_launch_opts opts;     /* launch options of every batch (hip_stream ignored) */
+} ckc_server_config;
+
+typedef struct ckc_job_stats {
+  uint64_t t_arrival_ns;    /* CLOCK_MONOTONIC times: arrival (as submitted), */
+  uint64_t t_admit_ns;      /* admission into a batch (its launch), */
+  uint64_t t_done_ns;       /* results copied to host memory (readable) */
+  uint64_t ws_bytes;        /* working-set estimate used for admission */
+  uint32_t batch_jobs;      /* jobs in the batch that ran this one */
+  int32_t status;           /* CKC_OK or the error that ended the job */
+} ckc_job_stats;            /* 40 bytes */
+
+typedef struct ckc_server_stats {
+  uint64_t submitted, completed, rejected, batches;
+  uint64_t max_inflight_bytes;  /* largest admitted working set at any time */
+  uint64_t max_inflight_jobs;
+} ckc_server_stats;             /* 48 bytes */
+
+/* Starts a server on ctx.  Errors: CKC_E_INVALID (limits), CKC_E_HIP. */
+int ckc_server_create(ckc_ctx ctx, const ckc_server_config* cfg, ckc_server* out);
+/* Drains every submitted job, stops the worker, frees the server (unread
+ * results are dropped). */
+void ckc_server_destroy(ckc_server srv);
+/* Queues one job: the inputs of one descriptor (host arrays copied before
+ * return; CKC_DENSE_MAP in desc->flags asks for maps).  arrival_ns: the
+ * job's arrival on CLOCK_MONOTONIC (0 = now).  The descriptor is validated
+ * here (errors as ckc_check_batch).  A job whose working set alone exceeds
+ * the cap is accepted and ends with CKC_E_NOMEM.  Thread-safe. */
+int ckc_server_submit(ckc_server srv, const ckc_batch* desc, uint64_t arrival_ns, uint64_t* ticket);
+/* Results of a job, then the job is forgotten.  recs: [n_inputs][n_accesses],
+ * maps: [n_inputs][65536] or NULL (requires CKC_DENSE_MAP), st: [n_inputs] or
+ * NULL, stats: may be NULL; all host pointers.  Without CKC_WAIT returns
+ * CKC_NOT_READY while the job is unfinished.  Returns the job's status
+ * (CKC_OK, or e.g. CKC_E_NOMEM for a job above the cap).  Thread-safe. */
+int ckc_server_result(ckc_server srv, uint64_t ticket, ckc_record* recs, uint8_t* maps, ckc_input_status* st,
+                      ckc_job_stats* stats, uint32_t flags);
+/* Counters since creation.  Thread-safe. */
+int ckc_server_get_stats(ckc_server srv, ckc_server_stats* out);
 
 #ifdef __cplusplus
 }

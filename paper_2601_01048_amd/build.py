@@ -41,7 +41,8 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, device in (("kernels.hip", True), ("loader.cpp", False), ("runtime.cpp", False)):
+    for src, device in (("kernels.hip", True), ("loader.cpp", False), ("runtime.cpp", False),
+                        ("server.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [hipcc] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         if device:
@@ -51,7 +52,7 @@ def build(verbose: bool = False) -> str:
         _run(cmd)
         objs.append(obj)
     tmp = LIB + f".tmp{os.getpid()}"
-    _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs)
+    _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

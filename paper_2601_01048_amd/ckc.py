@@ -17,6 +17,8 @@ LIB = os.path.join(HERE, "libckc.so")
 
 OK, NOT_READY = 0, 1
 FULL, REP_CORNERS, REP_BOUNDARY = 0, 1, 2
+SCHED_DEFAULT, SCHED_BLOCKED, SCHED_CYCLIC, SCHED_DYNAMIC, SCHED_LPT = 0, 1, 2, 3, 4
+SCHED_NAMES = {0: "default", 1: "blocked", 2: "cyclic", 3: "dynamic", 4: "lpt"}
 DENSE_MAP = 2
 WAIT, DST_DEVICE = 1, 2
 CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32)
@@ -49,8 +51,37 @@ class Batch(ctypes.Structure):
 
 
 class LaunchOpts(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_uint32), ("wg_size", ctypes.c_uint32), ("n_wg", ctypes.c_uint32),
-                ("force_generic", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p)]
+    _fields_ = [("schedule", ctypes.c_uint32), ("chunk", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("force_generic", ctypes.c_uint32), ("use_graph", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("hip_stream", ctypes.c_void_p)]
+
+    def as_dict(self):
+        return dict(schedule=SCHED_NAMES.get(self.schedule, self.schedule), chunk=self.chunk,
+                    wg_per_cu=self.wg_per_cu, use_graph=self.use_graph)
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("opts", LaunchOpts), ("ms", ctypes.c_float), ("pad", ctypes.c_uint32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_uint32), ("max_batch_jobs", ctypes.c_uint32),
+                ("hbm_cap_bytes", ctypes.c_uint64), ("opts", LaunchOpts)]
+
+
+class JobStats(ctypes.Structure):
+    _fields_ = [("t_arrival_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("ws_bytes", ctypes.c_uint64),
+                ("batch_jobs", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "batches",
+                                                "max_inflight_bytes", "max_inflight_jobs")]
+
+
+def launch_opts(schedule=0, chunk=0, wg_per_cu=0, force_generic=False, use_graph=False, stream=None):
+    return LaunchOpts(schedule, chunk, wg_per_cu, 1 if force_generic else 0, 1 if use_graph else 0, 0, stream)
 
 
 class CkcError(RuntimeError):
@@ -82,9 +113,19 @@ def lib():
         L.ckc_read_results.argtypes = [vp, u64, vp, vp, vp, u32]
         L.ckc_job_sizes.argtypes = [vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.ckc_job_timing.argtypes = [vp, u64, vp]
+        L.ckc_job_elapsed.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_float)]
+        L.ckc_autotune.argtypes = [vp, vp, u32, vp, u32, vp, vp, u32, ctypes.POINTER(u32)]
+        L.ckc_server_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.ckc_server_destroy.argtypes = [vp]
+        L.ckc_server_destroy.restype = None
+        L.ckc_server_submit.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
+        L.ckc_server_result.argtypes = [vp, u64, vp, vp, vp, vp, u32]
+        L.ckc_server_get_stats.argtypes = [vp, vp]
         for f in ("ckc_init", "ckc_analyze_ir", "ckc_load_program", "ckc_unload_program",
                   "ckc_put_alloc_table", "ckc_free_alloc_table", "ckc_check_batch",
-                  "ckc_read_results", "ckc_job_sizes", "ckc_job_timing"):
+                  "ckc_read_results", "ckc_job_sizes", "ckc_job_timing", "ckc_job_elapsed",
+                  "ckc_autotune", "ckc_server_create", "ckc_server_submit", "ckc_server_result",
+                  "ckc_server_get_stats"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -154,9 +195,10 @@ class Context:
     def free_table(self, tid: int):
         _check(lib().ckc_free_alloc_table(self.h, tid))
 
-    def check(self, descs, force_generic=False, n_wg=0, stream=None) -> int:
-        """descs: list of dict(prog, launch [n,6], scalars [n,k], table_ids [n],
-        mode, flags, cap_log2)."""
+    @staticmethod
+    def prepare(descs):
+        """ctypes descriptor array for ``descs`` (list of dict(prog, launch [n,6],
+        scalars [n,k], table_ids [n], mode, flags, cap_log2)); reusable."""
         keep = []
         arr = (Batch * len(descs))()
         for b, d in zip(arr, descs):
@@ -171,10 +213,38 @@ class Context:
             b.flags = d.get("flags", 0)
             cap = d.get("cap_log2", (20, 12))
             b.loop_cap_log2[0], b.loop_cap_log2[1] = cap
-        opts = LaunchOpts(0, 0, n_wg, 1 if force_generic else 0, stream)
+        return (arr, keep)
+
+    def check(self, descs, force_generic=False, stream=None, opts: LaunchOpts | None = None) -> int:
+        """Queues one job over ``descs`` (a list of descriptor dicts or the
+        result of ``prepare``); returns the job id."""
+        arr, keep = descs if isinstance(descs, tuple) else self.prepare(descs)
+        if opts is None:
+            opts = launch_opts(force_generic=force_generic, stream=stream)
         job = ctypes.c_uint64()
-        _check(lib().ckc_check_batch(self.h, arr, len(descs), ctypes.byref(opts), ctypes.byref(job)))
+        _check(lib().ckc_check_batch(self.h, arr, len(arr), ctypes.byref(opts), ctypes.byref(job)))
+        del keep
         return job.value
+
+    def elapsed(self, job: int) -> float:
+        ms = ctypes.c_float()
+        _check(lib().ckc_job_elapsed(self.h, job, ctypes.byref(ms)))
+        return ms.value
+
+    def release(self, job: int):
+        """Waits for a job and drops its results."""
+        _check(lib().ckc_read_results(self.h, job, None, None, None, WAIT))
+
+    def autotune(self, descs, reps: int = 2, base: LaunchOpts | None = None, log_cap: int = 128):
+        """Native autotuner: (best LaunchOpts, [(opts dict, ms), ...])."""
+        arr, keep = descs if isinstance(descs, tuple) else self.prepare(descs)
+        best = LaunchOpts()
+        log = (TuneEntry * log_cap)()
+        n = ctypes.c_uint32()
+        _check(lib().ckc_autotune(self.h, arr, len(arr), ctypes.byref(base) if base else None, reps,
+                                  ctypes.byref(best), log, log_cap, ctypes.byref(n)))
+        del keep
+        return best, [(log[k].opts.as_dict(), log[k].ms) for k in range(n.value)]
 
     def sizes(self, job: int):
         ni, nr = ctypes.c_uint64(), ctypes.c_uint64()
@@ -245,3 +315,162 @@ def run_workload(ctx: Context, wl, mode=None, force_generic=False, maps=True, ca
         dw.close()
     n = wl.n_inputs
     return dict(records=recs.reshape(n, -1), maps=mp, status=st, info=dw.info)
+
+
+class DeviceBatch:
+    """A mixed batch (one-input workloads with their own programs, tables and
+    data) placed on the device once: each distinct program is loaded once,
+    every data array sits in one int32 device buffer, one table per kernel."""
+
+    def __init__(self, ctx: Context, mb, device: str = "cuda"):
+        import torch
+        self.ctx, self.mb = ctx, mb
+        self.progs, self.infos = {}, {}
+        for k in mb.kernels:
+            if k.ir not in self.progs:
+                self.progs[k.ir], self.infos[k.ir] = ctx.load_program(k.ir)
+        # one flat buffer for every data array (all int32), 256-byte aligned offsets
+        offs, total = [], 0
+        for k in mb.kernels:
+            o = []
+            for d in k.data:
+                o.append(total)
+                total += (d.nbytes + 255) // 256 * 256
+            offs.append(o)
+        flat = np.zeros(max(total, 256) // 4, np.int32)
+        for k, o in zip(mb.kernels, offs):
+            for d, off in zip(k.data, o):
+                flat[off // 4: off // 4 + d.size] = np.ascontiguousarray(d, np.int32).reshape(-1)
+        self.buf = torch.from_numpy(flat).to(device)
+        base = self.buf.data_ptr()
+        self.table_ids = []
+        for k, o in zip(mb.kernels, offs):
+            e = np.array(k.tables[0], ALLOC_DTYPE)
+            refs = e["data"].astype(np.int64)
+            e["data"] = [base + o[r - 1] if r else 0 for r in refs]
+            self.table_ids.append(ctx.put_table(e))
+
+    def descs(self, idx=None, dense=True):
+        """One descriptor per kernel (kernels ``idx``, default all), in order."""
+        ks = range(len(self.mb.kernels)) if idx is None else idx
+        out = []
+        for i in ks:
+            k = self.mb.kernels[i]
+            out.append(dict(prog=self.progs[k.ir], launch=k.launch, scalars=k.scalars,
+                            table_ids=np.array([self.table_ids[i]], np.uint32), mode=k.mode,
+                            flags=DENSE_MAP if dense else 0, cap_log2=k.cap_log2))
+        return out
+
+    def n_accesses(self, i):
+        return self.infos[self.mb.kernels[i].ir]["n_accesses"]
+
+    def close(self):
+        for t in self.table_ids:
+            self.ctx.free_table(int(t))
+        for pid in self.progs.values():
+            self.ctx.unload_program(pid)
+        self.table_ids, self.progs, self.buf = [], {}, None
+
+
+def split_results(recs, maps, st, counts):
+    """Per-input views of a job's flat records given each input's access count."""
+    out, r = [], 0
+    for i, n in enumerate(counts):
+        out.append(dict(records=recs[r:r + n], maps=None if maps is None else maps[i], status=st[i]))
+        r += n
+    return out
+
+
+class Server:
+    """The library's request loop (ckc_server_*) on a context: continuous
+    batching of submitted jobs over ``n_streams`` streams under an HBM
+    working-set cap.  While it exists, the context is used only through it."""
+
+    def __init__(self, ctx: Context, n_streams=4, max_batch_jobs=0, hbm_cap_bytes=0,
+                 opts: LaunchOpts | None = None):
+        cfg = ServerConfig(n_streams, max_batch_jobs, hbm_cap_bytes, opts if opts is not None else LaunchOpts())
+        h = ctypes.c_void_p()
+        _check(lib().ckc_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, desc, arrival_ns: int = 0) -> int:
+        """desc: a descriptor dict or a ``Context.prepare([desc])`` result."""
+        arr, keep = desc if isinstance(desc, tuple) else Context.prepare([desc])
+        t = ctypes.c_uint64()
+        _check(lib().ckc_server_submit(self.h, arr, arrival_ns, ctypes.byref(t)))
+        del keep
+        return t.value
+
+    def result(self, ticket: int, n_inputs: int, n_acc: int, maps: bool = True, wait: bool = True):
+        """(code, records [n_inputs*n_acc], maps [n_inputs, 65536] or None, status, stats dict);
+        code is CKC_OK or the job's error (e.g. -4 for a job above the cap); None if not ready."""
+        recs = np.zeros(n_inputs * n_acc, RECORD_DTYPE)
+        mp = np.zeros((n_inputs, 65536), np.uint8) if maps else None
+        st = np.zeros(n_inputs, STATUS_DTYPE)
+        js = JobStats()
+        rc = lib().ckc_server_result(self.h, ticket, _p(recs), _p(mp) if maps else None, _p(st),
+                                     ctypes.byref(js), WAIT if wait else 0)
+        if rc == NOT_READY:
+            return None
+        stats = {f: getattr(js, f) for f, _ in JobStats._fields_}
+        return rc, recs, mp, st, stats
+
+    def stats(self):
+        out = ServerStats()
+        _check(lib().ckc_server_get_stats(self.h, ctypes.byref(out)))
+        return {f: getattr(out, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().ckc_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class DeviceStream:
+    """A served stream's programs, resident CSR pool (one device buffer) and
+    one allocation table per job, placed on the device before serving."""
+
+    def __init__(self, ctx: Context, ss, device: str = "cuda"):
+        import torch
+        self.ctx, self.ss = ctx, ss
+        self.progs, self.infos = {}, {}
+        for k in ss.jobs:
+            if k.ir not in self.progs:
+                self.progs[k.ir], self.infos[k.ir] = ctx.load_program(k.ir)
+        offs, total = [], 0
+        for d in ss.pool:
+            offs.append(total)
+            total += (d.nbytes + 255) // 256 * 256
+        flat = np.zeros(max(total, 256) // 4, np.int32)
+        for d, off in zip(ss.pool, offs):
+            flat[off // 4: off // 4 + d.size] = np.ascontiguousarray(d, np.int32).reshape(-1)
+        self.buf = torch.from_numpy(flat).to(device)
+        base = self.buf.data_ptr()
+        self.table_ids = []
+        for k in ss.jobs:
+            e = np.array(k.tables[0], ALLOC_DTYPE)
+            refs = e["data"].astype(np.int64)
+            e["data"] = [base + offs[r - 1] if r else 0 for r in refs]
+            self.table_ids.append(ctx.put_table(e))
+
+    def desc(self, j: int, dense: bool = True):
+        k = self.ss.jobs[j]
+        return dict(prog=self.progs[k.ir], launch=k.launch, scalars=k.scalars,
+                    table_ids=np.array([self.table_ids[j]], np.uint32), mode=k.mode,
+                    flags=DENSE_MAP if dense else 0, cap_log2=k.cap_log2)
+
+    def n_accesses(self, j: int) -> int:
+        return self.infos[self.ss.jobs[j].ir]["n_accesses"]
+
+    def close(self):
+        for t in self.table_ids:
+            self.ctx.free_table(int(t))
+        for pid in self.progs.values():
+            self.ctx.unload_program(pid)
+        self.table_ids, self.progs, self.buf = [], {}, None

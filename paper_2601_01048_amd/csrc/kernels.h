@@ -25,14 +25,26 @@ struct KArgs {
   ckc_input_status* status;
   uint8_t* maps;            // [n_inputs][65536] or null
   jobstate* js;
+  const uint32_t* order;    // [n_inputs]: tile-space position -> input index
+  uint32_t sched;           // ckc_schedule of the evaluator being launched (set per launch)
+  uint32_t chunk;           // tiles per work item
+};
+
+// Workgroups and schedule of each evaluator (index PATH_*).
+struct EvalGrid {
+  uint32_t n_wg[3];
+  uint32_t sched[3];
 };
 
 hipError_t launch_plan(const KArgs& a, hipStream_t s);
 hipError_t launch_scan(const KArgs& a, hipStream_t s);
-hipError_t launch_eval_trace(const KArgs& a, uint32_t n_wg, hipStream_t s);
-hipError_t launch_eval_trace_lanes(const KArgs& a, uint32_t n_wg, hipStream_t s);
-hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, uint32_t n_regs, hipStream_t s);
-hipError_t launch_fixup(const KArgs& a, uint64_t n_records, uint32_t n_regs, hipStream_t s);
+hipError_t launch_eval_trace(const KArgs& a, const EvalGrid& eg, hipStream_t s);
+hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream_t s);
+hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s);
+hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s);
 hipError_t launch_finish(const KArgs& a, hipStream_t s);
+// The whole job as one graph: plan -> scan -> the three evaluators (parallel
+// branches) -> first-violation replay -> finishing.
+hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uint64_t n_records);
 
 }  // namespace ckc

@@ -26,6 +26,8 @@
 #include "dformat.h"
 #include "kernels.h"
 
+#include <cstring>
+
 namespace ckc {
 
 // ---------------------------------------------------------------------------
@@ -597,7 +599,8 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
   }
 }
 
-// Exclusive prefix of per-input tile counts for the three evaluators.
+// Exclusive prefix of per-input tile counts for the three evaluators, taken in
+// tile-space order (a.order: position -> input).
 __global__ void __launch_bounds__(1024) scan_kernel(KArgs a) {
   __shared__ unsigned long long part[3][1024 / 64];
   __shared__ unsigned long long carry[3];
@@ -605,10 +608,11 @@ __global__ void __launch_bounds__(1024) scan_kernel(KArgs a) {
   if (t < 3) carry[t] = 0;
   __syncthreads();
   for (uint32_t base = 0; base < a.n_inputs; base += 1024) {
-    const uint32_t i = base + t;
+    const uint32_t pos = base + t;
+    const uint32_t i = pos < a.n_inputs ? a.order[pos] : 0u;
     uint64_t v[3], sc[3];
     for (int p = 0; p < 3; p++) {
-      v[p] = i < a.n_inputs ? a.inputs[i].n_tiles[p] : 0;
+      v[p] = pos < a.n_inputs ? a.inputs[i].n_tiles[p] : 0;
       sc[p] = v[p];
     }
     for (int o = 1; o < 64; o <<= 1)  // inclusive wavefront scan
@@ -624,7 +628,7 @@ __global__ void __launch_bounds__(1024) scan_kernel(KArgs a) {
       for (uint32_t q = 0; q < t / 64; q++) w[p] += part[p][q];
       c[p] = carry[p];
     }
-    if (i < a.n_inputs)
+    if (pos < a.n_inputs)
       for (int p = 0; p < 3; p++) a.inputs[i].tile_begin[p] = c[p] + w[p] + sc[p] - v[p];
     __syncthreads();
     if (t == 1023)
@@ -637,15 +641,74 @@ __global__ void __launch_bounds__(1024) scan_kernel(KArgs a) {
   }
 }
 
-// Largest input index i with tile_begin[path][i] <= t (t < total).
-__device__ __forceinline__ uint32_t find_input(const dinput* in, uint32_t n, uint32_t path, uint64_t t) {
+// Position p (into a.order) of the input whose tiles hold t (t < total): the
+// largest p with tile_begin[path] of input order[p] <= t, which always has
+// tiles since the next position starts after t.
+__device__ __forceinline__ uint32_t find_pos(const dinput* in, const uint32_t* order, uint32_t n, uint32_t path,
+                                             uint64_t t) {
   uint32_t lo = 0, hi = n - 1;
   while (lo < hi) {
     uint32_t mid = lo + (hi - lo + 1) / 2;
-    if (in[mid].tile_begin[path] <= t) lo = mid;
+    if (in[order[mid]].tile_begin[path] <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Work distribution of a persistent evaluator over its `total` tiles: work
+// items are runs of `chunk` consecutive tiles.  BLOCKED: workgroup g takes
+// tiles [total*g/G, total*(g+1)/G); CYCLIC: items g, g+G, g+2G, ...;
+// DYNAMIC and LPT: items from an atomic counter (LPT's tile space lists the
+// inputs largest first).  sched_next is called by the whole workgroup and
+// returns the same tile in every lane, ~0 when the workgroup is done.
+template <uint32_t SK>
+struct Sched {
+  uint32_t chunk;
+  uint64_t total, cur, end, item;
+};
+template <uint32_t SK>
+__device__ __forceinline__ void sched_init(Sched<SK>& s, const KArgs& a, uint64_t total) {
+  s.chunk = a.chunk ? a.chunk : 1u;
+  s.total = total;
+  const uint64_t G = gridDim.x, g = blockIdx.x;
+  if (SK == CKC_SCHED_BLOCKED) {
+    s.cur = total * g / G;
+    s.end = total * (g + 1) / G;
+  } else if (SK == CKC_SCHED_CYCLIC) {
+    s.item = g;
+    s.cur = g * s.chunk;
+    s.end = s.cur + s.chunk < total ? s.cur + s.chunk : total;
+  } else {
+    s.cur = s.end = 0;
+  }
+}
+template <uint32_t SK>
+__device__ __forceinline__ uint64_t sched_next(Sched<SK>& s, unsigned long long* counter, unsigned long long* slot) {
+  if (s.cur < s.end) return s.cur++;
+  if (SK == CKC_SCHED_BLOCKED) return ~0ull;
+  uint64_t item;
+  if (SK == CKC_SCHED_CYCLIC) {
+    s.item += gridDim.x;
+    item = s.item;
+  } else {
+    __syncthreads();  // every wavefront has read the previous item
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1ull);
+    __syncthreads();
+    item = *slot;
+  }
+  const uint64_t b = item * s.chunk;
+  if (b >= s.total) {
+    s.cur = s.end = 0;
+    return ~0ull;
+  }
+  s.cur = b + 1;
+  s.end = b + s.chunk < s.total ? b + s.chunk : s.total;
+  return b;
+}
+// The schedule a kernel instantiation is compiled for (LPT runs DYNAMIC over
+// its own tile order).
+constexpr uint32_t sched_impl(uint32_t k) {
+  return k == CKC_SCHED_BLOCKED ? CKC_SCHED_BLOCKED : k == CKC_SCHED_CYCLIC ? CKC_SCHED_CYCLIC : CKC_SCHED_DYNAMIC;
 }
 
 // ---------------------------------------------------------------------------
@@ -673,15 +736,29 @@ typedef const __attribute__((address_space(4))) dtrace_entry c_entry;
 typedef const __attribute__((address_space(4))) dtrace_head c_head;
 typedef const __attribute__((address_space(4))) dinput c_input;
 typedef const __attribute__((address_space(4))) jobstate c_jobstate;
+typedef const __attribute__((address_space(4))) uint32_t c_u32;
 
-__device__ __forceinline__ uint32_t find_input_c(c_input* in, uint32_t n, uint32_t path, uint64_t t) {
+__device__ __forceinline__ uint32_t find_pos_c(c_input* in, c_u32* order, uint32_t n, uint32_t path, uint64_t t) {
   uint32_t lo = 0, hi = n - 1;
   while (lo < hi) {
     uint32_t mid = lo + (hi - lo + 1) / 2;
-    if (in[mid].tile_begin[path] <= t) lo = mid;
+    if (in[order[mid]].tile_begin[path] <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Position of the input holding tile t: the next one or two positions are
+// tried first (consecutive tiles of one workgroup), then a binary search.
+__device__ __forceinline__ uint32_t pos_of_tile(c_input* ins, c_u32* order, uint32_t n, uint32_t path,
+                                                uint32_t pos, uint64_t cur_end, uint64_t t) {
+  if (pos != 0xFFFFFFFFu && t >= cur_end) {
+    for (uint32_t q = pos + 1; q < n && q <= pos + 2; q++) {
+      const uint32_t i = order[q];
+      if (t >= ins[i].tile_begin[path] && t < ins[i].tile_begin[path] + ins[i].n_tiles[path]) return q;
+    }
+  }
+  return find_pos_c(ins, order, n, path, t);
 }
 
 // Violations found by the trace evaluator are merged per workgroup in LDS (first
@@ -734,7 +811,6 @@ __device__ __forceinline__ uint64_t bset_block_call(uint32_t gx, uint32_t gy, ui
 }
 
 typedef const __attribute__((address_space(4))) int64_t c_i64;
-typedef const __attribute__((address_space(4))) uint32_t c_u32;
 typedef const __attribute__((address_space(4))) dprog c_dprog;
 
 // Violation path of entry e in a block-major job (rare): per block, the mask
@@ -998,17 +1074,20 @@ __device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_r
   tb = ins[i].tile_begin[path];
 }
 
-// Trace evaluator, block-major layout: persistent workgroups over a contiguous
-// range of tiles; a tile is four wavefront jobs.
+// Trace evaluator, block-major layout: persistent workgroups over the tile
+// space of PATH_BLOCKS under the job's schedule; a tile is four wavefront jobs.
+template <uint32_t SK>
 __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
   __shared__ TraceLds S;
+  __shared__ unsigned long long item_slot;
   c_jobstate* js = (c_jobstate*)a.js;
   c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
   const uint64_t total = js->total_tiles[PATH_BLOCKS];
   if (total == 0) return;
-  const uint64_t G = gridDim.x;
-  const uint64_t t_begin = total * blockIdx.x / G, t_end = total * (blockIdx.x + 1) / G;
-  if (t_begin >= t_end) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
   const uint32_t tid = threadIdx.x;
   for (uint32_t q = tid; q < TR_ACC_LDS; q += TILE) {
     S.fk[q] = ~0ull;
@@ -1016,20 +1095,20 @@ __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
     S.kinds[q] = 0;
   }
   __syncthreads();
-  uint32_t i = find_input_c(ins, a.n_inputs, PATH_BLOCKS, t_begin);
-  uint32_t cur = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint32_t pos = 0xFFFFFFFFu, ncls = 0, w0 = 32;
   uint64_t tb = 0, cur_end = 0;
   c_head* th = nullptr;
   TrIn I;
-  for (uint64_t t = t_begin; t < t_end; t++) {
-    if (t >= cur_end) {
-      while (ins[i].n_tiles[PATH_BLOCKS] == 0 ||
-             t >= ins[i].tile_begin[PATH_BLOCKS] + ins[i].n_tiles[PATH_BLOCKS])
-        i++;
-      cur_end = ins[i].tile_begin[PATH_BLOCKS] + ins[i].n_tiles[PATH_BLOCKS];
-      if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
-      cur = i;
+  for (;;) {
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_BLOCKS], &item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      const uint32_t np = pos_of_tile(ins, order, a.n_inputs, PATH_BLOCKS, pos, cur_end, t);
+      if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+      pos = np;
+      const uint32_t i = order[pos];
       tr_load(I, ins, i, a.recs, tb, PATH_BLOCKS, ncls, w0, th);
+      cur_end = tb + ins[i].n_tiles[PATH_BLOCKS];
     }
     const uint32_t wv = ufirst(tid >> 6);
     const uint64_t job = (t - tb) * 4 + wv;
@@ -1040,20 +1119,23 @@ __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
     if (w0 == 32) block_job<32>(S, I, g, o);
     else block_job<64>(S, I, g, o);
   }
-  if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+  if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
 }
 
 // Trace evaluator over lane tiles (thread sets or traces the block-major
 // layout does not cover): TILE consecutive lanes of the thread set per tile.
+template <uint32_t SK>
 __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
   __shared__ TraceLds S;
+  __shared__ unsigned long long item_slot;
   c_jobstate* js = (c_jobstate*)a.js;
   c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
   const uint64_t total = js->total_tiles[PATH_LANES];
   if (total == 0) return;
-  const uint64_t G = gridDim.x;
-  const uint64_t t_begin = total * blockIdx.x / G, t_end = total * (blockIdx.x + 1) / G;
-  if (t_begin >= t_end) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
   const uint32_t tid = threadIdx.x;
   for (uint32_t q = tid; q < TR_ACC_LDS; q += TILE) {
     S.fk[q] = ~0ull;
@@ -1061,20 +1143,20 @@ __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
     S.kinds[q] = 0;
   }
   __syncthreads();
-  uint32_t i = find_input_c(ins, a.n_inputs, PATH_LANES, t_begin);
-  uint32_t cur = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint32_t pos = 0xFFFFFFFFu, ncls = 0, w0 = 32;
   uint64_t tb = 0, cur_end = 0, lanes = 0;
   c_head* th = nullptr;
   TrIn I;
-  for (uint64_t t = t_begin; t < t_end; t++) {
-    if (t >= cur_end) {
-      while (ins[i].n_tiles[PATH_LANES] == 0 ||
-             t >= ins[i].tile_begin[PATH_LANES] + ins[i].n_tiles[PATH_LANES])
-        i++;
-      cur_end = ins[i].tile_begin[PATH_LANES] + ins[i].n_tiles[PATH_LANES];
-      if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
-      cur = i;
+  for (;;) {
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_LANES], &item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      const uint32_t np = pos_of_tile(ins, order, a.n_inputs, PATH_LANES, pos, cur_end, t);
+      if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+      pos = np;
+      const uint32_t i = order[pos];
       tr_load(I, ins, i, a.recs, tb, PATH_LANES, ncls, w0, th);
+      cur_end = tb + ins[i].n_tiles[PATH_LANES];
       lanes = ins[i].lanes;
     }
     const uint64_t l = (t - tb) * TILE + tid;
@@ -1109,7 +1191,7 @@ __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
       if (__ballot(act && x) || te[e].dead_kind) lanes_violation(S, te, e, v, act, T.gtid, I.rec, I.lds, I.Lsum);
     }
   }
-  if (cur != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+  if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1482,31 +1564,41 @@ __device__ __forceinline__ void lane_init(Lane& ln, bool act, uint64_t gtid) {
   ln.hangs = 0;
 }
 
+template <uint32_t SK>
 __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   __shared__ GenLds S;
+  __shared__ unsigned long long item_slot;
   const uint32_t tid = threadIdx.x;
   const uint64_t total = a.js->total_tiles[PATH_GENERIC];
   if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
-  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0;
+  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0;
+  uint64_t tb = 0, cur_end = 0;
   for (;;) {
     __syncthreads();
-    if (tid == 0) S.tile = atomicAdd((unsigned long long*)&a.js->next_tile[PATH_GENERIC], 1ull);
-    __syncthreads();
-    const uint64_t t = S.tile;
-    if (t >= total) break;
-    const uint32_t i = find_input(a.inputs, a.n_inputs, PATH_GENERIC, t);
-    const dinput& in = a.inputs[i];
-    if (i != cur) {
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_GENERIC], &item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      pos = pos_of_tile(ins, order, a.n_inputs, PATH_GENERIC, pos, cur_end, t);
+      const uint32_t i = order[pos];
       if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
-      const ckc_alloc* tab = (const ckc_alloc*)in.table;
-      const uint32_t ns = ((c_dprog*)in.prog)->n_slots;
+      const ckc_alloc* tab = (const ckc_alloc*)a.inputs[i].table;
+      const uint32_t ns = ((c_dprog*)a.inputs[i].prog)->n_slots;
       if (tid < ns) S.tab[tid] = tab[tid];
       cur = i;
-      cur_sites = ((c_dprog*)in.prog)->n_sites;
+      cur_sites = ((c_dprog*)a.inputs[i].prog)->n_sites;
+      tb = ins[i].tile_begin[PATH_GENERIC];
+      cur_end = tb + ins[i].n_tiles[PATH_GENERIC];
       __syncthreads();
     }
+    const uint32_t i = cur;
+    const dinput& in = a.inputs[i];
     const uint64_t l = (t - in.tile_begin[PATH_GENERIC]) * TILE + tid;
     const bool act = l < in.lanes;
     Thr T;
@@ -1614,28 +1706,96 @@ hipError_t launch_scan(const KArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_eval_trace(const KArgs& a, uint32_t n_wg, hipStream_t s) {
-  hipLaunchKernelGGL(eval_trace_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
-  return hipGetLastError();
+namespace {
+KArgs with_sched(const KArgs& a, const EvalGrid& eg, uint32_t path) {
+  KArgs k = a;
+  k.sched = eg.sched[path];
+  return k;
 }
-hipError_t launch_eval_trace_lanes(const KArgs& a, uint32_t n_wg, hipStream_t s) {
-  hipLaunchKernelGGL(eval_trace_lanes_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
-  return hipGetLastError();
+// Kernel of evaluator `path` compiled for schedule `sk`.
+void* eval_fn(uint32_t path, uint32_t sk) {
+  const uint32_t s = sched_impl(sk);
+  if (path == PATH_BLOCKS)
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_trace_kernel<CKC_SCHED_BLOCKED>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_trace_kernel<CKC_SCHED_CYCLIC>
+                                  : (void*)eval_trace_kernel<CKC_SCHED_DYNAMIC>;
+  if (path == PATH_LANES)
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_trace_lanes_kernel<CKC_SCHED_BLOCKED>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_trace_lanes_kernel<CKC_SCHED_CYCLIC>
+                                  : (void*)eval_trace_lanes_kernel<CKC_SCHED_DYNAMIC>;
+  return s == CKC_SCHED_BLOCKED ? (void*)eval_generic_kernel<CKC_SCHED_BLOCKED>
+       : s == CKC_SCHED_CYCLIC  ? (void*)eval_generic_kernel<CKC_SCHED_CYCLIC>
+                                : (void*)eval_generic_kernel<CKC_SCHED_DYNAMIC>;
 }
-hipError_t launch_eval_generic(const KArgs& a, uint32_t n_wg, uint32_t n_regs, hipStream_t s) {
-  (void)n_regs;
-  hipLaunchKernelGGL(eval_generic_kernel, dim3(n_wg), dim3(TILE), 0, s, a);
-  return hipGetLastError();
+hipError_t launch_eval(const KArgs& a, const EvalGrid& eg, uint32_t path, hipStream_t s) {
+  KArgs k = with_sched(a, eg, path);
+  void* args[] = {&k};
+  return hipLaunchKernel(eval_fn(path, eg.sched[path]), dim3(eg.n_wg[path]), dim3(TILE), args, 0, s);
 }
-hipError_t launch_fixup(const KArgs& a, uint64_t n_records, uint32_t n_regs, hipStream_t s) {
+}  // namespace
+
+hipError_t launch_eval_trace(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
+  return launch_eval(a, eg, PATH_BLOCKS, s);
+}
+hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
+  return launch_eval(a, eg, PATH_LANES, s);
+}
+hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
+  return launch_eval(a, eg, PATH_GENERIC, s);
+}
+hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s) {
   if (n_records == 0) return hipSuccess;
-  (void)n_regs;
   hipLaunchKernelGGL(fixup_kernel, dim3((uint32_t)n_records), dim3(64), 0, s, a, n_records);
   return hipGetLastError();
 }
 hipError_t launch_finish(const KArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(finish_kernel, dim3(a.n_inputs), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+namespace {
+hipError_t add_node(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t n_deps, void* fn,
+                    uint32_t grid, uint32_t block, void** args) {
+  hipKernelNodeParams p;
+  std::memset(&p, 0, sizeof p);
+  p.func = fn;
+  p.gridDim = dim3(grid);
+  p.blockDim = dim3(block);
+  p.sharedMemBytes = 0;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
+}
+}  // namespace
+
+hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uint64_t n_records) {
+  KArgs ka = a;
+  KArgs kp[3] = {with_sched(a, eg, 0), with_sched(a, eg, 1), with_sched(a, eg, 2)};
+  uint64_t nr = n_records;
+  void* args1[] = {&ka};
+  void* args2[] = {&ka, &nr};
+  void* argsp[3][1] = {{&kp[0]}, {&kp[1]}, {&kp[2]}};
+  hipGraphNode_t plan, scan, ev[3], fix, fin;
+  hipError_t e = add_node(g, &plan, nullptr, 0, (void*)plan_kernel, a.n_inputs, 64, args1);
+  if (e == hipSuccess) e = add_node(g, &scan, &plan, 1, (void*)scan_kernel, 1, 1024, args1);
+  if (e == hipSuccess)
+    e = add_node(g, &ev[0], &scan, 1, eval_fn(PATH_BLOCKS, eg.sched[PATH_BLOCKS]), eg.n_wg[PATH_BLOCKS], TILE,
+                 argsp[PATH_BLOCKS]);
+  if (e == hipSuccess)
+    e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC]), eg.n_wg[PATH_GENERIC], TILE,
+                 argsp[PATH_GENERIC]);
+  if (e == hipSuccess)
+    e = add_node(g, &ev[2], &scan, 1, eval_fn(PATH_LANES, eg.sched[PATH_LANES]), eg.n_wg[PATH_LANES], TILE,
+                 argsp[PATH_LANES]);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t last = nullptr;
+  if (n_records) {
+    e = add_node(g, &fix, ev, 3, (void*)fixup_kernel, (uint32_t)n_records, 64, args2);
+    last = fix;
+  }
+  if (e == hipSuccess)
+    e = add_node(g, &fin, last ? &last : ev, last ? 1 : 3, (void*)finish_kernel, a.n_inputs, 256, args1);
+  return e;
 }
 
 }  // namespace ckc

@@ -16,17 +16,24 @@
 #include "dformat.h"
 #include "kernels.h"
 #include "loader.h"
+#include "runtime.h"
 
 using namespace ckc;
+using ckc::rt::Job;
+using ckc::rt::Program;
+using ckc::rt::Table;
+using ckc::rt::fail;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const std::string& msg) {
+int ckc::rt::fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+
+namespace {
 
 #define HIPCHECK(expr)                                                                   \
   do {                                                                                   \
@@ -35,47 +42,7 @@ int fail(int code, const std::string& msg) {
       return fail(CKC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));         \
   } while (0)
 
-struct Program {
-  void* dblob = nullptr;
-  Loaded L;
-  int busy = 0;
-};
-
-struct Table {
-  void* dptr = nullptr;
-  std::vector<ckc_alloc> host;
-  int busy = 0;
-};
-
-struct Job {
-  hipStream_t stream = nullptr;
-  std::vector<std::pair<size_t, void*>> bufs;  // (bytes, device pointer)
-  dinput* d_inputs = nullptr;
-  ckc_record* d_recs = nullptr;
-  uint32_t* d_counts = nullptr;
-  ckc_input_status* d_status = nullptr;
-  uint8_t* d_maps = nullptr;
-  uint64_t n_inputs = 0, n_records = 0;
-  std::vector<uint32_t> progs, tables;
-  hipEvent_t ev[5] = {};
-  bool dense = false;
-};
-
 }  // namespace
-
-struct ckc_ctx_s {
-  int dev = 0;
-  hipStream_t stream = nullptr;
-  uint32_t next_prog = 1, next_table = 1;
-  uint64_t next_job = 1;
-  std::map<uint32_t, Program> progs;
-  std::map<uint32_t, Table> tables;
-  std::map<uint64_t, Job> jobs;
-  int n_cu = 256;
-  // device buffers of finished jobs, reused by later jobs of similar size
-  std::multimap<size_t, void*> pool;
-  size_t pool_bytes = 0;
-};
 
 namespace {
 
@@ -140,7 +107,82 @@ unsigned bits_of(uint64_t n) {  // bits needed for values 0..n-1
   return b;
 }
 
+
+// Launches the job's kernels as one graph; the executable graph is cached by
+// its launch parameters and reused when a later job has the same ones.
+hipError_t launch_graph(ckc_ctx c, const KArgs& a, const EvalGrid& eg, uint64_t n_records, hipStream_t s) {
+  std::string key((const char*)&a, sizeof a);
+  key.append((const char*)&eg, sizeof eg);
+  key.append((const char*)&n_records, sizeof n_records);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    e = build_job_graph(g, a, eg, n_records);
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    if (c->graphs.size() >= 32) {  // keep the cache small
+      hipGraphExecDestroy(c->graphs.begin()->second);
+      c->graphs.erase(c->graphs.begin());
+    }
+    it = c->graphs.emplace(key, x).first;
+  }
+  return hipGraphLaunch(it->second, s);
+}
+
 }  // namespace
+
+int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force_generic, uint64_t* ws_bytes) {
+  const std::string dk = "descriptor " + std::to_string(k) + ": ";
+  auto pit = c->progs.find(B.prog_id);
+  if (pit == c->progs.end()) return fail(CKC_E_INVALID, dk + "unknown program");
+  if (B.n_inputs && (!B.launch || !B.table_ids)) return fail(CKC_E_INVALID, dk + "arrays missing");
+  const Program& P = pit->second;
+  const dprog* h = (const dprog*)P.L.blob.data();
+  if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, dk + "scalars missing");
+  if (B.mode > CKC_REP_BOUNDARY) return fail(CKC_E_INVALID, dk + "unknown mode");
+  uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
+  if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
+  if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, dk + "loop cap above 2^32");
+  unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
+  uint64_t ws = 0;
+  for (uint32_t i = 0; i < B.n_inputs; i++) {
+    const std::string di = dk + "input " + std::to_string(i) + ": ";
+    const uint32_t* L = B.launch + 6 * (size_t)i;
+    uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
+    if (bs > 1024) return fail(CKC_E_INVALID, di + "block above 1024 threads");
+    if (nb > 0xFFFFFFFFull) return fail(CKC_E_INVALID, di + "grid of 2^32 blocks or more");
+    uint64_t nthr = nb * bs;
+    if (nthr > 1 && bits_of(nthr) + L1 + L2 > 64)
+      return fail(CKC_E_RANGE, di + "first-violation key needs more than 64 bits");
+    auto tit = c->tables.find(B.table_ids[i]);
+    if (tit == c->tables.end()) return fail(CKC_E_INVALID, di + "unknown table");
+    const Table& T = tit->second;
+    if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, di + "table has fewer slots than the program");
+    for (uint32_t s = 0; s < h->n_slots; s++) {
+      const ckc_alloc& A = T.host[s];
+      const bool live = A.base != 0 && !(A.flags & CKC_ALLOC_FREED) && A.size_bytes > 0;
+      if ((P.L.load_slots >> s & 1u) && live) {
+        if (A.data == nullptr) return fail(CKC_E_INVALID, di + "slot " + std::to_string(s) + " is loaded but has no data");
+        ws += A.size_bytes;
+      }
+    }
+    ws += sizeof(dinput) + 8 * MAX_SCALARS + 4 + sizeof(ckc_input_status) + (uint64_t)h->n_accesses * sizeof(ckc_record) +
+          (uint64_t)h->n_sites * 4;
+    if ((h->cls & CKC_CLS_UNIFORM) && !force_generic) ws += ckc::trace_bytes(h->trace_cap);
+    if (B.flags & CKC_DENSE_MAP) ws += 65536;
+  }
+  if (ws_bytes) *ws_bytes = ws;
+  return CKC_OK;
+}
+
+hipEvent_t ckc::rt::job_done_event(ckc_ctx c, uint64_t job) {
+  auto it = c->jobs.find(job);
+  return it == c->jobs.end() ? nullptr : it->second.ev[4];
+}
 
 extern "C" {
 
@@ -177,6 +219,7 @@ void ckc_shutdown(ckc_ctx c) {
   for (auto& kv : c->progs) hipFree(kv.second.dblob);
   for (auto& kv : c->tables) hipFree(kv.second.dptr);
   for (auto& kv : c->pool) hipFree(kv.second);
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -264,43 +307,27 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   ckc_launch_opts O;
   std::memset(&O, 0, sizeof O);
   if (opts) O = *opts;
+  if (O.schedule > CKC_SCHED_LPT) return fail(CKC_E_INVALID, "unknown schedule");
+  if (O.chunk > 256) return fail(CKC_E_INVALID, "chunk above 256 tiles");
+  if (O.wg_per_cu > 32) return fail(CKC_E_INVALID, "wg_per_cu above 32");
   // ---- validate and build the input list on the host (copies only) ----
   std::vector<dinput> hin;
   std::vector<int64_t> hsc;
+  std::vector<uint64_t> est;  // estimated work per input (LPT order)
   uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
-  uint32_t max_regs = 1;  // interpreter register file rows (LDS)
   for (uint32_t k = 0; k < n_descs; k++) {
     const ckc_batch& B = descs[k];
-    auto pit = c->progs.find(B.prog_id);
-    if (pit == c->progs.end()) return fail(CKC_E_INVALID, "descriptor " + std::to_string(k) + ": unknown program");
-    if (B.n_inputs && (!B.launch || !B.table_ids)) return fail(CKC_E_INVALID, "descriptor arrays missing");
-    const Program& P = pit->second;
+    int vr = ckc::rt::validate_desc(c, B, k, O.force_generic != 0, nullptr);
+    if (vr != CKC_OK) return vr;
+    const Program& P = c->progs.find(B.prog_id)->second;
     const dprog* h = (const dprog*)P.L.blob.data();
-    if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, "scalars missing");
-    if (B.mode > CKC_REP_BOUNDARY) return fail(CKC_E_INVALID, "unknown mode");
     uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
     if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
-    if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, "loop cap above 2^32");
     unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
-    max_regs = std::max(max_regs, h->n_regs);
     for (uint32_t i = 0; i < B.n_inputs; i++) {
       const uint32_t* L = B.launch + 6 * (size_t)i;
-      uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
-      if (bs > 1024) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": block above 1024 threads");
-      if (nb > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": grid of 2^32 blocks or more");
-      uint64_t nthr = nb * bs;
-      if (nthr > 1 && bits_of(nthr) + L1 + L2 > 64)
-        return fail(CKC_E_RANGE, "input " + std::to_string(i) + ": first-violation key needs more than 64 bits");
-      auto tit = c->tables.find(B.table_ids[i]);
-      if (tit == c->tables.end()) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": unknown table");
-      const Table& T = tit->second;
-      if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": table has fewer slots than the program");
-      for (uint32_t s = 0; s < h->n_slots; s++) {
-        const ckc_alloc& A = T.host[s];
-        if ((P.L.load_slots >> s & 1u) && A.base != 0 && !(A.flags & CKC_ALLOC_FREED) && A.size_bytes > 0 &&
-            A.data == nullptr)
-          return fail(CKC_E_INVALID, "input " + std::to_string(i) + ": slot " + std::to_string(s) + " is loaded but has no data");
-      }
+      const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
+      const Table& T = c->tables.find(B.table_ids[i])->second;
       dinput d;
       std::memset(&d, 0, sizeof d);
       d.prog = (uint64_t)(uintptr_t)P.dblob;
@@ -320,6 +347,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
         trace_bytes += ckc::trace_bytes(h->trace_cap);
       }
       hin.push_back(d);
+      est.push_back(nthr * (1 + h->n_accesses));
       for (uint32_t s = 0; s < MAX_SCALARS; s++)
         hsc.push_back(s < h->n_scalars ? B.scalars[(size_t)i * h->n_scalars + s] : 0);
       n_inputs++;
@@ -338,7 +366,14 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   int64_t* d_sc = nullptr;
   jobstate* d_js = nullptr;
   uint8_t* d_tr = nullptr;
+  uint32_t* d_order = nullptr;
+  // tile-space order of the inputs: as given, or largest first for LPT
+  std::vector<uint32_t> order(n_inputs);
+  for (uint64_t i = 0; i < n_inputs; i++) order[i] = (uint32_t)i;
+  if (O.schedule == CKC_SCHED_LPT)
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return est[x] > est[y]; });
   if ((rc = dalloc(c, J, &J.d_inputs, n_inputs)) || (rc = dalloc(c, J, &d_sc, hsc.size())) ||
+      (rc = dalloc(c, J, &d_order, n_inputs)) ||
       (rc = dalloc(c, J, &J.d_recs, n_records)) || (rc = dalloc(c, J, &J.d_counts, n_counts)) ||
       (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &d_js, 1)) ||
       (rc = dalloc(c, J, &d_tr, trace_bytes)) ||
@@ -355,6 +390,8 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   };
   hipError_t e = hipMemcpyAsync(J.d_inputs, hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, J.stream);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sc, hsc.data(), sizeof(int64_t) * hsc.size(), hipMemcpyHostToDevice, J.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_order, order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, J.stream);
   for (int q = 0; q < 5 && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e)));
   KArgs a;
@@ -367,19 +404,32 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   a.status = J.d_status;
   a.maps = J.d_maps;
   a.js = d_js;
-  uint32_t wg_trace = O.n_wg ? O.n_wg : (uint32_t)c->n_cu * 8;
-  uint32_t wg_gen = O.n_wg ? O.n_wg : (uint32_t)c->n_cu * 2;
+  a.order = d_order;
+  a.sched = CKC_SCHED_DYNAMIC;
+  a.chunk = O.chunk ? O.chunk : 1u;
+  EvalGrid eg;
+  const uint32_t defwg[3] = {8, 2, 2};  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES
+  for (int p = 0; p < 3; p++) {
+    eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
+    eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);
+  }
+  J.graph = O.use_graph != 0;
   e = hipEventRecord(J.ev[0], J.stream);
-  if (e == hipSuccess) e = launch_plan(a, J.stream);
-  if (e == hipSuccess) e = launch_scan(a, J.stream);
-  if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
-  if (e == hipSuccess) e = launch_eval_trace(a, wg_trace, J.stream);
-  if (e == hipSuccess) e = launch_eval_trace_lanes(a, wg_gen, J.stream);
-  if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
-  if (e == hipSuccess) e = launch_eval_generic(a, wg_gen, max_regs, J.stream);
-  if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
-  if (e == hipSuccess) e = launch_fixup(a, n_records, max_regs, J.stream);
-  if (e == hipSuccess) e = launch_finish(a, J.stream);
+  if (J.graph) {
+    if (e == hipSuccess) e = launch_graph(c, a, eg, n_records, J.stream);
+    for (int q = 1; q < 4 && e == hipSuccess; q++) e = hipEventRecord(J.ev[q], J.stream);
+  } else {
+    if (e == hipSuccess) e = launch_plan(a, J.stream);
+    if (e == hipSuccess) e = launch_scan(a, J.stream);
+    if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
+    if (e == hipSuccess) e = launch_eval_trace(a, eg, J.stream);
+    if (e == hipSuccess) e = launch_eval_trace_lanes(a, eg, J.stream);
+    if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
+    if (e == hipSuccess) e = launch_eval_generic(a, eg, J.stream);
+    if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
+    if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
+    if (e == hipSuccess) e = launch_finish(a, J.stream);
+  }
   if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));
   for (uint32_t k = 0; k < n_descs; k++) {
@@ -412,10 +462,25 @@ int ckc_job_timing(ckc_ctx c, uint64_t job, float* ms4) {
   Job& J = it->second;
   set_device(c);
   HIPCHECK(hipEventSynchronize(J.ev[4]));
+  if (J.graph) {
+    for (int q = 0; q < 4; q++) ms4[q] = -1.0f;
+    return CKC_OK;
+  }
   HIPCHECK(hipEventElapsedTime(&ms4[0], J.ev[0], J.ev[1]));
   HIPCHECK(hipEventElapsedTime(&ms4[1], J.ev[1], J.ev[2]));
   HIPCHECK(hipEventElapsedTime(&ms4[2], J.ev[2], J.ev[3]));
   HIPCHECK(hipEventElapsedTime(&ms4[3], J.ev[3], J.ev[4]));
+  return CKC_OK;
+}
+
+int ckc_job_elapsed(ckc_ctx c, uint64_t job, float* ms) {
+  if (!c || !ms) return fail(CKC_E_INVALID, "NULL argument");
+  auto it = c->jobs.find(job);
+  if (it == c->jobs.end()) return fail(CKC_E_INVALID, "unknown job");
+  Job& J = it->second;
+  set_device(c);
+  HIPCHECK(hipEventSynchronize(J.ev[4]));
+  HIPCHECK(hipEventElapsedTime(ms, J.ev[0], J.ev[4]));
   return CKC_OK;
 }
 
@@ -442,6 +507,55 @@ int ckc_read_results(ckc_ctx c, uint64_t job, ckc_record* recs, uint8_t* maps, c
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("readback: ") + hipGetErrorString(e));
   free_job(c, J);
   c->jobs.erase(it);
+  return CKC_OK;
+}
+
+int ckc_autotune(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts* base,
+                 uint32_t reps, ckc_launch_opts* best, ckc_tune_entry* log, uint32_t log_cap,
+                 uint32_t* n_log) {
+  if (!c || !descs || !best || n_descs == 0) return fail(CKC_E_INVALID, "NULL argument or no descriptor");
+  ckc_launch_opts B;
+  std::memset(&B, 0, sizeof B);
+  if (base) B = *base;
+  if (reps == 0) reps = 1;
+  const uint32_t scheds[4] = {CKC_SCHED_BLOCKED, CKC_SCHED_CYCLIC, CKC_SCHED_DYNAMIC, CKC_SCHED_LPT};
+  const uint32_t chunks[3] = {1, 4, 16};
+  const uint32_t wgs[5] = {0, 2, 4, 8, 16};
+  float best_ms = -1.0f;
+  uint32_t n = 0;
+  for (uint32_t sc : scheds)
+    for (uint32_t ch : chunks) {
+      if (sc == CKC_SCHED_BLOCKED && ch != 1) continue;  // one range per workgroup: chunk unused
+      for (uint32_t wg : wgs) {
+        ckc_launch_opts O = B;
+        O.schedule = sc;
+        O.chunk = ch;
+        O.wg_per_cu = wg;
+        float t_min = -1.0f;
+        for (uint32_t r = 0; r < reps; r++) {
+          uint64_t job = 0;
+          int rc = ckc_check_batch(c, descs, n_descs, &O, &job);
+          if (rc != CKC_OK) return rc;
+          float ms = 0;
+          rc = ckc_job_elapsed(c, job, &ms);
+          int rc2 = ckc_read_results(c, job, nullptr, nullptr, nullptr, CKC_WAIT);
+          if (rc != CKC_OK) return rc;
+          if (rc2 != CKC_OK) return rc2;
+          if (t_min < 0 || ms < t_min) t_min = ms;
+        }
+        if (log && n < log_cap) {
+          log[n].opts = O;
+          log[n].ms = t_min;
+          log[n].pad = 0;
+        }
+        n++;
+        if (best_ms < 0 || t_min < best_ms) {
+          best_ms = t_min;
+          *best = O;
+        }
+      }
+    }
+  if (n_log) *n_log = n < log_cap ? n : log_cap;
   return CKC_OK;
 }
 

@@ -390,3 +390,91 @@ def config4(seed: int = 1004, n_kernels: int = 10000, t_max: int = 65536) -> Mix
         else:
             ks.append(_f3_kernel(int(seeds[k]), t, w))
     return MixedBatch("config4_mixed", ks, meta=dict(seed=seed, T=T, family=fam, width=wid))
+
+
+# ---------------------------------------------------------------------------
+# served stream (open-loop arrivals of check jobs)
+# ---------------------------------------------------------------------------
+ACCESSES_PER_THREAD = {"F1": 4, "F2": 10, "F3": 51}  # F3: per row, 3 + 3 x mean 16 nonzeros
+
+
+@dataclass
+class ServedStream:
+    """Jobs with arrival times.  ``jobs[k]`` is a one-input Workload whose
+    data references (``tables["data"]``) index ``pool`` (1-based), the
+    resident CSR arrays shared by every F3 job."""
+    name: str
+    arrivals: np.ndarray   # seconds from the start, increasing
+    jobs: list
+    pool: list
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_jobs(self) -> int:
+        return len(self.jobs)
+
+
+def csr_pool(seed: int, log2_range=(4, 18), frac: float = 0.001):
+    """Pre-corrupted CSR matrices with 2^k rows (= columns) for k in
+    log2_range; returns (data list [row_ptr_k, col_k, ...], {k: (ref of
+    row_ptr, ref of col, nrows, nnz)}) with 1-based references."""
+    data, index = [], {}
+    for k in range(log2_range[0], log2_range[1] + 1):
+        n = 1 << k
+        rng, row_ptr, col = csr_structure(seed + k, n, n, 16)
+        col = corrupt_copy(rng, col, n, frac)
+        data += [row_ptr, col]
+        index[k] = (len(data) - 1, len(data), n, int(row_ptr[-1]))
+    return data, index
+
+
+def config5(seed: int = 1005, rate: float = 2000.0, duration_s: float = 35.0, a_range=(1e3, 1e7),
+            log2_range=(4, 18), dense: bool = True) -> ServedStream:
+    """Served stream: Poisson arrivals at ``rate`` jobs/s over ``duration_s``
+    seconds (exponential gaps); size A = exp(U[ln a_min, ln a_max]) thread-
+    accesses; family ~ U{F1, F2, F3}, width ~ U{32, 64}; T = ceil(A / a_f)
+    threads (a_f = 4, 10, 51).  F1 and F2 shapes as in the batched mix.  F3
+    jobs take the pool matrix of 2^k rows with k = round(log2 T) clamped to
+    log2_range, and an x vector of ncols + U{-64..64} elements."""
+    rng = np.random.default_rng(seed)
+    n = int(rate * duration_s * 1.2) + 16
+    gaps = rng.exponential(1.0 / rate, size=n)
+    arr = np.cumsum(gaps)
+    arr = arr[arr < duration_s]
+    n = arr.size
+    fam = rng.integers(0, 3, size=n)
+    wid = np.where(rng.integers(0, 2, size=n) == 1, 64, 32)
+    A = np.exp(rng.uniform(np.log(a_range[0]), np.log(a_range[1]), size=n))
+    seeds = rng.integers(0, 2**62, size=n)
+    pool, index = csr_pool(seed, log2_range)
+    jobs = []
+    for j in range(n):
+        sub = np.random.default_rng(int(seeds[j]))
+        w = int(wid[j])
+        if fam[j] == 0:
+            T = int(np.ceil(A[j] / ACCESSES_PER_THREAD["F1"]))
+            k = _f1_kernel(sub, T, w)
+        elif fam[j] == 1:
+            T = int(np.ceil(A[j] / ACCESSES_PER_THREAD["F2"]))
+            k = _f2_kernel(sub, T, w)
+        else:
+            T = int(np.ceil(A[j] / ACCESSES_PER_THREAD["F3"]))
+            lg = int(min(max(round(np.log2(max(T, 1))), log2_range[0]), log2_range[1]))
+            r_rp, r_col, nr, nnz = index[lg]
+            xs = nr + int(sub.integers(-64, 65))
+            extra = I64_BASE if w == 64 else 0
+            bs = min(256, nr)
+            launch = np.array([[-(-nr // bs), 1, 1, bs, 1, 1]], np.uint32)
+            scalars = np.array([[nr] + ([extra] if w == 64 else [])], np.int64)
+            tables = np.array([[alloc((nr + 1) * 4, r_rp, LOGICAL_BASE),
+                                alloc(nnz * 4, r_col, LOGICAL_BASE + (1 << 36)),
+                                alloc((nnz + extra) * 4, 0, LOGICAL_BASE + (2 << 36)),
+                                alloc((max(xs, 0) + extra) * 4, 0, LOGICAL_BASE + (3 << 36)),
+                                alloc((nr + extra) * 4, 0, LOGICAL_BASE + (4 << 36))]], ALLOC_DTYPE)
+            k = Workload(f"f3_i{w}", f3_program(w), launch, scalars, tables, np.zeros(1, np.uint32),
+                         [], MODE_FULL, meta=dict(family="F3", T=nr, nnz=nnz, x=xs, log2_rows=lg))
+        k.meta["A"] = float(A[j])
+        jobs.append(k)
+    return ServedStream("config5_served", arr, jobs, pool,
+                        meta=dict(seed=seed, rate=rate, duration_s=duration_s, family=fam, width=wid, A=A,
+                                  dense=dense))
