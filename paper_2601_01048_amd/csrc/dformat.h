@@ -76,8 +76,16 @@ struct dinput {
   uint32_t cap_log2[2];
   uint32_t path;          // evaluator, set by planning: PATH_BLOCKS, PATH_GENERIC, PATH_LANES
   uint32_t n_tiles[3];
-  uint32_t pad[2];
+  uint32_t pad;
+  // expanded loop (interpreter path): per-thread state arrays and this
+  // input's range of expanded tiles
+  uint64_t xstate;        // device address of xn x (3 + n_livein) uint64: trip-count
+                          // prefix within the tile, start, step, live-ins (0 = none)
+  uint64_t xt_begin;      // first expanded tile of this input
+  uint64_t xn;            // entries per state array (tiles x TILE, >= lanes)
+  uint64_t n_xt;          // expanded tiles reserved for this input
 };
+static_assert(sizeof(dinput) == 168, "dinput layout");
 // Evaluators of an input: the trace evaluator in block-major wavefront jobs,
 // the general interpreter, or the trace evaluator over lane tiles.
 enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };

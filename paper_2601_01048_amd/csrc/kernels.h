@@ -13,6 +13,8 @@ constexpr int TILE = 256;  // lanes per tile = threads per evaluation workgroup
 struct jobstate {
   unsigned long long total_tiles[3];  // tile space of each evaluator (dinput.path)
   unsigned long long next_tile[3];    // dynamic schedule counters
+  unsigned long long total_pieces;    // work items of the expanded-loop body pass
+  unsigned long long next_piece;
 };
 
 struct KArgs {
@@ -28,7 +30,18 @@ struct KArgs {
   const uint32_t* order;    // [n_inputs]: tile-space position -> input index
   uint32_t sched;           // ckc_schedule of the evaluator being launched (set per launch)
   uint32_t chunk;           // tiles per work item
+  // expanded loops: per expanded tile the trip-count total, the piece count
+  // (scanned in place into the first piece), the input; block sums of the scan
+  unsigned long long* xtot;
+  unsigned long long* xpb;
+  uint32_t* xin;
+  unsigned long long* xbsum;
+  uint64_t n_xtiles;
+  uint32_t max_regs;        // interpreter registers (LDS rows of TILE lanes) of the job's programs
+  uint32_t pad;
 };
+// LDS bytes of the interpreter's register file for a job.
+inline uint32_t regfile_bytes(const KArgs& a) { return (a.max_regs ? a.max_regs : 1u) * TILE * 8u; }
 
 // Workgroups and schedule of each evaluator (index PATH_*).
 struct EvalGrid {
@@ -42,6 +55,9 @@ hipError_t launch_eval_trace(const KArgs& a, const EvalGrid& eg, hipStream_t s);
 hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream_t s);
 hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s);
 hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s);
+// Body pass of expanded loops: scan of the piece counts, then the pass itself
+// (nothing is launched when the job has no expanded tiles).
+hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s);
 hipError_t launch_finish(const KArgs& a, hipStream_t s);
 // The whole job as one graph: plan -> scan -> the three evaluators (parallel
 // branches) -> first-violation replay -> finishing.

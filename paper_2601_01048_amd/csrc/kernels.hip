@@ -557,6 +557,11 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
   }
   uint32_t* cnt = a.counts + in.cnt_base;
   for (uint32_t s = j; s < P->n_sites; s += 64) cnt[s] = 0;
+  if (in.xstate)  // expanded tiles start with no iterations
+    for (uint64_t q = j; q < in.n_xt; q += 64) {
+      a.xtot[in.xt_begin + q] = 0;
+      a.xpb[in.xt_begin + q] = 0;
+    }
   uint64_t lanes = set_lanes(in.mode, in.launch);
   bool trace = (P->cls & CKC_CLS_UNIFORM) && !a.force_generic && in.trace != 0 && lanes > 0;
   __syncthreads();
@@ -1217,16 +1222,15 @@ __device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
 struct GenLds {
   ckc_alloc tab[MAX_SLOTS];
   uint32_t sites[MAX_SITES_LDS];
-  // expanded loop: one entry per lane of the workgroup
-  unsigned long long x_pref[TILE + 1];
-  uint64_t x_start[TILE], x_step[TILE], x_gtid[TILE];
-  uint64_t x_live[MAX_LIVEIN][TILE];
   unsigned long long wsum[TILE / 64];
   unsigned long long acc_checked, hangs, faults;
-  uint64_t tile;
+  unsigned long long pref[TILE + 1];  // trip-count prefix of the tile's threads (expanded loop)
 };
 
-enum { M_MAIN = 0, M_FIX = 1 };
+// Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
+// only recorded), M_BODY runs one iteration of the expanded loop's body per
+// lane, M_FIX replays one thread (lane 0) up to a target access.
+enum { M_MAIN = 0, M_FIX = 1, M_BODY = 2 };
 
 struct Lane {
   uint32_t dis;            // 0 = active; >0 disabled depth; >= DEAD stopped
@@ -1250,6 +1254,13 @@ struct Ctx {
   uint32_t Lsum, L2;
   uint64_t cap0, cap1;
   uint32_t t0, t1, t2, b0, b1, b2;  // thread coordinates (this lane)
+  // expanded loop: this input's thread-state arrays (pref, start, step,
+  // live-ins; xn entries each), the tile's first lane and expanded tile
+  uint64_t* xs;
+  uint64_t xn, lane0, xt;
+  unsigned long long *xtot, *xpb;
+  uint32_t* xin;
+  uint32_t input;
   // fix-up target
   uint32_t tacc;
   uint64_t tk0, tk1;
@@ -1269,35 +1280,34 @@ __device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint32_t s, 
   }
 }
 
-// Register file: two uint32_t[NREG] arrays per lane, indexed only by
-// wavefront-uniform register numbers (VGPR indexing, no scratch).  Reads happen
-// before the opcode switch and the single result write after it, so the arrays
-// never flow through the switch's control-flow joins.
-#define RGET(i) (((uint64_t)hi[(i)] << 32) | lo[(i)])
-#define RPUT(i, v)                  \
-  do {                              \
-    const uint64_t _v = (v);        \
-    lo[(i)] = (uint32_t)_v;         \
-    hi[(i)] = (uint32_t)(_v >> 32); \
-  } while (0)
+// Register file in LDS (dynamic shared memory): register r of lane t is
+// R[r * TILE + t], 64 bits, addressed by wavefront-uniform register numbers.
+#define RGET(i) R[(uint32_t)(i) * TILE + threadIdx.x]
+#define RPUT(i, v) (R[(uint32_t)(i) * TILE + threadIdx.x] = (v))
 
-// Runs the program for the wavefront.  MODE M_MAIN checks, counts and records;
-// M_FIX replays one thread (lane 0) towards the target access and stops there.
+// Iterations of an expanded loop per work item of the body pass.
+constexpr uint32_t PIECE = 2048;
+
+// Runs the program for the wavefront from pc0 until pc_end (exclusive) or the
+// end.  M_MAIN: whole threads; at the expanded loop each lane's trip count,
+// start, step and live-ins are stored with the tile's prefix of trip counts
+// and the loop is left at once (its iterations run in the body pass).  M_BODY:
+// registers hold the live-ins and the counter of iteration ln.k0; runs the body.
+// M_FIX: replays lane 0 towards the target access and stops there.
 template <int MODE>
-__device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
-  uint32_t lo[NREG], hi[NREG];
-#pragma unroll
-  for (int q = 0; q < NREG; q++) { lo[q] = 0; hi[q] = 0; }
-  // state of the expanded loop (one lane per iteration across the workgroup)
-  bool in_x = false;
-  uint64_t x_base = 0, x_total = 0;
-  uint32_t x_lpc = 0, x_own_dis = 0, x_hang = 0, x_act = 0, x_nlive = 0;
-  uint64_t x_own_gtid = 0;
+__device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t pc0, uint32_t pc_end) {
   c_dprog* P = C.P;
   c_dins* I = C.I;
-  const uint32_t n_instr = P->n_instr;
-  uint32_t pc = 0;
-  while (pc < n_instr) {
+  if (MODE == M_BODY) {
+    // live-ins of the owner thread, counter of this iteration
+    const uint64_t l = C.lane0;  // lane index of the owner (set per lane)
+    const uint32_t nl = P->n_livein;
+    for (uint32_t q = 0; q < nl; q++) RPUT(ufirst(P->livein[q]), C.xs[(3 + q) * C.xn + l]);
+    const dins L = ld_ins(I, pc0 - 1);
+    RPUT(ufirst(L.dst), narrow(C.xs[C.xn + l] + ln.k0 * C.xs[2 * C.xn + l], L.w));
+  }
+  uint32_t pc = pc0;
+  while (pc < pc_end) {
     const dins D = ld_ins(I, pc);
     const uint32_t op = D.op, w = D.w;
     const uint32_t da = ufirst(D.a), db = ufirst(D.b), dc = ufirst(D.c), dd = ufirst(D.dst);
@@ -1305,7 +1315,6 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
     const bool act = ln.dis == 0;
     uint64_t r = 0;
     uint32_t wreg = 0xFFu;   // register written after the switch
-    uint32_t chunk = 0;      // 1: set up a chunk of the expanded loop; 2: leave it
     uint32_t npc = pc + 1;
     switch (op) {
       case CKC_OP_CONST: r = narrow((uint64_t)C.K[D.x], w); wreg = dd; break;
@@ -1335,7 +1344,7 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
         const int64_t idx = (int64_t)narrow(va, w);
         const ckc_alloc& A = S.tab[slot];
         const uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
-        if (MODE == M_MAIN) {
+        if (MODE != M_FIX) {
           const uint64_t am = __ballot(act);
           if (lane_id() == 0 && am) atomicAdd(&S.acc_checked, (unsigned long long)__popcll(am));
           count_site(S, C, D.s0, am);
@@ -1358,7 +1367,7 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
       }
       case CKC_OP_IF: {
         const bool p = va != 0;
-        if (MODE == M_MAIN) {
+        if (MODE != M_FIX) {
           count_site(S, C, D.s0, __ballot(act && p));
           count_site(S, C, D.s1, __ballot(act && !p));
         }
@@ -1387,16 +1396,12 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
         const uint64_t cap = d == 0 ? C.cap0 : C.cap1;
         const uint64_t rn = nt < cap ? nt : cap;
         const bool hg = act && nt > cap;
-        if (fl & DI_EXPAND) {
-          // every wavefront of the workgroup arrives here exactly once per tile
+        if (MODE == M_MAIN && (fl & DI_EXPAND) && C.xs != nullptr) {
+          // every wavefront of the workgroup arrives here exactly once per tile:
+          // prefix of the trip counts over the tile, thread state to memory
           const uint32_t tid = threadIdx.x;
-          x_nlive = P->n_livein;
-          S.x_start[tid] = (uint64_t)s0;
-          S.x_step[tid] = (uint64_t)stp;
-          S.x_gtid[tid] = ln.gtid;
-          for (uint32_t q = 0; q < x_nlive; q++) S.x_live[q][tid] = RGET(ufirst(P->livein[q]));
-          const uint64_t v = act ? rn : 0;
-          uint64_t incl = v;
+          const uint64_t cnt = act ? rn : 0;
+          uint64_t incl = cnt;
           for (int o = 1; o < 64; o <<= 1) {
             const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
             if ((int)lane_id() >= o) incl += u;
@@ -1405,19 +1410,27 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
           __syncthreads();
           uint64_t wpre = 0;
           for (uint32_t q = 0; q < tid / 64; q++) wpre += S.wsum[q];
-          S.x_pref[tid] = wpre + incl - v;
-          if (tid == TILE - 1) S.x_pref[TILE] = wpre + incl;
+          const uint64_t pre = wpre + incl - cnt;
+          const uint64_t l = C.lane0 + tid;
+          C.xs[l] = pre;
+          if (cnt) {
+            C.xs[C.xn + l] = (uint64_t)s0;
+            C.xs[2 * C.xn + l] = (uint64_t)stp;
+            const uint32_t nl = P->n_livein;
+            for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = RGET(ufirst(P->livein[q]));
+          }
+          if (tid == TILE - 1) {
+            const uint64_t tot = pre + cnt;
+            C.xtot[C.xt] = tot;
+            C.xpb[C.xt] = (tot + PIECE - 1) / PIECE;
+            C.xin[C.xt] = C.input;
+          }
           __syncthreads();
-          x_total = S.x_pref[TILE];
-          x_base = 0;
-          x_lpc = pc;
-          x_own_dis = ln.dis;
-          x_own_gtid = ln.gtid;
-          x_hang = hg;
-          x_act = act;
-          in_x = true;
-          if (x_total == 0) { chunk = 2; break; }  // nothing to run: leave at once
-          chunk = 1;
+          // the loop is left at once: lanes that run it to the end pass its
+          // exit, lanes over the cap stop
+          count_site(S, C, D.s1, __ballot(act && !hg));
+          if (hg) { ln.dis = DEAD; ln.hangs++; }
+          npc = endpc + 1;
           break;
         }
         if (d == 0) { ln.run0 = rn; ln.st0 = (uint64_t)s0; ln.sp0 = (uint64_t)stp; ln.k0 = 0; }
@@ -1427,17 +1440,12 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
         if (__ballot(ln.dis == 0) == 0) { npc = endpc; break; }  // ENDLOOP: exit handling
         r = narrow((uint64_t)s0, w);
         wreg = dd;
-        if (MODE == M_MAIN) count_site(S, C, D.s0, __ballot(ln.dis == 0));
+        count_site(S, C, D.s0, __ballot(ln.dis == 0));
         break;
       }
       case CKC_OP_ENDLOOP: {
         if (MODE == M_FIX) return;  // target not reached in this iteration
         const uint32_t d = D.x, lpc = D.jmp;
-        if (in_x && lpc == x_lpc) {
-          x_base += TILE;
-          chunk = x_base < x_total ? 1u : 2u;
-          break;
-        }
         const dins Lp = ld_ins(I, lpc);
         if (ln.dis == 0) {
           const uint64_t kk = (d == 0 ? ln.k0 : ln.k1) + 1;
@@ -1450,14 +1458,14 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
           wreg = ufirst(Lp.dst);
           // lanes that left the loop keep their value
           r = ln.dis == 0 ? narrow(sa + kk * sp, Lp.w) : RGET(wreg);
-          if (MODE == M_MAIN) count_site(S, C, Lp.s0, __ballot(ln.dis == 0));
+          count_site(S, C, Lp.s0, __ballot(ln.dis == 0));
           npc = lpc + 1;
           break;
         }
         // exit: lanes that ran this loop leave it; a capped loop stops its lane
         const bool mine = ln.dis == 1;
         const bool hg = mine && ((ln.hangp >> d) & 1u);
-        if (MODE == M_MAIN) count_site(S, C, Lp.s1, __ballot(mine && !hg));
+        count_site(S, C, Lp.s1, __ballot(mine && !hg));
         if (mine) {
           if (hg) { ln.dis = DEAD; ln.hangs++; }
           else ln.dis = 0;
@@ -1476,44 +1484,6 @@ __device__ void run_program(GenLds& S, Ctx& C, Lane& ln) {
       }
     }
     if (wreg != 0xFFu) RPUT(wreg, r);
-    if (MODE == M_MAIN && chunk == 1) {
-      // next chunk of the expanded loop: every lane takes one iteration of some
-      // thread of the workgroup (owner o, last o with pref[o] <= g)
-      const dins L = ld_ins(I, x_lpc);
-      const uint32_t tid = threadIdx.x;
-      const uint64_t g = x_base + tid;
-      const bool ga = g < x_total;
-      uint32_t o = 0;
-      if (ga) {
-        uint32_t l2 = 0, h2 = TILE - 1;
-        while (l2 < h2) {
-          const uint32_t m = (l2 + h2 + 1) >> 1;
-          if (S.x_pref[m] <= g) l2 = m; else h2 = m - 1;
-        }
-        o = l2;
-      }
-      const uint64_t kk = ga ? g - S.x_pref[o] : 0;
-      for (uint32_t q = 0; q < x_nlive; q++) RPUT(ufirst(P->livein[q]), S.x_live[q][o]);
-      RPUT(ufirst(L.dst), narrow(S.x_start[o] + kk * S.x_step[o], L.w));
-      ln.dis = ga ? 0u : 1u;
-      ln.gtid = S.x_gtid[o];
-      ln.k0 = kk;
-      ln.k1 = 0;
-      count_site(S, C, L.s0, __ballot(ga));
-      npc = x_lpc + 1;
-    } else if (MODE == M_MAIN && chunk == 2) {
-      // expansion done: back to this lane's own thread
-      in_x = false;
-      for (uint32_t q = 0; q < x_nlive; q++) RPUT(ufirst(P->livein[q]), S.x_live[q][threadIdx.x]);
-      ln.gtid = x_own_gtid;
-      ln.k0 = 0;
-      ln.k1 = 0;
-      ln.dis = x_own_dis;
-      if (x_hang) { ln.dis = DEAD; ln.hangs++; }
-      count_site(S, C, ld_ins(I, x_lpc).s1, __ballot(x_act && !x_hang));
-      __syncthreads();
-      npc = ld_ins(I, x_lpc).jmp + 1;
-    }
     pc = npc;
   }
 }
@@ -1553,6 +1523,14 @@ __device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, const dinput& i
   C.cap0 = 1ull << in.cap_log2[0];
   C.cap1 = 1ull << in.cap_log2[1];
   C.t0 = T.t[0]; C.t1 = T.t[1]; C.t2 = T.t[2]; C.b0 = T.b[0]; C.b1 = T.b[1]; C.b2 = T.b[2];
+  C.xs = (uint64_t*)in.xstate;
+  C.xn = in.xn;
+  C.xtot = a.xtot;
+  C.xpb = a.xpb;
+  C.xin = a.xin;
+  C.input = i;
+  C.lane0 = 0;
+  C.xt = 0;
 }
 
 __device__ __forceinline__ void lane_init(Lane& ln, bool act, uint64_t gtid) {
@@ -1564,9 +1542,19 @@ __device__ __forceinline__ void lane_init(Lane& ln, bool act, uint64_t gtid) {
   ln.hangs = 0;
 }
 
+__device__ __forceinline__ void add_lane_totals(GenLds& S, const Lane& ln) {
+  const uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs);
+  if (lane_id() == 0) {
+    if (f) atomicAdd(&S.faults, (unsigned long long)f);
+    if (h) atomicAdd(&S.hangs, (unsigned long long)h);
+  }
+}
+
+// The interpreter over whole threads: one lane per thread of the thread set.
 template <uint32_t SK>
 __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // [n_regs][TILE]
   __shared__ unsigned long long item_slot;
   const uint32_t tid = threadIdx.x;
   const uint64_t total = a.js->total_tiles[PATH_GENERIC];
@@ -1599,19 +1587,177 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
     }
     const uint32_t i = cur;
     const dinput& in = a.inputs[i];
-    const uint64_t l = (t - in.tile_begin[PATH_GENERIC]) * TILE + tid;
+    const uint64_t l = (t - tb) * TILE + tid;
     const bool act = l < in.lanes;
     Thr T;
     decode_lane(in.mode, in.launch, act ? l : 0, T);
     Ctx C;
     ctx_init(C, a, in, i, T);
+    C.lane0 = (t - tb) * TILE;
+    C.xt = in.xt_begin + (t - tb);
     Lane ln;
     lane_init(ln, act, T.gtid);
-    run_program<M_MAIN>(S, C, ln);
-    uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs);
-    if (lane_id() == 0) {
-      if (f) atomicAdd(&S.faults, (unsigned long long)f);
-      if (h) atomicAdd(&S.hangs, (unsigned long long)h);
+    run_program<M_MAIN>(S, R, C, ln, 0, C.P->n_instr);
+    add_lane_totals(S, ln);
+  }
+  if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
+}
+
+// Exclusive scan, in place, of the per-tile piece counts of expanded loops
+// (a.xpb, a.n_xtiles entries) in three steps: per-block sums of XSB entries,
+// a scan of the block sums (which also stores the total), per-block rescans.
+constexpr uint32_t XSB = 4096;
+__global__ void __launch_bounds__(256) xscan_sums_kernel(KArgs a) {
+  __shared__ unsigned long long part[4];
+  const uint64_t b0 = (uint64_t)blockIdx.x * XSB;
+  unsigned long long v = 0;
+  for (uint32_t q = threadIdx.x; q < XSB; q += 256)
+    if (b0 + q < a.n_xtiles) v += a.xpb[b0 + q];
+  v = wave_sum64(v);
+  if (lane_id() == 0) part[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) a.xbsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+__global__ void __launch_bounds__(1024) xscan_blocks_kernel(KArgs a, uint32_t n_blocks) {
+  __shared__ unsigned long long part[16];
+  __shared__ unsigned long long carry;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n_blocks; base += 1024) {
+    const uint32_t i = base + t;
+    const uint64_t v = i < n_blocks ? a.xbsum[i] : 0;
+    uint64_t sc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t u = __shfl_up((unsigned long long)sc, o, 64);
+      if ((int)lane_id() >= o) sc += u;
+    }
+    if (lane_id() == 63) part[t / 64] = sc;
+    __syncthreads();
+    uint64_t w = 0;
+    for (uint32_t q = 0; q < t / 64; q++) w += part[q];
+    const uint64_t c = carry;
+    if (i < n_blocks) a.xbsum[i] = c + w + sc - v;
+    __syncthreads();
+    if (t == 1023) carry = c + w + sc;
+    __syncthreads();
+  }
+  if (t == 0) {
+    a.js->total_pieces = carry;
+    a.js->next_piece = 0;
+  }
+}
+__global__ void __launch_bounds__(256) xscan_apply_kernel(KArgs a) {
+  __shared__ unsigned long long part[4];
+  __shared__ unsigned long long carry;
+  const uint64_t b0 = (uint64_t)blockIdx.x * XSB;
+  if (threadIdx.x == 0) carry = a.xbsum[blockIdx.x];
+  __syncthreads();
+  for (uint32_t base = 0; base < XSB; base += 256) {
+    const uint64_t e = b0 + base + threadIdx.x;
+    const uint64_t v = e < a.n_xtiles ? a.xpb[e] : 0;
+    uint64_t sc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t u = __shfl_up((unsigned long long)sc, o, 64);
+      if ((int)lane_id() >= o) sc += u;
+    }
+    if (lane_id() == 63) part[threadIdx.x / 64] = sc;
+    __syncthreads();
+    uint64_t w = 0;
+    for (uint32_t q = 0; q < threadIdx.x / 64; q++) w += part[q];
+    const uint64_t c = carry;
+    if (e < a.n_xtiles) a.xpb[e] = c + w + sc - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = c + w + sc;
+    __syncthreads();
+  }
+}
+
+// Expanded tile of piece p: the largest xt with xpb[xt] <= p (it has pieces,
+// since the next tile starts after p).
+__device__ __forceinline__ uint64_t find_xtile(const unsigned long long* xpb, uint64_t n, uint64_t p) {
+  uint64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (xpb[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The body pass of expanded loops: work items are pieces of PIECE consecutive
+// iterations of one tile's flattened iteration space; each lane runs one
+// iteration (owner thread by binary search in the tile's prefix).
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
+  __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // [n_regs][TILE]
+  __shared__ unsigned long long item_slot;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t total = a.js->total_pieces;
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
+  if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0;
+  uint64_t cur_xt = ~0ull;
+  for (;;) {
+    __syncthreads();
+    const uint64_t p = sched_next(sc, &a.js->next_piece, &item_slot);
+    if (p == ~0ull) break;
+    const uint64_t xt = ufirst64(find_xtile(a.xpb, a.n_xtiles, p));
+    const uint32_t i = ufirst(a.xin[xt]);
+    const dinput& in = a.inputs[i];
+    if (i != cur) {
+      if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
+      const ckc_alloc* tab = (const ckc_alloc*)in.table;
+      const uint32_t ns = ((c_dprog*)in.prog)->n_slots;
+      if (tid < ns) S.tab[tid] = tab[tid];
+      cur = i;
+      cur_sites = ((c_dprog*)in.prog)->n_sites;
+      __syncthreads();
+    }
+    const uint64_t lane0 = (xt - in.xt_begin) * TILE;
+    const uint64_t* xs = (const uint64_t*)in.xstate;
+    if (xt != cur_xt) {
+      S.pref[tid] = xs[lane0 + tid];
+      if (tid == 0) S.pref[TILE] = a.xtot[xt];
+      cur_xt = xt;
+      __syncthreads();
+    }
+    const uint64_t it0 = (p - a.xpb[xt]) * PIECE;
+    const uint64_t tot = S.pref[TILE];
+    const uint64_t it1 = it0 + PIECE < tot ? it0 + PIECE : tot;
+    c_dprog* P = (c_dprog*)in.prog;
+    const uint32_t lpc = (uint32_t)P->expand_pc;
+    const uint32_t endpc = ld_ins((c_dins*)((const uint8_t*)in.prog + P->off_instr), lpc).jmp;
+    for (uint64_t base = it0; base < it1; base += TILE) {
+      const uint64_t g = base + tid;
+      const bool ga = g < it1;
+      uint32_t o = 0;
+      if (ga) {
+        uint32_t l2 = 0, h2 = TILE - 1;
+        while (l2 < h2) {
+          const uint32_t m = (l2 + h2 + 1) >> 1;
+          if (S.pref[m] <= g) l2 = m;
+          else h2 = m - 1;
+        }
+        o = l2;
+      }
+      const uint64_t l = lane0 + o;
+      Thr T;
+      decode_lane(in.mode, in.launch, l, T);
+      Ctx C;
+      ctx_init(C, a, in, i, T);
+      C.lane0 = l;
+      Lane ln;
+      lane_init(ln, ga, T.gtid);
+      ln.k0 = ga ? g - S.pref[o] : 0;
+      count_site(S, C, ld_ins(C.I, lpc).s0, __ballot(ga));
+      run_program<M_BODY>(S, R, C, ln, lpc + 1, endpc);
+      add_lane_totals(S, ln);
     }
   }
   if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
@@ -1621,6 +1767,7 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
 // and stores the index and kind there.
 __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) {
   __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // [n_regs][TILE], lanes 0..63 used
   const uint64_t r = blockIdx.x;
   if (r >= n_records) return;
   ckc_record* rec = a.recs + r;
@@ -1656,7 +1803,7 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   C.trec = rec;
   Lane ln;
   lane_init(ln, lane_id() == 0, gtid);
-  run_program<M_FIX>(S, C, ln);
+  run_program<M_FIX>(S, R, C, ln, 0, C.P->n_instr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1730,7 +1877,8 @@ void* eval_fn(uint32_t path, uint32_t sk) {
 hipError_t launch_eval(const KArgs& a, const EvalGrid& eg, uint32_t path, hipStream_t s) {
   KArgs k = with_sched(a, eg, path);
   void* args[] = {&k};
-  return hipLaunchKernel(eval_fn(path, eg.sched[path]), dim3(eg.n_wg[path]), dim3(TILE), args, 0, s);
+  return hipLaunchKernel(eval_fn(path, eg.sched[path]), dim3(eg.n_wg[path]), dim3(TILE), args,
+                         path == PATH_GENERIC ? regfile_bytes(a) : 0, s);
 }
 }  // namespace
 
@@ -1743,9 +1891,31 @@ hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream
 hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
   return launch_eval(a, eg, PATH_GENERIC, s);
 }
+static void* body_fn(uint32_t sk) {
+  const uint32_t s = sched_impl(sk);
+  return s == CKC_SCHED_BLOCKED ? (void*)eval_body_kernel<CKC_SCHED_BLOCKED>
+       : s == CKC_SCHED_CYCLIC  ? (void*)eval_body_kernel<CKC_SCHED_CYCLIC>
+                                : (void*)eval_body_kernel<CKC_SCHED_DYNAMIC>;
+}
+static uint32_t xscan_blocks(const KArgs& a) { return (uint32_t)((a.n_xtiles + XSB - 1) / XSB); }
+
+hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
+  if (a.n_xtiles == 0) return hipSuccess;
+  const uint32_t nb = xscan_blocks(a);
+  hipLaunchKernelGGL(xscan_sums_kernel, dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(xscan_blocks_kernel, dim3(1), dim3(1024), 0, s, a, nb);
+  hipLaunchKernelGGL(xscan_apply_kernel, dim3(nb), dim3(256), 0, s, a);
+  KArgs k = with_sched(a, eg, PATH_GENERIC);
+  void* args[] = {&k};
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipLaunchKernel(body_fn(eg.sched[PATH_GENERIC]), dim3(eg.n_wg[PATH_GENERIC]), dim3(TILE), args,
+                         regfile_bytes(a), s);
+}
+
 hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s) {
   if (n_records == 0) return hipSuccess;
-  hipLaunchKernelGGL(fixup_kernel, dim3((uint32_t)n_records), dim3(64), 0, s, a, n_records);
+  hipLaunchKernelGGL(fixup_kernel, dim3((uint32_t)n_records), dim3(64), regfile_bytes(a), s, a, n_records);
   return hipGetLastError();
 }
 hipError_t launch_finish(const KArgs& a, hipStream_t s) {
@@ -1755,13 +1925,13 @@ hipError_t launch_finish(const KArgs& a, hipStream_t s) {
 
 namespace {
 hipError_t add_node(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t n_deps, void* fn,
-                    uint32_t grid, uint32_t block, void** args) {
+                    uint32_t grid, uint32_t block, void** args, uint32_t smem = 0) {
   hipKernelNodeParams p;
   std::memset(&p, 0, sizeof p);
   p.func = fn;
   p.gridDim = dim3(grid);
   p.blockDim = dim3(block);
-  p.sharedMemBytes = 0;
+  p.sharedMemBytes = smem;
   p.kernelParams = args;
   p.extra = nullptr;
   return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
@@ -1783,14 +1953,27 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
                  argsp[PATH_BLOCKS]);
   if (e == hipSuccess)
     e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC]), eg.n_wg[PATH_GENERIC], TILE,
-                 argsp[PATH_GENERIC]);
+                 argsp[PATH_GENERIC], regfile_bytes(a));
   if (e == hipSuccess)
     e = add_node(g, &ev[2], &scan, 1, eval_fn(PATH_LANES, eg.sched[PATH_LANES]), eg.n_wg[PATH_LANES], TILE,
                  argsp[PATH_LANES]);
   if (e != hipSuccess) return e;
+  if (a.n_xtiles) {  // generic -> scan of pieces -> body pass
+    uint32_t nb = xscan_blocks(a);
+    void* argsb[] = {&ka, &nb};
+    hipGraphNode_t x1, x2, x3, xb;
+    e = add_node(g, &x1, &ev[1], 1, (void*)xscan_sums_kernel, nb, 256, args1);
+    if (e == hipSuccess) e = add_node(g, &x2, &x1, 1, (void*)xscan_blocks_kernel, 1, 1024, argsb);
+    if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, args1);
+    if (e == hipSuccess)
+      e = add_node(g, &xb, &x3, 1, body_fn(eg.sched[PATH_GENERIC]), eg.n_wg[PATH_GENERIC], TILE, argsp[PATH_GENERIC],
+                   regfile_bytes(a));
+    if (e != hipSuccess) return e;
+    ev[1] = xb;
+  }
   hipGraphNode_t last = nullptr;
   if (n_records) {
-    e = add_node(g, &fix, ev, 3, (void*)fixup_kernel, (uint32_t)n_records, 64, args2);
+    e = add_node(g, &fix, ev, 3, (void*)fixup_kernel, (uint32_t)n_records, 64, args2, regfile_bytes(a));
     last = fix;
   }
   if (e == hipSuccess)

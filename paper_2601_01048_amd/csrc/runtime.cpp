@@ -314,6 +314,8 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   std::vector<dinput> hin;
   std::vector<int64_t> hsc;
   std::vector<uint64_t> est;  // estimated work per input (LPT order)
+  uint64_t n_xtiles = 0, xstate_bytes = 0;  // expanded loops
+  uint32_t max_regs = 1;                     // interpreter register file rows
   uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
   for (uint32_t k = 0; k < n_descs; k++) {
     const ckc_batch& B = descs[k];
@@ -324,6 +326,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
     if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
     unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
+    max_regs = std::max(max_regs, h->n_regs);
     for (uint32_t i = 0; i < B.n_inputs; i++) {
       const uint32_t* L = B.launch + 6 * (size_t)i;
       const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
@@ -346,6 +349,17 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
         d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
         trace_bytes += ckc::trace_bytes(h->trace_cap);
       }
+      if (h->expand_pc >= 0 && (!(h->cls & CKC_CLS_UNIFORM) || O.force_generic) && nthr > 0) {
+        // expanded loop: thread-state arrays over at most nthr lanes (64 for corners)
+        const uint64_t lanes_max = B.mode == CKC_REP_CORNERS ? std::min<uint64_t>(nthr, 64) : nthr;
+        const uint64_t n_xt = (lanes_max + TILE - 1) / TILE;
+        d.xstate = xstate_bytes + 1;  // rebased after allocation
+        d.xt_begin = n_xtiles;
+        d.xn = n_xt * TILE;
+        d.n_xt = n_xt;
+        n_xtiles += n_xt;
+        xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
+      }
       hin.push_back(d);
       est.push_back(nthr * (1 + h->n_accesses));
       for (uint32_t s = 0; s < MAX_SCALARS; s++)
@@ -367,6 +381,9 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   jobstate* d_js = nullptr;
   uint8_t* d_tr = nullptr;
   uint32_t* d_order = nullptr;
+  uint8_t* d_xs = nullptr;
+  unsigned long long *d_xtot = nullptr, *d_xpb = nullptr, *d_xbsum = nullptr;
+  uint32_t* d_xin = nullptr;
   // tile-space order of the inputs: as given, or largest first for LPT
   std::vector<uint32_t> order(n_inputs);
   for (uint64_t i = 0; i < n_inputs; i++) order[i] = (uint32_t)i;
@@ -374,6 +391,9 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return est[x] > est[y]; });
   if ((rc = dalloc(c, J, &J.d_inputs, n_inputs)) || (rc = dalloc(c, J, &d_sc, hsc.size())) ||
       (rc = dalloc(c, J, &d_order, n_inputs)) ||
+      (n_xtiles && ((rc = dalloc(c, J, &d_xs, xstate_bytes)) || (rc = dalloc(c, J, &d_xtot, n_xtiles)) ||
+                    (rc = dalloc(c, J, &d_xpb, n_xtiles)) || (rc = dalloc(c, J, &d_xin, n_xtiles)) ||
+                    (rc = dalloc(c, J, &d_xbsum, (n_xtiles + 4095) / 4096)))) ||
       (rc = dalloc(c, J, &J.d_recs, n_records)) || (rc = dalloc(c, J, &J.d_counts, n_counts)) ||
       (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &d_js, 1)) ||
       (rc = dalloc(c, J, &d_tr, trace_bytes)) ||
@@ -381,8 +401,10 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     free_job(c, J);
     return rc;
   }
-  for (auto& d : hin)
+  for (auto& d : hin) {
     if (d.trace) d.trace = (uint64_t)(uintptr_t)(d_tr + (d.trace - 1));
+    if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(d_xs + (d.xstate - 1));
+  }
   auto bail = [&](int code) {
     hipStreamSynchronize(J.stream);
     free_job(c, J);
@@ -405,6 +427,13 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   a.maps = J.d_maps;
   a.js = d_js;
   a.order = d_order;
+  a.xtot = d_xtot;
+  a.xpb = d_xpb;
+  a.xin = d_xin;
+  a.xbsum = d_xbsum;
+  a.n_xtiles = n_xtiles;
+  a.max_regs = max_regs;
+  a.pad = 0;
   a.sched = CKC_SCHED_DYNAMIC;
   a.chunk = O.chunk ? O.chunk : 1u;
   EvalGrid eg;
@@ -426,6 +455,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     if (e == hipSuccess) e = launch_eval_trace_lanes(a, eg, J.stream);
     if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
     if (e == hipSuccess) e = launch_eval_generic(a, eg, J.stream);
+    if (e == hipSuccess) e = launch_expand(a, eg, J.stream);
     if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
     if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
     if (e == hipSuccess) e = launch_finish(a, J.stream);

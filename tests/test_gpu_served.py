@@ -75,14 +75,25 @@ def test_served_equals_alone_and_oracle(ctx, stream):
         same(res[int(j)], oracle_job(ss, int(j)), f"job {j} oracle")
 
 
-def test_admission_cap_1mib(ctx, stream):
-    ss, ds = stream
+def test_admission_cap_1mib(ctx):
+    """All jobs at once under a 1 MiB cap: the cap binds (at most a few jobs with
+    their 64 KiB maps in flight), jobs above it alone end with CKC_E_NOMEM, the
+    rest equal their results alone."""
+    ss = W.config5(seed=77, rate=20000.0, duration_s=0.012, a_range=(1e3, 5e6), log2_range=(4, 16))
+    ds = ckc.DeviceStream(ctx, ss)
     cap = 1 << 20
-    print("[case] served stream under a 1 MiB cap", flush=True)
-    with ckc.Server(ctx, n_streams=4, hbm_cap_bytes=cap) as srv:
-        res, _ = serve.replay(srv, ds, time_scale=0.0, keep_results=True)
-        st = srv.stats()
-    assert st["max_inflight_bytes"] <= cap
+    print(f"[case] served stream of {ss.n_jobs} jobs under a 1 MiB cap", flush=True)
+    try:
+        with ckc.Server(ctx, n_streams=4, hbm_cap_bytes=cap) as srv:
+            res, _ = serve.replay(srv, ds, time_scale=0.0, keep_results=True)
+            st = srv.stats()
+        _check_cap(ctx, ds, res, st, cap)
+    finally:
+        ds.close()
+
+
+def _check_cap(ctx, ds, res, st, cap):
+    assert 0 < st["max_inflight_bytes"] <= cap
     big = [r for r in res if r["stats"]["ws_bytes"] > cap]
     assert big, "the stream should hold jobs above 1 MiB"
     assert st["rejected"] == len(big)
