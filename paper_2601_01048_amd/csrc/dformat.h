@@ -55,7 +55,7 @@ struct dprog {
   uint32_t trace_cap;         // entries reserved per input for the trace path (0 = none)
   uint8_t livein[MAX_LIVEIN]; // physical registers read by the expanded body
   uint8_t load_slots;         // unused
-  uint8_t pad0;
+  uint8_t body_special;       // the expanded body reads tid or bid
   uint32_t off_instr, off_consts, off_access, off_sites;  // byte offsets from the header
   uint32_t total_bytes;
   uint32_t pad1[3];

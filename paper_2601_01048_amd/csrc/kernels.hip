@@ -152,6 +152,22 @@ __device__ __forceinline__ void merge_violation(ckc_record* rec, uint32_t bad, u
   }
 }
 
+// Unsigned 32-bit division by a runtime divisor d >= 1 with a precomputed
+// multiplier (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): m = floor(2^32 (2^s - d) / d) + 1, s = ceil(log2 d),
+// q = (mulhi(n, m) + n) >> s, the sum taken in 64 bits.
+struct UDiv {
+  uint32_t m, s;
+};
+__device__ __forceinline__ UDiv udiv_make(uint32_t d) {
+  const uint32_t s = 32u - (uint32_t)__clz((int)(d - 1u));
+  const uint64_t m = ((1ull << 32) * ((1ull << s) - d)) / d + 1ull;
+  return UDiv{(uint32_t)m, s};
+}
+__device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv D) {
+  return (uint32_t)(((uint64_t)__umulhi(n, D.m) + n) >> D.s);
+}
+
 // ---------------------------------------------------------------------------
 // thread sets (CKC_FULL, CKC_REP_CORNERS, CKC_REP_BOUNDARY)
 // ---------------------------------------------------------------------------
@@ -174,6 +190,45 @@ __device__ __forceinline__ void thr_from(const uint32_t* L, uint64_t blin, uint3
   th.t[1] = q / bx;
   th.t[0] = q - th.t[1] * bx;
   th.gtid = blin * bsz + tlin;
+}
+
+// Divisors of the whole-grid decode of one input, as multiply-shift pairs.
+struct Dec {
+  UDiv dbs, dgxy, dgx, dbxy, dbx;
+  uint32_t bs, gxy, gx, bxy, bx;
+};
+__device__ __forceinline__ void dec_make(Dec& d, const uint32_t* L) {
+  d.gx = L[0];
+  d.gxy = L[0] * L[1];
+  d.bx = L[3];
+  d.bxy = L[3] * L[4];
+  d.bs = d.bxy * L[5];
+  d.dbs = udiv_make(d.bs);
+  d.dgxy = udiv_make(d.gxy);
+  d.dgx = udiv_make(d.gx);
+  d.dbxy = udiv_make(d.bxy);
+  d.dbx = udiv_make(d.bx);
+}
+// Whole-grid lane l: the lane index is the global thread id.
+__device__ __forceinline__ void decode_full(const Dec& d, uint64_t l, Thr& th) {
+  uint32_t blin, tlin;
+  if (l < (1ull << 32)) {
+    blin = udiv((uint32_t)l, d.dbs);
+    tlin = (uint32_t)l - blin * d.bs;
+  } else {
+    const uint64_t q = l / d.bs;
+    blin = (uint32_t)q;
+    tlin = (uint32_t)(l - q * d.bs);
+  }
+  th.b[2] = udiv(blin, d.dgxy);
+  const uint32_t r = blin - th.b[2] * d.gxy;
+  th.b[1] = udiv(r, d.dgx);
+  th.b[0] = r - th.b[1] * d.gx;
+  th.t[2] = udiv(tlin, d.dbxy);
+  const uint32_t q = tlin - th.t[2] * d.bxy;
+  th.t[1] = udiv(q, d.dbx);
+  th.t[0] = q - th.t[1] * d.bx;
+  th.gtid = l;
 }
 
 // The boundary thread set: every block that, along some grid dimension of
@@ -719,22 +774,6 @@ constexpr uint32_t sched_impl(uint32_t k) {
 // ---------------------------------------------------------------------------
 // trace evaluator
 // ---------------------------------------------------------------------------
-// Unsigned 32-bit division by a runtime divisor d >= 1 with a precomputed
-// multiplier (Granlund and Montgomery, "Division by invariant integers using
-// multiplication", 1994): m = floor(2^32 (2^s - d) / d) + 1, s = ceil(log2 d),
-// q = (mulhi(n, m) + n) >> s, the sum taken in 64 bits.
-struct UDiv {
-  uint32_t m, s;
-};
-__device__ __forceinline__ UDiv udiv_make(uint32_t d) {
-  const uint32_t s = 32u - (uint32_t)__clz((int)(d - 1u));
-  const uint64_t m = ((1ull << 32) * ((1ull << s) - d)) / d + 1ull;
-  return UDiv{(uint32_t)m, s};
-}
-__device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv D) {
-  return (uint32_t)(((uint64_t)__umulhi(n, D.m) + n) >> D.s);
-}
-
 // Read-only job data is read through the constant address space so that
 // wavefront-uniform loads become scalar loads.
 typedef const __attribute__((address_space(4))) dtrace_entry c_entry;
@@ -1219,8 +1258,9 @@ __device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
   return d;
 }
 
+typedef const __attribute__((address_space(4))) ckc_alloc c_alloc;
+
 struct GenLds {
-  ckc_alloc tab[MAX_SLOTS];
   uint32_t sites[MAX_SITES_LDS];
   unsigned long long wsum[TILE / 64];
   unsigned long long acc_checked, hangs, faults;
@@ -1241,6 +1281,7 @@ struct Lane {
   uint32_t hangp;          // bit d: the loop at depth d exceeds its cap
   uint64_t gtid;
   uint32_t faults, hangs;
+  uint32_t acc;            // ACCESS and LOAD executions
 };
 
 struct Ctx {
@@ -1249,6 +1290,7 @@ struct Ctx {
   c_dins* I;
   c_i64* K;
   const int64_t* sc;
+  c_alloc* tab;            // this input's allocation table (scalar loads)
   ckc_record* rec;
   uint32_t* gcnt;          // global site counters (sites beyond the LDS range)
   uint32_t Lsum, L2;
@@ -1268,15 +1310,21 @@ struct Ctx {
   ckc_record* trec;
 };
 
-__device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint32_t s, uint64_t mask) {
+// Coverage of site s by the lanes of `mask`: one LDS add per wavefront.  `sat`
+// (wavefront-uniform) marks sites below 64 whose workgroup count has reached
+// the saturation value 255, after which counting them changes nothing.
+__device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint64_t& sat, uint32_t s, uint64_t mask) {
   if (s == NOSITE || mask == 0) return;
-  if (lane_id() == (uint32_t)(__ffsll((unsigned long long)mask) - 1)) {
-    uint32_t c = (uint32_t)__popcll(mask);
-    if (s < MAX_SITES_LDS) {
-      if (S.sites[s] < 255u) atomicAdd(&S.sites[s], c);
-    } else if (C.gcnt[s] < 255u) {
-      atomicAdd(&C.gcnt[s], c);
-    }
+  if (s < 64 && ((sat >> s) & 1u)) return;
+  const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+  const uint32_t c = (uint32_t)__popcll(mask);
+  if (s < MAX_SITES_LDS) {
+    uint32_t old = 0;
+    if (lane_id() == leader) old = atomicAdd(&S.sites[s], c);
+    old = __builtin_amdgcn_readlane(old, leader);
+    if (s < 64 && old + c >= 255u) sat |= 1ull << s;
+  } else if (lane_id() == leader && C.gcnt[s] < 255u) {
+    atomicAdd(&C.gcnt[s], c);
   }
 }
 
@@ -1295,7 +1343,8 @@ constexpr uint32_t PIECE = 2048;
 // registers hold the live-ins and the counter of iteration ln.k0; runs the body.
 // M_FIX: replays lane 0 towards the target access and stops there.
 template <int MODE>
-__device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t pc0, uint32_t pc_end) {
+__device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& sat, uint32_t pc0,
+                            uint32_t pc_end) {
   c_dprog* P = C.P;
   c_dins* I = C.I;
   if (MODE == M_BODY) {
@@ -1311,7 +1360,12 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t p
     const dins D = ld_ins(I, pc);
     const uint32_t op = D.op, w = D.w;
     const uint32_t da = ufirst(D.a), db = ufirst(D.b), dc = ufirst(D.c), dd = ufirst(D.dst);
-    const uint64_t va = RGET(da), vb = RGET(db), vc = RGET(dc);
+    // operands: a for every op that reads registers, b for binary ops, SELECT
+    // and LOOP, c for SELECT and LOOP (uniform tests, no lane reads otherwise)
+    const bool rd_a = op >= CKC_OP_ADD && op != CKC_OP_ELSE && op != CKC_OP_ENDIF && op != CKC_OP_ENDLOOP;
+    const bool rd_b = (op >= CKC_OP_ADD && op <= CKC_OP_SELECT) || op == CKC_OP_LOOP;
+    const bool rd_c = op == CKC_OP_SELECT || op == CKC_OP_LOOP;
+    const uint64_t va = rd_a ? RGET(da) : 0, vb = rd_b ? RGET(db) : 0, vc = rd_c ? RGET(dc) : 0;
     const bool act = ln.dis == 0;
     uint64_t r = 0;
     uint32_t wreg = 0xFFu;   // register written after the switch
@@ -1342,12 +1396,11 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t p
       case CKC_OP_LOAD: {
         const uint32_t slot = D.slot, lg = D.fl & 3u, acc = D.x;
         const int64_t idx = (int64_t)narrow(va, w);
-        const ckc_alloc& A = S.tab[slot];
+        c_alloc& A = C.tab[slot];
         const uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
         if (MODE != M_FIX) {
-          const uint64_t am = __ballot(act);
-          if (lane_id() == 0 && am) atomicAdd(&S.acc_checked, (unsigned long long)__popcll(am));
-          count_site(S, C, D.s0, am);
+          ln.acc += act ? 1u : 0u;
+          count_site(S, C, sat, D.s0, __ballot(act));
           if (__ballot(kd != 0)) {
             const uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2) | ln.k1;
             merge_violation(C.rec + acc, kd, key);
@@ -1368,8 +1421,8 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t p
       case CKC_OP_IF: {
         const bool p = va != 0;
         if (MODE != M_FIX) {
-          count_site(S, C, D.s0, __ballot(act && p));
-          count_site(S, C, D.s1, __ballot(act && !p));
+          count_site(S, C, sat, D.s0, __ballot(act && p));
+          count_site(S, C, sat, D.s1, __ballot(act && !p));
         }
         ln.dis = act ? (p ? 0u : 1u) : ln.dis + 1;
         if (!(D.fl & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) npc = D.jmp;  // ELSE / ENDIF handle it
@@ -1428,7 +1481,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t p
           __syncthreads();
           // the loop is left at once: lanes that run it to the end pass its
           // exit, lanes over the cap stop
-          count_site(S, C, D.s1, __ballot(act && !hg));
+          count_site(S, C, sat, D.s1, __ballot(act && !hg));
           if (hg) { ln.dis = DEAD; ln.hangs++; }
           npc = endpc + 1;
           break;
@@ -1440,7 +1493,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t p
         if (__ballot(ln.dis == 0) == 0) { npc = endpc; break; }  // ENDLOOP: exit handling
         r = narrow((uint64_t)s0, w);
         wreg = dd;
-        count_site(S, C, D.s0, __ballot(ln.dis == 0));
+        count_site(S, C, sat, D.s0, __ballot(ln.dis == 0));
         break;
       }
       case CKC_OP_ENDLOOP: {
@@ -1458,14 +1511,14 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint32_t p
           wreg = ufirst(Lp.dst);
           // lanes that left the loop keep their value
           r = ln.dis == 0 ? narrow(sa + kk * sp, Lp.w) : RGET(wreg);
-          count_site(S, C, Lp.s0, __ballot(ln.dis == 0));
+          count_site(S, C, sat, Lp.s0, __ballot(ln.dis == 0));
           npc = lpc + 1;
           break;
         }
         // exit: lanes that ran this loop leave it; a capped loop stops its lane
         const bool mine = ln.dis == 1;
         const bool hg = mine && ((ln.hangp >> d) & 1u);
-        count_site(S, C, Lp.s1, __ballot(mine && !hg));
+        count_site(S, C, sat, Lp.s1, __ballot(mine && !hg));
         if (mine) {
           if (hg) { ln.dis = DEAD; ln.hangs++; }
           else ln.dis = 0;
@@ -1516,6 +1569,7 @@ __device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, const dinput& i
   C.I = (c_dins*)((const uint8_t*)in.prog + C.P->off_instr);
   C.K = (c_i64*)((const uint8_t*)in.prog + C.P->off_consts);
   C.sc = a.scalars + (size_t)i * MAX_SCALARS;
+  C.tab = (c_alloc*)in.table;
   C.rec = a.recs + in.rec_base;
   C.gcnt = a.counts + in.cnt_base;
   C.Lsum = in.L1 + in.L2;
@@ -1540,13 +1594,15 @@ __device__ __forceinline__ void lane_init(Lane& ln, bool act, uint64_t gtid) {
   ln.gtid = gtid;
   ln.faults = 0;
   ln.hangs = 0;
+  ln.acc = 0;
 }
 
 __device__ __forceinline__ void add_lane_totals(GenLds& S, const Lane& ln) {
-  const uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs);
+  const uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs), n = wave_sum64(ln.acc);
   if (lane_id() == 0) {
     if (f) atomicAdd(&S.faults, (unsigned long long)f);
     if (h) atomicAdd(&S.hangs, (unsigned long long)h);
+    if (n) atomicAdd(&S.acc_checked, (unsigned long long)n);
   }
 }
 
@@ -1567,7 +1623,8 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
   uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0;
-  uint64_t tb = 0, cur_end = 0;
+  uint64_t tb = 0, cur_end = 0, sat = 0;
+  Dec dec;
   for (;;) {
     __syncthreads();
     const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_GENERIC], &item_slot);
@@ -1576,28 +1633,29 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
       pos = pos_of_tile(ins, order, a.n_inputs, PATH_GENERIC, pos, cur_end, t);
       const uint32_t i = order[pos];
       if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
-      const ckc_alloc* tab = (const ckc_alloc*)a.inputs[i].table;
-      const uint32_t ns = ((c_dprog*)a.inputs[i].prog)->n_slots;
-      if (tid < ns) S.tab[tid] = tab[tid];
+      sat = 0;
       cur = i;
       cur_sites = ((c_dprog*)a.inputs[i].prog)->n_sites;
       tb = ins[i].tile_begin[PATH_GENERIC];
       cur_end = tb + ins[i].n_tiles[PATH_GENERIC];
-      __syncthreads();
+      const uint32_t L6[6] = {ins[i].launch[0], ins[i].launch[1], ins[i].launch[2],
+                              ins[i].launch[3], ins[i].launch[4], ins[i].launch[5]};
+      dec_make(dec, L6);
     }
     const uint32_t i = cur;
     const dinput& in = a.inputs[i];
     const uint64_t l = (t - tb) * TILE + tid;
     const bool act = l < in.lanes;
     Thr T;
-    decode_lane(in.mode, in.launch, act ? l : 0, T);
+    if (in.mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
+    else decode_lane(in.mode, in.launch, act ? l : 0, T);
     Ctx C;
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
     C.xt = in.xt_begin + (t - tb);
     Lane ln;
     lane_init(ln, act, T.gtid);
-    run_program<M_MAIN>(S, R, C, ln, 0, C.P->n_instr);
+    run_program<M_MAIN>(S, R, C, ln, sat, 0, C.P->n_instr);
     add_lane_totals(S, ln);
   }
   if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
@@ -1702,7 +1760,8 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
   uint32_t cur = 0xFFFFFFFFu, cur_sites = 0;
-  uint64_t cur_xt = ~0ull;
+  uint64_t cur_xt = ~0ull, sat = 0;
+  Dec dec;
   for (;;) {
     __syncthreads();
     const uint64_t p = sched_next(sc, &a.js->next_piece, &item_slot);
@@ -1712,12 +1771,11 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
     const dinput& in = a.inputs[i];
     if (i != cur) {
       if (cur != 0xFFFFFFFFu) flush_input(S, a, cur, cur_sites);
-      const ckc_alloc* tab = (const ckc_alloc*)in.table;
-      const uint32_t ns = ((c_dprog*)in.prog)->n_slots;
-      if (tid < ns) S.tab[tid] = tab[tid];
+      sat = 0;
       cur = i;
       cur_sites = ((c_dprog*)in.prog)->n_sites;
-      __syncthreads();
+      const uint32_t L6[6] = {in.launch[0], in.launch[1], in.launch[2], in.launch[3], in.launch[4], in.launch[5]};
+      dec_make(dec, L6);
     }
     const uint64_t lane0 = (xt - in.xt_begin) * TILE;
     const uint64_t* xs = (const uint64_t*)in.xstate;
@@ -1748,15 +1806,22 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
       }
       const uint64_t l = lane0 + o;
       Thr T;
-      decode_lane(in.mode, in.launch, l, T);
+      if (in.mode != CKC_FULL) {
+        decode_lane(in.mode, in.launch, l, T);
+      } else if (P->body_special) {
+        decode_full(dec, l, T);
+      } else {  // the body reads no thread coordinate
+        T.t[0] = T.t[1] = T.t[2] = T.b[0] = T.b[1] = T.b[2] = 0;
+        T.gtid = l;
+      }
       Ctx C;
       ctx_init(C, a, in, i, T);
       C.lane0 = l;
       Lane ln;
       lane_init(ln, ga, T.gtid);
       ln.k0 = ga ? g - S.pref[o] : 0;
-      count_site(S, C, ld_ins(C.I, lpc).s0, __ballot(ga));
-      run_program<M_BODY>(S, R, C, ln, lpc + 1, endpc);
+      count_site(S, C, sat, ld_ins(C.I, lpc).s0, __ballot(ga));
+      run_program<M_BODY>(S, R, C, ln, sat, lpc + 1, endpc);
       add_lane_totals(S, ln);
     }
   }
@@ -1781,9 +1846,6 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   const dinput& in = a.inputs[lo_i];
   const dprog* P = (const dprog*)in.prog;
   const uint32_t acc = (uint32_t)(r - in.rec_base);
-  const ckc_alloc* tab = (const ckc_alloc*)in.table;
-  if (threadIdx.x < P->n_slots) S.tab[threadIdx.x] = tab[threadIdx.x];
-  __syncthreads();
   const uint64_t key = rec->first_key;
   const uint32_t Lsum = in.L1 + in.L2;
   const uint64_t gtid = Lsum >= 64 ? 0 : key >> Lsum;
@@ -1803,7 +1865,8 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   C.trec = rec;
   Lane ln;
   lane_init(ln, lane_id() == 0, gtid);
-  run_program<M_FIX>(S, R, C, ln, 0, C.P->n_instr);
+  uint64_t sat = 0;
+  run_program<M_FIX>(S, R, C, ln, sat, 0, C.P->n_instr);
 }
 
 // ---------------------------------------------------------------------------

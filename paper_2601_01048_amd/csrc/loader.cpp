@@ -588,6 +588,9 @@ struct Analyzer {
     h.n_regs = (uint32_t)n_phys;
     h.expand_pc = expand_pc >= 0 ? newpc[expand_pc] : -1;
     h.n_livein = (uint32_t)livein.size();
+    if (expand_pc >= 0)
+      for (int i = expand_pc + 1; i < ins[expand_pc].end; i++)
+        if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
     h.off_instr = al(sizeof(dprog));

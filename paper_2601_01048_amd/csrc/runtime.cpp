@@ -437,7 +437,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   a.sched = CKC_SCHED_DYNAMIC;
   a.chunk = O.chunk ? O.chunk : 1u;
   EvalGrid eg;
-  const uint32_t defwg[3] = {8, 2, 2};  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES
+  const uint32_t defwg[3] = {8, 4, 2};  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES
   for (int p = 0; p < 3; p++) {
     eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
     eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);
