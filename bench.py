@@ -36,6 +36,18 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9
 OPS_PER_ACCESS = 2
 
 
+# sources of the trace evaluator (its counters stay valid while these are unchanged)
+TRACE_SOURCES = ("dev_common.h", "dev_plan.h", "dev_trace.h", "dformat.h", "kernels.h")
+
+
+def trace_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2601_01048_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,10 +317,8 @@ def main():
         # the kernel source they were taken on
         traffic = None
         try:
-            import hashlib
             rec_t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["eval_trace_kernel"]
-            src = open(os.path.join(ROOT, "paper_2601_01048_amd", "csrc", "kernels.hip"), "rb").read()
-            if hashlib.sha256(src).hexdigest()[:16] == rec_t["kernels_hip_sha256_16"]:
+            if trace_source_hash() == rec_t["source_sha256_16"]:
                 traffic = rec_t["traffic_bytes"]
         except (OSError, KeyError, ValueError):
             traffic = None

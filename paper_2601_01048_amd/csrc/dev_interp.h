@@ -1,0 +1,666 @@
+// dev_interp.h — the interpreter (whole threads, the body pass of expanded loops, first-violation replay).
+// Part of the device code of libckc; included by kernels.hip only (one
+// translation unit, no relocatable device code).
+#pragma once
+
+namespace ckc {
+
+// ---------------------------------------------------------------------------
+// generic interpreter
+// ---------------------------------------------------------------------------
+// The register file lives in LDS (dynamic shared memory): register r of lane t
+// is R[r * TILE + t], 64 bits, so operands are addressed by wavefront-uniform
+// register numbers without any per-lane indexing.  The lowered bytecode and
+// its constants are read through the scalar cache (constant address space):
+// every instruction field arrives in scalar registers.
+typedef const __attribute__((address_space(4))) dins c_dins;
+typedef const __attribute__((address_space(4))) daccess c_daccess;
+
+// One 16-byte instruction through four scalar loads.
+__device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
+  c_u32* p = (c_u32*)(I + pc);
+  const uint32_t w[4] = {p[0], p[1], p[2], p[3]};
+  dins d;
+  __builtin_memcpy(&d, w, sizeof d);
+  return d;
+}
+
+typedef const __attribute__((address_space(4))) ckc_alloc c_alloc;
+
+struct GenLds {
+  uint32_t sites[MAX_SITES_LDS];
+  unsigned long long wsum[TILE / 64];
+  unsigned long long acc_checked, hangs, faults;
+  unsigned long long pref[TILE + 1];  // trip-count prefix of the tile's threads (expanded loop)
+};
+
+// Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
+// only recorded), M_BODY runs one iteration of the expanded loop's body per
+// lane, M_FIX replays one thread (lane 0) up to a target access.
+enum { M_MAIN = 0, M_FIX = 1, M_BODY = 2 };
+
+struct Lane {
+  uint32_t dis;            // 0 = active; >0 disabled depth; >= DEAD stopped
+  uint64_t k0, k1;         // iteration ordinals at depth 0 / 1
+  uint64_t run0, run1;     // iterations to run
+  uint64_t st0, st1;       // loop start
+  uint64_t sp0, sp1;       // loop step
+  uint32_t hangp;          // bit d: the loop at depth d exceeds its cap
+  uint64_t gtid;
+  // totals of this lane since the last flush (several threads or iterations)
+  uint64_t faults, acc;    // divisions by zero; ACCESS and LOAD executions
+  uint32_t hangs;          // threads stopped by a trip cap
+};
+
+struct Ctx {
+  const dinput* in;
+  c_dprog* P;
+  c_dins* I;
+  c_i64* K;
+  const int64_t* sc;
+  c_alloc* tab;            // this input's allocation table (scalar loads)
+  ckc_record* rec;
+  uint32_t* gcnt;          // global site counters (sites beyond the LDS range)
+  uint32_t Lsum, L2;
+  uint64_t cap0, cap1;
+  uint32_t t0, t1, t2, b0, b1, b2;  // thread coordinates (this lane)
+  // expanded loop: this input's thread-state arrays (pref, start, step,
+  // live-ins; xn entries each), the tile's first lane and expanded tile
+  uint64_t* xs;
+  uint64_t xn, lane0, xt;
+  unsigned long long *xtot, *xpb;
+  uint32_t* xin;
+  uint32_t input;
+  // fix-up target
+  uint32_t tacc;
+  uint64_t tk0, tk1;
+  int32_t tloop0, tloop1;
+  ckc_record* trec;
+};
+
+// Coverage of site s by the lanes of `mask`: one LDS add per wavefront.  `sat`
+// (wavefront-uniform) marks sites below 64 whose workgroup count has reached
+// the saturation value 255, after which counting them changes nothing.
+__device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint64_t& sat, uint32_t s, uint64_t mask) {
+  if (s == NOSITE || mask == 0) return;
+  if (s < 64 && ((sat >> s) & 1u)) return;
+  const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+  const uint32_t c = (uint32_t)__popcll(mask);
+  if (s < MAX_SITES_LDS) {
+    uint32_t old = 0;
+    if (lane_id() == leader) old = atomicAdd(&S.sites[s], c);
+    old = __builtin_amdgcn_readlane(old, leader);
+    if (s < 64 && old + c >= 255u) sat |= 1ull << s;
+  } else if (lane_id() == leader && C.gcnt[s] < 255u) {
+    atomicAdd(&C.gcnt[s], c);
+  }
+}
+
+// Register file in LDS (dynamic shared memory): register r of lane t is
+// R[r * TILE + t], 64 bits, addressed by wavefront-uniform register numbers.
+#define RGET(i) R[(uint32_t)(i) * TILE + threadIdx.x]
+#define RPUT(i, v) (R[(uint32_t)(i) * TILE + threadIdx.x] = (v))
+
+// Iterations of an expanded loop per work item of the body pass.
+constexpr uint32_t PIECE = 2048;
+
+// Runs the program for the wavefront from pc0 until pc_end (exclusive) or the
+// end.  M_MAIN: whole threads; at the expanded loop each lane's trip count,
+// start, step and live-ins are stored with the tile's prefix of trip counts
+// and the loop is left at once (its iterations run in the body pass).  M_BODY:
+// registers hold the live-ins and the counter of iteration ln.k0; runs the body.
+// M_FIX: replays lane 0 towards the target access and stops there.
+template <int MODE>
+__device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& sat, uint32_t pc0,
+                            uint32_t pc_end) {
+  c_dprog* P = C.P;
+  c_dins* I = C.I;
+  if (MODE == M_BODY) {
+    // live-ins of the owner thread, counter of this iteration
+    const uint64_t l = C.lane0;  // lane index of the owner (set per lane)
+    const uint32_t nl = P->n_livein;
+    for (uint32_t q = 0; q < nl; q++) RPUT(ufirst(P->livein[q]), C.xs[(3 + q) * C.xn + l]);
+    const dins L = ld_ins(I, pc0 - 1);
+    RPUT(ufirst(L.dst), narrow(C.xs[C.xn + l] + ln.k0 * C.xs[2 * C.xn + l], L.w));
+  }
+  uint32_t pc = pc0;
+  while (pc < pc_end) {
+    const dins D = ld_ins(I, pc);
+    const uint32_t op = D.op, w = D.w;
+    const uint32_t da = ufirst(D.a), db = ufirst(D.b), dc = ufirst(D.c), dd = ufirst(D.dst);
+    // operands: a for every op that reads registers, b for binary ops, SELECT
+    // and LOOP, c for SELECT and LOOP (uniform tests, no lane reads otherwise)
+    const bool rd_a = op >= CKC_OP_ADD && op != CKC_OP_ELSE && op != CKC_OP_ENDIF && op != CKC_OP_ENDLOOP;
+    const bool rd_b = (op >= CKC_OP_ADD && op <= CKC_OP_SELECT) || op == CKC_OP_LOOP;
+    const bool rd_c = op == CKC_OP_SELECT || op == CKC_OP_LOOP;
+    const uint64_t va = rd_a ? RGET(da) : 0, vb = rd_b ? RGET(db) : 0, vc = rd_c ? RGET(dc) : 0;
+    const bool act = ln.dis == 0;
+    uint64_t r = 0;
+    uint32_t wreg = 0xFFu;   // register written after the switch
+    uint32_t npc = pc + 1;
+    switch (op) {
+      case CKC_OP_CONST: r = narrow((uint64_t)C.K[D.x], w); wreg = dd; break;
+      case CKC_OP_SCALAR: r = narrow((uint64_t)C.sc[D.x], w); wreg = dd; break;
+      case CKC_OP_SPECIAL: {
+        const uint32_t x = D.x;
+        uint32_t v;
+        switch (x) {
+          case 0: v = C.t0; break;
+          case 1: v = C.t1; break;
+          case 2: v = C.t2; break;
+          case 3: v = C.b0; break;
+          case 4: v = C.b1; break;
+          case 5: v = C.b2; break;
+          default: v = x < 9 ? C.in->launch[3 + x - 6] : C.in->launch[x - 9]; break;
+        }
+        r = v;
+        wreg = dd;
+        break;
+      }
+      case CKC_OP_SELECT: r = narrow(va != 0 ? vb : vc, w); wreg = dd; break;
+      case CKC_OP_SEXT: case CKC_OP_TRUNC: r = narrow(va, 32); wreg = dd; break;
+      case CKC_OP_ZEXT: r = va & 0xFFFFFFFFull; wreg = dd; break;
+      case CKC_OP_ACCESS:
+      case CKC_OP_LOAD: {
+        const uint32_t slot = D.slot, lg = D.fl & 3u, acc = D.x;
+        const int64_t idx = (int64_t)narrow(va, w);
+        c_alloc& A = C.tab[slot];
+        const uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
+        if (MODE != M_FIX) {
+          ln.acc += act ? 1u : 0u;
+          count_site(S, C, sat, D.s0, __ballot(act));
+          if (__ballot(kd != 0)) {
+            const uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2) | ln.k1;
+            merge_violation(C.rec + acc, kd, key);
+          }
+        } else if (acc == C.tacc) {
+          if (lane_id() == 0) { C.trec->index = idx; C.trec->first_kind = kd; }
+          return;
+        }
+        if (op == CKC_OP_LOAD) {
+          uint64_t v = 0;
+          if (act && kd == 0)
+            v = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
+          r = v;
+          wreg = dd;
+        }
+        break;
+      }
+      case CKC_OP_IF: {
+        const bool p = va != 0;
+        if (MODE != M_FIX) {
+          count_site(S, C, sat, D.s0, __ballot(act && p));
+          count_site(S, C, sat, D.s1, __ballot(act && !p));
+        }
+        ln.dis = act ? (p ? 0u : 1u) : ln.dis + 1;
+        if (!(D.fl & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) npc = D.jmp;  // ELSE / ENDIF handle it
+        break;
+      }
+      case CKC_OP_ELSE:
+        ln.dis = ln.dis == 1 ? 0u : (ln.dis == 0 ? 1u : ln.dis);
+        if (!(D.fl & DI_NOSKIP) && __ballot(ln.dis == 0) == 0) npc = D.jmp;
+        break;
+      case CKC_OP_ENDIF: ln.dis = ln.dis > 0 ? ln.dis - 1 : 0u; break;
+      case CKC_OP_LOOP: {
+        const uint32_t d = D.x, fl = D.fl, endpc = D.jmp;
+        const int64_t s0 = (int64_t)narrow(va, w), e0 = (int64_t)narrow(vb, w), stp = (int64_t)narrow(vc, w);
+        if (MODE == M_FIX) {
+          const int32_t me = (int32_t)pc;
+          if (me != C.tloop0 && me != C.tloop1) { npc = endpc + 1; break; }
+          const uint64_t kk = me == C.tloop0 ? C.tk0 : C.tk1;
+          r = narrow((uint64_t)s0 + kk * (uint64_t)stp, w);
+          wreg = dd;
+          if (d == 0) ln.k0 = kk; else ln.k1 = kk;
+          break;  // into the body for exactly the target iteration
+        }
+        const uint64_t nt = act ? trip_count(s0, e0, stp) : 0;
+        const uint64_t cap = d == 0 ? C.cap0 : C.cap1;
+        const uint64_t rn = nt < cap ? nt : cap;
+        const bool hg = act && nt > cap;
+        if (MODE == M_MAIN && (fl & DI_EXPAND) && C.xs != nullptr) {
+          // every wavefront of the workgroup arrives here exactly once per tile:
+          // prefix of the trip counts over the tile, thread state to memory
+          const uint32_t tid = threadIdx.x;
+          const uint64_t cnt = act ? rn : 0;
+          uint64_t incl = cnt;
+          for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
+            if ((int)lane_id() >= o) incl += u;
+          }
+          if (lane_id() == 63) S.wsum[tid / 64] = incl;
+          __syncthreads();
+          uint64_t wpre = 0;
+          for (uint32_t q = 0; q < tid / 64; q++) wpre += S.wsum[q];
+          const uint64_t pre = wpre + incl - cnt;
+          const uint64_t l = C.lane0 + tid;
+          C.xs[l] = pre;
+          if (cnt) {
+            C.xs[C.xn + l] = (uint64_t)s0;
+            C.xs[2 * C.xn + l] = (uint64_t)stp;
+            const uint32_t nl = P->n_livein;
+            for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = RGET(ufirst(P->livein[q]));
+          }
+          if (tid == TILE - 1) {
+            const uint64_t tot = pre + cnt;
+            C.xtot[C.xt] = tot;
+            C.xpb[C.xt] = (tot + PIECE - 1) / PIECE;
+            C.xin[C.xt] = C.input;
+          }
+          __syncthreads();
+          // the loop is left at once: lanes that run it to the end pass its
+          // exit, lanes over the cap stop
+          count_site(S, C, sat, D.s1, __ballot(act && !hg));
+          if (hg) { ln.dis = DEAD; ln.hangs++; }
+          npc = endpc + 1;
+          break;
+        }
+        if (d == 0) { ln.run0 = rn; ln.st0 = (uint64_t)s0; ln.sp0 = (uint64_t)stp; ln.k0 = 0; }
+        else { ln.run1 = rn; ln.st1 = (uint64_t)s0; ln.sp1 = (uint64_t)stp; ln.k1 = 0; }
+        ln.hangp = (ln.hangp & ~(1u << d)) | (hg ? (1u << d) : 0u);
+        ln.dis = act ? (rn > 0 ? 0u : 1u) : ln.dis + 1;
+        if (__ballot(ln.dis == 0) == 0) { npc = endpc; break; }  // ENDLOOP: exit handling
+        r = narrow((uint64_t)s0, w);
+        wreg = dd;
+        count_site(S, C, sat, D.s0, __ballot(ln.dis == 0));
+        break;
+      }
+      case CKC_OP_ENDLOOP: {
+        if (MODE == M_FIX) return;  // target not reached in this iteration
+        const uint32_t d = D.x, lpc = D.jmp;
+        const dins Lp = ld_ins(I, lpc);
+        if (ln.dis == 0) {
+          const uint64_t kk = (d == 0 ? ln.k0 : ln.k1) + 1;
+          if (d == 0) ln.k0 = kk; else ln.k1 = kk;
+          if (kk == (d == 0 ? ln.run0 : ln.run1)) ln.dis = 1;  // done at this level
+        }
+        if (__ballot(ln.dis == 0)) {
+          const uint64_t kk = d == 0 ? ln.k0 : ln.k1;
+          const uint64_t sa = d == 0 ? ln.st0 : ln.st1, sp = d == 0 ? ln.sp0 : ln.sp1;
+          wreg = ufirst(Lp.dst);
+          // lanes that left the loop keep their value
+          r = ln.dis == 0 ? narrow(sa + kk * sp, Lp.w) : RGET(wreg);
+          count_site(S, C, sat, Lp.s0, __ballot(ln.dis == 0));
+          npc = lpc + 1;
+          break;
+        }
+        // exit: lanes that ran this loop leave it; a capped loop stops its lane
+        const bool mine = ln.dis == 1;
+        const bool hg = mine && ((ln.hangp >> d) & 1u);
+        count_site(S, C, sat, Lp.s1, __ballot(mine && !hg));
+        if (mine) {
+          if (hg) { ln.dis = DEAD; ln.hangs++; }
+          else ln.dis = 0;
+        } else if (ln.dis > 1) {
+          ln.dis--;
+        }
+        if (d == 0) ln.k0 = 0; else ln.k1 = 0;
+        break;
+      }
+      default: {
+        uint32_t f = 0;
+        r = alu(op, w, va, vb, f);
+        if (act) ln.faults += f;
+        wreg = dd;
+        break;
+      }
+    }
+    if (wreg != 0xFFu) RPUT(wreg, r);
+    pc = npc;
+  }
+}
+
+__device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, uint32_t n_sites) {
+  __syncthreads();
+  const dinput& in = a.inputs[input];
+  uint32_t* cnt = a.counts + in.cnt_base;
+  const uint32_t ns = n_sites < (uint32_t)MAX_SITES_LDS ? n_sites : (uint32_t)MAX_SITES_LDS;
+  for (uint32_t s = threadIdx.x; s < ns; s += TILE) {
+    uint32_t c = S.sites[s];
+    if (c) {
+      if (cnt[s] < 255u) atomicAdd(&cnt[s], c < 255u ? c : 255u);
+      S.sites[s] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    ckc_input_status* st = a.status + input;
+    if (S.acc_checked) atomicAdd((unsigned long long*)&st->accesses_checked, S.acc_checked);
+    if (S.hangs) atomicAdd((unsigned long long*)&st->hang_lanes, S.hangs);
+    if (S.faults) atomicAdd((unsigned long long*)&st->arith_faults, S.faults);
+    S.acc_checked = 0; S.hangs = 0; S.faults = 0;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, const dinput& in, uint32_t i, const Thr& T) {
+  C.in = &in;
+  C.P = (c_dprog*)in.prog;
+  C.I = (c_dins*)((const uint8_t*)in.prog + C.P->off_instr);
+  C.K = (c_i64*)((const uint8_t*)in.prog + C.P->off_consts);
+  C.sc = a.scalars + (size_t)i * MAX_SCALARS;
+  C.tab = (c_alloc*)in.table;
+  C.rec = a.recs + in.rec_base;
+  C.gcnt = a.counts + in.cnt_base;
+  C.Lsum = in.L1 + in.L2;
+  C.L2 = in.L2;
+  C.cap0 = 1ull << in.cap_log2[0];
+  C.cap1 = 1ull << in.cap_log2[1];
+  C.t0 = T.t[0]; C.t1 = T.t[1]; C.t2 = T.t[2]; C.b0 = T.b[0]; C.b1 = T.b[1]; C.b2 = T.b[2];
+  C.xs = (uint64_t*)in.xstate;
+  C.xn = in.xn;
+  C.xtot = a.xtot;
+  C.xpb = a.xpb;
+  C.xin = a.xin;
+  C.input = i;
+  C.lane0 = 0;
+  C.xt = 0;
+}
+
+// Per-thread state of a lane (its totals are kept).
+__device__ __forceinline__ void lane_init(Lane& ln, bool act, uint64_t gtid) {
+  ln.dis = act ? 0u : DEAD;
+  ln.k0 = ln.k1 = ln.run0 = ln.run1 = ln.st0 = ln.st1 = ln.sp0 = ln.sp1 = 0;
+  ln.hangp = 0;
+  ln.gtid = gtid;
+}
+__device__ __forceinline__ void lane_zero_totals(Lane& ln) {
+  ln.faults = 0;
+  ln.acc = 0;
+  ln.hangs = 0;
+}
+// Adds the wavefront's totals to the workgroup's and clears them (called by
+// the whole workgroup before a flush).
+__device__ __forceinline__ void add_lane_totals(GenLds& S, Lane& ln) {
+  const uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs), n = wave_sum64(ln.acc);
+  if (lane_id() == 0) {
+    if (f) atomicAdd(&S.faults, (unsigned long long)f);
+    if (h) atomicAdd(&S.hangs, (unsigned long long)h);
+    if (n) atomicAdd(&S.acc_checked, (unsigned long long)n);
+  }
+  lane_zero_totals(ln);
+}
+
+// The interpreter over whole threads: one lane per thread of the thread set.
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
+  __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // [n_regs][TILE]
+  __shared__ unsigned long long item_slot;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t total = a.js->total_tiles[PATH_GENERIC];
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
+  for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
+  if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
+  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0;
+  uint64_t tb = 0, cur_end = 0, sat = 0;
+  Dec dec;
+  Lane ln;
+  lane_zero_totals(ln);
+  for (;;) {
+    __syncthreads();
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_GENERIC], &item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      pos = pos_of_tile(ins, order, a.n_inputs, PATH_GENERIC, pos, cur_end, t);
+      const uint32_t i = order[pos];
+      if (cur != 0xFFFFFFFFu) {
+        add_lane_totals(S, ln);
+        flush_input(S, a, cur, cur_sites);
+      }
+      sat = 0;
+      cur = i;
+      cur_sites = ((c_dprog*)a.inputs[i].prog)->n_sites;
+      tb = ins[i].tile_begin[PATH_GENERIC];
+      cur_end = tb + ins[i].n_tiles[PATH_GENERIC];
+      const uint32_t L6[6] = {ins[i].launch[0], ins[i].launch[1], ins[i].launch[2],
+                              ins[i].launch[3], ins[i].launch[4], ins[i].launch[5]};
+      dec_make(dec, L6);
+    }
+    const uint32_t i = cur;
+    const dinput& in = a.inputs[i];
+    const uint64_t l = (t - tb) * TILE + tid;
+    const bool act = l < in.lanes;
+    Thr T;
+    if (in.mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
+    else decode_lane(in.mode, in.launch, act ? l : 0, T);
+    Ctx C;
+    ctx_init(C, a, in, i, T);
+    C.lane0 = (t - tb) * TILE;
+    C.xt = in.xt_begin + (t - tb);
+    lane_init(ln, act, T.gtid);
+    run_program<M_MAIN>(S, R, C, ln, sat, 0, C.P->n_instr);
+  }
+  if (cur != 0xFFFFFFFFu) {
+    add_lane_totals(S, ln);
+    flush_input(S, a, cur, cur_sites);
+  }
+}
+
+// Exclusive scan, in place, of the per-tile piece counts of expanded loops
+// (a.xpb, a.n_xtiles entries) in three steps: per-block sums of XSB entries,
+// a scan of the block sums (which also stores the total), per-block rescans.
+constexpr uint32_t XSB = 4096;
+__global__ void __launch_bounds__(256) xscan_sums_kernel(KArgs a) {
+  __shared__ unsigned long long part[4];
+  const uint64_t b0 = (uint64_t)blockIdx.x * XSB;
+  unsigned long long v = 0;
+  for (uint32_t q = threadIdx.x; q < XSB; q += 256)
+    if (b0 + q < a.n_xtiles) v += a.xpb[b0 + q];
+  v = wave_sum64(v);
+  if (lane_id() == 0) part[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) a.xbsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+__global__ void __launch_bounds__(1024) xscan_blocks_kernel(KArgs a, uint32_t n_blocks) {
+  __shared__ unsigned long long part[16];
+  __shared__ unsigned long long carry;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n_blocks; base += 1024) {
+    const uint32_t i = base + t;
+    const uint64_t v = i < n_blocks ? a.xbsum[i] : 0;
+    uint64_t sc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t u = __shfl_up((unsigned long long)sc, o, 64);
+      if ((int)lane_id() >= o) sc += u;
+    }
+    if (lane_id() == 63) part[t / 64] = sc;
+    __syncthreads();
+    uint64_t w = 0;
+    for (uint32_t q = 0; q < t / 64; q++) w += part[q];
+    const uint64_t c = carry;
+    if (i < n_blocks) a.xbsum[i] = c + w + sc - v;
+    __syncthreads();
+    if (t == 1023) carry = c + w + sc;
+    __syncthreads();
+  }
+  if (t == 0) {
+    a.js->total_pieces = carry;
+    a.js->next_piece = 0;
+  }
+}
+__global__ void __launch_bounds__(256) xscan_apply_kernel(KArgs a) {
+  __shared__ unsigned long long part[4];
+  __shared__ unsigned long long carry;
+  const uint64_t b0 = (uint64_t)blockIdx.x * XSB;
+  if (threadIdx.x == 0) carry = a.xbsum[blockIdx.x];
+  __syncthreads();
+  for (uint32_t base = 0; base < XSB; base += 256) {
+    const uint64_t e = b0 + base + threadIdx.x;
+    const uint64_t v = e < a.n_xtiles ? a.xpb[e] : 0;
+    uint64_t sc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t u = __shfl_up((unsigned long long)sc, o, 64);
+      if ((int)lane_id() >= o) sc += u;
+    }
+    if (lane_id() == 63) part[threadIdx.x / 64] = sc;
+    __syncthreads();
+    uint64_t w = 0;
+    for (uint32_t q = 0; q < threadIdx.x / 64; q++) w += part[q];
+    const uint64_t c = carry;
+    if (e < a.n_xtiles) a.xpb[e] = c + w + sc - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = c + w + sc;
+    __syncthreads();
+  }
+}
+
+// Expanded tile of piece p: the largest xt with xpb[xt] <= p (it has pieces,
+// since the next tile starts after p).
+__device__ __forceinline__ uint64_t find_xtile(const unsigned long long* xpb, uint64_t n, uint64_t p) {
+  uint64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (xpb[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The body pass of expanded loops: work items are pieces of PIECE consecutive
+// iterations of one tile's flattened iteration space; each lane runs one
+// iteration (owner thread by binary search in the tile's prefix).
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
+  __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // [n_regs][TILE]
+  __shared__ unsigned long long item_slot;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t total = a.js->total_pieces;
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
+  if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0;
+  uint64_t cur_xt = ~0ull, sat = 0;
+  Dec dec;
+  Lane ln;
+  lane_zero_totals(ln);
+  for (;;) {
+    __syncthreads();
+    const uint64_t p = sched_next(sc, &a.js->next_piece, &item_slot);
+    if (p == ~0ull) break;
+    const uint64_t xt = ufirst64(find_xtile(a.xpb, a.n_xtiles, p));
+    const uint32_t i = ufirst(a.xin[xt]);
+    const dinput& in = a.inputs[i];
+    if (i != cur) {
+      if (cur != 0xFFFFFFFFu) {
+        add_lane_totals(S, ln);
+        flush_input(S, a, cur, cur_sites);
+      }
+      sat = 0;
+      cur = i;
+      cur_sites = ((c_dprog*)in.prog)->n_sites;
+      const uint32_t L6[6] = {in.launch[0], in.launch[1], in.launch[2], in.launch[3], in.launch[4], in.launch[5]};
+      dec_make(dec, L6);
+    }
+    const uint64_t lane0 = (xt - in.xt_begin) * TILE;
+    const uint64_t* xs = (const uint64_t*)in.xstate;
+    if (xt != cur_xt) {
+      S.pref[tid] = xs[lane0 + tid];
+      if (tid == 0) S.pref[TILE] = a.xtot[xt];
+      cur_xt = xt;
+      __syncthreads();
+    }
+    const uint64_t it0 = (p - a.xpb[xt]) * PIECE;
+    const uint64_t tot = S.pref[TILE];
+    const uint64_t it1 = it0 + PIECE < tot ? it0 + PIECE : tot;
+    c_dprog* P = (c_dprog*)in.prog;
+    const uint32_t lpc = (uint32_t)P->expand_pc;
+    const uint32_t endpc = ld_ins((c_dins*)((const uint8_t*)in.prog + P->off_instr), lpc).jmp;
+    Thr T0;
+    T0.t[0] = T0.t[1] = T0.t[2] = T0.b[0] = T0.b[1] = T0.b[2] = 0;
+    T0.gtid = 0;
+    Ctx C;
+    ctx_init(C, a, in, i, T0);
+    const uint32_t site_iter = ld_ins(C.I, lpc).s0;
+    for (uint64_t base = it0; base < it1; base += TILE) {
+      const uint64_t g = base + tid;
+      const bool ga = g < it1;
+      uint32_t o = 0;
+      if (ga) {
+        uint32_t l2 = 0, h2 = TILE - 1;
+        while (l2 < h2) {
+          const uint32_t m = (l2 + h2 + 1) >> 1;
+          if (S.pref[m] <= g) l2 = m;
+          else h2 = m - 1;
+        }
+        o = l2;
+      }
+      const uint64_t l = lane0 + o;
+      Thr T;
+      if (in.mode != CKC_FULL) {
+        decode_lane(in.mode, in.launch, l, T);
+      } else if (P->body_special) {
+        decode_full(dec, l, T);
+      } else {  // the body reads no thread coordinate
+        T.t[0] = T.t[1] = T.t[2] = T.b[0] = T.b[1] = T.b[2] = 0;
+        T.gtid = l;
+      }
+      C.t0 = T.t[0]; C.t1 = T.t[1]; C.t2 = T.t[2]; C.b0 = T.b[0]; C.b1 = T.b[1]; C.b2 = T.b[2];
+      C.lane0 = l;
+      ln.dis = ga ? 0u : DEAD;
+      ln.k0 = ga ? g - S.pref[o] : 0;
+      ln.k1 = 0;
+      ln.gtid = T.gtid;
+      count_site(S, C, sat, site_iter, __ballot(ga));
+      run_program<M_BODY>(S, R, C, ln, sat, lpc + 1, endpc);
+    }
+  }
+  if (cur != 0xFFFFFFFFu) {
+    add_lane_totals(S, ln);
+    flush_input(S, a, cur, cur_sites);
+  }
+}
+
+// One wavefront per record: replays the thread of first_key up to the access
+// and stores the index and kind there.
+__global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) {
+  __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // [n_regs][TILE], lanes 0..63 used
+  const uint64_t r = blockIdx.x;
+  if (r >= n_records) return;
+  ckc_record* rec = a.recs + r;
+  if (rec->count == 0) return;
+  // input owning record r
+  uint32_t lo_i = 0, hi_i = a.n_inputs - 1;
+  while (lo_i < hi_i) {
+    uint32_t mid = (lo_i + hi_i + 1) / 2;
+    if (a.inputs[mid].rec_base <= r) lo_i = mid; else hi_i = mid - 1;
+  }
+  const dinput& in = a.inputs[lo_i];
+  const dprog* P = (const dprog*)in.prog;
+  const uint32_t acc = (uint32_t)(r - in.rec_base);
+  const uint64_t key = rec->first_key;
+  const uint32_t Lsum = in.L1 + in.L2;
+  const uint64_t gtid = Lsum >= 64 ? 0 : key >> Lsum;
+  const uint64_t i1 = in.L1 ? (key >> in.L2) & ((1ull << in.L1) - 1) : 0;
+  const uint64_t i2 = in.L2 ? key & ((1ull << in.L2) - 1) : 0;
+  const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
+  Thr T;
+  thr_from(in.launch, gtid / bs, (uint32_t)(gtid % bs), T);
+  const daccess A = prog_access(P)[acc];
+  Ctx C;
+  ctx_init(C, a, in, lo_i, T);
+  C.tacc = acc;
+  C.tk0 = i1;
+  C.tk1 = i2;
+  C.tloop0 = A.loop_pc[0];
+  C.tloop1 = A.loop_pc[1];
+  C.trec = rec;
+  Lane ln;
+  lane_init(ln, lane_id() == 0, gtid);
+  lane_zero_totals(ln);
+  uint64_t sat = 0;
+  run_program<M_FIX>(S, R, C, ln, sat, 0, C.P->n_instr);
+}
+
+
+}  // namespace ckc

@@ -1,0 +1,457 @@
+// dev_plan.h — planning (thread sets, per-input traces, tile scan), work schedules, finishing (totals, dense maps).
+// Part of the device code of libckc; included by kernels.hip only (one
+// translation unit, no relocatable device code).
+#pragma once
+
+namespace ckc {
+
+// ---------------------------------------------------------------------------
+// plan: thread-set sizes and per-input traces of uniform-control programs
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const dins* prog_ins(const dprog* p) {
+  return (const dins*)((const uint8_t*)p + p->off_instr);
+}
+__device__ __forceinline__ const int64_t* prog_consts(const dprog* p) {
+  return (const int64_t*)((const uint8_t*)p + p->off_consts);
+}
+__device__ __forceinline__ const daccess* prog_access(const dprog* p) {
+  return (const daccess*)((const uint8_t*)p + p->off_access);
+}
+__device__ __forceinline__ const uint16_t* prog_sites(const dprog* p) {
+  return (const uint16_t*)((const uint8_t*)p + p->off_sites);
+}
+
+__device__ __forceinline__ uint64_t rget(const uint32_t* lo, const uint32_t* hi, uint32_t i) {
+  return ((uint64_t)hi[i] << 32) | lo[i];
+}
+#define RSET(i, v)                      \
+  do {                                  \
+    uint64_t _v = (v);                  \
+    lo[(i)] = (uint32_t)_v;             \
+    hi[(i)] = (uint32_t)(_v >> 32);     \
+  } while (0)
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  return ((uint64_t)h << 32) | w;
+}
+
+// Symbolic evaluation of a uniform-control program for one input.  Lane j of
+// the wavefront holds coefficient j (tid.x, tid.y, tid.z, bid.x, bid.y, bid.z)
+// and lane 6 the thread-invariant part of every register.  Sites, accesses and
+// faults are counted per thread (every thread performs the same sequence).
+__device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc, const ckc_alloc* tab,
+                            dtrace_head* th, dtrace_entry* te, uint32_t* visits,
+                            ckc_input_status* st) {
+  const uint32_t j = lane_id();
+  const dins* I = prog_ins(P);
+  const int64_t* K = prog_consts(P);
+  uint32_t lo[NREG], hi[NREG];
+#pragma unroll
+  for (int r = 0; r < NREG; r++) { lo[r] = 0; hi[r] = 0; }
+  uint32_t n_ent = 0, n_cls = 0, overflow = 0, hang = 0, any_dead = 0;
+  uint64_t acc_per_thread = 0, faults_per_thread = 0;
+  __shared__ int64_t cls_coef[MAX_CLASSES][6];
+  __shared__ uint32_t cls_w[MAX_CLASSES];
+  uint64_t k[2] = {0, 0}, run[2] = {0, 0}, lstart[2] = {0, 0}, lstep[2] = {0, 0};
+  uint32_t lhang[2] = {0, 0};
+  const uint32_t L2 = in.L2;
+  const uint32_t n = P->n_instr;
+  const uint32_t cap_log2_0 = in.cap_log2[0], cap_log2_1 = in.cap_log2[1];
+  uint32_t pc = 0;
+  auto visit = [&](uint32_t s) {
+    if (s != NOSITE && j == 0 && visits[s] < 255u) visits[s] += 1;  // only min(255, .) is observable
+  };
+  while (pc < n && !hang && !overflow) {
+    const dins D = I[pc];
+    const uint32_t op = D.op, w = D.w;
+    switch (op) {
+      case CKC_OP_CONST: RSET(D.dst, j == 6 ? narrow((uint64_t)K[D.x], w) : 0ull); break;
+      case CKC_OP_SCALAR: RSET(D.dst, j == 6 ? narrow((uint64_t)sc[D.x], w) : 0ull); break;
+      case CKC_OP_SPECIAL: {
+        uint64_t v = 0;
+        if (D.x < 6) v = (j == D.x) ? 1ull : 0ull;
+        else if (j == 6) v = D.x < 9 ? in.launch[3 + (D.x - 6)] : in.launch[D.x - 9];
+        RSET(D.dst, v);
+        break;
+      }
+      case CKC_OP_ADD: case CKC_OP_SUB: {
+        uint64_t a = rget(lo, hi, D.a), b = rget(lo, hi, D.b);
+        RSET(D.dst, narrow(op == CKC_OP_ADD ? a + b : a - b, w));
+        break;
+      }
+      case CKC_OP_MUL: case CKC_OP_SHL: {
+        uint64_t a = rget(lo, hi, D.a), b = rget(lo, hi, D.b);
+        bool b_uni = __ballot(j < 6 && b != 0) == 0;
+        uint64_t r;
+        if (op == CKC_OP_SHL) {
+          uint64_t amt = readlane64(b, 6) & (uint64_t)(w - 1);
+          r = a << amt;
+        } else if (b_uni) {
+          r = a * readlane64(b, 6);
+        } else {
+          r = b * readlane64(a, 6);
+        }
+        RSET(D.dst, narrow(r, w));
+        break;
+      }
+      case CKC_OP_TRUNC: RSET(D.dst, narrow(rget(lo, hi, D.a), 32)); break;
+      case CKC_OP_SEXT: RSET(D.dst, j == 6 ? narrow(rget(lo, hi, D.a), 32) : 0ull); break;
+      case CKC_OP_ZEXT: RSET(D.dst, j == 6 ? (rget(lo, hi, D.a) & 0xFFFFFFFFull) : 0ull); break;
+      case CKC_OP_SELECT: {
+        uint64_t c = readlane64(rget(lo, hi, D.a), 6);
+        RSET(D.dst, narrow(c != 0 ? rget(lo, hi, D.b) : rget(lo, hi, D.c), w));
+        break;
+      }
+      case CKC_OP_ACCESS: case CKC_OP_LOAD: {
+        uint64_t v = rget(lo, hi, D.a);
+        const ckc_alloc A = tab[D.slot];
+        uint32_t lg = D.fl & 3u;
+        // coefficient vector of this index (wrapped to the access width)
+        uint64_t cw = narrow(v, w);
+        int64_t coef[6];
+#pragma unroll
+        for (int d = 0; d < 6; d++) coef[d] = (int64_t)readlane64(cw, d);
+        int64_t off = (int64_t)readlane64(cw, 6);
+        int cls = -1;
+        for (uint32_t c = 0; c < n_cls; c++) {
+          bool same = cls_w[c] == w;
+          for (int d = 0; d < 6; d++) same = same && cls_coef[c][d] == coef[d];
+          if (same) { cls = (int)c; break; }
+        }
+        if (cls < 0) {
+          if (n_cls == MAX_CLASSES) { overflow = 1; break; }
+          cls = (int)n_cls++;
+          for (int d = 0; d < 6; d++) cls_coef[cls][d] = coef[d];
+          cls_w[cls] = w;
+        }
+        if (n_ent >= P->trace_cap) { overflow = 1; break; }
+        if (j == 0) {
+          const uint32_t cap8 = (P->trace_cap + 7u) & ~7u;
+          int64_t* h64 = (int64_t*)(th + 1);
+          uint32_t* h32 = (uint32_t*)(h64 + 2 * (size_t)cap8);
+          dtrace_entry E;
+          E.off = off;
+          E.keylo = (k[0] << L2) | k[1];
+          uint64_t lim = w == 32 ? (1ull << 31) : (1ull << 63);
+          uint64_t nel = A.size_bytes >> lg;
+          E.bound = nel < lim ? nel : lim;
+          E.acc = D.x;
+          E.cls = (uint8_t)cls;
+          E.w = (uint8_t)w;
+          E.dead_kind = A.base == 0 ? CKC_KIND_NULL : ((A.flags & CKC_ALLOC_FREED) ? CKC_KIND_FREED : 0);
+          E.pad = 0;
+          te[n_ent] = E;
+          h64[2 * n_ent] = off;
+          h64[2 * n_ent + 1] = (int64_t)E.bound;
+          h32[2 * n_ent] = (uint32_t)off;
+          h32[2 * n_ent + 1] = (uint32_t)E.bound;
+          if (E.dead_kind) any_dead = 1;
+        }
+        n_ent++;
+        acc_per_thread++;
+        visit(D.s0);
+        if (op == CKC_OP_LOAD) {
+          // a LOAD whose value is used has a thread-invariant index here
+          uint64_t val = 0;
+          uint32_t kd = kind_of(A.base, A.size_bytes, A.flags, off, lg);
+          bool uni_idx = __ballot(j < 6 && v != 0) == 0;
+          if (!kd && uni_idx && A.data) {
+            val = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[off]
+                          : (uint64_t)((const int64_t*)A.data)[off];
+          }
+          RSET(D.dst, j == 6 ? val : 0ull);
+        }
+        break;
+      }
+      case CKC_OP_IF: {
+        uint64_t c = readlane64(rget(lo, hi, D.a), 6);
+        if (c != 0) {
+          visit(D.s0);
+        } else {
+          visit(D.s1);
+          pc = D.jmp;  // ELSE (its arm follows) or ENDIF
+        }
+        break;
+      }
+      case CKC_OP_ELSE: pc = D.jmp; break;  // end of the taken arm: skip to ENDIF
+      case CKC_OP_ENDIF: break;
+      case CKC_OP_LOOP: {
+        uint32_t d = D.x;
+        int64_t s = (int64_t)narrow(readlane64(rget(lo, hi, D.a), 6), w);
+        int64_t e = (int64_t)narrow(readlane64(rget(lo, hi, D.b), 6), w);
+        int64_t stp = (int64_t)narrow(readlane64(rget(lo, hi, D.c), 6), w);
+        uint64_t nt = trip_count(s, e, stp);
+        uint64_t cap = 1ull << (d == 0 ? cap_log2_0 : cap_log2_1);
+        uint64_t rn = nt < cap ? nt : cap;
+        if (d == 0) { run[0] = rn; lstart[0] = (uint64_t)s; lstep[0] = (uint64_t)stp; lhang[0] = nt > cap; k[0] = 0; }
+        else { run[1] = rn; lstart[1] = (uint64_t)s; lstep[1] = (uint64_t)stp; lhang[1] = nt > cap; k[1] = 0; }
+        if (rn == 0) {
+          if (nt > cap) { hang = 1; break; }  // cap 2^k >= 1, unreachable
+          visit(D.s1);
+          pc = D.jmp;  // ENDLOOP; continue after it
+          break;
+        }
+        RSET(D.dst, j == 6 ? narrow((uint64_t)s, w) : 0ull);
+        visit(D.s0);
+        break;
+      }
+      case CKC_OP_ENDLOOP: {
+        uint32_t d = D.x;
+        const dins Lp = I[D.jmp];
+        uint64_t kk = (d == 0 ? k[0] : k[1]) + 1;
+        uint64_t rn = d == 0 ? run[0] : run[1];
+        if (kk < rn) {
+          if (d == 0) k[0] = kk; else k[1] = kk;
+          uint64_t s0 = d == 0 ? lstart[0] : lstart[1], st0 = d == 0 ? lstep[0] : lstep[1];
+          RSET(Lp.dst, j == 6 ? narrow(s0 + kk * st0, Lp.w) : 0ull);
+          visit(Lp.s0);
+          pc = D.jmp;  // back to the LOOP; body follows
+        } else {
+          if (d == 0) k[0] = 0; else k[1] = 0;
+          if (d == 0 ? lhang[0] : lhang[1]) { hang = 1; break; }
+          visit(Lp.s1);
+        }
+        break;
+      }
+      default: {
+        // remaining ops only see thread-invariant operands here
+        uint32_t f = 0;
+        uint64_t r = alu(op, w, readlane64(rget(lo, hi, D.a), 6), readlane64(rget(lo, hi, D.b), 6), f);
+        faults_per_thread += f;
+        RSET(D.dst, j == 6 ? r : 0ull);
+        break;
+      }
+    }
+    pc++;
+  }
+  if (j == 0) {
+    th->n_entries = n_ent;
+    th->n_classes = n_cls;
+    th->overflow = overflow;
+    th->hang = hang;
+    th->any_dead = any_dead;
+    th->cap8 = (P->trace_cap + 7u) & ~7u;
+    for (uint32_t c = 0; c < n_cls; c++) {
+      for (int d = 0; d < 6; d++) th->coef[c][d] = cls_coef[c][d];
+      th->cls_w[c] = (uint8_t)cls_w[c];
+    }
+    st->accesses_checked = acc_per_thread;
+    st->arith_faults = faults_per_thread;
+    st->hang_lanes = hang;
+  }
+}
+
+__global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
+  const uint32_t i = blockIdx.x;
+  if (i >= a.n_inputs) return;
+  dinput& in = a.inputs[i];
+  const dprog* P = (const dprog*)in.prog;
+  const uint32_t j = threadIdx.x;
+  // records: no violation yet
+  ckc_record* rec = a.recs + in.rec_base;
+  for (uint32_t r = j; r < P->n_accesses; r += 64) {
+    ckc_record z;
+    z.first_key = ~0ull; z.index = 0; z.count = 0; z.kinds = 0; z.first_kind = 0;
+    rec[r] = z;
+  }
+  uint32_t* cnt = a.counts + in.cnt_base;
+  for (uint32_t s = j; s < P->n_sites; s += 64) cnt[s] = 0;
+  if (in.xstate)  // expanded tiles start with no iterations
+    for (uint64_t q = j; q < in.n_xt; q += 64) {
+      a.xtot[in.xt_begin + q] = 0;
+      a.xpb[in.xt_begin + q] = 0;
+    }
+  uint64_t lanes = set_lanes(in.mode, in.launch);
+  bool trace = (P->cls & CKC_CLS_UNIFORM) && !a.force_generic && in.trace != 0 && lanes > 0;
+  __syncthreads();
+  ckc_input_status* st = a.status + i;
+  if (j == 0) {
+    st->lanes = lanes; st->accesses_checked = 0; st->hang_lanes = 0; st->arith_faults = 0;
+    st->flags = 0; st->pad = 0;
+  }
+  uint32_t path = 1;
+  if (trace) {
+    dtrace_head* th = (dtrace_head*)in.trace;
+    const uint32_t cap8 = (P->trace_cap + 7u) & ~7u;
+    dtrace_entry* te = (dtrace_entry*)((uint8_t*)(th + 1) + (size_t)cap8 * 24);
+    build_trace(P, in, a.scalars + (size_t)i * MAX_SCALARS, (const ckc_alloc*)in.table, th, te, cnt, st);
+    __syncthreads();
+    path = th->overflow ? 1 : 0;
+    if (path == 1) {  // fall back: undo the per-thread counts
+      for (uint32_t s = j; s < P->n_sites; s += 64) cnt[s] = 0;
+      if (j == 0) { st->accesses_checked = 0; st->arith_faults = 0; st->hang_lanes = 0; }
+    }
+  }
+  if (j == 0) {
+    uint64_t tiles = (lanes + TILE - 1) / TILE;
+    const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
+    if (path == 0) {
+      if (in.mode != CKC_REP_CORNERS && bs % 64u == 0 && ((const dtrace_head*)in.trace)->n_classes == 1) {
+        // block-major jobs: (64-thread slice position, group of LPB set blocks)
+        const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
+                                                 : bset_size(in.launch);
+        const uint64_t jobs = (uint64_t)(bs / 64u) * ((nsb + LPB - 1) / LPB);
+        tiles = (jobs + 3) / 4;
+        path = PATH_BLOCKS;
+      } else {
+        path = PATH_LANES;
+      }
+    }
+    in.lanes = lanes;
+    in.path = path;
+    for (uint32_t q = 0; q < 3; q++) in.n_tiles[q] = q == path ? (uint32_t)tiles : 0u;
+  }
+}
+
+// Exclusive prefix of per-input tile counts for the three evaluators, taken in
+// tile-space order (a.order: position -> input).
+__global__ void __launch_bounds__(1024) scan_kernel(KArgs a) {
+  __shared__ unsigned long long part[3][1024 / 64];
+  __shared__ unsigned long long carry[3];
+  const uint32_t t = threadIdx.x;
+  if (t < 3) carry[t] = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < a.n_inputs; base += 1024) {
+    const uint32_t pos = base + t;
+    const uint32_t i = pos < a.n_inputs ? a.order[pos] : 0u;
+    uint64_t v[3], sc[3];
+    for (int p = 0; p < 3; p++) {
+      v[p] = pos < a.n_inputs ? a.inputs[i].n_tiles[p] : 0;
+      sc[p] = v[p];
+    }
+    for (int o = 1; o < 64; o <<= 1)  // inclusive wavefront scan
+      for (int p = 0; p < 3; p++) {
+        const uint64_t u = __shfl_up((unsigned long long)sc[p], o, 64);
+        if ((int)lane_id() >= o) sc[p] += u;
+      }
+    if (lane_id() == 63)
+      for (int p = 0; p < 3; p++) part[p][t / 64] = sc[p];
+    __syncthreads();
+    uint64_t w[3] = {0, 0, 0}, c[3];
+    for (int p = 0; p < 3; p++) {
+      for (uint32_t q = 0; q < t / 64; q++) w[p] += part[p][q];
+      c[p] = carry[p];
+    }
+    if (pos < a.n_inputs)
+      for (int p = 0; p < 3; p++) a.inputs[i].tile_begin[p] = c[p] + w[p] + sc[p] - v[p];
+    __syncthreads();
+    if (t == 1023)
+      for (int p = 0; p < 3; p++) carry[p] = c[p] + w[p] + sc[p];
+    __syncthreads();
+  }
+  if (t < 3) {
+    a.js->total_tiles[t] = carry[t];
+    a.js->next_tile[t] = 0;
+  }
+}
+
+// Position p (into a.order) of the input whose tiles hold t (t < total): the
+// largest p with tile_begin[path] of input order[p] <= t, which always has
+// tiles since the next position starts after t.
+__device__ __forceinline__ uint32_t find_pos(const dinput* in, const uint32_t* order, uint32_t n, uint32_t path,
+                                             uint64_t t) {
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (in[order[mid]].tile_begin[path] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Work distribution of a persistent evaluator over its `total` tiles: work
+// items are runs of `chunk` consecutive tiles.  BLOCKED: workgroup g takes
+// tiles [total*g/G, total*(g+1)/G); CYCLIC: items g, g+G, g+2G, ...;
+// DYNAMIC and LPT: items from an atomic counter (LPT's tile space lists the
+// inputs largest first).  sched_next is called by the whole workgroup and
+// returns the same tile in every lane, ~0 when the workgroup is done.
+template <uint32_t SK>
+struct Sched {
+  uint32_t chunk;
+  uint64_t total, cur, end, item;
+};
+template <uint32_t SK>
+__device__ __forceinline__ void sched_init(Sched<SK>& s, const KArgs& a, uint64_t total) {
+  s.chunk = a.chunk ? a.chunk : 1u;
+  s.total = total;
+  const uint64_t G = gridDim.x, g = blockIdx.x;
+  if (SK == CKC_SCHED_BLOCKED) {
+    s.cur = total * g / G;
+    s.end = total * (g + 1) / G;
+  } else if (SK == CKC_SCHED_CYCLIC) {
+    s.item = g;
+    s.cur = g * s.chunk;
+    s.end = s.cur + s.chunk < total ? s.cur + s.chunk : total;
+  } else {
+    s.cur = s.end = 0;
+  }
+}
+template <uint32_t SK>
+__device__ __forceinline__ uint64_t sched_next(Sched<SK>& s, unsigned long long* counter, unsigned long long* slot) {
+  if (s.cur < s.end) return s.cur++;
+  if (SK == CKC_SCHED_BLOCKED) return ~0ull;
+  uint64_t item;
+  if (SK == CKC_SCHED_CYCLIC) {
+    s.item += gridDim.x;
+    item = s.item;
+  } else {
+    __syncthreads();  // every wavefront has read the previous item
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1ull);
+    __syncthreads();
+    item = *slot;
+  }
+  const uint64_t b = item * s.chunk;
+  if (b >= s.total) {
+    s.cur = s.end = 0;
+    return ~0ull;
+  }
+  s.cur = b + 1;
+  s.end = b + s.chunk < s.total ? b + s.chunk : s.total;
+  return b;
+}
+// The schedule a kernel instantiation is compiled for (LPT runs DYNAMIC over
+// its own tile order).
+constexpr uint32_t sched_impl(uint32_t k) {
+  return k == CKC_SCHED_BLOCKED ? CKC_SCHED_BLOCKED : k == CKC_SCHED_CYCLIC ? CKC_SCHED_CYCLIC : CKC_SCHED_DYNAMIC;
+}
+
+// ---------------------------------------------------------------------------
+// Per input: trace-path totals from per-thread counts, then the dense map.
+__global__ void __launch_bounds__(256) finish_kernel(KArgs a) {
+  const uint32_t i = blockIdx.x;
+  if (i >= a.n_inputs) return;
+  const dinput& in = a.inputs[i];
+  const dprog* P = (const dprog*)in.prog;
+  uint32_t* cnt = a.counts + in.cnt_base;
+  const uint64_t lanes = in.lanes;
+  if (in.path != PATH_GENERIC) {
+    for (uint32_t s = threadIdx.x; s < P->n_sites; s += blockDim.x) {
+      uint64_t v = (uint64_t)cnt[s] * lanes;
+      cnt[s] = v > 255 ? 255u : (uint32_t)v;
+    }
+    if (threadIdx.x == 0) {
+      ckc_input_status* st = a.status + i;
+      st->accesses_checked *= lanes;
+      st->arith_faults *= lanes;
+      st->hang_lanes = st->hang_lanes ? lanes : 0;
+    }
+  }
+  __syncthreads();
+  if (a.maps) {
+    uint4* m = (uint4*)(a.maps + (size_t)i * 65536);
+    const uint4 z = {0, 0, 0, 0};
+    for (uint32_t q = threadIdx.x; q < 65536 / 16; q += blockDim.x) m[q] = z;
+    __syncthreads();
+    const uint16_t* ids = prog_sites(P);
+    uint8_t* mb = a.maps + (size_t)i * 65536;
+    for (uint32_t s = threadIdx.x; s < P->n_sites; s += blockDim.x) {
+      uint32_t c = cnt[s];
+      mb[ids[s]] = (uint8_t)(c > 255 ? 255 : c);
+    }
+  }
+}
+
+
+}  // namespace ckc

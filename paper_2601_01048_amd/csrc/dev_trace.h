@@ -1,0 +1,476 @@
+// dev_trace.h — the trace evaluator (uniform-control programs with affine indices).
+// Part of the device code of libckc; included by kernels.hip only (one
+// translation unit, no relocatable device code).
+#pragma once
+
+namespace ckc {
+
+// ---------------------------------------------------------------------------
+// trace evaluator
+// ---------------------------------------------------------------------------
+// Read-only job data is read through the constant address space so that
+// wavefront-uniform loads become scalar loads.
+typedef const __attribute__((address_space(4))) dtrace_entry c_entry;
+typedef const __attribute__((address_space(4))) dtrace_head c_head;
+typedef const __attribute__((address_space(4))) dinput c_input;
+typedef const __attribute__((address_space(4))) jobstate c_jobstate;
+typedef const __attribute__((address_space(4))) uint32_t c_u32;
+
+__device__ __forceinline__ uint32_t find_pos_c(c_input* in, c_u32* order, uint32_t n, uint32_t path, uint64_t t) {
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (in[order[mid]].tile_begin[path] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Position of the input holding tile t: the next one or two positions are
+// tried first (consecutive tiles of one workgroup), then a binary search.
+__device__ __forceinline__ uint32_t pos_of_tile(c_input* ins, c_u32* order, uint32_t n, uint32_t path,
+                                                uint32_t pos, uint64_t cur_end, uint64_t t) {
+  if (pos != 0xFFFFFFFFu && t >= cur_end) {
+    for (uint32_t q = pos + 1; q < n && q <= pos + 2; q++) {
+      const uint32_t i = order[q];
+      if (t >= ins[i].tile_begin[path] && t < ins[i].tile_begin[path] + ins[i].n_tiles[path]) return q;
+    }
+  }
+  return find_pos_c(ins, order, n, path, t);
+}
+
+// Violations found by the trace evaluator are merged per workgroup in LDS (first
+// key, count, kinds per access of the current input) and flushed into the job's
+// records once per input.  Every thread-set decode of this evaluator is
+// increasing in the global thread id along the lanes of a wavefront, and the
+// blocks of a wavefront job are increasing too, so the first violation of a
+// wavefront is its lowest violating lane.
+constexpr uint32_t TR_ACC_LDS = 256;
+struct TraceLds {
+  unsigned long long fk[TR_ACC_LDS];
+  unsigned long long cnt[TR_ACC_LDS];
+  uint32_t kinds[TR_ACC_LDS];
+};
+
+__device__ __forceinline__ void tr_note(TraceLds& S, ckc_record* rec, uint32_t acc, bool lds, uint64_t key,
+                                        uint64_t cnt, uint32_t kinds) {
+  if (lane_id() == 0) {
+    if (lds) {
+      atomicMin(&S.fk[acc], (unsigned long long)key);
+      atomicAdd(&S.cnt[acc], (unsigned long long)cnt);
+      atomicOr(&S.kinds[acc], kinds);
+    } else {
+      atomicMin((unsigned long long*)&rec[acc].first_key, (unsigned long long)key);
+      atomicAdd((unsigned long long*)&rec[acc].count, (unsigned long long)cnt);
+      atomicOr(&rec[acc].kinds, kinds);
+    }
+  }
+}
+
+__device__ void tr_flush(TraceLds& S, ckc_record* rec, uint32_t n_acc) {
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < n_acc && q < TR_ACC_LDS; q += TILE) {
+    if (S.cnt[q]) {
+      atomicMin((unsigned long long*)&rec[q].first_key, S.fk[q]);
+      atomicAdd((unsigned long long*)&rec[q].count, S.cnt[q]);
+      atomicOr(&rec[q].kinds, S.kinds[q]);
+      S.fk[q] = ~0ull;
+      S.cnt[q] = 0;
+      S.kinds[q] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// Out-of-line boundary-set decode (keeps its divisions off the FULL path).
+__device__ __forceinline__ uint64_t bset_block_call(uint32_t gx, uint32_t gy, uint32_t gz, uint64_t k) {
+  const uint32_t L[3] = {gx, gy, gz};
+  return bset_block(L, k);
+}
+
+typedef const __attribute__((address_space(4))) int64_t c_i64;
+typedef const __attribute__((address_space(4))) dprog c_dprog;
+
+// Violation path of entry e in a block-major job (rare): per block, the mask
+// of violating lanes and of negative indices; the first block with a
+// violation gives the first key at its lowest violating lane.
+template <int W, class BT>
+__device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint32_t e, uint64_t tpart,
+                                                 const BT* bp, const uint32_t* Lg, uint64_t g, uint32_t bs,
+                                                 uint32_t nvalid, uint32_t tlin_lane0, ckc_record* rec,
+                                                 bool lds, uint32_t Lsum) {
+  const int64_t off = te[e].off;
+  const uint64_t bound = te[e].bound;
+  const uint32_t dead = te[e].dead_kind;
+  uint64_t fk = ~0ull, cnt = 0;
+  uint32_t kinds = 0;
+  for (uint32_t j = 0; j < nvalid; j++) {
+    uint64_t badm, underm;
+    if (W == 32) {
+      const uint32_t v = (uint32_t)tpart + (uint32_t)off + (uint32_t)bp[j];
+      badm = __ballot(v >= (uint32_t)bound);
+      underm = __ballot((int32_t)v < 0);
+    } else {
+      const uint64_t v = tpart + (uint64_t)off + (uint64_t)bp[j];
+      badm = __ballot(v >= bound);
+      underm = __ballot((int64_t)v < 0);
+    }
+    if (dead) {
+      badm = ~0ull;
+      kinds |= dead;
+    } else {
+      underm &= badm;
+      kinds |= (underm ? CKC_KIND_UNDER : 0u) | ((badm & ~underm) ? CKC_KIND_OVER : 0u);
+    }
+    if (badm) {
+      if (fk == ~0ull) {
+        // block of member g*LPB + j of the thread set (Lg[6] holds the mode)
+        const uint64_t k = g * LPB + j;
+        const uint64_t blin = Lg[6] == CKC_FULL ? k : bset_block(Lg, k);
+        fk = ((blin * bs + tlin_lane0 + (uint64_t)(__ffsll((unsigned long long)badm) - 1)) << Lsum) |
+             te[e].keylo;
+      }
+      cnt += (uint64_t)__popcll(badm);
+    }
+  }
+  if (cnt) tr_note(S, rec, te[e].acc, lds, fk, cnt, kinds);
+}
+
+// Block-major checks of one wavefront job: this lane's thread position in up to
+// LPB set blocks; tpart is the thread part of the index base, bp[j] the block
+// parts (wavefront-uniform).  Entries come as packed (offset, bound) pairs
+// through scalar loads.  Width 32: an index is in bounds iff its unsigned
+// value is below the bound (clamped to 2^31), so one entry is clean for all
+// blocks iff the unsigned maximum over the blocks is below the bound -- one
+// add per block, a max tree and one compare.
+template <int W, bool ALL, class BT>
+__device__ __forceinline__ bool entry_bad(uint64_t tpart, uint64_t off, uint64_t bnd, const BT* bp,
+                                          uint32_t nvalid) {
+  if (W == 32) {
+    const uint32_t t = (uint32_t)tpart + (uint32_t)off;
+    uint32_t mx = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < LPB; j++) {
+      const uint32_t v = t + (uint32_t)bp[j];
+      if (ALL || j < nvalid) mx = v > mx ? v : mx;
+    }
+    return mx >= (uint32_t)bnd;
+  } else {
+    const uint64_t t = tpart + off;
+    bool x = false;
+#pragma unroll
+    for (uint32_t j = 0; j < LPB; j++)
+      if (ALL || j < nvalid) x |= (t + (uint64_t)bp[j]) >= bnd;
+    return x;
+  }
+}
+
+template <int W, bool ALL, bool DEADS, class BT>
+__device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h64, c_u32* h32, uint32_t ne,
+                                             uint64_t tpart, const BT* bp, const uint32_t* Lg, uint64_t g,
+                                             uint32_t bs, uint32_t nvalid, uint32_t tlin_lane0,
+                                             ckc_record* rec, bool lds, uint32_t Lsum) {
+  constexpr uint32_t EB = W == 32 ? 8 : 4;  // entries per scalar-load batch
+  uint32_t e = 0;  // first entry that needs the violation path
+  if (!DEADS) {
+    // fast scan: stop at the first entry with a violating lane
+    const uint32_t neb = ne - ne % EB;
+    bool hit = false;
+    for (uint32_t e0 = 0; e0 < neb && !hit; e0 += EB) {
+      uint64_t off[EB], bnd[EB];
+#pragma unroll
+      for (uint32_t k = 0; k < EB; k++) {
+        if (W == 32) {
+          off[k] = h32[2 * (e0 + k)];
+          bnd[k] = h32[2 * (e0 + k) + 1];
+        } else {
+          off[k] = (uint64_t)h64[2 * (e0 + k)];
+          bnd[k] = (uint64_t)h64[2 * (e0 + k) + 1];
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < EB; k++) {
+        if (!hit && __ballot(entry_bad<W, ALL>(tpart, off[k], bnd[k], bp, nvalid))) {
+          hit = true;
+          e = e0 + k;
+        }
+      }
+      if (!hit) e = e0 + EB;
+    }
+    if (!hit) {
+      for (; e < ne; e++) {
+        uint64_t off, bnd;
+        if (W == 32) {
+          off = h32[2 * e];
+          bnd = h32[2 * e + 1];
+        } else {
+          off = (uint64_t)h64[2 * e];
+          bnd = (uint64_t)h64[2 * e + 1];
+        }
+        if (__ballot(entry_bad<W, ALL>(tpart, off, bnd, bp, nvalid))) break;
+      }
+    }
+    if (e >= ne) return;
+  }
+  // violation path: the remaining entries one by one (one copy of this code)
+  for (; e < ne; e++) {
+    uint64_t off, bnd;
+    if (W == 32) {
+      off = h32[2 * e];
+      bnd = h32[2 * e + 1];
+    } else {
+      off = (uint64_t)h64[2 * e];
+      bnd = (uint64_t)h64[2 * e + 1];
+    }
+    if (DEADS || __ballot(entry_bad<W, false>(tpart, off, bnd, bp, nvalid)))
+      blocks_violation<W>(S, te, e, tpart, bp, Lg, g, bs, nvalid, tlin_lane0, rec, lds, Lsum);
+  }
+}
+
+// Per-input state of the trace evaluator (wavefront-uniform).
+struct TrIn {
+  uint32_t L[7];  // launch dims, then the thread-set mode
+  uint32_t bs, gxy, bxy, mode, Lsum, ne, n_acc;
+  UDiv dgx, dgxy, dbx, dbxy, dspb;
+  uint64_t nsb;
+  c_head* th;     // coefficients are re-read per job (scalar loads)
+  uint32_t any_dead;
+  bool lds;
+  c_entry* te;
+  c_i64* h64;
+  c_u32* h32;
+  ckc_record* rec;
+};
+
+// One block-major wavefront job: slice position o (64 threads) of the blocks
+// g*LPB .. g*LPB+LPB-1 of the set.
+template <int W>
+__device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint64_t g, uint32_t o) {
+  typedef typename std::conditional<W == 32, uint32_t, uint64_t>::type BT;
+  const uint32_t tlin = o * 64u + (threadIdx.x & 63u);
+  const uint32_t tz = udiv(tlin, I.dbxy), tr = tlin - tz * I.bxy;
+  const uint32_t ty = udiv(tr, I.dbx);
+  const uint32_t tx = tr - ty * I.L[3];
+  const int64_t k0 = I.th->coef[0][0], k1 = I.th->coef[0][1], k2 = I.th->coef[0][2];
+  const int64_t k3 = I.th->coef[0][3], k4 = I.th->coef[0][4], k5 = I.th->coef[0][5];
+  uint64_t tpart = 0;
+  if (k0 == 1) tpart += tx; else if (k0 != 0) tpart += (uint64_t)k0 * tx;
+  if (k1 == 1) tpart += ty; else if (k1 != 0) tpart += (uint64_t)k1 * ty;
+  if (k2 == 1) tpart += tz; else if (k2 != 0) tpart += (uint64_t)k2 * tz;
+  BT bp[LPB];
+  const uint64_t left = I.nsb - g * LPB;
+  const uint32_t nvalid = left < LPB ? (uint32_t)left : LPB;
+  if (I.mode == CKC_FULL) {
+    // blocks g*LPB ..: walk x with carries from the first one
+    const uint32_t b0 = (uint32_t)(g * LPB);
+    uint32_t bz = udiv(b0, I.dgxy), brem = b0 - bz * I.gxy;
+    uint32_t by = udiv(brem, I.dgx), bx = brem - by * I.L[0];
+#pragma unroll
+    for (uint32_t jj = 0; jj < LPB; jj++) {
+      bp[jj] = (BT)((uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz);
+      if (++bx == I.L[0]) {
+        bx = 0;
+        if (++by == I.L[1]) { by = 0; ++bz; }
+      }
+    }
+  } else {
+    for (uint32_t jj = 0; jj < LPB; jj++) {
+      const uint32_t blin = jj < nvalid ? (uint32_t)bset_block_call(I.L[0], I.L[1], I.L[2], g * LPB + jj) : 0u;
+      const uint32_t bz = udiv(blin, I.dgxy), brem = blin - bz * I.gxy;
+      const uint32_t by = udiv(brem, I.dgx), bx = brem - by * I.L[0];
+      bp[jj] = (BT)((uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz);
+    }
+  }
+  const uint32_t t0 = o * 64u;
+  if (I.any_dead) {
+    trace_blocks<W, false, true>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+  } else if (nvalid == LPB) {
+    trace_blocks<W, true, false>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+  } else {
+    trace_blocks<W, false, false>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+  }
+}
+
+// Per-lane checks of one lane tile (thread sets without the block-major
+// layout).  The lowest violating lane has the smallest key.
+__device__ __forceinline__ void lanes_violation(TraceLds& S, c_entry* te, uint32_t e, uint64_t v, bool act,
+                                                uint64_t gtid, ckc_record* rec, bool lds, uint32_t Lsum) {
+  const uint32_t w = te[e].w;
+  const uint64_t bound = te[e].bound;
+  const uint32_t dead = te[e].dead_kind;
+  uint64_t badm, underm;
+  if (w == 32) {
+    badm = __ballot(act && (uint32_t)v >= (uint32_t)bound);
+    underm = __ballot(act && (int32_t)(uint32_t)v < 0);
+  } else {
+    badm = __ballot(act && v >= bound);
+    underm = __ballot(act && (int64_t)v < 0);
+  }
+  uint32_t kinds;
+  if (dead) {
+    badm = __ballot(act);
+    kinds = dead;
+  } else {
+    underm &= badm;
+    kinds = (underm ? CKC_KIND_UNDER : 0u) | ((badm & ~underm) ? CKC_KIND_OVER : 0u);
+  }
+  if (!badm) return;
+  const int first = __ffsll((unsigned long long)badm) - 1;
+  const uint64_t key = (readlane64(gtid, first) << Lsum) | te[e].keylo;
+  tr_note(S, rec, te[e].acc, lds, key, (uint64_t)__popcll(badm), kinds);
+}
+
+// Loads the per-input state of the trace evaluator.
+__device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_record* recs, uint64_t& tb,
+                                        uint32_t path, uint32_t& ncls, uint32_t& w0, c_head*& th) {
+  for (int q = 0; q < 6; q++) I.L[q] = ins[i].launch[q];
+  I.L[6] = ins[i].mode;
+  I.bs = I.L[3] * I.L[4] * I.L[5];
+  I.gxy = I.L[0] * I.L[1];
+  I.bxy = I.L[3] * I.L[4];
+  I.dgx = udiv_make(I.L[0]);
+  I.dgxy = udiv_make(I.gxy);
+  I.dbx = udiv_make(I.L[3]);
+  I.dbxy = udiv_make(I.bxy);
+  I.dspb = udiv_make(I.bs >= 64 ? I.bs / 64u : 1u);
+  I.mode = ins[i].mode;
+  I.Lsum = ins[i].L1 + ins[i].L2;
+  I.n_acc = ((c_dprog*)ins[i].prog)->n_accesses;
+  I.lds = I.n_acc <= TR_ACC_LDS;
+  th = (c_head*)ins[i].trace;
+  const uint32_t cap8 = th->cap8;
+  I.h64 = (c_i64*)(th + 1);
+  I.h32 = (c_u32*)(I.h64 + 2 * (size_t)cap8);
+  I.te = (c_entry*)(I.h32 + 2 * (size_t)cap8);
+  I.any_dead = th->any_dead;
+  I.rec = recs + ins[i].rec_base;
+  I.ne = th->n_entries;
+  ncls = th->n_classes;
+  w0 = th->cls_w[0];
+  I.nsb = I.mode == CKC_FULL ? (uint64_t)I.L[0] * I.L[1] * I.L[2] : bset_size(I.L);
+  I.th = th;
+  tb = ins[i].tile_begin[path];
+}
+
+// Trace evaluator, block-major layout: persistent workgroups over the tile
+// space of PATH_BLOCKS under the job's schedule; a tile is four wavefront jobs.
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
+  __shared__ TraceLds S;
+  __shared__ unsigned long long item_slot;
+  c_jobstate* js = (c_jobstate*)a.js;
+  c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
+  const uint64_t total = js->total_tiles[PATH_BLOCKS];
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t q = tid; q < TR_ACC_LDS; q += TILE) {
+    S.fk[q] = ~0ull;
+    S.cnt[q] = 0;
+    S.kinds[q] = 0;
+  }
+  __syncthreads();
+  uint32_t pos = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint64_t tb = 0, cur_end = 0;
+  c_head* th = nullptr;
+  TrIn I;
+  for (;;) {
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_BLOCKS], &item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      const uint32_t np = pos_of_tile(ins, order, a.n_inputs, PATH_BLOCKS, pos, cur_end, t);
+      if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+      pos = np;
+      const uint32_t i = order[pos];
+      tr_load(I, ins, i, a.recs, tb, PATH_BLOCKS, ncls, w0, th);
+      cur_end = tb + ins[i].n_tiles[PATH_BLOCKS];
+    }
+    const uint32_t wv = ufirst(tid >> 6);
+    const uint64_t job = (t - tb) * 4 + wv;
+    const uint32_t spb = I.bs / 64u;
+    const uint64_t g = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, I.dspb) : job / spb;
+    const uint32_t o = (uint32_t)(job - g * spb);
+    if (g * LPB >= I.nsb) continue;  // past the last group (whole wavefront)
+    if (w0 == 32) block_job<32>(S, I, g, o);
+    else block_job<64>(S, I, g, o);
+  }
+  if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+}
+
+// Trace evaluator over lane tiles (thread sets or traces the block-major
+// layout does not cover): TILE consecutive lanes of the thread set per tile.
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
+  __shared__ TraceLds S;
+  __shared__ unsigned long long item_slot;
+  c_jobstate* js = (c_jobstate*)a.js;
+  c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
+  const uint64_t total = js->total_tiles[PATH_LANES];
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t q = tid; q < TR_ACC_LDS; q += TILE) {
+    S.fk[q] = ~0ull;
+    S.cnt[q] = 0;
+    S.kinds[q] = 0;
+  }
+  __syncthreads();
+  uint32_t pos = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint64_t tb = 0, cur_end = 0, lanes = 0;
+  c_head* th = nullptr;
+  TrIn I;
+  for (;;) {
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_LANES], &item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      const uint32_t np = pos_of_tile(ins, order, a.n_inputs, PATH_LANES, pos, cur_end, t);
+      if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+      pos = np;
+      const uint32_t i = order[pos];
+      tr_load(I, ins, i, a.recs, tb, PATH_LANES, ncls, w0, th);
+      cur_end = tb + ins[i].n_tiles[PATH_LANES];
+      lanes = ins[i].lanes;
+    }
+    const uint64_t l = (t - tb) * TILE + tid;
+    const bool act = l < lanes;
+    Thr T;
+    decode_lane(I.mode, I.L, act ? l : 0, T);
+    const uint32_t c6[6] = {T.t[0], T.t[1], T.t[2], T.b[0], T.b[1], T.b[2]};
+    // base of each coefficient class: sum of coefficient x coordinate,
+    // skipping zero coefficients (uniform branches)
+    uint64_t base[MAX_CLASSES];
+#pragma unroll
+    for (int c = 0; c < MAX_CLASSES; c++) {
+      uint64_t b = 0;
+      if ((uint32_t)c < ncls) {
+#pragma unroll
+        for (int d = 0; d < 6; d++) {
+          const int64_t k = th->coef[c][d];
+          if (k == 1) b += c6[d];
+          else if (k != 0) b += (uint64_t)k * c6[d];
+        }
+      }
+      base[c] = b;
+    }
+    c_entry* te = I.te;
+    for (uint32_t e = 0; e < I.ne; e++) {
+      const uint32_t c = te[e].cls;
+      const uint64_t b = c == 0 ? base[0] : c == 1 ? base[1] : c == 2 ? base[2] : base[3];
+      const uint64_t v = b + (uint64_t)te[e].off;
+      bool x;
+      if (te[e].w == 32) x = (uint32_t)v >= (uint32_t)te[e].bound;
+      else x = v >= te[e].bound;
+      if (__ballot(act && x) || te[e].dead_kind) lanes_violation(S, te, e, v, act, T.gtid, I.rec, I.lds, I.Lsum);
+    }
+  }
+  if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+}
+
+
+}  // namespace ckc
