@@ -67,7 +67,10 @@ enum ckc_prog_class {
   CKC_CLS_I64 = 8,        /* some access index has width 64 */
   CKC_CLS_UNIFORM = 16,   /* control flow is thread-invariant and every index is
                              affine: evaluated as a per-input access trace */
-  CKC_CLS_EXPANDED = 32   /* one loop is evaluated one lane per iteration */
+  CKC_CLS_EXPANDED = 32,  /* one loop is evaluated one lane per iteration */
+  CKC_CLS_GATHER = 64     /* that loop's body is straight-line with indices affine in
+                             the counter or in one loaded value (an indirect gather),
+                             evaluated from per-input entries rather than interpreted */
 };
 
 typedef struct ckc_ctx_s* ckc_ctx;

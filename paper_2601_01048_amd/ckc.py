@@ -21,7 +21,7 @@ SCHED_DEFAULT, SCHED_BLOCKED, SCHED_CYCLIC, SCHED_DYNAMIC, SCHED_LPT = 0, 1, 2, 
 SCHED_NAMES = {0: "default", 1: "blocked", 2: "cyclic", 3: "dynamic", 4: "lpt"}
 DENSE_MAP = 2
 WAIT, DST_DEVICE = 1, 2
-CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32)
+CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32, GATHER=64)
 
 RECORD_DTYPE = np.dtype([("first_key", "<u8"), ("index", "<i8"), ("count", "<u8"),
                          ("kinds", "<u4"), ("first_kind", "<u4")])

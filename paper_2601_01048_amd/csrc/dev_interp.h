@@ -27,11 +27,32 @@ __device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
 
 typedef const __attribute__((address_space(4))) ckc_alloc c_alloc;
 
+// One access of a gather body: index = narrow(off + coef * X[var], w) with
+// X[0] the loop counter and X[k] (k >= 1) the value of the k-th LOAD of the
+// body (var 0xFF: a uniform index `off`).
+constexpr uint32_t MAX_GENT = 32;
+struct GEnt {
+  int64_t coef, off;
+  uint32_t acc;
+  uint16_t site;
+  uint8_t slot, lg;
+  uint8_t w, var, dst;  // dst: variable a LOAD defines (0 for ACCESS)
+  uint8_t pad[5];
+};
+static_assert(sizeof(GEnt) == 32, "gather entry layout");
+struct GBody {
+  GEnt e[MAX_GENT];
+  uint32_t n, ok, faults;  // entries, usable, division faults per iteration
+  uint8_t var[NREG];       // symbolic walk: variable of each register (0xFF uniform)
+};
+
 struct GenLds {
   uint32_t sites[MAX_SITES_LDS];
   unsigned long long wsum[TILE / 64];
   unsigned long long acc_checked, hangs, faults;
   unsigned long long pref[TILE + 1];  // trip-count prefix of the tile's threads (expanded loop)
+  GBody gb;                           // gather entries of the current input (body pass)
+  unsigned long long xstart[TILE], xstep[TILE];  // loop start and step of the tile's threads (gather pass)
 };
 
 // Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
@@ -68,7 +89,7 @@ struct Ctx {
   // live-ins; xn entries each), the tile's first lane and expanded tile
   uint64_t* xs;
   uint64_t xn, lane0, xt;
-  unsigned long long *xtot, *xpb;
+  unsigned long long *xtot, *xpb, *xpg;
   uint32_t* xin;
   uint32_t input;
   // fix-up target
@@ -243,7 +264,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
           if (tid == TILE - 1) {
             const uint64_t tot = pre + cnt;
             C.xtot[C.xt] = tot;
-            C.xpb[C.xt] = (tot + PIECE - 1) / PIECE;
+            (P->body_gather ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
             C.xin[C.xt] = C.input;
           }
           __syncthreads();
@@ -349,6 +370,7 @@ __device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, const dinput& i
   C.xn = in.xn;
   C.xtot = a.xtot;
   C.xpb = a.xpb;
+  C.xpg = a.xpg;
   C.xin = a.xin;
   C.input = i;
   C.lane0 = 0;
@@ -444,26 +466,29 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
 // (a.xpb, a.n_xtiles entries) in three steps: per-block sums of XSB entries,
 // a scan of the block sums (which also stores the total), per-block rescans.
 constexpr uint32_t XSB = 4096;
-__global__ void __launch_bounds__(256) xscan_sums_kernel(KArgs a) {
+__global__ void __launch_bounds__(256) xscan_sums_kernel(KArgs a, uint32_t which) {
   __shared__ unsigned long long part[4];
+  unsigned long long* xp = which ? a.xpg : a.xpb;
+  unsigned long long* bsum = a.xbsum + which * gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * XSB;
   unsigned long long v = 0;
   for (uint32_t q = threadIdx.x; q < XSB; q += 256)
-    if (b0 + q < a.n_xtiles) v += a.xpb[b0 + q];
+    if (b0 + q < a.n_xtiles) v += xp[b0 + q];
   v = wave_sum64(v);
   if (lane_id() == 0) part[threadIdx.x / 64] = v;
   __syncthreads();
-  if (threadIdx.x == 0) a.xbsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+  if (threadIdx.x == 0) bsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
-__global__ void __launch_bounds__(1024) xscan_blocks_kernel(KArgs a, uint32_t n_blocks) {
+__global__ void __launch_bounds__(1024) xscan_blocks_kernel(KArgs a, uint32_t n_blocks, uint32_t which) {
   __shared__ unsigned long long part[16];
   __shared__ unsigned long long carry;
+  unsigned long long* bsum = a.xbsum + which * n_blocks;
   const uint32_t t = threadIdx.x;
   if (t == 0) carry = 0;
   __syncthreads();
   for (uint32_t base = 0; base < n_blocks; base += 1024) {
     const uint32_t i = base + t;
-    const uint64_t v = i < n_blocks ? a.xbsum[i] : 0;
+    const uint64_t v = i < n_blocks ? bsum[i] : 0;
     uint64_t sc = v;
     for (int o = 1; o < 64; o <<= 1) {
       const uint64_t u = __shfl_up((unsigned long long)sc, o, 64);
@@ -474,25 +499,26 @@ __global__ void __launch_bounds__(1024) xscan_blocks_kernel(KArgs a, uint32_t n_
     uint64_t w = 0;
     for (uint32_t q = 0; q < t / 64; q++) w += part[q];
     const uint64_t c = carry;
-    if (i < n_blocks) a.xbsum[i] = c + w + sc - v;
+    if (i < n_blocks) bsum[i] = c + w + sc - v;
     __syncthreads();
     if (t == 1023) carry = c + w + sc;
     __syncthreads();
   }
   if (t == 0) {
-    a.js->total_pieces = carry;
-    a.js->next_piece = 0;
+    a.js->total_pieces[which] = carry;
+    a.js->next_piece[which] = 0;
   }
 }
-__global__ void __launch_bounds__(256) xscan_apply_kernel(KArgs a) {
+__global__ void __launch_bounds__(256) xscan_apply_kernel(KArgs a, uint32_t which) {
   __shared__ unsigned long long part[4];
   __shared__ unsigned long long carry;
+  unsigned long long* xp = which ? a.xpg : a.xpb;
   const uint64_t b0 = (uint64_t)blockIdx.x * XSB;
-  if (threadIdx.x == 0) carry = a.xbsum[blockIdx.x];
+  if (threadIdx.x == 0) carry = a.xbsum[which * gridDim.x + blockIdx.x];
   __syncthreads();
   for (uint32_t base = 0; base < XSB; base += 256) {
     const uint64_t e = b0 + base + threadIdx.x;
-    const uint64_t v = e < a.n_xtiles ? a.xpb[e] : 0;
+    const uint64_t v = e < a.n_xtiles ? xp[e] : 0;
     uint64_t sc = v;
     for (int o = 1; o < 64; o <<= 1) {
       const uint64_t u = __shfl_up((unsigned long long)sc, o, 64);
@@ -503,7 +529,7 @@ __global__ void __launch_bounds__(256) xscan_apply_kernel(KArgs a) {
     uint64_t w = 0;
     for (uint32_t q = 0; q < threadIdx.x / 64; q++) w += part[q];
     const uint64_t c = carry;
-    if (e < a.n_xtiles) a.xpb[e] = c + w + sc - v;
+    if (e < a.n_xtiles) xp[e] = c + w + sc - v;
     __syncthreads();
     if (threadIdx.x == 255) carry = c + w + sc;
     __syncthreads();
@@ -522,16 +548,181 @@ __device__ __forceinline__ uint64_t find_xtile(const unsigned long long* xpb, ui
   return lo;
 }
 
-// The body pass of expanded loops: work items are pieces of PIECE consecutive
-// iterations of one tile's flattened iteration space; each lane runs one
-// iteration (owner thread by binary search in the tile's prefix).
+// Builds the gather entries of the expanded body for the current input
+// (wavefront 0; lane 0 holds the constant part of each register, lane 1 its
+// coefficient of the register's variable).  `live` is the owner thread's lane
+// whose stored live-ins are used (they are uniform over the input).
+__device__ void build_gather(GenLds& S, uint64_t* R, const Ctx& C, uint32_t lpc, uint32_t endpc, uint64_t live) {
+  const uint32_t j = lane_id();
+  c_dprog* P = C.P;
+  c_dins* I = C.I;
+  GBody& G = S.gb;
+  auto rg = [&](uint32_t r) -> uint64_t& { return R[r * TILE + j]; };
+  // one wavefront: its LDS accesses are performed in program order
+  if (j == 0) { G.n = 0; G.ok = 1; G.faults = 0; }
+  for (uint32_t r = j; r < NREG; r += 64) G.var[r] = 0xFF;
+  const uint32_t nl = P->n_livein;
+  for (uint32_t q = 0; q < nl; q++) {
+    const uint32_t r = ufirst(P->livein[q]);
+    if (j < 2) rg(r) = j == 0 ? C.xs[(3 + q) * C.xn + live] : 0ull;
+  }
+  const dins L = ld_ins(I, lpc);
+  const uint32_t ctr = ufirst(L.dst);
+  if (j < 2) rg(ctr) = j == 0 ? 0ull : 1ull;
+  if (j == 0) G.var[ctr] = 0;
+  uint32_t n_load = 0, ok = 1, n = 0, faults = 0;
+  for (uint32_t pc = lpc + 1; pc < endpc && ok; pc++) {
+    const dins D = ld_ins(I, pc);
+    const uint32_t op = D.op, w = D.w;
+    const uint32_t da = ufirst(D.a), db = ufirst(D.b), dc = ufirst(D.c), dd = ufirst(D.dst);
+    const uint64_t a = j < 2 ? rg(da) : 0, b = j < 2 ? rg(db) : 0, c = j < 2 ? rg(dc) : 0;
+    const uint32_t va = G.var[da], vb = G.var[db];
+    uint64_t r = 0;
+    uint32_t rv = 0xFF;
+    bool wr = true;
+    switch (op) {
+      case CKC_OP_CONST: r = j == 0 ? narrow((uint64_t)C.K[D.x], w) : 0; break;
+      case CKC_OP_SCALAR: r = j == 0 ? narrow((uint64_t)C.sc[D.x], w) : 0; break;
+      case CKC_OP_SPECIAL:
+        if (D.x < 6) { ok = 0; break; }
+        r = j == 0 ? (D.x < 9 ? C.in->launch[3 + D.x - 6] : C.in->launch[D.x - 9]) : 0;
+        break;
+      case CKC_OP_ACCESS:
+      case CKC_OP_LOAD: {
+        if (n >= MAX_GENT) { ok = 0; break; }
+        const uint64_t off = readlane64(a, 0), coef = readlane64(a, 1);
+        if (j == 0) {
+          GEnt& E = G.e[n];
+          E.coef = va == 0xFF ? 0 : (int64_t)coef;
+          E.off = (int64_t)off;
+          E.acc = D.x;
+          E.site = D.s0;
+          E.slot = D.slot;
+          E.lg = D.fl & 3u;
+          E.w = (uint8_t)w;
+          E.var = (uint8_t)va;
+          E.dst = op == CKC_OP_LOAD ? (uint8_t)(n_load + 1) : 0;
+        }
+        n++;
+        if (op == CKC_OP_LOAD) {
+          n_load++;
+          r = j == 1 ? 1ull : 0ull;
+          rv = n_load;
+        } else {
+          wr = false;
+        }
+        break;
+      }
+      case CKC_OP_ADD: case CKC_OP_SUB:
+        if (va != 0xFF && vb != 0xFF && va != vb) { ok = 0; break; }
+        r = narrow(op == CKC_OP_ADD ? a + b : a - b, w);
+        rv = va != 0xFF ? va : vb;
+        break;
+      case CKC_OP_MUL:
+        if (va != 0xFF && vb != 0xFF) { ok = 0; break; }
+        r = narrow(va != 0xFF ? a * readlane64(b, 0) : b * readlane64(a, 0), w);
+        rv = va != 0xFF ? va : vb;
+        if (va == 0xFF && vb == 0xFF) r = j == 0 ? narrow(readlane64(a, 0) * readlane64(b, 0), w) : 0;
+        break;
+      case CKC_OP_SHL:
+        if (vb != 0xFF) { ok = 0; break; }
+        r = narrow(a << (readlane64(b, 0) & (uint64_t)(w - 1)), w);
+        rv = va;
+        break;
+      case CKC_OP_SELECT:
+        if (va != 0xFF || vb != 0xFF || G.var[dc] != 0xFF) { ok = 0; break; }
+        r = j == 0 ? narrow(readlane64(a, 0) != 0 ? readlane64(b, 0) : readlane64(c, 0), w) : 0;
+        break;
+      case CKC_OP_SEXT: case CKC_OP_TRUNC:
+        if (va != 0xFF) { ok = 0; break; }
+        r = j == 0 ? narrow(readlane64(a, 0), 32) : 0;
+        break;
+      case CKC_OP_ZEXT:
+        if (va != 0xFF) { ok = 0; break; }
+        r = j == 0 ? (readlane64(a, 0) & 0xFFFFFFFFull) : 0;
+        break;
+      default: {
+        if (op < CKC_OP_ADD || op > CKC_OP_CMPLEU || va != 0xFF || vb != 0xFF) { ok = 0; break; }
+        uint32_t f = 0;
+        const uint64_t v = alu(op, w, readlane64(a, 0), readlane64(b, 0), f);
+        faults += f;
+        r = j == 0 ? v : 0;
+        break;
+      }
+    }
+    if (ok && wr) {
+      if (j < 2) rg(dd) = r;
+      if (j == 0) G.var[dd] = (uint8_t)rv;
+    }
+  }
+  if (j == 0) { G.n = n; G.ok = ok; G.faults = faults; }
+}
+
+// Evaluates one chunk of a gather body: X lives in the register file rows
+// 0..7 of the lane.  `k` is the lane's iteration, `ctr` the counter value.
+__device__ __forceinline__ void run_gather(GenLds& S, uint64_t* R, const Ctx& C, Lane& ln, uint64_t& sat,
+                                           uint64_t ctr) {
+  const bool act = ln.dis == 0;
+  R[threadIdx.x] = ctr;
+  const uint32_t n = S.gb.n;
+  const uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2);
+  const uint64_t am = __ballot(act);
+  for (uint32_t e = 0; e < n; e++) {
+    const GEnt& E = S.gb.e[e];
+    const uint32_t var = ufirst(E.var), slot = ufirst(E.slot), lg = ufirst(E.lg), w = ufirst(E.w);
+    const uint64_t coef = ufirst64((uint64_t)E.coef), off = ufirst64((uint64_t)E.off);
+    uint64_t v = off;
+    if (var != 0xFF) {
+      const uint64_t x = R[var * TILE + threadIdx.x];
+      v = coef == 1 ? off + x : off + coef * x;
+    }
+    const int64_t idx = (int64_t)narrow(v, w);
+    c_alloc& A = C.tab[slot];
+    const uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
+    count_site(S, C, sat, ufirst(E.site), am);
+    if (__ballot(kd != 0)) merge_violation(C.rec + ufirst(E.acc), kd, key);
+    const uint32_t dst = ufirst(E.dst);
+    if (dst) {
+      uint64_t x = 0;
+      if (act && kd == 0)
+        x = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
+      R[dst * TILE + threadIdx.x] = x;
+    }
+  }
+  if (act) {
+    ln.acc += n;
+    ln.faults += S.gb.faults;
+  }
+}
+
+// Owner of iteration g in a tile: the largest o with pref[o] <= g.
+__device__ __forceinline__ uint32_t owner_of(const GenLds& S, uint64_t g) {
+  uint32_t l2 = 0, h2 = TILE - 1;
+  while (l2 < h2) {
+    const uint32_t m = (l2 + h2 + 1) >> 1;
+    if (S.pref[m] <= g) l2 = m;
+    else h2 = m - 1;
+  }
+  return l2;
+}
+
+// Piece p of body pass `which` (0 interpreted, 1 gather): its expanded tile
+// and input.  Uniform.
+__device__ __forceinline__ void piece_tile(const KArgs& a, uint32_t which, uint64_t p, uint64_t& xt, uint32_t& i) {
+  xt = ufirst64(find_xtile(which ? a.xpg : a.xpb, a.n_xtiles, p));
+  i = ufirst(a.xin[xt]);
+}
+
+// The body pass of interpreted expanded loops: work items are pieces of PIECE
+// consecutive iterations of one tile's flattened iteration space; each lane
+// runs one iteration (owner thread by binary search in the tile's prefix).
 template <uint32_t SK>
 __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // [n_regs][TILE]
   __shared__ unsigned long long item_slot;
   const uint32_t tid = threadIdx.x;
-  const uint64_t total = a.js->total_pieces;
+  const uint64_t total = a.js->total_pieces[0];
   if (total == 0) return;
   Sched<SK> sc;
   sched_init(sc, a, total);
@@ -545,10 +736,11 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
   lane_zero_totals(ln);
   for (;;) {
     __syncthreads();
-    const uint64_t p = sched_next(sc, &a.js->next_piece, &item_slot);
+    const uint64_t p = sched_next(sc, &a.js->next_piece[0], &item_slot);
     if (p == ~0ull) break;
-    const uint64_t xt = ufirst64(find_xtile(a.xpb, a.n_xtiles, p));
-    const uint32_t i = ufirst(a.xin[xt]);
+    uint64_t xt;
+    uint32_t i;
+    piece_tile(a, 0, p, xt, i);
     const dinput& in = a.inputs[i];
     if (i != cur) {
       if (cur != 0xFFFFFFFFu) {
@@ -584,16 +776,7 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
     for (uint64_t base = it0; base < it1; base += TILE) {
       const uint64_t g = base + tid;
       const bool ga = g < it1;
-      uint32_t o = 0;
-      if (ga) {
-        uint32_t l2 = 0, h2 = TILE - 1;
-        while (l2 < h2) {
-          const uint32_t m = (l2 + h2 + 1) >> 1;
-          if (S.pref[m] <= g) l2 = m;
-          else h2 = m - 1;
-        }
-        o = l2;
-      }
+      const uint32_t o = ga ? owner_of(S, g) : 0u;
       const uint64_t l = lane0 + o;
       Thr T;
       if (in.mode != CKC_FULL) {
@@ -612,6 +795,106 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
       ln.gtid = T.gtid;
       count_site(S, C, sat, site_iter, __ballot(ga));
       run_program<M_BODY>(S, R, C, ln, sat, lpc + 1, endpc);
+    }
+  }
+  if (cur != 0xFFFFFFFFu) {
+    add_lane_totals(S, ln);
+    flush_input(S, a, cur, cur_sites);
+  }
+}
+
+// The body pass of gather bodies: as above, but each input's body is first
+// reduced to its gather entries, and every lane evaluates the entries of its
+// iteration (no instruction dispatch).  The owners' start and step are staged
+// in LDS with the tile's prefix, so an iteration costs one memory round trip
+// per dependent load of the body.
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE) eval_gather_kernel(KArgs a) {
+  __shared__ GenLds S;
+  extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
+  __shared__ unsigned long long item_slot;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t total = a.js->total_pieces[1];
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
+  if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0;
+  uint64_t cur_xt = ~0ull, sat = 0;
+  Dec dec;
+  Lane ln;
+  lane_zero_totals(ln);
+  for (;;) {
+    __syncthreads();
+    const uint64_t p = sched_next(sc, &a.js->next_piece[1], &item_slot);
+    if (p == ~0ull) break;
+    uint64_t xt;
+    uint32_t i;
+    piece_tile(a, 1, p, xt, i);
+    const dinput& in = a.inputs[i];
+    if (i != cur) {
+      if (cur != 0xFFFFFFFFu) {
+        add_lane_totals(S, ln);
+        flush_input(S, a, cur, cur_sites);
+      }
+      sat = 0;
+      cur = i;
+      built = 0;
+      cur_sites = ((c_dprog*)in.prog)->n_sites;
+      const uint32_t L6[6] = {in.launch[0], in.launch[1], in.launch[2], in.launch[3], in.launch[4], in.launch[5]};
+      dec_make(dec, L6);
+    }
+    const uint64_t lane0 = (xt - in.xt_begin) * TILE;
+    const uint64_t* xs = (const uint64_t*)in.xstate;
+    const uint64_t xn = in.xn;
+    if (xt != cur_xt) {
+      S.pref[tid] = xs[lane0 + tid];
+      S.xstart[tid] = xs[xn + lane0 + tid];
+      S.xstep[tid] = xs[2 * xn + lane0 + tid];
+      if (tid == 0) S.pref[TILE] = a.xtot[xt];
+      cur_xt = xt;
+      __syncthreads();
+    }
+    const uint64_t it0 = (p - a.xpg[xt]) * PIECE;
+    const uint64_t tot = S.pref[TILE];
+    const uint64_t it1 = it0 + PIECE < tot ? it0 + PIECE : tot;
+    c_dprog* P = (c_dprog*)in.prog;
+    const uint32_t lpc = (uint32_t)P->expand_pc;
+    c_dins* I = (c_dins*)((const uint8_t*)in.prog + P->off_instr);
+    const dins Lx = ld_ins(I, lpc);
+    Thr T0;
+    T0.t[0] = T0.t[1] = T0.t[2] = T0.b[0] = T0.b[1] = T0.b[2] = 0;
+    T0.gtid = 0;
+    Ctx C;
+    ctx_init(C, a, in, i, T0);
+    if (!built) {
+      // live-ins are uniform over the input: take the owner of this piece's first iteration
+      const uint32_t o0 = ufirst(owner_of(S, it0));
+      if (tid < 64) build_gather(S, R, C, lpc, Lx.jmp, lane0 + o0);
+      __syncthreads();
+      built = 1;
+      ok = S.gb.ok;
+    }
+    if (!ok) continue;  // cannot happen for a body the loader accepted
+    for (uint64_t base = it0; base < it1; base += TILE) {
+      const uint64_t g = base + tid;
+      const bool ga = g < it1;
+      const uint32_t o = ga ? owner_of(S, g) : 0u;
+      const uint64_t l = lane0 + o;
+      uint64_t gtid = l;
+      if (in.mode != CKC_FULL) {
+        Thr T;
+        decode_lane(in.mode, in.launch, l, T);
+        gtid = T.gtid;
+      }
+      ln.dis = ga ? 0u : DEAD;
+      ln.k0 = ga ? g - S.pref[o] : 0;
+      ln.gtid = gtid;
+      count_site(S, C, sat, Lx.s0, __ballot(ga));
+      const uint64_t ctr = narrow(S.xstart[o] + ln.k0 * S.xstep[o], Lx.w);
+      run_gather(S, R, C, ln, sat, ctr);
     }
   }
   if (cur != 0xFFFFFFFFu) {

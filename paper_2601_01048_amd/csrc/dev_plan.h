@@ -262,6 +262,7 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
     for (uint64_t q = j; q < in.n_xt; q += 64) {
       a.xtot[in.xt_begin + q] = 0;
       a.xpb[in.xt_begin + q] = 0;
+      a.xpg[in.xt_begin + q] = 0;
     }
   uint64_t lanes = set_lanes(in.mode, in.launch);
   bool trace = (P->cls & CKC_CLS_UNIFORM) && !a.force_generic && in.trace != 0 && lanes > 0;

@@ -58,7 +58,8 @@ struct dprog {
   uint8_t body_special;       // the expanded body reads tid or bid
   uint32_t off_instr, off_consts, off_access, off_sites;  // byte offsets from the header
   uint32_t total_bytes;
-  uint32_t pad1[3];
+  uint32_t body_gather;       // the expanded body is evaluated as a gather (entries)
+  uint32_t pad1[2];
 };
 
 // One input of a job (the global input list concatenates the descriptors).

@@ -13,8 +13,8 @@ constexpr int TILE = 256;  // lanes per tile = threads per evaluation workgroup
 struct jobstate {
   unsigned long long total_tiles[3];  // tile space of each evaluator (dinput.path)
   unsigned long long next_tile[3];    // dynamic schedule counters
-  unsigned long long total_pieces;    // work items of the expanded-loop body pass
-  unsigned long long next_piece;
+  unsigned long long total_pieces[2];  // work items of the expanded-loop body passes
+  unsigned long long next_piece[2];    // [0] interpreted bodies, [1] gather bodies
 };
 
 struct KArgs {
@@ -33,15 +33,18 @@ struct KArgs {
   // expanded loops: per expanded tile the trip-count total, the piece count
   // (scanned in place into the first piece), the input; block sums of the scan
   unsigned long long* xtot;
-  unsigned long long* xpb;
+  unsigned long long* xpb;    // pieces of interpreted bodies
+  unsigned long long* xpg;    // pieces of gather bodies
   uint32_t* xin;
-  unsigned long long* xbsum;
+  unsigned long long* xbsum;  // [2][blocks]
   uint64_t n_xtiles;
   uint32_t max_regs;        // interpreter registers (LDS rows of TILE lanes) of the job's programs
   uint32_t pad;
 };
 // LDS bytes of the interpreter's register file for a job.
-inline uint32_t regfile_bytes(const KArgs& a) { return (a.max_regs ? a.max_regs : 1u) * TILE * 8u; }
+// At least 8 rows: the gather evaluation of expanded bodies keeps the counter
+// and up to 7 loaded values there.
+inline uint32_t regfile_bytes(const KArgs& a) { return (a.max_regs > 8u ? a.max_regs : 8u) * TILE * 8u; }
 
 // Workgroups and schedule of each evaluator (index PATH_*).
 struct EvalGrid {

@@ -90,8 +90,12 @@ hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream
 hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
   return launch_eval(a, eg, PATH_GENERIC, s);
 }
-static void* body_fn(uint32_t sk) {
+static void* body_fn(uint32_t sk, uint32_t which) {
   const uint32_t s = sched_impl(sk);
+  if (which)
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_gather_kernel<CKC_SCHED_BLOCKED>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_gather_kernel<CKC_SCHED_CYCLIC>
+                                  : (void*)eval_gather_kernel<CKC_SCHED_DYNAMIC>;
   return s == CKC_SCHED_BLOCKED ? (void*)eval_body_kernel<CKC_SCHED_BLOCKED>
        : s == CKC_SCHED_CYCLIC  ? (void*)eval_body_kernel<CKC_SCHED_CYCLIC>
                                 : (void*)eval_body_kernel<CKC_SCHED_DYNAMIC>;
@@ -101,15 +105,19 @@ static uint32_t xscan_blocks(const KArgs& a) { return (uint32_t)((a.n_xtiles + X
 hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
   if (a.n_xtiles == 0) return hipSuccess;
   const uint32_t nb = xscan_blocks(a);
-  hipLaunchKernelGGL(xscan_sums_kernel, dim3(nb), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(xscan_blocks_kernel, dim3(1), dim3(1024), 0, s, a, nb);
-  hipLaunchKernelGGL(xscan_apply_kernel, dim3(nb), dim3(256), 0, s, a);
   KArgs k = with_sched(a, eg, PATH_GENERIC);
   void* args[] = {&k};
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return hipLaunchKernel(body_fn(eg.sched[PATH_GENERIC]), dim3(eg.n_wg[PATH_GENERIC]), dim3(TILE), args,
-                         regfile_bytes(a), s);
+  for (uint32_t which = 0; which < 2; which++) {
+    hipLaunchKernelGGL(xscan_sums_kernel, dim3(nb), dim3(256), 0, s, a, which);
+    hipLaunchKernelGGL(xscan_blocks_kernel, dim3(1), dim3(1024), 0, s, a, nb, which);
+    hipLaunchKernelGGL(xscan_apply_kernel, dim3(nb), dim3(256), 0, s, a, which);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipLaunchKernel(body_fn(eg.sched[PATH_GENERIC], which), dim3(eg.n_wg[PATH_GENERIC]), dim3(TILE), args,
+                          regfile_bytes(a), s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s) {
@@ -157,18 +165,27 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
     e = add_node(g, &ev[2], &scan, 1, eval_fn(PATH_LANES, eg.sched[PATH_LANES]), eg.n_wg[PATH_LANES], TILE,
                  argsp[PATH_LANES]);
   if (e != hipSuccess) return e;
-  if (a.n_xtiles) {  // generic -> scan of pieces -> body pass
+  if (a.n_xtiles) {  // generic -> (scan of pieces -> body pass) for both kinds of bodies, in parallel
     uint32_t nb = xscan_blocks(a);
-    void* argsb[] = {&ka, &nb};
-    hipGraphNode_t x1, x2, x3, xb;
-    e = add_node(g, &x1, &ev[1], 1, (void*)xscan_sums_kernel, nb, 256, args1);
-    if (e == hipSuccess) e = add_node(g, &x2, &x1, 1, (void*)xscan_blocks_kernel, 1, 1024, argsb);
-    if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, args1);
-    if (e == hipSuccess)
-      e = add_node(g, &xb, &x3, 1, body_fn(eg.sched[PATH_GENERIC]), eg.n_wg[PATH_GENERIC], TILE, argsp[PATH_GENERIC],
-                   regfile_bytes(a));
+    uint32_t wh[2] = {0, 1};
+    void* argsw[2][2] = {{&ka, &wh[0]}, {&ka, &wh[1]}};
+    void* argsb[2][3] = {{&ka, &nb, &wh[0]}, {&ka, &nb, &wh[1]}};
+    hipGraphNode_t xb[2];
+    for (uint32_t which = 0; which < 2 && e == hipSuccess; which++) {
+      hipGraphNode_t x1, x2, x3;
+      e = add_node(g, &x1, &ev[1], 1, (void*)xscan_sums_kernel, nb, 256, argsw[which]);
+      if (e == hipSuccess) e = add_node(g, &x2, &x1, 1, (void*)xscan_blocks_kernel, 1, 1024, argsb[which]);
+      if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, argsw[which]);
+      if (e == hipSuccess)
+        e = add_node(g, &xb[which], &x3, 1, body_fn(eg.sched[PATH_GENERIC], which), eg.n_wg[PATH_GENERIC], TILE,
+                     argsp[PATH_GENERIC], regfile_bytes(a));
+    }
     if (e != hipSuccess) return e;
-    ev[1] = xb;
+    // the replay waits for both body passes
+    hipGraphNode_t join;
+    e = hipGraphAddEmptyNode(&join, g, xb, 2);
+    if (e != hipSuccess) return e;
+    ev[1] = join;
   }
   hipGraphNode_t last = nullptr;
   if (n_records) {

@@ -10,6 +10,7 @@
 //     thread-invariant T and b (the affine-access definition of Section 5.1.1);
 //     the coefficient vector reported per access is a row of the paper's T.
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -508,6 +509,87 @@ struct Analyzer {
     }
   }
 
+  // The expanded body as a gather: straight-line code whose live-ins are
+  // uniform and whose every varying value is affine in one variable (the loop
+  // counter or one loaded value) with uniform coefficients, valid modulo 2^w
+  // for each access of width w that uses it.  Such a body is evaluated from a
+  // per-input list of (coefficient, offset, variable) entries instead of being
+  // interpreted.
+  bool body_gather = false;
+
+  void check_gather() {
+    if (expand_pc < 0) return;
+    const Ins& L = ins[expand_pc];
+    std::vector<int> var(n_regs, -1), valid(n_regs, 64);
+    var[L.dst] = 0;
+    int n_load = 0, n_ent = 0;
+    auto operand_ok = [&](int r) {  // live-ins must be uniform
+      if (r >= n_regs) return true;
+      if (def_pc[r] < expand_pc && r != L.dst) return (bool)uni[r];
+      return true;
+    };
+    auto v_of = [&](int r) { return r < n_regs ? var[r] : -1; };
+    auto k_of = [&](int r) { return r < n_regs ? valid[r] : 64; };
+    for (int i = expand_pc + 1; i < L.end; i++) {
+      const Ins& I = ins[i];
+      if (!I.live) continue;
+      const int op = I.op, w = I.w;
+      switch (op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR: var[I.dst] = -1; break;
+        case CKC_OP_SPECIAL:
+          if (I.a < 6) return;  // thread coordinates: keep the interpreter
+          var[I.dst] = -1;
+          break;
+        case CKC_OP_ACCESS: case CKC_OP_LOAD: {
+          if (!operand_ok(I.a)) return;
+          if (v_of(I.a) >= 0 && k_of(I.a) < w) return;
+          if (++n_ent > 32) return;
+          if (op == CKC_OP_LOAD) {
+            if (++n_load > 7) return;
+            var[I.dst] = n_load;
+            valid[I.dst] = 64;
+          }
+          break;
+        }
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC:
+          if (!operand_ok(I.a) || v_of(I.a) >= 0) return;
+          var[I.dst] = -1;
+          break;
+        case CKC_OP_SELECT:
+          if (!operand_ok(I.a) || !operand_ok(I.b) || !operand_ok(I.c)) return;
+          if (v_of(I.a) >= 0 || v_of(I.b) >= 0 || v_of(I.c) >= 0) return;
+          var[I.dst] = -1;
+          break;
+        default: {
+          if (!is_binary(op)) return;  // control flow inside the body
+          if (!operand_ok(I.a) || !operand_ok(I.b)) return;
+          const int va = v_of(I.a), vb = v_of(I.b);
+          if (va < 0 && vb < 0) { var[I.dst] = -1; break; }
+          int v, k;
+          if (op == CKC_OP_ADD || op == CKC_OP_SUB) {
+            if (va >= 0 && vb >= 0 && va != vb) return;
+            v = va >= 0 ? va : vb;
+            k = std::min({va >= 0 ? k_of(I.a) : 64, vb >= 0 ? k_of(I.b) : 64, w});
+          } else if (op == CKC_OP_MUL) {
+            if (va >= 0 && vb >= 0) return;
+            v = va >= 0 ? va : vb;
+            k = std::min(va >= 0 ? k_of(I.a) : k_of(I.b), w);
+          } else if (op == CKC_OP_SHL) {
+            if (vb >= 0) return;
+            v = va;
+            k = std::min(k_of(I.a), w);
+          } else {
+            return;
+          }
+          var[I.dst] = v;
+          valid[I.dst] = k;
+          break;
+        }
+      }
+    }
+    body_gather = true;
+  }
+
   std::vector<uint8_t> lower(uint32_t cls, uint32_t trace_cap, int* n_live_out) {
     std::vector<int> newpc(n_instr, -1);
     int m = 0;
@@ -591,6 +673,7 @@ struct Analyzer {
     if (expand_pc >= 0)
       for (int i = expand_pc + 1; i < ins[expand_pc].end; i++)
         if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
+    h.body_gather = body_gather ? 1u : 0u;
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
     h.off_instr = al(sizeof(dprog));
@@ -699,7 +782,9 @@ int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
                  (any_ind ? CKC_CLS_INDIRECT : 0) | (any64 ? CKC_CLS_I64 : 0) |
                  (uniform_prog ? CKC_CLS_UNIFORM : 0);
   A.choose_expansion(uniform_prog);
+  A.check_gather();
   if (A.expand_pc >= 0) cls |= CKC_CLS_EXPANDED;
+  if (A.body_gather) cls |= CKC_CLS_GATHER;
   uint32_t trace_cap = 0;
   if (uniform_prog) {
     uint64_t s = A.static_trace_len();

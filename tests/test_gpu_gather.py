@@ -1,0 +1,36 @@
+"""GPU parity of expanded loops evaluated as gathers (entries built once per
+input) and of their near misses (interpreted), against the oracle."""
+import numpy as np
+import pytest
+
+import gatherprog as G
+from oracle import oracle as O
+from paper_2601_01048_amd import ckc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = ckc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_gather_bodies(ctx, seed):
+    from test_gpu_parity import compare
+    rng = np.random.default_rng(500 + seed)
+    n_gather = 0
+    for k in range(30):
+        ir = G.gather_program(rng, near_miss=(k % 5 == 4))
+        info, _ = ckc.analyze(ir)
+        n_gather += bool(info["cls"] & ckc.CLS["GATHER"])
+        wl = G.gather_workload(rng, ir)
+        print(f"[case] seed {seed} prog {k} cls {info['cls']}", flush=True)
+        g = ckc.run_workload(ctx, wl)
+        o = O.check(wl)
+        compare(g, o, what=f"gather seed {seed} prog {k} ir {ir.hex()}")
+    assert n_gather > 0

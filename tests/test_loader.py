@@ -60,7 +60,8 @@ def test_program_classes():
         return {k for k, v in ckc.CLS.items() if ckc.analyze(ir)[0]["cls"] & v}
     assert cls(W.f1_program()) == {"AFFINE", "UNIFORM"}
     assert cls(W.f2_program(64)) == {"AFFINE", "UNIFORM", "I64"}
-    assert cls(W.f3_program()) == {"GUARDED", "INDIRECT", "EXPANDED"}
+    assert cls(W.f3_program()) == {"GUARDED", "INDIRECT", "EXPANDED", "GATHER"}
+    assert cls(W.f3_program(64)) == {"GUARDED", "INDIRECT", "I64", "EXPANDED", "GATHER"}
     assert cls(K.listing3_program()) == {"AFFINE", "GUARDED"}
     # thread-dependent product: not affine
     p = Program(n_scalars=0, n_slots=1)
@@ -134,3 +135,20 @@ def test_truncated_and_garbage_ir():
     for b in (b"", b"\x00" * 8, W.f1_program()[:-16], b"CKC1" + b"\xff" * 60):
         with pytest.raises(ckc.CkcError):
             ckc.analyze(b)
+
+
+def test_gather_classification():
+    """Expanded bodies with a thread coordinate, two varying operands in one
+    index, control flow or a product of varying values stay interpreted; the
+    plain gather shapes are recognised."""
+    import gatherprog as G
+    rng = np.random.default_rng(3)
+    n_gather = 0
+    for k in range(80):
+        near = k % 2 == 1
+        info, _ = ckc.analyze(G.gather_program(rng, near_miss=near))
+        assert info["cls"] & ckc.CLS["EXPANDED"]
+        if near:
+            assert not info["cls"] & ckc.CLS["GATHER"], k
+        n_gather += bool(info["cls"] & ckc.CLS["GATHER"])
+    assert n_gather >= 10
