@@ -168,7 +168,9 @@ enum ckc_schedule {
 
 typedef struct ckc_launch_opts {
   uint32_t schedule;      /* ckc_schedule */
-  uint32_t chunk;         /* tiles per work item (1..256); 0 = 1 */
+  uint32_t chunk;         /* tiles per work item (1..256); 0 = per-evaluator defaults (1 for
+                             the trace evaluators, 4 for the interpreter); the body pass of
+                             expanded loops always takes runs of 8 pieces */
   uint32_t wg_per_cu;     /* persistent workgroups per compute unit for every evaluator
                              (1..32); 0 = per-evaluator defaults (8 trace, 2 interpreter) */
   uint32_t force_generic; /* 1: evaluate every program with the general interpreter */

@@ -27,19 +27,26 @@ __device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
 
 typedef const __attribute__((address_space(4))) ckc_alloc c_alloc;
 
+// Iterations of an expanded loop per work item of the body pass (also the
+// length of the owner map staged in LDS).
+constexpr uint32_t PIECE_LDS = 2048;
+
 // One access of a gather body: index = narrow(off + coef * X[var], w) with
 // X[0] the loop counter and X[k] (k >= 1) the value of the k-th LOAD of the
 // body (var 0xFF: a uniform index `off`).
 constexpr uint32_t MAX_GENT = 32;
 struct GEnt {
   int64_t coef, off;
+  uint64_t bound;       // elements of the slot's allocation (size >> lg)
+  const void* data;     // the slot's data (LOAD)
   uint32_t acc;
   uint16_t site;
   uint8_t slot, lg;
   uint8_t w, var, dst;  // dst: variable a LOAD defines (0 for ACCESS)
-  uint8_t pad[5];
+  uint8_t dead;         // NULL or FREED kind of the slot, else 0
+  uint8_t pad[4];
 };
-static_assert(sizeof(GEnt) == 32, "gather entry layout");
+static_assert(sizeof(GEnt) == 48, "gather entry layout");
 struct GBody {
   GEnt e[MAX_GENT];
   uint32_t n, ok, faults;  // entries, usable, division faults per iteration
@@ -53,6 +60,8 @@ struct GenLds {
   unsigned long long pref[TILE + 1];  // trip-count prefix of the tile's threads (expanded loop)
   GBody gb;                           // gather entries of the current input (body pass)
   unsigned long long xstart[TILE], xstep[TILE];  // loop start and step of the tile's threads (gather pass)
+  uint16_t own[PIECE_LDS];            // owner thread of each iteration of the current piece
+  uint16_t omax[TILE / 64];           // owner-map scan: per-wavefront maxima
 };
 
 // Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
@@ -74,7 +83,7 @@ struct Lane {
 };
 
 struct Ctx {
-  const dinput* in;
+  c_input* in;             // read through scalar loads
   c_dprog* P;
   c_dins* I;
   c_i64* K;
@@ -122,8 +131,7 @@ __device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint64_t& sa
 #define RGET(i) R[(uint32_t)(i) * TILE + threadIdx.x]
 #define RPUT(i, v) (R[(uint32_t)(i) * TILE + threadIdx.x] = (v))
 
-// Iterations of an expanded loop per work item of the body pass.
-constexpr uint32_t PIECE = 2048;
+constexpr uint32_t PIECE = PIECE_LDS;
 
 // Runs the program for the wavefront from pc0 until pc_end (exclusive) or the
 // end.  M_MAIN: whole threads; at the expanded loop each lane's trip count,
@@ -352,7 +360,7 @@ __device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, uint32_t 
   __syncthreads();
 }
 
-__device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, const dinput& in, uint32_t i, const Thr& T) {
+__device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, c_input& in, uint32_t i, const Thr& T) {
   C.in = &in;
   C.P = (c_dprog*)in.prog;
   C.I = (c_dins*)((const uint8_t*)in.prog + C.P->off_instr);
@@ -403,7 +411,7 @@ __device__ __forceinline__ void add_lane_totals(GenLds& S, Lane& ln) {
 
 // The interpreter over whole threads: one lane per thread of the thread set.
 template <uint32_t SK>
-__global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // [n_regs][TILE]
   __shared__ unsigned long long item_slot;
@@ -417,8 +425,9 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
   c_u32* order = (c_u32*)a.order;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
-  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0;
-  uint64_t tb = 0, cur_end = 0, sat = 0;
+  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0;
+  uint64_t tb = 0, cur_end = 0, sat = 0, cur_lanes = 0;
+  uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
   Dec dec;
   Lane ln;
   lane_zero_totals(ln);
@@ -438,17 +447,18 @@ __global__ void __launch_bounds__(TILE) eval_generic_kernel(KArgs a) {
       cur_sites = ((c_dprog*)a.inputs[i].prog)->n_sites;
       tb = ins[i].tile_begin[PATH_GENERIC];
       cur_end = tb + ins[i].n_tiles[PATH_GENERIC];
-      const uint32_t L6[6] = {ins[i].launch[0], ins[i].launch[1], ins[i].launch[2],
-                              ins[i].launch[3], ins[i].launch[4], ins[i].launch[5]};
-      dec_make(dec, L6);
+      for (int q = 0; q < 6; q++) cur_L[q] = ins[i].launch[q];
+      cur_mode = ins[i].mode;
+      cur_lanes = ins[i].lanes;
+      dec_make(dec, cur_L);
     }
     const uint32_t i = cur;
-    const dinput& in = a.inputs[i];
+    c_input& in = ins[i];
     const uint64_t l = (t - tb) * TILE + tid;
-    const bool act = l < in.lanes;
+    const bool act = l < cur_lanes;
     Thr T;
-    if (in.mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
-    else decode_lane(in.mode, in.launch, act ? l : 0, T);
+    if (cur_mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
+    else decode_lane(cur_mode, cur_L, act ? l : 0, T);
     Ctx C;
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
@@ -602,6 +612,10 @@ __device__ void build_gather(GenLds& S, uint64_t* R, const Ctx& C, uint32_t lpc,
           E.w = (uint8_t)w;
           E.var = (uint8_t)va;
           E.dst = op == CKC_OP_LOAD ? (uint8_t)(n_load + 1) : 0;
+          c_alloc& A = C.tab[D.slot];
+          E.bound = A.size_bytes >> E.lg;
+          E.data = A.data;
+          E.dead = A.base == 0 ? CKC_KIND_NULL : ((A.flags & CKC_ALLOC_FREED) ? CKC_KIND_FREED : 0);
         }
         n++;
         if (op == CKC_OP_LOAD) {
@@ -695,6 +709,86 @@ __device__ __forceinline__ void run_gather(GenLds& S, uint64_t* R, const Ctx& C,
   }
 }
 
+// Kind of index idx of a live-or-dead slot with `bound` elements (the same
+// precedence as kind_of: NULL > FREED > UNDER > OVER).
+__device__ __forceinline__ uint32_t kind_bound(uint32_t dead, uint64_t bound, int64_t idx) {
+  if (dead) return dead;
+  if (idx < 0) return CKC_KIND_UNDER;
+  return (uint64_t)idx >= bound ? CKC_KIND_OVER : 0u;
+}
+
+// Entries kept in registers by the piece evaluator.
+constexpr uint32_t GREG = 4;
+
+// Evaluates the iterations [it0, it1) of a piece of a gather body with at most
+// GREG entries: the entries are read once into (uniform) registers; per chunk
+// of TILE iterations a lane forms its counter from its owner's start and step
+// and evaluates every entry.  The loaded values live in R rows 1..GREG.
+__device__ __forceinline__ void gather_piece(GenLds& S, uint64_t* R, const Ctx& C, Lane& ln, uint64_t& sat,
+                                             uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
+                                             const uint32_t* L6, uint32_t site_iter, uint32_t ctr_w) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = S.gb.n;
+  uint64_t coef[GREG], off[GREG], bound[GREG];
+  const void* data[GREG];
+  uint32_t meta[GREG];  // w64 | var << 8 | dst << 16 | lg << 24 | dead << 28
+  uint32_t site[GREG];
+#pragma unroll
+  for (uint32_t e = 0; e < GREG; e++) {
+    const GEnt& E = S.gb.e[e < n ? e : 0];
+    site[e] = ufirst(E.site);
+    coef[e] = ufirst64((uint64_t)E.coef);
+    off[e] = ufirst64((uint64_t)E.off);
+    bound[e] = ufirst64(E.bound);
+    data[e] = (const void*)ufirst64((uint64_t)E.data);
+    meta[e] = ufirst((E.w == 64 ? 1u : 0u) | ((uint32_t)E.var << 8) | ((uint32_t)E.dst << 16) |
+                     ((uint32_t)E.lg << 24) | ((uint32_t)E.dead << 28));
+  }
+  const uint32_t faults = S.gb.faults;
+  for (uint64_t base = it0; base < it1; base += TILE) {
+    const uint64_t g = base + tid;
+    const bool act = g < it1;
+    const uint32_t o = act ? (uint32_t)S.own[g - it0] : 0u;
+    const uint64_t l = lane0 + o;
+    uint64_t gtid = l;
+    if (mode != CKC_FULL) {
+      Thr T;
+      decode_lane(mode, L6, l, T);
+      gtid = T.gtid;
+    }
+    const uint64_t k = act ? g - S.pref[o] : 0;
+    const uint64_t am = __ballot(act);
+    count_site(S, C, sat, site_iter, am);
+    R[tid] = narrow(S.xstart[o] + k * S.xstep[o], ctr_w);
+    const uint64_t key = (gtid << C.Lsum) | (k << C.L2);
+#pragma unroll
+    for (uint32_t e = 0; e < GREG; e++) {
+      if (e >= n) break;
+      const uint32_t m = meta[e], var = (m >> 8) & 0xFFu, dst = (m >> 16) & 0xFFu;
+      uint64_t v = off[e];
+      if (var != 0xFF) {
+        const uint64_t x = R[var * TILE + tid];
+        v = coef[e] == 1 ? v + x : v + coef[e] * x;
+      }
+      const int64_t idx = (m & 1u) ? (int64_t)v : (int64_t)(int32_t)(uint32_t)v;
+      const uint32_t kd = act ? kind_bound(m >> 28, bound[e], idx) : 0u;
+      count_site(S, C, sat, site[e], am);
+      if (__ballot(kd != 0)) merge_violation(C.rec + S.gb.e[e].acc, kd, key);
+      if (dst) {
+        uint64_t x = 0;
+        if (act && kd == 0)
+          x = ((m >> 24) & 3u) == 2 ? (uint64_t)(int64_t)((const int32_t*)data[e])[idx]
+                                    : (uint64_t)((const int64_t*)data[e])[idx];
+        R[dst * TILE + tid] = x;
+      }
+    }
+    if (act) {
+      ln.acc += n;
+      ln.faults += faults;
+    }
+  }
+}
+
 // Owner of iteration g in a tile: the largest o with pref[o] <= g.
 __device__ __forceinline__ uint32_t owner_of(const GenLds& S, uint64_t g) {
   uint32_t l2 = 0, h2 = TILE - 1;
@@ -706,10 +800,70 @@ __device__ __forceinline__ uint32_t owner_of(const GenLds& S, uint64_t g) {
   return l2;
 }
 
+// Owner map of the iterations [it0, it1) of a piece: S.own[g - it0] is the
+// tile thread that owns iteration g.  Every thread of the tile whose iteration
+// range starts inside the piece marks its start; a workgroup max-scan over the
+// marks (owners increase with the iteration) fills the rest, the piece's
+// first iteration taking the owner found by one binary search.
+__device__ void build_owner_map(GenLds& S, uint64_t it0, uint64_t it1) {
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t PER = PIECE_LDS / TILE;  // entries per thread
+  for (uint32_t q = 0; q < PER; q++) S.own[tid * PER + q] = 0;
+  const uint32_t o0 = owner_of(S, it0);
+  __syncthreads();
+  {
+    const uint64_t st = S.pref[tid], en = S.pref[tid + 1];
+    if (en > st && st > it0 && st < it1) S.own[st - it0] = (uint16_t)tid;
+    if (tid == 0) S.own[0] = (uint16_t)o0;
+  }
+  __syncthreads();
+  // max-scan: PER entries per thread, then across threads
+  uint32_t m = 0;
+  for (uint32_t q = 0; q < PER; q++) {
+    const uint32_t v = S.own[tid * PER + q];
+    m = v > m ? v : m;
+  }
+  uint32_t incl = m;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o, 64);
+    if ((int)lane_id() >= o) incl = u > incl ? u : incl;
+  }
+  if (lane_id() == 63) S.omax[tid / 64] = (uint16_t)incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t w = 0; w < tid / 64; w++) before = S.omax[w] > before ? S.omax[w] : before;
+  uint32_t prev = __shfl_up(incl, 1, 64);
+  if (lane_id() == 0) prev = 0;
+  uint32_t run = prev > before ? prev : before;
+  for (uint32_t q = 0; q < PER; q++) {
+    const uint32_t v = S.own[tid * PER + q];
+    run = v > run ? v : run;
+    S.own[tid * PER + q] = (uint16_t)run;
+  }
+  __syncthreads();
+}
+
+// Pieces per work item of the body passes: a workgroup takes runs of
+// consecutive pieces, so that finding a piece's tile is a step forward from
+// the previous piece's tile rather than a search.
+constexpr uint32_t PIECE_RUN = 8;
+
 // Piece p of body pass `which` (0 interpreted, 1 gather): its expanded tile
-// and input.  Uniform.
+// and input.  `xt` holds the previous piece's tile (~0 for none); the next two
+// tiles are tried before a binary search.  Uniform.
 __device__ __forceinline__ void piece_tile(const KArgs& a, uint32_t which, uint64_t p, uint64_t& xt, uint32_t& i) {
-  xt = ufirst64(find_xtile(which ? a.xpg : a.xpb, a.n_xtiles, p));
+  typedef const __attribute__((address_space(4))) unsigned long long c_u64;
+  c_u64* xp = (c_u64*)(which ? a.xpg : a.xpb);
+  const uint64_t n = a.n_xtiles;
+  uint64_t t = ~0ull;
+  if (xt != ~0ull) {
+    for (uint64_t q = xt; q < n && q <= xt + 2; q++) {
+      const uint64_t b = xp[q], e = q + 1 < n ? xp[q + 1] : ~0ull;
+      if (p >= b && p < e) { t = q; break; }
+    }
+  }
+  if (t == ~0ull) t = find_xtile(which ? a.xpg : a.xpb, n, p);
+  xt = ufirst64(t);
   i = ufirst(a.xin[xt]);
 }
 
@@ -717,7 +871,7 @@ __device__ __forceinline__ void piece_tile(const KArgs& a, uint32_t which, uint6
 // consecutive iterations of one tile's flattened iteration space; each lane
 // runs one iteration (owner thread by binary search in the tile's prefix).
 template <uint32_t SK>
-__global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // [n_regs][TILE]
   __shared__ unsigned long long item_slot;
@@ -725,12 +879,15 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
   const uint64_t total = a.js->total_pieces[0];
   if (total == 0) return;
   Sched<SK> sc;
-  sched_init(sc, a, total);
+  KArgs ar = a;
+  ar.chunk = PIECE_RUN;
+  sched_init(sc, ar, total);
   if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
-  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0;
-  uint64_t cur_xt = ~0ull, sat = 0;
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0;
+  uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t cur_xt = ~0ull, sat = 0, cur_xt_hint = ~0ull;
   Dec dec;
   Lane ln;
   lane_zero_totals(ln);
@@ -738,10 +895,11 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
     __syncthreads();
     const uint64_t p = sched_next(sc, &a.js->next_piece[0], &item_slot);
     if (p == ~0ull) break;
-    uint64_t xt;
+    uint64_t xt = cur_xt_hint;
     uint32_t i;
     piece_tile(a, 0, p, xt, i);
-    const dinput& in = a.inputs[i];
+    cur_xt_hint = xt;
+    c_input& in = ((c_input*)a.inputs)[i];
     if (i != cur) {
       if (cur != 0xFFFFFFFFu) {
         add_lane_totals(S, ln);
@@ -750,8 +908,9 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
       sat = 0;
       cur = i;
       cur_sites = ((c_dprog*)in.prog)->n_sites;
-      const uint32_t L6[6] = {in.launch[0], in.launch[1], in.launch[2], in.launch[3], in.launch[4], in.launch[5]};
-      dec_make(dec, L6);
+      for (int q = 0; q < 6; q++) cur_L[q] = in.launch[q];
+      cur_mode = in.mode;
+      dec_make(dec, cur_L);
     }
     const uint64_t lane0 = (xt - in.xt_begin) * TILE;
     const uint64_t* xs = (const uint64_t*)in.xstate;
@@ -773,15 +932,17 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
     Ctx C;
     ctx_init(C, a, in, i, T0);
     const uint32_t site_iter = ld_ins(C.I, lpc).s0;
+    const uint32_t body_special = P->body_special;
+    build_owner_map(S, it0, it1);
     for (uint64_t base = it0; base < it1; base += TILE) {
       const uint64_t g = base + tid;
       const bool ga = g < it1;
-      const uint32_t o = ga ? owner_of(S, g) : 0u;
+      const uint32_t o = ga ? (uint32_t)S.own[g - it0] : 0u;
       const uint64_t l = lane0 + o;
       Thr T;
-      if (in.mode != CKC_FULL) {
-        decode_lane(in.mode, in.launch, l, T);
-      } else if (P->body_special) {
+      if (cur_mode != CKC_FULL) {
+        decode_lane(cur_mode, cur_L, l, T);
+      } else if (body_special) {
         decode_full(dec, l, T);
       } else {  // the body reads no thread coordinate
         T.t[0] = T.t[1] = T.t[2] = T.b[0] = T.b[1] = T.b[2] = 0;
@@ -809,7 +970,7 @@ __global__ void __launch_bounds__(TILE) eval_body_kernel(KArgs a) {
 // in LDS with the tile's prefix, so an iteration costs one memory round trip
 // per dependent load of the body.
 template <uint32_t SK>
-__global__ void __launch_bounds__(TILE) eval_gather_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, 6) eval_gather_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
   __shared__ unsigned long long item_slot;
@@ -817,23 +978,26 @@ __global__ void __launch_bounds__(TILE) eval_gather_kernel(KArgs a) {
   const uint64_t total = a.js->total_pieces[1];
   if (total == 0) return;
   Sched<SK> sc;
-  sched_init(sc, a, total);
+  KArgs ar = a;
+  ar.chunk = PIECE_RUN;
+  sched_init(sc, ar, total);
   if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
-  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0;
-  uint64_t cur_xt = ~0ull, sat = 0;
-  Dec dec;
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0, cur_mode = 0;
+  uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t cur_xt = ~0ull, sat = 0, cur_xt_hint = ~0ull;
   Lane ln;
   lane_zero_totals(ln);
   for (;;) {
     __syncthreads();
     const uint64_t p = sched_next(sc, &a.js->next_piece[1], &item_slot);
     if (p == ~0ull) break;
-    uint64_t xt;
+    uint64_t xt = cur_xt_hint;
     uint32_t i;
     piece_tile(a, 1, p, xt, i);
-    const dinput& in = a.inputs[i];
+    cur_xt_hint = xt;
+    c_input& in = ((c_input*)a.inputs)[i];
     if (i != cur) {
       if (cur != 0xFFFFFFFFu) {
         add_lane_totals(S, ln);
@@ -843,8 +1007,8 @@ __global__ void __launch_bounds__(TILE) eval_gather_kernel(KArgs a) {
       cur = i;
       built = 0;
       cur_sites = ((c_dprog*)in.prog)->n_sites;
-      const uint32_t L6[6] = {in.launch[0], in.launch[1], in.launch[2], in.launch[3], in.launch[4], in.launch[5]};
-      dec_make(dec, L6);
+      for (int q = 0; q < 6; q++) cur_L[q] = in.launch[q];
+      cur_mode = in.mode;
     }
     const uint64_t lane0 = (xt - in.xt_begin) * TILE;
     const uint64_t* xs = (const uint64_t*)in.xstate;
@@ -878,15 +1042,20 @@ __global__ void __launch_bounds__(TILE) eval_gather_kernel(KArgs a) {
       ok = S.gb.ok;
     }
     if (!ok) continue;  // cannot happen for a body the loader accepted
+    build_owner_map(S, it0, it1);
+    if (S.gb.n <= GREG) {
+      gather_piece(S, R, C, ln, sat, it0, it1, lane0, cur_mode, cur_L, Lx.s0, Lx.w);
+      continue;
+    }
     for (uint64_t base = it0; base < it1; base += TILE) {
       const uint64_t g = base + tid;
       const bool ga = g < it1;
-      const uint32_t o = ga ? owner_of(S, g) : 0u;
+      const uint32_t o = ga ? (uint32_t)S.own[g - it0] : 0u;
       const uint64_t l = lane0 + o;
       uint64_t gtid = l;
-      if (in.mode != CKC_FULL) {
+      if (cur_mode != CKC_FULL) {
         Thr T;
-        decode_lane(in.mode, in.launch, l, T);
+        decode_lane(cur_mode, cur_L, l, T);
         gtid = T.gtid;
       }
       ln.dis = ga ? 0u : DEAD;
@@ -918,7 +1087,7 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
     uint32_t mid = (lo_i + hi_i + 1) / 2;
     if (a.inputs[mid].rec_base <= r) lo_i = mid; else hi_i = mid - 1;
   }
-  const dinput& in = a.inputs[lo_i];
+  c_input& in = ((c_input*)a.inputs)[lo_i];
   const dprog* P = (const dprog*)in.prog;
   const uint32_t acc = (uint32_t)(r - in.rec_base);
   const uint64_t key = rec->first_key;
@@ -926,9 +1095,10 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   const uint64_t gtid = Lsum >= 64 ? 0 : key >> Lsum;
   const uint64_t i1 = in.L1 ? (key >> in.L2) & ((1ull << in.L1) - 1) : 0;
   const uint64_t i2 = in.L2 ? key & ((1ull << in.L2) - 1) : 0;
-  const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
+  const uint32_t L6[6] = {in.launch[0], in.launch[1], in.launch[2], in.launch[3], in.launch[4], in.launch[5]};
+  const uint32_t bs = L6[3] * L6[4] * L6[5];
   Thr T;
-  thr_from(in.launch, gtid / bs, (uint32_t)(gtid % bs), T);
+  thr_from(L6, gtid / bs, (uint32_t)(gtid % bs), T);
   const daccess A = prog_access(P)[acc];
   Ctx C;
   ctx_init(C, a, in, lo_i, T);

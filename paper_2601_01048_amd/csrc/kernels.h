@@ -50,6 +50,8 @@ inline uint32_t regfile_bytes(const KArgs& a) { return (a.max_regs > 8u ? a.max_
 struct EvalGrid {
   uint32_t n_wg[3];
   uint32_t sched[3];
+  uint32_t chunk[3];
+  uint32_t n_wg_body;  // workgroups of the body passes of expanded loops
 };
 
 hipError_t launch_plan(const KArgs& a, hipStream_t s);

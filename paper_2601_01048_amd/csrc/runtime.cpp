@@ -316,6 +316,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   std::vector<uint64_t> est;  // estimated work per input (LPT order)
   uint64_t n_xtiles = 0, xstate_bytes = 0;  // expanded loops
   uint32_t max_regs = 1;                     // interpreter register file rows
+  uint64_t gen_tiles = 0;                    // interpreter tiles (estimate from the launch shapes)
   uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
   for (uint32_t k = 0; k < n_descs; k++) {
     const ckc_batch& B = descs[k];
@@ -362,6 +363,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
       }
       hin.push_back(d);
       est.push_back(nthr * (1 + h->n_accesses));
+      if (!(h->cls & CKC_CLS_UNIFORM) || O.force_generic) gen_tiles += (nthr + TILE - 1) / TILE;
       for (uint32_t s = 0; s < MAX_SCALARS; s++)
         hsc.push_back(s < h->n_scalars ? B.scalars[(size_t)i * h->n_scalars + s] : 0);
       n_inputs++;
@@ -443,7 +445,11 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   for (int p = 0; p < 3; p++) {
     eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
     eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);
+    // interpreter tiles: by default several per work item when there are
+    // plenty (each item costs a schedule step and a lookup of its input)
+    eg.chunk[p] = O.chunk ? O.chunk : (p == PATH_GENERIC && gen_tiles >= 16ull * eg.n_wg[p] ? 4u : 1u);
   }
+  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
   J.graph = O.use_graph != 0;
   e = hipEventRecord(J.ev[0], J.stream);
   if (J.graph) {
