@@ -40,12 +40,46 @@ OPS_PER_ACCESS = 2
 TRACE_SOURCES = ("dev_common.h", "dev_plan.h", "dev_trace.h", "dformat.h", "kernels.h")
 
 
-def trace_source_hash() -> str:
+# sources of the interpreter's body passes (the CSR gather kernel)
+INTERP_SOURCES = ("dev_common.h", "dev_plan.h", "dev_interp.h", "dformat.h", "kernels.h")
+
+
+def source_hash(files=TRACE_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in TRACE_SOURCES:
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2601_01048_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, files) -> float | None:
+    """HBM bytes per launch from the committed counter runs, valid only for the
+    kernel sources they were taken on."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        return rec["traffic_bytes"] if source_hash(files) == rec["source_sha256_16"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_ms(kern) -> dict:
+    """Mean per-stage device times (HIP events on the job's stream)."""
+    names = ("plan", "eval_trace", "interpreter", "body_passes", "finish")
+    return {k: float(kern[:, q].mean()) for q, k in enumerate(names)}
+
+
+def copy_probe():
+    """One 1 GiB device-to-device copy: the reference for HBM byte counters."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def parse():
@@ -82,6 +116,8 @@ def bench_other(args):
         wl = W.config1()
         desc_w = "1-D affine kernel, 256 inputs, 32-80 blocks of 256, 4 accesses per thread"
     n = wl.n_inputs
+    if args.copy_probe:
+        copy_probe()
     with ckc.Context(0) as ctx:
         dw = ckc.DeviceWorkload(ctx, wl)
         n_acc = dw.info["n_accesses"]
@@ -103,16 +139,16 @@ def bench_other(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
            "data": "synthetic", "config": {"workload": desc_w, "inputs": n, "accesses_per_batch": accesses},
-           "inputs_per_s": n / step_s,
-           "kernel_ms": {"plan": float(kern[:, 0].mean()), "eval_trace": float(kern[:, 1].mean()),
-                         "interpreter": float(kern[:, 2].mean()), "finish": float(kern[:, 3].mean())}}
+           "inputs_per_s": n / step_s, "kernel_ms": kernel_ms(kern)}
     if args.workload == "csr":
-        nnz, nrows = wl.meta["nnz"], wl.meta["nrows"]
-        alg = n * 4 * (nnz + nrows + 1)  # col_idx per input + row_ptr per input
-        ms = float(kern[:, 2].mean())
-        res["roofline"] = {"bound": "hbm", "kernel": "eval_generic_kernel", "achieved": alg / (ms * 1e-3) / 1e9,
+        # the body pass reads col_idx once per nonzero (4 B); val and x are
+        # address-only; row_ptr is read by the whole-thread pass
+        nnz = wl.meta["nnz"]
+        alg = n * 4 * nnz
+        ms = float(kern[:, 3].mean())
+        res["roofline"] = {"bound": "hbm", "kernel": "eval_gather_kernel", "achieved": alg / (ms * 1e-3) / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": alg / (ms * 1e-3) / HBM_PEAK,
-                           "traffic": None}
+                           "traffic": recorded_traffic("eval_gather_kernel", INTERP_SOURCES)}
     else:
         ms = float(kern[:, 1].mean())
         ach = OPS_PER_ACCESS * accesses / (ms * 1e-3)
@@ -139,6 +175,7 @@ def bench_batched(args):
         out = dict(recs=torch.empty(n_rec * 32, dtype=torch.uint8, device="cuda"),
                    maps=torch.empty(n * 65536, dtype=torch.uint8, device="cuda"),
                    st=torch.empty(n * 40, dtype=torch.uint8, device="cuda"))
+        progress("batched: generated and uploaded")
         t_tune = time.perf_counter()
         best, log = ctx.autotune(prep, reps=1)
         t_tune = time.perf_counter() - t_tune
@@ -192,14 +229,14 @@ def bench_batched(args):
            "kernels_per_s": n / step_s,
            "per_kernel_launches": {"ms_total": per_kernel_s * 1e3, "kernels_per_s": n / per_kernel_s,
                                    "accesses_per_s": accesses / per_kernel_s,
-                                   "launches": 7 * n},
+                                   "launches": int(sum(8 + (8 if k.meta["family"] == "F3" else 0)
+                                                       for k in mb.kernels))},
            "speedup_vs_per_kernel": per_kernel_s / step_s,
            "autotune": {"best": best.as_dict(), "candidates": len(log), "seconds": t_tune,
                         "best_ms": min(ms for _, ms in log), "worst_ms": max(ms for _, ms in log),
                         "default_ms": [ms for d, ms in log
                                        if d["schedule"] == "blocked" and d["wg_per_cu"] == 0][0]},
-           "kernel_ms_tuned_no_graph": {"plan": split[0], "eval_trace": split[1], "interpreter": split[2],
-                                        "finish": split[3]},
+           "kernel_ms_tuned_no_graph": kernel_ms(np.array([split])),
            "generator_s": t_gen}
     return res
 
@@ -215,6 +252,7 @@ def bench_served(args):
         t0 = time.perf_counter()
         ds = ckc.DeviceStream(ctx, ss)
         t_setup = time.perf_counter() - t0
+        progress(f"served: {ss.n_jobs} jobs staged, replaying")
         with ckc.Server(ctx, n_streams=4) as srv:
             res, lag = serve.replay(srv, ds)
             st = srv.stats()
@@ -263,11 +301,7 @@ def main():
         bench_other(args)
         return
     if args.copy_probe:
-        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe()
     wl = W.config2(mode=W.MODE_FULL)
     n = wl.n_inputs
     with ckc.Context(0) as ctx:
@@ -285,7 +319,7 @@ def main():
         st = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
         accesses = int(st["accesses_checked"].sum())
         step_s = (t1 - t0) / args.steps
-        kern = np.array(tim)  # [steps, 4] ms: plan, trace eval, interpreter, finish
+        kern = np.array(tim)  # [steps, 5] ms per stage
         eval_ms = float(kern[:, 1].mean())
         result = {
             "metric": "checked thread-accesses/sec",
@@ -309,19 +343,11 @@ def main():
                 "seed": 1002,
             },
             "inputs_per_s": n / step_s,
-            "kernel_ms": {"plan": float(kern[:, 0].mean()), "eval_trace": eval_ms,
-                          "interpreter": float(kern[:, 2].mean()), "finish": float(kern[:, 3].mean())},
+            "kernel_ms": kernel_ms(kern),
         }
         achieved = OPS_PER_ACCESS * accesses / (eval_ms * 1e-3)
-        # HBM bytes per launch from the committed counter runs, valid only for
-        # the kernel source they were taken on
-        traffic = None
-        try:
-            rec_t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["eval_trace_kernel"]
-            if trace_source_hash() == rec_t["source_sha256_16"]:
-                traffic = rec_t["traffic_bytes"]
-        except (OSError, KeyError, ValueError):
-            traffic = None
+        # HBM bytes per launch from the committed counter runs
+        traffic = recorded_traffic("eval_trace_kernel", TRACE_SOURCES)
         result["roofline"] = {
             "bound": "alu",
             "kernel": "eval_trace_kernel",
@@ -345,13 +371,16 @@ def main():
                                       "lanes_per_batch": int(rst["lanes"].sum()),
                                       "speedup_inputs_per_s_vs_full": step_s / rs}
         dw.close()
+    progress("stencil done")
     if not args.no_batched:
         b = bench_batched(args)
+        progress("batched done")
         result["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "kernels_per_s",
                                                 "per_kernel_launches", "speedup_vs_per_kernel", "autotune",
                                                 "kernel_ms_tuned_no_graph", "config")}
     if not args.no_served:
         sv = bench_served(args)
+        progress("served done")
         result["served"] = {k: sv[k] for k in ("value", "unit", "p50_ms", "p99_ms", "mean_ms", "jobs_per_s",
                                                 "offered_accesses_per_s", "config", "server")}
     if not args.no_cpu_baseline:

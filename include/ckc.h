@@ -221,12 +221,13 @@ int ckc_read_results(ckc_ctx ctx, uint64_t job, ckc_record* recs, uint8_t* maps,
 /* Number of inputs and records of a job (for sizing result buffers). */
 int ckc_job_sizes(ckc_ctx ctx, uint64_t job, uint64_t* n_inputs, uint64_t* n_records);
 
-/* Device timing of the job's kernels in milliseconds (HIP events on the job's
+/* Device timing of the job's stages in milliseconds (HIP events on the job's
  * stream; waits for the job): [0] planning (thread sets, traces, tile scan),
- * [1] trace evaluator, [2] interpreter, [3] finishing (first-violation replay,
- * status, dense maps).  Jobs run as a graph report -1 in all four.  Call
- * before ckc_read_results releases the job. */
-int ckc_job_timing(ckc_ctx ctx, uint64_t job, float* ms4);
+ * [1] trace evaluators, [2] interpreter over whole threads, [3] body passes of
+ * expanded loops (piece scans, interpreted bodies, gather bodies), [4]
+ * finishing (first-violation replay, status, dense maps).  Jobs run as a
+ * graph report -1 in all five.  Call before ckc_read_results releases the job. */
+int ckc_job_timing(ckc_ctx ctx, uint64_t job, float* ms5);
 /* Device time of the whole job (first kernel start to last kernel end), in
  * milliseconds; waits for the job.  Errors: CKC_E_INVALID (unknown job). */
 int ckc_job_elapsed(ckc_ctx ctx, uint64_t job, float* ms);

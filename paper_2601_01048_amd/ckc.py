@@ -252,7 +252,8 @@ class Context:
         return ni.value, nr.value
 
     def timing(self, job: int):
-        ms = (ctypes.c_float * 4)()
+        """[plan, trace evaluators, interpreter, body passes, finishing] in ms."""
+        ms = (ctypes.c_float * 5)()
         _check(lib().ckc_job_timing(self.h, job, ms))
         return list(ms)
 

@@ -181,7 +181,7 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
 
 hipEvent_t ckc::rt::job_done_event(ckc_ctx c, uint64_t job) {
   auto it = c->jobs.find(job);
-  return it == c->jobs.end() ? nullptr : it->second.ev[4];
+  return it == c->jobs.end() ? nullptr : it->second.ev[ckc::rt::NEV - 1];
 }
 
 extern "C" {
@@ -417,7 +417,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   if (e == hipSuccess) e = hipMemcpyAsync(d_sc, hsc.data(), sizeof(int64_t) * hsc.size(), hipMemcpyHostToDevice, J.stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_order, order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, J.stream);
-  for (int q = 0; q < 5 && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
+  for (int q = 0; q < ckc::rt::NEV && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e)));
   KArgs a;
   a.inputs = J.d_inputs;
@@ -454,7 +454,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   e = hipEventRecord(J.ev[0], J.stream);
   if (J.graph) {
     if (e == hipSuccess) e = launch_graph(c, a, eg, n_records, J.stream);
-    for (int q = 1; q < 4 && e == hipSuccess; q++) e = hipEventRecord(J.ev[q], J.stream);
+    for (int q = 1; q < ckc::rt::NEV - 1 && e == hipSuccess; q++) e = hipEventRecord(J.ev[q], J.stream);
   } else {
     if (e == hipSuccess) e = launch_plan(a, J.stream);
     if (e == hipSuccess) e = launch_scan(a, J.stream);
@@ -463,12 +463,13 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     if (e == hipSuccess) e = launch_eval_trace_lanes(a, eg, J.stream);
     if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
     if (e == hipSuccess) e = launch_eval_generic(a, eg, J.stream);
-    if (e == hipSuccess) e = launch_expand(a, eg, J.stream);
     if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
+    if (e == hipSuccess) e = launch_expand(a, eg, J.stream);
+    if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
     if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
     if (e == hipSuccess) e = launch_finish(a, J.stream);
   }
-  if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[ckc::rt::NEV - 1], J.stream);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));
   for (uint32_t k = 0; k < n_descs; k++) {
     J.progs.push_back(descs[k].prog_id);
@@ -493,21 +494,18 @@ int ckc_job_sizes(ckc_ctx c, uint64_t job, uint64_t* n_inputs, uint64_t* n_recor
   return CKC_OK;
 }
 
-int ckc_job_timing(ckc_ctx c, uint64_t job, float* ms4) {
-  if (!c || !ms4) return fail(CKC_E_INVALID, "NULL argument");
+int ckc_job_timing(ckc_ctx c, uint64_t job, float* ms5) {
+  if (!c || !ms5) return fail(CKC_E_INVALID, "NULL argument");
   auto it = c->jobs.find(job);
   if (it == c->jobs.end()) return fail(CKC_E_INVALID, "unknown job");
   Job& J = it->second;
   set_device(c);
-  HIPCHECK(hipEventSynchronize(J.ev[4]));
+  HIPCHECK(hipEventSynchronize(J.ev[ckc::rt::NEV - 1]));
   if (J.graph) {
-    for (int q = 0; q < 4; q++) ms4[q] = -1.0f;
+    for (int q = 0; q < ckc::rt::NEV - 1; q++) ms5[q] = -1.0f;
     return CKC_OK;
   }
-  HIPCHECK(hipEventElapsedTime(&ms4[0], J.ev[0], J.ev[1]));
-  HIPCHECK(hipEventElapsedTime(&ms4[1], J.ev[1], J.ev[2]));
-  HIPCHECK(hipEventElapsedTime(&ms4[2], J.ev[2], J.ev[3]));
-  HIPCHECK(hipEventElapsedTime(&ms4[3], J.ev[3], J.ev[4]));
+  for (int q = 0; q < ckc::rt::NEV - 1; q++) HIPCHECK(hipEventElapsedTime(&ms5[q], J.ev[q], J.ev[q + 1]));
   return CKC_OK;
 }
 
@@ -517,8 +515,8 @@ int ckc_job_elapsed(ckc_ctx c, uint64_t job, float* ms) {
   if (it == c->jobs.end()) return fail(CKC_E_INVALID, "unknown job");
   Job& J = it->second;
   set_device(c);
-  HIPCHECK(hipEventSynchronize(J.ev[4]));
-  HIPCHECK(hipEventElapsedTime(ms, J.ev[0], J.ev[4]));
+  HIPCHECK(hipEventSynchronize(J.ev[ckc::rt::NEV - 1]));
+  HIPCHECK(hipEventElapsedTime(ms, J.ev[0], J.ev[ckc::rt::NEV - 1]));
   return CKC_OK;
 }
 
@@ -531,7 +529,7 @@ int ckc_read_results(ckc_ctx c, uint64_t job, ckc_record* recs, uint8_t* maps, c
   int rc;
   if ((rc = set_device(c))) return rc;
   if (!(flags & CKC_WAIT)) {
-    hipError_t q = hipEventQuery(J.ev[4]);
+    hipError_t q = hipEventQuery(J.ev[ckc::rt::NEV - 1]);
     if (q == hipErrorNotReady) return CKC_NOT_READY;
     if (q != hipSuccess) return fail(CKC_E_HIP, std::string("job: ") + hipGetErrorString(q));
   }

@@ -15,6 +15,8 @@
 namespace ckc {
 namespace rt {
 
+constexpr int NEV = 6;  // plan | trace evaluators | interpreter | body passes | finishing
+
 struct Program {
   void* dblob = nullptr;
   Loaded L;
@@ -37,9 +39,9 @@ struct Job {
   uint8_t* d_maps = nullptr;
   uint64_t n_inputs = 0, n_records = 0;
   std::vector<uint32_t> progs, tables;
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[NEV] = {};  // job start, then the end of each timed stage
   bool dense = false;
-  bool graph = false;  // ran as one graph: only ev[0] and ev[4] are meaningful
+  bool graph = false;  // ran as one graph: only the first and last events are meaningful
 };
 
 }  // namespace rt

@@ -82,7 +82,7 @@ def test_alone_equals_in_batch(ctx, mini):
 def test_graph_timing_and_elapsed(ctx, mini):
     mb, db = mini
     job = ctx.check(db.descs(), opts=ckc.launch_opts(use_graph=True))
-    assert ctx.timing(job) == [-1.0] * 4
+    assert ctx.timing(job) == [-1.0] * 5
     assert ctx.elapsed(job) > 0
     ctx.release(job)
     job = ctx.check(db.descs())
