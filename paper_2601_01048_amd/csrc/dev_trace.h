@@ -173,10 +173,11 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h6
   constexpr uint32_t EB = W == 32 ? 8 : 4;  // entries per scalar-load batch
   uint32_t e = 0;  // first entry that needs the violation path
   if (!DEADS) {
-    // fast scan: stop at the first entry with a violating lane
+    // fast scan: one test per batch of EB entries (the OR of their lane
+    // masks); a batch with a violating lane goes to the violation path whole
     const uint32_t neb = ne - ne % EB;
     bool hit = false;
-    for (uint32_t e0 = 0; e0 < neb && !hit; e0 += EB) {
+    for (uint32_t e0 = 0; e0 < neb; e0 += EB) {
       uint64_t off[EB], bnd[EB];
 #pragma unroll
       for (uint32_t k = 0; k < EB; k++) {
@@ -188,14 +189,15 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h6
           bnd[k] = (uint64_t)h64[2 * (e0 + k) + 1];
         }
       }
+      uint64_t badm = 0;
 #pragma unroll
-      for (uint32_t k = 0; k < EB; k++) {
-        if (!hit && __ballot(entry_bad<W, ALL>(tpart, off[k], bnd[k], bp, nvalid))) {
-          hit = true;
-          e = e0 + k;
-        }
+      for (uint32_t k = 0; k < EB; k++) badm |= __ballot(entry_bad<W, ALL>(tpart, off[k], bnd[k], bp, nvalid));
+      e = e0;
+      if (badm) {
+        hit = true;
+        break;
       }
-      if (!hit) e = e0 + EB;
+      e = e0 + EB;
     }
     if (!hit) {
       for (; e < ne; e++) {
