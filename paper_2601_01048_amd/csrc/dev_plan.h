@@ -290,10 +290,11 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
     const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
     if (path == 0) {
       if (in.mode != CKC_REP_CORNERS && bs % 64u == 0 && ((const dtrace_head*)in.trace)->n_classes == 1) {
-        // block-major jobs: (64-thread slice position, group of LPB set blocks)
+        // block-major jobs: (64-thread slice position, NGJ groups of LPB set blocks)
         const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
                                                  : bset_size(in.launch);
-        const uint64_t jobs = (uint64_t)(bs / 64u) * ((nsb + LPB - 1) / LPB);
+        const uint64_t ngroups = (nsb + LPB - 1) / LPB;
+        const uint64_t jobs = (uint64_t)(bs / 64u) * ((ngroups + NGJ - 1) / NGJ);
         tiles = (jobs + 3) / 4;
         path = PATH_BLOCKS;
       } else {

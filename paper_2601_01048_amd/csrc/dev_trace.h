@@ -93,12 +93,12 @@ typedef const __attribute__((address_space(4))) dprog c_dprog;
 
 // Violation path of entry e in a block-major job (rare): per block, the mask
 // of violating lanes and of negative indices; the first block with a
-// violation gives the first key at its lowest violating lane.
+// violation gives the first key at its lowest violating lane.  w[j] is this
+// lane's index base (thread part + block part) in block j of group g.
 template <int W, class BT>
-__device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint32_t e, uint64_t tpart,
-                                                 const BT* bp, const uint32_t* Lg, uint64_t g, uint32_t bs,
-                                                 uint32_t nvalid, uint32_t tlin_lane0, ckc_record* rec,
-                                                 bool lds, uint32_t Lsum) {
+__device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint32_t e, const BT* w,
+                                                 const uint32_t* Lg, uint64_t g, uint32_t bs, uint32_t nvalid,
+                                                 uint32_t tlin_lane0, ckc_record* rec, bool lds, uint32_t Lsum) {
   const int64_t off = te[e].off;
   const uint64_t bound = te[e].bound;
   const uint32_t dead = te[e].dead_kind;
@@ -107,11 +107,11 @@ __device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint3
   for (uint32_t j = 0; j < nvalid; j++) {
     uint64_t badm, underm;
     if (W == 32) {
-      const uint32_t v = (uint32_t)tpart + (uint32_t)off + (uint32_t)bp[j];
+      const uint32_t v = (uint32_t)w[j] + (uint32_t)off;
       badm = __ballot(v >= (uint32_t)bound);
       underm = __ballot((int32_t)v < 0);
     } else {
-      const uint64_t v = tpart + (uint64_t)off + (uint64_t)bp[j];
+      const uint64_t v = (uint64_t)w[j] + (uint64_t)off;
       badm = __ballot(v >= bound);
       underm = __ballot((int64_t)v < 0);
     }
@@ -136,38 +136,35 @@ __device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint3
   if (cnt) tr_note(S, rec, te[e].acc, lds, fk, cnt, kinds);
 }
 
-// Block-major checks of one wavefront job: this lane's thread position in up to
-// LPB set blocks; tpart is the thread part of the index base, bp[j] the block
-// parts (wavefront-uniform).  Entries come as packed (offset, bound) pairs
-// through scalar loads.  Width 32: an index is in bounds iff its unsigned
-// value is below the bound (clamped to 2^31), so one entry is clean for all
-// blocks iff the unsigned maximum over the blocks is below the bound -- one
-// add per block, a max tree and one compare.
+// Block-major checks of one group: w[j] is this lane's index base in block j
+// of the group (thread part + block part, wrapped at the index width).
+// Entries come as packed (offset, bound) pairs through scalar loads.  Width
+// 32: an index is in bounds iff its unsigned value is below the bound (clamped
+// to 2^31), so one entry is clean for all blocks iff the unsigned maximum over
+// the blocks is below the bound -- one add per block, a max tree and one
+// compare.
 template <int W, bool ALL, class BT>
-__device__ __forceinline__ bool entry_bad(uint64_t tpart, uint64_t off, uint64_t bnd, const BT* bp,
-                                          uint32_t nvalid) {
+__device__ __forceinline__ bool entry_bad(uint64_t off, uint64_t bnd, const BT* w, uint32_t nvalid) {
   if (W == 32) {
-    const uint32_t t = (uint32_t)tpart + (uint32_t)off;
     uint32_t mx = 0;
 #pragma unroll
     for (uint32_t j = 0; j < LPB; j++) {
-      const uint32_t v = t + (uint32_t)bp[j];
+      const uint32_t v = (uint32_t)w[j] + (uint32_t)off;
       if (ALL || j < nvalid) mx = v > mx ? v : mx;
     }
     return mx >= (uint32_t)bnd;
   } else {
-    const uint64_t t = tpart + off;
     bool x = false;
 #pragma unroll
     for (uint32_t j = 0; j < LPB; j++)
-      if (ALL || j < nvalid) x |= (t + (uint64_t)bp[j]) >= bnd;
+      if (ALL || j < nvalid) x |= ((uint64_t)w[j] + off) >= bnd;
     return x;
   }
 }
 
 template <int W, bool ALL, bool DEADS, class BT>
 __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h64, c_u32* h32, uint32_t ne,
-                                             uint64_t tpart, const BT* bp, const uint32_t* Lg, uint64_t g,
+                                             const BT* w, const uint32_t* Lg, uint64_t g,
                                              uint32_t bs, uint32_t nvalid, uint32_t tlin_lane0,
                                              ckc_record* rec, bool lds, uint32_t Lsum) {
   constexpr uint32_t EB = W == 32 ? 8 : 4;  // entries per scalar-load batch
@@ -191,7 +188,7 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h6
       }
       uint64_t badm = 0;
 #pragma unroll
-      for (uint32_t k = 0; k < EB; k++) badm |= __ballot(entry_bad<W, ALL>(tpart, off[k], bnd[k], bp, nvalid));
+      for (uint32_t k = 0; k < EB; k++) badm |= __ballot(entry_bad<W, ALL>(off[k], bnd[k], w, nvalid));
       e = e0;
       if (badm) {
         hit = true;
@@ -209,7 +206,7 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h6
           off = (uint64_t)h64[2 * e];
           bnd = (uint64_t)h64[2 * e + 1];
         }
-        if (__ballot(entry_bad<W, ALL>(tpart, off, bnd, bp, nvalid))) break;
+        if (__ballot(entry_bad<W, ALL>(off, bnd, w, nvalid))) break;
       }
     }
     if (e >= ne) return;
@@ -224,8 +221,8 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h6
       off = (uint64_t)h64[2 * e];
       bnd = (uint64_t)h64[2 * e + 1];
     }
-    if (DEADS || __ballot(entry_bad<W, false>(tpart, off, bnd, bp, nvalid)))
-      blocks_violation<W>(S, te, e, tpart, bp, Lg, g, bs, nvalid, tlin_lane0, rec, lds, Lsum);
+    if (DEADS || __ballot(entry_bad<W, false>(off, bnd, w, nvalid)))
+      blocks_violation<W>(S, te, e, w, Lg, g, bs, nvalid, tlin_lane0, rec, lds, Lsum);
   }
 }
 
@@ -234,7 +231,8 @@ struct TrIn {
   uint32_t L[7];  // launch dims, then the thread-set mode
   uint32_t bs, gxy, bxy, mode, Lsum, ne, n_acc;
   UDiv dgx, dgxy, dbx, dbxy, dspb;
-  uint64_t nsb;
+  uint32_t nsb;      // blocks of the thread set (below 2^32)
+  uint32_t ngroups;  // groups of LPB set blocks
   c_head* th;     // coefficients are re-read per job (scalar loads)
   uint32_t any_dead;
   bool lds;
@@ -244,10 +242,13 @@ struct TrIn {
   ckc_record* rec;
 };
 
-// One block-major wavefront job: slice position o (64 threads) of the blocks
-// g*LPB .. g*LPB+LPB-1 of the set.
+// One block-major wavefront job: slice position o (64 threads) of the groups
+// gs*NGJ .. gs*NGJ+NGJ-1 (LPB set blocks each).  The thread part of the index
+// base is formed once per job; in the whole-grid mode the block coordinates
+// are walked from group to group, and a group that stays inside one grid row
+// forms its block parts by adding the x coefficient.
 template <int W>
-__device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint64_t g, uint32_t o) {
+__device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint32_t gs, uint32_t o) {
   typedef typename std::conditional<W == 32, uint32_t, uint64_t>::type BT;
   const uint32_t tlin = o * 64u + (threadIdx.x & 63u);
   const uint32_t tz = udiv(tlin, I.dbxy), tr = tlin - tz * I.bxy;
@@ -255,41 +256,91 @@ __device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint64_t g
   const uint32_t tx = tr - ty * I.L[3];
   const int64_t k0 = I.th->coef[0][0], k1 = I.th->coef[0][1], k2 = I.th->coef[0][2];
   const int64_t k3 = I.th->coef[0][3], k4 = I.th->coef[0][4], k5 = I.th->coef[0][5];
-  uint64_t tpart = 0;
-  if (k0 == 1) tpart += tx; else if (k0 != 0) tpart += (uint64_t)k0 * tx;
-  if (k1 == 1) tpart += ty; else if (k1 != 0) tpart += (uint64_t)k1 * ty;
-  if (k2 == 1) tpart += tz; else if (k2 != 0) tpart += (uint64_t)k2 * tz;
-  BT bp[LPB];
-  const uint64_t left = I.nsb - g * LPB;
-  const uint32_t nvalid = left < LPB ? (uint32_t)left : LPB;
+  // thread part at the index width (wrapping there is the index semantics)
+  BT tp = 0;
+  if (k0 == 1) tp += (BT)tx; else if (k0 != 0) tp += (BT)k0 * (BT)tx;
+  if (k1 == 1) tp += (BT)ty; else if (k1 != 0) tp += (BT)k1 * (BT)ty;
+  if (k2 == 1) tp += (BT)tz; else if (k2 != 0) tp += (BT)k2 * (BT)tz;
+  const uint32_t t0 = o * 64u;
+  uint32_t g = gs * NGJ;
+  const uint32_t gend = g + NGJ < I.ngroups ? g + NGJ : I.ngroups;
+  // whole grid: coordinates and block part of the group's first block; the
+  // block part moves by k3 per block, by k4 - k3 (gx-1) when x wraps and by
+  // k5 - k3 (gx-1) - k4 (gy-1) when y wraps as well
+  const BT d1 = (BT)k3;
+  const BT dy = (BT)k4 - (BT)k3 * (BT)(I.L[0] - 1);
+  const BT dz = (BT)k5 - (BT)k3 * (BT)(I.L[0] - 1) - (BT)k4 * (BT)(I.L[1] - 1);
+  uint32_t bx = 0, by = 0, bz = 0;
+  BT cur = 0;
   if (I.mode == CKC_FULL) {
-    // blocks g*LPB ..: walk x with carries from the first one
-    const uint32_t b0 = (uint32_t)(g * LPB);
-    uint32_t bz = udiv(b0, I.dgxy), brem = b0 - bz * I.gxy;
-    uint32_t by = udiv(brem, I.dgx), bx = brem - by * I.L[0];
+    const uint32_t b0 = g * LPB;
+    bz = udiv(b0, I.dgxy);
+    const uint32_t brem = b0 - bz * I.gxy;
+    by = udiv(brem, I.dgx);
+    bx = brem - by * I.L[0];
+    cur = (BT)k3 * (BT)bx + (BT)k4 * (BT)by + (BT)k5 * (BT)bz;
+  }
+#pragma unroll 1
+  for (; g < gend; g++) {
+    BT w[LPB];
+    const uint32_t left = I.nsb - g * LPB;
+    const uint32_t nvalid = left < LPB ? left : LPB;
+    if (I.mode == CKC_FULL) {
+      if (bx + LPB <= I.L[0]) {
+        // the group stays in one row
+        BT v = tp + cur;
 #pragma unroll
-    for (uint32_t jj = 0; jj < LPB; jj++) {
-      bp[jj] = (BT)((uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz);
-      if (++bx == I.L[0]) {
-        bx = 0;
-        if (++by == I.L[1]) { by = 0; ++bz; }
+        for (uint32_t jj = 0; jj < LPB; jj++) {
+          w[jj] = v;
+          v += d1;
+        }
+        bx += LPB;
+        cur += (BT)LPB * d1;
+        if (bx == I.L[0]) {
+          bx = 0;
+          if (++by == I.L[1]) {
+            by = 0;
+            ++bz;
+            cur += dz;
+          } else {
+            cur += dy;
+          }
+          cur -= d1;
+        }
+      } else {
+#pragma unroll
+        for (uint32_t jj = 0; jj < LPB; jj++) {
+          w[jj] = tp + cur;
+          if (++bx == I.L[0]) {
+            bx = 0;
+            if (++by == I.L[1]) {
+              by = 0;
+              ++bz;
+              cur += dz;
+            } else {
+              cur += dy;
+            }
+          } else {
+            cur += d1;
+          }
+        }
+      }
+    } else {
+      for (uint32_t jj = 0; jj < LPB; jj++) {
+        const uint32_t blin =
+            jj < nvalid ? (uint32_t)bset_block_call(I.L[0], I.L[1], I.L[2], (uint64_t)g * LPB + jj) : 0u;
+        const uint32_t cz = udiv(blin, I.dgxy), crem = blin - cz * I.gxy;
+        const uint32_t cy = udiv(crem, I.dgx), cx = crem - cy * I.L[0];
+        w[jj] = tp + (BT)((uint64_t)k3 * cx + (uint64_t)k4 * cy + (uint64_t)k5 * cz);
       }
     }
-  } else {
-    for (uint32_t jj = 0; jj < LPB; jj++) {
-      const uint32_t blin = jj < nvalid ? (uint32_t)bset_block_call(I.L[0], I.L[1], I.L[2], g * LPB + jj) : 0u;
-      const uint32_t bz = udiv(blin, I.dgxy), brem = blin - bz * I.gxy;
-      const uint32_t by = udiv(brem, I.dgx), bx = brem - by * I.L[0];
-      bp[jj] = (BT)((uint64_t)k3 * bx + (uint64_t)k4 * by + (uint64_t)k5 * bz);
+    if (I.any_dead) {
+      trace_blocks<W, false, true>(S, I.te, I.h64, I.h32, I.ne, w, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+    } else if (nvalid == LPB) {
+      trace_blocks<W, true, false>(S, I.te, I.h64, I.h32, I.ne, w, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+    } else {
+      trace_blocks<W, false, false>(S, I.te, I.h64, I.h32, I.ne, w, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
     }
-  }
-  const uint32_t t0 = o * 64u;
-  if (I.any_dead) {
-    trace_blocks<W, false, true>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
-  } else if (nvalid == LPB) {
-    trace_blocks<W, true, false>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
-  } else {
-    trace_blocks<W, false, false>(S, I.te, I.h64, I.h32, I.ne, tpart, bp, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
   }
 }
 
@@ -349,7 +400,8 @@ __device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_r
   I.ne = th->n_entries;
   ncls = th->n_classes;
   w0 = th->cls_w[0];
-  I.nsb = I.mode == CKC_FULL ? (uint64_t)I.L[0] * I.L[1] * I.L[2] : bset_size(I.L);
+  I.nsb = (uint32_t)(I.mode == CKC_FULL ? (uint64_t)I.L[0] * I.L[1] * I.L[2] : bset_size(I.L));
+  I.ngroups = (I.nsb + LPB - 1) / LPB;
   I.th = th;
   tb = ins[i].tile_begin[path];
 }
@@ -357,7 +409,7 @@ __device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_r
 // Trace evaluator, block-major layout: persistent workgroups over the tile
 // space of PATH_BLOCKS under the job's schedule; a tile is four wavefront jobs.
 template <uint32_t SK>
-__global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, 7) eval_trace_kernel(KArgs a) {
   __shared__ TraceLds S;
   __shared__ unsigned long long item_slot;
   c_jobstate* js = (c_jobstate*)a.js;
@@ -393,11 +445,11 @@ __global__ void __launch_bounds__(TILE) eval_trace_kernel(KArgs a) {
     const uint32_t wv = ufirst(tid >> 6);
     const uint64_t job = (t - tb) * 4 + wv;
     const uint32_t spb = I.bs / 64u;
-    const uint64_t g = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, I.dspb) : job / spb;
-    const uint32_t o = (uint32_t)(job - g * spb);
-    if (g * LPB >= I.nsb) continue;  // past the last group (whole wavefront)
-    if (w0 == 32) block_job<32>(S, I, g, o);
-    else block_job<64>(S, I, g, o);
+    const uint64_t gs = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, I.dspb) : job / spb;
+    const uint32_t o = (uint32_t)(job - gs * spb);
+    if (gs * NGJ >= I.ngroups) continue;  // past the last group (whole wavefront)
+    if (w0 == 32) block_job<32>(S, I, (uint32_t)gs, o);
+    else block_job<64>(S, I, (uint32_t)gs, o);
   }
   if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
 }

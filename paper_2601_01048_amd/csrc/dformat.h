@@ -92,7 +92,8 @@ static_assert(sizeof(dinput) == 168, "dinput layout");
 enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };
 
 constexpr int MAX_SCALARS = 16;
-constexpr uint32_t LPB = 16;  // blocks per wavefront job of the block-major trace path
+constexpr uint32_t LPB = 16;  // blocks per group of the block-major trace path
+constexpr uint32_t NGJ = 4;   // groups per wavefront job of the block-major trace path
 
 // Trace of a uniform-control program for one input: every thread performs the
 // same access sequence; each access index is base[class](thread) + off.
