@@ -297,6 +297,39 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
         const uint64_t jobs = (uint64_t)(bs / 64u) * ((ngroups + NGJ - 1) / NGJ);
         tiles = (jobs + 3) / 4;
         path = PATH_BLOCKS;
+        dtrace_head* th = (dtrace_head*)in.trace;
+        dblk& B = th->blk;
+        for (int q = 0; q < 6; q++) B.L[q] = in.launch[q];
+        const uint32_t L0 = in.launch[0], L1 = in.launch[1], L3 = in.launch[3], L4 = in.launch[4];
+        B.mode = in.mode;
+        B.bs = bs;
+        B.gxy = L0 * L1;
+        B.bxy = L3 * L4;
+        B.nsb = (uint32_t)nsb;
+        B.ngroups = (uint32_t)ngroups;
+        B.spb = bs / 64u;
+        B.ne = th->n_entries;
+        B.any_dead = th->any_dead;
+        B.w = th->cls_w[0];
+        B.Lsum = in.L1 + in.L2;
+        B.n_acc = P->n_accesses;
+        UDiv u = udiv_make(L0);
+        B.m_gx = u.m; B.s_gx = u.s;
+        u = udiv_make(L0 * L1);
+        B.m_gxy = u.m; B.s_gxy = u.s;
+        u = udiv_make(L3);
+        B.m_bx = u.m; B.s_bx = u.s;
+        u = udiv_make(L3 * L4);
+        B.m_bxy = u.m; B.s_bxy = u.s;
+        u = udiv_make(bs / 64u);
+        B.m_spb = u.m; B.s_spb = u.s;
+        for (int q = 0; q < 4; q++) B.pad[q] = 0;
+        for (int q = 0; q < 6; q++) B.k[q] = th->coef[0][q];
+        const uint64_t k3 = (uint64_t)B.k[3], k4 = (uint64_t)B.k[4], k5 = (uint64_t)B.k[5];
+        B.d1 = k3;
+        B.dy = k4 - k3 * (uint64_t)(L0 - 1);
+        B.dz = k5 - k3 * (uint64_t)(L0 - 1) - k4 * (uint64_t)(L1 - 1);
+        B.rec = (uint64_t)(a.recs + in.rec_base);
       } else {
         path = PATH_LANES;
       }

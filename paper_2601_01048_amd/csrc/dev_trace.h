@@ -90,15 +90,34 @@ __device__ __forceinline__ uint64_t bset_block_call(uint32_t gx, uint32_t gy, ui
 
 typedef const __attribute__((address_space(4))) int64_t c_i64;
 typedef const __attribute__((address_space(4))) dprog c_dprog;
+typedef const __attribute__((address_space(4))) dblk c_blk;
 
-// Violation path of entry e in a block-major job (rare): per block, the mask
-// of violating lanes and of negative indices; the first block with a
-// violation gives the first key at its lowest violating lane.  w[j] is this
-// lane's index base (thread part + block part) in block j of group g.
+// An opaque copy of p: loads through it cannot be hoisted out of the loop the
+// copy is made in, so such per-input values are reloaded with scalar loads
+// where they are used instead of being held in registers across the loop.
+template <class T>
+__device__ __forceinline__ T* fresh(T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+__device__ __forceinline__ c_i64* trace_hot64(c_head* th) { return (c_i64*)(th + 1); }
+__device__ __forceinline__ c_u32* trace_hot32(c_head* th) {
+  return (c_u32*)(trace_hot64(th) + 2 * (size_t)th->cap8);
+}
+__device__ __forceinline__ c_entry* trace_entries(c_head* th) {
+  return (c_entry*)(trace_hot32(th) + 2 * (size_t)th->cap8);
+}
+
+// Violation path of entry e in group g of a block-major job (rare): per
+// block, the mask of violating lanes and of negative indices; the first block
+// with a violation gives the first key at its lowest violating lane.  w[j] is
+// this lane's index base (thread part + block part) in block j of the group.
 template <int W, class BT>
-__device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint32_t e, const BT* w,
-                                                 const uint32_t* Lg, uint64_t g, uint32_t bs, uint32_t nvalid,
-                                                 uint32_t tlin_lane0, ckc_record* rec, bool lds, uint32_t Lsum) {
+__device__ __forceinline__ void blocks_violation(TraceLds& S, c_head* th, uint32_t e, const BT* w, uint32_t g,
+                                              uint32_t nvalid, uint32_t t0) {
+  c_blk* B = &th->blk;
+  c_entry* te = trace_entries(th);
   const int64_t off = te[e].off;
   const uint64_t bound = te[e].bound;
   const uint32_t dead = te[e].dead_kind;
@@ -124,94 +143,90 @@ __device__ __forceinline__ void blocks_violation(TraceLds& S, c_entry* te, uint3
     }
     if (badm) {
       if (fk == ~0ull) {
-        // block of member g*LPB + j of the thread set (Lg[6] holds the mode)
-        const uint64_t k = g * LPB + j;
-        const uint64_t blin = Lg[6] == CKC_FULL ? k : bset_block(Lg, k);
-        fk = ((blin * bs + tlin_lane0 + (uint64_t)(__ffsll((unsigned long long)badm) - 1)) << Lsum) |
+        // block of member g*LPB + j of the thread set
+        const uint64_t k = (uint64_t)g * LPB + j;
+        uint32_t L[6];
+        for (int q = 0; q < 6; q++) L[q] = B->L[q];
+        const uint64_t blin = B->mode == CKC_FULL ? k : bset_block(L, k);
+        fk = ((blin * B->bs + t0 + (uint64_t)(__ffsll((unsigned long long)badm) - 1)) << B->Lsum) |
              te[e].keylo;
       }
       cnt += (uint64_t)__popcll(badm);
     }
   }
-  if (cnt) tr_note(S, rec, te[e].acc, lds, fk, cnt, kinds);
+  if (cnt) tr_note(S, (ckc_record*)B->rec, te[e].acc, B->n_acc <= TR_ACC_LDS, fk, cnt, kinds);
 }
 
 // Block-major checks of one group: w[j] is this lane's index base in block j
-// of the group (thread part + block part, wrapped at the index width).
-// Entries come as packed (offset, bound) pairs through scalar loads.  Width
-// 32: an index is in bounds iff its unsigned value is below the bound (clamped
-// to 2^31), so one entry is clean for all blocks iff the unsigned maximum over
-// the blocks is below the bound -- one add per block, a max tree and one
-// compare.
-template <int W, bool ALL, class BT>
-__device__ __forceinline__ bool entry_bad(uint64_t off, uint64_t bnd, const BT* w, uint32_t nvalid) {
+// of the group (thread part + block part, wrapped at the index width); a
+// group with fewer than LPB blocks repeats its first block's base in the
+// unused slots.  Entries come as packed (offset, bound) pairs through scalar
+// loads.  Width 32: an index is in bounds iff its unsigned value is below the
+// bound (clamped to 2^31), so one entry is clean for all blocks iff the
+// unsigned maximum over the blocks is below the bound -- one add per block, a
+// max tree and one compare.
+template <int W, class BT>
+__device__ __forceinline__ bool entry_bad(uint64_t off, uint64_t bnd, const BT* w) {
   if (W == 32) {
     uint32_t mx = 0;
 #pragma unroll
     for (uint32_t j = 0; j < LPB; j++) {
       const uint32_t v = (uint32_t)w[j] + (uint32_t)off;
-      if (ALL || j < nvalid) mx = v > mx ? v : mx;
+      mx = v > mx ? v : mx;
     }
     return mx >= (uint32_t)bnd;
   } else {
     bool x = false;
 #pragma unroll
-    for (uint32_t j = 0; j < LPB; j++)
-      if (ALL || j < nvalid) x |= ((uint64_t)w[j] + off) >= bnd;
+    for (uint32_t j = 0; j < LPB; j++) x |= ((uint64_t)w[j] + off) >= bnd;
     return x;
   }
 }
 
-template <int W, bool ALL, bool DEADS, class BT>
-__device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h64, c_u32* h32, uint32_t ne,
-                                             const BT* w, const uint32_t* Lg, uint64_t g,
-                                             uint32_t bs, uint32_t nvalid, uint32_t tlin_lane0,
-                                             ckc_record* rec, bool lds, uint32_t Lsum) {
+template <int W, bool DEADS, class BT>
+__device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, const BT* w, uint32_t g, uint32_t nvalid,
+                                             uint32_t t0) {
   constexpr uint32_t EB = W == 32 ? 8 : 4;  // entries per scalar-load batch
+  const uint32_t ne = th->blk.ne;
+  c_i64* h64 = trace_hot64(th);
+  c_u32* h32 = trace_hot32(th);
   uint32_t e = 0;  // first entry that needs the violation path
   if (!DEADS) {
     // fast scan: one test per batch of EB entries (the OR of their lane
-    // masks); a batch with a violating lane goes to the violation path whole
-    const uint32_t neb = ne - ne % EB;
+    // masks); a batch with a violating lane goes to the violation path whole.
+    // The trace arrays hold a multiple of 8 entries, so the last batch load
+    // stays inside them; its entries past the end are not tested.
     bool hit = false;
-    for (uint32_t e0 = 0; e0 < neb; e0 += EB) {
+    for (; e < ne; e += EB) {
       uint64_t off[EB], bnd[EB];
 #pragma unroll
       for (uint32_t k = 0; k < EB; k++) {
         if (W == 32) {
-          off[k] = h32[2 * (e0 + k)];
-          bnd[k] = h32[2 * (e0 + k) + 1];
+          off[k] = h32[2 * (e + k)];
+          bnd[k] = h32[2 * (e + k) + 1];
         } else {
-          off[k] = (uint64_t)h64[2 * (e0 + k)];
-          bnd[k] = (uint64_t)h64[2 * (e0 + k) + 1];
+          off[k] = (uint64_t)h64[2 * (e + k)];
+          bnd[k] = (uint64_t)h64[2 * (e + k) + 1];
         }
       }
       uint64_t badm = 0;
+      if (e + EB <= ne) {
 #pragma unroll
-      for (uint32_t k = 0; k < EB; k++) badm |= __ballot(entry_bad<W, ALL>(off[k], bnd[k], w, nvalid));
-      e = e0;
+        for (uint32_t k = 0; k < EB; k++) badm |= __ballot(entry_bad<W>(off[k], bnd[k], w));
+      } else {
+        const uint32_t r = ne - e;
+#pragma unroll
+        for (uint32_t k = 0; k < EB - 1; k++)
+          if (k < r) badm |= __ballot(entry_bad<W>(off[k], bnd[k], w));
+      }
       if (badm) {
         hit = true;
         break;
       }
-      e = e0 + EB;
     }
-    if (!hit) {
-      for (; e < ne; e++) {
-        uint64_t off, bnd;
-        if (W == 32) {
-          off = h32[2 * e];
-          bnd = h32[2 * e + 1];
-        } else {
-          off = (uint64_t)h64[2 * e];
-          bnd = (uint64_t)h64[2 * e + 1];
-        }
-        if (__ballot(entry_bad<W, ALL>(off, bnd, w, nvalid))) break;
-      }
-    }
-    if (e >= ne) return;
+    if (!hit) return;
   }
-  // violation path: the remaining entries one by one (one copy of this code)
+  // violation path: the remaining entries one by one
   for (; e < ne; e++) {
     uint64_t off, bnd;
     if (W == 32) {
@@ -221,8 +236,7 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_entry* te, c_i64* h6
       off = (uint64_t)h64[2 * e];
       bnd = (uint64_t)h64[2 * e + 1];
     }
-    if (DEADS || __ballot(entry_bad<W, false>(off, bnd, w, nvalid)))
-      blocks_violation<W>(S, te, e, w, Lg, g, bs, nvalid, tlin_lane0, rec, lds, Lsum);
+    if (DEADS || __ballot(entry_bad<W>(off, bnd, w))) blocks_violation<W>(S, th, e, w, g, nvalid, t0);
   }
 }
 
@@ -247,15 +261,15 @@ struct TrIn {
 // base is formed once per job; in the whole-grid mode the block coordinates
 // are walked from group to group, and a group that stays inside one grid row
 // forms its block parts by adding the x coefficient.
-template <int W>
-__device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint32_t gs, uint32_t o) {
+template <int W, bool FULL>
+__device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, uint32_t o) {
   typedef typename std::conditional<W == 32, uint32_t, uint64_t>::type BT;
+  c_blk* B = &th->blk;
   const uint32_t tlin = o * 64u + (threadIdx.x & 63u);
-  const uint32_t tz = udiv(tlin, I.dbxy), tr = tlin - tz * I.bxy;
-  const uint32_t ty = udiv(tr, I.dbx);
-  const uint32_t tx = tr - ty * I.L[3];
-  const int64_t k0 = I.th->coef[0][0], k1 = I.th->coef[0][1], k2 = I.th->coef[0][2];
-  const int64_t k3 = I.th->coef[0][3], k4 = I.th->coef[0][4], k5 = I.th->coef[0][5];
+  const uint32_t tz = udiv(tlin, UDiv{B->m_bxy, B->s_bxy}), tr = tlin - tz * B->bxy;
+  const uint32_t ty = udiv(tr, UDiv{B->m_bx, B->s_bx});
+  const uint32_t tx = tr - ty * B->L[3];
+  const int64_t k0 = B->k[0], k1 = B->k[1], k2 = B->k[2];
   // thread part at the index width (wrapping there is the index semantics)
   BT tp = 0;
   if (k0 == 1) tp += (BT)tx; else if (k0 != 0) tp += (BT)k0 * (BT)tx;
@@ -263,30 +277,31 @@ __device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint32_t g
   if (k2 == 1) tp += (BT)tz; else if (k2 != 0) tp += (BT)k2 * (BT)tz;
   const uint32_t t0 = o * 64u;
   uint32_t g = gs * NGJ;
-  const uint32_t gend = g + NGJ < I.ngroups ? g + NGJ : I.ngroups;
-  // whole grid: coordinates and block part of the group's first block; the
-  // block part moves by k3 per block, by k4 - k3 (gx-1) when x wraps and by
-  // k5 - k3 (gx-1) - k4 (gy-1) when y wraps as well
-  const BT d1 = (BT)k3;
-  const BT dy = (BT)k4 - (BT)k3 * (BT)(I.L[0] - 1);
-  const BT dz = (BT)k5 - (BT)k3 * (BT)(I.L[0] - 1) - (BT)k4 * (BT)(I.L[1] - 1);
+  const uint32_t gend = g + NGJ < B->ngroups ? g + NGJ : B->ngroups;
+  // whole grid: coordinates and block part of the group's first block
   uint32_t bx = 0, by = 0, bz = 0;
   BT cur = 0;
-  if (I.mode == CKC_FULL) {
+  if (FULL) {
     const uint32_t b0 = g * LPB;
-    bz = udiv(b0, I.dgxy);
-    const uint32_t brem = b0 - bz * I.gxy;
-    by = udiv(brem, I.dgx);
-    bx = brem - by * I.L[0];
-    cur = (BT)k3 * (BT)bx + (BT)k4 * (BT)by + (BT)k5 * (BT)bz;
+    bz = udiv(b0, UDiv{B->m_gxy, B->s_gxy});
+    const uint32_t brem = b0 - bz * B->gxy;
+    by = udiv(brem, UDiv{B->m_gx, B->s_gx});
+    bx = brem - by * B->L[0];
+    cur = (BT)B->k[3] * (BT)bx + (BT)B->k[4] * (BT)by + (BT)B->k[5] * (BT)bz;
   }
 #pragma unroll 1
   for (; g < gend; g++) {
+    c_head* tg = fresh(th);
+    c_blk* Bg = &tg->blk;
     BT w[LPB];
-    const uint32_t left = I.nsb - g * LPB;
+    const uint32_t left = Bg->nsb - g * LPB;
     const uint32_t nvalid = left < LPB ? left : LPB;
-    if (I.mode == CKC_FULL) {
-      if (bx + LPB <= I.L[0]) {
+    if (FULL) {
+      // the block part moves by d1 per block, by dy when x wraps and by dz
+      // when y wraps as well
+      const uint32_t gx = Bg->L[0];
+      const BT d1 = (BT)Bg->d1;
+      if (bx + LPB <= gx) {
         // the group stays in one row
         BT v = tp + cur;
 #pragma unroll
@@ -296,24 +311,26 @@ __device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint32_t g
         }
         bx += LPB;
         cur += (BT)LPB * d1;
-        if (bx == I.L[0]) {
+        if (bx == gx) {
           bx = 0;
-          if (++by == I.L[1]) {
+          if (++by == Bg->L[1]) {
             by = 0;
             ++bz;
-            cur += dz;
+            cur += (BT)Bg->dz;
           } else {
-            cur += dy;
+            cur += (BT)Bg->dy;
           }
           cur -= d1;
         }
       } else {
+        const uint32_t gy = Bg->L[1];
+        const BT dy = (BT)Bg->dy, dz = (BT)Bg->dz;
 #pragma unroll
         for (uint32_t jj = 0; jj < LPB; jj++) {
           w[jj] = tp + cur;
-          if (++bx == I.L[0]) {
+          if (++bx == gx) {
             bx = 0;
-            if (++by == I.L[1]) {
+            if (++by == gy) {
               by = 0;
               ++bz;
               cur += dz;
@@ -326,21 +343,26 @@ __device__ __forceinline__ void block_job(TraceLds& S, const TrIn& I, uint32_t g
         }
       }
     } else {
+      uint32_t L[6];
+      for (int q = 0; q < 6; q++) L[q] = Bg->L[q];
+      const UDiv dgx{Bg->m_gx, Bg->s_gx}, dgxy{Bg->m_gxy, Bg->s_gxy};
+      const uint32_t gxy = Bg->gxy;
+      const int64_t k3 = Bg->k[3], k4 = Bg->k[4], k5 = Bg->k[5];
       for (uint32_t jj = 0; jj < LPB; jj++) {
-        const uint32_t blin =
-            jj < nvalid ? (uint32_t)bset_block_call(I.L[0], I.L[1], I.L[2], (uint64_t)g * LPB + jj) : 0u;
-        const uint32_t cz = udiv(blin, I.dgxy), crem = blin - cz * I.gxy;
-        const uint32_t cy = udiv(crem, I.dgx), cx = crem - cy * I.L[0];
+        const uint32_t blin = jj < nvalid ? (uint32_t)bset_block(L, (uint64_t)g * LPB + jj) : 0u;
+        const uint32_t cz = udiv(blin, dgxy), crem = blin - cz * gxy;
+        const uint32_t cy = udiv(crem, dgx), cx = crem - cy * L[0];
         w[jj] = tp + (BT)((uint64_t)k3 * cx + (uint64_t)k4 * cy + (uint64_t)k5 * cz);
       }
     }
-    if (I.any_dead) {
-      trace_blocks<W, false, true>(S, I.te, I.h64, I.h32, I.ne, w, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
-    } else if (nvalid == LPB) {
-      trace_blocks<W, true, false>(S, I.te, I.h64, I.h32, I.ne, w, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
-    } else {
-      trace_blocks<W, false, false>(S, I.te, I.h64, I.h32, I.ne, w, I.L, g, I.bs, nvalid, t0, I.rec, I.lds, I.Lsum);
+    if (nvalid < LPB) {
+      // the last group of the set: unused slots repeat the first block
+#pragma unroll
+      for (uint32_t jj = 1; jj < LPB; jj++)
+        if (jj >= nvalid) w[jj] = w[0];
     }
+    if (Bg->any_dead) trace_blocks<W, true>(S, tg, w, g, nvalid, t0);
+    else trace_blocks<W, false>(S, tg, w, g, nvalid, t0);
   }
 }
 
@@ -427,31 +449,39 @@ __global__ void __launch_bounds__(TILE, 7) eval_trace_kernel(KArgs a) {
     S.kinds[q] = 0;
   }
   __syncthreads();
-  uint32_t pos = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  const uint32_t wv = ufirst(tid >> 6);
+  uint32_t pos = 0xFFFFFFFFu;
   uint64_t tb = 0, cur_end = 0;
   c_head* th = nullptr;
-  TrIn I;
   for (;;) {
     const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_BLOCKS], &item_slot);
     if (t == ~0ull) break;
     if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
       const uint32_t np = pos_of_tile(ins, order, a.n_inputs, PATH_BLOCKS, pos, cur_end, t);
-      if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+      if (pos != 0xFFFFFFFFu && th->blk.n_acc <= TR_ACC_LDS)
+        tr_flush(S, (ckc_record*)th->blk.rec, th->blk.n_acc);
       pos = np;
       const uint32_t i = order[pos];
-      tr_load(I, ins, i, a.recs, tb, PATH_BLOCKS, ncls, w0, th);
+      th = (c_head*)ins[i].trace;
+      tb = ins[i].tile_begin[PATH_BLOCKS];
       cur_end = tb + ins[i].n_tiles[PATH_BLOCKS];
     }
-    const uint32_t wv = ufirst(tid >> 6);
+    c_head* tj = fresh(th);
+    c_blk* B = &tj->blk;
     const uint64_t job = (t - tb) * 4 + wv;
-    const uint32_t spb = I.bs / 64u;
-    const uint64_t gs = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, I.dspb) : job / spb;
-    const uint32_t o = (uint32_t)(job - gs * spb);
-    if (gs * NGJ >= I.ngroups) continue;  // past the last group (whole wavefront)
-    if (w0 == 32) block_job<32>(S, I, (uint32_t)gs, o);
-    else block_job<64>(S, I, (uint32_t)gs, o);
+    const uint64_t gs = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, UDiv{B->m_spb, B->s_spb}) : job / B->spb;
+    const uint32_t o = (uint32_t)(job - gs * B->spb);
+    if (gs * NGJ >= B->ngroups) continue;  // past the last group (whole wavefront)
+    const bool full = B->mode == CKC_FULL;
+    if (B->w == 32) {
+      if (full) block_job<32, true>(S, tj, (uint32_t)gs, o);
+      else block_job<32, false>(S, tj, (uint32_t)gs, o);
+    } else {
+      if (full) block_job<64, true>(S, tj, (uint32_t)gs, o);
+      else block_job<64, false>(S, tj, (uint32_t)gs, o);
+    }
   }
-  if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
+  if (pos != 0xFFFFFFFFu && th->blk.n_acc <= TR_ACC_LDS) tr_flush(S, (ckc_record*)th->blk.rec, th->blk.n_acc);
 }
 
 // Trace evaluator over lane tiles (thread sets or traces the block-major

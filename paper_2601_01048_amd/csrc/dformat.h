@@ -109,6 +109,20 @@ struct dtrace_entry {
 };
 static_assert(sizeof(dtrace_entry) == 32, "trace entry layout");
 
+// Block-major parameters of an input on the trace path PATH_BLOCKS, formed by
+// the plan kernel once per input; the evaluator reloads them with scalar loads
+// where it uses them.  Divisors come as multiply-shift pairs (m, s).
+struct dblk {
+  uint32_t L[6];        // gx gy gz bx by bz
+  uint32_t mode, bs, gxy, bxy, nsb, ngroups, spb, ne;
+  uint32_t any_dead, w, Lsum, n_acc;
+  uint32_t m_gx, s_gx, m_gxy, s_gxy, m_bx, s_bx, m_bxy, s_bxy, m_spb, s_spb, pad[4];
+  int64_t k[6];         // coefficients of the one class: tid.xyz, bid.xyz
+  uint64_t d1, dy, dz;  // block-part steps: next x, x wrap, x and y wrap
+  uint64_t rec;         // the input's records
+};
+static_assert(sizeof(dblk) % 16 == 0, "block-major parameters alignment");
+
 struct dtrace_head {
   uint32_t n_entries;
   uint32_t n_classes;
@@ -119,6 +133,7 @@ struct dtrace_head {
   uint32_t any_dead;    // some entry names a NULL or FREED slot
   uint32_t cap8;        // entry capacity rounded up to a multiple of 8
   uint32_t pad;
+  dblk blk;             // set when the input takes the block-major path
 };
 static_assert(sizeof(dtrace_head) % 16 == 0, "trace head alignment");
 // Followed by three arrays of cap8 entries each:
