@@ -62,6 +62,12 @@ struct GenLds {
   unsigned long long xstart[TILE], xstep[TILE];  // loop start and step of the tile's threads (gather pass)
   uint16_t own[PIECE_LDS];            // owner thread of each iteration of the current piece
   uint16_t omax[TILE / 64];           // owner-map scan: per-wavefront maxima
+  // gather pass: the tile's counter offset (start - prefix, equal for all
+  // owners of a contiguous tile) and the violations of the current input's
+  // gather entries, merged here and flushed per input
+  unsigned long long xdmin, xdmax;
+  unsigned long long vfk[MAX_GENT], vcnt[MAX_GENT];
+  uint32_t vkinds[MAX_GENT];
 };
 
 // Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
@@ -717,78 +723,6 @@ __device__ __forceinline__ uint32_t kind_bound(uint32_t dead, uint64_t bound, in
   return (uint64_t)idx >= bound ? CKC_KIND_OVER : 0u;
 }
 
-// Entries kept in registers by the piece evaluator.
-constexpr uint32_t GREG = 4;
-
-// Evaluates the iterations [it0, it1) of a piece of a gather body with at most
-// GREG entries: the entries are read once into (uniform) registers; per chunk
-// of TILE iterations a lane forms its counter from its owner's start and step
-// and evaluates every entry.  The loaded values live in R rows 1..GREG.
-__device__ __forceinline__ void gather_piece(GenLds& S, uint64_t* R, const Ctx& C, Lane& ln, uint64_t& sat,
-                                             uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
-                                             const uint32_t* L6, uint32_t site_iter, uint32_t ctr_w) {
-  const uint32_t tid = threadIdx.x;
-  const uint32_t n = S.gb.n;
-  uint64_t coef[GREG], off[GREG], bound[GREG];
-  const void* data[GREG];
-  uint32_t meta[GREG];  // w64 | var << 8 | dst << 16 | lg << 24 | dead << 28
-  uint32_t site[GREG];
-#pragma unroll
-  for (uint32_t e = 0; e < GREG; e++) {
-    const GEnt& E = S.gb.e[e < n ? e : 0];
-    site[e] = ufirst(E.site);
-    coef[e] = ufirst64((uint64_t)E.coef);
-    off[e] = ufirst64((uint64_t)E.off);
-    bound[e] = ufirst64(E.bound);
-    data[e] = (const void*)ufirst64((uint64_t)E.data);
-    meta[e] = ufirst((E.w == 64 ? 1u : 0u) | ((uint32_t)E.var << 8) | ((uint32_t)E.dst << 16) |
-                     ((uint32_t)E.lg << 24) | ((uint32_t)E.dead << 28));
-  }
-  const uint32_t faults = S.gb.faults;
-  for (uint64_t base = it0; base < it1; base += TILE) {
-    const uint64_t g = base + tid;
-    const bool act = g < it1;
-    const uint32_t o = act ? (uint32_t)S.own[g - it0] : 0u;
-    const uint64_t l = lane0 + o;
-    uint64_t gtid = l;
-    if (mode != CKC_FULL) {
-      Thr T;
-      decode_lane(mode, L6, l, T);
-      gtid = T.gtid;
-    }
-    const uint64_t k = act ? g - S.pref[o] : 0;
-    const uint64_t am = __ballot(act);
-    count_site(S, C, sat, site_iter, am);
-    R[tid] = narrow(S.xstart[o] + k * S.xstep[o], ctr_w);
-    const uint64_t key = (gtid << C.Lsum) | (k << C.L2);
-#pragma unroll
-    for (uint32_t e = 0; e < GREG; e++) {
-      if (e >= n) break;
-      const uint32_t m = meta[e], var = (m >> 8) & 0xFFu, dst = (m >> 16) & 0xFFu;
-      uint64_t v = off[e];
-      if (var != 0xFF) {
-        const uint64_t x = R[var * TILE + tid];
-        v = coef[e] == 1 ? v + x : v + coef[e] * x;
-      }
-      const int64_t idx = (m & 1u) ? (int64_t)v : (int64_t)(int32_t)(uint32_t)v;
-      const uint32_t kd = act ? kind_bound(m >> 28, bound[e], idx) : 0u;
-      count_site(S, C, sat, site[e], am);
-      if (__ballot(kd != 0)) merge_violation(C.rec + S.gb.e[e].acc, kd, key);
-      if (dst) {
-        uint64_t x = 0;
-        if (act && kd == 0)
-          x = ((m >> 24) & 3u) == 2 ? (uint64_t)(int64_t)((const int32_t*)data[e])[idx]
-                                    : (uint64_t)((const int64_t*)data[e])[idx];
-        R[dst * TILE + tid] = x;
-      }
-    }
-    if (act) {
-      ln.acc += n;
-      ln.faults += faults;
-    }
-  }
-}
-
 // Owner of iteration g in a tile: the largest o with pref[o] <= g.
 __device__ __forceinline__ uint32_t owner_of(const GenLds& S, uint64_t g) {
   uint32_t l2 = 0, h2 = TILE - 1;
@@ -798,6 +732,268 @@ __device__ __forceinline__ uint32_t owner_of(const GenLds& S, uint64_t g) {
     else h2 = m - 1;
   }
   return l2;
+}
+
+// Adds c visits of site s for the wavefront (lane 0 updates the counter); the
+// wavefront is converged.
+__device__ __forceinline__ void count_site_n(GenLds& S, const Ctx& C, uint64_t& sat, uint32_t s, uint32_t c) {
+  if (s == NOSITE || c == 0) return;
+  if (s < 64 && ((sat >> s) & 1u)) return;
+  if (s < MAX_SITES_LDS) {
+    uint32_t old = 0;
+    if (lane_id() == 0) old = atomicAdd(&S.sites[s], c);
+    old = __builtin_amdgcn_readlane(old, 0);
+    if (s < 64 && old + c >= 255u) sat |= 1ull << s;
+  } else if (lane_id() == 0 && C.gcnt[s] < 255u) {
+    atomicAdd(&C.gcnt[s], c);
+  }
+}
+
+// Entries of a gather body evaluated by the piece evaluator (larger bodies go
+// through run_gather).
+constexpr uint32_t GREG = 4;
+
+// Evaluates the iterations [it0, it1) of a piece of a gather body with at most
+// GREG entries.  A lane takes U iterations at a time (one per chunk of TILE),
+// forms each counter from its owner's start and step, and evaluates each entry
+// for all U before the next entry, so that the U loads of an entry are in
+// flight together.  The loaded value of LOAD number d (1-based) for chunk q
+// lives in R row (d-1)*U + q, so the body's loads need U rows each.  A
+// violation (rare) is recorded by recomputing that chunk's key and index.
+template <uint32_t U>
+__device__ __forceinline__ void gather_piece(GenLds& S, uint64_t* R, const Ctx& C, Lane& ln, uint64_t& sat,
+                                             uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
+                                             const uint32_t* L6, uint32_t site_iter, uint32_t ctr_w) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = S.gb.n;
+  const uint32_t faults = S.gb.faults;
+  for (uint64_t base = it0; base < it1; base += (uint64_t)TILE * U) {
+    uint64_t ctr[U];
+    bool act[U];
+    uint32_t nact = 0, mine = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < U; q++) {
+      const uint64_t g = base + q * TILE + tid;
+      act[q] = g < it1;
+      const uint32_t o = act[q] ? (uint32_t)S.own[g - it0] : 0u;
+      const uint64_t k = act[q] ? g - S.pref[o] : 0;
+      ctr[q] = narrow(S.xstart[o] + k * S.xstep[o], ctr_w);
+      nact += (uint32_t)__popcll(__ballot(act[q]));
+      mine += act[q] ? 1u : 0u;
+    }
+    count_site_n(S, C, sat, site_iter, nact);
+    for (uint32_t e = 0; e < n; e++) {
+      const GEnt& E = S.gb.e[e];
+      const uint32_t var = ufirst(E.var), dst = ufirst(E.dst), lg = ufirst(E.lg), w64 = ufirst(E.w) == 64;
+      const uint32_t dead = ufirst(E.dead);
+      const uint64_t coef = ufirst64((uint64_t)E.coef), off = ufirst64((uint64_t)E.off);
+      const uint64_t bound = ufirst64(E.bound);
+      const void* data = (const void*)ufirst64((uint64_t)E.data);
+      uint32_t vio = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < U; q++) {
+        uint64_t v = off;
+        if (var != 0xFF) {
+          const uint64_t x = var == 0 ? ctr[q] : R[((var - 1) * U + q) * TILE + tid];
+          v = coef == 1 ? v + x : v + coef * x;
+        }
+        const int64_t idx = w64 ? (int64_t)v : (int64_t)(int32_t)(uint32_t)v;
+        const uint32_t kd = act[q] ? kind_bound(dead, bound, idx) : 0u;
+        if (__ballot(kd != 0)) vio |= 1u << q;
+        if (dst) {
+          uint64_t x = 0;
+          if (act[q] && kd == 0)
+            x = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)data)[idx] : (uint64_t)((const int64_t*)data)[idx];
+          R[((dst - 1) * U + q) * TILE + tid] = x;
+        }
+      }
+      count_site_n(S, C, sat, ufirst(E.site), nact);
+      for (uint32_t q = 0; q < U; q++) {
+        if (!((vio >> q) & 1u)) continue;
+        const uint64_t g = base + q * TILE + tid;
+        const bool a = g < it1;
+        const uint32_t o = a ? (uint32_t)S.own[g - it0] : 0u;
+        const uint64_t k = a ? g - S.pref[o] : 0;
+        const uint64_t l = lane0 + o;
+        uint64_t gtid = l;
+        if (mode != CKC_FULL) {
+          Thr T;
+          decode_lane(mode, L6, l, T);
+          gtid = T.gtid;
+        }
+        uint64_t v = off;
+        if (var != 0xFF) {
+          const uint64_t x = var == 0 ? narrow(S.xstart[o] + k * S.xstep[o], ctr_w) : R[((var - 1) * U + q) * TILE + tid];
+          v = coef == 1 ? v + x : v + coef * x;
+        }
+        const int64_t idx = w64 ? (int64_t)v : (int64_t)(int32_t)(uint32_t)v;
+        const uint32_t kd = a ? kind_bound(dead, bound, idx) : 0u;
+        merge_violation(C.rec + ufirst(E.acc), kd, (gtid << C.Lsum) | (k << C.L2));
+      }
+    }
+    ln.acc += (uint64_t)n * mine;
+    ln.faults += (uint64_t)faults * mine;
+  }
+}
+
+// Merges this wavefront's violations of gather entry e into the workgroup's
+// per-entry record in LDS.
+__device__ __forceinline__ void merge_vio_lds(GenLds& S, uint32_t e, uint32_t kd, uint64_t key) {
+  const uint64_t mask = __ballot(kd != 0);
+  if (mask == 0) return;
+  const uint64_t k = wave_min64(kd ? key : ~0ull);
+  uint32_t kinds = 0;
+  if (__ballot(kd & CKC_KIND_OVER)) kinds |= CKC_KIND_OVER;
+  if (__ballot(kd & CKC_KIND_UNDER)) kinds |= CKC_KIND_UNDER;
+  if (__ballot(kd & CKC_KIND_FREED)) kinds |= CKC_KIND_FREED;
+  if (__ballot(kd & CKC_KIND_NULL)) kinds |= CKC_KIND_NULL;
+  const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+  if (lane_id() == leader) {
+    atomicMin(&S.vfk[e], (unsigned long long)k);
+    atomicAdd(&S.vcnt[e], (unsigned long long)__popcll(mask));
+    atomicOr(&S.vkinds[e], kinds);
+  }
+}
+
+// Flushes the per-entry violation records of the current gather body into the
+// input's records (workgroup-converged; S.gb still holds that body).
+__device__ __forceinline__ void flush_vio_lds(GenLds& S, ckc_record* rec) {
+  const uint32_t e = threadIdx.x;
+  if (e < MAX_GENT && e < S.gb.n && S.vcnt[e]) {
+    ckc_record* r = rec + S.gb.e[e].acc;
+    atomicMin((unsigned long long*)&r->first_key, S.vfk[e]);
+    atomicAdd((unsigned long long*)&r->count, S.vcnt[e]);
+    atomicOr(&r->kinds, S.vkinds[e]);
+  }
+  if (e < MAX_GENT) {
+    S.vfk[e] = ~0ull;
+    S.vcnt[e] = 0;
+    S.vkinds[e] = 0;
+  }
+}
+
+// Gather bodies of at most GREG entries whose entries and counter are all of
+// width 32, with at most two loads, over a contiguous tile (every owner's
+// counter is start + k with start - prefix the same d for all owners): the
+// counter of iteration g is d + g, so no owner map is needed, and all index
+// arithmetic is 32-bit (the low 32 bits of an index depend only on the low 32
+// bits of its operands).  A lane takes U iterations at a time, one per chunk
+// of TILE, and evaluates each entry for all U before the next one, so that
+// the U loads of an entry are in flight together.  The body is straight-line,
+// so every site of it is visited once per iteration: the visits are counted
+// once at the end.  A violating chunk of an entry keeps its index values in
+// R32 (row q of TILE lanes, 32 bits) and, right after the entry (rare), finds
+// each lane's owner by binary search and merges into the workgroup's
+// per-entry records.
+typedef const __attribute__((address_space(1))) int32_t g_i32;
+typedef const __attribute__((address_space(1))) int64_t g_i64;
+
+// One entry of the contiguous form over U chunks: XV selects the index
+// variable (-1 none, 0 the counter, 1 or 2 the first or second loaded value),
+// DV the loaded value the entry defines (0 none).  Loads land directly in
+// their variable, so the U loads are in flight together.  Returns the chunks
+// with a violating lane; their index values go to R32.
+template <uint32_t U, int XV, int DV>
+__device__ __forceinline__ uint32_t c32_entry(const uint32_t* ctr, uint32_t* l1, uint32_t* l2, const bool* act,
+                                              uint32_t off, uint32_t coef, bool c1, uint32_t bnd, bool dead,
+                                              bool lg2, const void* data, uint32_t* R32, uint32_t tid) {
+  uint32_t vio = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < U; q++) {
+    uint32_t vv = off;
+    if (XV >= 0) {
+      const uint32_t x = XV == 0 ? ctr[q] : XV == 1 ? l1[q] : l2[q];
+      if (c1) vv += x;
+      else vv += coef * x;
+    }
+    const bool bad = act[q] && (dead || vv >= bnd);
+    if (__ballot(bad)) {
+      vio |= 1u << q;
+      R32[q * TILE + tid] = vv;
+    }
+    if (DV != 0) {
+      uint32_t val = 0;
+      if (act[q] && !bad) {
+        if (lg2) val = (uint32_t)((g_i32*)data)[vv];
+        else val = (uint32_t)((g_i64*)data)[vv];
+      }
+      if (DV == 1) l1[q] = val;
+      else l2[q] = val;
+    }
+  }
+  return vio;
+}
+
+template <uint32_t U>
+__device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
+                                           uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
+                                           const uint32_t* L6, uint32_t site_iter, uint32_t d32) {
+  static_assert(U <= 16, "violation rows");
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = S.gb.n, faults = S.gb.faults;
+  uint64_t visits = 0;
+  uint32_t mine = 0;
+  for (uint64_t base = it0; base < it1; base += (uint64_t)TILE * U) {
+    uint32_t ctr[U], l1[U], l2[U];
+    bool act[U];
+#pragma unroll
+    for (uint32_t q = 0; q < U; q++) {
+      const uint64_t g = base + q * TILE + tid;
+      act[q] = g < it1;
+      ctr[q] = d32 + (uint32_t)g;
+      l1[q] = 0;
+      l2[q] = 0;
+      mine += act[q] ? 1u : 0u;
+      visits += (uint64_t)__popcll(__ballot(act[q]));  // this wavefront's iterations
+    }
+    for (uint32_t e = 0; e < n; e++) {
+      const GEnt& E = S.gb.e[e];
+      // control fields uniform (scalar), values per lane from LDS
+      const uint32_t meta = ufirst((uint32_t)E.var | ((uint32_t)E.dst << 8) | ((uint32_t)E.lg << 16) |
+                                   ((uint32_t)(E.coef == 1) << 24) | ((uint32_t)(E.dead != 0) << 25));
+      const uint32_t var = meta & 0xFFu, dst = (meta >> 8) & 0xFFu;
+      const bool lg2 = ((meta >> 16) & 0xFFu) == 2, c1 = (meta >> 24) & 1u, dead = (meta >> 25) & 1u;
+      const uint32_t off = (uint32_t)E.off, coef = (uint32_t)E.coef;
+      const uint64_t b64 = E.bound;
+      const uint32_t bnd = b64 > 0x80000000ull ? 0x80000000u : (uint32_t)b64;
+      const void* data = (const void*)ufirst64((uint64_t)E.data);
+      uint32_t vio;
+#define C32E(XV, DV) vio = c32_entry<U, XV, DV>(ctr, l1, l2, act, off, coef, c1, bnd, dead, lg2, data, R32, tid)
+#define C32D(XV)         \
+  if (dst == 0) C32E(XV, 0); \
+  else if (dst == 1) C32E(XV, 1); \
+  else C32E(XV, 2)
+      if (var == 0xFF) { C32D(-1); }
+      else if (var == 0) { C32D(0); }
+      else if (var == 1) { C32D(1); }
+      else { C32D(2); }
+#undef C32D
+#undef C32E
+      for (uint32_t bits = vio; bits; bits &= bits - 1) {
+        const uint32_t q = (uint32_t)__ffs((int)bits) - 1;
+        const uint32_t vv = R32[q * TILE + tid];
+        const uint64_t g = base + q * TILE + tid;
+        const bool bad = g < it1 && (dead || vv >= bnd);
+        const uint32_t kd = !bad ? 0u : dead ? ufirst(E.dead) : ((int32_t)vv < 0 ? CKC_KIND_UNDER : CKC_KIND_OVER);
+        const uint32_t o = owner_of(S, g < it1 ? g : it0);
+        const uint64_t k = g < it1 ? g - S.pref[o] : 0;
+        const uint64_t l = lane0 + o;
+        uint64_t gtid = l;
+        if (mode != CKC_FULL) {
+          Thr T;
+          decode_lane(mode, L6, l, T);
+          gtid = T.gtid;
+        }
+        merge_vio_lds(S, e, kd, (gtid << C.Lsum) | (k << C.L2));
+      }
+    }
+  }
+  // visits of the counter's site and of every entry's site
+  const uint32_t vc = (uint32_t)(visits < 0xFFFFFFFFull ? visits : 0xFFFFFFFFull);
+  count_site_n(S, C, sat, site_iter, vc);
+  for (uint32_t e = 0; e < n; e++) count_site_n(S, C, sat, ufirst(S.gb.e[e].site), vc);
+  ln.acc += (uint64_t)n * mine;
+  ln.faults += (uint64_t)faults * mine;
 }
 
 // Owner map of the iterations [it0, it1) of a piece: S.own[g - it0] is the
@@ -970,7 +1166,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
 // in LDS with the tile's prefix, so an iteration costs one memory round trip
 // per dependent load of the body.
 template <uint32_t SK>
-__global__ void __launch_bounds__(TILE, 6) eval_gather_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
   __shared__ unsigned long long item_slot;
@@ -984,24 +1180,34 @@ __global__ void __launch_bounds__(TILE, 6) eval_gather_kernel(KArgs a) {
   if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
-  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0, cur_mode = 0;
+  if (tid < MAX_GENT) {
+    S.vfk[tid] = ~0ull;
+    S.vcnt[tid] = 0;
+    S.vkinds[tid] = 0;
+  }
+  uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0, fast = 0, cur_mode = 0, cont = 0;
   uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
-  uint64_t cur_xt = ~0ull, sat = 0, cur_xt_hint = ~0ull;
+  uint64_t cur_xt = ~0ull, sat = 0, xd = 0;
+  uint64_t pb = 0, pe = 0;  // pieces of the current tile
   Lane ln;
   lane_zero_totals(ln);
   for (;;) {
     __syncthreads();
     const uint64_t p = sched_next(sc, &a.js->next_piece[1], &item_slot);
     if (p == ~0ull) break;
-    uint64_t xt = cur_xt_hint;
-    uint32_t i;
-    piece_tile(a, 1, p, xt, i);
-    cur_xt_hint = xt;
+    uint64_t xt = cur_xt;
+    uint32_t i = cur;
+    if (cur_xt == ~0ull || p < pb || p >= pe) {
+      piece_tile(a, 1, p, xt, i);
+      pb = a.xpg[xt];
+      pe = xt + 1 < a.n_xtiles ? a.xpg[xt + 1] : ~0ull;
+    }
     c_input& in = ((c_input*)a.inputs)[i];
     if (i != cur) {
       if (cur != 0xFFFFFFFFu) {
         add_lane_totals(S, ln);
         flush_input(S, a, cur, cur_sites);
+        flush_vio_lds(S, a.recs + ((c_input*)a.inputs)[cur].rec_base);
       }
       sat = 0;
       cur = i;
@@ -1017,11 +1223,26 @@ __global__ void __launch_bounds__(TILE, 6) eval_gather_kernel(KArgs a) {
       S.pref[tid] = xs[lane0 + tid];
       S.xstart[tid] = xs[xn + lane0 + tid];
       S.xstep[tid] = xs[2 * xn + lane0 + tid];
-      if (tid == 0) S.pref[TILE] = a.xtot[xt];
+      if (tid == 0) {
+        S.pref[TILE] = a.xtot[xt];
+        S.xdmin = ~0ull;
+        S.xdmax = 0;
+      }
       cur_xt = xt;
       __syncthreads();
+      // contiguous tile: every owner with iterations has step 1 and the same
+      // start - prefix
+      const bool has = S.pref[tid + 1] != S.pref[tid];
+      if (has) {
+        const unsigned long long d = S.xstart[tid] - S.pref[tid];
+        atomicMin(&S.xdmin, d);
+        atomicMax(&S.xdmax, d);
+      }
+      const int nonunit = __syncthreads_or(has && S.xstep[tid] != 1);
+      cont = !nonunit && S.xdmin == S.xdmax;
+      xd = S.xdmin;
     }
-    const uint64_t it0 = (p - a.xpg[xt]) * PIECE;
+    const uint64_t it0 = (p - pb) * PIECE;
     const uint64_t tot = S.pref[TILE];
     const uint64_t it1 = it0 + PIECE < tot ? it0 + PIECE : tot;
     c_dprog* P = (c_dprog*)in.prog;
@@ -1040,11 +1261,31 @@ __global__ void __launch_bounds__(TILE, 6) eval_gather_kernel(KArgs a) {
       __syncthreads();
       built = 1;
       ok = S.gb.ok;
+      // all-32-bit bodies with at most two loads take the contiguous form
+      fast = S.gb.n >= 1 && S.gb.n <= GREG && Lx.w == 32;
+      for (uint32_t e = 0; e < S.gb.n && e < GREG; e++) {
+        const GEnt& E = S.gb.e[e];
+        if (E.w != 32 || (E.var != 0xFF && E.var > 2) || E.dst > 2) fast = 0;
+      }
+      fast = ufirst(fast);
     }
     if (!ok) continue;  // cannot happen for a body the loader accepted
+    if (fast && cont) {
+      // the rest of this tile's pieces in the workgroup's current range go
+      // with this one (no owner map bounds the length)
+      const uint64_t lim = pe < sc.end ? pe : sc.end;
+      uint64_t iend = it1;
+      if (lim > p + 1) {
+        const uint64_t e1 = (lim - pb) * PIECE;
+        iend = e1 < tot ? e1 : tot;
+        sc.cur = lim;
+      }
+      gather_c32<8>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd);
+      continue;
+    }
     build_owner_map(S, it0, it1);
     if (S.gb.n <= GREG) {
-      gather_piece(S, R, C, ln, sat, it0, it1, lane0, cur_mode, cur_L, Lx.s0, Lx.w);
+      gather_piece<1>(S, R, C, ln, sat, it0, it1, lane0, cur_mode, cur_L, Lx.s0, Lx.w);
       continue;
     }
     for (uint64_t base = it0; base < it1; base += TILE) {
@@ -1069,6 +1310,7 @@ __global__ void __launch_bounds__(TILE, 6) eval_gather_kernel(KArgs a) {
   if (cur != 0xFFFFFFFFu) {
     add_lane_totals(S, ln);
     flush_input(S, a, cur, cur_sites);
+    flush_vio_lds(S, a.recs + ((c_input*)a.inputs)[cur].rec_base);
   }
 }
 

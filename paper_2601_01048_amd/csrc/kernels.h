@@ -51,7 +51,8 @@ struct EvalGrid {
   uint32_t n_wg[3];
   uint32_t sched[3];
   uint32_t chunk[3];
-  uint32_t n_wg_body;  // workgroups of the body passes of expanded loops
+  uint32_t n_wg_body;   // workgroups of the body passes of expanded loops
+  uint32_t sched_body;  // schedule of the body passes
 };
 
 hipError_t launch_plan(const KArgs& a, hipStream_t s);

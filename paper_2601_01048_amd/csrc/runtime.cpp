@@ -450,6 +450,9 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     eg.chunk[p] = O.chunk ? O.chunk : (p == PATH_GENERIC && gen_tiles >= 16ull * eg.n_wg[p] ? 4u : 1u);
   }
   eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
+  // body passes: pieces are near-equal work, and a workgroup walking one
+  // contiguous range of them finds each piece's tile by a step from the last
+  eg.sched_body = O.schedule ? O.schedule : CKC_SCHED_BLOCKED;
   J.graph = O.use_graph != 0;
   e = hipEventRecord(J.ev[0], J.stream);
   if (J.graph) {
