@@ -1189,6 +1189,9 @@ __global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
   uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
   uint64_t cur_xt = ~0ull, sat = 0, xd = 0;
   uint64_t pb = 0, pe = 0;  // pieces of the current tile
+  // the next tile of the same input, loaded while the current one runs:
+  // its index, this lane's prefix, start and step, its total and piece end
+  uint64_t nx = ~0ull, nx_pref = 0, nx_start = 0, nx_step = 0, nx_tot = 0, nx_pe = 0;
   Lane ln;
   lane_zero_totals(ln);
   for (;;) {
@@ -1198,9 +1201,16 @@ __global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
     uint64_t xt = cur_xt;
     uint32_t i = cur;
     if (cur_xt == ~0ull || p < pb || p >= pe) {
-      piece_tile(a, 1, p, xt, i);
-      pb = a.xpg[xt];
-      pe = xt + 1 < a.n_xtiles ? a.xpg[xt + 1] : ~0ull;
+      const uint64_t npe = ufirst64(nx_pe);
+      if (nx != ~0ull && p >= pe && p < npe) {
+        xt = nx;
+        pb = pe;
+        pe = npe;
+      } else {
+        piece_tile(a, 1, p, xt, i);
+        pb = a.xpg[xt];
+        pe = xt + 1 < a.n_xtiles ? a.xpg[xt + 1] : ~0ull;
+      }
     }
     c_input& in = ((c_input*)a.inputs)[i];
     if (i != cur) {
@@ -1220,15 +1230,32 @@ __global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
     const uint64_t* xs = (const uint64_t*)in.xstate;
     const uint64_t xn = in.xn;
     if (xt != cur_xt) {
-      S.pref[tid] = xs[lane0 + tid];
-      S.xstart[tid] = xs[xn + lane0 + tid];
-      S.xstep[tid] = xs[2 * xn + lane0 + tid];
+      if (xt == nx) {
+        S.pref[tid] = nx_pref;
+        S.xstart[tid] = nx_start;
+        S.xstep[tid] = nx_step;
+        if (tid == 0) S.pref[TILE] = nx_tot;
+      } else {
+        S.pref[tid] = xs[lane0 + tid];
+        S.xstart[tid] = xs[xn + lane0 + tid];
+        S.xstep[tid] = xs[2 * xn + lane0 + tid];
+        if (tid == 0) S.pref[TILE] = a.xtot[xt];
+      }
       if (tid == 0) {
-        S.pref[TILE] = a.xtot[xt];
         S.xdmin = ~0ull;
         S.xdmax = 0;
       }
       cur_xt = xt;
+      if (xt + 1 < in.xt_begin + in.n_xt) {
+        nx = xt + 1;
+        nx_pref = xs[lane0 + TILE + tid];
+        nx_start = xs[xn + lane0 + TILE + tid];
+        nx_step = xs[2 * xn + lane0 + TILE + tid];
+        nx_tot = a.xtot[nx];
+        nx_pe = nx + 1 < a.n_xtiles ? a.xpg[nx + 1] : ~0ull;
+      } else {
+        nx = ~0ull;
+      }
       __syncthreads();
       // contiguous tile: every owner with iterations has step 1 and the same
       // start - prefix
