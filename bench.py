@@ -188,7 +188,7 @@ def bench_batched(args):
 
         def step():
             j = ctx.check(prep, opts=best)
-            ctx.read_device(j, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr())
+            ctx.read_device(j, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr(), enqueue=True)
 
         for _ in range(args.warmup):
             step()

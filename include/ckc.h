@@ -207,14 +207,20 @@ typedef struct ckc_input_status {
   uint32_t flags, pad;
 } ckc_input_status;          /* 40 bytes */
 
-enum ckc_read_flags { CKC_WAIT = 1, CKC_DST_DEVICE = 2 };
+enum ckc_read_flags { CKC_WAIT = 1, CKC_DST_DEVICE = 2, CKC_ENQUEUE = 4 };
 
 /* Copies a job's results out and releases the job.  Inputs are numbered in
  * descriptor order.  recs: [sum over inputs of n_accesses]; maps: [inputs][65536]
  * or NULL (requires CKC_DENSE_MAP); st: [inputs] or NULL.  With CKC_DST_DEVICE
  * the three pointers are device pointers (device-to-device copies on the
  * job's stream).  Without CKC_WAIT returns CKC_NOT_READY while the job runs.
- * Errors: CKC_E_INVALID (unknown job), CKC_E_HIP. */
+ * CKC_ENQUEUE (with CKC_DST_DEVICE only) queues the copies behind the job on
+ * its stream and returns at once, CKC_WAIT or not: the destination is valid
+ * once that stream (or the device) has been synchronized, and the job's
+ * buffers are reused by later jobs only after the copies have completed.
+ * The job's programs and tables count as in use until then.
+ * Errors: CKC_E_INVALID (unknown job, CKC_ENQUEUE without CKC_DST_DEVICE),
+ * CKC_E_HIP. */
 int ckc_read_results(ckc_ctx ctx, uint64_t job, ckc_record* recs, uint8_t* maps,
                      ckc_input_status* st, uint32_t flags);
 

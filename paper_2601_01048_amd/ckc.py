@@ -20,7 +20,7 @@ FULL, REP_CORNERS, REP_BOUNDARY = 0, 1, 2
 SCHED_DEFAULT, SCHED_BLOCKED, SCHED_CYCLIC, SCHED_DYNAMIC, SCHED_LPT = 0, 1, 2, 3, 4
 SCHED_NAMES = {0: "default", 1: "blocked", 2: "cyclic", 3: "dynamic", 4: "lpt"}
 DENSE_MAP = 2
-WAIT, DST_DEVICE = 1, 2
+WAIT, DST_DEVICE, ENQUEUE = 1, 2, 4
 CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32, GATHER=64)
 
 RECORD_DTYPE = np.dtype([("first_key", "<u8"), ("index", "<i8"), ("count", "<u8"),
@@ -269,8 +269,12 @@ class Context:
             return None
         return recs, mp, st
 
-    def read_device(self, job: int, recs_ptr: int, maps_ptr: int | None, st_ptr: int | None):
-        _check(lib().ckc_read_results(self.h, job, recs_ptr, maps_ptr, st_ptr, WAIT | DST_DEVICE))
+    def read_device(self, job: int, recs_ptr: int, maps_ptr: int | None, st_ptr: int | None,
+                    enqueue: bool = False):
+        """Device-to-device readback; with enqueue the copies are only queued
+        behind the job (synchronize the device before using the results)."""
+        flags = WAIT | DST_DEVICE | (ENQUEUE if enqueue else 0)
+        _check(lib().ckc_read_results(self.h, job, recs_ptr, maps_ptr, st_ptr, flags))
 
 
 class DeviceWorkload:

@@ -64,6 +64,7 @@ __device__ __forceinline__ uint64_t trip_count(int64_t s, int64_t e, int64_t st)
     if (!(s < e)) return 0;
     if (st == 0) return ~0ull;
     uint64_t span = (uint64_t)e - (uint64_t)s;
+    if (st == 1) return span;  // the common unit step: no 64-bit division
     return span / (uint64_t)st + (span % (uint64_t)st != 0);
   }
   if (!(s > e)) return 0;

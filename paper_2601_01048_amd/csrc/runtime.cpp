@@ -75,6 +75,25 @@ void free_job(ckc_ctx c, Job& J) {
   }
 }
 
+// Releases the retiring jobs whose copies have completed (all of them, waiting,
+// with wait).
+void reap(ckc_ctx c, bool wait) {
+  auto& R = c->retiring;
+  size_t k = 0;
+  for (size_t q = 0; q < R.size(); q++) {
+    hipEvent_t ev = R[q].first;
+    const bool done = wait ? (hipEventSynchronize(ev), true) : hipEventQuery(ev) != hipErrorNotReady;
+    if (done) {
+      hipEventDestroy(ev);
+      free_job(c, R[q].second);
+    } else {
+      if (k != q) R[k] = std::move(R[q]);
+      k++;
+    }
+  }
+  R.resize(k);
+}
+
 template <class T>
 int dalloc(ckc_ctx c, Job& J, T** out, size_t count) {
   size_t bytes = std::max<size_t>(count * sizeof(T), 256);
@@ -88,7 +107,8 @@ int dalloc(ckc_ctx c, Job& J, T** out, size_t count) {
     c->pool.erase(it);
   } else {
     hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {  // release pooled buffers and retry once
+    if (e != hipSuccess) {  // release retiring jobs and pooled buffers, retry once
+      reap(c, true);
       for (auto& kv : c->pool) hipFree(kv.second);
       c->pool.clear();
       c->pool_bytes = 0;
@@ -211,6 +231,7 @@ int ckc_init(int hip_device, ckc_ctx* out) {
 void ckc_shutdown(ckc_ctx c) {
   if (!c) return;
   hipSetDevice(c->dev);
+  reap(c, true);
   for (auto& kv : c->jobs) {
     if (kv.second.stream) hipStreamSynchronize(kv.second.stream);
     free_job(c, kv.second);
@@ -261,6 +282,7 @@ int ckc_unload_program(ckc_ctx c, uint32_t prog_id) {
   if (!c) return fail(CKC_E_INVALID, "NULL context");
   auto it = c->progs.find(prog_id);
   if (it == c->progs.end()) return fail(CKC_E_INVALID, "unknown program id");
+  if (it->second.busy) reap(c, true);
   if (it->second.busy) return fail(CKC_E_BUSY, "program used by an unread job");
   set_device(c);
   hipFree(it->second.dblob);
@@ -294,6 +316,7 @@ int ckc_free_alloc_table(ckc_ctx c, uint32_t table_id) {
   if (!c) return fail(CKC_E_INVALID, "NULL context");
   auto it = c->tables.find(table_id);
   if (it == c->tables.end()) return fail(CKC_E_INVALID, "unknown table id");
+  if (it->second.busy) reap(c, true);
   if (it->second.busy) return fail(CKC_E_BUSY, "table used by an unread job");
   set_device(c);
   hipFree(it->second.dptr);
@@ -373,6 +396,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   if (n_inputs > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "too many inputs");
   int rc;
   if ((rc = set_device(c))) return rc;
+  reap(c, false);
   Job J;
   J.n_inputs = n_inputs;
   J.n_records = n_records;
@@ -537,11 +561,24 @@ int ckc_read_results(ckc_ctx c, uint64_t job, ckc_record* recs, uint8_t* maps, c
     if (q != hipSuccess) return fail(CKC_E_HIP, std::string("job: ") + hipGetErrorString(q));
   }
   if (maps && !J.dense) return fail(CKC_E_INVALID, "maps requested but the job was not run with CKC_DENSE_MAP");
+  const bool enq = (flags & CKC_ENQUEUE) != 0;
+  if (enq && !(flags & CKC_DST_DEVICE)) return fail(CKC_E_INVALID, "CKC_ENQUEUE needs CKC_DST_DEVICE");
   hipMemcpyKind kind = (flags & CKC_DST_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   hipError_t e = hipSuccess;
   if (recs) e = hipMemcpyAsync(recs, J.d_recs, sizeof(ckc_record) * J.n_records, kind, J.stream);
   if (e == hipSuccess && maps) e = hipMemcpyAsync(maps, J.d_maps, J.n_inputs * 65536, kind, J.stream);
   if (e == hipSuccess && st) e = hipMemcpyAsync(st, J.d_status, sizeof(ckc_input_status) * J.n_inputs, kind, J.stream);
+  if (enq && e == hipSuccess) {
+    hipEvent_t done = nullptr;
+    e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(done, J.stream);
+    if (e == hipSuccess) {
+      c->retiring.emplace_back(done, std::move(J));
+      c->jobs.erase(it);
+      return CKC_OK;
+    }
+    if (done) hipEventDestroy(done);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(J.stream);
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("readback: ") + hipGetErrorString(e));
   free_job(c, J);

@@ -63,6 +63,9 @@ struct ckc_ctx_s {
   // arguments hold the job's buffers, so a key is never shared by two
   // unread jobs)
   std::map<std::string, hipGraphExec_t> graphs;
+  // jobs read with CKC_ENQUEUE whose copies may still run: released (buffers
+  // back to the pool) once their event has completed
+  std::vector<std::pair<hipEvent_t, ckc::rt::Job>> retiring;
 };
 
 

@@ -79,6 +79,34 @@ def test_alone_equals_in_batch(ctx, mini):
         B.same(alone, full[int(i)], f"kernel {i} alone")
 
 
+def test_enqueued_readback_equals_waiting_readback(ctx, mini):
+    """Results read with CKC_ENQUEUE (copies queued behind the job, no host
+    wait) equal a waiting readback, also when later jobs reuse the pool while
+    earlier copies may still run."""
+    import torch
+    mb, db = mini
+    print("[case] enqueued readback, 3 jobs in flight", flush=True)
+    ref = run_batch(ctx, db)
+    n = mb.n_kernels
+    n_rec = sum(db.n_accesses(i) for i in range(n))
+    outs = []
+    for rep in range(3):
+        o = dict(recs=torch.zeros(n_rec * 32, dtype=torch.uint8, device="cuda"),
+                 maps=torch.zeros(n * 65536, dtype=torch.uint8, device="cuda"),
+                 st=torch.zeros(n * 40, dtype=torch.uint8, device="cuda"))
+        job = ctx.check(db.descs(), opts=ckc.launch_opts(use_graph=rep == 1))
+        ctx.read_device(job, o["recs"].data_ptr(), o["maps"].data_ptr(), o["st"].data_ptr(), enqueue=True)
+        outs.append(o)
+    torch.cuda.synchronize()
+    for rep, o in enumerate(outs):
+        recs = np.frombuffer(o["recs"].cpu().numpy().tobytes(), ckc.RECORD_DTYPE)
+        maps = o["maps"].cpu().numpy().reshape(n, 65536)
+        st = np.frombuffer(o["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
+        g = ckc.split_results(recs, maps, st, [db.n_accesses(i) for i in range(n)])
+        for i in range(n):
+            B.same(g[i], ref[i], f"kernel {i} enqueued rep {rep}")
+
+
 def test_graph_timing_and_elapsed(ctx, mini):
     mb, db = mini
     job = ctx.check(db.descs(), opts=ckc.launch_opts(use_graph=True))
