@@ -66,6 +66,8 @@ struct GenLds {
   // owners of a contiguous tile) and the violations of the current input's
   // gather entries, merged here and flushed per input
   unsigned long long xdmin, xdmax;
+  unsigned long long wemin[TILE / 64], wemax[TILE / 64];  // whole-thread pass: tile contiguity per wavefront
+  uint32_t wflag[TILE / 64];
   unsigned long long vfk[MAX_GENT], vcnt[MAX_GENT];
   uint32_t vkinds[MAX_GENT];
 };
@@ -104,7 +106,7 @@ struct Ctx {
   // live-ins; xn entries each), the tile's first lane and expanded tile
   uint64_t* xs;
   uint64_t xn, lane0, xt;
-  unsigned long long *xtot, *xpb, *xpg;
+  unsigned long long *xtot, *xpb, *xpg, *xd;
   uint32_t* xin;
   uint32_t input;
   // fix-up target
@@ -255,23 +257,51 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
         if (MODE == M_MAIN && (fl & DI_EXPAND) && C.xs != nullptr) {
           // every wavefront of the workgroup arrives here exactly once per tile:
           // prefix of the trip counts over the tile, thread state to memory
-          const uint32_t tid = threadIdx.x;
+          const uint32_t tid = threadIdx.x, wv = tid / 64;
           const uint64_t cnt = act ? rn : 0;
           uint64_t incl = cnt;
           for (int o = 1; o < 64; o <<= 1) {
             const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
             if ((int)lane_id() >= o) incl += u;
           }
-          if (lane_id() == 63) S.wsum[tid / 64] = incl;
+          // contiguous tile: every thread with iterations has step 1 and the
+          // same start - prefix d (iteration g of the tile has counter d + g);
+          // per wavefront, start minus the prefix within the wavefront
+          const uint64_t e = (uint64_t)s0 - (incl - cnt);
+          const uint64_t emin = wave_min64(cnt ? e : ~0ull), emax = ~wave_min64(cnt ? ~e : ~0ull);
+          const uint64_t has = __ballot(cnt != 0), nonunit = __ballot(cnt != 0 && (uint64_t)stp != 1);
+          if (lane_id() == 63) {
+            S.wsum[wv] = incl;
+            S.wemin[wv] = emin;
+            S.wemax[wv] = emax;
+            S.wflag[wv] = (has ? 1u : 0u) | (nonunit ? 2u : 0u);
+          }
           __syncthreads();
           uint64_t wpre = 0;
-          for (uint32_t q = 0; q < tid / 64; q++) wpre += S.wsum[q];
+          for (uint32_t q = 0; q < wv; q++) wpre += S.wsum[q];
           const uint64_t pre = wpre + incl - cnt;
+          bool contig = true, any = false;
+          uint64_t dref = 0, sum = 0;
+          for (uint32_t q = 0; q < TILE / 64; q++) {
+            const uint32_t f = S.wflag[q];
+            if (f & 1u) {
+              const uint64_t dq = S.wemin[q] - sum;
+              if ((f & 2u) || S.wemin[q] != S.wemax[q] || (any && dq != dref)) contig = false;
+              dref = dq;
+              any = true;
+            }
+            sum += S.wsum[q];
+          }
+          contig = contig && any;
           const uint64_t l = C.lane0 + tid;
           C.xs[l] = pre;
           if (cnt) {
-            C.xs[C.xn + l] = (uint64_t)s0;
-            C.xs[2 * C.xn + l] = (uint64_t)stp;
+            // gather bodies of contiguous tiles keep no start and step (the
+            // gather pass forms them from d)
+            if (!(contig && P->body_gather)) {
+              C.xs[C.xn + l] = (uint64_t)s0;
+              C.xs[2 * C.xn + l] = (uint64_t)stp;
+            }
             const uint32_t nl = P->n_livein;
             for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = RGET(ufirst(P->livein[q]));
           }
@@ -280,6 +310,8 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
             C.xtot[C.xt] = tot;
             (P->body_gather ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
             C.xin[C.xt] = C.input;
+            C.xd[2 * C.xt] = dref;
+            C.xd[2 * C.xt + 1] = contig ? 1ull : 0ull;
           }
           __syncthreads();
           // the loop is left at once: lanes that run it to the end pass its
@@ -386,6 +418,7 @@ __device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, c_input& in, ui
   C.xpb = a.xpb;
   C.xpg = a.xpg;
   C.xin = a.xin;
+  C.xd = a.xd;
   C.input = i;
   C.lane0 = 0;
   C.xt = 0;
@@ -1190,8 +1223,8 @@ __global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
   uint64_t cur_xt = ~0ull, sat = 0, xd = 0;
   uint64_t pb = 0, pe = 0;  // pieces of the current tile
   // the next tile of the same input, loaded while the current one runs:
-  // its index, this lane's prefix, start and step, its total and piece end
-  uint64_t nx = ~0ull, nx_pref = 0, nx_start = 0, nx_step = 0, nx_tot = 0, nx_pe = 0;
+  // its index, this lane's prefix, its total, piece end, d and contiguity
+  uint64_t nx = ~0ull, nx_pref = 0, nx_tot = 0, nx_pe = 0, nx_d = 0, nx_c = 0;
   Lane ln;
   lane_zero_totals(ln);
   for (;;) {
@@ -1230,44 +1263,43 @@ __global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
     const uint64_t* xs = (const uint64_t*)in.xstate;
     const uint64_t xn = in.xn;
     if (xt != cur_xt) {
+      // the tile's d and contiguity come from the whole-thread pass; a
+      // contiguous tile of a gather body keeps no start and step in memory:
+      // start = prefix + d, step 1
+      uint64_t pv;
       if (xt == nx) {
-        S.pref[tid] = nx_pref;
-        S.xstart[tid] = nx_start;
-        S.xstep[tid] = nx_step;
-        if (tid == 0) S.pref[TILE] = nx_tot;
+        pv = nx_pref;
+        xd = ufirst64(nx_d);
+        cont = (uint32_t)ufirst64(nx_c);
+        if (tid == 0) S.pref[TILE] = ufirst64(nx_tot);
       } else {
-        S.pref[tid] = xs[lane0 + tid];
-        S.xstart[tid] = xs[xn + lane0 + tid];
-        S.xstep[tid] = xs[2 * xn + lane0 + tid];
+        typedef const __attribute__((address_space(4))) unsigned long long c_u64;
+        pv = xs[lane0 + tid];
+        xd = ((c_u64*)a.xd)[2 * xt];
+        cont = (uint32_t)((c_u64*)a.xd)[2 * xt + 1];
         if (tid == 0) S.pref[TILE] = a.xtot[xt];
       }
-      if (tid == 0) {
-        S.xdmin = ~0ull;
-        S.xdmax = 0;
+      S.pref[tid] = pv;
+      if (cont) {
+        S.xstart[tid] = pv + xd;
+        S.xstep[tid] = 1;
+      } else {
+        S.xstart[tid] = xs[xn + lane0 + tid];
+        S.xstep[tid] = xs[2 * xn + lane0 + tid];
       }
       cur_xt = xt;
       if (xt + 1 < in.xt_begin + in.n_xt) {
         nx = xt + 1;
+        typedef const __attribute__((address_space(4))) unsigned long long c_u64;
         nx_pref = xs[lane0 + TILE + tid];
-        nx_start = xs[xn + lane0 + TILE + tid];
-        nx_step = xs[2 * xn + lane0 + TILE + tid];
-        nx_tot = a.xtot[nx];
-        nx_pe = nx + 1 < a.n_xtiles ? a.xpg[nx + 1] : ~0ull;
+        nx_tot = ((c_u64*)a.xtot)[nx];
+        nx_pe = nx + 1 < a.n_xtiles ? ((c_u64*)a.xpg)[nx + 1] : ~0ull;
+        nx_d = ((c_u64*)a.xd)[2 * nx];
+        nx_c = ((c_u64*)a.xd)[2 * nx + 1];
       } else {
         nx = ~0ull;
       }
       __syncthreads();
-      // contiguous tile: every owner with iterations has step 1 and the same
-      // start - prefix
-      const bool has = S.pref[tid + 1] != S.pref[tid];
-      if (has) {
-        const unsigned long long d = S.xstart[tid] - S.pref[tid];
-        atomicMin(&S.xdmin, d);
-        atomicMax(&S.xdmax, d);
-      }
-      const int nonunit = __syncthreads_or(has && S.xstep[tid] != 1);
-      cont = !nonunit && S.xdmin == S.xdmax;
-      xd = S.xdmin;
     }
     const uint64_t it0 = (p - pb) * PIECE;
     const uint64_t tot = S.pref[TILE];

@@ -36,6 +36,7 @@ struct KArgs {
   unsigned long long* xpb;    // pieces of interpreted bodies
   unsigned long long* xpg;    // pieces of gather bodies
   uint32_t* xin;
+  unsigned long long* xd;     // [2 per expanded tile]: start - prefix (d), contiguous (1) or not
   unsigned long long* xbsum;  // [2][blocks]
   uint64_t n_xtiles;
   uint32_t max_regs;        // interpreter registers (LDS rows of TILE lanes) of the job's programs

@@ -410,6 +410,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   uint8_t* d_xs = nullptr;
   unsigned long long *d_xtot = nullptr, *d_xpb = nullptr, *d_xpg = nullptr, *d_xbsum = nullptr;
   uint32_t* d_xin = nullptr;
+  unsigned long long* d_xd = nullptr;
   // tile-space order of the inputs: as given, or largest first for LPT
   std::vector<uint32_t> order(n_inputs);
   for (uint64_t i = 0; i < n_inputs; i++) order[i] = (uint32_t)i;
@@ -419,7 +420,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
       (rc = dalloc(c, J, &d_order, n_inputs)) ||
       (n_xtiles && ((rc = dalloc(c, J, &d_xs, xstate_bytes)) || (rc = dalloc(c, J, &d_xtot, n_xtiles)) ||
                     (rc = dalloc(c, J, &d_xpb, n_xtiles)) || (rc = dalloc(c, J, &d_xpg, n_xtiles)) ||
-                    (rc = dalloc(c, J, &d_xin, n_xtiles)) ||
+                    (rc = dalloc(c, J, &d_xin, n_xtiles)) || (rc = dalloc(c, J, &d_xd, 2 * n_xtiles)) ||
                     (rc = dalloc(c, J, &d_xbsum, 2 * ((n_xtiles + 4095) / 4096))))) ||
       (rc = dalloc(c, J, &J.d_recs, n_records)) || (rc = dalloc(c, J, &J.d_counts, n_counts)) ||
       (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &d_js, 1)) ||
@@ -458,6 +459,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   a.xpb = d_xpb;
   a.xpg = d_xpg;
   a.xin = d_xin;
+  a.xd = d_xd;
   a.xbsum = d_xbsum;
   a.n_xtiles = n_xtiles;
   a.max_regs = max_regs;
