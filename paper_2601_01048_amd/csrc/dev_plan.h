@@ -21,15 +21,10 @@ __device__ __forceinline__ const uint16_t* prog_sites(const dprog* p) {
   return (const uint16_t*)((const uint8_t*)p + p->off_sites);
 }
 
-__device__ __forceinline__ uint64_t rget(const uint32_t* lo, const uint32_t* hi, uint32_t i) {
-  return ((uint64_t)hi[i] << 32) | lo[i];
-}
-#define RSET(i, v)                      \
-  do {                                  \
-    uint64_t _v = (v);                  \
-    lo[(i)] = (uint32_t)_v;             \
-    hi[(i)] = (uint32_t)(_v >> 32);     \
-  } while (0)
+// Symbolic register file of the planning wavefront in LDS: register r of
+// lane j is RG[r * 64 + j] (64 bits).
+#define RGET64(i) RG[(uint32_t)(i) * 64u + j]
+#define RSET(i, v) (RG[(uint32_t)(i) * 64u + j] = (uint64_t)(v))
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -43,13 +38,11 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 // faults are counted per thread (every thread performs the same sequence).
 __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc, const ckc_alloc* tab,
                             dtrace_head* th, dtrace_entry* te, uint32_t* visits,
-                            ckc_input_status* st) {
+                            ckc_input_status* st, uint64_t* RG) {
   const uint32_t j = lane_id();
   const dins* I = prog_ins(P);
   const int64_t* K = prog_consts(P);
-  uint32_t lo[NREG], hi[NREG];
-#pragma unroll
-  for (int r = 0; r < NREG; r++) { lo[r] = 0; hi[r] = 0; }
+  for (uint32_t r = 0; r < P->n_regs; r++) RSET(r, 0ull);
   uint32_t n_ent = 0, n_cls = 0, overflow = 0, hang = 0, any_dead = 0;
   uint64_t acc_per_thread = 0, faults_per_thread = 0;
   __shared__ int64_t cls_coef[MAX_CLASSES][6];
@@ -77,12 +70,12 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
         break;
       }
       case CKC_OP_ADD: case CKC_OP_SUB: {
-        uint64_t a = rget(lo, hi, D.a), b = rget(lo, hi, D.b);
+        uint64_t a = RGET64(D.a), b = RGET64(D.b);
         RSET(D.dst, narrow(op == CKC_OP_ADD ? a + b : a - b, w));
         break;
       }
       case CKC_OP_MUL: case CKC_OP_SHL: {
-        uint64_t a = rget(lo, hi, D.a), b = rget(lo, hi, D.b);
+        uint64_t a = RGET64(D.a), b = RGET64(D.b);
         bool b_uni = __ballot(j < 6 && b != 0) == 0;
         uint64_t r;
         if (op == CKC_OP_SHL) {
@@ -96,16 +89,16 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
         RSET(D.dst, narrow(r, w));
         break;
       }
-      case CKC_OP_TRUNC: RSET(D.dst, narrow(rget(lo, hi, D.a), 32)); break;
-      case CKC_OP_SEXT: RSET(D.dst, j == 6 ? narrow(rget(lo, hi, D.a), 32) : 0ull); break;
-      case CKC_OP_ZEXT: RSET(D.dst, j == 6 ? (rget(lo, hi, D.a) & 0xFFFFFFFFull) : 0ull); break;
+      case CKC_OP_TRUNC: RSET(D.dst, narrow(RGET64(D.a), 32)); break;
+      case CKC_OP_SEXT: RSET(D.dst, j == 6 ? narrow(RGET64(D.a), 32) : 0ull); break;
+      case CKC_OP_ZEXT: RSET(D.dst, j == 6 ? (RGET64(D.a) & 0xFFFFFFFFull) : 0ull); break;
       case CKC_OP_SELECT: {
-        uint64_t c = readlane64(rget(lo, hi, D.a), 6);
-        RSET(D.dst, narrow(c != 0 ? rget(lo, hi, D.b) : rget(lo, hi, D.c), w));
+        uint64_t c = readlane64(RGET64(D.a), 6);
+        RSET(D.dst, narrow(c != 0 ? RGET64(D.b) : RGET64(D.c), w));
         break;
       }
       case CKC_OP_ACCESS: case CKC_OP_LOAD: {
-        uint64_t v = rget(lo, hi, D.a);
+        uint64_t v = RGET64(D.a);
         const ckc_alloc A = tab[D.slot];
         uint32_t lg = D.fl & 3u;
         // coefficient vector of this index (wrapped to the access width)
@@ -166,7 +159,7 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
         break;
       }
       case CKC_OP_IF: {
-        uint64_t c = readlane64(rget(lo, hi, D.a), 6);
+        uint64_t c = readlane64(RGET64(D.a), 6);
         if (c != 0) {
           visit(D.s0);
         } else {
@@ -179,9 +172,9 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
       case CKC_OP_ENDIF: break;
       case CKC_OP_LOOP: {
         uint32_t d = D.x;
-        int64_t s = (int64_t)narrow(readlane64(rget(lo, hi, D.a), 6), w);
-        int64_t e = (int64_t)narrow(readlane64(rget(lo, hi, D.b), 6), w);
-        int64_t stp = (int64_t)narrow(readlane64(rget(lo, hi, D.c), 6), w);
+        int64_t s = (int64_t)narrow(readlane64(RGET64(D.a), 6), w);
+        int64_t e = (int64_t)narrow(readlane64(RGET64(D.b), 6), w);
+        int64_t stp = (int64_t)narrow(readlane64(RGET64(D.c), 6), w);
         uint64_t nt = trip_count(s, e, stp);
         uint64_t cap = 1ull << (d == 0 ? cap_log2_0 : cap_log2_1);
         uint64_t rn = nt < cap ? nt : cap;
@@ -218,7 +211,7 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
       default: {
         // remaining ops only see thread-invariant operands here
         uint32_t f = 0;
-        uint64_t r = alu(op, w, readlane64(rget(lo, hi, D.a), 6), readlane64(rget(lo, hi, D.b), 6), f);
+        uint64_t r = alu(op, w, readlane64(RGET64(D.a), 6), readlane64(RGET64(D.b), 6), f);
         faults_per_thread += f;
         RSET(D.dst, j == 6 ? r : 0ull);
         break;
@@ -243,7 +236,8 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
   }
 }
 
-__global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
+__global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
+  extern __shared__ uint64_t RG[];  // [max_regs][64]: symbolic registers of build_trace
   const uint32_t i = blockIdx.x;
   if (i >= a.n_inputs) return;
   dinput& in = a.inputs[i];
@@ -277,7 +271,7 @@ __global__ void __launch_bounds__(64) plan_kernel(KArgs a) {
     dtrace_head* th = (dtrace_head*)in.trace;
     const uint32_t cap8 = (P->trace_cap + 7u) & ~7u;
     dtrace_entry* te = (dtrace_entry*)((uint8_t*)(th + 1) + (size_t)cap8 * 24);
-    build_trace(P, in, a.scalars + (size_t)i * MAX_SCALARS, (const ckc_alloc*)in.table, th, te, cnt, st);
+    build_trace(P, in, a.scalars + (size_t)i * MAX_SCALARS, (const ckc_alloc*)in.table, th, te, cnt, st, RG);
     __syncthreads();
     path = th->overflow ? 1 : 0;
     if (path == 1) {  // fall back: undo the per-thread counts

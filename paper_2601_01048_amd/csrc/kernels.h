@@ -46,6 +46,8 @@ struct KArgs {
 // At least 8 rows: the gather evaluation of expanded bodies keeps the counter
 // and up to 7 loaded values there.
 inline uint32_t regfile_bytes(const KArgs& a) { return (a.max_regs > 8u ? a.max_regs : 8u) * TILE * 8u; }
+// LDS bytes of the planning wavefront's symbolic register file.
+inline uint32_t plan_lds_bytes(const KArgs& a) { return (a.max_regs > 1u ? a.max_regs : 1u) * 64u * 8u; }
 
 // Workgroups and schedule of each evaluator (index PATH_*).
 struct EvalGrid {

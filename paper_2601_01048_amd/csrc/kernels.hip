@@ -45,7 +45,7 @@ namespace ckc {
 // host-callable launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_plan(const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(plan_kernel, dim3(a.n_inputs), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(plan_kernel, dim3(a.n_inputs), dim3(64), plan_lds_bytes(a), s, a);
   return hipGetLastError();
 }
 hipError_t launch_scan(const KArgs& a, hipStream_t s) {
@@ -154,7 +154,7 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
   void* args2[] = {&ka, &nr};
   void* argsp[3][1] = {{&kp[0]}, {&kp[1]}, {&kp[2]}};
   hipGraphNode_t plan, scan, ev[3], fix, fin;
-  hipError_t e = add_node(g, &plan, nullptr, 0, (void*)plan_kernel, a.n_inputs, 64, args1);
+  hipError_t e = add_node(g, &plan, nullptr, 0, (void*)plan_kernel, a.n_inputs, 64, args1, plan_lds_bytes(a));
   if (e == hipSuccess) e = add_node(g, &scan, &plan, 1, (void*)scan_kernel, 1, 1024, args1);
   if (e == hipSuccess)
     e = add_node(g, &ev[0], &scan, 1, eval_fn(PATH_BLOCKS, eg.sched[PATH_BLOCKS]), eg.n_wg[PATH_BLOCKS], TILE,
