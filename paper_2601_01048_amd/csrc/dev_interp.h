@@ -1199,7 +1199,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
 // in LDS with the tile's prefix, so an iteration costs one memory round trip
 // per dependent load of the body.
 template <uint32_t SK>
-__global__ void __launch_bounds__(TILE, 4) eval_gather_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
   __shared__ unsigned long long item_slot;
