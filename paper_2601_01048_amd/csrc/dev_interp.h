@@ -62,12 +62,13 @@ struct GenLds {
   unsigned long long xstart[TILE], xstep[TILE];  // loop start and step of the tile's threads (gather pass)
   uint16_t own[PIECE_LDS];            // owner thread of each iteration of the current piece
   uint16_t omax[TILE / 64];           // owner-map scan: per-wavefront maxima
-  // gather pass: the tile's counter offset (start - prefix, equal for all
-  // owners of a contiguous tile) and the violations of the current input's
-  // gather entries, merged here and flushed per input
-  unsigned long long xdmin, xdmax;
-  unsigned long long wemin[TILE / 64], wemax[TILE / 64];  // whole-thread pass: tile contiguity per wavefront
+  // whole-thread pass: per wavefront, the least and greatest start minus
+  // prefix of its threads with iterations, and flags (1: some thread has
+  // iterations, 2: some step is not 1), for the tile's contiguity
+  unsigned long long wemin[TILE / 64], wemax[TILE / 64];
   uint32_t wflag[TILE / 64];
+  // gather pass: the violations of the current input's gather entries,
+  // merged here and flushed per input
   unsigned long long vfk[MAX_GENT], vcnt[MAX_GENT];
   uint32_t vkinds[MAX_GENT];
 };

@@ -82,12 +82,6 @@ __device__ void tr_flush(TraceLds& S, ckc_record* rec, uint32_t n_acc) {
   __syncthreads();
 }
 
-// Out-of-line boundary-set decode (keeps its divisions off the FULL path).
-__device__ __forceinline__ uint64_t bset_block_call(uint32_t gx, uint32_t gy, uint32_t gz, uint64_t k) {
-  const uint32_t L[3] = {gx, gy, gz};
-  return bset_block(L, k);
-}
-
 typedef const __attribute__((address_space(4))) int64_t c_i64;
 typedef const __attribute__((address_space(4))) dprog c_dprog;
 typedef const __attribute__((address_space(4))) dblk c_blk;
@@ -240,19 +234,12 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, const BT* 
   }
 }
 
-// Per-input state of the trace evaluator (wavefront-uniform).
+// Per-input state of the trace evaluator over lane tiles (wavefront-uniform).
 struct TrIn {
   uint32_t L[7];  // launch dims, then the thread-set mode
-  uint32_t bs, gxy, bxy, mode, Lsum, ne, n_acc;
-  UDiv dgx, dgxy, dbx, dbxy, dspb;
-  uint32_t nsb;      // blocks of the thread set (below 2^32)
-  uint32_t ngroups;  // groups of LPB set blocks
-  c_head* th;     // coefficients are re-read per job (scalar loads)
-  uint32_t any_dead;
+  uint32_t mode, Lsum, ne, n_acc;
   bool lds;
   c_entry* te;
-  c_i64* h64;
-  c_u32* h32;
   ckc_record* rec;
 };
 
@@ -395,36 +382,20 @@ __device__ __forceinline__ void lanes_violation(TraceLds& S, c_entry* te, uint32
   tr_note(S, rec, te[e].acc, lds, key, (uint64_t)__popcll(badm), kinds);
 }
 
-// Loads the per-input state of the trace evaluator.
+// Loads the per-input state of the trace evaluator over lane tiles.
 __device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_record* recs, uint64_t& tb,
-                                        uint32_t path, uint32_t& ncls, uint32_t& w0, c_head*& th) {
+                                        uint32_t path, uint32_t& ncls, c_head*& th) {
   for (int q = 0; q < 6; q++) I.L[q] = ins[i].launch[q];
   I.L[6] = ins[i].mode;
-  I.bs = I.L[3] * I.L[4] * I.L[5];
-  I.gxy = I.L[0] * I.L[1];
-  I.bxy = I.L[3] * I.L[4];
-  I.dgx = udiv_make(I.L[0]);
-  I.dgxy = udiv_make(I.gxy);
-  I.dbx = udiv_make(I.L[3]);
-  I.dbxy = udiv_make(I.bxy);
-  I.dspb = udiv_make(I.bs >= 64 ? I.bs / 64u : 1u);
   I.mode = ins[i].mode;
   I.Lsum = ins[i].L1 + ins[i].L2;
   I.n_acc = ((c_dprog*)ins[i].prog)->n_accesses;
   I.lds = I.n_acc <= TR_ACC_LDS;
   th = (c_head*)ins[i].trace;
-  const uint32_t cap8 = th->cap8;
-  I.h64 = (c_i64*)(th + 1);
-  I.h32 = (c_u32*)(I.h64 + 2 * (size_t)cap8);
-  I.te = (c_entry*)(I.h32 + 2 * (size_t)cap8);
-  I.any_dead = th->any_dead;
+  I.te = trace_entries(th);
   I.rec = recs + ins[i].rec_base;
   I.ne = th->n_entries;
   ncls = th->n_classes;
-  w0 = th->cls_w[0];
-  I.nsb = (uint32_t)(I.mode == CKC_FULL ? (uint64_t)I.L[0] * I.L[1] * I.L[2] : bset_size(I.L));
-  I.ngroups = (I.nsb + LPB - 1) / LPB;
-  I.th = th;
   tb = ins[i].tile_begin[path];
 }
 
@@ -505,7 +476,7 @@ __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
     S.kinds[q] = 0;
   }
   __syncthreads();
-  uint32_t pos = 0xFFFFFFFFu, ncls = 0, w0 = 32;
+  uint32_t pos = 0xFFFFFFFFu, ncls = 0;
   uint64_t tb = 0, cur_end = 0, lanes = 0;
   c_head* th = nullptr;
   TrIn I;
@@ -517,7 +488,7 @@ __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
       if (pos != 0xFFFFFFFFu && I.lds) tr_flush(S, I.rec, I.n_acc);
       pos = np;
       const uint32_t i = order[pos];
-      tr_load(I, ins, i, a.recs, tb, PATH_LANES, ncls, w0, th);
+      tr_load(I, ins, i, a.recs, tb, PATH_LANES, ncls, th);
       cur_end = tb + ins[i].n_tiles[PATH_LANES];
       lanes = ins[i].lanes;
     }

@@ -107,6 +107,22 @@ def test_enqueued_readback_equals_waiting_readback(ctx, mini):
             B.same(g[i], ref[i], f"kernel {i} enqueued rep {rep}")
 
 
+def test_enqueue_needs_device_destination(ctx, mini):
+    """CKC_ENQUEUE with host destinations is rejected and leaves the job
+    readable."""
+    import ctypes
+    mb, db = mini
+    job = ctx.check(db.descs([0, 1]))
+    ni, nr = ctx.sizes(job)
+    recs = np.zeros(nr, ckc.RECORD_DTYPE)
+    st = np.zeros(ni, ckc.STATUS_DTYPE)
+    rc = ckc.lib().ckc_read_results(ctx.h, job, recs.ctypes.data_as(ctypes.c_void_p), None,
+                                    st.ctypes.data_as(ctypes.c_void_p), ckc.WAIT | ckc.ENQUEUE)
+    assert rc == -1
+    out = ctx.read(job, maps=False)
+    assert out is not None and int(out[2]["lanes"].sum()) > 0
+
+
 def test_graph_timing_and_elapsed(ctx, mini):
     mb, db = mini
     job = ctx.check(db.descs(), opts=ckc.launch_opts(use_graph=True))
