@@ -12,7 +12,52 @@ __device__ __forceinline__ uint64_t narrow(uint64_t v, uint32_t w) {
   return w == 32 ? (uint64_t)(int64_t)(int32_t)(uint32_t)v : v;
 }
 
+// Width 32 in 32-bit arithmetic: the low 32 bits of every result depend only
+// on the low 32 bits of the operands, and a 32-bit signed quotient cannot
+// overflow once INT32_MIN / -1 is taken apart; the result is sign-extended as
+// every 32-bit value in a register is.
+__device__ __forceinline__ uint64_t alu32(uint32_t op, uint32_t a, uint32_t b, uint32_t& faults) {
+  const int32_t sa = (int32_t)a, sb = (int32_t)b;
+  uint32_t r;
+  switch (op) {
+    case CKC_OP_ADD: r = a + b; break;
+    case CKC_OP_SUB: r = a - b; break;
+    case CKC_OP_MUL: r = a * b; break;
+    case CKC_OP_DIVS:
+      if (sb == 0) { faults++; r = 0; }
+      else if (sa == INT32_MIN && sb == -1) r = (uint32_t)INT32_MIN;
+      else r = (uint32_t)(sa / sb);
+      break;
+    case CKC_OP_REMS:
+      if (sb == 0) { faults++; r = 0; }
+      else if (sa == INT32_MIN && sb == -1) r = 0;
+      else r = (uint32_t)(sa % sb);
+      break;
+    case CKC_OP_DIVU: if (b == 0) { faults++; r = 0; } else r = a / b; break;
+    case CKC_OP_REMU: if (b == 0) { faults++; r = 0; } else r = a % b; break;
+    case CKC_OP_AND: r = a & b; break;
+    case CKC_OP_OR: r = a | b; break;
+    case CKC_OP_XOR: r = a ^ b; break;
+    case CKC_OP_SHL: r = a << (b & 31u); break;
+    case CKC_OP_SHRA: r = (uint32_t)(sa >> (b & 31u)); break;
+    case CKC_OP_SHRL: r = a >> (b & 31u); break;
+    case CKC_OP_MINS: r = (uint32_t)(sa < sb ? sa : sb); break;
+    case CKC_OP_MAXS: r = (uint32_t)(sa > sb ? sa : sb); break;
+    case CKC_OP_MINU: r = a < b ? a : b; break;
+    case CKC_OP_MAXU: r = a > b ? a : b; break;
+    case CKC_OP_CMPEQ: r = a == b; break;
+    case CKC_OP_CMPNE: r = a != b; break;
+    case CKC_OP_CMPLTS: r = sa < sb; break;
+    case CKC_OP_CMPLES: r = sa <= sb; break;
+    case CKC_OP_CMPLTU: r = a < b; break;
+    case CKC_OP_CMPLEU: r = a <= b; break;
+    default: r = 0; break;
+  }
+  return (uint64_t)(int64_t)(int32_t)r;
+}
+
 __device__ __forceinline__ uint64_t alu(uint32_t op, uint32_t w, uint64_t x, uint64_t y, uint32_t& faults) {
+  if (w == 32) return alu32(op, (uint32_t)x, (uint32_t)y, faults);
   const bool n32 = (w == 32);
   const uint64_t ux = n32 ? (uint64_t)(uint32_t)x : x;
   const uint64_t uy = n32 ? (uint64_t)(uint32_t)y : y;
