@@ -335,12 +335,16 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
       const UDiv dgx{Bg->m_gx, Bg->s_gx}, dgxy{Bg->m_gxy, Bg->s_gxy};
       const uint32_t gxy = Bg->gxy;
       const int64_t k3 = Bg->k[3], k4 = Bg->k[4], k5 = Bg->k[5];
-      for (uint32_t jj = 0; jj < LPB; jj++) {
-        const uint32_t blin = jj < nvalid ? (uint32_t)bset_block(L, (uint64_t)g * LPB + jj) : 0u;
-        const uint32_t cz = udiv(blin, dgxy), crem = blin - cz * gxy;
-        const uint32_t cy = udiv(crem, dgx), cx = crem - cy * L[0];
-        w[jj] = tp + (BT)((uint64_t)k3 * cx + (uint64_t)k4 * cy + (uint64_t)k5 * cz);
-      }
+      // lane jj of the wavefront decodes member g*LPB + jj of the set (the
+      // decodes of the group run side by side), then each block part is
+      // broadcast from its lane
+      const uint32_t jl = lane_id() & (LPB - 1);
+      const uint32_t blin = jl < nvalid ? (uint32_t)bset_block(L, (uint64_t)g * LPB + jl) : 0u;
+      const uint32_t cz = udiv(blin, dgxy), crem = blin - cz * gxy;
+      const uint32_t cy = udiv(crem, dgx), cx = crem - cy * L[0];
+      const uint64_t part = (uint64_t)k3 * cx + (uint64_t)k4 * cy + (uint64_t)k5 * cz;
+#pragma unroll
+      for (uint32_t jj = 0; jj < LPB; jj++) w[jj] = tp + (BT)readlane64(part, (int)jj);
     }
     if (nvalid < LPB) {
       // the last group of the set: unused slots repeat the first block
