@@ -26,6 +26,9 @@ __device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
 }
 
 typedef const __attribute__((address_space(4))) ckc_alloc c_alloc;
+// Loaded data through the global address space (global rather than flat loads).
+typedef const __attribute__((address_space(1))) int32_t g_i32;
+typedef const __attribute__((address_space(1))) int64_t g_i64;
 
 // Iterations of an expanded loop per work item of the body pass (also the
 // length of the owner map staged in LDS).
@@ -218,7 +221,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
         if (op == CKC_OP_LOAD) {
           uint64_t v = 0;
           if (act && kd == 0)
-            v = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
+            v = lg == 2 ? (uint64_t)(int64_t)((g_i32*)A.data)[idx] : (uint64_t)((g_i64*)A.data)[idx];
           r = v;
           wreg = dd;
         }
@@ -739,7 +742,7 @@ __device__ __forceinline__ void run_gather(GenLds& S, uint64_t* R, const Ctx& C,
     if (dst) {
       uint64_t x = 0;
       if (act && kd == 0)
-        x = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
+        x = lg == 2 ? (uint64_t)(int64_t)((g_i32*)A.data)[idx] : (uint64_t)((g_i64*)A.data)[idx];
       R[dst * TILE + threadIdx.x] = x;
     }
   }
@@ -837,7 +840,7 @@ __device__ __forceinline__ void gather_piece(GenLds& S, uint64_t* R, const Ctx& 
         if (dst) {
           uint64_t x = 0;
           if (act[q] && kd == 0)
-            x = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)data)[idx] : (uint64_t)((const int64_t*)data)[idx];
+            x = lg == 2 ? (uint64_t)(int64_t)((g_i32*)data)[idx] : (uint64_t)((g_i64*)data)[idx];
           R[((dst - 1) * U + q) * TILE + tid] = x;
         }
       }
@@ -919,9 +922,6 @@ __device__ __forceinline__ void flush_vio_lds(GenLds& S, ckc_record* rec) {
 // R32 (row q of TILE lanes, 32 bits) and, right after the entry (rare), finds
 // each lane's owner by binary search and merges into the workgroup's
 // per-entry records.
-typedef const __attribute__((address_space(1))) int32_t g_i32;
-typedef const __attribute__((address_space(1))) int64_t g_i64;
-
 // One entry of the contiguous form over U chunks: XV selects the index
 // variable (-1 none, 0 the counter, 1 or 2 the first or second loaded value),
 // DV the loaded value the entry defines (0 none).  Loads land directly in
