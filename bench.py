@@ -369,7 +369,8 @@ def main():
             result["rep_boundary"] = {"inputs_per_s": n / rs, "ms_per_step": rs * 1e3,
                                       "accesses_per_s": int(rst["accesses_checked"].sum()) / rs,
                                       "lanes_per_batch": int(rst["lanes"].sum()),
-                                      "speedup_inputs_per_s_vs_full": step_s / rs}
+                                      "speedup_inputs_per_s_vs_full": step_s / rs,
+                                      "kernel_ms": kernel_ms(np.array(rt))}
         dw.close()
     progress("stencil done")
     if not args.no_batched:

@@ -1,6 +1,7 @@
 """Host-side checks of the batched form: the mixed-batch generator and the
 C-ABI layout of the launch options (no GPU)."""
 import ctypes
+import os
 
 import numpy as np
 
@@ -75,3 +76,15 @@ def test_server_struct_layouts():
     assert ctypes.sizeof(ckc.ServerConfig) == 48
     assert ctypes.sizeof(ckc.JobStats) == 40
     assert ctypes.sizeof(ckc.ServerStats) == 48
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: --gpus above 1 ends with a message and
+    a nonzero status, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
