@@ -309,12 +309,14 @@ class DeviceWorkload:
         self.tensors = []
 
 
-def run_workload(ctx: Context, wl, mode=None, force_generic=False, maps=True, cap_log2=None):
+def run_workload(ctx: Context, wl, mode=None, force_generic=False, maps=True, cap_log2=None,
+                 opts: LaunchOpts | None = None):
     """Check every input of a workload; returns the oracle-shaped result dict
-    (records [n, n_acc], maps [n, 65536] or None, status [n])."""
+    (records [n, n_acc], maps [n, 65536] or None, status [n]).  ``opts``
+    (launch_opts) overrides force_generic."""
     dw = DeviceWorkload(ctx, wl)
     try:
-        job = ctx.check([dw.desc(mode, maps, cap_log2)], force_generic=force_generic)
+        job = ctx.check([dw.desc(mode, maps, cap_log2)], force_generic=force_generic, opts=opts)
         recs, mp, st = ctx.read(job, maps=maps)
     finally:
         dw.close()

@@ -38,6 +38,8 @@ constexpr uint32_t PIECE_LDS = 2048;
 // X[0] the loop counter and X[k] (k >= 1) the value of the k-th LOAD of the
 // body (var 0xFF: a uniform index `off`).
 constexpr uint32_t MAX_GENT = 32;
+// tiles after the first that one run of the gather pass may take
+constexpr uint32_t RUN_TILES = 64;
 struct GEnt {
   int64_t coef, off;
   uint64_t bound;       // elements of the slot's allocation (size >> lg)
@@ -74,6 +76,14 @@ struct GenLds {
   // merged here and flushed per input
   unsigned long long vfk[MAX_GENT], vcnt[MAX_GENT];
   uint32_t vkinds[MAX_GENT];
+  // gather pass over a run of chained contiguous tiles (iterations numbered
+  // from the run's first tile on): per gather entry the least violating
+  // iteration, the start of each tile after the first, the number of those
+  // tiles, the run's end and its piece end
+  unsigned long long rmin[MAX_GENT];
+  unsigned long long rstart[RUN_TILES + 1];
+  unsigned long long rend, rpend;
+  uint32_t rn;
 };
 
 // Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
@@ -892,6 +902,26 @@ __device__ __forceinline__ void merge_vio_lds(GenLds& S, uint32_t e, uint32_t kd
   }
 }
 
+// As merge_vio_lds, for a run of chained tiles: the wavefront's least
+// violating iteration goes to S.rmin (its owner is found once, at the end of
+// the run); count and kinds go to the records directly.
+__device__ __forceinline__ void merge_vio_run(GenLds& S, uint32_t e, uint32_t kd, uint64_t g) {
+  const uint64_t mask = __ballot(kd != 0);
+  if (mask == 0) return;
+  const uint64_t gm = wave_min64(kd ? g : ~0ull);
+  uint32_t kinds = 0;
+  if (__ballot(kd & CKC_KIND_OVER)) kinds |= CKC_KIND_OVER;
+  if (__ballot(kd & CKC_KIND_UNDER)) kinds |= CKC_KIND_UNDER;
+  if (__ballot(kd & CKC_KIND_FREED)) kinds |= CKC_KIND_FREED;
+  if (__ballot(kd & CKC_KIND_NULL)) kinds |= CKC_KIND_NULL;
+  const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+  if (lane_id() == leader) {
+    atomicMin(&S.rmin[e], (unsigned long long)gm);
+    atomicAdd(&S.vcnt[e], (unsigned long long)__popcll(mask));
+    atomicOr(&S.vkinds[e], kinds);
+  }
+}
+
 // Flushes the per-entry violation records of the current gather body into the
 // input's records (workgroup-converged; S.gb still holds that body).
 __device__ __forceinline__ void flush_vio_lds(GenLds& S, ckc_record* rec) {
@@ -958,10 +988,13 @@ __device__ __forceinline__ uint32_t c32_entry(const uint32_t* ctr, uint32_t* l1,
   return vio;
 }
 
+// run: [it0, it1) spans a run of chained tiles (full thread set only): a
+// violation's owner is not looked up here, merge_vio_run keeps the least
+// violating iteration per entry instead.
 template <uint32_t U>
 __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
                                            uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
-                                           const uint32_t* L6, uint32_t site_iter, uint32_t d32) {
+                                           const uint32_t* L6, uint32_t site_iter, uint32_t d32, bool run) {
   static_assert(U <= 16, "violation rows");
   const uint32_t tid = threadIdx.x;
   const uint32_t n = S.gb.n, faults = S.gb.faults;
@@ -1009,6 +1042,10 @@ __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& 
         const uint64_t g = base + q * TILE + tid;
         const bool bad = g < it1 && (dead || vv >= bnd);
         const uint32_t kd = !bad ? 0u : dead ? ufirst(E.dead) : ((int32_t)vv < 0 ? CKC_KIND_UNDER : CKC_KIND_OVER);
+        if (run) {
+          merge_vio_run(S, e, kd, g);
+          continue;
+        }
         const uint32_t o = owner_of(S, g < it1 ? g : it0);
         const uint64_t k = g < it1 ? g - S.pref[o] : 0;
         const uint64_t l = lane0 + o;
@@ -1028,6 +1065,44 @@ __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& 
   for (uint32_t e = 0; e < n; e++) count_site_n(S, C, sat, ufirst(S.gb.e[e].site), vc);
   ln.acc += (uint64_t)n * mine;
   ln.faults += (uint64_t)faults * mine;
+}
+
+// Ends a run of chained tiles (workgroup-converged): for each gather entry
+// with a violation in the run, the owner of its least violating iteration is
+// found in the prefix of the tile that holds it (the first tile's in LDS, a
+// later one's in memory), and the entry's key is merged.  lane0 is the first
+// tile's first lane.
+__device__ __forceinline__ void end_run(GenLds& S, const Ctx& C, const uint64_t* xs, uint64_t lane0, uint32_t n) {
+  __syncthreads();
+  const uint32_t e = threadIdx.x;
+  if (e < n && S.rmin[e] != ~0ull) {
+    const uint64_t g = S.rmin[e];
+    uint32_t lo = 0, hi = S.rn;
+    while (lo < hi) {
+      const uint32_t m = (lo + hi + 1) >> 1;
+      if (S.rstart[m] <= g) lo = m;
+      else hi = m - 1;
+    }
+    const uint64_t gl = g - S.rstart[lo];
+    const uint64_t l0 = lane0 + (uint64_t)lo * TILE;
+    uint32_t o;
+    uint64_t pre;
+    if (lo == 0) {
+      o = owner_of(S, gl);
+      pre = S.pref[o];
+    } else {
+      uint32_t l2 = 0, h2 = TILE - 1;
+      while (l2 < h2) {
+        const uint32_t m = (l2 + h2 + 1) >> 1;
+        if (xs[l0 + m] <= gl) l2 = m;
+        else h2 = m - 1;
+      }
+      o = l2;
+      pre = xs[l0 + o];
+    }
+    atomicMin(&S.vfk[e], (unsigned long long)(((l0 + o) << C.Lsum) | ((gl - pre) << C.L2)));
+    S.rmin[e] = ~0ull;
+  }
 }
 
 // Owner map of the iterations [it0, it1) of a piece: S.own[g - it0] is the
@@ -1218,6 +1293,7 @@ __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
     S.vfk[tid] = ~0ull;
     S.vcnt[tid] = 0;
     S.vkinds[tid] = 0;
+    S.rmin[tid] = ~0ull;
   }
   uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0, fast = 0, cur_mode = 0, cont = 0;
   uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
@@ -1335,12 +1411,62 @@ __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
       // with this one (no owner map bounds the length)
       const uint64_t lim = pe < sc.end ? pe : sc.end;
       uint64_t iend = it1;
+      bool run = false;
       if (lim > p + 1) {
         const uint64_t e1 = (lim - pb) * PIECE;
         iend = e1 < tot ? e1 : tot;
         sc.cur = lim;
       }
-      gather_c32<8>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd);
+      // The tile ends inside the workgroup's range: the following tiles of
+      // the input that are contiguous, continue the counter where the one
+      // before ends and start inside the range form one run with this one
+      // (empty tiles are passed over).  Wavefront 0 reads one tile per lane.
+      if (cur_mode == CKC_FULL && pe < sc.end) {
+        if (tid < 64) {
+          const uint64_t tl = xt + 1 + tid;
+          const bool valid = tl < in.xt_begin + in.n_xt;
+          uint64_t tt = 0, dd = 0, cc = 0, tb = ~0ull, te = ~0ull;
+          if (valid) {
+            tt = a.xtot[tl];
+            dd = a.xd[2 * tl];
+            cc = a.xd[2 * tl + 1];
+            tb = a.xpg[tl];
+            te = tl + 1 < a.n_xtiles ? a.xpg[tl + 1] : ~0ull;
+          }
+          uint64_t incl = tt;
+          for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
+            if ((int)lane_id() >= o) incl += u;
+          }
+          const uint64_t F = tot + incl - tt;  // the tile's first iteration in the run
+          const bool link = valid && tb < sc.end && (tt == 0 || (cc && (uint32_t)dd == (uint32_t)(xd + F)));
+          const uint64_t broken = __ballot(!link);
+          const uint32_t m = broken ? (uint32_t)__ffsll((unsigned long long)broken) - 1 : 64u;
+          if (tid < m) S.rstart[tid + 1] = F;
+          if (m != 0 && tid == m - 1) {
+            const uint64_t pend = te < sc.end ? te : sc.end;
+            const uint64_t span = (pend - tb) * PIECE;
+            S.rend = F + (span < tt ? span : tt);
+            S.rpend = pend;
+          }
+          if (tid == 0) {
+            S.rn = m;
+            S.rstart[0] = 0;
+          }
+        }
+        __syncthreads();
+        if (S.rn != 0) {
+          iend = S.rend;
+          sc.cur = S.rpend;
+          run = true;
+        }
+      }
+      gather_c32<8>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd, run);
+      if (run) {
+        end_run(S, C, xs, lane0, S.gb.n);
+        cur_xt = ~0ull;  // the next piece sets its tile up afresh
+        nx = ~0ull;
+      }
       continue;
     }
     build_owner_map(S, it0, it1);

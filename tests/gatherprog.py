@@ -93,3 +93,48 @@ def gather_workload(rng, ir, n_inputs=4):
         tabs[i] = [t + (0,) for t in tables[i]]
     return W.Workload("gather", ir, launches, np.asarray(scalars, np.int64), tabs,
                       np.arange(n_inputs, dtype=np.uint32), [D, E], W.MODE_FULL, (20, 12))
+
+
+def csr_runs_workload(seed: int, log2_rows: int = 15, n_inputs: int = 4):
+    """CSR gathers (the F3 program) whose row pointers exercise how the gather
+    pass joins consecutive contiguous tiles of 256 rows into one run:
+    input 0 a plain matrix (every tile continues the one before); input 1
+    tile boundaries where the last row of a tile runs backwards, so the next
+    tile restarts below the previous end (each tile contiguous, the chain
+    broken); input 2 whole tiles of empty rows and a short last tile; input 3
+    rows running backwards inside tiles (tiles not contiguous).  Every input
+    has its own corrupted col_idx, a val allocation that ends before the last
+    nonzeros (violations in late tiles of long runs) and an x allocation short
+    of ncols (violations spread over every tile)."""
+    rng = np.random.default_rng(seed)
+    data, tables, launch, scalars = [], [], [], []
+    for i in range(n_inputs):
+        nrows = (1 << log2_rows) - (77 if i == 2 else 0)
+        ncols = 1 << log2_rows
+        L = W.powerlaw_row_lengths(rng, nrows, ncols, 16)
+        if i == 2:  # empty tiles
+            for t in rng.choice(nrows // 256 - 1, size=12, replace=False):
+                L[256 * t:256 * (t + 1)] = 0
+        rp = np.zeros(nrows + 1, np.int64)
+        np.cumsum(L, out=rp[1:])
+        if i == 1:  # backward last rows at tile boundaries
+            for t in rng.choice(np.arange(1, nrows // 256), size=20, replace=False):
+                rp[256 * t] = rp[256 * t - 1] - int(rng.integers(1, 9))
+        if i == 3:  # backward rows inside tiles
+            for r in rng.choice(nrows - 2, size=15, replace=False) + 1:
+                rp[r] = max(0, rp[r - 1] - int(rng.integers(1, 9)))
+        nnz = int(rp.max())
+        col = rng.integers(0, ncols, size=nnz, dtype=np.int64).astype(np.int32)
+        col = W.corrupt_copy(rng, col, ncols, 0.002)
+        data += [rp.astype(np.int32), col]
+        val_len = nnz - int(rng.integers(1, 2000))
+        tables.append([W.alloc((nrows + 1) * 4, len(data) - 1, W.LOGICAL_BASE),
+                       W.alloc(nnz * 4, len(data), W.LOGICAL_BASE + (1 << 36)),
+                       W.alloc(val_len * 4, 0, W.LOGICAL_BASE + (2 << 36)),
+                       W.alloc((ncols - int(rng.integers(100, 1000))) * 4, 0, W.LOGICAL_BASE + (3 << 36)),
+                       W.alloc(nrows * 4, 0, W.LOGICAL_BASE + (4 << 36))])
+        launch.append([(nrows + 255) // 256, 1, 1, 256, 1, 1])
+        scalars.append([nrows])
+    return W.Workload("csr_runs", W.f3_program(32), np.array(launch, np.uint32), np.array(scalars, np.int64),
+                      np.array([[tuple(a) for a in t] for t in tables], dtype=W.ALLOC_DTYPE),
+                      np.arange(n_inputs, dtype=np.uint32), data, W.MODE_FULL)

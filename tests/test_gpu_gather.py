@@ -34,3 +34,18 @@ def test_random_gather_bodies(ctx, seed):
         o = O.check(wl)
         compare(g, o, what=f"gather seed {seed} prog {k} ir {ir.hex()}")
     assert n_gather > 0
+
+
+@pytest.mark.parametrize("schedule,wg", [(ckc.SCHED_DEFAULT, 1), (ckc.SCHED_DEFAULT, 0), (ckc.SCHED_DYNAMIC, 1),
+                                         (ckc.SCHED_CYCLIC, 2)])
+def test_gather_tile_runs(ctx, schedule, wg):
+    """Runs of chained contiguous tiles in the gather pass: broken chains,
+    empty tiles, tiles that are not contiguous, violations in late tiles of a
+    run; few workgroups, so that each takes many pieces."""
+    from test_gpu_parity import compare
+    wl = G.csr_runs_workload(11)
+    print(f"[case] csr runs schedule {schedule} wg_per_cu {wg}", flush=True)
+    g = ckc.run_workload(ctx, wl, opts=ckc.launch_opts(schedule=schedule, wg_per_cu=wg))
+    o = O.check(wl, nthreads=4)
+    compare(g, o, what=f"csr runs schedule {schedule} wg {wg}")
+    assert (o["records"]["count"][:, 3] > 0).all() and (o["records"]["count"][:, 4] > 100).all()
