@@ -949,38 +949,44 @@ __device__ __forceinline__ void flush_vio_lds(GenLds& S, ckc_record* rec) {
 // the U loads of an entry are in flight together.  The body is straight-line,
 // so every site of it is visited once per iteration: the visits are counted
 // once at the end.  A violating chunk of an entry keeps its index values in
-// R32 (row q of TILE lanes, 32 bits) and, right after the entry (rare), finds
-// each lane's owner by binary search and merges into the workgroup's
-// per-entry records.
+// R32 (row q of TILE lanes, 32 bits; the dynamic LDS holds at least 16 such
+// rows) and, right after the entry (rare), finds each lane's owner by binary
+// search and merges into the workgroup's per-entry records.  Rounds wholly
+// inside the range drop the per-lane range tests, and an entry indexed by the
+// counter with coefficient 1 whose indices in the round all lie in bounds
+// (one uniform test) is loaded, or passed over, with no per-lane check.
 // One entry of the contiguous form over U chunks: XV selects the index
 // variable (-1 none, 0 the counter, 1 or 2 the first or second loaded value),
-// DV the loaded value the entry defines (0 none).  Loads land directly in
-// their variable, so the U loads are in flight together.  Returns the chunks
-// with a violating lane; their index values go to R32.
-template <uint32_t U, int XV, int DV>
-__device__ __forceinline__ uint32_t c32_entry(const uint32_t* ctr, uint32_t* l1, uint32_t* l2, const bool* act,
+// DV the loaded value the entry defines (0 none), FULL that every iteration
+// of the round is in range (act unused).  The counter of chunk q is
+// c0 + q * TILE.  Loads land directly in their variable, so the U loads are in
+// flight together; a lane with nothing to load reads element 0 (valid: the
+// caller passes DV = 0 when no index can be in bounds) and keeps 0.  Returns
+// the chunks with a violating lane; their index values go to R32.
+template <uint32_t U, int XV, int DV, bool FULL>
+__device__ __forceinline__ uint32_t c32_entry(uint32_t c0, uint32_t* l1, uint32_t* l2, const bool* act,
                                               uint32_t off, uint32_t coef, bool c1, uint32_t bnd, bool dead,
-                                              bool lg2, const void* data, uint32_t* R32, uint32_t tid) {
+                                              uint32_t sh, const void* data, uint32_t* R32, uint32_t tid) {
   uint32_t vio = 0;
 #pragma unroll
   for (uint32_t q = 0; q < U; q++) {
     uint32_t vv = off;
     if (XV >= 0) {
-      const uint32_t x = XV == 0 ? ctr[q] : XV == 1 ? l1[q] : l2[q];
+      const uint32_t x = XV == 0 ? c0 + q * TILE : XV == 1 ? l1[q] : l2[q];
       if (c1) vv += x;
       else vv += coef * x;
     }
-    const bool bad = act[q] && (dead || vv >= bnd);
+    const bool on = FULL || act[q];
+    const bool bad = on && (dead || vv >= bnd);
     if (__ballot(bad)) {
       vio |= 1u << q;
       R32[q * TILE + tid] = vv;
     }
     if (DV != 0) {
-      uint32_t val = 0;
-      if (act[q] && !bad) {
-        if (lg2) val = (uint32_t)((g_i32*)data)[vv];
-        else val = (uint32_t)((g_i64*)data)[vv];
-      }
+      const bool ld = on && !bad;
+      const uint32_t ix = ld ? vv : 0u;
+      uint32_t val = (uint32_t) * (g_i32*)((const __attribute__((address_space(1))) uint8_t*)data + ((uint64_t)ix << sh));
+      val = ld ? val : 0u;
       if (DV == 1) l1[q] = val;
       else l2[q] = val;
     }
@@ -988,77 +994,136 @@ __device__ __forceinline__ uint32_t c32_entry(const uint32_t* ctr, uint32_t* l1,
   return vio;
 }
 
-// run: [it0, it1) spans a run of chained tiles (full thread set only): a
-// violation's owner is not looked up here, merge_vio_run keeps the least
-// violating iteration per entry instead.
-template <uint32_t U>
-__device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
-                                           uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
-                                           const uint32_t* L6, uint32_t site_iter, uint32_t d32, bool run) {
-  static_assert(U <= 16, "violation rows");
-  const uint32_t tid = threadIdx.x;
-  const uint32_t n = S.gb.n, faults = S.gb.faults;
-  uint64_t visits = 0;
-  uint32_t mine = 0;
-  for (uint64_t base = it0; base < it1; base += (uint64_t)TILE * U) {
-    uint32_t ctr[U], l1[U], l2[U];
-    bool act[U];
+// Loads of an entry whose U * TILE indices of the round are the consecutive
+// values i0, i0 + 1, ..., all in bounds: no check, and the address of chunk q
+// is a uniform base plus the lane and an immediate.
+template <uint32_t U, bool W32>
+__device__ __forceinline__ void c32_stream(uint32_t* l, const void* data, uint32_t i0, uint32_t tid) {
+  if (W32) {
+    const g_i32* p = (const g_i32*)data + i0;
 #pragma unroll
-    for (uint32_t q = 0; q < U; q++) {
-      const uint64_t g = base + q * TILE + tid;
-      act[q] = g < it1;
-      ctr[q] = d32 + (uint32_t)g;
-      l1[q] = 0;
-      l2[q] = 0;
+    for (uint32_t q = 0; q < U; q++) l[q] = (uint32_t)p[q * TILE + tid];
+  } else {
+    const g_i64* p = (const g_i64*)data + i0;
+#pragma unroll
+    for (uint32_t q = 0; q < U; q++) l[q] = (uint32_t)p[q * TILE + tid];
+  }
+}
+
+// One round of the contiguous form: U chunks of TILE iterations from base.
+// FULL: the whole round lies before it1.  An entry indexed by the counter with
+// coefficient 1 whose round of indices lies inside its allocation (one
+// uniform comparison) takes no per-iteration check.
+template <uint32_t U, bool FULL>
+__device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C, uint64_t base, uint64_t it0,
+                                          uint64_t it1, uint32_t d32, uint32_t n, uint64_t lane0, uint32_t mode,
+                                          const uint32_t* L6, bool run, uint32_t& mine, uint64_t& visits) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t l1[U], l2[U];
+  bool act[U];
+  const uint32_t c0 = d32 + (uint32_t)(base + tid);
+#pragma unroll
+  for (uint32_t q = 0; q < U; q++) {
+    act[q] = FULL || base + q * TILE + tid < it1;
+    l1[q] = 0;
+    l2[q] = 0;
+    if (!FULL) {
       mine += act[q] ? 1u : 0u;
       visits += (uint64_t)__popcll(__ballot(act[q]));  // this wavefront's iterations
     }
-    for (uint32_t e = 0; e < n; e++) {
-      const GEnt& E = S.gb.e[e];
-      // control fields uniform (scalar), values per lane from LDS
-      const uint32_t meta = ufirst((uint32_t)E.var | ((uint32_t)E.dst << 8) | ((uint32_t)E.lg << 16) |
-                                   ((uint32_t)(E.coef == 1) << 24) | ((uint32_t)(E.dead != 0) << 25));
-      const uint32_t var = meta & 0xFFu, dst = (meta >> 8) & 0xFFu;
-      const bool lg2 = ((meta >> 16) & 0xFFu) == 2, c1 = (meta >> 24) & 1u, dead = (meta >> 25) & 1u;
-      const uint32_t off = (uint32_t)E.off, coef = (uint32_t)E.coef;
-      const uint64_t b64 = E.bound;
-      const uint32_t bnd = b64 > 0x80000000ull ? 0x80000000u : (uint32_t)b64;
-      const void* data = (const void*)ufirst64((uint64_t)E.data);
-      uint32_t vio;
-#define C32E(XV, DV) vio = c32_entry<U, XV, DV>(ctr, l1, l2, act, off, coef, c1, bnd, dead, lg2, data, R32, tid)
-#define C32D(XV)         \
-  if (dst == 0) C32E(XV, 0); \
-  else if (dst == 1) C32E(XV, 1); \
-  else C32E(XV, 2)
-      if (var == 0xFF) { C32D(-1); }
-      else if (var == 0) { C32D(0); }
-      else if (var == 1) { C32D(1); }
-      else { C32D(2); }
-#undef C32D
-#undef C32E
-      for (uint32_t bits = vio; bits; bits &= bits - 1) {
-        const uint32_t q = (uint32_t)__ffs((int)bits) - 1;
-        const uint32_t vv = R32[q * TILE + tid];
-        const uint64_t g = base + q * TILE + tid;
-        const bool bad = g < it1 && (dead || vv >= bnd);
-        const uint32_t kd = !bad ? 0u : dead ? ufirst(E.dead) : ((int32_t)vv < 0 ? CKC_KIND_UNDER : CKC_KIND_OVER);
-        if (run) {
-          merge_vio_run(S, e, kd, g);
-          continue;
+  }
+  if (FULL) {
+    mine += U;
+    visits += (uint64_t)U * 64;
+  }
+  for (uint32_t e = 0; e < n; e++) {
+    const GEnt& E = S.gb.e[e];
+    const uint32_t meta = ufirst((uint32_t)E.var | ((uint32_t)E.dst << 8) | ((uint32_t)E.lg << 16) |
+                                 ((uint32_t)(E.coef == 1) << 24) | ((uint32_t)(E.dead != 0) << 25));
+    const uint32_t var = meta & 0xFFu, dst = (meta >> 8) & 0xFFu;
+    const bool lg2 = ((meta >> 16) & 0xFFu) == 2, c1 = (meta >> 24) & 1u, dead = (meta >> 25) & 1u;
+    const uint32_t off = ufirst((uint32_t)E.off), coef = (uint32_t)E.coef;
+    const uint64_t b64 = ufirst64(E.bound);
+    const uint32_t bnd = b64 > 0x80000000ull ? 0x80000000u : (uint32_t)b64;
+    const void* data = (const void*)ufirst64((uint64_t)E.data);
+    if (FULL && var == 0 && c1 && !dead && dst != 2) {
+      const uint32_t i0 = ufirst(off + d32 + (uint32_t)base);  // index of the round's first iteration
+      if ((uint64_t)i0 + (uint64_t)U * TILE <= bnd) {
+        if (dst == 1) {
+          if (lg2) c32_stream<U, true>(l1, data, i0, tid);
+          else c32_stream<U, false>(l1, data, i0, tid);
         }
-        const uint32_t o = owner_of(S, g < it1 ? g : it0);
-        const uint64_t k = g < it1 ? g - S.pref[o] : 0;
-        const uint64_t l = lane0 + o;
-        uint64_t gtid = l;
-        if (mode != CKC_FULL) {
-          Thr T;
-          decode_lane(mode, L6, l, T);
-          gtid = T.gtid;
-        }
-        merge_vio_lds(S, e, kd, (gtid << C.Lsum) | (k << C.L2));
+        continue;
       }
     }
+    // no index of the entry can be in bounds: nothing to load, values 0
+    const bool none = dead || bnd == 0;
+    uint32_t vio;
+#define C32E(XV, DV) \
+  vio = c32_entry<U, XV, DV, FULL>(c0, l1, l2, act, off, coef, c1, bnd, dead, lg2 ? 2u : 3u, data, R32, tid)
+#define C32D(XV)                  \
+  if (dst == 0 || none) C32E(XV, 0); \
+  else if (dst == 1) C32E(XV, 1);   \
+  else C32E(XV, 2)
+    if (var == 0xFF) { C32D(-1); }
+    else if (var == 0) { C32D(0); }
+    else if (var == 1) { C32D(1); }
+    else { C32D(2); }
+#undef C32D
+#undef C32E
+    if (dst != 0 && none) {
+#pragma unroll
+      for (uint32_t q = 0; q < U; q++) {
+        if (dst == 1) l1[q] = 0;
+        else l2[q] = 0;
+      }
+    }
+    for (uint32_t bits = vio; bits; bits &= bits - 1) {
+      const uint32_t q = (uint32_t)__ffs((int)bits) - 1;
+      const uint32_t vv = R32[q * TILE + tid];
+      const uint64_t g = base + q * TILE + tid;
+      const bool bad = g < it1 && (dead || vv >= bnd);
+      const uint32_t kd = !bad ? 0u : dead ? ufirst(E.dead) : ((int32_t)vv < 0 ? CKC_KIND_UNDER : CKC_KIND_OVER);
+      if (run) {
+        merge_vio_run(S, e, kd, g);
+        continue;
+      }
+      const uint32_t o = owner_of(S, g < it1 ? g : it0);
+      const uint64_t k = g < it1 ? g - S.pref[o] : 0;
+      const uint64_t l = lane0 + o;
+      uint64_t gtid = l;
+      if (mode != CKC_FULL) {
+        Thr T;
+        decode_lane(mode, L6, l, T);
+        gtid = T.gtid;
+      }
+      merge_vio_lds(S, e, kd, (gtid << C.Lsum) | (k << C.L2));
+    }
   }
+}
+
+// With BIG, long ranges go in rounds of 16 chunks (more loads in flight), the
+// rest in rounds of 8 (a piece of PIECE iterations is one round); the larger
+// rounds cost registers that the per-piece state of jobs of many small inputs
+// then spills.  run: [it0, it1)
+// spans a run of chained tiles (full thread set only): a violation's owner is
+// not looked up here, merge_vio_run keeps the least violating iteration per
+// entry instead.
+template <bool BIG>
+__device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
+                                           uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
+                                           const uint32_t* L6, uint32_t site_iter, uint32_t d32, bool run) {
+  constexpr uint32_t UL = 16, US = 8;  // R32 rows: at most 16
+  const uint32_t n = S.gb.n, faults = S.gb.faults;
+  uint64_t visits = 0;
+  uint32_t mine = 0;
+  uint64_t base = it0;
+  if (BIG)
+    for (; base + (uint64_t)TILE * UL <= it1; base += (uint64_t)TILE * UL)
+      c32_round<UL, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, L6, run, mine, visits);
+  for (; base + (uint64_t)TILE * US <= it1; base += (uint64_t)TILE * US)
+    c32_round<US, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, L6, run, mine, visits);
+  if (base < it1) c32_round<US, false>(S, R32, C, base, it0, it1, d32, n, lane0, mode, L6, run, mine, visits);
   // visits of the counter's site and of every entry's site
   const uint32_t vc = (uint32_t)(visits < 0xFFFFFFFFull ? visits : 0xFFFFFFFFull);
   count_site_n(S, C, sat, site_iter, vc);
@@ -1274,7 +1339,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
 // iteration (no instruction dispatch).  The owners' start and step are staged
 // in LDS with the tile's prefix, so an iteration costs one memory round trip
 // per dependent load of the body.
-template <uint32_t SK>
+template <uint32_t SK, bool BIG>
 __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
@@ -1461,7 +1526,7 @@ __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
           run = true;
         }
       }
-      gather_c32<8>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd, run);
+      gather_c32<BIG>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd, run);
       if (run) {
         end_run(S, C, xs, lane0, S.gb.n);
         cur_xt = ~0ull;  // the next piece sets its tile up afresh

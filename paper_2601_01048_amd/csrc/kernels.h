@@ -56,6 +56,7 @@ struct EvalGrid {
   uint32_t chunk[3];
   uint32_t n_wg_body;   // workgroups of the body passes of expanded loops
   uint32_t sched_body;  // schedule of the body passes
+  uint32_t big_body;    // gather pass with 16-chunk rounds (inputs of many tiles)
 };
 
 hipError_t launch_plan(const KArgs& a, hipStream_t s);

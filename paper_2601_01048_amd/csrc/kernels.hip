@@ -91,12 +91,16 @@ hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream
 hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
   return launch_eval(a, eg, PATH_GENERIC, s);
 }
-static void* body_fn(uint32_t sk, uint32_t which) {
+static void* body_fn(uint32_t sk, uint32_t which, uint32_t big) {
   const uint32_t s = sched_impl(sk);
+  if (which && big)
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_gather_kernel<CKC_SCHED_BLOCKED, true>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_gather_kernel<CKC_SCHED_CYCLIC, true>
+                                  : (void*)eval_gather_kernel<CKC_SCHED_DYNAMIC, true>;
   if (which)
-    return s == CKC_SCHED_BLOCKED ? (void*)eval_gather_kernel<CKC_SCHED_BLOCKED>
-         : s == CKC_SCHED_CYCLIC  ? (void*)eval_gather_kernel<CKC_SCHED_CYCLIC>
-                                  : (void*)eval_gather_kernel<CKC_SCHED_DYNAMIC>;
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_gather_kernel<CKC_SCHED_BLOCKED, false>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_gather_kernel<CKC_SCHED_CYCLIC, false>
+                                  : (void*)eval_gather_kernel<CKC_SCHED_DYNAMIC, false>;
   return s == CKC_SCHED_BLOCKED ? (void*)eval_body_kernel<CKC_SCHED_BLOCKED>
        : s == CKC_SCHED_CYCLIC  ? (void*)eval_body_kernel<CKC_SCHED_CYCLIC>
                                 : (void*)eval_body_kernel<CKC_SCHED_DYNAMIC>;
@@ -114,7 +118,7 @@ hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
     hipLaunchKernelGGL(xscan_apply_kernel, dim3(nb), dim3(256), 0, s, a, which);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
-      e = hipLaunchKernel(body_fn(eg.sched_body, which), dim3(eg.n_wg_body), dim3(TILE), args,
+      e = hipLaunchKernel(body_fn(eg.sched_body, which, eg.big_body), dim3(eg.n_wg_body), dim3(TILE), args,
                           regfile_bytes(a), s);
     if (e != hipSuccess) return e;
   }
@@ -178,7 +182,7 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
       if (e == hipSuccess) e = add_node(g, &x2, &x1, 1, (void*)xscan_blocks_kernel, 1, 1024, argsb[which]);
       if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, argsw[which]);
       if (e == hipSuccess)
-        e = add_node(g, &xb[which], &x3, 1, body_fn(eg.sched_body, which), eg.n_wg_body, TILE,
+        e = add_node(g, &xb[which], &x3, 1, body_fn(eg.sched_body, which, eg.big_body), eg.n_wg_body, TILE,
                      argsp[PATH_GENERIC], regfile_bytes(a));
     }
     if (e != hipSuccess) return e;

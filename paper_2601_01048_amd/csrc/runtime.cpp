@@ -337,7 +337,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   std::vector<dinput> hin;
   std::vector<int64_t> hsc;
   std::vector<uint64_t> est;  // estimated work per input (LPT order)
-  uint64_t n_xtiles = 0, xstate_bytes = 0;  // expanded loops
+  uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
   uint32_t max_regs = 1;                     // interpreter register file rows
   uint64_t gen_tiles = 0;                    // interpreter tiles (estimate from the launch shapes)
   uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
@@ -382,6 +382,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
         d.xn = n_xt * TILE;
         d.n_xt = n_xt;
         n_xtiles += n_xt;
+        n_xin++;
         xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
       }
       hin.push_back(d);
@@ -479,6 +480,9 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   // body passes: pieces are near-equal work, and a workgroup walking one
   // contiguous range of them finds each piece's tile by a step from the last
   eg.sched_body = O.schedule ? O.schedule : CKC_SCHED_BLOCKED;
+  // long gather ranges (inputs of 64 tiles or more on average) take the
+  // variant with larger rounds
+  eg.big_body = n_xin != 0 && n_xtiles >= 64 * n_xin ? 1u : 0u;
   J.graph = O.use_graph != 0;
   e = hipEventRecord(J.ev[0], J.stream);
   if (J.graph) {

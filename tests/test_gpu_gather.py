@@ -36,15 +36,18 @@ def test_random_gather_bodies(ctx, seed):
     assert n_gather > 0
 
 
-@pytest.mark.parametrize("schedule,wg", [(ckc.SCHED_DEFAULT, 1), (ckc.SCHED_DEFAULT, 0), (ckc.SCHED_DYNAMIC, 1),
-                                         (ckc.SCHED_CYCLIC, 2)])
-def test_gather_tile_runs(ctx, schedule, wg):
+@pytest.mark.parametrize("schedule,wg,log2_rows", [(ckc.SCHED_DEFAULT, 1, 15), (ckc.SCHED_DEFAULT, 0, 15),
+                                                   (ckc.SCHED_DYNAMIC, 1, 15), (ckc.SCHED_CYCLIC, 2, 15),
+                                                   (ckc.SCHED_DEFAULT, 1, 13)])
+def test_gather_tile_runs(ctx, schedule, wg, log2_rows):
     """Runs of chained contiguous tiles in the gather pass: broken chains,
     empty tiles, tiles that are not contiguous, violations in late tiles of a
-    run; few workgroups, so that each takes many pieces."""
+    run; few workgroups, so that each takes many pieces.  Inputs of 128 tiles
+    take the gather pass with 16-chunk rounds, inputs of 32 tiles the one
+    without."""
     from test_gpu_parity import compare
-    wl = G.csr_runs_workload(11)
-    print(f"[case] csr runs schedule {schedule} wg_per_cu {wg}", flush=True)
+    wl = G.csr_runs_workload(11, log2_rows=log2_rows)
+    print(f"[case] csr runs schedule {schedule} wg_per_cu {wg} rows 2^{log2_rows}", flush=True)
     g = ckc.run_workload(ctx, wl, opts=ckc.launch_opts(schedule=schedule, wg_per_cu=wg))
     o = O.check(wl, nthreads=4)
     compare(g, o, what=f"csr runs schedule {schedule} wg {wg}")
