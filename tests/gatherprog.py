@@ -138,3 +138,74 @@ def csr_runs_workload(seed: int, log2_rows: int = 15, n_inputs: int = 4):
     return W.Workload("csr_runs", W.f3_program(32), np.array(launch, np.uint32), np.array(scalars, np.int64),
                       np.array([[tuple(a) for a in t] for t in tables], dtype=W.ALLOC_DTYPE),
                       np.arange(n_inputs, dtype=np.uint32), data, W.MODE_FULL)
+
+
+def long_gather_program(rng):
+    """Contiguous 32-bit gathers over long ranges: thread gid of the grid runs
+    j over [gid*L + s, gid*L + s + L) (scalar 0 = s, scalar 1 = L), so every
+    tile is contiguous and whole rounds of the contiguous form occur.  The body
+    has two to four entries of width 32: loads from D (int32, slot 0) or E
+    (int64, slot 1) and address-only accesses (slots 2, 3), indexed by the
+    counter or a loaded value (coefficient 1 or 2, constant or scalar offsets)
+    or by a constant."""
+    p = Program(n_scalars=3, n_slots=4)
+    gid = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), 32), p.special("tid.x"), 32)
+    L = p.scalar(1, 32)
+    start = p.add(p.mul(gid, L, 32), p.scalar(0, 32), 32)
+    with p.loop(start, p.add(start, L, 32), 1, w=32) as j:
+        vals, n_load = [j], 0
+        for _ in range(int(rng.integers(2, 5))):
+            src = vals[int(rng.integers(len(vals)))]
+            k = rng.random()
+            if k < 0.3:
+                idx = src
+            elif k < 0.55:
+                idx = p.add(src, p.const(int(rng.integers(-3, 4)), 32), 32)
+            elif k < 0.7:
+                idx = p.mul(src, p.const(2, 32), 32)
+            elif k < 0.85:
+                idx = p.add(src, p.scalar(2, 32), 32)
+            else:
+                idx = p.const(int(rng.integers(0, 40)), 32)
+            if n_load < 2 and rng.random() < 0.5:
+                slot, elem = (0, 4) if rng.random() < 0.6 else (1, 8)
+                vals.append(p.load(slot, idx, elem=elem, w=32))
+                n_load += 1
+            else:
+                p.access(int(rng.integers(2, 4)), idx, elem=int(rng.choice([4, 8])), w=32)
+    return p.to_bytes()
+
+
+def long_gather_workload(rng, ir, n_inputs=4, blocks=2, L_range=(40, 100)):
+    """Inputs of long_gather_program: `blocks` blocks of 256 threads, L drawn
+    from L_range, start offsets that may be negative, loaded allocations that
+    cover the whole counter range or end inside it, address-only allocations
+    of any size, freed or NULL."""
+    span = blocks * 256 * L_range[1] + 256
+    n = 2 * span + 64
+    D = rng.integers(-40, span + 40, size=n).astype(np.int32)
+    E = rng.integers(-40, span + 40, size=n).astype(np.int64)
+    launches, tables, scalars = [], [], []
+    for i in range(n_inputs):
+        launches.append([blocks, 1, 1, 256, 1, 1])
+        L = int(rng.integers(L_range[0], L_range[1] + 1))
+        s = int(rng.choice([0, 0, int(rng.integers(-50, 0)), int(rng.integers(1, 200))]))
+        scalars.append([s, L, int(rng.integers(-8, 9))])
+        used = blocks * 256 * L + max(s, 0) + 8
+
+        def loaded(elem):
+            return n * elem if rng.random() < 0.5 else int(rng.integers(used // 2, used)) * elem
+
+        def addr_only():
+            r = rng.random()
+            if r < 0.15:
+                return (0, 64, 0, 0)  # NULL
+            if r < 0.3:
+                return (LB + (2 << 36), 4 * used, 0, W.ALLOC_FREED)
+            return (LB + (2 << 36), int(rng.integers(0, 8 * used)), 0, 0)
+        tables.append([(LB, loaded(4), 1, 0), (LB + (1 << 36), loaded(8), 2, 0), addr_only(), addr_only()])
+    tabs = np.zeros((n_inputs, 4), W.ALLOC_DTYPE)
+    for i in range(n_inputs):
+        tabs[i] = [t + (0,) for t in tables[i]]
+    return W.Workload("long_gather", ir, np.asarray(launches, np.uint32), np.asarray(scalars, np.int64), tabs,
+                      np.arange(n_inputs, dtype=np.uint32), [D, E], W.MODE_FULL, (20, 12))

@@ -52,3 +52,26 @@ def test_gather_tile_runs(ctx, schedule, wg, log2_rows):
     o = O.check(wl, nthreads=4)
     compare(g, o, what=f"csr runs schedule {schedule} wg {wg}")
     assert (o["records"]["count"][:, 3] > 0).all() and (o["records"]["count"][:, 4] > 100).all()
+
+
+@pytest.mark.parametrize("big", [False, True])
+@pytest.mark.parametrize("seed", range(3))
+def test_long_gather_rounds(ctx, seed, big):
+    """Whole rounds of the contiguous form over random 32-bit gather bodies:
+    loads of int32 and int64 data by the counter (in bounds for the whole
+    round or not), by a loaded value or a constant, second loads, checks of
+    freed and NULL slots.  Inputs of 2 tiles take the gather kernel with
+    8-chunk rounds, inputs of 64 tiles the one with 16-chunk rounds; one
+    workgroup per compute unit gives each workgroup several pieces."""
+    from test_gpu_parity import compare
+    rng = np.random.default_rng(900 + seed + 10 * big)
+    for k in range(8):
+        ir = G.long_gather_program(rng)
+        info, _ = ckc.analyze(ir)
+        assert info["cls"] & ckc.CLS["GATHER"]
+        wl = G.long_gather_workload(rng, ir, blocks=64 if big else 2, L_range=(16, 24) if big else (40, 100))
+        o = O.check(wl, nthreads=4)
+        for wg in (1, 0):
+            print(f"[case] long gather seed {seed} big {big} prog {k} wg_per_cu {wg}", flush=True)
+            g = ckc.run_workload(ctx, wl, opts=ckc.launch_opts(wg_per_cu=wg))
+            compare(g, o, what=f"long gather seed {seed} big {big} prog {k} wg {wg} ir {ir.hex()}")
