@@ -272,12 +272,24 @@ def bench_served(args):
 
 
 def run_steps(ctx, dw, out, mode, steps):
-    """Runs `steps` checks; returns per-step (kernel timing list)."""
-    timings = []
+    """Runs `steps` checks back to back on the context's stream: each job is
+    queued before the previous one's stage timing is read, and every job's
+    results are copied to the device buffers behind it on the same stream
+    (CKC_ENQUEUE), so the device never waits for the host.  Returns the
+    per-step stage timings."""
+    timings, prev = [], None
+
+    def retire(job):
+        timings.append(ctx.timing(job))
+        ctx.read_device(job, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr(), enqueue=True)
+
     for _ in range(steps):
         job = ctx.check([dw.desc(mode=mode, dense=True)])
-        timings.append(ctx.timing(job))
-        ctx.read_device(job, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr())
+        if prev is not None:
+            retire(prev)
+        prev = job
+    if prev is not None:
+        retire(prev)
     return timings
 
 
