@@ -34,6 +34,25 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9
 # algorithmic work of one checked access on the affine path: form the index
 # (per-thread base + per-access offset) and one unsigned bound compare
 OPS_PER_ACCESS = 2
+# a group of LPB consecutive blocks inside one grid row whose bases form a
+# small-step progression is decided per access offset by its two end indices:
+# two adds, one max and one compare for the LPB accesses
+LPB = 16
+OPS_PER_LIN_GROUP_ENTRY = 4
+
+
+def trace_alg_ops(launch, acc_per_thread) -> float:
+    """Algorithmic int ops of the block-major trace evaluator over a
+    whole-grid batch of width-32 inputs whose block-x step is small (the
+    stencil: 16 per block): per thread and access offset, 4 ops for each group
+    of LPB blocks inside one grid row, 2 ops per block elsewhere."""
+    total = 0.0
+    for (gx, gy, gz, bx, by, bz), ne in zip(launch.astype(np.int64), acc_per_thread):
+        nsb = gx * gy * gz
+        b0 = np.arange(0, nsb, LPB, dtype=np.int64)
+        lin = int(np.count_nonzero(((b0 % gx) + LPB <= gx) & (b0 + LPB <= nsb)))
+        total += bx * by * bz * ne * (lin * OPS_PER_LIN_GROUP_ENTRY + (nsb - LPB * lin) * OPS_PER_ACCESS)
+    return total
 
 
 # sources of the trace evaluator (its counters stay valid while these are unchanged)
@@ -357,7 +376,9 @@ def main():
             "inputs_per_s": n / step_s,
             "kernel_ms": kernel_ms(kern),
         }
-        achieved = OPS_PER_ACCESS * accesses / (eval_ms * 1e-3)
+        lanes = st["lanes"].astype(np.float64)
+        per_thread = np.where(lanes > 0, st["accesses_checked"] / np.maximum(lanes, 1), 0)
+        achieved = trace_alg_ops(wl.launch, per_thread) / (eval_ms * 1e-3)
         # HBM bytes per launch from the committed counter runs
         traffic = recorded_traffic("eval_trace_kernel", TRACE_SOURCES)
         result["roofline"] = {

@@ -177,9 +177,24 @@ __device__ __forceinline__ bool entry_bad(uint64_t off, uint64_t bnd, const BT* 
   }
 }
 
-template <int W, bool DEADS, class BT>
-__device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, const BT* w, uint32_t g, uint32_t nvalid,
-                                             uint32_t t0) {
+// Width 32, LIN groups: the bases are an arithmetic progression
+// w[j] = w[0] + j*s (mod 2^32) over all LPB blocks with (LPB-1)*|s| < 2^31.
+// Then every index of the entry is in bounds iff both end indices are: if
+// both are below the bound (at most 2^31), the progression between them
+// spans less than 2^32 from a value below 2^31, so it does not wrap and
+// every term lies between the ends.  Exact, with two adds, one max and one
+// compare for the LPB indices.
+template <class BT>
+__device__ __forceinline__ bool entry_bad_lin(uint64_t off, uint64_t bnd, const BT* w) {
+  const uint32_t a = (uint32_t)w[0] + (uint32_t)off, b = (uint32_t)w[LPB - 1] + (uint32_t)off;
+  return (a > b ? a : b) >= (uint32_t)bnd;
+}
+
+// LIN: only w[0] and w[LPB-1] are formed by the caller; the rest are filled
+// from the step before the violation path needs them.
+template <int W, bool DEADS, bool LIN, class BT>
+__device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, BT* w, uint32_t g, uint32_t nvalid,
+                                             uint32_t t0, BT step) {
   constexpr uint32_t EB = W == 32 ? 8 : 4;  // entries per scalar-load batch
   const uint32_t ne = th->blk.ne;
   c_i64* h64 = trace_hot64(th);
@@ -206,12 +221,13 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, const BT* 
       uint64_t badm = 0;
       if (e + EB <= ne) {
 #pragma unroll
-        for (uint32_t k = 0; k < EB; k++) badm |= __ballot(entry_bad<W>(off[k], bnd[k], w));
+        for (uint32_t k = 0; k < EB; k++)
+          badm |= __ballot(LIN ? entry_bad_lin(off[k], bnd[k], w) : entry_bad<W>(off[k], bnd[k], w));
       } else {
         const uint32_t r = ne - e;
 #pragma unroll
         for (uint32_t k = 0; k < EB - 1; k++)
-          if (k < r) badm |= __ballot(entry_bad<W>(off[k], bnd[k], w));
+          if (k < r) badm |= __ballot(LIN ? entry_bad_lin(off[k], bnd[k], w) : entry_bad<W>(off[k], bnd[k], w));
       }
       if (badm) {
         hit = true;
@@ -219,6 +235,10 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, const BT* 
       }
     }
     if (!hit) return;
+  }
+  if (LIN) {
+#pragma unroll
+    for (uint32_t jj = 1; jj < LPB - 1; jj++) w[jj] = w[0] + (BT)jj * step;
   }
   // violation path: the remaining entries one by one
   for (; e < ne; e++) {
@@ -283,6 +303,7 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
     BT w[LPB];
     const uint32_t left = Bg->nsb - g * LPB;
     const uint32_t nvalid = left < LPB ? left : LPB;
+    bool lin = false;  // w is an arithmetic progression with a small step (width 32)
     if (FULL) {
       // the block part moves by d1 per block, by dy when x wraps and by dz
       // when y wraps as well
@@ -290,11 +311,20 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
       const BT d1 = (BT)Bg->d1;
       if (bx + LPB <= gx) {
         // the group stays in one row
+        if (W == 32 && nvalid == LPB && !Bg->any_dead) {
+          const uint32_t sd = (uint32_t)d1, ad = (int32_t)sd < 0 ? 0u - sd : sd;
+          lin = ad <= 0x7FFFFFFFu / (LPB - 1);
+        }
         BT v = tp + cur;
+        if (lin) {
+          w[0] = v;
+          w[LPB - 1] = v + (BT)(LPB - 1) * d1;
+        } else {
 #pragma unroll
-        for (uint32_t jj = 0; jj < LPB; jj++) {
-          w[jj] = v;
-          v += d1;
+          for (uint32_t jj = 0; jj < LPB; jj++) {
+            w[jj] = v;
+            v += d1;
+          }
         }
         bx += LPB;
         cur += (BT)LPB * d1;
@@ -352,8 +382,9 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
       for (uint32_t jj = 1; jj < LPB; jj++)
         if (jj >= nvalid) w[jj] = w[0];
     }
-    if (Bg->any_dead) trace_blocks<W, true>(S, tg, w, g, nvalid, t0);
-    else trace_blocks<W, false>(S, tg, w, g, nvalid, t0);
+    if (Bg->any_dead) trace_blocks<W, true, false>(S, tg, w, g, nvalid, t0, (BT)0);
+    else if (lin) trace_blocks<W, false, true>(S, tg, w, g, nvalid, t0, (BT)Bg->d1);
+    else trace_blocks<W, false, false>(S, tg, w, g, nvalid, t0, (BT)0);
   }
 }
 

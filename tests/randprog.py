@@ -137,3 +137,57 @@ def random_workload(rng, ir: bytes, n_inputs=4, n_scalars=2, n_slots=3, mode=W.M
             tables[i, s] = (base, size, 1 if s == 0 else 0, flags, 0)
     return W.Workload("rand", ir, launch, scalars, tables, np.arange(n_inputs, dtype=np.uint32), data,
                       mode, tuple(cap))
+
+
+# block-x coefficients around the largest step whose 16-block progressions
+# cannot wrap (0x7FFFFFFF // 15 = 143165576), and ordinary ones
+GRID_STEPS = [1, 16, 256, -1, -16, 4096, 143165576, 143165577, -143165576, -143165577, 1 << 30, -(1 << 30)]
+
+
+def affine_grid_program(rng, k_bx: int, n_acc: int = 4) -> bytes:
+    """Width-32 accesses sharing one linear part in the thread and block
+    coordinates (k_bx per block along x, random small coefficients
+    elsewhere, scalar 0 added) at different constant offsets: the shape the
+    block-major trace evaluator takes, over grids wide enough for whole
+    groups of 16 blocks in one row."""
+    p = Program(n_scalars=1, n_slots=2)
+    tx, bx, by = p.special("tid.x"), p.special("bid.x"), p.special("bid.y")
+    base = p.add(p.mul(bx, p.const(k_bx, 32), 32), p.mul(tx, p.const(int(rng.choice([1, 2, -1])), 32), 32), 32)
+    base = p.add(base, p.mul(by, p.const(int(rng.choice([0, 1000, 5000, -3000])), 32), 32), 32)
+    base = p.add(base, p.scalar(0, 32), 32)
+    for _ in range(n_acc):
+        p.access(int(rng.integers(2)), p.add(base, p.const(int(rng.integers(-70, 70)), 32), 32), elem=4)
+    return p.to_bytes()
+
+
+def affine_grid_workload(rng, ir: bytes, k_bx: int, n_inputs: int = 6) -> W.Workload:
+    """Grids of 16 to 70 blocks along x (1 or 2 rows) of 64 threads; scalar 0
+    and the allocation sizes put the bounds anywhere in the index range, so
+    some groups are clean, some cross a bound at one end, and inputs with a
+    freed or NULL slot take the general path."""
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    scalars = np.zeros((n_inputs, 1), np.int64)
+    tables = np.zeros((n_inputs, 2), W.ALLOC_DTYPE)
+    for i in range(n_inputs):
+        gx, gy = int(rng.integers(16, 71)), int(rng.integers(1, 3))
+        launch[i] = [gx, gy, 1, 64, 1, 1]
+        span = abs(k_bx) * gx + 64 * 2 + 6000 * gy
+        s0 = int(rng.choice([0, 100, -50, abs(k_bx) * gx // 2 if k_bx < 0 else 0, (1 << 31) - 10]))
+        scalars[i, 0] = s0 if s0 < (1 << 31) else s0 - (1 << 32)
+        for s in range(2):
+            u = rng.random()
+            if u < 0.5:
+                size = (1 << 31) - 1  # every non-negative 32-bit index
+            elif u < 0.8:
+                size = int(rng.integers(1, min(span, 1 << 31)))
+            else:
+                size = int(rng.integers(1, 5000))
+            base, flags = W.LOGICAL_BASE + (s << 36), 0
+            u = rng.random()
+            if s == 1 and u < 0.1:
+                base = 0
+            elif s == 1 and u < 0.2:
+                flags = W.ALLOC_FREED
+            tables[i, s] = (base, 4 * size, 0, flags, 0)
+    return W.Workload("affine_grid", ir, launch, scalars, tables, np.arange(n_inputs, dtype=np.uint32), [],
+                      W.MODE_FULL, (4, 3))

@@ -227,3 +227,19 @@ def test_config3_full_sampled(ctx):
     o = O.check(wl.subset([0, 7]), nthreads=2)
     sub = dict(records=g["records"][[0, 7]], maps=g["maps"][[0, 7]], status=g["status"][[0, 7]])
     compare(sub, o, what="config3 sample")
+
+
+@pytest.mark.parametrize("k_bx", R.GRID_STEPS)
+def test_affine_grid_groups(ctx, k_bx):
+    """Block-major trace evaluator over grids of 16 to 70 blocks per row: whole
+    groups of 16 blocks in one row whose block bases step by k_bx (the
+    two-end test applies while 15*|k_bx| < 2^31, the largest such step and
+    the next are both here), groups across rows, a short last group, bounds
+    anywhere in the index range, freed and NULL slots; every record, map and
+    status against the oracle."""
+    rng = np.random.default_rng(4000 + R.GRID_STEPS.index(k_bx))
+    for k in range(3):
+        ir = R.affine_grid_program(rng, k_bx)
+        wl = R.affine_grid_workload(rng, ir, k_bx)
+        g, o = both(ctx, wl)
+        compare(g, o, what=f"affine grid k_bx {k_bx} prog {k} ir {ir.hex()}")
