@@ -8,8 +8,10 @@
 //              (affine forms of every index, evaluated once per input);
 //   scan       tile offsets of the three evaluators over the inputs;
 //   eval_trace, eval_trace_lanes
-//              persistent: per checked access one add and one unsigned compare
-//              against the bound (block-major wavefront jobs, or lane tiles);
+//              persistent: per checked access at most one add and one
+//              unsigned compare against the bound (block-major wavefront
+//              jobs, where 16 blocks in one grid row share one exact test of
+//              their two end indices, or lane tiles);
 //   eval_generic
 //              persistent: a wavefront-uniform interpreter of the lowered
 //              bytecode, one lane per thread; the program's expandable loop is
