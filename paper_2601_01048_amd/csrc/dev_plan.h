@@ -284,11 +284,12 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
     const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
     if (path == 0) {
       if (in.mode != CKC_REP_CORNERS && bs % 64u == 0 && ((const dtrace_head*)in.trace)->n_classes == 1) {
-        // block-major jobs: (64-thread slice position, NGJ groups of LPB set blocks)
+        // block-major jobs: (64-thread slice position, ngj groups of LPB set blocks)
         const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
                                                  : bset_size(in.launch);
         const uint64_t ngroups = (nsb + LPB - 1) / LPB;
-        const uint64_t jobs = (uint64_t)(bs / 64u) * ((ngroups + NGJ - 1) / NGJ);
+        const uint32_t ngj = in.mode == CKC_FULL ? NGJ_FULL : NGJ_SET;
+        const uint64_t jobs = (uint64_t)(bs / 64u) * ((ngroups + ngj - 1) / ngj);
         tiles = (jobs + 3) / 4;
         path = PATH_BLOCKS;
         dtrace_head* th = (dtrace_head*)in.trace;
@@ -296,6 +297,7 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
         for (int q = 0; q < 6; q++) B.L[q] = in.launch[q];
         const uint32_t L0 = in.launch[0], L1 = in.launch[1], L3 = in.launch[3], L4 = in.launch[4];
         B.mode = in.mode;
+        B.ngj = ngj;
         B.bs = bs;
         B.gxy = L0 * L1;
         B.bxy = L3 * L4;

@@ -264,7 +264,7 @@ struct TrIn {
 };
 
 // One block-major wavefront job: slice position o (64 threads) of the groups
-// gs*NGJ .. gs*NGJ+NGJ-1 (LPB set blocks each).  The thread part of the index
+// gs*ngj .. gs*ngj+ngj-1 (LPB set blocks each; ngj from the plan).  The thread part of the index
 // base is formed once per job; in the whole-grid mode the block coordinates
 // are walked from group to group, and a group that stays inside one grid row
 // forms its block parts by adding the x coefficient.
@@ -283,8 +283,9 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
   if (k1 == 1) tp += (BT)ty; else if (k1 != 0) tp += (BT)k1 * (BT)ty;
   if (k2 == 1) tp += (BT)tz; else if (k2 != 0) tp += (BT)k2 * (BT)tz;
   const uint32_t t0 = o * 64u;
-  uint32_t g = gs * NGJ;
-  const uint32_t gend = g + NGJ < B->ngroups ? g + NGJ : B->ngroups;
+  const uint32_t ngj = B->ngj;
+  uint32_t g = gs * ngj;
+  const uint32_t gend = g + ngj < B->ngroups ? g + ngj : B->ngroups;
   // whole grid: coordinates and block part of the group's first block
   uint32_t bx = 0, by = 0, bz = 0;
   BT cur = 0;
@@ -477,7 +478,7 @@ __global__ void __launch_bounds__(TILE, 7) eval_trace_kernel(KArgs a) {
     const uint64_t job = (t - tb) * 4 + wv;
     const uint64_t gs = job < (1ull << 32) ? (uint64_t)udiv((uint32_t)job, UDiv{B->m_spb, B->s_spb}) : job / B->spb;
     const uint32_t o = (uint32_t)(job - gs * B->spb);
-    if (gs * NGJ >= B->ngroups) continue;  // past the last group (whole wavefront)
+    if (gs * B->ngj >= B->ngroups) continue;  // past the last group (whole wavefront)
     const bool full = B->mode == CKC_FULL;
     if (B->w == 32) {
       if (full) block_job<32, true>(S, tj, (uint32_t)gs, o);

@@ -93,7 +93,10 @@ enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };
 
 constexpr int MAX_SCALARS = 16;
 constexpr uint32_t LPB = 16;  // blocks per group of the block-major trace path
-constexpr uint32_t NGJ = 4;   // groups per wavefront job of the block-major trace path
+// groups per wavefront job of the block-major trace path: the whole grid
+// (jobs of many groups amortize the job's set-up), and a thread set of
+// boundary blocks (fewer groups per input: more jobs to spread)
+constexpr uint32_t NGJ_FULL = 16, NGJ_SET = 4;
 
 // Trace of a uniform-control program for one input: every thread performs the
 // same access sequence; each access index is base[class](thread) + off.
@@ -116,7 +119,7 @@ struct dblk {
   uint32_t L[6];        // gx gy gz bx by bz
   uint32_t mode, bs, gxy, bxy, nsb, ngroups, spb, ne;
   uint32_t any_dead, w, Lsum, n_acc;
-  uint32_t m_gx, s_gx, m_gxy, s_gxy, m_bx, s_bx, m_bxy, s_bxy, m_spb, s_spb, pad[4];
+  uint32_t m_gx, s_gx, m_gxy, s_gxy, m_bx, s_bx, m_bxy, s_bxy, m_spb, s_spb, ngj, pad[3];
   int64_t k[6];         // coefficients of the one class: tid.xyz, bid.xyz
   uint64_t d1, dy, dz;  // block-part steps: next x, x wrap, x and y wrap
   uint64_t rec;         // the input's records
