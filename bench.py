@@ -34,24 +34,43 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9
 # algorithmic work of one checked access on the affine path: form the index
 # (per-thread base + per-access offset) and one unsigned bound compare
 OPS_PER_ACCESS = 2
-# a group of LPB consecutive blocks inside one grid row whose bases form a
-# small-step progression is decided per access offset by its two end indices:
-# two adds, one max and one compare for the LPB accesses
+# consecutive blocks inside one grid row whose bases form a small-step
+# progression are decided per access offset by the two end indices of the
+# run: two adds, one max and one compare
 LPB = 16
 OPS_PER_LIN_GROUP_ENTRY = 4
+
+
+# groups of LPB blocks per wavefront job of the whole grid
+NGJ_FULL = 16
 
 
 def trace_alg_ops(launch, acc_per_thread) -> float:
     """Algorithmic int ops of the block-major trace evaluator over a
     whole-grid batch of width-32 inputs whose block-x step is small (the
-    stencil: 16 per block): per thread and access offset, 4 ops for each group
-    of LPB blocks inside one grid row, 2 ops per block elsewhere."""
+    stencil: 16 per block), walking each job's groups as the kernel does: the
+    whole groups of a job that lie in one grid row are one progression, and
+    each access offset costs 4 ops per thread for the run (2 adds, 1 max,
+    1 compare of its two end indices), as does a lone whole group inside a
+    row; a group across rows or the short last group costs 2 ops per block."""
     total = 0.0
     for (gx, gy, gz, bx, by, bz), ne in zip(launch.astype(np.int64), acc_per_thread):
-        nsb = gx * gy * gz
-        b0 = np.arange(0, nsb, LPB, dtype=np.int64)
-        lin = int(np.count_nonzero(((b0 % gx) + LPB <= gx) & (b0 + LPB <= nsb)))
-        total += bx * by * bz * ne * (lin * OPS_PER_LIN_GROUP_ENTRY + (nsb - LPB * lin) * OPS_PER_ACCESS)
+        nsb = int(gx * gy * gz)
+        ngroups, full = (nsb + LPB - 1) // LPB, nsb // LPB
+        tests = 0  # two-end tests per thread and offset
+        blocks = 0  # blocks checked one by one
+        for j0 in range(0, ngroups, NGJ_FULL):
+            g, gend = j0, min(j0 + NGJ_FULL, ngroups)
+            while g < gend:
+                x = (g * LPB) % gx
+                k = min((gx - x) // LPB, min(gend, full) - g) if g < min(gend, full) else 0
+                if k >= 1:
+                    tests += 1
+                    g += k
+                else:
+                    blocks += min(LPB, nsb - g * LPB)
+                    g += 1
+        total += bx * by * bz * ne * (tests * OPS_PER_LIN_GROUP_ENTRY + blocks * OPS_PER_ACCESS)
     return total
 
 

@@ -192,6 +192,33 @@ __device__ __forceinline__ bool entry_bad_lin(uint64_t off, uint64_t bnd, const 
 
 // LIN: only w[0] and w[LPB-1] are formed by the caller; the rest are filled
 // from the step before the violation path needs them.
+// Width 32: true if some lane has an access offset out of bounds somewhere in
+// the progression from v0 to v1 (bases of consecutive blocks of one row, the
+// span below 2^31, as for entry_bad_lin); one test per batch of 8 offsets.
+template <class BT>
+__device__ __forceinline__ bool span_bad(c_head* th, BT v0, BT v1) {
+  const uint32_t ne = th->blk.ne;
+  c_u32* h32 = trace_hot32(th);
+  for (uint32_t e = 0; e < ne; e += 8) {
+    uint32_t off[8], bnd[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; k++) {
+      off[k] = h32[2 * (e + k)];
+      bnd[k] = h32[2 * (e + k) + 1];
+    }
+    uint64_t badm = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; k++) {
+      if (e + k < ne) {
+        const uint32_t a = (uint32_t)v0 + off[k], b = (uint32_t)v1 + off[k];
+        badm |= __ballot((a > b ? a : b) >= bnd[k]);
+      }
+    }
+    if (badm) return true;
+  }
+  return false;
+}
+
 template <int W, bool DEADS, bool LIN, class BT>
 __device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, BT* w, uint32_t g, uint32_t nvalid,
                                              uint32_t t0, BT step) {
@@ -301,6 +328,37 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
   for (; g < gend; g++) {
     c_head* tg = fresh(th);
     c_blk* Bg = &tg->blk;
+    if (FULL && W == 32 && !Bg->any_dead) {
+      // the whole groups of the job from g on that lie in the current row
+      // form one progression of block bases: when its span stays below 2^31
+      // and no offset is out of bounds at either end, they are all clean
+      const uint32_t gx = Bg->L[0], full_groups = Bg->nsb / LPB;
+      uint32_t k = (gx - bx) / LPB;
+      const uint32_t glim = gend < full_groups ? gend : full_groups;
+      k = g < glim ? (k < glim - g ? k : glim - g) : 0u;
+      const uint32_t sd = (uint32_t)Bg->d1, ad = (int32_t)sd < 0 ? 0u - sd : sd;
+      if (k >= 2 && (uint64_t)ad * (LPB * k - 1) <= 0x7FFFFFFFull) {
+        const BT d1 = (BT)Bg->d1;
+        const BT v0 = tp + cur;
+        if (!span_bad(tg, v0, v0 + (BT)(LPB * k - 1) * d1)) {
+          bx += LPB * k;
+          cur += (BT)(LPB * k) * d1;
+          if (bx == gx) {
+            bx = 0;
+            if (++by == Bg->L[1]) {
+              by = 0;
+              ++bz;
+              cur += (BT)Bg->dz;
+            } else {
+              cur += (BT)Bg->dy;
+            }
+            cur -= d1;
+          }
+          g += k - 1;
+          continue;
+        }
+      }
+    }
     BT w[LPB];
     const uint32_t left = Bg->nsb - g * LPB;
     const uint32_t nvalid = left < LPB ? left : LPB;
