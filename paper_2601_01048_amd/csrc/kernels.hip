@@ -10,8 +10,8 @@
 //   eval_trace, eval_trace_lanes
 //              persistent: per checked access at most one add and one
 //              unsigned compare against the bound (block-major wavefront
-//              jobs, where 16 blocks in one grid row share one exact test of
-//              their two end indices, or lane tiles);
+//              jobs, where the blocks a job has in one grid row share one
+//              exact test of their two end indices, or lane tiles);
 //   eval_generic
 //              persistent: a wavefront-uniform interpreter of the lowered
 //              bytecode, one lane per thread; the program's expandable loop is
