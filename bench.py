@@ -48,11 +48,12 @@ NGJ_FULL = 16
 def trace_alg_ops(launch, acc_per_thread) -> float:
     """Algorithmic int ops of the block-major trace evaluator over a
     whole-grid batch of width-32 inputs whose block-x step is small (the
-    stencil: 16 per block), walking each job's groups as the kernel does: the
-    whole groups of a job that lie in one grid row are one progression, and
-    each access offset costs 4 ops per thread for the run (2 adds, 1 max,
-    1 compare of its two end indices), as does a lone whole group inside a
-    row; a group across rows or the short last group costs 2 ops per block."""
+    stencil: 16 per block), walking each job as the kernel does: a job whose
+    blocks fall into at most 4 row segments is decided by the two end indices
+    of each segment, 4 ops per thread, offset and segment (2 adds, 1 max,
+    1 compare); otherwise the whole groups it has in one grid row form one
+    such run, as does a lone whole group inside a row, and a group across rows
+    or the short last group costs 2 ops per block."""
     total = 0.0
     for (gx, gy, gz, bx, by, bz), ne in zip(launch.astype(np.int64), acc_per_thread):
         nsb = int(gx * gy * gz)
@@ -61,6 +62,11 @@ def trace_alg_ops(launch, acc_per_thread) -> float:
         blocks = 0  # blocks checked one by one
         for j0 in range(0, ngroups, NGJ_FULL):
             g, gend = j0, min(j0 + NGJ_FULL, ngroups)
+            b0, nb = g * LPB, min(gend * LPB, nsb) - g * LPB
+            nseg = (b0 % gx + nb + gx - 1) // gx
+            if nseg <= 4:
+                tests += nseg
+                continue
             while g < gend:
                 x = (g * LPB) % gx
                 k = min((gx - x) // LPB, min(gend, full) - g) if g < min(gend, full) else 0

@@ -219,6 +219,39 @@ __device__ __forceinline__ bool span_bad(c_head* th, BT v0, BT v1) {
   return false;
 }
 
+// Width 32: as span_bad over up to 4 progressions at once (the row segments
+// of a job), nseg of them in use.
+template <class BT>
+__device__ __forceinline__ bool segs_bad(c_head* th, const BT* v0, const BT* v1, uint32_t nseg) {
+  const uint32_t ne = th->blk.ne;
+  c_u32* h32 = trace_hot32(th);
+  for (uint32_t e = 0; e < ne; e += 8) {
+    uint32_t off[8], bnd[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; k++) {
+      off[k] = h32[2 * (e + k)];
+      bnd[k] = h32[2 * (e + k) + 1];
+    }
+    uint64_t badm = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; k++) {
+      if (e + k < ne) {
+        bool b = false;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; q++) {
+          if (q < nseg) {
+            const uint32_t a = (uint32_t)v0[q] + off[k], c = (uint32_t)v1[q] + off[k];
+            b |= (a > c ? a : c) >= bnd[k];
+          }
+        }
+        badm |= __ballot(b);
+      }
+    }
+    if (badm) return true;
+  }
+  return false;
+}
+
 template <int W, bool DEADS, bool LIN, class BT>
 __device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, BT* w, uint32_t g, uint32_t nvalid,
                                              uint32_t t0, BT step) {
@@ -323,6 +356,46 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
     by = udiv(brem, UDiv{B->m_gx, B->s_gx});
     bx = brem - by * B->L[0];
     cur = (BT)B->k[3] * (BT)bx + (BT)B->k[4] * (BT)by + (BT)B->k[5] * (BT)bz;
+    if (W == 32 && !B->any_dead) {
+      // the job's blocks split at row ends into at most 4 row segments, each
+      // a progression of block bases: when every segment's span stays below
+      // 2^31 and no offset is out of bounds at the ends of any segment, the
+      // whole job is clean
+      const uint32_t gx = B->L[0], gy = B->L[1];
+      const uint32_t bend = gend * LPB < B->nsb ? gend * LPB : B->nsb;
+      const uint32_t sd = (uint32_t)B->d1, ad = (int32_t)sd < 0 ? 0u - sd : sd;
+      const BT d1 = (BT)B->d1, dy = (BT)B->dy, dz = (BT)B->dz;
+      uint32_t left = bend - g * LPB, sx = bx, sy = by, nseg = 0;
+      BT sc = cur, v0[4], v1[4];
+      bool ok = true;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++) {
+        if (left != 0 && ok) {
+          const uint32_t len = gx - sx < left ? gx - sx : left;
+          if ((uint64_t)ad * (len - 1) > 0x7FFFFFFFull) {
+            ok = false;
+          } else {
+            v0[q] = tp + sc;
+            v1[q] = v0[q] + (BT)(len - 1) * d1;
+            nseg = q + 1;
+            left -= len;
+            sx += len;
+            sc += (BT)len * d1;
+            if (sx == gx) {
+              sx = 0;
+              if (++sy == gy) {
+                sy = 0;
+                sc += dz;
+              } else {
+                sc += dy;
+              }
+              sc -= d1;
+            }
+          }
+        }
+      }
+      if (ok && left == 0 && !segs_bad(th, v0, v1, nseg)) return;
+    }
   }
 #pragma unroll 1
   for (; g < gend; g++) {
