@@ -97,6 +97,7 @@ typedef struct {
   int max_depth;
   uint8_t* load_slot; /* slot used by some LOAD */
   int64_t* const_copy;
+  uint8_t* in_slice;  /* [n_instr]: an index, IF predicate or loop bound depends on it */
 } or_prog;
 
 static uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
@@ -104,7 +105,7 @@ static uint32_t rd32(const uint8_t* p) { return (uint32_t)rd16(p) | ((uint32_t)r
 static int64_t rd64(const uint8_t* p) { return (int64_t)((uint64_t)rd32(p) | ((uint64_t)rd32(p + 4) << 32)); }
 
 static void prog_free(or_prog* P) {
-  free(P->site_ids); free(P->ins); free(P->load_slot); free(P->const_copy);
+  free(P->site_ids); free(P->ins); free(P->load_slot); free(P->const_copy); free(P->in_slice);
   memset(P, 0, sizeof *P);
 }
 
@@ -224,6 +225,28 @@ static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
   }
   if (sp != 0) goto out;
   for (int a = 0; a < P->n_accesses; a++) if (!acc_used[a]) goto out;
+  /* The slice of the indices, IF predicates and loop bounds: the accesses
+   * and control instructions themselves and, walking backwards (every
+   * definition precedes its uses), every instruction whose result a slice
+   * instruction reads. */
+  {
+    uint8_t* need = (uint8_t*)calloc(P->n_regs + 1, 1);
+    P->in_slice = (uint8_t*)calloc(P->n_instr + 1, 1);
+    for (int i = P->n_instr - 1; i >= 0; i--) {
+      const or_ins* I = &P->ins[i];
+      int op = I->op;
+      int root = op == O_ACCESS || op == O_LOAD || op == O_IF || op == O_LOOP;
+      int defines = !(op == O_ACCESS || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP);
+      int keep = root || (defines && op != O_LOOP && I->dst < P->n_regs && need[I->dst]);
+      if (!keep) continue;
+      P->in_slice[i] = 1;
+      if (op == O_CONST || op == O_SCALAR || op == O_SPECIAL) continue;
+      need[I->a] = 1;
+      if (op == O_LOOP || op == O_SELECT) { need[I->b] = 1; need[I->c] = 1; }
+      else if (is_binary(op)) need[I->b] = 1;
+    }
+    free(need);
+  }
   rc = E_OK;
 out:
 #undef USE
@@ -315,9 +338,56 @@ typedef struct {
   uint64_t* cnt;   /* this input's site counters [n_sites] */
   or_status* st;
   uint8_t* acc_seen; /* [n_accesses]: executed at least once in this input */
+  /* vertex run (rep-exact flag): no records, visits or status updates; wraps
+   * of slice instructions and the control decisions are observed instead */
+  int dry;
+  int wrapped;        /* some slice operation wrapped */
+  int abort_run;      /* control path differs from vertex 0, or budget exceeded */
+  uint64_t budget;    /* IF and LOOP executions plus loop iterations so far */
+  uint64_t* dec;      /* decisions of vertex 0 (IF outcome, LOOP trip count) */
+  size_t ndec, pos;
+  int recording;
+  uint64_t dummy_faults;
 } thr;
 
-static void visit(thr* t, uint16_t s) { if (s != NOSITE) t->cnt[s]++; }
+#define VERTEX_BUDGET 65536u
+
+/* One control decision of a vertex run: vertex 0 records it, the others must
+ * repeat it; the budget counts it. */
+static void decide(thr* t, uint64_t v) {
+  if (++t->budget > VERTEX_BUDGET) { t->abort_run = 1; t->stopped = 1; return; }
+  if (t->recording) { t->dec[t->ndec++] = v; return; }
+  if (t->pos >= t->ndec || t->dec[t->pos] != v) { t->abort_run = 1; t->stopped = 1; return; }
+  t->pos++;
+}
+
+/* Exact-integer checks of the vertex run.  fits(v, w): the signed value v is
+ * representable at width w. */
+static int fits(__int128 v, int w) {
+  __int128 lo = w == 32 ? -((__int128)1 << 31) : -((__int128)1 << 63);
+  __int128 hi = w == 32 ? ((__int128)1 << 31) : ((__int128)1 << 63);
+  return v >= lo && v < hi;
+}
+/* A register read at width 32 must already hold an int32 value. */
+static int read32_ok(uint64_t c) { return fits((__int128)(int64_t)c, 32); }
+
+static void check_wrap(thr* t, const or_ins* I, uint64_t x, uint64_t y) {
+  int w = I->w, op = I->op;
+  if (w == 32 && (!read32_ok(x) || (is_binary(op) && !read32_ok(y)))) { t->wrapped = 1; return; }
+  int64_t sx = (int64_t)narrow(x, w), sy = (int64_t)narrow(y, w);
+  __int128 r;
+  switch (op) {
+    case O_ADD: r = (__int128)sx + sy; break;
+    case O_SUB: r = (__int128)sx - sy; break;
+    case O_MUL: r = (__int128)sx * sy; break;
+    case O_SHL: r = (__int128)sx * ((__int128)1 << ((uint64_t)sy & (uint64_t)(w - 1))); break;
+    case O_DIVS: r = (sy == -1 && sx == (w == 32 ? (int64_t)INT32_MIN : INT64_MIN)) ? -(__int128)sx : 0; break;
+    default: return;
+  }
+  if (!fits(r, w)) t->wrapped = 1;
+}
+
+static void visit(thr* t, uint16_t s) { if (s != NOSITE && !t->dry) t->cnt[s]++; }
 
 /* Check one access (the allocation-table check of an ASan-style detector). */
 static uint32_t check_kind(const or_alloc* a, int64_t idx, unsigned log2e) {
@@ -330,6 +400,7 @@ static uint32_t check_kind(const or_alloc* a, int64_t idx, unsigned log2e) {
 }
 
 static void record(thr* t, int acc, uint32_t kind, int64_t idx) {
+  if (t->dry) return;
   or_record* R = &t->rec[acc];
   uint64_t key = (t->gtid << (t->L1 + t->L2)) | (t->iter[0] << t->L2) | t->iter[1];
   R->count++;
@@ -349,7 +420,17 @@ static void exec_one_loop(thr* t, int pc) {
   int d = I->depth; /* 0 for a depth-1 loop */
   uint64_t cap = t->cap[d];
   uint64_t run = n < cap ? n : cap;
+  if (t->dry) {
+    if (w == 32 && (!read32_ok(t->regs[I->a]) || !read32_ok(t->regs[I->b]) || !read32_ok(t->regs[I->c])))
+      t->wrapped = 1;
+    decide(t, n);
+    if (t->stopped) return;
+  }
   for (uint64_t k = 0; k < run && !t->stopped; k++) {
+    if (t->dry) {
+      if (!fits((__int128)s + (__int128)k * st, w)) t->wrapped = 1;
+      if (++t->budget > VERTEX_BUDGET) { t->abort_run = 1; t->stopped = 1; break; }
+    }
     t->regs[I->dst] = narrow((uint64_t)s + k * (uint64_t)st, w);
     t->iter[d] = k;
     visit(t, I->s0);
@@ -357,7 +438,7 @@ static void exec_one_loop(thr* t, int pc) {
   }
   t->iter[d] = 0;
   if (t->stopped) return;
-  if (n > cap) { t->stopped = 1; t->st->hang_lanes++; return; }
+  if (n > cap) { t->stopped = 1; if (!t->dry) t->st->hang_lanes++; return; }
   visit(t, I->s1);
 }
 
@@ -379,17 +460,31 @@ static void exec_range(thr* t, int pc, int end) {
         R[I->dst] = (uint64_t)v;
         break;
       }
-      case O_SELECT: R[I->dst] = narrow(R[I->a] != 0 ? R[I->b] : R[I->c], I->w); break;
-      case O_SEXT: case O_TRUNC: R[I->dst] = narrow(R[I->a], 32); break;
-      case O_ZEXT: R[I->dst] = R[I->a] & 0xFFFFFFFFull; break;
+      case O_SELECT: {
+        uint64_t v = R[I->a] != 0 ? R[I->b] : R[I->c];
+        if (t->dry && P->in_slice[pc] && I->w == 32 && !read32_ok(v)) t->wrapped = 1;
+        R[I->dst] = narrow(v, I->w);
+        break;
+      }
+      case O_SEXT: case O_TRUNC:
+        if (t->dry && P->in_slice[pc] && !read32_ok(R[I->a])) t->wrapped = 1;
+        R[I->dst] = narrow(R[I->a], 32);
+        break;
+      case O_ZEXT:
+        if (t->dry && P->in_slice[pc] && !(read32_ok(R[I->a]) && (int64_t)R[I->a] >= 0)) t->wrapped = 1;
+        R[I->dst] = R[I->a] & 0xFFFFFFFFull;
+        break;
       case O_ACCESS:
       case O_LOAD: {
+        if (t->dry && I->w == 32 && !read32_ok(R[I->a])) t->wrapped = 1;
         int64_t idx = (int64_t)narrow(R[I->a], I->w);
         unsigned log2e = I->op == O_ACCESS ? (I->d & 3u) : I->d;
         const or_alloc* A = &t->table[I->c];
         uint32_t kind = check_kind(A, idx, log2e);
-        t->st->accesses_checked++;
-        t->acc_seen[I->b] = 1;
+        if (!t->dry) {
+          t->st->accesses_checked++;
+          t->acc_seen[I->b] = 1;
+        }
         visit(t, I->s0);
         if (kind) record(t, I->b, kind, idx);
         if (I->op == O_LOAD) {
@@ -404,6 +499,10 @@ static void exec_range(thr* t, int pc, int end) {
       }
       case O_IF: {
         int taken = R[I->a] != 0;
+        if (t->dry) {
+          decide(t, (uint64_t)taken);
+          if (t->stopped) return;
+        }
         if (taken) {
           visit(t, I->s0);
           exec_range(t, pc + 1, I->alt >= 0 ? I->alt : I->end);
@@ -421,7 +520,8 @@ static void exec_range(thr* t, int pc, int end) {
       case O_ELSE: case O_ENDIF: case O_ENDLOOP:
         break; /* reached only as range ends */
       default:
-        R[I->dst] = alu(I->op, I->w, R[I->a], R[I->b], &t->st->arith_faults);
+        if (t->dry && P->in_slice[pc]) check_wrap(t, I, R[I->a], R[I->b]);
+        R[I->dst] = alu(I->op, I->w, R[I->a], R[I->b], t->dry ? &t->dummy_faults : &t->st->arith_faults);
         break;
     }
     pc++;
@@ -442,7 +542,7 @@ static void run_thread(thr* t, uint64_t blin, uint32_t tlin) {
   memset(t->regs, 0, sizeof(uint64_t) * (t->P->n_regs + 1));
   t->iter[0] = t->iter[1] = 0;
   t->stopped = 0;
-  t->st->lanes++;
+  if (!t->dry) t->st->lanes++;
   exec_range(t, 0, t->P->n_instr);
 }
 
@@ -456,6 +556,60 @@ static int is_boundary_block(const uint32_t* L, uint64_t blin) {
   uint32_t x = (uint32_t)(blin % gx), y = (uint32_t)((blin / gx) % gy), z = (uint32_t)(blin / ((uint64_t)gx * gy));
   return (gx >= 2 && (x == 0 || x == gx - 1)) || (gy >= 2 && (y == 0 || y == gy - 1)) ||
          (gz >= 2 && (z == 0 || z == gz - 1));
+}
+
+/* Vertices of the box of block and thread coordinates: per dimension the
+ * first and the last coordinate (one when the extent is 1). */
+static int n_vertices(const uint32_t* L) {
+  int tot = 1;
+  for (int d = 0; d < 6; d++) tot *= L[d] == 1 ? 1 : 2;
+  return tot;
+}
+/* Vertex v in global-thread-id order: block coordinates outermost (z, y, x),
+ * then thread coordinates (z, y, x). */
+static void vertex(const uint32_t* L, int tot, int v, uint64_t* blin, uint32_t* tlin) {
+  uint32_t c[6];
+  int rem = v, div = tot;
+  const int order[6] = {2, 1, 0, 5, 4, 3}; /* bz by bx tz ty tx (gx..gz = 0..2, bx..bz = 3..5) */
+  for (int o = 0; o < 6; o++) {
+    int d = order[o];
+    int cnt = L[d] == 1 ? 1 : 2;
+    div /= cnt;
+    int digit = rem / div;
+    rem %= div;
+    c[d] = digit ? L[d] - 1 : 0;
+  }
+  *blin = c[0] + (uint64_t)L[0] * (c[1] + (uint64_t)L[1] * c[2]);
+  *tlin = c[3] + L[3] * (c[4] + L[4] * c[5]);
+}
+
+/* The rep-exact flag of a representative mode (the reading of the Theorem's
+ * exact-integer premise, Section 5.1.1): run every vertex thread without
+ * recording anything; the flag holds when they all take vertex 0's control
+ * decisions within the budget and no slice operation wraps at any of them.
+ * Then every intermediate of an affine index is affine over the whole box in
+ * exact integers (an affine function on a box is extremal at a vertex), so no
+ * interior thread wraps either. */
+static uint32_t vertex_exact(thr* t) {
+  const uint32_t* L = t->launch;
+  if ((uint64_t)L[0] * L[1] * L[2] == 0 || (uint64_t)L[3] * L[4] * L[5] == 0) return 0;
+  int tot = n_vertices(L);
+  t->dry = 1; t->wrapped = 0; t->abort_run = 0;
+  t->dec = (uint64_t*)malloc(sizeof(uint64_t) * (VERTEX_BUDGET + 1));
+  t->ndec = 0;
+  for (int v = 0; v < tot && !t->abort_run && !t->wrapped; v++) {
+    uint64_t blin; uint32_t tlin;
+    vertex(L, tot, v, &blin, &tlin);
+    t->recording = v == 0;
+    t->pos = 0;
+    t->budget = 0;
+    run_thread(t, blin, tlin);
+    if (v > 0 && t->pos != t->ndec) t->abort_run = 1;
+  }
+  uint32_t ok = !t->abort_run && !t->wrapped;
+  free(t->dec); t->dec = NULL;
+  t->dry = 0;
+  return ok;
 }
 
 /* One input under the chosen thread set. */
@@ -473,30 +627,10 @@ static void run_input(thr* t, uint32_t mode) {
     /* The PREX Theorem's representative threads {first, last thread} x
      * {first, last block} (Section 5.1.1), taken per dimension: every vertex
      * of the box of block and thread coordinates. */
-    uint32_t lo_hi[6][2];
-    int cnt[6];
-    for (int d = 0; d < 6; d++) {
-      lo_hi[d][0] = 0; lo_hi[d][1] = L[d] - 1;
-      cnt[d] = L[d] == 1 ? 1 : 2;
-    }
-    int tot = 1;
-    for (int d = 0; d < 6; d++) tot *= cnt[d];
-    /* Enumerate vertices in global-thread-id order: block coordinates
-     * outermost (z, y, x), then thread coordinates (z, y, x). */
+    int tot = n_vertices(L);
     for (int v = 0; v < tot; v++) {
-      uint32_t c[6];
-      int rem = v;
-      int order[6] = {2, 1, 0, 5, 4, 3}; /* bz by bx tz ty tx (gx..gz = 0..2, bx..bz = 3..5) */
-      int div = tot;
-      for (int o = 0; o < 6; o++) {
-        int d = order[o];
-        div /= cnt[d];
-        int digit = rem / div;
-        rem %= div;
-        c[d] = lo_hi[d][digit];
-      }
-      uint64_t blin = c[0] + (uint64_t)L[0] * (c[1] + (uint64_t)L[1] * c[2]);
-      uint32_t tlin = c[3] + L[3] * (c[4] + L[4] * c[5]);
+      uint64_t blin; uint32_t tlin;
+      vertex(L, tot, v, &blin, &tlin);
       run_thread(t, blin, tlin);
     }
   } else if (mode == M_BOUNDARY) {
@@ -565,6 +699,7 @@ static void* worker(void* arg) {
     t.cnt = J->counts + (size_t)P->n_sites * i;
     t.st = J->st + i;
     memset(t.acc_seen, 0, P->n_accesses + 1);
+    if (J->mode != M_FULL) t.st->flags = vertex_exact(&t) ? 1u : 0u;
     run_input(&t, J->mode);
   }
   free(t.regs);

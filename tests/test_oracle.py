@@ -286,6 +286,7 @@ def test_theorem_equality_on_affine_unguarded(name, mode):
     wl = W.mini(name)
     full = O.check(wl, mode=W.MODE_FULL)
     rep = O.check(wl, mode=mode)
+    assert (rep["status"]["flags"] & 1).all()  # no vertex wraps: the Theorem's premise holds
     assert_subset(rep, full)
     assert flagged(rep) == flagged(full)
     assert ((rep["records"]["count"] > 0) == (full["records"]["count"] > 0)).all()
