@@ -34,52 +34,6 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9
 # algorithmic work of one checked access on the affine path: form the index
 # (per-thread base + per-access offset) and one unsigned bound compare
 OPS_PER_ACCESS = 2
-# consecutive blocks inside one grid row whose bases form a small-step
-# progression are decided per access offset by the two end indices of the
-# run: two adds, one max and one compare
-LPB = 16
-OPS_PER_LIN_GROUP_ENTRY = 4
-
-
-# groups of LPB blocks per wavefront job of the whole grid
-NGJ_FULL = 16
-
-
-def trace_alg_ops(launch, acc_per_thread) -> float:
-    """Algorithmic int ops of the block-major trace evaluator over a
-    whole-grid batch of width-32 inputs whose block-x step is small (the
-    stencil: 16 per block), walking each job as the kernel does: a job whose
-    blocks fall into at most 4 row segments is decided by the two end indices
-    of each segment, 4 ops per thread, offset and segment (2 adds, 1 max,
-    1 compare); otherwise the whole groups it has in one grid row form one
-    such run, as does a lone whole group inside a row, and a group across rows
-    or the short last group costs 2 ops per block."""
-    total = 0.0
-    for (gx, gy, gz, bx, by, bz), ne in zip(launch.astype(np.int64), acc_per_thread):
-        nsb = int(gx * gy * gz)
-        ngroups, full = (nsb + LPB - 1) // LPB, nsb // LPB
-        tests = 0  # two-end tests per thread and offset
-        blocks = 0  # blocks checked one by one
-        for j0 in range(0, ngroups, NGJ_FULL):
-            g, gend = j0, min(j0 + NGJ_FULL, ngroups)
-            b0, nb = g * LPB, min(gend * LPB, nsb) - g * LPB
-            nseg = (b0 % gx + nb + gx - 1) // gx
-            if nseg <= 4:
-                tests += nseg
-                continue
-            while g < gend:
-                x = (g * LPB) % gx
-                k = min((gx - x) // LPB, min(gend, full) - g) if g < min(gend, full) else 0
-                if k >= 1:
-                    tests += 1
-                    g += k
-                else:
-                    blocks += min(LPB, nsb - g * LPB)
-                    g += 1
-        total += bx * by * bz * ne * (tests * OPS_PER_LIN_GROUP_ENTRY + blocks * OPS_PER_ACCESS)
-    return total
-
-
 # sources of the trace evaluator (its counters stay valid while these are unchanged)
 TRACE_SOURCES = ("dev_common.h", "dev_plan.h", "dev_trace.h", "dformat.h", "kernels.h")
 
@@ -401,9 +355,7 @@ def main():
             "inputs_per_s": n / step_s,
             "kernel_ms": kernel_ms(kern),
         }
-        lanes = st["lanes"].astype(np.float64)
-        per_thread = np.where(lanes > 0, st["accesses_checked"] / np.maximum(lanes, 1), 0)
-        achieved = trace_alg_ops(wl.launch, per_thread) / (eval_ms * 1e-3)
+        achieved = OPS_PER_ACCESS * accesses / (eval_ms * 1e-3)
         # HBM bytes per launch from the committed counter runs
         traffic = recorded_traffic("eval_trace_kernel", TRACE_SOURCES)
         result["roofline"] = {
@@ -415,6 +367,18 @@ def main():
             "frac": achieved / PEAK_INT_OPS,
             "traffic": traffic,
         }
+        # the same batch decided by the end indices of row progressions:
+        # identical results, most indices never formed -> inputs/s only
+        run_steps(ctx, dw, out, W.MODE_ENDPOINTS, 1)
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        et = run_steps(ctx, dw, out, W.MODE_ENDPOINTS, max(2, args.steps // 2))
+        torch.cuda.synchronize()
+        e1 = time.perf_counter()
+        es = (e1 - e0) / len(et)
+        result["full_endpoints"] = {"inputs_per_s": n / es, "ms_per_step": es * 1e3,
+                                    "speedup_inputs_per_s_vs_full": step_s / es,
+                                    "kernel_ms": kernel_ms(np.array(et))}
         if not args.no_rep:
             run_steps(ctx, dw, out, W.MODE_BOUNDARY, 1)
             torch.cuda.synchronize()

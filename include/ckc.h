@@ -46,12 +46,48 @@ enum ckc_status_code {
 /* thread-set modes (ckc_batch.mode) */
 enum ckc_mode {
   CKC_FULL = 0,         /* every thread of the grid (Section 5.1: the fall-back for
-                           kernels that are not affine-access) */
+                           kernels that are not affine-access); every index of every
+                           thread is formed and compared against its bound */
   CKC_REP_CORNERS = 1,  /* the vertices of the (grid x block) coordinate box: the
                            first/last thread of the first/last block of the PREX
                            Theorem (Section 5.1.1), per dimension */
-  CKC_REP_BOUNDARY = 2  /* every block with a coordinate first or last along its grid
+  CKC_REP_BOUNDARY = 2, /* every block with a coordinate first or last along its grid
                            dimension, plus the middle block, all of their threads */
+  CKC_REP_PREX = 3,     /* the PREX runtime sweep (Section 5.1.2, Algorithm 1): rounds
+                           of block pairs (r, nblocks-1-r), r = 0, 1, ..., all their
+                           threads; an input stops before its next round once every
+                           ACCESS/LOAD instruction of the program has executed at
+                           least once or some access has violated (a single middle
+                           block runs once).  ckc_check_batch returns only after
+                           every input has stopped (the round decisions need the
+                           device's results); a job holds PREX descriptors only */
+  CKC_FULL_ENDPOINTS = 4 /* the whole grid, with results identical to CKC_FULL, but
+                           programs on the trace path at width 32 are decided by the
+                           end-point argument of the Section 5.1.1 Theorem applied to
+                           rows of blocks: the block bases of consecutive blocks in a
+                           grid row form an arithmetic progression, and a progression
+                           spanning less than 2^31 is in bounds exactly when its two
+                           end indices are, so most indices are never formed.
+                           Report it in inputs/s, not per access */
+};
+
+/* ckc_input_status.flags bits */
+enum ckc_status_flags {
+  /* REP modes: the vertex threads of the (grid x block) coordinate box (the
+   * CKC_REP_CORNERS set) all follow one control path (same IF outcomes, same
+   * loop trip counts, at most 2^16 loop iterations in all) and no operation
+   * that an index, an IF predicate or a loop bound depends on wraps at any of
+   * them: no ADD/SUB/MUL/SHL whose exact signed result leaves its width's
+   * range, no DIVS of the minimum by -1, no LOOP counter start + k*step
+   * outside the range, and no 64-bit value outside the int32 range read at
+   * width 32 (an operand of a width-32 operation, a width-32 index or
+   * loop bound, SEXT/TRUNC/ZEXT or a width-32 SELECT; ZEXT of a negative
+   * value also counts).  Each intermediate of an affine index is then affine
+   * over the box in exact integers and extremal at a vertex, which is the
+   * condition under which the Section 5.1.1 Theorem makes a representative set
+   * flag exactly the (access, kind) pairs of the whole grid for affine,
+   * unguarded programs.  Never set in CKC_FULL / CKC_FULL_ENDPOINTS. */
+  CKC_ST_VERTEX_EXACT = 1
 };
 
 /* violation kinds (ckc_record.kinds / first_kind) */

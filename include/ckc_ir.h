@@ -106,6 +106,15 @@
 #define CKC_IR_MAX_SITES 4096u
 #define CKC_IR_MAX_LOOP_DEPTH 2u
 #define CKC_IR_MAX_NEST 16u /* IF and LOOP nesting together */
+/* Register pressure.  A register is live from the instruction that defines
+ * it to its last use; a use inside a LOOP body that does not contain the
+ * definition keeps the register live to the ENDLOOP of the outermost such
+ * LOOP, and a loop counter stays live to its ENDLOOP.  At every instruction
+ * that defines a register, the registers defined before it that are still
+ * live after it, plus the one it defines, must number at most
+ * CKC_IR_MAX_LIVE_REGS.  The rule applies to the program as written, before
+ * any unused instruction is removed. */
+#define CKC_IR_MAX_LIVE_REGS 32u
 #define CKC_IR_NO_SITE 0xFFFFu
 #define CKC_IR_NO_REG 0xFFFFu
 

@@ -111,6 +111,55 @@ static void prog_free(or_prog* P) {
 
 static int is_binary(int op) { return op >= O_ADD && op <= O_CMPLEU; }
 
+/* The live-register rule of the IR description: a register lives from its
+ * definition to its last use, a use inside a loop that does not contain the
+ * definition extends it to that loop's end (the outermost such loop), a loop
+ * counter lives to its ENDLOOP; at each defining instruction, the registers
+ * defined earlier and live beyond it, plus one, are at most 32.  Needs the
+ * loop ends (I->end) filled in. */
+static int pressure_ok(const or_prog* P) {
+  int n = P->n_instr, nr = P->n_regs, ok = 1;
+  int* def_at = (int*)malloc(sizeof(int) * (nr + 1));
+  int* endr = (int*)malloc(sizeof(int) * (nr + 1));
+  int* diff = (int*)calloc(n + 2, sizeof(int));
+  for (int r = 0; r < nr; r++) { def_at[r] = -1; endr[r] = -1; }
+  for (int i = 0; i < n; i++) {
+    const or_ins* I = &P->ins[i];
+    int op = I->op;
+    if (!(op == O_ACCESS || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP)) def_at[I->dst] = i;
+  }
+  int loops[4], nl = 0; /* open LOOPs, outermost first */
+  for (int u = 0; u < n; u++) {
+    const or_ins* I = &P->ins[u];
+    int op = I->op, uses[3], nu = 0;
+    if (op == O_ENDLOOP) { nl--; continue; }
+    if (op == O_SELECT || op == O_LOOP) { uses[nu++] = I->a; uses[nu++] = I->b; uses[nu++] = I->c; }
+    else if (op == O_SEXT || op == O_ZEXT || op == O_TRUNC || op == O_ACCESS || op == O_LOAD || op == O_IF) uses[nu++] = I->a;
+    else if (is_binary(op)) { uses[nu++] = I->a; uses[nu++] = I->b; }
+    for (int k = 0; k < nu; k++) {
+      int r = uses[k], e = u;
+      for (int q = 0; q < nl; q++)
+        if (loops[q] > def_at[r]) { if (P->ins[loops[q]].end > e) e = P->ins[loops[q]].end; break; }
+      if (e > endr[r]) endr[r] = e;
+    }
+    if (op == O_LOOP) {
+      if (I->end > endr[I->dst]) endr[I->dst] = I->end;
+      loops[nl++] = u;
+    }
+  }
+  for (int r = 0; r < nr; r++)
+    if (def_at[r] >= 0 && endr[r] > def_at[r]) { diff[def_at[r] + 1]++; diff[endr[r]]--; }
+  int cur = 0;
+  for (int i = 0; i < n && ok; i++) {
+    cur += diff[i];
+    int op = P->ins[i].op;
+    int defines = !(op == O_ACCESS || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP);
+    if (defines && cur + 1 > 32) ok = 0;
+  }
+  free(def_at); free(endr); free(diff);
+  return ok;
+}
+
 /* Decode and validate the byte format (include/ckc_ir.h describes it; this is
  * an independent reading of that description). */
 static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
@@ -225,6 +274,7 @@ static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
   }
   if (sp != 0) goto out;
   for (int a = 0; a < P->n_accesses; a++) if (!acc_used[a]) goto out;
+  if (!pressure_ok(P)) goto out;
   /* The slice of the indices, IF predicates and loop bounds: the accesses
    * and control instructions themselves and, walking backwards (every
    * definition precedes its uses), every instruction whose result a slice

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libckc.so")
 
 OK, NOT_READY = 0, 1
-FULL, REP_CORNERS, REP_BOUNDARY = 0, 1, 2
+FULL, REP_CORNERS, REP_BOUNDARY, REP_PREX, FULL_ENDPOINTS = 0, 1, 2, 3, 4
+ST_VERTEX_EXACT = 1
 SCHED_DEFAULT, SCHED_BLOCKED, SCHED_CYCLIC, SCHED_DYNAMIC, SCHED_LPT = 0, 1, 2, 3, 4
 SCHED_NAMES = {0: "default", 1: "blocked", 2: "cyclic", 3: "dynamic", 4: "lpt"}
 DENSE_MAP = 2

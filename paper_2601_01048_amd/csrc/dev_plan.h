@@ -236,6 +236,196 @@ __device__ void build_trace(const dprog* P, const dinput& in, const int64_t* sc,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vertex-exact flag of the representative modes (the exact-integer premise
+// of the Section 5.1.1 Theorem): the vertex threads of the (grid x block) box
+// run the lowered program in lockstep, one lane each, with concrete values in
+// the LDS register file.  The flag is set when they take the same control
+// decisions (IF outcomes, exact loop trip counts; at most 2^16 decisions and
+// iterations in all) and no slice operation wraps at any of them.
+// ---------------------------------------------------------------------------
+constexpr uint32_t VERTEX_BUDGET = 65536;
+
+__device__ __forceinline__ bool fits32(uint64_t c) { return (uint64_t)((int64_t)c + (1ll << 31)) < (1ull << 32); }
+
+// Exact signed result of ADD/SUB/MUL/SHL/DIVS at width w outside its range,
+// or a width-32 operand outside int32.
+__device__ __forceinline__ bool op_wraps(uint32_t op, uint32_t w, uint64_t x, uint64_t y) {
+  const bool bin = op >= CKC_OP_ADD && op <= CKC_OP_CMPLEU;
+  if (w == 32 && (!fits32(x) || (bin && !fits32(y)))) return true;
+  const int64_t sx = (int64_t)narrow(x, w), sy = (int64_t)narrow(y, w);
+  if (w == 32) {
+    int64_t r;
+    switch (op) {
+      case CKC_OP_ADD: r = sx + sy; break;
+      case CKC_OP_SUB: r = sx - sy; break;
+      case CKC_OP_MUL: r = sx * sy; break;  // |operands| <= 2^31: no 64-bit overflow
+      case CKC_OP_SHL: r = sx * (int64_t)(1ll << ((uint32_t)sy & 31u)); break;  // |r| < 2^62
+      case CKC_OP_DIVS: return sx == INT32_MIN && sy == -1;
+      default: return false;
+    }
+    return !fits32((uint64_t)r);
+  }
+  switch (op) {
+    case CKC_OP_ADD: { int64_t r; return __builtin_add_overflow(sx, sy, &r); }
+    case CKC_OP_SUB: { int64_t r; return __builtin_sub_overflow(sx, sy, &r); }
+    case CKC_OP_MUL: { int64_t r; return __builtin_mul_overflow(sx, sy, &r); }
+    case CKC_OP_SHL: {
+      const uint32_t sh = (uint32_t)sy & 63u;
+      if (sx == 0 || sh == 0) return false;
+      // exact x * 2^sh fits in int64 iff the top sh+1 bits of x are all equal
+      const int64_t t = sx >> (63 - sh);
+      return !(t == 0 || t == -1);
+    }
+    case CKC_OP_DIVS: return sx == INT64_MIN && sy == -1;
+    default: return false;
+  }
+}
+
+__device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t* sc, const ckc_alloc* tab,
+                                uint64_t* RG) {
+  const uint32_t j = lane_id();
+  const uint32_t* L = in.launch;
+  uint32_t nv = 1;
+  for (int d = 0; d < 6; d++) nv *= L[d] >= 2 ? 2u : 1u;
+  if ((uint64_t)L[0] * L[1] * L[2] == 0 || (uint64_t)L[3] * L[4] * L[5] == 0) return 0;
+  const bool act = j < nv;
+  const uint64_t actm = __ballot(act);
+  // coordinates of vertex j: tid.xyz then bid.xyz, each first or last
+  uint32_t crd[6];
+  {
+    uint32_t v = j;
+    const int ord[6] = {3, 4, 5, 0, 1, 2};  // launch index of tid.x .. bid.z
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+      const uint32_t e = L[ord[d]];
+      if (e >= 2) {
+        crd[d] = (v & 1u) ? e - 1 : 0u;
+        v >>= 1;
+      } else {
+        crd[d] = 0;
+      }
+    }
+  }
+  const dins* I = prog_ins(P);
+  const int64_t* K = prog_consts(P);
+  for (uint32_t r = 0; r < P->n_regs; r++) RSET(r, 0ull);
+  uint64_t k[2] = {0, 0}, run[2] = {0, 0}, lstart[2] = {0, 0}, lstep[2] = {0, 0};
+  uint32_t lhang[2] = {0, 0}, lw[2] = {32, 32};
+  uint32_t budget = 0;
+  bool wrapped = false, abort_run = false;
+  const uint32_t n = P->n_instr;
+  uint32_t pc = 0;
+  auto decide = [&](uint64_t v) {
+    if (++budget > VERTEX_BUDGET) { abort_run = true; return; }
+    const uint64_t lo = wave_min64(act ? v : ~0ull), hi = ~wave_min64(act ? ~v : ~0ull);
+    if (lo != hi) abort_run = true;
+  };
+  while (pc < n && !abort_run) {
+    const dins D = I[pc];
+    const uint32_t op = D.op, w = D.w;
+    const bool sl = (D.fl & DI_SLICE) != 0;
+    switch (op) {
+      case CKC_OP_CONST: RSET(D.dst, narrow((uint64_t)K[D.x], w)); break;
+      case CKC_OP_SCALAR: RSET(D.dst, narrow((uint64_t)sc[D.x], w)); break;
+      case CKC_OP_SPECIAL:
+        RSET(D.dst, (uint64_t)(D.x < 6 ? crd[D.x] : D.x < 9 ? L[3 + (D.x - 6)] : L[D.x - 9]));
+        break;
+      case CKC_OP_TRUNC: case CKC_OP_SEXT: {
+        const uint64_t x = RGET64(D.a);
+        if (sl && act && !fits32(x)) wrapped = true;
+        RSET(D.dst, narrow(x, 32));
+        break;
+      }
+      case CKC_OP_ZEXT: {
+        const uint64_t x = RGET64(D.a);
+        if (sl && act && !(fits32(x) && (int64_t)x >= 0)) wrapped = true;
+        RSET(D.dst, x & 0xFFFFFFFFull);
+        break;
+      }
+      case CKC_OP_SELECT: {
+        const uint64_t v = RGET64(D.a) != 0 ? RGET64(D.b) : RGET64(D.c);
+        if (sl && act && w == 32 && !fits32(v)) wrapped = true;
+        RSET(D.dst, narrow(v, w));
+        break;
+      }
+      case CKC_OP_ACCESS: case CKC_OP_LOAD: {
+        const uint64_t x = RGET64(D.a);
+        if (act && w == 32 && !fits32(x)) wrapped = true;
+        if (op == CKC_OP_LOAD) {
+          const ckc_alloc A = tab[D.slot];
+          const uint32_t lg = D.fl & 3u;
+          const int64_t idx = (int64_t)narrow(x, w);
+          const uint32_t kd = kind_of(A.base, A.size_bytes, A.flags, idx, lg);
+          uint64_t val = 0;
+          if (act && !kd)
+            val = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
+          RSET(D.dst, val);
+        }
+        break;
+      }
+      case CKC_OP_IF: {
+        const bool taken = RGET64(D.a) != 0;
+        decide(taken ? 1ull : 0ull);
+        if (abort_run) break;
+        if (!__ballot(act && taken)) pc = D.jmp;  // ELSE (its arm follows) or ENDIF
+        break;
+      }
+      case CKC_OP_ELSE: pc = D.jmp; break;
+      case CKC_OP_ENDIF: break;
+      case CKC_OP_LOOP: {
+        const uint32_t d = D.x;
+        const uint64_t xa = RGET64(D.a), xb = RGET64(D.b), xc = RGET64(D.c);
+        if (act && w == 32 && (!fits32(xa) || !fits32(xb) || !fits32(xc))) wrapped = true;
+        const int64_t s0 = (int64_t)narrow(xa, w), e0 = (int64_t)narrow(xb, w), st0 = (int64_t)narrow(xc, w);
+        const uint64_t nt = trip_count(s0, e0, st0);
+        decide(nt);
+        if (abort_run) break;
+        const uint64_t cap = 1ull << (d == 0 ? in.cap_log2[0] : in.cap_log2[1]);
+        const uint64_t rn = nt < cap ? nt : cap;
+        run[d & 1] = rn; lstart[d & 1] = (uint64_t)s0; lstep[d & 1] = (uint64_t)st0;
+        lhang[d & 1] = nt > cap; k[d & 1] = 0; lw[d & 1] = w;
+        if (rn == 0) {
+          pc = D.jmp;  // ENDLOOP; continue after it
+          break;
+        }
+        if (++budget > VERTEX_BUDGET) { abort_run = true; break; }
+        RSET(D.dst, narrow((uint64_t)s0, w));
+        break;
+      }
+      case CKC_OP_ENDLOOP: {
+        const uint32_t d = D.x & 1u;
+        const dins Lp = I[D.jmp];
+        const uint64_t kk = k[d] + 1;
+        if (kk < run[d]) {
+          if (++budget > VERTEX_BUDGET) { abort_run = true; break; }
+          k[d] = kk;
+          // the counter lies between start and end for every iteration below
+          // the exact trip count, so it cannot leave the width's range
+          RSET(Lp.dst, narrow(lstart[d] + kk * lstep[d], lw[d]));
+          pc = D.jmp;
+        } else {
+          k[d] = 0;
+          if (lhang[d]) pc = n;  // every vertex thread stops here
+        }
+        break;
+      }
+      default: {
+        const uint64_t x = RGET64(D.a), y = RGET64(D.b);
+        if (sl && act && op_wraps(op, w, x, y)) wrapped = true;
+        uint32_t f = 0;
+        RSET(D.dst, alu(op, w, x, y, f));
+        break;
+      }
+    }
+    if (pc >= n) break;
+    pc++;
+  }
+  (void)actm;
+  const bool bad = abort_run || __ballot(act && wrapped) != 0;
+  return bad ? 0u : 1u;
+}
+
 __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
   extern __shared__ uint64_t RG[];  // [max_regs][64]: symbolic registers of build_trace
   const uint32_t i = blockIdx.x;
@@ -265,6 +455,11 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
   if (j == 0) {
     st->lanes = lanes; st->accesses_checked = 0; st->hang_lanes = 0; st->arith_faults = 0;
     st->flags = 0; st->pad = 0;
+  }
+  if (in.mode == CKC_REP_CORNERS || in.mode == CKC_REP_BOUNDARY) {
+    const uint32_t f = vertex_flag(P, in, a.scalars + (size_t)i * MAX_SCALARS, (const ckc_alloc*)in.table, RG);
+    if (j == 0) st->flags = f;
+    __syncthreads();
   }
   uint32_t path = 1;
   if (trace) {
@@ -319,7 +514,8 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
         B.m_bxy = u.m; B.s_bxy = u.s;
         u = udiv_make(bs / 64u);
         B.m_spb = u.m; B.s_spb = u.s;
-        for (int q = 0; q < 4; q++) B.pad[q] = 0;
+        B.proof = in.mode == CKC_FULL && in.aux == 1u ? 1u : 0u;
+        for (int q = 0; q < 2; q++) B.pad[q] = 0;
         for (int q = 0; q < 6; q++) B.k[q] = th->coef[0][q];
         const uint64_t k3 = (uint64_t)B.k[3], k4 = (uint64_t)B.k[4], k5 = (uint64_t)B.k[5];
         B.d1 = k3;

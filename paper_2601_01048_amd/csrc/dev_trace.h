@@ -325,10 +325,19 @@ struct TrIn {
 
 // One block-major wavefront job: slice position o (64 threads) of the groups
 // gs*ngj .. gs*ngj+ngj-1 (LPB set blocks each; ngj from the plan).  The thread part of the index
-// base is formed once per job; in the whole-grid mode the block coordinates
+// base is formed once per job; in the whole-grid modes the block coordinates
 // are walked from group to group, and a group that stays inside one grid row
 // forms its block parts by adding the x coefficient.
-template <int W, bool FULL>
+//
+// PROOF = false (CKC_FULL): every index of every thread is formed (one add
+// per access) and compared against its bound (a max tree over the 16 blocks
+// of a group, one compare per tree).
+// PROOF = true (CKC_FULL_ENDPOINTS, width 32): the whole grid is decided by
+// the end-point argument of the affine-access Theorem (Section 5.1.1) applied
+// to row progressions of block bases: a progression whose span stays below
+// 2^31 is in bounds exactly when its two end indices are, so most indices are
+// never formed.  Results are identical; the work is not per access.
+template <int W, bool FULL, bool PROOF>
 __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, uint32_t o) {
   typedef typename std::conditional<W == 32, uint32_t, uint64_t>::type BT;
   c_blk* B = &th->blk;
@@ -356,7 +365,7 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
     by = udiv(brem, UDiv{B->m_gx, B->s_gx});
     bx = brem - by * B->L[0];
     cur = (BT)B->k[3] * (BT)bx + (BT)B->k[4] * (BT)by + (BT)B->k[5] * (BT)bz;
-    if (W == 32 && !B->any_dead) {
+    if (PROOF && W == 32 && !B->any_dead) {
       // the job's blocks split at row ends into at most 4 row segments, each
       // a progression of block bases: when every segment's span stays below
       // 2^31 and no offset is out of bounds at the ends of any segment, the
@@ -401,7 +410,7 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
   for (; g < gend; g++) {
     c_head* tg = fresh(th);
     c_blk* Bg = &tg->blk;
-    if (FULL && W == 32 && !Bg->any_dead) {
+    if (FULL && PROOF && W == 32 && !Bg->any_dead) {
       // the whole groups of the job from g on that lie in the current row
       // form one progression of block bases: when its span stays below 2^31
       // and no offset is out of bounds at either end, they are all clean
@@ -443,7 +452,7 @@ __device__ __forceinline__ void block_job(TraceLds& S, c_head* th, uint32_t gs, 
       const BT d1 = (BT)Bg->d1;
       if (bx + LPB <= gx) {
         // the group stays in one row
-        if (W == 32 && nvalid == LPB && !Bg->any_dead) {
+        if (PROOF && W == 32 && nvalid == LPB && !Bg->any_dead) {
           const uint32_t sd = (uint32_t)d1, ad = (int32_t)sd < 0 ? 0u - sd : sd;
           lin = ad <= 0x7FFFFFFFu / (LPB - 1);
         }
@@ -612,11 +621,15 @@ __global__ void __launch_bounds__(TILE, 7) eval_trace_kernel(KArgs a) {
     if (gs * B->ngj >= B->ngroups) continue;  // past the last group (whole wavefront)
     const bool full = B->mode == CKC_FULL;
     if (B->w == 32) {
-      if (full) block_job<32, true>(S, tj, (uint32_t)gs, o);
-      else block_job<32, false>(S, tj, (uint32_t)gs, o);
+      if (full) {
+        if (B->proof) block_job<32, true, true>(S, tj, (uint32_t)gs, o);
+        else block_job<32, true, false>(S, tj, (uint32_t)gs, o);
+      } else {
+        block_job<32, false, false>(S, tj, (uint32_t)gs, o);
+      }
     } else {
-      if (full) block_job<64, true>(S, tj, (uint32_t)gs, o);
-      else block_job<64, false>(S, tj, (uint32_t)gs, o);
+      if (full) block_job<64, true, false>(S, tj, (uint32_t)gs, o);
+      else block_job<64, false, false>(S, tj, (uint32_t)gs, o);
     }
   }
   if (pos != 0xFFFFFFFFu && th->blk.n_acc <= TR_ACC_LDS) tr_flush(S, (ckc_record*)th->blk.rec, th->blk.n_acc);

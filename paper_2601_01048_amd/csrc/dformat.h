@@ -7,8 +7,6 @@
 namespace ckc {
 
 constexpr int NREG = 32;          // physical registers per lane (64-bit each)
-constexpr int MAX_DINSTR = 1024;  // lowered instructions per program
-constexpr int MAX_DCONST = 256;   // constants per program
 constexpr int MAX_SLOTS = 16;
 constexpr int MAX_CLASSES = 4;    // distinct coefficient vectors in a trace
 constexpr int MAX_LIVEIN = 6;     // registers carried into an expanded loop body
@@ -34,7 +32,8 @@ static_assert(sizeof(dins) == 16, "dins layout");
 enum : uint8_t {
   DI_NOSKIP = 1,    // IF/LOOP: never skip the region (holds the expanded loop)
   DI_EXPAND = 2,    // LOOP: evaluated one lane per iteration
-  DI_HASELSE = 4    // IF: jmp points at an ELSE
+  DI_HASELSE = 4,   // IF: jmp points at an ELSE
+  DI_SLICE = 0x80   // value op that an index, IF predicate or loop bound depends on
 };
 
 // Per-access facts used by the fix-up pass.
@@ -77,7 +76,8 @@ struct dinput {
   uint32_t cap_log2[2];
   uint32_t path;          // evaluator, set by planning: PATH_BLOCKS, PATH_GENERIC, PATH_LANES
   uint32_t n_tiles[3];
-  uint32_t pad;
+  uint32_t aux;           // mode CKC_FULL: 1 = decide row progressions by their end indices
+                          // (CKC_FULL_ENDPOINTS); mode MODE_PAIR: the round r
   // expanded loop (interpreter path): per-thread state arrays and this
   // input's range of expanded tiles
   uint64_t xstate;        // device address of xn x (3 + n_livein) uint64: trip-count
@@ -87,6 +87,11 @@ struct dinput {
   uint64_t n_xt;          // expanded tiles reserved for this input
 };
 static_assert(sizeof(dinput) == 168, "dinput layout");
+// Internal thread-set mode of one round of the PREX sweep (Algorithm 1): the
+// blocks r and nblocks-1-r (one block when they coincide), all their threads,
+// in block order.  Never seen at the C-ABI.
+constexpr uint32_t MODE_PAIR = 8;
+
 // Evaluators of an input: the trace evaluator in block-major wavefront jobs,
 // the general interpreter, or the trace evaluator over lane tiles.
 enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };
@@ -119,7 +124,9 @@ struct dblk {
   uint32_t L[6];        // gx gy gz bx by bz
   uint32_t mode, bs, gxy, bxy, nsb, ngroups, spb, ne;
   uint32_t any_dead, w, Lsum, n_acc;
-  uint32_t m_gx, s_gx, m_gxy, s_gxy, m_bx, s_bx, m_bxy, s_bxy, m_spb, s_spb, ngj, pad[3];
+  uint32_t m_gx, s_gx, m_gxy, s_gxy, m_bx, s_bx, m_bxy, s_bxy, m_spb, s_spb, ngj;
+  uint32_t proof;       // whole grid decided by the end indices of row progressions
+  uint32_t pad[2];
   int64_t k[6];         // coefficients of the one class: tid.xyz, bid.xyz
   uint64_t d1, dy, dz;  // block-part steps: next x, x wrap, x and y wrap
   uint64_t rec;         // the input's records

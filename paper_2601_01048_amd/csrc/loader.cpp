@@ -260,13 +260,78 @@ struct Analyzer {
     if (!ctl.empty()) return fail(-1, "unclosed IF or LOOP");
     for (int a = 0; a < n_accesses; a++)
       if (!acc_used[a]) return fail(-1, "an access id is never used");
+    return pressure_ok();
+  }
+
+  // The live-register rule of ckc_ir.h (CKC_IR_MAX_LIVE_REGS) over the program
+  // as written.  Pruning only shortens live ranges, so the allocation of the
+  // pruned program then needs at most as many registers.
+  bool pressure_ok() {
+    std::vector<int> end(n_regs, -1);
+    auto touch = [&](int r, int pc) {
+      if (r >= n_regs) return;
+      int e = pc;
+      for (int p = ins[pc].parent; p >= 0; p = ins[p].parent)
+        if (ins[p].op == CKC_OP_LOOP && def_pc[r] < p) e = std::max(e, ins[p].end);
+      end[r] = std::max(end[r], e);
+    };
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      switch (I.op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
+        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
+        case CKC_OP_SELECT: case CKC_OP_LOOP: touch(I.a, i); touch(I.b, i); touch(I.c, i); break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
+        case CKC_OP_LOAD: case CKC_OP_IF: touch(I.a, i); break;
+        default: touch(I.a, i); touch(I.b, i); break;
+      }
+      if (I.op == CKC_OP_LOOP) end[I.dst] = std::max(end[I.dst], I.end);
+    }
+    // live after instruction i: registers r with def_pc[r] < i < end[r]
+    std::vector<int> diff(n_instr + 2, 0);
+    for (int r = 0; r < n_regs; r++)
+      if (def_pc[r] >= 0 && end[r] > def_pc[r]) {
+        diff[def_pc[r] + 1]++;
+        diff[end[r]]--;
+      }
+    int cur = 0;
+    for (int i = 0; i < n_instr; i++) {
+      cur += diff[i];
+      const Ins& I = ins[i];
+      const bool defines = (I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF) || I.op == CKC_OP_LOOP;
+      if (defines && cur + 1 > (int)CKC_IR_MAX_LIVE_REGS)
+        return fail(i, "more than CKC_IR_MAX_LIVE_REGS (32) registers live");
+    }
     return true;
   }
 
   // Pruning: keep accesses, control flow, divisions (they count faults) and
   // everything that feeds them; one backward pass suffices because every
   // definition precedes its uses.
+  // The slice of the indices, IF predicates and loop bounds (the same walk
+  // without the division roots): the instructions whose wraps at the vertex
+  // threads clear the vertex-exact flag.
+  std::vector<char> slice;
   void prune() {
+    slice.assign(n_instr, 0);
+    {
+      std::vector<char> need(n_regs, 0);
+      for (int i = n_instr - 1; i >= 0; i--) {
+        const Ins& I = ins[i];
+        const bool root = I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD || I.op == CKC_OP_IF || I.op == CKC_OP_LOOP;
+        const bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF;
+        if (!(root || (defines && I.dst < n_regs && need[I.dst]))) continue;
+        slice[i] = 1;
+        auto mark = [&](uint16_t r) { if (r < n_regs) need[r] = 1; };
+        switch (I.op) {
+          case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: break;
+          case CKC_OP_SELECT: case CKC_OP_LOOP: mark(I.a); mark(I.b); mark(I.c); break;
+          case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
+          case CKC_OP_LOAD: case CKC_OP_IF: mark(I.a); break;
+          default: mark(I.a); mark(I.b); break;
+        }
+      }
+    }
     std::vector<char> reg_live(n_regs, 0);
     for (int i = n_instr - 1; i >= 0; i--) {
       Ins& I = ins[i];
@@ -654,6 +719,7 @@ struct Analyzer {
         case CKC_OP_ENDLOOP: D.jmp = (uint16_t)newpc[I.end]; D.x = (uint16_t)ins[I.end].depth; break;
         default: D.dst = P(I.dst); D.a = P(I.a); D.b = P(I.b); break;
       }
+      if (slice[i] && I.op < CKC_OP_ACCESS) D.fl |= DI_SLICE;
       out[newpc[i]] = D;
     }
     auto al = [](uint32_t v) { return (v + 15u) & ~15u; };
@@ -793,15 +859,6 @@ int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
   }
   int n_live = 0;
   out->blob = A.lower(cls, trace_cap, &n_live);
-  if (n_live > MAX_DINSTR) {
-    out->err = "program has more than 1024 instructions after pruning";
-    return CKC_E_IR;
-  }
-  const dprog* h = (const dprog*)out->blob.data();
-  if (h->n_consts > (uint32_t)MAX_DCONST) {
-    out->err = "program uses more than 256 constants";
-    return CKC_E_IR;
-  }
   std::memset(&out->info, 0, sizeof out->info);
   out->info.n_accesses = A.n_accesses;
   out->info.n_sites = A.n_sites;

@@ -163,7 +163,8 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
   const Program& P = pit->second;
   const dprog* h = (const dprog*)P.L.blob.data();
   if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, dk + "scalars missing");
-  if (B.mode > CKC_REP_BOUNDARY) return fail(CKC_E_INVALID, dk + "unknown mode");
+  if (B.mode > CKC_FULL_ENDPOINTS) return fail(CKC_E_INVALID, dk + "unknown mode");
+  if (B.mode == CKC_REP_PREX) return fail(CKC_E_INVALID, dk + "CKC_REP_PREX is not available yet");
   uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
   if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
   if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, dk + "loop cap above 2^32");
@@ -360,7 +361,8 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
       d.prog = (uint64_t)(uintptr_t)P.dblob;
       d.table = (uint64_t)(uintptr_t)T.dptr;
       for (int q = 0; q < 6; q++) d.launch[q] = L[q];
-      d.mode = B.mode;
+      d.mode = B.mode == CKC_FULL_ENDPOINTS ? CKC_FULL : B.mode;
+      d.aux = B.mode == CKC_FULL_ENDPOINTS ? 1u : 0u;
       d.L1 = L1;
       d.L2 = L2;
       d.cap_log2[0] = c0;

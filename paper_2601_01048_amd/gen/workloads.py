@@ -34,7 +34,7 @@ ALLOC_DTYPE = np.dtype([("base", "<u8"), ("size_bytes", "<u8"), ("data", "<u8"),
                         ("flags", "<u4"), ("pad", "<u4")])
 ALLOC_FREED = 1
 
-MODE_FULL, MODE_CORNERS, MODE_BOUNDARY, MODE_PREX = 0, 1, 2, 3
+MODE_FULL, MODE_CORNERS, MODE_BOUNDARY, MODE_PREX, MODE_ENDPOINTS = 0, 1, 2, 3, 4
 DEFAULT_CAP_LOG2 = (20, 12)
 I64_BASE = 1 << 32  # base offset of the int64 variants (no memory behind it)
 LOGICAL_BASE = 0x7F00_0000_0000  # nonzero logical base for live allocations

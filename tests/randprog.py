@@ -191,3 +191,90 @@ def affine_grid_workload(rng, ir: bytes, k_bx: int, n_inputs: int = 6) -> W.Work
             tables[i, s] = (base, 4 * size, 0, flags, 0)
     return W.Workload("affine_grid", ir, launch, scalars, tables, np.arange(n_inputs, dtype=np.uint32), [],
                       W.MODE_FULL, (4, 3))
+
+
+def grid3d_program(rng, n_acc: int = 5) -> bytes:
+    """Width-32 accesses sharing one linear part in all six coordinates
+    (nonzero tid.z and bid.z coefficients) at different constant offsets: one
+    coefficient class, so 64-thread blocks take the block-major trace layout
+    with the z parts of the thread and block walks in use."""
+    p = Program(n_scalars=1, n_slots=2)
+    coef = [int(rng.choice(v)) for v in ((1, 2, -1), (16, 40, -16), (32, 100, -70), (64, 3, -64),
+                                          (2048, 700, -999), (65536, 9000, -40000))]
+    names = ("tid.x", "tid.y", "tid.z", "bid.x", "bid.y", "bid.z")
+    base = p.scalar(0, 32)
+    for nm, k in zip(names, coef):
+        base = p.add(base, p.mul(p.special(nm), p.const(k, 32), 32), 32)
+    for _ in range(n_acc):
+        p.access(int(rng.integers(2)), p.add(base, p.const(int(rng.integers(-90, 90)), 32), 32), elem=4)
+    return p.to_bytes()
+
+
+def grid3d_workload(rng, ir: bytes, n_inputs: int = 8) -> W.Workload:
+    """3-D grids (gx 16..40, gy 1..3, gz 2..4) of 16x2x2 blocks: jobs cross
+    x, y and z wraps; scalar 0 and the allocation sizes put bounds inside
+    the grid's index range, so some blocks violate and most do not."""
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    scalars = np.zeros((n_inputs, 1), np.int64)
+    tables = np.zeros((n_inputs, 2), W.ALLOC_DTYPE)
+    for i in range(n_inputs):
+        launch[i] = [int(rng.integers(16, 41)), int(rng.integers(1, 4)), int(rng.integers(2, 5)), 16, 2, 2]
+        scalars[i, 0] = int(rng.choice([0, 50, 200000, 400000]))
+        for s in range(2):
+            u = rng.random()
+            size = (1 << 31) - 1 if u < 0.3 else int(rng.integers(1, 600000))
+            tables[i, s] = (W.LOGICAL_BASE + (s << 36), 4 * size, 0, 0, 0)
+    return W.Workload("grid3d", ir, launch, scalars, tables, np.arange(n_inputs, dtype=np.uint32), [],
+                      W.MODE_FULL, (4, 3))
+
+
+def segment_program(k_bx: int, k_by: int, offsets=(-3, 0, 5, 70)) -> bytes:
+    """idx = k_bx*bid.x + k_by*bid.y + tid.x + s0 + off (width 32): the block
+    bases of a grid row form one arithmetic progression with step k_bx."""
+    p = Program(n_scalars=1, n_slots=2)
+    base = p.add(p.mul(p.special("bid.x"), p.const(k_bx, 32), 32), p.special("tid.x"), 32)
+    base = p.add(base, p.mul(p.special("bid.y"), p.const(k_by, 32), 32), 32)
+    base = p.add(base, p.scalar(0, 32), 32)
+    for k, off in enumerate(offsets):
+        p.access(k % 2, p.add(base, p.const(off, 32), 32), elem=4)
+    return p.to_bytes()
+
+
+def segment_workload(rng, ir: bytes, k_bx: int, k_by: int, offsets=(-3, 0, 5, 70),
+                     n_inputs: int = 8) -> W.Workload:
+    """Whole grids of 64-thread blocks with 70..127 blocks per row and 3..7
+    rows, so a job of 256 blocks covers 3 or 4 row segments (partial first
+    row, whole rows, partial last row).  Bounds are set from the index at a
+    chosen block that ends a row inside a job (x = gx-1 or x = 0, not the
+    job's first or last block), so the only violations sit at interior
+    segment ends and next to them."""
+    def idx(bx, by, tx, s0, off):
+        v = (k_bx * bx + k_by * by + tx + s0 + off) & 0xFFFFFFFF
+        return v - (1 << 32) if v >= (1 << 31) else v
+
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    scalars = np.zeros((n_inputs, 1), np.int64)
+    tables = np.zeros((n_inputs, 2), W.ALLOC_DTYPE)
+    for i in range(n_inputs):
+        gx, gy = int(rng.integers(70, 128)), int(rng.integers(3, 8))
+        launch[i] = [gx, gy, 1, 64, 1, 1]
+        s0 = int(rng.choice([0, 7, 1 << 20]))
+        scalars[i, 0] = s0
+        # a row end strictly inside the first job (blocks 0..255)
+        row = int(rng.integers(0, min(gy, 256 // gx)))
+        bx = gx - 1 if k_bx >= 0 else 0
+        if row * gx + bx in (0, 255) or row * gx + bx > 255:
+            row, bx = 0, gx - 1 if k_bx >= 0 else 1
+        for s in range(2):
+            offs = [o for k, o in enumerate(offsets) if k % 2 == s]
+            hi = max(idx(bx, row, 63, s0, o) for o in offs)
+            u = rng.random()
+            if u < 0.6 and 0 < hi < (1 << 31) - 1:
+                size = hi  # exactly the largest index at that block is out of bounds
+            elif u < 0.8:
+                size = (1 << 31) - 1
+            else:
+                size = int(rng.integers(1, 1 << 31))
+            tables[i, s] = (W.LOGICAL_BASE + (s << 36), 4 * size, 0, 0, 0)
+    return W.Workload("segments", ir, launch, scalars, tables, np.arange(n_inputs, dtype=np.uint32), [],
+                      W.MODE_FULL, (4, 3))

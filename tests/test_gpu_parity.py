@@ -36,7 +36,7 @@ def compare(gpu, ora, n=None, maps=True, what=""):
             i, a = int(bad[0][0]), int(bad[1][0])
             raise AssertionError(f"{what}: field {f} differs at {bad[0].size} records; first "
                                  f"(input {i}, access {a}): gpu {g[i, a]} oracle {o[i, a]}")
-    for f in ("lanes", "accesses_checked", "hang_lanes", "arith_faults"):
+    for f in ("lanes", "accesses_checked", "hang_lanes", "arith_faults", "flags"):
         np.testing.assert_array_equal(gpu["status"][f][:n], ora["status"][f][:n], err_msg=f"{what} {f}")
     if maps:
         bad = np.nonzero(gpu["maps"][:n] != ora["maps"][:n])

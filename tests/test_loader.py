@@ -90,23 +90,62 @@ def test_pruning_keeps_only_index_slice():
     assert info["n_instr_live"] == 6
 
 
-def test_register_limit():
+def _pressure_program(k):
+    """tid.x, then k values tid.x + c_j that all stay live until a final sum:
+    the pressure peaks at k + 1 (the last constant, the k - 1 earlier sums'
+    operands, tid.x and the constant itself)."""
+    p = Program(n_scalars=0, n_slots=1)
+    t = p.special("tid.x")
+    vs = [p.add(t, p.const(j, 32), 32) for j in range(k)]
+    acc = vs[0]
+    for v in vs[1:]:
+        acc = p.add(acc, v, 32)
+    p.access(0, acc)
+    return p.to_bytes()
+
+
+def test_register_limit_at_and_over():
+    """The live-register rule of ckc_ir.h (CKC_IR_MAX_LIVE_REGS = 32): the
+    library and the oracle accept a program at the limit and both reject one
+    register over it."""
     p = Program(n_scalars=0, n_slots=1)
     t = p.special("tid.x")
     for k in range(40):  # each value dies at its access: registers are reused
         p.access(0, p.add(t, p.const(k, 32), 32))
-    # 40 values plus tid.x live at once: over the 32-register file
-    p2 = Program(n_scalars=0, n_slots=1)
-    t2 = p2.special("tid.x")
-    vs = [p2.add(t2, k, 32) for k in range(40)]
-    acc = vs[0]
-    for v in vs[1:]:
-        acc = p2.add(acc, v, 32)
-    p2.access(0, acc)
+    ckc.analyze(p.to_bytes())
+    O.validate(p.to_bytes())
+    at, over = _pressure_program(31), _pressure_program(32)
+    info, _ = ckc.analyze(at)
+    assert info["n_regs_phys"] <= 32
+    O.validate(at)
     with pytest.raises(ckc.CkcError) as e:
-        ckc.analyze(p2.to_bytes())
+        ckc.analyze(over)
     assert e.value.code == -2
-    ckc.analyze(p.to_bytes())  # sequential uses fit
+    with pytest.raises(O.OracleError):
+        O.validate(over)
+
+
+def test_register_rule_agrees_with_oracle_on_random_programs():
+    """Random programs around the limit (loops keep values live to their end):
+    the library accepts exactly what the oracle accepts."""
+    import randprog as R
+    rng = np.random.default_rng(31)
+    verdicts = set()
+    for k in range(300):
+        ir = R.random_program(rng, budget=int(rng.integers(20, 140)))
+        try:
+            O.validate(ir)
+            ok_o = True
+        except O.OracleError:
+            ok_o = False
+        try:
+            ckc.analyze(ir)
+            ok_l = True
+        except ckc.CkcError:
+            ok_l = False
+        assert ok_o == ok_l, ir.hex()
+        verdicts.add(ok_o)
+    assert verdicts == {True, False}
 
 
 def test_malformed_ir_agrees_with_oracle():
