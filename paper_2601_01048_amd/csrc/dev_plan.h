@@ -289,12 +289,12 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
   uint32_t nv = 1;
   for (int d = 0; d < 6; d++) nv *= L[d] >= 2 ? 2u : 1u;
   if ((uint64_t)L[0] * L[1] * L[2] == 0 || (uint64_t)L[3] * L[4] * L[5] == 0) return 0;
-  const bool act = j < nv;
-  const uint64_t actm = __ballot(act);
+  // lanes past the vertex count run vertex 0 again (a duplicate changes
+  // nothing and keeps every lane's control decisions equal)
   // coordinates of vertex j: tid.xyz then bid.xyz, each first or last
   uint32_t crd[6];
   {
-    uint32_t v = j;
+    uint32_t v = j < nv ? j : 0u;
     const int ord[6] = {3, 4, 5, 0, 1, 2};  // launch index of tid.x .. bid.z
 #pragma unroll
     for (int d = 0; d < 6; d++) {
@@ -318,7 +318,7 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
   uint32_t pc = 0;
   auto decide = [&](uint64_t v) {
     if (++budget > VERTEX_BUDGET) { abort_run = true; return; }
-    const uint64_t lo = wave_min64(act ? v : ~0ull), hi = ~wave_min64(act ? ~v : ~0ull);
+    const uint64_t lo = wave_min64(v), hi = ~wave_min64(~v);
     if (lo != hi) abort_run = true;
   };
   while (pc < n && !abort_run) {
@@ -333,32 +333,32 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
         break;
       case CKC_OP_TRUNC: case CKC_OP_SEXT: {
         const uint64_t x = RGET64(D.a);
-        if (sl && act && !fits32(x)) wrapped = true;
+        if (sl && !fits32(x)) wrapped = true;
         RSET(D.dst, narrow(x, 32));
         break;
       }
       case CKC_OP_ZEXT: {
         const uint64_t x = RGET64(D.a);
-        if (sl && act && !(fits32(x) && (int64_t)x >= 0)) wrapped = true;
+        if (sl && !(fits32(x) && (int64_t)x >= 0)) wrapped = true;
         RSET(D.dst, x & 0xFFFFFFFFull);
         break;
       }
       case CKC_OP_SELECT: {
         const uint64_t v = RGET64(D.a) != 0 ? RGET64(D.b) : RGET64(D.c);
-        if (sl && act && w == 32 && !fits32(v)) wrapped = true;
+        if (sl && w == 32 && !fits32(v)) wrapped = true;
         RSET(D.dst, narrow(v, w));
         break;
       }
       case CKC_OP_ACCESS: case CKC_OP_LOAD: {
         const uint64_t x = RGET64(D.a);
-        if (act && w == 32 && !fits32(x)) wrapped = true;
+        if (w == 32 && !fits32(x)) wrapped = true;
         if (op == CKC_OP_LOAD) {
           const ckc_alloc A = tab[D.slot];
           const uint32_t lg = D.fl & 3u;
           const int64_t idx = (int64_t)narrow(x, w);
           const uint32_t kd = kind_of(A.base, A.size_bytes, A.flags, idx, lg);
           uint64_t val = 0;
-          if (act && !kd)
+          if (!kd)
             val = lg == 2 ? (uint64_t)(int64_t)((const int32_t*)A.data)[idx] : (uint64_t)((const int64_t*)A.data)[idx];
           RSET(D.dst, val);
         }
@@ -368,7 +368,7 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
         const bool taken = RGET64(D.a) != 0;
         decide(taken ? 1ull : 0ull);
         if (abort_run) break;
-        if (!__ballot(act && taken)) pc = D.jmp;  // ELSE (its arm follows) or ENDIF
+        if (!__ballot(taken)) pc = D.jmp;  // ELSE (its arm follows) or ENDIF
         break;
       }
       case CKC_OP_ELSE: pc = D.jmp; break;
@@ -376,11 +376,12 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
       case CKC_OP_LOOP: {
         const uint32_t d = D.x;
         const uint64_t xa = RGET64(D.a), xb = RGET64(D.b), xc = RGET64(D.c);
-        if (act && w == 32 && (!fits32(xa) || !fits32(xb) || !fits32(xc))) wrapped = true;
+        if (w == 32 && (!fits32(xa) || !fits32(xb) || !fits32(xc))) wrapped = true;
         const int64_t s0 = (int64_t)narrow(xa, w), e0 = (int64_t)narrow(xb, w), st0 = (int64_t)narrow(xc, w);
-        const uint64_t nt = trip_count(s0, e0, st0);
-        decide(nt);
+        const uint64_t nt0 = trip_count(s0, e0, st0);
+        decide(nt0);
         if (abort_run) break;
+        const uint64_t nt = ufirst64(nt0);  // equal in every lane once decided
         const uint64_t cap = 1ull << (d == 0 ? in.cap_log2[0] : in.cap_log2[1]);
         const uint64_t rn = nt < cap ? nt : cap;
         run[d & 1] = rn; lstart[d & 1] = (uint64_t)s0; lstep[d & 1] = (uint64_t)st0;
@@ -412,7 +413,7 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
       }
       default: {
         const uint64_t x = RGET64(D.a), y = RGET64(D.b);
-        if (sl && act && op_wraps(op, w, x, y)) wrapped = true;
+        if (sl && op_wraps(op, w, x, y)) wrapped = true;
         uint32_t f = 0;
         RSET(D.dst, alu(op, w, x, y, f));
         break;
@@ -421,8 +422,7 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
     if (pc >= n) break;
     pc++;
   }
-  (void)actm;
-  const bool bad = abort_run || __ballot(act && wrapped) != 0;
+  const bool bad = abort_run || __ballot(wrapped) != 0;
   return bad ? 0u : 1u;
 }
 
