@@ -111,7 +111,9 @@ enum ckc_prog_class {
 
 typedef struct ckc_ctx_s* ckc_ctx;
 
-/* One context per HIP device.  Creates the context's stream-independent
+/* One context per HIP device: the counterpart of the runtime library the
+ * paper links every translated program with, whose thread pool runs the
+ * kernel's blocks (Section 4).  Creates the context's stream-independent
  * state; no kernel runs.  Errors: CKC_E_INVALID (no such device), CKC_E_HIP. */
 int ckc_init(int hip_device, ckc_ctx* out);
 /* Waits for outstanding work, frees every program, table and job. */
@@ -144,14 +146,19 @@ typedef struct ckc_access_info {
   uint64_t coef[7];
 } ckc_access_info;        /* 88 bytes */
 
-/* Host-only analysis of IR bytes (no device needed): validation, pruning,
- * classification.  info and acc (n_accesses entries) may be NULL.
+/* Host-only analysis of IR bytes (no device needed): validation, pruning of
+ * instructions that feed no index (Section 5.2, Algorithm 2), and the
+ * affine-access classification of every access (Section 5.1.1: an index is
+ * affine when it is a linear function of the thread and block indices with
+ * thread-invariant coefficients, the rows of the paper's matrix T).  info and acc (n_accesses entries) may be NULL.
  * Errors: CKC_E_IR with a message naming the offending instruction. */
 int ckc_analyze_ir(const void* ir, size_t ir_bytes, ckc_prog_info* info, ckc_access_info* acc,
                    uint32_t acc_capacity);
 
 /* Validates, analyses and lowers the program, and uploads its device form
- * once.  ir: host bytes in the ckc_ir.h layout (copied).  *prog_id receives a
+ * once: the compile-time half of the paper's flow (Section 4: the kernel
+ * translator's AXIPrune pass, then the PREX analysis, then the lowering that
+ * decides how threads are executed, Section 4.1).  ir: host bytes in the ckc_ir.h layout (copied).  *prog_id receives a
  * nonzero id.  info may be NULL.  Errors: CKC_E_IR, CKC_E_NOMEM, CKC_E_HIP. */
 int ckc_load_program(ckc_ctx ctx, const void* ir, size_t ir_bytes, uint32_t* prog_id,
                      ckc_prog_info* info);
@@ -171,7 +178,11 @@ typedef struct ckc_alloc {
   uint32_t pad;
 } ckc_alloc;            /* 32 bytes */
 
-/* Copies n (1..16) host entries into a device-resident table.  *table_id
+/* Copies n (1..16) host entries into a device-resident table.  Each entry
+ * is one buffer of the kernel's global memory with its exact base and size:
+ * the base-and-bounds metadata that the exact detectors of Section 7.1 keep
+ * (GPUShield, CuCatch, No-Fat), here per allocation slot; the FREED flag is
+ * the dangling-pointer case of Section 2.2 (temporal errors, Section 7.2.2).  *table_id
  * receives a nonzero id.  Errors: CKC_E_INVALID, CKC_E_NOMEM. */
 int ckc_put_alloc_table(ckc_ctx ctx, const ckc_alloc* entries, uint32_t n, uint32_t* table_id);
 /* CKC_E_BUSY while an unread job uses the table. */
@@ -216,8 +227,13 @@ typedef struct ckc_launch_opts {
   void* hip_stream;       /* hipStream_t; NULL = the context's own stream */
 } ckc_launch_opts;        /* 32 bytes; all zeros = defaults */
 
-/* Checks every input of every descriptor in one job (one planning pass and
- * one persistent evaluation over all of them).  Host arrays are copied before
+/* One fuzzing execution per input, for every input of every descriptor, in
+ * one job: the thread set of the chosen mode (Section 5.1, Algorithm 1 for
+ * CKC_REP_PREX) runs the program, every ACCESS/LOAD is checked against its
+ * allocation as an address sanitizer would (Section 2.1, exact bounds of
+ * Section 7.1), and every instrumented site counts into the input's coverage
+ * map (Section 2.1, the LLVM-PCGuard mode of Section 7.1).  One planning pass
+ * and one persistent evaluation cover all inputs.  Host arrays are copied before
  * the call returns; the work is queued on the stream and the call returns
  * without waiting.  Launch limits: block <= 1024 threads, grid < 2^32 blocks.
  * Errors: CKC_E_INVALID (ids, sizes, missing LOAD data), CKC_E_RANGE (key
@@ -226,6 +242,10 @@ typedef struct ckc_launch_opts {
 int ckc_check_batch(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_descs,
                     const ckc_launch_opts* opts, uint64_t* job);
 
+/* What the address sanitizer reports for one (input, access): a spatial
+ * violation (out of bounds below or above, Section 2.2) or a temporal one
+ * (NULL or freed allocation), here recorded and continued rather than aborted
+ * at, with the first one in sequential thread order. */
 typedef struct ckc_record {
   uint64_t first_key;   /* smallest (gtid << (L1+L2) | i1 << L2 | i2) that violated;
                            UINT64_MAX if none */
@@ -235,6 +255,9 @@ typedef struct ckc_record {
   uint32_t first_kind;  /* kind at first_key */
 } ckc_record;           /* 32 bytes */
 
+/* Per-input counters.  hang_lanes is the per-thread form of the paper's
+ * hang timeout (Section 7.1); arith_faults counts the division-by-zero kernel
+ * errors of Section 2.3.2. */
 typedef struct ckc_input_status {
   uint64_t lanes;            /* threads executed */
   uint64_t accesses_checked; /* ACCESS and LOAD executions */
@@ -245,7 +268,9 @@ typedef struct ckc_input_status {
 
 enum ckc_read_flags { CKC_WAIT = 1, CKC_DST_DEVICE = 2, CKC_ENQUEUE = 4 };
 
-/* Copies a job's results out and releases the job.  Inputs are numbered in
+/* Copies a job's results out and releases the job: the step at which a
+ * fuzzer reads the coverage data and the sanitizer's reports after each
+ * execution (Section 2.1).  The dense map is AFL's 64 KiB map.  Inputs are numbered in
  * descriptor order.  recs: [sum over inputs of n_accesses]; maps: [inputs][65536]
  * or NULL (requires CKC_DENSE_MAP); st: [inputs] or NULL.  With CKC_DST_DEVICE
  * the three pointers are device pointers (device-to-device copies on the
@@ -260,10 +285,13 @@ enum ckc_read_flags { CKC_WAIT = 1, CKC_DST_DEVICE = 2, CKC_ENQUEUE = 4 };
 int ckc_read_results(ckc_ctx ctx, uint64_t job, ckc_record* recs, uint8_t* maps,
                      ckc_input_status* st, uint32_t flags);
 
-/* Number of inputs and records of a job (for sizing result buffers). */
+/* Number of inputs and records of a job (for sizing result buffers;
+ * records are [inputs][accesses] as in ckc_read_results). */
 int ckc_job_sizes(ckc_ctx ctx, uint64_t job, uint64_t* n_inputs, uint64_t* n_records);
 
-/* Device timing of the job's stages in milliseconds (HIP events on the job's
+/* Device timing of the job's stages in milliseconds (the paper measures
+ * throughput as executions per second, Section 7.1; this splits one job's
+ * device time) (HIP events on the job's
  * stream; waits for the job): [0] planning (thread sets, traces, tile scan),
  * [1] trace evaluators, [2] interpreter over whole threads, [3] body passes of
  * expanded loops (piece scans, interpreted bodies, gather bodies), [4]
@@ -281,7 +309,11 @@ typedef struct ckc_tune_entry {
   uint32_t pad;
 } ckc_tune_entry;         /* 40 bytes */
 
-/* Times candidate launch options on this very batch and returns the fastest
+/* The paper maps blocks to CPU threads with a fixed thread pool
+ * (Section 4.1); on the GPU the equivalent choice is how persistent
+ * workgroups take tiles.  Times candidate launch options on the batch given
+ * (pass a batch other than the one to be measured to keep tuning and
+ * measurement apart) and returns the fastest
  * in *best.  Candidates: every schedule (BLOCKED, CYCLIC, DYNAMIC, LPT) x
  * chunk {1, 4, 16} x wg_per_cu {defaults, 2, 4, 8, 16}; `base` supplies
  * force_generic, use_graph and the stream (NULL = defaults).  Each candidate
@@ -294,6 +326,9 @@ int ckc_autotune(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_descs, const ck
                  uint32_t* n_log);
 
 /* ---- serving: a request loop with continuous batching ---------------------
+ * The paper's fuzzer runs one execution after another as a child process
+ * (Section 2.1) against a service that processes untrusted inputs
+ * (Section 3); here executions arrive as independent check jobs.
  * A server owns a worker thread that admits submitted check jobs in arrival
  * order while their device working set fits under a cap, packs the admitted
  * jobs into one batched check per free stream (jobs that arrive while others

@@ -190,7 +190,8 @@ __device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv D) {
 }
 
 // ---------------------------------------------------------------------------
-// thread sets (CKC_FULL, CKC_REP_CORNERS, CKC_REP_BOUNDARY)
+// thread sets (CKC_FULL, CKC_REP_CORNERS, CKC_REP_BOUNDARY, and MODE_PAIR: one
+// round of the PREX sweep)
 // ---------------------------------------------------------------------------
 struct Thr {
   uint32_t t[3], b[3];
@@ -338,11 +339,14 @@ __device__ __forceinline__ uint64_t bset_block(const uint32_t* L, uint64_t k) {
   return zbase + (uint64_t)y * s.gx + x;
 }
 
-__device__ __forceinline__ uint64_t set_lanes(uint32_t mode, const uint32_t* L) {
+// `aux` is the round r of a MODE_PAIR thread set (r <= nblocks-1-r) and is
+// unused otherwise.
+__device__ __forceinline__ uint64_t set_lanes(uint32_t mode, const uint32_t* L, uint32_t aux) {
   uint64_t nb = (uint64_t)L[0] * L[1] * L[2];
   uint64_t bs = (uint64_t)L[3] * L[4] * L[5];
   if (nb == 0 || bs == 0) return 0;
   if (mode == CKC_FULL) return nb * bs;
+  if (mode == MODE_PAIR) return (nb - 1 - aux == aux ? 1ull : 2ull) * bs;
   if (mode == CKC_REP_CORNERS) {
     uint64_t n = 1;
     for (int d = 0; d < 6; d++) n *= L[d] == 1 ? 1 : 2;
@@ -351,9 +355,18 @@ __device__ __forceinline__ uint64_t set_lanes(uint32_t mode, const uint32_t* L) 
   return bset_size(L) * bs;
 }
 
-// Thread of lane `l` (< set_lanes) of the input's thread set.
-__device__ __forceinline__ void decode_lane(uint32_t mode, const uint32_t* L, uint64_t l, Thr& th) {
+// Thread of lane `l` (< set_lanes) of the input's thread set.  A MODE_PAIR
+// set (round r = aux) holds block r, then block nblocks-1-r, each with all of
+// its threads in thread order, so lanes run in increasing global thread id as
+// in every other set.
+__device__ __forceinline__ void decode_lane(uint32_t mode, const uint32_t* L, uint32_t aux, uint64_t l, Thr& th) {
   uint32_t bs = L[3] * L[4] * L[5];
+  if (mode == MODE_PAIR) {
+    const uint64_t nb = (uint64_t)L[0] * L[1] * L[2];
+    const uint32_t half = l >= bs ? 1u : 0u;
+    thr_from(L, half ? nb - 1 - aux : (uint64_t)aux, (uint32_t)(l - (uint64_t)half * bs), th);
+    return;
+  }
   if (mode == CKC_REP_CORNERS) {
     uint32_t c[6];
     uint32_t v = (uint32_t)l;

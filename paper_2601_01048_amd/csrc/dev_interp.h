@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
   uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0;
   uint64_t tb = 0, cur_end = 0, sat = 0, cur_lanes = 0;
-  uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t cur_L[7] = {0, 0, 0, 0, 0, 0, 0};  // launch dims, then the PREX round
   Dec dec;
   Lane ln;
   lane_zero_totals(ln);
@@ -501,6 +501,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
       tb = ins[i].tile_begin[PATH_GENERIC];
       cur_end = tb + ins[i].n_tiles[PATH_GENERIC];
       for (int q = 0; q < 6; q++) cur_L[q] = ins[i].launch[q];
+      cur_L[6] = ins[i].aux;
       cur_mode = ins[i].mode;
       cur_lanes = ins[i].lanes;
       dec_make(dec, cur_L);
@@ -511,7 +512,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
     const bool act = l < cur_lanes;
     Thr T;
     if (cur_mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
-    else decode_lane(cur_mode, cur_L, act ? l : 0, T);
+    else decode_lane(cur_mode, cur_L, cur_L[6], act ? l : 0, T);
     Ctx C;
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
@@ -807,10 +808,11 @@ constexpr uint32_t GREG = 4;
 // flight together.  The loaded value of LOAD number d (1-based) for chunk q
 // lives in R row (d-1)*U + q, so the body's loads need U rows each.  A
 // violation (rare) is recorded by recomputing that chunk's key and index.
+// TS: the input's thread set -- launch dims, then the PREX round (MODE_PAIR).
 template <uint32_t U>
 __device__ __forceinline__ void gather_piece(GenLds& S, uint64_t* R, const Ctx& C, Lane& ln, uint64_t& sat,
                                              uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
-                                             const uint32_t* L6, uint32_t site_iter, uint32_t ctr_w) {
+                                             const uint32_t* TS, uint32_t site_iter, uint32_t ctr_w) {
   const uint32_t tid = threadIdx.x;
   const uint32_t n = S.gb.n;
   const uint32_t faults = S.gb.faults;
@@ -865,7 +867,7 @@ __device__ __forceinline__ void gather_piece(GenLds& S, uint64_t* R, const Ctx& 
         uint64_t gtid = l;
         if (mode != CKC_FULL) {
           Thr T;
-          decode_lane(mode, L6, l, T);
+          decode_lane(mode, TS, TS[6], l, T);
           gtid = T.gtid;
         }
         uint64_t v = off;
@@ -1017,7 +1019,7 @@ __device__ __forceinline__ void c32_stream(uint32_t* l, const void* data, uint32
 template <uint32_t U, bool FULL>
 __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C, uint64_t base, uint64_t it0,
                                           uint64_t it1, uint32_t d32, uint32_t n, uint64_t lane0, uint32_t mode,
-                                          const uint32_t* L6, bool run, uint32_t& mine, uint64_t& visits) {
+                                          const uint32_t* TS, bool run, uint32_t& mine, uint64_t& visits) {
   const uint32_t tid = threadIdx.x;
   uint32_t l1[U], l2[U];
   bool act[U];
@@ -1094,7 +1096,7 @@ __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C
       uint64_t gtid = l;
       if (mode != CKC_FULL) {
         Thr T;
-        decode_lane(mode, L6, l, T);
+        decode_lane(mode, TS, TS[6], l, T);
         gtid = T.gtid;
       }
       merge_vio_lds(S, e, kd, (gtid << C.Lsum) | (k << C.L2));
@@ -1112,7 +1114,7 @@ __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C
 template <bool BIG>
 __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
                                            uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
-                                           const uint32_t* L6, uint32_t site_iter, uint32_t d32, bool run) {
+                                           const uint32_t* TS, uint32_t site_iter, uint32_t d32, bool run) {
   constexpr uint32_t UL = 16, US = 8;  // R32 rows: at most 16
   const uint32_t n = S.gb.n, faults = S.gb.faults;
   uint64_t visits = 0;
@@ -1120,10 +1122,10 @@ __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& 
   uint64_t base = it0;
   if (BIG)
     for (; base + (uint64_t)TILE * UL <= it1; base += (uint64_t)TILE * UL)
-      c32_round<UL, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, L6, run, mine, visits);
+      c32_round<UL, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
   for (; base + (uint64_t)TILE * US <= it1; base += (uint64_t)TILE * US)
-    c32_round<US, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, L6, run, mine, visits);
-  if (base < it1) c32_round<US, false>(S, R32, C, base, it0, it1, d32, n, lane0, mode, L6, run, mine, visits);
+    c32_round<US, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
+  if (base < it1) c32_round<US, false>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
   // visits of the counter's site and of every entry's site
   const uint32_t vc = (uint32_t)(visits < 0xFFFFFFFFull ? visits : 0xFFFFFFFFull);
   count_site_n(S, C, sat, site_iter, vc);
@@ -1256,7 +1258,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; S.faults = 0; }
   uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0;
-  uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t cur_L[7] = {0, 0, 0, 0, 0, 0, 0};  // launch dims, then the PREX round
   uint64_t cur_xt = ~0ull, sat = 0, cur_xt_hint = ~0ull;
   Dec dec;
   Lane ln;
@@ -1279,6 +1281,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
       cur = i;
       cur_sites = ((c_dprog*)in.prog)->n_sites;
       for (int q = 0; q < 6; q++) cur_L[q] = in.launch[q];
+      cur_L[6] = in.aux;
       cur_mode = in.mode;
       dec_make(dec, cur_L);
     }
@@ -1311,7 +1314,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
       const uint64_t l = lane0 + o;
       Thr T;
       if (cur_mode != CKC_FULL) {
-        decode_lane(cur_mode, cur_L, l, T);
+        decode_lane(cur_mode, cur_L, cur_L[6], l, T);
       } else if (body_special) {
         decode_full(dec, l, T);
       } else {  // the body reads no thread coordinate
@@ -1361,7 +1364,7 @@ __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
     S.rmin[tid] = ~0ull;
   }
   uint32_t cur = 0xFFFFFFFFu, cur_sites = 0, built = 0, ok = 0, fast = 0, cur_mode = 0, cont = 0;
-  uint32_t cur_L[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t cur_L[7] = {0, 0, 0, 0, 0, 0, 0};  // launch dims, then the PREX round
   uint64_t cur_xt = ~0ull, sat = 0, xd = 0;
   uint64_t pb = 0, pe = 0;  // pieces of the current tile
   // the next tile of the same input, loaded while the current one runs:
@@ -1399,6 +1402,7 @@ __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
       built = 0;
       cur_sites = ((c_dprog*)in.prog)->n_sites;
       for (int q = 0; q < 6; q++) cur_L[q] = in.launch[q];
+      cur_L[6] = in.aux;
       cur_mode = in.mode;
     }
     const uint64_t lane0 = (xt - in.xt_begin) * TILE;
@@ -1547,7 +1551,7 @@ __global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
       uint64_t gtid = l;
       if (cur_mode != CKC_FULL) {
         Thr T;
-        decode_lane(cur_mode, cur_L, l, T);
+        decode_lane(cur_mode, cur_L, cur_L[6], l, T);
         gtid = T.gtid;
       }
       ln.dis = ga ? 0u : DEAD;

@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
       a.xpb[in.xt_begin + q] = 0;
       a.xpg[in.xt_begin + q] = 0;
     }
-  uint64_t lanes = set_lanes(in.mode, in.launch);
+  uint64_t lanes = set_lanes(in.mode, in.launch, in.aux);
   bool trace = (P->cls & CKC_CLS_UNIFORM) && !a.force_generic && in.trace != 0 && lanes > 0;
   __syncthreads();
   ckc_input_status* st = a.status + i;
@@ -456,7 +456,9 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
     st->lanes = lanes; st->accesses_checked = 0; st->hang_lanes = 0; st->arith_faults = 0;
     st->flags = 0; st->pad = 0;
   }
-  if (in.mode == CKC_REP_CORNERS || in.mode == CKC_REP_BOUNDARY) {
+  // the flag of the representative modes; a PREX sweep takes it from its
+  // first round
+  if (in.mode == CKC_REP_CORNERS || in.mode == CKC_REP_BOUNDARY || (in.mode == MODE_PAIR && in.aux == 0)) {
     const uint32_t f = vertex_flag(P, in, a.scalars + (size_t)i * MAX_SCALARS, (const ckc_alloc*)in.table, RG);
     if (j == 0) st->flags = f;
     __syncthreads();
@@ -478,7 +480,8 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
     uint64_t tiles = (lanes + TILE - 1) / TILE;
     const uint32_t bs = in.launch[3] * in.launch[4] * in.launch[5];
     if (path == 0) {
-      if (in.mode != CKC_REP_CORNERS && bs % 64u == 0 && ((const dtrace_head*)in.trace)->n_classes == 1) {
+      if ((in.mode == CKC_FULL || in.mode == CKC_REP_BOUNDARY) && bs % 64u == 0 &&
+          ((const dtrace_head*)in.trace)->n_classes == 1) {
         // block-major jobs: (64-thread slice position, ngj groups of LPB set blocks)
         const uint64_t nsb = in.mode == CKC_FULL ? (uint64_t)in.launch[0] * in.launch[1] * in.launch[2]
                                                  : bset_size(in.launch);
@@ -673,12 +676,108 @@ __global__ void __launch_bounds__(256) finish_kernel(KArgs a) {
     __syncthreads();
     const uint16_t* ids = prog_sites(P);
     uint8_t* mb = a.maps + (size_t)i * 65536;
-    for (uint32_t s = threadIdx.x; s < P->n_sites; s += blockDim.x) {
+    for (uint32_t s = threadIdx.x; s < P->n_map_sites; s += blockDim.x) {
       uint32_t c = cnt[s];
       mb[ids[s]] = (uint8_t)(c > 255 ? 255 : c);
     }
   }
 }
 
+// ---------------------------------------------------------------------------
+// PREX sweep (Algorithm 1): initial state and the fold of one window of rounds
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) prex_init_kernel(PrexArgs p) {
+  const uint32_t i = blockIdx.x;
+  if (i >= p.n_real) return;
+  const dinput& in = p.real_in[i];
+  const dprog* P = (const dprog*)in.prog;
+  const uint32_t j = threadIdx.x;
+  ckc_record* rec = p.real_recs + in.rec_base;
+  for (uint32_t r = j; r < P->n_accesses; r += 64) {
+    ckc_record z;
+    z.first_key = ~0ull; z.index = 0; z.count = 0; z.kinds = 0; z.first_kind = 0;
+    rec[r] = z;
+  }
+  uint32_t* cnt = p.real_counts + in.cnt_base;
+  for (uint32_t s = j; s < P->n_sites; s += 64) cnt[s] = 0;
+  if (j == 0) {
+    ckc_input_status* st = p.real_status + i;
+    st->lanes = 0; st->accesses_checked = 0; st->hang_lanes = 0; st->arith_faults = 0;
+    st->flags = 0; st->pad = 0;
+    p.stopped[i] = 0;
+  }
+}
+
+// One workgroup per item: the input's rounds of this window in round order.
+// Before each round, the test of Algorithm 1: the sweep stops once every
+// ACCESS/LOAD instruction has executed at least once (its site counter is
+// nonzero; every access has a site, internal if the program gave none) or
+// some access has violated.  A round's results are then added: counters as
+// saturating sums (a trace-path round counts per thread, times its lanes),
+// records by least first key, summed counts and OR of kinds (index and kind
+// at the least key are filled afterwards by replaying that thread), status
+// by sums.  The first round also carries the vertex flag.
+__global__ void __launch_bounds__(256) prex_merge_kernel(PrexArgs p) {
+  const uint32_t it = blockIdx.x;
+  if (it >= p.n_items) return;
+  const prex_item X = p.items[it];
+  const dinput& in = p.real_in[X.real];
+  const dprog* P = (const dprog*)in.prog;
+  const dins* I = prog_ins(P);
+  const daccess* A = prog_access(P);
+  ckc_record* rr = p.real_recs + in.rec_base;
+  uint32_t* rc = p.real_counts + in.cnt_base;
+  ckc_input_status* rs = p.real_status + X.real;
+  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t stop;
+  if (tid == 0) {
+    stop = p.stopped[X.real];
+    if (X.r0 == 0) rs->flags = p.vstatus[X.vbeg].flags;
+  }
+  __syncthreads();
+  for (uint32_t k = 0; k < X.vcnt; k++) {
+    if (stop) break;  // read after a barrier: the same in every lane
+    int miss = 0, bug = 0;
+    for (uint32_t q = tid; q < P->n_accesses; q += blockDim.x) {
+      if (rc[I[A[q].pc].s0] == 0) miss = 1;
+      if (rr[q].count != 0) bug = 1;
+    }
+    miss = __syncthreads_or(miss);
+    bug = __syncthreads_or(bug);
+    if (!miss || bug) {
+      if (tid == 0) stop = 1;
+      break;
+    }
+    const dinput& V = p.vin[X.vbeg + k];
+    const bool per_thread = V.path != PATH_GENERIC;
+    const uint64_t lanes = V.lanes;
+    const uint32_t* vc = p.vcounts + V.cnt_base;
+    for (uint32_t s = tid; s < P->n_sites; s += blockDim.x) {
+      uint64_t c = vc[s];
+      if (per_thread) c *= lanes;
+      const uint64_t t = (uint64_t)rc[s] + (c < 255 ? c : 255);
+      rc[s] = t < 255 ? (uint32_t)t : 255u;
+    }
+    const ckc_record* vr = p.vrecs + V.rec_base;
+    for (uint32_t q = tid; q < P->n_accesses; q += blockDim.x) {
+      const ckc_record v = vr[q];
+      if (v.count == 0) continue;
+      if (v.first_key < rr[q].first_key) rr[q].first_key = v.first_key;
+      rr[q].count += v.count;
+      rr[q].kinds |= v.kinds;
+    }
+    if (tid == 0) {
+      const ckc_input_status& vs = p.vstatus[X.vbeg + k];
+      rs->lanes += lanes;
+      rs->accesses_checked += per_thread ? vs.accesses_checked * lanes : vs.accesses_checked;
+      rs->arith_faults += per_thread ? vs.arith_faults * lanes : vs.arith_faults;
+      rs->hang_lanes += per_thread ? (vs.hang_lanes ? lanes : 0ull) : vs.hang_lanes;
+      if (X.r0 + k == X.last) stop = 1;  // every block has run
+    }
+    __syncthreads();  // the next round's test reads what this one wrote
+  }
+  __syncthreads();
+  if (tid == 0) p.stopped[X.real] = stop;
+}
 
 }  // namespace ckc

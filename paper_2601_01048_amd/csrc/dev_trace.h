@@ -316,8 +316,8 @@ __device__ __forceinline__ void trace_blocks(TraceLds& S, c_head* th, BT* w, uin
 
 // Per-input state of the trace evaluator over lane tiles (wavefront-uniform).
 struct TrIn {
-  uint32_t L[7];  // launch dims, then the thread-set mode
-  uint32_t mode, Lsum, ne, n_acc;
+  uint32_t L[6];  // launch dims
+  uint32_t mode, aux, Lsum, ne, n_acc;  // thread-set mode, its PREX round
   bool lds;
   c_entry* te;
   ckc_record* rec;
@@ -562,8 +562,8 @@ __device__ __forceinline__ void lanes_violation(TraceLds& S, c_entry* te, uint32
 __device__ __forceinline__ void tr_load(TrIn& I, c_input* ins, uint32_t i, ckc_record* recs, uint64_t& tb,
                                         uint32_t path, uint32_t& ncls, c_head*& th) {
   for (int q = 0; q < 6; q++) I.L[q] = ins[i].launch[q];
-  I.L[6] = ins[i].mode;
   I.mode = ins[i].mode;
+  I.aux = ins[i].aux;
   I.Lsum = ins[i].L1 + ins[i].L2;
   I.n_acc = ((c_dprog*)ins[i].prog)->n_accesses;
   I.lds = I.n_acc <= TR_ACC_LDS;
@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(TILE) eval_trace_lanes_kernel(KArgs a) {
     const uint64_t l = (t - tb) * TILE + tid;
     const bool act = l < lanes;
     Thr T;
-    decode_lane(I.mode, I.L, act ? l : 0, T);
+    decode_lane(I.mode, I.L, I.aux, act ? l : 0, T);
     const uint32_t c6[6] = {T.t[0], T.t[1], T.t[2], T.b[0], T.b[1], T.b[2]};
     // base of each coefficient class: sum of coefficient x coordinate,
     // skipping zero coefficients (uniform branches)

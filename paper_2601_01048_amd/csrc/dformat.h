@@ -58,7 +58,11 @@ struct dprog {
   uint32_t off_instr, off_consts, off_access, off_sites;  // byte offsets from the header
   uint32_t total_bytes;
   uint32_t body_gather;       // the expanded body is evaluated as a gather (entries)
-  uint32_t pad1[2];
+  uint32_t n_map_sites;       // sites 0..n_map_sites-1 have a coverage-map position
+                              // (site_ids); sites n_map_sites..n_sites-1 are internal:
+                              // one per ACCESS/LOAD written without a site, so that
+                              // every access instruction's execution is counted
+  uint32_t pad1;
 };
 
 // One input of a job (the global input list concatenates the descriptors).

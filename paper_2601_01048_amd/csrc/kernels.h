@@ -59,6 +59,37 @@ struct EvalGrid {
   uint32_t big_body;    // gather pass with 16-chunk rounds (inputs of many tiles)
 };
 
+// The PREX sweep (Algorithm 1) runs in windows of rounds.  A window is an
+// ordinary job whose inputs are (input, round r) pairs of thread set MODE_PAIR
+// with their own records, counters and status; after it, prex_merge folds each
+// input's rounds into the input's own results in round order, applying the
+// stop test of Algorithm 1 before every round.
+struct prex_item {
+  uint32_t real;   // index of the input (into PrexArgs.real_in)
+  uint32_t vbeg;   // its first round's input in the window's input list
+  uint32_t vcnt;   // consecutive rounds of the input in this window
+  uint32_t r0;     // round of vbeg
+  uint32_t last;   // last round of the whole sweep: ceil(nblocks / 2) - 1
+  uint32_t pad;
+};
+struct PrexArgs {
+  const dinput* real_in;
+  uint32_t n_real, n_items;
+  ckc_record* real_recs;
+  uint32_t* real_counts;
+  ckc_input_status* real_status;
+  uint32_t* stopped;          // per input: 1 once the sweep has stopped
+  const prex_item* items;     // [n_items]
+  const dinput* vin;          // the window's inputs
+  const ckc_record* vrecs;
+  const uint32_t* vcounts;
+  const ckc_input_status* vstatus;
+};
+// Clears the inputs' records, counters, status and stop flags.
+hipError_t launch_prex_init(const PrexArgs& p, hipStream_t s);
+// Folds one window into the inputs' results (one workgroup per item).
+hipError_t launch_prex_merge(const PrexArgs& p, hipStream_t s);
+
 hipError_t launch_plan(const KArgs& a, hipStream_t s);
 hipError_t launch_scan(const KArgs& a, hipStream_t s);
 hipError_t launch_eval_trace(const KArgs& a, const EvalGrid& eg, hipStream_t s);

@@ -46,6 +46,16 @@ namespace ckc {
 // ---------------------------------------------------------------------------
 // host-callable launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_prex_init(const PrexArgs& p, hipStream_t s) {
+  if (p.n_real == 0) return hipSuccess;
+  hipLaunchKernelGGL(prex_init_kernel, dim3(p.n_real), dim3(64), 0, s, p);
+  return hipGetLastError();
+}
+hipError_t launch_prex_merge(const PrexArgs& p, hipStream_t s) {
+  if (p.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(prex_merge_kernel, dim3(p.n_items), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
 hipError_t launch_plan(const KArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(plan_kernel, dim3(a.n_inputs), dim3(64), plan_lds_bytes(a), s, a);
   return hipGetLastError();

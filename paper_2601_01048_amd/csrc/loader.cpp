@@ -665,6 +665,7 @@ struct Analyzer {
     std::vector<int64_t> dconsts;
     std::vector<dins> out(m);
     std::vector<daccess> acc(n_accesses);
+    int n_internal = 0;
     // IFs enclosing the expanded loop are never skipped
     std::vector<char> noskip(n_instr, 0);
     if (expand_pc >= 0)
@@ -680,6 +681,8 @@ struct Analyzer {
       D.op = I.op;
       D.w = I.w;
       D.s0 = I.s0; D.s1 = I.s1;
+      if ((I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD) && I.s0 == CKC_IR_NO_SITE)
+        D.s0 = (uint16_t)(n_sites + n_internal++);  // internal site: counted, never mapped
       auto P = [&](uint16_t r) -> uint8_t { return r < n_regs && phys[r] >= 0 ? (uint8_t)phys[r] : 0; };
       switch (I.op) {
         case CKC_OP_CONST: {
@@ -728,7 +731,8 @@ struct Analyzer {
     h.n_instr = (uint32_t)m;
     h.n_consts = (uint32_t)dconsts.size();
     h.n_accesses = (uint32_t)n_accesses;
-    h.n_sites = (uint32_t)n_sites;
+    h.n_sites = (uint32_t)(n_sites + n_internal);
+    h.n_map_sites = (uint32_t)n_sites;
     h.n_slots = (uint32_t)n_slots;
     h.n_scalars = (uint32_t)n_scalars;
     h.max_depth = (uint32_t)max_depth;

@@ -164,7 +164,6 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
   const dprog* h = (const dprog*)P.L.blob.data();
   if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, dk + "scalars missing");
   if (B.mode > CKC_FULL_ENDPOINTS) return fail(CKC_E_INVALID, dk + "unknown mode");
-  if (B.mode == CKC_REP_PREX) return fail(CKC_E_INVALID, dk + "CKC_REP_PREX is not available yet");
   uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
   if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
   if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, dk + "loop cap above 2^32");
@@ -204,6 +203,356 @@ hipEvent_t ckc::rt::job_done_event(ckc_ctx c, uint64_t job) {
   auto it = c->jobs.find(job);
   return it == c->jobs.end() ? nullptr : it->second.ev[ckc::rt::NEV - 1];
 }
+
+namespace {
+
+// Inputs of one launch sequence (a job, or one window of a PREX sweep) staged
+// on the host: their descriptors with buffer offsets, scalars, work estimates,
+// and the sizes of the buffers they need.
+struct Stage {
+  std::vector<dinput> hin;
+  std::vector<int64_t> hsc;
+  std::vector<uint64_t> est;  // estimated work per input (LPT order)
+  uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
+  uint32_t max_regs = 1;                               // interpreter register file rows
+  uint64_t gen_tiles = 0;  // interpreter tiles (estimate from the launch shapes)
+  uint64_t n_records = 0, n_counts = 0, trace_bytes = 0;
+
+  // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;
+  // lanes_max: most lanes of its thread set; sc: the program's scalars.
+  void add(const dprog* h, dinput d, const int64_t* sc, uint64_t lanes_max, bool force_generic) {
+    max_regs = std::max(max_regs, h->n_regs);
+    d.rec_base = n_records;
+    d.cnt_base = n_counts;
+    n_records += h->n_accesses;
+    n_counts += h->n_sites;
+    const bool uniform = (h->cls & CKC_CLS_UNIFORM) && !force_generic;
+    if (uniform) {
+      d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
+      trace_bytes += ckc::trace_bytes(h->trace_cap);
+    }
+    if (h->expand_pc >= 0 && !uniform && lanes_max > 0) {
+      // expanded loop: thread-state arrays over at most lanes_max lanes
+      const uint64_t n_xt = (lanes_max + TILE - 1) / TILE;
+      d.xstate = xstate_bytes + 1;  // rebased after allocation
+      d.xt_begin = n_xtiles;
+      d.xn = n_xt * TILE;
+      d.n_xt = n_xt;
+      n_xtiles += n_xt;
+      n_xin++;
+      xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
+    }
+    hin.push_back(d);
+    est.push_back(lanes_max * (1 + h->n_accesses));
+    if (!uniform) gen_tiles += (lanes_max + TILE - 1) / TILE;
+    for (uint32_t s = 0; s < MAX_SCALARS; s++) hsc.push_back(s < h->n_scalars ? sc[s] : 0);
+  }
+};
+
+// Buffers of a staged launch sequence, allocated into J.
+struct StageBufs {
+  int64_t* sc = nullptr;
+  jobstate* js = nullptr;
+  uint8_t* tr = nullptr;
+  uint32_t* order = nullptr;
+  uint8_t* xs = nullptr;
+  unsigned long long *xtot = nullptr, *xpb = nullptr, *xpg = nullptr, *xbsum = nullptr, *xd = nullptr;
+  uint32_t* xin = nullptr;
+};
+
+// Allocates S's buffers into J (records, counters, status, maps when dense),
+// copies the inputs and fills a (kernel arguments) and eg (evaluator grid).
+int stage_upload(ckc_ctx c, Job& J, Stage& S, const ckc_launch_opts& O, bool dense, KArgs& a, EvalGrid& eg) {
+  const uint64_t n_inputs = S.hin.size();
+  StageBufs b;
+  // tile-space order of the inputs: as given, or largest first for LPT
+  std::vector<uint32_t> order(n_inputs);
+  for (uint64_t i = 0; i < n_inputs; i++) order[i] = (uint32_t)i;
+  if (O.schedule == CKC_SCHED_LPT)
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return S.est[x] > S.est[y]; });
+  int rc;
+  const uint64_t nx = S.n_xtiles;
+  if ((rc = dalloc(c, J, &J.d_inputs, n_inputs)) || (rc = dalloc(c, J, &b.sc, S.hsc.size())) ||
+      (rc = dalloc(c, J, &b.order, n_inputs)) ||
+      (nx && ((rc = dalloc(c, J, &b.xs, S.xstate_bytes)) || (rc = dalloc(c, J, &b.xtot, nx)) ||
+              (rc = dalloc(c, J, &b.xpb, nx)) || (rc = dalloc(c, J, &b.xpg, nx)) ||
+              (rc = dalloc(c, J, &b.xin, nx)) || (rc = dalloc(c, J, &b.xd, 2 * nx)) ||
+              (rc = dalloc(c, J, &b.xbsum, 2 * ((nx + 4095) / 4096))))) ||
+      (rc = dalloc(c, J, &J.d_recs, S.n_records)) || (rc = dalloc(c, J, &J.d_counts, S.n_counts)) ||
+      (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &b.js, 1)) ||
+      (rc = dalloc(c, J, &b.tr, S.trace_bytes)) || (dense && (rc = dalloc(c, J, &J.d_maps, n_inputs * 65536))))
+    return rc;
+  for (auto& d : S.hin) {
+    if (d.trace) d.trace = (uint64_t)(uintptr_t)(b.tr + (d.trace - 1));
+    if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(b.xs + (d.xstate - 1));
+  }
+  hipError_t e = hipMemcpyAsync(J.d_inputs, S.hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, J.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.sc, S.hsc.data(), sizeof(int64_t) * S.hsc.size(), hipMemcpyHostToDevice, J.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.order, order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, J.stream);
+  // the host arrays must outlive the copies: pageable copies are staged
+  // before hipMemcpyAsync returns, so S may be reused afterwards
+  if (e != hipSuccess) return fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e));
+  a.inputs = J.d_inputs;
+  a.scalars = b.sc;
+  a.n_inputs = (uint32_t)n_inputs;
+  a.force_generic = O.force_generic;
+  a.recs = J.d_recs;
+  a.counts = J.d_counts;
+  a.status = J.d_status;
+  a.maps = J.d_maps;
+  a.js = b.js;
+  a.order = b.order;
+  a.xtot = b.xtot;
+  a.xpb = b.xpb;
+  a.xpg = b.xpg;
+  a.xin = b.xin;
+  a.xd = b.xd;
+  a.xbsum = b.xbsum;
+  a.n_xtiles = nx;
+  a.max_regs = S.max_regs;
+  a.pad = 0;
+  a.sched = CKC_SCHED_DYNAMIC;
+  a.chunk = O.chunk ? O.chunk : 1u;
+  const uint32_t defwg[3] = {8, 4, 2};  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES
+  for (int p = 0; p < 3; p++) {
+    eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
+    eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);
+    // interpreter tiles: by default several per work item when there are
+    // plenty (each item costs a schedule step and a lookup of its input)
+    eg.chunk[p] = O.chunk ? O.chunk : (p == PATH_GENERIC && S.gen_tiles >= 16ull * eg.n_wg[p] ? 4u : 1u);
+  }
+  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
+  // body passes: pieces are near-equal work, and a workgroup walking one
+  // contiguous range of them finds each piece's tile by a step from the last
+  eg.sched_body = O.schedule ? O.schedule : CKC_SCHED_BLOCKED;
+  // long gather ranges (inputs of 64 tiles or more on average) take the
+  // variant with larger rounds
+  eg.big_body = S.n_xin != 0 && S.n_xtiles >= 64 * S.n_xin ? 1u : 0u;
+  return CKC_OK;
+}
+
+// Planning and every evaluator of a staged launch sequence (no replay, no
+// finishing), with the stage events ev[1..3] when ev is given.
+hipError_t launch_evaluation(const KArgs& a, const EvalGrid& eg, hipStream_t s, hipEvent_t* ev) {
+  hipError_t e = launch_plan(a, s);
+  if (e == hipSuccess) e = launch_scan(a, s);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = launch_eval_trace(a, eg, s);
+  if (e == hipSuccess) e = launch_eval_trace_lanes(a, eg, s);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
+  if (e == hipSuccess) e = launch_eval_generic(a, eg, s);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
+  if (e == hipSuccess) e = launch_expand(a, eg, s);
+  return e;
+}
+
+// Key bits of the loop depths a program uses, from a descriptor's caps.
+void key_bits(const ckc_batch& B, const dprog* h, uint32_t& c0, uint32_t& c1, unsigned& L1, unsigned& L2) {
+  c0 = B.loop_cap_log2[0];
+  c1 = B.loop_cap_log2[1];
+  if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
+  L1 = h->max_depth >= 1 ? c0 : 0;
+  L2 = h->max_depth >= 2 ? c1 : 0;
+}
+
+dinput input_of(const Program& P, const Table& T, const ckc_batch& B, uint32_t i) {
+  const dprog* h = (const dprog*)P.L.blob.data();
+  dinput d;
+  std::memset(&d, 0, sizeof d);
+  d.prog = (uint64_t)(uintptr_t)P.dblob;
+  d.table = (uint64_t)(uintptr_t)T.dptr;
+  for (int q = 0; q < 6; q++) d.launch[q] = B.launch[6 * (size_t)i + q];
+  uint32_t c0, c1;
+  unsigned L1, L2;
+  key_bits(B, h, c0, c1, L1, L2);
+  d.L1 = L1;
+  d.L2 = L2;
+  d.cap_log2[0] = c0;
+  d.cap_log2[1] = c1;
+  return d;
+}
+
+void mark_busy(ckc_ctx c, Job& J, const ckc_batch* descs, uint32_t n_descs) {
+  for (uint32_t k = 0; k < n_descs; k++) {
+    J.progs.push_back(descs[k].prog_id);
+    c->progs[descs[k].prog_id].busy++;
+    for (uint32_t i = 0; i < descs[k].n_inputs; i++) {
+      J.tables.push_back(descs[k].table_ids[i]);
+      c->tables[descs[k].table_ids[i]].busy++;
+    }
+  }
+}
+
+// Most (input, round) pairs and most lanes in one window of a PREX sweep.
+constexpr uint64_t PREX_WINDOW_PAIRS = 1ull << 18;
+constexpr uint64_t PREX_WINDOW_LANES = 1ull << 30;
+
+// CKC_REP_PREX: the sweep of Algorithm 1 over every input, in windows of
+// rounds (1, then 1, 2, 4, ... rounds per input), each an evaluation of
+// (input, round) pairs followed by the fold; the stop flags are read back
+// after each window to decide the next one.  Then the replay of first
+// violations and the finishing pass over the inputs themselves.
+int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts& O, uint64_t* job) {
+  Stage R;  // the inputs themselves
+  std::vector<uint32_t> rounds;  // ceil(nblocks / 2) per input (0: empty grid)
+  std::vector<const dprog*> heads;
+  for (uint32_t k = 0; k < n_descs; k++) {
+    const ckc_batch& B = descs[k];
+    const Program& P = c->progs.find(B.prog_id)->second;
+    const dprog* h = (const dprog*)P.L.blob.data();
+    for (uint32_t i = 0; i < B.n_inputs; i++) {
+      const Table& T = c->tables.find(B.table_ids[i])->second;
+      dinput d = input_of(P, T, B, i);
+      d.mode = CKC_REP_PREX;
+      d.path = PATH_GENERIC;  // results arrive folded: the finishing pass only builds maps
+      const uint32_t* L = d.launch;
+      const uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
+      rounds.push_back(nb == 0 || bs == 0 ? 0u : (uint32_t)((nb + 1) / 2));
+      heads.push_back(h);
+      // the inputs need no trace or loop state of their own
+      R.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, 0, true);
+    }
+  }
+  const uint64_t n_inputs = R.hin.size();
+  if (n_inputs == 0) return fail(CKC_E_INVALID, "no inputs");
+  if (n_inputs > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "too many inputs");
+  int rc;
+  if ((rc = set_device(c))) return rc;
+  reap(c, false);
+  Job J;
+  J.n_inputs = n_inputs;
+  J.n_records = R.n_records;
+  J.stream = O.hip_stream ? (hipStream_t)O.hip_stream : c->stream;
+  J.dense = false;
+  for (uint32_t k = 0; k < n_descs; k++) J.dense |= (descs[k].flags & CKC_DENSE_MAP) != 0;
+  auto bail = [&](int code) {
+    hipStreamSynchronize(J.stream);
+    free_job(c, J);
+    return code;
+  };
+  KArgs a;
+  EvalGrid eg;
+  uint32_t* d_stop = nullptr;
+  prex_item* d_items = nullptr;
+  if ((rc = stage_upload(c, J, R, O, J.dense, a, eg)) || (rc = dalloc(c, J, &d_stop, n_inputs)) ||
+      (rc = dalloc(c, J, &d_items, std::min<uint64_t>(n_inputs, PREX_WINDOW_PAIRS))))
+    return bail(rc);
+  std::vector<uint32_t> h_stop(n_inputs, 0);
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < ckc::rt::NEV && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
+  if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("events: ") + hipGetErrorString(e)));
+  PrexArgs p;
+  std::memset(&p, 0, sizeof p);
+  p.real_in = a.inputs;
+  p.n_real = (uint32_t)n_inputs;
+  p.real_recs = a.recs;
+  p.real_counts = a.counts;
+  p.real_status = a.status;
+  p.stopped = d_stop;
+  p.items = d_items;
+  e = hipEventRecord(J.ev[0], J.stream);
+  if (e == hipSuccess) e = launch_prex_init(p, J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
+  if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));
+  // inputs whose sweep goes on, and the next round of each
+  std::vector<uint32_t> active, next(n_inputs, 0);
+  for (uint64_t i = 0; i < n_inputs; i++)
+    if (rounds[i]) active.push_back((uint32_t)i);
+  ckc_launch_opts WO = O;
+  WO.use_graph = 0;
+  uint64_t per = 1;   // rounds per input in the current pass over the active inputs
+  size_t cursor = 0;  // first active input of the next window
+  while (!active.empty()) {
+    Stage W;
+    std::vector<prex_item> items;
+    uint64_t lanes = 0;
+    size_t end = cursor;
+    for (; end < active.size(); end++) {
+      const uint32_t i = active[end];
+      const dinput& d = R.hin[i];
+      const uint64_t bs2 = 2ull * d.launch[3] * d.launch[4] * d.launch[5];
+      // window limits; every window takes at least one round of one input
+      const uint64_t room = std::min<uint64_t>(PREX_WINDOW_PAIRS - W.hin.size(),
+                                               lanes < PREX_WINDOW_LANES ? (PREX_WINDOW_LANES - lanes) / bs2 : 0);
+      if (room == 0 && !items.empty()) break;
+      const uint64_t n = std::max<uint64_t>(1, std::min<uint64_t>({per, (uint64_t)(rounds[i] - next[i]), room}));
+      prex_item X;
+      X.real = i;
+      X.vbeg = (uint32_t)W.hin.size();
+      X.vcnt = (uint32_t)n;
+      X.r0 = next[i];
+      X.last = rounds[i] - 1;
+      X.pad = 0;
+      items.push_back(X);
+      const int64_t* sc = &R.hsc[(size_t)i * MAX_SCALARS];
+      for (uint64_t r = 0; r < n; r++) {
+        dinput v = d;
+        v.rec_base = v.cnt_base = 0;
+        v.trace = v.xstate = v.xt_begin = v.xn = v.n_xt = 0;
+        v.mode = MODE_PAIR;
+        v.aux = next[i] + (uint32_t)r;
+        v.path = 0;
+        W.add(heads[i], v, sc, bs2, O.force_generic != 0);
+        lanes += bs2;
+      }
+    }
+    // the window's buffers live until its stop flags have been read back
+    Job WJ;
+    WJ.stream = J.stream;
+    KArgs wa;
+    EvalGrid weg;
+    if ((rc = stage_upload(c, WJ, W, WO, false, wa, weg))) {
+      free_job(c, WJ);
+      return bail(rc);
+    }
+    p.n_items = (uint32_t)items.size();
+    p.vin = wa.inputs;
+    p.vrecs = wa.recs;
+    p.vcounts = wa.counts;
+    p.vstatus = wa.status;
+    e = hipMemcpyAsync(d_items, items.data(), sizeof(prex_item) * items.size(), hipMemcpyHostToDevice, J.stream);
+    if (e == hipSuccess) e = launch_evaluation(wa, weg, J.stream, nullptr);
+    if (e == hipSuccess) e = launch_prex_merge(p, J.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_stop.data(), d_stop, sizeof(uint32_t) * n_inputs, hipMemcpyDeviceToHost, J.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(J.stream);
+    free_job(c, WJ);
+    if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("PREX window: ") + hipGetErrorString(e)));
+    // inputs of this window move on or drop out; the others wait their turn
+    for (const prex_item& X : items) next[X.real] += X.vcnt;
+    std::vector<uint32_t> still;
+    size_t new_cursor = 0;
+    for (size_t q = 0; q < active.size(); q++) {
+      const uint32_t i = active[q];
+      if (q == end) new_cursor = still.size();
+      if (q >= cursor && q < end && (h_stop[i] || next[i] >= rounds[i])) continue;
+      still.push_back(i);
+    }
+    if (end == active.size()) {  // a whole pass: the next one takes twice the rounds
+      cursor = 0;
+      per *= 2;
+    } else {
+      cursor = new_cursor;
+    }
+    active.swap(still);
+  }
+  e = hipEventRecord(J.ev[2], J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
+  if (e == hipSuccess) e = launch_fixup(a, R.n_records, J.stream);
+  if (e == hipSuccess) e = launch_finish(a, J.stream);
+  if (e == hipSuccess) e = hipEventRecord(J.ev[ckc::rt::NEV - 1], J.stream);
+  if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));
+  mark_busy(c, J, descs, n_descs);
+  uint64_t id = c->next_job++;
+  c->jobs.emplace(id, std::move(J));
+  *job = id;
+  return CKC_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -335,66 +684,33 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   if (O.chunk > 256) return fail(CKC_E_INVALID, "chunk above 256 tiles");
   if (O.wg_per_cu > 32) return fail(CKC_E_INVALID, "wg_per_cu above 32");
   // ---- validate and build the input list on the host (copies only) ----
-  std::vector<dinput> hin;
-  std::vector<int64_t> hsc;
-  std::vector<uint64_t> est;  // estimated work per input (LPT order)
-  uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
-  uint32_t max_regs = 1;                     // interpreter register file rows
-  uint64_t gen_tiles = 0;                    // interpreter tiles (estimate from the launch shapes)
-  uint64_t n_inputs = 0, n_records = 0, n_counts = 0, trace_bytes = 0;
+  uint32_t n_prex = 0;
+  for (uint32_t k = 0; k < n_descs; k++) {
+    int vr = ckc::rt::validate_desc(c, descs[k], k, O.force_generic != 0, nullptr);
+    if (vr != CKC_OK) return vr;
+    n_prex += descs[k].mode == CKC_REP_PREX;
+  }
+  if (n_prex && n_prex != n_descs)
+    return fail(CKC_E_INVALID, "a job holds CKC_REP_PREX descriptors only, or none");
+  if (n_prex) return check_prex(c, descs, n_descs, O, job);
+  Stage S;
   for (uint32_t k = 0; k < n_descs; k++) {
     const ckc_batch& B = descs[k];
-    int vr = ckc::rt::validate_desc(c, B, k, O.force_generic != 0, nullptr);
-    if (vr != CKC_OK) return vr;
     const Program& P = c->progs.find(B.prog_id)->second;
     const dprog* h = (const dprog*)P.L.blob.data();
-    uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
-    if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
-    unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
-    max_regs = std::max(max_regs, h->n_regs);
     for (uint32_t i = 0; i < B.n_inputs; i++) {
-      const uint32_t* L = B.launch + 6 * (size_t)i;
-      const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
       const Table& T = c->tables.find(B.table_ids[i])->second;
-      dinput d;
-      std::memset(&d, 0, sizeof d);
-      d.prog = (uint64_t)(uintptr_t)P.dblob;
-      d.table = (uint64_t)(uintptr_t)T.dptr;
-      for (int q = 0; q < 6; q++) d.launch[q] = L[q];
+      dinput d = input_of(P, T, B, i);
       d.mode = B.mode == CKC_FULL_ENDPOINTS ? CKC_FULL : B.mode;
       d.aux = B.mode == CKC_FULL_ENDPOINTS ? 1u : 0u;
-      d.L1 = L1;
-      d.L2 = L2;
-      d.cap_log2[0] = c0;
-      d.cap_log2[1] = c1;
-      d.rec_base = n_records;
-      d.cnt_base = n_counts;
-      n_records += h->n_accesses;
-      n_counts += h->n_sites;
-      if ((h->cls & CKC_CLS_UNIFORM) && !O.force_generic) {
-        d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
-        trace_bytes += ckc::trace_bytes(h->trace_cap);
-      }
-      if (h->expand_pc >= 0 && (!(h->cls & CKC_CLS_UNIFORM) || O.force_generic) && nthr > 0) {
-        // expanded loop: thread-state arrays over at most nthr lanes (64 for corners)
-        const uint64_t lanes_max = B.mode == CKC_REP_CORNERS ? std::min<uint64_t>(nthr, 64) : nthr;
-        const uint64_t n_xt = (lanes_max + TILE - 1) / TILE;
-        d.xstate = xstate_bytes + 1;  // rebased after allocation
-        d.xt_begin = n_xtiles;
-        d.xn = n_xt * TILE;
-        d.n_xt = n_xt;
-        n_xtiles += n_xt;
-        n_xin++;
-        xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
-      }
-      hin.push_back(d);
-      est.push_back(nthr * (1 + h->n_accesses));
-      if (!(h->cls & CKC_CLS_UNIFORM) || O.force_generic) gen_tiles += (nthr + TILE - 1) / TILE;
-      for (uint32_t s = 0; s < MAX_SCALARS; s++)
-        hsc.push_back(s < h->n_scalars ? B.scalars[(size_t)i * h->n_scalars + s] : 0);
-      n_inputs++;
+      const uint32_t* L = d.launch;
+      const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
+      // most lanes of the thread set (the corner set has at most 64)
+      const uint64_t lanes_max = B.mode == CKC_REP_CORNERS ? std::min<uint64_t>(nthr, 64) : nthr;
+      S.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, lanes_max, O.force_generic != 0);
     }
   }
+  const uint64_t n_inputs = S.hin.size();
   if (n_inputs == 0) return fail(CKC_E_INVALID, "no inputs");
   if (n_inputs > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "too many inputs");
   int rc;
@@ -402,118 +718,35 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   reap(c, false);
   Job J;
   J.n_inputs = n_inputs;
-  J.n_records = n_records;
+  J.n_records = S.n_records;
   J.stream = O.hip_stream ? (hipStream_t)O.hip_stream : c->stream;
   J.dense = false;
   for (uint32_t k = 0; k < n_descs; k++) J.dense |= (descs[k].flags & CKC_DENSE_MAP) != 0;
-  int64_t* d_sc = nullptr;
-  jobstate* d_js = nullptr;
-  uint8_t* d_tr = nullptr;
-  uint32_t* d_order = nullptr;
-  uint8_t* d_xs = nullptr;
-  unsigned long long *d_xtot = nullptr, *d_xpb = nullptr, *d_xpg = nullptr, *d_xbsum = nullptr;
-  uint32_t* d_xin = nullptr;
-  unsigned long long* d_xd = nullptr;
-  // tile-space order of the inputs: as given, or largest first for LPT
-  std::vector<uint32_t> order(n_inputs);
-  for (uint64_t i = 0; i < n_inputs; i++) order[i] = (uint32_t)i;
-  if (O.schedule == CKC_SCHED_LPT)
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return est[x] > est[y]; });
-  if ((rc = dalloc(c, J, &J.d_inputs, n_inputs)) || (rc = dalloc(c, J, &d_sc, hsc.size())) ||
-      (rc = dalloc(c, J, &d_order, n_inputs)) ||
-      (n_xtiles && ((rc = dalloc(c, J, &d_xs, xstate_bytes)) || (rc = dalloc(c, J, &d_xtot, n_xtiles)) ||
-                    (rc = dalloc(c, J, &d_xpb, n_xtiles)) || (rc = dalloc(c, J, &d_xpg, n_xtiles)) ||
-                    (rc = dalloc(c, J, &d_xin, n_xtiles)) || (rc = dalloc(c, J, &d_xd, 2 * n_xtiles)) ||
-                    (rc = dalloc(c, J, &d_xbsum, 2 * ((n_xtiles + 4095) / 4096))))) ||
-      (rc = dalloc(c, J, &J.d_recs, n_records)) || (rc = dalloc(c, J, &J.d_counts, n_counts)) ||
-      (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &d_js, 1)) ||
-      (rc = dalloc(c, J, &d_tr, trace_bytes)) ||
-      (J.dense && (rc = dalloc(c, J, &J.d_maps, n_inputs * 65536)))) {
-    free_job(c, J);
-    return rc;
-  }
-  for (auto& d : hin) {
-    if (d.trace) d.trace = (uint64_t)(uintptr_t)(d_tr + (d.trace - 1));
-    if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(d_xs + (d.xstate - 1));
-  }
   auto bail = [&](int code) {
     hipStreamSynchronize(J.stream);
     free_job(c, J);
     return code;
   };
-  hipError_t e = hipMemcpyAsync(J.d_inputs, hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, J.stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_sc, hsc.data(), sizeof(int64_t) * hsc.size(), hipMemcpyHostToDevice, J.stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_order, order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, J.stream);
+  KArgs a;
+  EvalGrid eg;
+  if ((rc = stage_upload(c, J, S, O, J.dense, a, eg))) return bail(rc);
+  hipError_t e = hipSuccess;
   for (int q = 0; q < ckc::rt::NEV && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e)));
-  KArgs a;
-  a.inputs = J.d_inputs;
-  a.scalars = d_sc;
-  a.n_inputs = (uint32_t)n_inputs;
-  a.force_generic = O.force_generic;
-  a.recs = J.d_recs;
-  a.counts = J.d_counts;
-  a.status = J.d_status;
-  a.maps = J.d_maps;
-  a.js = d_js;
-  a.order = d_order;
-  a.xtot = d_xtot;
-  a.xpb = d_xpb;
-  a.xpg = d_xpg;
-  a.xin = d_xin;
-  a.xd = d_xd;
-  a.xbsum = d_xbsum;
-  a.n_xtiles = n_xtiles;
-  a.max_regs = max_regs;
-  a.pad = 0;
-  a.sched = CKC_SCHED_DYNAMIC;
-  a.chunk = O.chunk ? O.chunk : 1u;
-  EvalGrid eg;
-  const uint32_t defwg[3] = {8, 4, 2};  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES
-  for (int p = 0; p < 3; p++) {
-    eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
-    eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);
-    // interpreter tiles: by default several per work item when there are
-    // plenty (each item costs a schedule step and a lookup of its input)
-    eg.chunk[p] = O.chunk ? O.chunk : (p == PATH_GENERIC && gen_tiles >= 16ull * eg.n_wg[p] ? 4u : 1u);
-  }
-  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
-  // body passes: pieces are near-equal work, and a workgroup walking one
-  // contiguous range of them finds each piece's tile by a step from the last
-  eg.sched_body = O.schedule ? O.schedule : CKC_SCHED_BLOCKED;
-  // long gather ranges (inputs of 64 tiles or more on average) take the
-  // variant with larger rounds
-  eg.big_body = n_xin != 0 && n_xtiles >= 64 * n_xin ? 1u : 0u;
   J.graph = O.use_graph != 0;
   e = hipEventRecord(J.ev[0], J.stream);
   if (J.graph) {
-    if (e == hipSuccess) e = launch_graph(c, a, eg, n_records, J.stream);
+    if (e == hipSuccess) e = launch_graph(c, a, eg, S.n_records, J.stream);
     for (int q = 1; q < ckc::rt::NEV - 1 && e == hipSuccess; q++) e = hipEventRecord(J.ev[q], J.stream);
   } else {
-    if (e == hipSuccess) e = launch_plan(a, J.stream);
-    if (e == hipSuccess) e = launch_scan(a, J.stream);
-    if (e == hipSuccess) e = hipEventRecord(J.ev[1], J.stream);
-    if (e == hipSuccess) e = launch_eval_trace(a, eg, J.stream);
-    if (e == hipSuccess) e = launch_eval_trace_lanes(a, eg, J.stream);
-    if (e == hipSuccess) e = hipEventRecord(J.ev[2], J.stream);
-    if (e == hipSuccess) e = launch_eval_generic(a, eg, J.stream);
-    if (e == hipSuccess) e = hipEventRecord(J.ev[3], J.stream);
-    if (e == hipSuccess) e = launch_expand(a, eg, J.stream);
+    if (e == hipSuccess) e = launch_evaluation(a, eg, J.stream, J.ev);
     if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
-    if (e == hipSuccess) e = launch_fixup(a, n_records, J.stream);
+    if (e == hipSuccess) e = launch_fixup(a, S.n_records, J.stream);
     if (e == hipSuccess) e = launch_finish(a, J.stream);
   }
   if (e == hipSuccess) e = hipEventRecord(J.ev[ckc::rt::NEV - 1], J.stream);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e)));
-  for (uint32_t k = 0; k < n_descs; k++) {
-    J.progs.push_back(descs[k].prog_id);
-    c->progs[descs[k].prog_id].busy++;
-    for (uint32_t i = 0; i < descs[k].n_inputs; i++) {
-      J.tables.push_back(descs[k].table_ids[i]);
-      c->tables[descs[k].table_ids[i]].busy++;
-    }
-  }
+  mark_busy(c, J, descs, n_descs);
   uint64_t id = c->next_job++;
   c->jobs.emplace(id, std::move(J));
   *job = id;

@@ -274,6 +274,9 @@ void ckc_server_destroy(ckc_server s) {
 int ckc_server_submit(ckc_server s, const ckc_batch* desc, uint64_t arrival_ns, uint64_t* ticket) {
   if (!s || !desc || !ticket) return ckc::rt::fail(CKC_E_INVALID, "NULL argument");
   if (desc->n_inputs == 0) return ckc::rt::fail(CKC_E_INVALID, "no inputs");
+  // the sweep decides its rounds on the host between windows, which would
+  // hold the worker: served jobs use the other thread sets
+  if (desc->mode == CKC_REP_PREX) return ckc::rt::fail(CKC_E_INVALID, "CKC_REP_PREX jobs are not served");
   SJob J;
   uint64_t ws = 0;
   {
