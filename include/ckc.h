@@ -302,6 +302,41 @@ int ckc_job_timing(ckc_ctx ctx, uint64_t job, float* ms5);
  * milliseconds; waits for the job.  Errors: CKC_E_INVALID (unknown job). */
 int ckc_job_elapsed(ckc_ctx ctx, uint64_t job, float* ms);
 
+/* ---- checking without allocation ------------------------------------------
+ * For callers that cannot allocate device memory: code that runs under HIP
+ * graph capture, tight serving loops, and harnesses that forbid hipMalloc. */
+#define CKC_NOALLOC_SCRATCH_BYTES (64u << 20) /* static scratch of the library, per device */
+#define CKC_NOALLOC_MAX_INPUTS 4096u          /* inputs per call, over all descriptors */
+
+/* The work of ckc_check_batch followed by ckc_read_results with
+ * CKC_DST_DEVICE, in one call that allocates nothing: no hipMalloc or
+ * hipFree, no pooled job buffer, no event, no graph, no host heap (host
+ * staging arrays are reserved by ckc_init).  The job's internal buffers (input
+ * descriptors, scalars, per-site counters, access traces, the loop state of
+ * expanded loops) are consecutive pieces of one static device array of
+ * CKC_NOALLOC_SCRATCH_BYTES, held by every device the library runs on until
+ * the process ends; records, maps and status are written straight into the
+ * caller's device buffers.  Results are identical to ckc_check_batch's.
+ *   recs: device [sum over inputs of n_accesses] records (required);
+ *   maps: device [inputs][65536] when some descriptor has CKC_DENSE_MAP, else
+ *         NULL;
+ *   st:   device [inputs] status (required).
+ * The work is queued on opts->hip_stream (NULL: the context's stream) and the
+ * call returns without waiting; the outputs are valid once that stream has
+ * completed it.  Every call on a device shares that device's scratch, which
+ * keeps the last call's contents: calls queued on one stream run in order,
+ * but calls that overlap on one device (other streams, other contexts of the
+ * same device) race and their results are undefined.  Programs and tables
+ * are not marked in use: keep them loaded until the stream has completed.
+ * Not available here: CKC_REP_PREX (its sweep reads stop flags back between
+ * rounds) and use_graph.
+ * Errors: as ckc_check_batch, plus CKC_E_INVALID (more than
+ * CKC_NOALLOC_MAX_INPUTS inputs, recs or st NULL, maps NULL with dense maps
+ * requested or given without, CKC_REP_PREX, use_graph) and CKC_E_NOMEM when
+ * the batch's buffers do not fit in the scratch; nothing is queued then. */
+int ckc_check_batch_noalloc(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts* opts,
+                            ckc_record* recs, uint8_t* maps, ckc_input_status* st);
+
 /* ---- autotuning of the persistent launch ---------------------------------- */
 typedef struct ckc_tune_entry {
   ckc_launch_opts opts;   /* candidate (hip_stream as passed in base) */

@@ -111,6 +111,7 @@ def lib():
         L.ckc_put_alloc_table.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         L.ckc_free_alloc_table.argtypes = [vp, u32]
         L.ckc_check_batch.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u64)]
+        L.ckc_check_batch_noalloc.argtypes = [vp, vp, u32, vp, vp, vp, vp]
         L.ckc_read_results.argtypes = [vp, u64, vp, vp, vp, u32]
         L.ckc_job_sizes.argtypes = [vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.ckc_job_timing.argtypes = [vp, u64, vp]
@@ -123,7 +124,7 @@ def lib():
         L.ckc_server_result.argtypes = [vp, u64, vp, vp, vp, vp, u32]
         L.ckc_server_get_stats.argtypes = [vp, vp]
         for f in ("ckc_init", "ckc_analyze_ir", "ckc_load_program", "ckc_unload_program",
-                  "ckc_put_alloc_table", "ckc_free_alloc_table", "ckc_check_batch",
+                  "ckc_put_alloc_table", "ckc_free_alloc_table", "ckc_check_batch", "ckc_check_batch_noalloc",
                   "ckc_read_results", "ckc_job_sizes", "ckc_job_timing", "ckc_job_elapsed",
                   "ckc_autotune", "ckc_server_create", "ckc_server_submit", "ckc_server_result",
                   "ckc_server_get_stats"):
@@ -226,6 +227,16 @@ class Context:
         _check(lib().ckc_check_batch(self.h, arr, len(arr), ctypes.byref(opts), ctypes.byref(job)))
         del keep
         return job.value
+
+    def check_noalloc(self, descs, recs_ptr: int, maps_ptr: int | None, st_ptr: int,
+                      opts: LaunchOpts | None = None):
+        """ckc_check_batch_noalloc: queues the check of ``descs`` with results
+        written to the given device buffers; allocates nothing.  The results
+        are valid once the context's stream (or the device) is synchronized."""
+        arr, keep = descs if isinstance(descs, tuple) else self.prepare(descs)
+        _check(lib().ckc_check_batch_noalloc(self.h, arr, len(arr), ctypes.byref(opts) if opts else None,
+                                             recs_ptr, maps_ptr, st_ptr))
+        del keep
 
     def elapsed(self, job: int) -> float:
         ms = ctypes.c_float()

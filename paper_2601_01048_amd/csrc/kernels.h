@@ -104,4 +104,8 @@ hipError_t launch_finish(const KArgs& a, hipStream_t s);
 // branches) -> first-violation replay -> finishing.
 hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uint64_t n_records);
 
+// Device address of the static scratch array (CKC_NOALLOC_SCRATCH_BYTES) on
+// device dev, which must be the current device; looked up once per device.
+hipError_t scratch_address(int dev, void** out);
+
 }  // namespace ckc

@@ -35,13 +35,40 @@
 #include "kernels.h"
 
 #include <cstring>
+#include <mutex>
 
 #include "dev_common.h"
 #include "dev_plan.h"
 #include "dev_trace.h"
 #include "dev_interp.h"
 
+// Buffers of ckc_check_batch_noalloc: one static array per device, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host it names a stand-in, not device memory): it uses the address that
+// scratch_address looked up for the device.
+static __device__ __align__(256) uint8_t scratch[CKC_NOALLOC_SCRATCH_BYTES];
+
 namespace ckc {
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];
+}  // namespace
+
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // host-callable launchers

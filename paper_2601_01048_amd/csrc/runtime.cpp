@@ -21,6 +21,7 @@
 using namespace ckc;
 using ckc::rt::Job;
 using ckc::rt::Program;
+using ckc::rt::Stage;
 using ckc::rt::Table;
 using ckc::rt::fail;
 
@@ -156,37 +157,38 @@ hipError_t launch_graph(ckc_ctx c, const KArgs& a, const EvalGrid& eg, uint64_t 
 }  // namespace
 
 int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force_generic, uint64_t* ws_bytes) {
-  const std::string dk = "descriptor " + std::to_string(k) + ": ";
+  // messages are built only on failure (a valid batch allocates nothing here)
+  auto dk = [&]() { return "descriptor " + std::to_string(k) + ": "; };
   auto pit = c->progs.find(B.prog_id);
-  if (pit == c->progs.end()) return fail(CKC_E_INVALID, dk + "unknown program");
-  if (B.n_inputs && (!B.launch || !B.table_ids)) return fail(CKC_E_INVALID, dk + "arrays missing");
+  if (pit == c->progs.end()) return fail(CKC_E_INVALID, dk() + "unknown program");
+  if (B.n_inputs && (!B.launch || !B.table_ids)) return fail(CKC_E_INVALID, dk() + "arrays missing");
   const Program& P = pit->second;
   const dprog* h = (const dprog*)P.L.blob.data();
-  if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, dk + "scalars missing");
-  if (B.mode > CKC_FULL_ENDPOINTS) return fail(CKC_E_INVALID, dk + "unknown mode");
+  if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, dk() + "scalars missing");
+  if (B.mode > CKC_FULL_ENDPOINTS) return fail(CKC_E_INVALID, dk() + "unknown mode");
   uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
   if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
-  if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, dk + "loop cap above 2^32");
+  if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, dk() + "loop cap above 2^32");
   unsigned L1 = h->max_depth >= 1 ? c0 : 0, L2 = h->max_depth >= 2 ? c1 : 0;
   uint64_t ws = 0;
   for (uint32_t i = 0; i < B.n_inputs; i++) {
-    const std::string di = dk + "input " + std::to_string(i) + ": ";
+    auto di = [&]() { return dk() + "input " + std::to_string(i) + ": "; };
     const uint32_t* L = B.launch + 6 * (size_t)i;
     uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
-    if (bs > 1024) return fail(CKC_E_INVALID, di + "block above 1024 threads");
-    if (nb > 0xFFFFFFFFull) return fail(CKC_E_INVALID, di + "grid of 2^32 blocks or more");
+    if (bs > 1024) return fail(CKC_E_INVALID, di() + "block above 1024 threads");
+    if (nb > 0xFFFFFFFFull) return fail(CKC_E_INVALID, di() + "grid of 2^32 blocks or more");
     uint64_t nthr = nb * bs;
     if (nthr > 1 && bits_of(nthr) + L1 + L2 > 64)
-      return fail(CKC_E_RANGE, di + "first-violation key needs more than 64 bits");
+      return fail(CKC_E_RANGE, di() + "first-violation key needs more than 64 bits");
     auto tit = c->tables.find(B.table_ids[i]);
-    if (tit == c->tables.end()) return fail(CKC_E_INVALID, di + "unknown table");
+    if (tit == c->tables.end()) return fail(CKC_E_INVALID, di() + "unknown table");
     const Table& T = tit->second;
-    if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, di + "table has fewer slots than the program");
+    if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, di() + "table has fewer slots than the program");
     for (uint32_t s = 0; s < h->n_slots; s++) {
       const ckc_alloc& A = T.host[s];
       const bool live = A.base != 0 && !(A.flags & CKC_ALLOC_FREED) && A.size_bytes > 0;
       if ((P.L.load_slots >> s & 1u) && live) {
-        if (A.data == nullptr) return fail(CKC_E_INVALID, di + "slot " + std::to_string(s) + " is loaded but has no data");
+        if (A.data == nullptr) return fail(CKC_E_INVALID, di() + "slot " + std::to_string(s) + " is loaded but has no data");
         ws += A.size_bytes;
       }
     }
@@ -206,110 +208,112 @@ hipEvent_t ckc::rt::job_done_event(ckc_ctx c, uint64_t job) {
 
 namespace {
 
-// Inputs of one launch sequence (a job, or one window of a PREX sweep) staged
-// on the host: their descriptors with buffer offsets, scalars, work estimates,
-// and the sizes of the buffers they need.
-struct Stage {
-  std::vector<dinput> hin;
-  std::vector<int64_t> hsc;
-  std::vector<uint64_t> est;  // estimated work per input (LPT order)
-  uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
-  uint32_t max_regs = 1;                               // interpreter register file rows
-  uint64_t gen_tiles = 0;  // interpreter tiles (estimate from the launch shapes)
-  uint64_t n_records = 0, n_counts = 0, trace_bytes = 0;
+// Where the device buffers of a staged launch sequence come from.
+struct BufSource {
+  virtual int get(size_t bytes, void** out) = 0;
+};
 
-  // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;
-  // lanes_max: most lanes of its thread set; sc: the program's scalars.
-  void add(const dprog* h, dinput d, const int64_t* sc, uint64_t lanes_max, bool force_generic) {
-    max_regs = std::max(max_regs, h->n_regs);
-    d.rec_base = n_records;
-    d.cnt_base = n_counts;
-    n_records += h->n_accesses;
-    n_counts += h->n_sites;
-    const bool uniform = (h->cls & CKC_CLS_UNIFORM) && !force_generic;
-    if (uniform) {
-      d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
-      trace_bytes += ckc::trace_bytes(h->trace_cap);
-    }
-    if (h->expand_pc >= 0 && !uniform && lanes_max > 0) {
-      // expanded loop: thread-state arrays over at most lanes_max lanes
-      const uint64_t n_xt = (lanes_max + TILE - 1) / TILE;
-      d.xstate = xstate_bytes + 1;  // rebased after allocation
-      d.xt_begin = n_xtiles;
-      d.xn = n_xt * TILE;
-      d.n_xt = n_xt;
-      n_xtiles += n_xt;
-      n_xin++;
-      xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
-    }
-    hin.push_back(d);
-    est.push_back(lanes_max * (1 + h->n_accesses));
-    if (!uniform) gen_tiles += (lanes_max + TILE - 1) / TILE;
-    for (uint32_t s = 0; s < MAX_SCALARS; s++) hsc.push_back(s < h->n_scalars ? sc[s] : 0);
+// A job's buffers: the context's pool, else hipMalloc (kept in J.bufs).
+struct JobBufs : BufSource {
+  ckc_ctx c;
+  Job& J;
+  JobBufs(ckc_ctx c_, Job& J_) : c(c_), J(J_) {}
+  int get(size_t bytes, void** out) override { return dalloc(c, J, (uint8_t**)out, bytes); }
+};
+
+// Consecutive pieces of the library's static scratch array (no allocation).
+struct ScratchBufs : BufSource {
+  uint8_t* base;
+  size_t cap, used = 0;
+  ScratchBufs(void* b, size_t n) : base((uint8_t*)b), cap(n) {}
+  int get(size_t bytes, void** out) override {
+    if (bytes > cap - used)
+      return fail(CKC_E_NOMEM, "the batch needs more than the " + std::to_string(cap >> 20) +
+                                   " MiB scratch of the no-allocation entry point (at least " +
+                                   std::to_string((used + bytes) >> 20) + " MiB so far)");
+    *out = base + used;
+    used += bytes;
+    return CKC_OK;
   }
 };
 
-// Buffers of a staged launch sequence, allocated into J.
-struct StageBufs {
-  int64_t* sc = nullptr;
-  jobstate* js = nullptr;
-  uint8_t* tr = nullptr;
-  uint32_t* order = nullptr;
-  uint8_t* xs = nullptr;
-  unsigned long long *xtot = nullptr, *xpb = nullptr, *xpg = nullptr, *xbsum = nullptr, *xd = nullptr;
-  uint32_t* xin = nullptr;
+// count elements of T, in 256-byte units
+template <class T>
+int take(BufSource& B, T** out, size_t count) {
+  size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  bytes = (bytes + 255) & ~(size_t)255;
+  void* p = nullptr;
+  int rc = B.get(bytes, &p);
+  if (rc != CKC_OK) return rc;
+  *out = (T*)p;
+  return CKC_OK;
+}
+
+// Result buffers a caller brings (all NULL: take them from the source).
+struct ExtOut {
+  ckc_record* recs = nullptr;
+  ckc_input_status* st = nullptr;
+  uint8_t* maps = nullptr;
 };
 
-// Allocates S's buffers into J (records, counters, status, maps when dense),
-// copies the inputs and fills a (kernel arguments) and eg (evaluator grid).
-int stage_upload(ckc_ctx c, Job& J, Stage& S, const ckc_launch_opts& O, bool dense, KArgs& a, EvalGrid& eg) {
+// Takes S's buffers from B (records, status and maps from ext when given),
+// queues the copies of the inputs on stream s and fills a (kernel arguments)
+// and eg (evaluator grid).  Every buffer is initialised by the kernels
+// themselves, so none needs clearing here.
+int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_launch_opts& O, bool dense,
+                 const ExtOut& ext, KArgs& a, EvalGrid& eg) {
   const uint64_t n_inputs = S.hin.size();
-  StageBufs b;
   // tile-space order of the inputs: as given, or largest first for LPT
-  std::vector<uint32_t> order(n_inputs);
-  for (uint64_t i = 0; i < n_inputs; i++) order[i] = (uint32_t)i;
+  S.order.resize(n_inputs);
+  for (uint64_t i = 0; i < n_inputs; i++) S.order[i] = (uint32_t)i;
   if (O.schedule == CKC_SCHED_LPT)
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return S.est[x] > S.est[y]; });
+    std::stable_sort(S.order.begin(), S.order.end(), [&](uint32_t x, uint32_t y) { return S.est[x] > S.est[y]; });
   int rc;
   const uint64_t nx = S.n_xtiles;
-  if ((rc = dalloc(c, J, &J.d_inputs, n_inputs)) || (rc = dalloc(c, J, &b.sc, S.hsc.size())) ||
-      (rc = dalloc(c, J, &b.order, n_inputs)) ||
-      (nx && ((rc = dalloc(c, J, &b.xs, S.xstate_bytes)) || (rc = dalloc(c, J, &b.xtot, nx)) ||
-              (rc = dalloc(c, J, &b.xpb, nx)) || (rc = dalloc(c, J, &b.xpg, nx)) ||
-              (rc = dalloc(c, J, &b.xin, nx)) || (rc = dalloc(c, J, &b.xd, 2 * nx)) ||
-              (rc = dalloc(c, J, &b.xbsum, 2 * ((nx + 4095) / 4096))))) ||
-      (rc = dalloc(c, J, &J.d_recs, S.n_records)) || (rc = dalloc(c, J, &J.d_counts, S.n_counts)) ||
-      (rc = dalloc(c, J, &J.d_status, n_inputs)) || (rc = dalloc(c, J, &b.js, 1)) ||
-      (rc = dalloc(c, J, &b.tr, S.trace_bytes)) || (dense && (rc = dalloc(c, J, &J.d_maps, n_inputs * 65536))))
+  dinput* d_in = nullptr;
+  int64_t* sc = nullptr;
+  jobstate* js = nullptr;
+  uint8_t *tr = nullptr, *xs = nullptr;
+  uint32_t *order = nullptr, *xin = nullptr, *counts = nullptr;
+  unsigned long long *xtot = nullptr, *xpb = nullptr, *xpg = nullptr, *xbsum = nullptr, *xd = nullptr;
+  ckc_record* recs = ext.recs;
+  ckc_input_status* st = ext.st;
+  uint8_t* maps = ext.maps;
+  if ((rc = take(B, &d_in, n_inputs)) || (rc = take(B, &sc, S.hsc.size())) || (rc = take(B, &order, n_inputs)) ||
+      (nx && ((rc = take(B, &xs, S.xstate_bytes)) || (rc = take(B, &xtot, nx)) || (rc = take(B, &xpb, nx)) ||
+              (rc = take(B, &xpg, nx)) || (rc = take(B, &xin, nx)) || (rc = take(B, &xd, 2 * nx)) ||
+              (rc = take(B, &xbsum, 2 * ((nx + 4095) / 4096))))) ||
+      (!recs && (rc = take(B, &recs, S.n_records))) || (rc = take(B, &counts, S.n_counts)) ||
+      (!st && (rc = take(B, &st, n_inputs))) || (rc = take(B, &js, 1)) || (rc = take(B, &tr, S.trace_bytes)) ||
+      (dense && !maps && (rc = take(B, &maps, n_inputs * 65536))))
     return rc;
   for (auto& d : S.hin) {
-    if (d.trace) d.trace = (uint64_t)(uintptr_t)(b.tr + (d.trace - 1));
-    if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(b.xs + (d.xstate - 1));
+    if (d.trace) d.trace = (uint64_t)(uintptr_t)(tr + (d.trace - 1));
+    if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(xs + (d.xstate - 1));
   }
-  hipError_t e = hipMemcpyAsync(J.d_inputs, S.hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, J.stream);
+  // pageable copies are staged before hipMemcpyAsync returns, so S may be
+  // reused afterwards
+  hipError_t e = hipMemcpyAsync(d_in, S.hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(sc, S.hsc.data(), sizeof(int64_t) * S.hsc.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(b.sc, S.hsc.data(), sizeof(int64_t) * S.hsc.size(), hipMemcpyHostToDevice, J.stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b.order, order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, J.stream);
-  // the host arrays must outlive the copies: pageable copies are staged
-  // before hipMemcpyAsync returns, so S may be reused afterwards
+    e = hipMemcpyAsync(order, S.order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e));
-  a.inputs = J.d_inputs;
-  a.scalars = b.sc;
+  a.inputs = d_in;
+  a.scalars = sc;
   a.n_inputs = (uint32_t)n_inputs;
   a.force_generic = O.force_generic;
-  a.recs = J.d_recs;
-  a.counts = J.d_counts;
-  a.status = J.d_status;
-  a.maps = J.d_maps;
-  a.js = b.js;
-  a.order = b.order;
-  a.xtot = b.xtot;
-  a.xpb = b.xpb;
-  a.xpg = b.xpg;
-  a.xin = b.xin;
-  a.xd = b.xd;
-  a.xbsum = b.xbsum;
+  a.recs = recs;
+  a.counts = counts;
+  a.status = st;
+  a.maps = dense ? maps : nullptr;
+  a.js = js;
+  a.order = order;
+  a.xtot = xtot;
+  a.xpb = xpb;
+  a.xpg = xpg;
+  a.xin = xin;
+  a.xd = xd;
+  a.xbsum = xbsum;
   a.n_xtiles = nx;
   a.max_regs = S.max_regs;
   a.pad = 0;
@@ -330,6 +334,19 @@ int stage_upload(ckc_ctx c, Job& J, Stage& S, const ckc_launch_opts& O, bool den
   // long gather ranges (inputs of 64 tiles or more on average) take the
   // variant with larger rounds
   eg.big_body = S.n_xin != 0 && S.n_xtiles >= 64 * S.n_xin ? 1u : 0u;
+  return CKC_OK;
+}
+
+// A job's buffers from the pool, recorded in J.
+int stage_job(ckc_ctx c, Job& J, Stage& S, const ckc_launch_opts& O, bool dense, KArgs& a, EvalGrid& eg) {
+  JobBufs B(c, J);
+  int rc = stage_upload(c, B, J.stream, S, O, dense, ExtOut(), a, eg);
+  if (rc != CKC_OK) return rc;
+  J.d_inputs = a.inputs;
+  J.d_recs = a.recs;
+  J.d_counts = a.counts;
+  J.d_status = a.status;
+  J.d_maps = a.maps;
   return CKC_OK;
 }
 
@@ -372,6 +389,26 @@ dinput input_of(const Program& P, const Table& T, const ckc_batch& B, uint32_t i
   d.cap_log2[0] = c0;
   d.cap_log2[1] = c1;
   return d;
+}
+
+// Every input of every (validated, non-PREX) descriptor, in order.
+void stage_inputs(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts& O, Stage& S) {
+  for (uint32_t k = 0; k < n_descs; k++) {
+    const ckc_batch& B = descs[k];
+    const Program& P = c->progs.find(B.prog_id)->second;
+    const dprog* h = (const dprog*)P.L.blob.data();
+    for (uint32_t i = 0; i < B.n_inputs; i++) {
+      const Table& T = c->tables.find(B.table_ids[i])->second;
+      dinput d = input_of(P, T, B, i);
+      d.mode = B.mode == CKC_FULL_ENDPOINTS ? CKC_FULL : B.mode;
+      d.aux = B.mode == CKC_FULL_ENDPOINTS ? 1u : 0u;
+      const uint32_t* L = d.launch;
+      const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
+      // most lanes of the thread set (the corner set has at most 64)
+      const uint64_t lanes_max = B.mode == CKC_REP_CORNERS ? std::min<uint64_t>(nthr, 64) : nthr;
+      S.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, lanes_max, O.force_generic != 0);
+    }
+  }
 }
 
 void mark_busy(ckc_ctx c, Job& J, const ckc_batch* descs, uint32_t n_descs) {
@@ -436,7 +473,7 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
   EvalGrid eg;
   uint32_t* d_stop = nullptr;
   prex_item* d_items = nullptr;
-  if ((rc = stage_upload(c, J, R, O, J.dense, a, eg)) || (rc = dalloc(c, J, &d_stop, n_inputs)) ||
+  if ((rc = stage_job(c, J, R, O, J.dense, a, eg)) || (rc = dalloc(c, J, &d_stop, n_inputs)) ||
       (rc = dalloc(c, J, &d_items, std::min<uint64_t>(n_inputs, PREX_WINDOW_PAIRS))))
     return bail(rc);
   std::vector<uint32_t> h_stop(n_inputs, 0);
@@ -503,7 +540,7 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
     WJ.stream = J.stream;
     KArgs wa;
     EvalGrid weg;
-    if ((rc = stage_upload(c, WJ, W, WO, false, wa, weg))) {
+    if ((rc = stage_job(c, WJ, W, WO, false, wa, weg))) {
       free_job(c, WJ);
       return bail(rc);
     }
@@ -574,6 +611,21 @@ int ckc_init(int hip_device, ckc_ctx* out) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  // the no-allocation entry point: the scratch address on this device (the
+  // device is current) and host staging room for its largest call
+  e = ckc::scratch_address(hip_device, &c->scratch);
+  if (e != hipSuccess) {
+    hipStreamDestroy(c->stream);
+    delete c;
+    return fail(CKC_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  }
+  try {
+    c->na_stage.reserve(CKC_NOALLOC_MAX_INPUTS);
+  } catch (const std::bad_alloc&) {
+    hipStreamDestroy(c->stream);
+    delete c;
+    return fail(CKC_E_NOMEM, "context staging arrays");
+  }
   *out = c;
   return CKC_OK;
 }
@@ -694,22 +746,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
     return fail(CKC_E_INVALID, "a job holds CKC_REP_PREX descriptors only, or none");
   if (n_prex) return check_prex(c, descs, n_descs, O, job);
   Stage S;
-  for (uint32_t k = 0; k < n_descs; k++) {
-    const ckc_batch& B = descs[k];
-    const Program& P = c->progs.find(B.prog_id)->second;
-    const dprog* h = (const dprog*)P.L.blob.data();
-    for (uint32_t i = 0; i < B.n_inputs; i++) {
-      const Table& T = c->tables.find(B.table_ids[i])->second;
-      dinput d = input_of(P, T, B, i);
-      d.mode = B.mode == CKC_FULL_ENDPOINTS ? CKC_FULL : B.mode;
-      d.aux = B.mode == CKC_FULL_ENDPOINTS ? 1u : 0u;
-      const uint32_t* L = d.launch;
-      const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
-      // most lanes of the thread set (the corner set has at most 64)
-      const uint64_t lanes_max = B.mode == CKC_REP_CORNERS ? std::min<uint64_t>(nthr, 64) : nthr;
-      S.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, lanes_max, O.force_generic != 0);
-    }
-  }
+  stage_inputs(c, descs, n_descs, O, S);
   const uint64_t n_inputs = S.hin.size();
   if (n_inputs == 0) return fail(CKC_E_INVALID, "no inputs");
   if (n_inputs > 0xFFFFFFFFull) return fail(CKC_E_INVALID, "too many inputs");
@@ -729,7 +766,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   };
   KArgs a;
   EvalGrid eg;
-  if ((rc = stage_upload(c, J, S, O, J.dense, a, eg))) return bail(rc);
+  if ((rc = stage_job(c, J, S, O, J.dense, a, eg))) return bail(rc);
   hipError_t e = hipSuccess;
   for (int q = 0; q < ckc::rt::NEV && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e)));
@@ -750,6 +787,56 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   uint64_t id = c->next_job++;
   c->jobs.emplace(id, std::move(J));
   *job = id;
+  return CKC_OK;
+}
+
+int ckc_check_batch_noalloc(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts* opts,
+                            ckc_record* recs, uint8_t* maps, ckc_input_status* st) {
+  if (!c || !descs || n_descs == 0) return fail(CKC_E_INVALID, "NULL argument or no descriptor");
+  if (!recs || !st) return fail(CKC_E_INVALID, "records and status buffers are required");
+  if (!c->scratch) return fail(CKC_E_HIP, "no scratch address on this device");
+  ckc_launch_opts O;
+  std::memset(&O, 0, sizeof O);
+  if (opts) O = *opts;
+  if (O.schedule > CKC_SCHED_LPT) return fail(CKC_E_INVALID, "unknown schedule");
+  if (O.chunk > 256) return fail(CKC_E_INVALID, "chunk above 256 tiles");
+  if (O.wg_per_cu > 32) return fail(CKC_E_INVALID, "wg_per_cu above 32");
+  if (O.use_graph) return fail(CKC_E_INVALID, "use_graph is not available without allocation");
+  uint64_t n_inputs = 0;
+  bool dense = false;
+  for (uint32_t k = 0; k < n_descs; k++) {
+    int vr = ckc::rt::validate_desc(c, descs[k], k, O.force_generic != 0, nullptr);
+    if (vr != CKC_OK) return vr;
+    if (descs[k].mode == CKC_REP_PREX)
+      return fail(CKC_E_INVALID, "CKC_REP_PREX is not available without allocation");
+    n_inputs += descs[k].n_inputs;
+    dense |= (descs[k].flags & CKC_DENSE_MAP) != 0;
+  }
+  if (n_inputs == 0) return fail(CKC_E_INVALID, "no inputs");
+  if (n_inputs > CKC_NOALLOC_MAX_INPUTS)
+    return fail(CKC_E_INVALID, "more than " + std::to_string(CKC_NOALLOC_MAX_INPUTS) +
+                                   " inputs in one call without allocation");
+  if (dense != (maps != nullptr))
+    return fail(CKC_E_INVALID, dense ? "dense maps requested but maps is NULL"
+                                     : "maps given but no descriptor has CKC_DENSE_MAP");
+  Stage& S = c->na_stage;  // reserved for CKC_NOALLOC_MAX_INPUTS inputs by ckc_init
+  S.clear();
+  stage_inputs(c, descs, n_descs, O, S);
+  int rc;
+  if ((rc = set_device(c))) return rc;
+  const hipStream_t s = O.hip_stream ? (hipStream_t)O.hip_stream : c->stream;
+  ScratchBufs B(c->scratch, CKC_NOALLOC_SCRATCH_BYTES);
+  ExtOut ext;
+  ext.recs = recs;
+  ext.st = st;
+  ext.maps = maps;
+  KArgs a;
+  EvalGrid eg;
+  if ((rc = stage_upload(c, B, s, S, O, dense, ext, a, eg))) return rc;
+  hipError_t e = launch_evaluation(a, eg, s, nullptr);
+  if (e == hipSuccess) e = launch_fixup(a, S.n_records, s);
+  if (e == hipSuccess) e = launch_finish(a, s);
+  if (e != hipSuccess) return fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e));
   return CKC_OK;
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <utility>
@@ -10,6 +11,7 @@
 
 #include "../../include/ckc.h"
 #include "dformat.h"
+#include "kernels.h"
 #include "loader.h"
 
 namespace ckc {
@@ -44,6 +46,69 @@ struct Job {
   bool graph = false;  // ran as one graph: only the first and last events are meaningful
 };
 
+// Inputs of one launch sequence (a job, or one window of a PREX sweep) staged
+// on the host: their descriptors with buffer offsets, scalars, work estimates,
+// the tile-space order, and the sizes of the device buffers they need.
+struct Stage {
+  std::vector<dinput> hin;
+  std::vector<int64_t> hsc;
+  std::vector<uint64_t> est;     // estimated work per input (LPT order)
+  std::vector<uint32_t> order;   // tile-space position -> input (filled when uploaded)
+  uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
+  uint32_t max_regs = 1;                               // interpreter register file rows
+  uint64_t gen_tiles = 0;  // interpreter tiles (estimate from the launch shapes)
+  uint64_t n_records = 0, n_counts = 0, trace_bytes = 0;
+
+  // Room for n inputs, so that staging up to n allocates no host memory.
+  void reserve(size_t n) {
+    hin.reserve(n);
+    hsc.reserve(n * MAX_SCALARS);
+    est.reserve(n);
+    order.reserve(n);
+  }
+  // Empties the stage and keeps the reserved room.
+  void clear() {
+    hin.clear();
+    hsc.clear();
+    est.clear();
+    order.clear();
+    n_xtiles = xstate_bytes = n_xin = 0;
+    max_regs = 1;
+    gen_tiles = 0;
+    n_records = n_counts = trace_bytes = 0;
+  }
+
+  // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;
+  // lanes_max: most lanes of its thread set; sc: the program's scalars.
+  void add(const dprog* h, dinput d, const int64_t* sc, uint64_t lanes_max, bool force_generic) {
+    max_regs = std::max(max_regs, h->n_regs);
+    d.rec_base = n_records;
+    d.cnt_base = n_counts;
+    n_records += h->n_accesses;
+    n_counts += h->n_sites;
+    const bool uniform = (h->cls & CKC_CLS_UNIFORM) && !force_generic;
+    if (uniform) {
+      d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
+      trace_bytes += ckc::trace_bytes(h->trace_cap);
+    }
+    if (h->expand_pc >= 0 && !uniform && lanes_max > 0) {
+      // expanded loop: thread-state arrays over at most lanes_max lanes
+      const uint64_t n_xt = (lanes_max + TILE - 1) / TILE;
+      d.xstate = xstate_bytes + 1;  // rebased after allocation
+      d.xt_begin = n_xtiles;
+      d.xn = n_xt * TILE;
+      d.n_xt = n_xt;
+      n_xtiles += n_xt;
+      n_xin++;
+      xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
+    }
+    hin.push_back(d);
+    est.push_back(lanes_max * (1 + h->n_accesses));
+    if (!uniform) gen_tiles += (lanes_max + TILE - 1) / TILE;
+    for (uint32_t s = 0; s < MAX_SCALARS; s++) hsc.push_back(s < h->n_scalars ? sc[s] : 0);
+  }
+};
+
 }  // namespace rt
 }  // namespace ckc
 
@@ -66,6 +131,11 @@ struct ckc_ctx_s {
   // jobs read with CKC_ENQUEUE whose copies may still run: released (buffers
   // back to the pool) once their event has completed
   std::vector<std::pair<hipEvent_t, ckc::rt::Job>> retiring;
+  // ckc_check_batch_noalloc: the device address of the library's static
+  // scratch array on this context's device (looked up once per device), and
+  // host staging arrays reserved at creation for CKC_NOALLOC_MAX_INPUTS inputs
+  void* scratch = nullptr;
+  ckc::rt::Stage na_stage;
 };
 
 
