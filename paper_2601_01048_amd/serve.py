@@ -70,6 +70,7 @@ def summarize(res, t_from_s: float = 0.0, t0_ns: int = 0, arrivals=None):
     span = (last - first) / 1e9
     batch = np.array([r["stats"]["batch_jobs"] for r in ok])
     return dict(jobs=len(sel), completed_ok=len(ok), p50_ms=float(np.percentile(lat, 50)),
-                p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()), max_ms=float(lat.max()),
+                p99_ms=float(np.percentile(lat, 99)), p999_ms=float(np.percentile(lat, 99.9)),
+                mean_ms=float(lat.mean()), max_ms=float(lat.max()),
                 accesses=acc, window_s=span, accesses_per_s=acc / span, jobs_per_s=len(ok) / span,
                 mean_batch_jobs=float(batch.mean()), max_batch_jobs=int(batch.max()))
