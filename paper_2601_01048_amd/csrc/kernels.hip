@@ -8,10 +8,11 @@
 //              (affine forms of every index, evaluated once per input);
 //   scan       tile offsets of the three evaluators over the inputs;
 //   eval_trace, eval_trace_lanes
-//              persistent: per checked access at most one add and one
-//              unsigned compare against the bound (block-major wavefront
-//              jobs, where the blocks a job has in one grid row share one
-//              exact test of their two end indices, or lane tiles);
+//              persistent: every index formed with one add of the thread's
+//              base and the access offset, checked 16 at a time by an
+//              unsigned maximum and one compare (block-major wavefront jobs,
+//              or lane tiles); the end-point mode instead decides the blocks
+//              a job has in one grid row by the two end indices of the row;
 //   eval_generic
 //              persistent: a wavefront-uniform interpreter of the lowered
 //              bytecode, one lane per thread; the program's expandable loop is
