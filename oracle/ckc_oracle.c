@@ -66,6 +66,15 @@ enum {
 #define K_NULL 8u
 #define A_FREED 1u
 
+/* memory spaces of allocation slots (2 bits per slot in the IR header) */
+#define SP_GLOBAL 0u
+#define SP_SHARED 1u
+#define SP_LOCAL 2u
+
+/* detector models */
+#define DET_EXACT 0u
+#define DET_TRIPWIRE 1u
+
 /* thread-set modes */
 #define M_FULL 0u
 #define M_CORNERS 1u
@@ -77,7 +86,7 @@ enum {
 #define E_IR (-2)
 #define E_RANGE (-3)
 
-typedef struct { uint64_t base, size_bytes; const void* data; uint32_t flags, pad; } or_alloc;
+typedef struct { uint64_t base, size_bytes; const void* data; uint32_t flags, redzone; } or_alloc;
 typedef struct { uint64_t first_key; int64_t index; uint64_t count; uint32_t kinds, first_kind; } or_record;
 typedef struct { uint64_t lanes, accesses_checked, hang_lanes, arith_faults; uint32_t flags, pad; } or_status;
 
@@ -98,6 +107,7 @@ typedef struct {
   uint8_t* load_slot; /* slot used by some LOAD */
   int64_t* const_copy;
   uint8_t* in_slice;  /* [n_instr]: an index, IF predicate or loop bound depends on it */
+  uint8_t space[16];  /* memory space of each slot */
 } or_prog;
 
 static uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
@@ -169,9 +179,19 @@ static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
   P->n_instr = rd16(ir + 6); P->n_consts = rd16(ir + 8); P->n_scalars = rd16(ir + 10);
   P->n_slots = rd16(ir + 12); P->n_accesses = rd16(ir + 14); P->n_sites = rd16(ir + 16);
   P->n_regs = rd16(ir + 18);
-  for (int i = 20; i < 32; i++) if (ir[i]) return E_IR;
+  for (int i = 24; i < 32; i++) if (ir[i]) return E_IR;
   if (P->n_scalars > 16 || P->n_slots > 16 || P->n_accesses > 1024 || P->n_sites > 4096 ||
       P->n_instr > 4096 || P->n_consts > 4096) return E_IR;
+  /* slot spaces: two bits per slot, global / shared / local; none for slots
+   * the program does not have */
+  {
+    uint32_t spaces = rd32(ir + 20);
+    for (int s = 0; s < 16; s++) {
+      uint32_t v = (spaces >> (2 * s)) & 3u;
+      if (v > SP_LOCAL || (s >= P->n_slots && v != 0)) return E_IR;
+      P->space[s] = (uint8_t)v;
+    }
+  }
   size_t site_bytes = ((size_t)P->n_sites * 2 + 7) / 8 * 8;
   size_t need = 32 + (size_t)P->n_consts * 8 + site_bytes + (size_t)P->n_instr * 16;
   if (need != n) return E_IR;
@@ -227,7 +247,13 @@ static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
         acc_used[I->b] = 1;
         if (I->c >= P->n_slots) goto out;
         if (I->op == O_ACCESS) { if (I->d > 7) goto out; }
-        else { if (I->d != 2 && I->d != 3) goto out; P->load_slot[I->c] = 1; DEF(I->dst); }
+        else {
+          /* loads read global memory only: shared and local slots hold no
+           * data the host provides */
+          if ((I->d != 2 && I->d != 3) || P->space[I->c] != SP_GLOBAL) goto out;
+          P->load_slot[I->c] = 1;
+          DEF(I->dst);
+        }
         SITE(I->s0);
         break;
       case O_IF:
@@ -377,6 +403,8 @@ typedef struct {
   const int64_t* scalars;
   const uint32_t* launch; /* gx gy gz bx by bz */
   const or_alloc* table;
+  uint32_t table_n;   /* entries of this input's table */
+  uint32_t detector;  /* DET_EXACT or DET_TRIPWIRE */
   uint32_t tid[3], bid[3];
   uint64_t gtid;
   unsigned L1, L2;
@@ -446,6 +474,44 @@ static uint32_t check_kind(const or_alloc* a, int64_t idx, unsigned log2e) {
   if (idx < 0) return K_UNDER;
   uint64_t n_elems = a->size_bytes >> log2e;
   if ((uint64_t)idx >= n_elems) return K_OVER;
+  return 0;
+}
+
+/* The tripwire (redzone) detector of the address sanitizers the paper
+ * contrasts with base-and-bounds checkers (Section 7.1, Table 1): memory is
+ * poisoned only around allocations, so an access is caught when one of its
+ * bytes falls in a redzone or in freed memory, and missed when it jumps over
+ * the redzone into other memory.  Allocation k of the access's memory space
+ * occupies [base, base + size); its redzones are the `redzone` bytes on each
+ * side; a freed allocation is poisoned whole, redzones included.  A shared or
+ * local slot lives in its block's or thread's own window, which ends at the
+ * largest allocation end (redzone included) of that space: bytes beyond it
+ * are caught too.  Addresses are exact integers (base + index * element
+ * size), not wrapped.  Only called for an access that is out of exact bounds
+ * on a non-NULL slot; returns 1 if the detector reports it. */
+static int overlaps(__int128 a, __int128 b, __int128 x, __int128 y) { return x < y && a < y && x < b; }
+
+static int tripwire_catches(const thr* t, int slot, int64_t idx, unsigned log2e) {
+  const or_alloc* T = t->table;
+  const int sp = t->P->space[slot];
+  const __int128 a = (__int128)T[slot].base + (__int128)idx * ((__int128)1 << log2e);
+  const __int128 b = a + ((__int128)1 << log2e); /* one past the last byte */
+  __int128 window = 0;
+  for (uint32_t k = 0; k < t->table_n; k++) {
+    const or_alloc* A = &T[k];
+    int ksp = k < 16 ? t->P->space[k] : (int)SP_GLOBAL;
+    if (A->base == 0 || ksp != sp) continue;
+    const __int128 lo = (__int128)A->base - A->redzone;
+    const __int128 end = (__int128)A->base + A->size_bytes;
+    const __int128 hi = end + A->redzone;
+    if (hi > window) window = hi;
+    if (A->flags & A_FREED) {
+      if (overlaps(a, b, lo, hi)) return 1;
+    } else if (overlaps(a, b, lo, (__int128)A->base) || overlaps(a, b, end, hi)) {
+      return 1; /* a redzone */
+    }
+  }
+  if (sp != SP_GLOBAL && (a < 0 || b > window)) return 1;
   return 0;
 }
 
@@ -531,12 +597,16 @@ static void exec_range(thr* t, int pc, int end) {
         unsigned log2e = I->op == O_ACCESS ? (I->d & 3u) : I->d;
         const or_alloc* A = &t->table[I->c];
         uint32_t kind = check_kind(A, idx, log2e);
+        /* the tripwire model reports a subset of the exact violations; a
+         * LOAD outside exact bounds reads 0 under either model */
+        int reported = kind != 0 && (t->detector == DET_EXACT || kind == K_NULL ||
+                                     tripwire_catches(t, I->c, idx, log2e));
         if (!t->dry) {
           t->st->accesses_checked++;
           t->acc_seen[I->b] = 1;
         }
         visit(t, I->s0);
-        if (kind) record(t, I->b, kind, idx);
+        if (reported) record(t, I->b, kind, idx);
         if (I->op == O_LOAD) {
           uint64_t v = 0;
           if (!kind) {
@@ -722,7 +792,8 @@ typedef struct {
   const int64_t* scalars;
   const or_alloc* tables;     /* concatenated */
   const uint64_t* table_off;  /* [n_inputs] first entry of each input's table */
-  uint32_t mode;
+  const uint32_t* table_len;  /* [n_inputs] entries of each input's table */
+  uint32_t mode, detector;
   unsigned L1, L2;
   uint64_t cap[2];
   or_record* recs;
@@ -745,6 +816,8 @@ static void* worker(void* arg) {
     t.launch = J->launch + 6 * (size_t)i;
     t.scalars = P->n_scalars ? J->scalars + (size_t)P->n_scalars * i : zero_scalars;
     t.table = J->tables + J->table_off[i];
+    t.table_n = J->table_len[i];
+    t.detector = J->detector;
     t.rec = J->recs + (size_t)P->n_accesses * i;
     t.cnt = J->counts + (size_t)P->n_sites * i;
     t.st = J->st + i;
@@ -763,18 +836,22 @@ static void* worker(void* arg) {
  *   tables   concatenated allocation tables; input i's table starts at
  *            table_off[i] and has table_len[i] >= n_slots entries
  *   mode     0 whole grid, 1 corner threads, 2 boundary blocks, 3 PREX sweep
+ *   detector 0 exact bounds, 1 tripwire (redzones)
  *   cap_log2 trip caps 2^cap_log2[d] for loops at depth d+1
  *   recs     [n_inputs][n_accesses] out; counts [n_inputs][n_sites] out (u64);
  *   maps     [n_inputs][65536] out or NULL; st [n_inputs] out
  * Returns 0, or a negative code (-1 invalid arguments, -2 bad IR, -3 key range). */
 int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint32_t* launch,
                const int64_t* scalars, const or_alloc* tables, const uint64_t* table_off,
-               const uint32_t* table_len, uint32_t mode, const uint32_t* cap_log2,
+               const uint32_t* table_len, uint32_t mode, uint32_t detector, const uint32_t* cap_log2,
                or_record* recs, uint64_t* counts, uint8_t* maps, or_status* st, int nthreads) {
   or_prog P;
   int rc = prog_decode(ir, ir_bytes, &P);
   if (rc) return rc;
-  if (mode > M_PREX || cap_log2[0] > 32 || cap_log2[1] > 32) { prog_free(&P); return E_INVALID; }
+  if (mode > M_PREX || detector > DET_TRIPWIRE || cap_log2[0] > 32 || cap_log2[1] > 32) {
+    prog_free(&P);
+    return E_INVALID;
+  }
   unsigned L1 = P.max_depth >= 1 ? cap_log2[0] : 0;
   unsigned L2 = P.max_depth >= 2 ? cap_log2[1] : 0;
   for (uint32_t i = 0; i < n_inputs; i++) {
@@ -786,6 +863,18 @@ int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint
         prog_free(&P); return E_INVALID;
       }
     }
+    /* the tripwire model needs every allocation with its redzones inside
+     * [0, 2^63] */
+    if (detector == DET_TRIPWIRE)
+      for (uint32_t k = 0; k < table_len[i]; k++) {
+        const or_alloc* A = tables + table_off[i] + k;
+        if (A->base == 0) continue;
+        if (A->base < A->redzone ||
+            (unsigned __int128)A->base + A->size_bytes + A->redzone > ((unsigned __int128)1 << 63)) {
+          prog_free(&P);
+          return E_INVALID;
+        }
+      }
     unsigned __int128 nthr = (unsigned __int128)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
     if ((uint64_t)L[3] * L[4] * L[5] > 1024 || (uint64_t)L[0] * L[1] * L[2] > 0xFFFFFFFFull) { prog_free(&P); return E_INVALID; }
     if (nthr > 0 && L1 + L2 > 0) {
@@ -805,7 +894,8 @@ int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint
   for (int k = 0; k < nthreads; k++) {
     job_t* J = &jobs[k];
     J->P = &P; J->n_inputs = n_inputs; J->launch = launch; J->scalars = scalars;
-    J->tables = tables; J->table_off = table_off; J->mode = mode; J->L1 = L1; J->L2 = L2;
+    J->tables = tables; J->table_off = table_off; J->table_len = table_len; J->mode = mode;
+    J->detector = detector; J->L1 = L1; J->L2 = L2;
     J->cap[0] = 1ull << cap_log2[0]; J->cap[1] = 1ull << cap_log2[1];
     J->recs = recs; J->counts = counts; J->st = st; J->nthreads = nthreads; J->me = k;
   }

@@ -45,7 +45,7 @@ def _load():
             lib = ctypes.CDLL(LIB)
             p = ctypes.c_void_p
             lib.ckco_check.argtypes = [p, ctypes.c_size_t, ctypes.c_uint32, p, p, p, p, p,
-                                       ctypes.c_uint32, p, p, p, p, p, ctypes.c_int]
+                                       ctypes.c_uint32, ctypes.c_uint32, p, p, p, p, p, ctypes.c_int]
             lib.ckco_check.restype = ctypes.c_int
             lib.ckco_validate.argtypes = [p, ctypes.c_size_t, p]
             lib.ckco_validate.restype = ctypes.c_int
@@ -74,8 +74,10 @@ def validate(ir: bytes):
     return tuple(int(v) for v in out)
 
 
-def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: bool = True):
-    """Run the oracle over every input of workload ``wl``.
+def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: bool = True,
+          detector: int | None = None):
+    """Run the oracle over every input of workload ``wl`` (``detector``: 0
+    exact bounds, 1 the tripwire model; default the workload's).
 
     Returns dict(records [n, n_acc] RECORD_DTYPE, counts [n, n_sites] uint64,
     maps [n, 65536] uint8 or None, status [n] STATUS_DTYPE)."""
@@ -83,6 +85,7 @@ def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: b
     n_acc, n_sites, _, n_slots = validate(wl.ir)
     n = wl.n_inputs
     mode = wl.mode if mode is None else mode
+    detector = getattr(wl, "detector", 0) if detector is None else detector
     cap = np.asarray(wl.cap_log2 if cap_log2 is None else cap_log2, np.uint32)
     launch = np.ascontiguousarray(wl.launch, np.uint32)
     scalars = np.ascontiguousarray(wl.scalars, np.int64)
@@ -104,7 +107,7 @@ def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: b
     st = np.zeros(n, STATUS_DTYPE)
     buf = ctypes.create_string_buffer(wl.ir, len(wl.ir))
     rc = lib.ckco_check(buf, len(wl.ir), n, _ptr(launch), _ptr(scalars), _ptr(flat),
-                        _ptr(table_off), _ptr(table_len), int(mode), _ptr(cap),
+                        _ptr(table_off), _ptr(table_len), int(mode), int(detector), _ptr(cap),
                         _ptr(recs), _ptr(counts), _ptr(mp) if maps else None, _ptr(st),
                         int(nthreads))
     if rc:

@@ -21,6 +21,8 @@ ST_VERTEX_EXACT = 1
 SCHED_DEFAULT, SCHED_BLOCKED, SCHED_CYCLIC, SCHED_DYNAMIC, SCHED_LPT = 0, 1, 2, 3, 4
 SCHED_NAMES = {0: "default", 1: "blocked", 2: "cyclic", 3: "dynamic", 4: "lpt"}
 DENSE_MAP = 2
+TRIPWIRE = 4
+SPACE_GLOBAL, SPACE_SHARED, SPACE_LOCAL = 0, 1, 2
 WAIT, DST_DEVICE, ENQUEUE = 1, 2, 4
 CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32, GATHER=64)
 
@@ -29,7 +31,7 @@ RECORD_DTYPE = np.dtype([("first_key", "<u8"), ("index", "<i8"), ("count", "<u8"
 STATUS_DTYPE = np.dtype([("lanes", "<u8"), ("accesses_checked", "<u8"), ("hang_lanes", "<u8"),
                          ("arith_faults", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
 ALLOC_DTYPE = np.dtype([("base", "<u8"), ("size_bytes", "<u8"), ("data", "<u8"),
-                        ("flags", "<u4"), ("pad", "<u4")])
+                        ("flags", "<u4"), ("redzone", "<u4")])
 
 
 class ProgInfo(ctypes.Structure):
@@ -309,9 +311,10 @@ class DeviceWorkload:
     def desc(self, mode=None, dense=True, cap_log2=None, idx=None):
         wl = self.wl
         sel = slice(None) if idx is None else idx
+        flags = (DENSE_MAP if dense else 0) | (TRIPWIRE if getattr(wl, "detector", 0) else 0)
         return dict(prog=self.prog, launch=wl.launch[sel], scalars=wl.scalars[sel],
                     table_ids=self.table_ids[wl.table_idx[sel]],
-                    mode=wl.mode if mode is None else mode, flags=DENSE_MAP if dense else 0,
+                    mode=wl.mode if mode is None else mode, flags=flags,
                     cap_log2=wl.cap_log2 if cap_log2 is None else cap_log2)
 
     def close(self):

@@ -36,7 +36,8 @@ SPECIALS = ["tid.x", "tid.y", "tid.z", "bid.x", "bid.y", "bid.z",
             "bdim.x", "bdim.y", "bdim.z", "gdim.x", "gdim.y", "gdim.z"]
 
 INSTR = struct.Struct("<BBHHHHHHH")   # op, w, dst, a, b, c, d, s0, s1  (16 bytes)
-HEADER = struct.Struct("<IHHHHHHHH12x")
+HEADER = struct.Struct("<IHHHHHHHHI8x")  # ... n_regs, slot_spaces, reserved
+SPACE = dict(global_=0, shared=1, local=2)
 
 
 @dataclass(frozen=True)
@@ -51,9 +52,11 @@ class Program:
     creation order; their coverage-map ids default to ``site_base + index``."""
 
     def __init__(self, n_scalars: int = 0, n_slots: int = 1, site_base: int = 0,
-                 site_stride: int = 1):
+                 site_stride: int = 1, spaces=None):
         self.n_scalars = n_scalars
         self.n_slots = n_slots
+        # memory space per slot: 0 global, 1 shared (per block), 2 local (per thread)
+        self.spaces = list(spaces) if spaces is not None else [0] * n_slots
         self.instrs: list[tuple] = []
         self.consts: list[int] = []
         self.site_ids: list[int] = []
@@ -193,9 +196,12 @@ class Program:
     # -- output --------------------------------------------------------------
     def to_bytes(self) -> bytes:
         assert not self._open, "unclosed IF/LOOP"
+        spaces = 0
+        for k, sp in enumerate(self.spaces):
+            spaces |= (sp & 3) << (2 * k)
         out = bytearray(HEADER.pack(MAGIC, VERSION, len(self.instrs), len(self.consts),
                                     self.n_scalars, self.n_slots, self.n_accesses,
-                                    len(self.site_ids), self.n_regs))
+                                    len(self.site_ids), self.n_regs, spaces))
         for c in self.consts:
             out += struct.pack("<q", c)
         sites = struct.pack(f"<{len(self.site_ids)}H", *self.site_ids)
@@ -221,5 +227,5 @@ def header_of(ir: bytes) -> dict:
     """Decode only the header (for generators and harness bookkeeping)."""
     f = HEADER.unpack_from(ir, 0)
     keys = ["magic", "version", "n_instr", "n_consts", "n_scalars", "n_slots",
-            "n_accesses", "n_sites", "n_regs"]
+            "n_accesses", "n_sites", "n_regs", "slot_spaces"]
     return dict(zip(keys, f))

@@ -31,8 +31,9 @@ from .ir import Program
 # the ``data`` field holds a 1-based index into ``Workload.data`` here (0 = no
 # data); consumers replace it with a host or device address.
 ALLOC_DTYPE = np.dtype([("base", "<u8"), ("size_bytes", "<u8"), ("data", "<u8"),
-                        ("flags", "<u4"), ("pad", "<u4")])
+                        ("flags", "<u4"), ("redzone", "<u4")])
 ALLOC_FREED = 1
+DETECT_EXACT, DETECT_TRIPWIRE = 0, 1
 
 MODE_FULL, MODE_CORNERS, MODE_BOUNDARY, MODE_PREX, MODE_ENDPOINTS = 0, 1, 2, 3, 4
 DEFAULT_CAP_LOG2 = (20, 12)
@@ -52,6 +53,7 @@ class Workload:
     mode: int = MODE_FULL
     cap_log2: tuple = DEFAULT_CAP_LOG2
     meta: dict = field(default_factory=dict)
+    detector: int = DETECT_EXACT  # exact bounds, or the tripwire (redzone) model
 
     @property
     def n_inputs(self) -> int:
@@ -62,11 +64,11 @@ class Workload:
         idx = np.asarray(idx)
         return Workload(self.name, self.ir, self.launch[idx].copy(), self.scalars[idx].copy(),
                         self.tables, self.table_idx[idx].copy(), self.data, self.mode,
-                        self.cap_log2, dict(self.meta))
+                        self.cap_log2, dict(self.meta), self.detector)
 
 
-def alloc(size_bytes: int, data_ref: int = 0, base: int = LOGICAL_BASE, flags: int = 0):
-    return (base, size_bytes, data_ref, flags, 0)
+def alloc(size_bytes: int, data_ref: int = 0, base: int = LOGICAL_BASE, flags: int = 0, redzone: int = 0):
+    return (base, size_bytes, data_ref, flags, redzone)
 
 
 # ---------------------------------------------------------------------------

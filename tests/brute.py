@@ -31,6 +31,44 @@ def kind_of(entry, idx, elem):
     return 0
 
 
+def shadow(table, spaces):
+    """Byte-level shadow memory of one input's table under the tripwire
+    model, as an address sanitizer keeps it: per memory space the set of
+    poisoned byte addresses (the redzone bytes around every live allocation,
+    every byte of a freed allocation and its redzones) and the end of the
+    space's window (largest allocation end with its redzone)."""
+    poisoned, window = {}, {}
+    for k, e in enumerate(table):
+        base, size, flags = int(e[0]), int(e[1]), int(e[3])
+        rz = int(e[4]) if len(e) > 4 else 0
+        if base == 0:
+            continue
+        sp = spaces[k] if k < len(spaces) else 0
+        P = poisoned.setdefault(sp, set())
+        if flags & 1:
+            P.update(range(base - rz, base + size + rz))
+        else:
+            P.update(range(base - rz, base))
+            P.update(range(base + size, base + size + rz))
+        window[sp] = max(window.get(sp, 0), base + size + rz)
+    return poisoned, window
+
+
+def tripwire_reports(table, spaces, sh, slot, idx, elem):
+    """Whether an access out of exact bounds is reported: NULL always;
+    otherwise one of its bytes is poisoned in its space, or (shared and local
+    spaces) it leaves the space's window."""
+    e = table[slot]
+    if int(e[0]) == 0:
+        return True
+    sp = spaces[slot] if slot < len(spaces) else 0
+    a = int(e[0]) + idx * elem
+    poisoned, window = sh
+    if any(b in poisoned.get(sp, ()) for b in range(a, a + elem)):
+        return True
+    return sp != 0 and (a < 0 or a + elem > window.get(sp, 0))
+
+
 def threads(launch, mode="full"):
     gx, gy, gz, bx, by, bz = (int(v) for v in launch)
     nb, bs = gx * gy * gz, bx * by * bz
@@ -63,11 +101,15 @@ def threads(launch, mode="full"):
     raise ValueError(mode)
 
 
-def run(kernel, launches, tables, n_acc, n_sites, mode="full", L=(0, 0), scalars=None):
+def run(kernel, launches, tables, n_acc, n_sites, mode="full", L=(0, 0), scalars=None, tripwire=False,
+        spaces=()):
     """kernel(tid, bid, launch, scalars) -> events.  Returns (records as list of
-    dicts per input, counts [n][n_sites], status list of dicts)."""
+    dicts per input, counts [n][n_sites], status list of dicts).  With
+    ``tripwire`` an exact violation is recorded only when the shadow model
+    reports it (``spaces``: memory space per slot, default global)."""
     recs, counts, status = [], [], []
     for i, launch in enumerate(launches):
+        sh = shadow(tables[i], spaces) if tripwire else None
         rec = [dict(first_key=U64MAX, index=0, count=0, kinds=0, first_kind=0) for _ in range(n_acc)]
         cnt = [0] * n_sites
         st = dict(lanes=0, accesses_checked=0, hang_lanes=0, arith_faults=0)
@@ -86,6 +128,8 @@ def run(kernel, launches, tables, n_acc, n_sites, mode="full", L=(0, 0), scalars
                     _, acc, slot, idx, elem, i1, i2 = ev
                     st["accesses_checked"] += 1
                     k = kind_of(tables[i][slot], idx, elem)
+                    if k and tripwire and not tripwire_reports(tables[i], spaces, sh, slot, idx, elem):
+                        k = 0
                     if k:
                         r = rec[acc]
                         key = (gtid << (L[0] + L[1])) | (i1 << L[1]) | i2
