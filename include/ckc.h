@@ -169,13 +169,16 @@ int ckc_unload_program(ckc_ctx ctx, uint32_t prog_id);
  *      kernels run against, Section 4.1) -------------------------------- */
 #define CKC_ALLOC_FREED 1u
 typedef struct ckc_alloc {
-  uint64_t base;        /* logical address; 0 = NULL allocation */
+  uint64_t base;        /* logical address; 0 = NULL allocation.  Slots of the
+                           shared and local spaces (ckc_ir_space) take addresses
+                           within their block's or thread's own window */
   uint64_t size_bytes;  /* bounds; metadata only unless data != NULL */
   const void* data;     /* device pointer to size_bytes bytes; required for slots
                            read by LOAD; borrowed: must stay valid until every job
                            using the table has been read */
   uint32_t flags;       /* CKC_ALLOC_FREED */
-  uint32_t pad;
+  uint32_t redzone;     /* bytes poisoned on each side of the allocation under the
+                           tripwire detector (CKC_TRIPWIRE); ignored otherwise */
 } ckc_alloc;            /* 32 bytes */
 
 /* Copies n (1..16) host entries into a device-resident table.  Each entry
@@ -189,7 +192,25 @@ int ckc_put_alloc_table(ckc_ctx ctx, const ckc_alloc* entries, uint32_t n, uint3
 int ckc_free_alloc_table(ckc_ctx ctx, uint32_t table_id);
 
 /* ---- checking ----------------------------------------------------------- */
-enum ckc_batch_flags { CKC_DENSE_MAP = 2 };  /* also build the dense 64 KiB maps */
+enum ckc_batch_flags {
+  CKC_DENSE_MAP = 2,  /* also build the dense 64 KiB maps */
+  /* Detector model of the redzone ("tripwire") address sanitizers that the
+   * paper contrasts with base-and-bounds checkers (Section 7.1, Table 1;
+   * the memory spaces of Section 6.1) instead of exact bounds: an access that
+   * is out of its slot's exact bounds is reported only when its slot is NULL,
+   * when one of its bytes (base + index * element size, an exact integer)
+   * falls in a redzone of an allocation of its own memory space (the
+   * `redzone` bytes on each side of a live allocation) or in a freed
+   * allocation of that space (its bytes and redzones), or, for a shared or
+   * local slot, when it leaves that space's window [0, the largest allocation
+   * end plus redzone of the space).  Linear overflows into a redzone are
+   * caught; accesses that jump over it into other memory are not.  Reported
+   * records carry the exact kind and index; a LOAD out of exact bounds reads 0
+   * either way.  Every allocation with a nonzero base must satisfy base >=
+   * redzone and base + size_bytes + redzone <= 2^63 (else CKC_E_INVALID).
+   * Inputs run on the interpreter path. */
+  CKC_TRIPWIRE = 4
+};
 
 typedef struct ckc_batch {
   uint32_t prog_id;

@@ -68,7 +68,9 @@
  *          = OVER  if index >= floor(size_bytes / 2^log2_elem)
  *          = none  otherwise
  * LOAD then reads the element (4 bytes sign-extended, or 8 bytes) from the
- * slot's data; a violating LOAD reads 0 and the lane continues.
+ * slot's data; a LOAD outside those bounds reads 0 and the lane continues.
+ * Slots live in a memory space declared in the header (global, per-block
+ * shared, per-thread local); LOAD reads global slots only.
  *
  * ------------------------------------------------------------------------
  * Control flow (structured; matching is by nesting, not by stored targets)
@@ -128,8 +130,18 @@ typedef struct ckc_ir_header {
   uint16_t n_accesses;
   uint16_t n_sites;
   uint16_t n_regs;
-  uint32_t reserved[3]; /* must be zero */
+  uint32_t slot_spaces; /* memory space of slot k in bits 2k..2k+1 (ckc_ir_space);
+                           0 for slots k >= n_slots */
+  uint32_t reserved[2]; /* must be zero */
 } ckc_ir_header;        /* 32 bytes */
+
+/* Memory space of an allocation slot (the CUDA memory spaces of the paper's
+ * Section 6.1): global memory has one instance per input; shared memory one
+ * per block of the launch; local memory one per thread.  Bounds are the same
+ * for every instance (the slot's size); under the tripwire detector each
+ * space is its own address window (see ckc.h, CKC_TRIPWIRE).  Only global
+ * slots may be read by LOAD. */
+enum ckc_ir_space { CKC_SPACE_GLOBAL = 0, CKC_SPACE_SHARED = 1, CKC_SPACE_LOCAL = 2 };
 
 typedef struct ckc_ir_instr {
   uint8_t op;   /* ckc_ir_op */

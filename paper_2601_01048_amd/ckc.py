@@ -308,10 +308,14 @@ class DeviceWorkload:
             self.table_ids.append(ctx.put_table(e))
         self.table_ids = np.array(self.table_ids, np.uint32)
 
-    def desc(self, mode=None, dense=True, cap_log2=None, idx=None):
+    def desc(self, mode=None, dense=True, cap_log2=None, idx=None, detector=None):
+        """Descriptor dict of the workload (inputs ``idx``, default all);
+        ``detector`` overrides the workload's detector model (0 exact, 1
+        tripwire)."""
         wl = self.wl
         sel = slice(None) if idx is None else idx
-        flags = (DENSE_MAP if dense else 0) | (TRIPWIRE if getattr(wl, "detector", 0) else 0)
+        det = getattr(wl, "detector", 0) if detector is None else detector
+        flags = (DENSE_MAP if dense else 0) | (TRIPWIRE if det else 0)
         return dict(prog=self.prog, launch=wl.launch[sel], scalars=wl.scalars[sel],
                     table_ids=self.table_ids[wl.table_idx[sel]],
                     mode=wl.mode if mode is None else mode, flags=flags,

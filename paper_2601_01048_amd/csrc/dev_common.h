@@ -126,6 +126,45 @@ __device__ __forceinline__ uint32_t kind_of(uint64_t base, uint64_t size, uint32
   return (uint64_t)idx >= (size >> lg) ? CKC_KIND_OVER : 0u;
 }
 
+// The tripwire (redzone) detector model (CKC_TRIPWIRE), for an access out of
+// its slot's exact bounds on a non-NULL slot: caught when one of its bytes
+// falls in a redzone of a live allocation or in a freed allocation (with its
+// redzones) of the slot's memory space, or, for shared and local slots, when
+// it leaves that space's window [0, largest allocation end plus redzone).
+// The byte address base + idx * 2^lg is an exact integer; every allocation and
+// redzone lies in [0, 2^63] (checked at submission), so addresses are held
+// plus 8 and clamped to [-8, 2^63] + 8 in 64 bits: below -8 or above 2^63
+// nothing changes (no poisoned byte, outside every window).  T: the input's
+// table of MAX_SLOTS entries (unused ones have base 0).
+template <class TAB>
+__device__ bool tripwire_catches(TAB* T, uint32_t spaces, uint32_t slot, int64_t idx, uint32_t lg) {
+  constexpr uint64_t TOP = 1ull << 63;
+  const uint32_t sp = (spaces >> (2 * slot)) & 3u;
+  const uint64_t base = T[slot].base, e = 1ull << lg;
+  uint64_t a8;  // address + 8, clamped
+  if (idx < 0) {
+    const uint64_t mag = 0ull - (uint64_t)idx;
+    a8 = mag > ((base + 8) >> lg) ? 0ull : base + 8 - (mag << lg);
+  } else {
+    const uint64_t u = (uint64_t)idx;
+    a8 = (u > (TOP >> lg) || (u << lg) > TOP - base) ? TOP + 8 : base + (u << lg) + 8;
+  }
+  const uint64_t b8 = a8 + e;
+  uint64_t win8 = 8;
+  for (uint32_t k = 0; k < MAX_SLOTS; k++) {
+    const uint64_t kb = T[k].base;
+    if (kb == 0 || ((spaces >> (2 * k)) & 3u) != sp) continue;
+    const uint64_t rz = T[k].redzone, lo8 = kb - rz + 8, end8 = kb + T[k].size_bytes + 8, hi8 = end8 + rz;
+    win8 = hi8 > win8 ? hi8 : win8;
+    if (T[k].flags & CKC_ALLOC_FREED) {
+      if (lo8 < hi8 && a8 < hi8 && lo8 < b8) return true;
+    } else if ((lo8 < kb + 8 && a8 < kb + 8 && lo8 < b8) || (end8 < hi8 && a8 < hi8 && end8 < b8)) {
+      return true;
+    }
+  }
+  return sp != CKC_SPACE_GLOBAL && (a8 < 8 || b8 > win8);
+}
+
 // ---------------------------------------------------------------------------
 // wavefront reductions
 // ---------------------------------------------------------------------------

@@ -123,6 +123,8 @@ struct Ctx {
   unsigned long long *xtot, *xpb, *xpg, *xd;
   uint32_t* xin;
   uint32_t input;
+  uint32_t tw;              // the input runs under the tripwire detector model
+  uint32_t spaces;          // memory space of each slot (2 bits per slot)
   // fix-up target
   uint32_t tacc;
   uint64_t tk0, tk1;
@@ -216,7 +218,11 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
         const uint32_t slot = D.slot, lg = D.fl & 3u, acc = D.x;
         const int64_t idx = (int64_t)narrow(va, w);
         c_alloc& A = C.tab[slot];
-        const uint32_t kd = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
+        // kx: exact kind (decides what a LOAD reads); kd: the kind reported
+        // under the input's detector model
+        const uint32_t kx = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
+        uint32_t kd = kx;
+        if (C.tw && kx != 0 && kx != CKC_KIND_NULL && !tripwire_catches(C.tab, C.spaces, slot, idx, lg)) kd = 0;
         if (MODE != M_FIX) {
           ln.acc += act ? 1u : 0u;
           count_site(S, C, sat, D.s0, __ballot(act));
@@ -230,7 +236,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
         }
         if (op == CKC_OP_LOAD) {
           uint64_t v = 0;
-          if (act && kd == 0)
+          if (act && kx == 0)
             v = lg == 2 ? (uint64_t)(int64_t)((g_i32*)A.data)[idx] : (uint64_t)((g_i64*)A.data)[idx];
           r = v;
           wreg = dd;
@@ -312,7 +318,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
           if (cnt) {
             // gather bodies of contiguous tiles keep no start and step (the
             // gather pass forms them from d)
-            if (!(contig && P->body_gather)) {
+            if (!(contig && P->body_gather && !C.tw)) {
               C.xs[C.xn + l] = (uint64_t)s0;
               C.xs[2 * C.xn + l] = (uint64_t)stp;
             }
@@ -322,7 +328,8 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
           if (tid == TILE - 1) {
             const uint64_t tot = pre + cnt;
             C.xtot[C.xt] = tot;
-            (P->body_gather ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
+            // the tripwire model is checked by the interpreted body form
+            (P->body_gather && !C.tw ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
             C.xin[C.xt] = C.input;
             C.xd[2 * C.xt] = dref;
             C.xd[2 * C.xt + 1] = contig ? 1ull : 0ull;
@@ -436,6 +443,8 @@ __device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, c_input& in, ui
   C.input = i;
   C.lane0 = 0;
   C.xt = 0;
+  C.tw = in.detector;
+  C.spaces = C.P->slot_spaces;
 }
 
 // Per-thread state of a lane (its totals are kept).

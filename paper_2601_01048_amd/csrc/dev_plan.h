@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
       a.xpg[in.xt_begin + q] = 0;
     }
   uint64_t lanes = set_lanes(in.mode, in.launch, in.aux);
-  bool trace = (P->cls & CKC_CLS_UNIFORM) && !a.force_generic && in.trace != 0 && lanes > 0;
+  bool trace = (P->cls & CKC_CLS_UNIFORM) && !a.force_generic && in.trace != 0 && lanes > 0 && !in.detector;
   __syncthreads();
   ckc_input_status* st = a.status + i;
   if (j == 0) {

@@ -62,7 +62,7 @@ struct dprog {
                               // (site_ids); sites n_map_sites..n_sites-1 are internal:
                               // one per ACCESS/LOAD written without a site, so that
                               // every access instruction's execution is counted
-  uint32_t pad1;
+  uint32_t slot_spaces;       // memory space of slot k in bits 2k..2k+1 (ckc_ir_space)
 };
 
 // One input of a job (the global input list concatenates the descriptors).
@@ -89,8 +89,10 @@ struct dinput {
   uint64_t xt_begin;      // first expanded tile of this input
   uint64_t xn;            // entries per state array (tiles x TILE, >= lanes)
   uint64_t n_xt;          // expanded tiles reserved for this input
+  uint32_t detector;      // 0 exact bounds, 1 the tripwire model (CKC_TRIPWIRE)
+  uint32_t pad2;
 };
-static_assert(sizeof(dinput) == 168, "dinput layout");
+static_assert(sizeof(dinput) == 176, "dinput layout");
 // Internal thread-set mode of one round of the PREX sweep (Algorithm 1): the
 // blocks r and nblocks-1-r (one block when they coincide), all their threads,
 // in block order.  Never seen at the C-ABI.

@@ -74,6 +74,7 @@ struct Analyzer {
   size_t n = 0;
   int n_instr = 0, n_consts = 0, n_scalars = 0, n_slots = 0, n_accesses = 0, n_sites = 0,
       n_regs = 0;
+  uint32_t slot_spaces = 0;
   std::vector<int64_t> consts;
   std::vector<uint16_t> site_ids;
   std::vector<Ins> ins;
@@ -97,9 +98,15 @@ struct Analyzer {
     std::memcpy(&h, ir, sizeof h);
     if (h.magic != CKC_IR_MAGIC) return fail(-1, "bad magic");
     if (h.version != CKC_IR_VERSION) return fail(-1, "unsupported IR version");
-    if (h.reserved[0] || h.reserved[1] || h.reserved[2]) return fail(-1, "reserved header bytes not zero");
+    if (h.reserved[0] || h.reserved[1]) return fail(-1, "reserved header bytes not zero");
     n_instr = h.n_instr; n_consts = h.n_consts; n_scalars = h.n_scalars; n_slots = h.n_slots;
     n_accesses = h.n_accesses; n_sites = h.n_sites; n_regs = h.n_regs;
+    slot_spaces = h.slot_spaces;
+    for (int k = 0; k < 16; k++) {
+      const uint32_t sp = (slot_spaces >> (2 * k)) & 3u;
+      if (sp > CKC_SPACE_LOCAL || (k >= n_slots && k < 16 && sp != 0))
+        return fail(-1, "bad memory space of an allocation slot");
+    }
     if (n_instr > (int)CKC_IR_MAX_INSTR || n_consts > (int)CKC_IR_MAX_CONSTS ||
         n_scalars > (int)CKC_IR_MAX_SCALARS || n_slots > (int)CKC_IR_MAX_SLOTS ||
         n_accesses > (int)CKC_IR_MAX_ACCESSES || n_sites > (int)CKC_IR_MAX_SITES)
@@ -198,6 +205,8 @@ struct Analyzer {
             if (I.d > 7) return fail(i, "bad ACCESS flags");
           } else {
             if (I.d != 2 && I.d != 3) return fail(i, "LOAD element must be 4 or 8 bytes");
+            if (((slot_spaces >> (2 * I.c)) & 3u) != CKC_SPACE_GLOBAL)
+              return fail(i, "LOAD reads a global slot only");
             if (!def(i, I.dst)) return false;
           }
           if (!site(i, I.s0)) return false;
@@ -744,6 +753,7 @@ struct Analyzer {
       for (int i = expand_pc + 1; i < ins[expand_pc].end; i++)
         if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
     h.body_gather = body_gather ? 1u : 0u;
+    h.slot_spaces = slot_spaces;
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
     h.off_instr = al(sizeof(dprog));

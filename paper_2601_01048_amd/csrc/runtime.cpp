@@ -166,6 +166,8 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
   const dprog* h = (const dprog*)P.L.blob.data();
   if (h->n_scalars && B.n_inputs && !B.scalars) return fail(CKC_E_INVALID, dk() + "scalars missing");
   if (B.mode > CKC_FULL_ENDPOINTS) return fail(CKC_E_INVALID, dk() + "unknown mode");
+  if (B.flags & ~(uint32_t)(CKC_DENSE_MAP | CKC_TRIPWIRE)) return fail(CKC_E_INVALID, dk() + "unknown flags");
+  const bool tripwire = (B.flags & CKC_TRIPWIRE) != 0;
   uint32_t c0 = B.loop_cap_log2[0], c1 = B.loop_cap_log2[1];
   if (c0 == 0 && c1 == 0) { c0 = 20; c1 = 12; }
   if (c0 > 32 || c1 > 32) return fail(CKC_E_INVALID, dk() + "loop cap above 2^32");
@@ -184,6 +186,15 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
     if (tit == c->tables.end()) return fail(CKC_E_INVALID, di() + "unknown table");
     const Table& T = tit->second;
     if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, di() + "table has fewer slots than the program");
+    if (tripwire)  // every allocation with its redzones inside [0, 2^63]
+      for (size_t s = 0; s < T.host.size(); s++) {
+        const ckc_alloc& A = T.host[s];
+        if (A.base != 0 && (A.base < A.redzone || A.base > (1ull << 63) ||
+                            A.size_bytes > (1ull << 63) - A.base ||
+                            A.redzone > (1ull << 63) - A.base - A.size_bytes))
+          return fail(CKC_E_INVALID, di() + "slot " + std::to_string(s) +
+                                         ": allocation and redzones leave [0, 2^63] (tripwire detector)");
+      }
     for (uint32_t s = 0; s < h->n_slots; s++) {
       const ckc_alloc& A = T.host[s];
       const bool live = A.base != 0 && !(A.flags & CKC_ALLOC_FREED) && A.size_bytes > 0;
@@ -194,7 +205,7 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
     }
     ws += sizeof(dinput) + 8 * MAX_SCALARS + 4 + sizeof(ckc_input_status) + (uint64_t)h->n_accesses * sizeof(ckc_record) +
           (uint64_t)h->n_sites * 4;
-    if ((h->cls & CKC_CLS_UNIFORM) && !force_generic) ws += ckc::trace_bytes(h->trace_cap);
+    if ((h->cls & CKC_CLS_UNIFORM) && !force_generic && !tripwire) ws += ckc::trace_bytes(h->trace_cap);
     if (B.flags & CKC_DENSE_MAP) ws += 65536;
   }
   if (ws_bytes) *ws_bytes = ws;
@@ -402,11 +413,14 @@ void stage_inputs(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc
       dinput d = input_of(P, T, B, i);
       d.mode = B.mode == CKC_FULL_ENDPOINTS ? CKC_FULL : B.mode;
       d.aux = B.mode == CKC_FULL_ENDPOINTS ? 1u : 0u;
+      d.detector = (B.flags & CKC_TRIPWIRE) ? 1u : 0u;
       const uint32_t* L = d.launch;
       const uint64_t nthr = (uint64_t)L[0] * L[1] * L[2] * ((uint64_t)L[3] * L[4] * L[5]);
       // most lanes of the thread set (the corner set has at most 64)
       const uint64_t lanes_max = B.mode == CKC_REP_CORNERS ? std::min<uint64_t>(nthr, 64) : nthr;
-      S.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, lanes_max, O.force_generic != 0);
+      // tripwire inputs take the interpreter: no trace of their own
+      S.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, lanes_max,
+            O.force_generic != 0 || d.detector != 0);
     }
   }
 }
@@ -443,6 +457,7 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
       const Table& T = c->tables.find(B.table_ids[i])->second;
       dinput d = input_of(P, T, B, i);
       d.mode = CKC_REP_PREX;
+      d.detector = (B.flags & CKC_TRIPWIRE) ? 1u : 0u;
       d.path = PATH_GENERIC;  // results arrive folded: the finishing pass only builds maps
       const uint32_t* L = d.launch;
       const uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
@@ -531,7 +546,7 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
         v.mode = MODE_PAIR;
         v.aux = next[i] + (uint32_t)r;
         v.path = 0;
-        W.add(heads[i], v, sc, bs2, O.force_generic != 0);
+        W.add(heads[i], v, sc, bs2, O.force_generic != 0 || v.detector != 0);
         lanes += bs2;
       }
     }

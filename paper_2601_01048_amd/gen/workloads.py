@@ -285,6 +285,28 @@ def config3(seed: int = 1003, n_inputs: int = 64, log2_rows: int = 20, mean: int
                     meta=dict(seed=seed, nrows=nrows, ncols=ncols, nnz=nnz))
 
 
+def adjacent_layout(wl: Workload, redzone: int, gap: int = 0) -> Workload:
+    """The workload under the tripwire detector model with each input's live
+    allocations placed one after the other in slot order, each with
+    ``redzone`` bytes on both sides and ``gap`` bytes between neighbours (how
+    a sanitizer's allocator packs buffers), so that overflows can land in a
+    redzone or in the next buffer.  One table per input."""
+    n = wl.n_inputs
+    src = wl.tables[wl.table_idx]
+    tabs = src.copy()
+    for i in range(n):
+        cur = LOGICAL_BASE + 4096
+        for s in range(src.shape[1]):
+            if src[i, s]["base"] != 0:
+                cur += redzone + gap
+                tabs[i, s]["base"] = cur
+                tabs[i, s]["redzone"] = redzone
+                cur += int(src[i, s]["size_bytes"]) + redzone
+    return Workload(wl.name + "_tripwire", wl.ir, wl.launch.copy(), wl.scalars.copy(), tabs,
+                    np.arange(n, dtype=np.uint32), wl.data, wl.mode, wl.cap_log2, dict(wl.meta),
+                    DETECT_TRIPWIRE)
+
+
 def mini(name: str, **kw) -> Workload:
     """Reduced forms of the configurations: small enough for the oracle to
     finish in seconds, still spanning many tiles and a ragged tail."""

@@ -191,3 +191,36 @@ def test_gather_classification():
             assert not info["cls"] & ckc.CLS["GATHER"], k
         n_gather += bool(info["cls"] & ckc.CLS["GATHER"])
     assert n_gather >= 10
+
+
+def test_slot_spaces_agree_with_oracle():
+    """The header's slot-space word (2 bits per slot: global, shared, local):
+    every value of each field, fields beyond n_slots, and LOADs from non-global
+    slots, accepted or refused alike by the loader and the oracle's decoder."""
+    from paper_2601_01048_amd.gen.ir import Program
+    cases = []
+    for spaces in ([0, 0], [1, 2], [2, 0], [3, 0], [0, 3], [1, 1, 1], [0, 0, 2]):
+        p = Program(n_slots=2, spaces=spaces)
+        p.access(0, p.const(0, 32), elem=4)
+        p.access(1, p.const(1, 32), elem=4)
+        cases.append(p.to_bytes())
+    for sp in (0, 1, 2):
+        p = Program(n_slots=2, spaces=[0, sp])
+        p.load(1, p.const(0, 32), elem=4)
+        cases.append(p.to_bytes())
+    results = []
+    for b in cases:
+        try:
+            O.validate(b)
+            ok_oracle = True
+        except O.OracleError:
+            ok_oracle = False
+        try:
+            ckc.analyze(b)
+            ok_lib = True
+        except ckc.CkcError as e:
+            assert e.code == -2
+            ok_lib = False
+        assert ok_oracle == ok_lib, b[:32].hex()
+        results.append(ok_lib)
+    assert results == [True, True, True, False, False, False, False, True, False, False]
