@@ -110,13 +110,13 @@ def parse(argv=None):
     ap.add_argument("--no-plain", action="store_true", help="skip the CSR and 1-D sub-results")
     ap.add_argument("--served-seconds", type=float, default=35.0,
                     help="length of the served stream (the first 5 s are warm-up)")
-    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d", "batched", "served"],
+    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d", "batched", "served", "tripwire"],
                     help="stencil: the benchmark line (with every sub-result unless switched off); "
                          "csr / affine1d / batched / served: that form alone")
     return ap.parse_args(argv)
 
 
-def run_steps(ctx, dw, out, mode, steps):
+def run_steps(ctx, dw, out, mode, steps, detector=None):
     """Runs `steps` checks back to back on the context's stream: each job is
     queued before the previous one's stage timing is read, and every job's
     results are copied to the device buffers behind it on the same stream
@@ -129,7 +129,7 @@ def run_steps(ctx, dw, out, mode, steps):
         ctx.read_device(job, out["recs"].data_ptr(), out["maps"].data_ptr(), out["st"].data_ptr(), enqueue=True)
 
     for _ in range(steps):
-        job = ctx.check([dw.desc(mode=mode, dense=True)])
+        job = ctx.check([dw.desc(mode=mode, dense=True, detector=detector)])
         if prev is not None:
             retire(prev)
         prev = job
@@ -145,13 +145,13 @@ def out_buffers(n, n_acc):
                 st=torch.empty(n * 40, dtype=torch.uint8, device="cuda"))
 
 
-def timed(ctx, dw, out, mode, warmup, steps):
+def timed(ctx, dw, out, mode, warmup, steps, detector=None):
     """(seconds per step, stage timings, status of the last step)."""
     import torch
-    run_steps(ctx, dw, out, mode, warmup)
+    run_steps(ctx, dw, out, mode, warmup, detector)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tim = run_steps(ctx, dw, out, mode, steps)
+    tim = run_steps(ctx, dw, out, mode, steps, detector)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = np.frombuffer(out["st"].cpu().numpy().tobytes(), ckc.STATUS_DTYPE)
@@ -269,6 +269,37 @@ def bench_plain(args, ctx, which):
     else:
         res["roofline"] = alu_roofline("eval_trace_kernel", OPS_PER_ACCESS_1D * accesses, km["eval_trace"], None,
                                        "2.25 int ops per checked access")
+    return res
+
+
+def bench_tripwire(args, ctx):
+    """Exact bounds against the tripwire (redzone) detector model on the 1-D
+    and CSR batches with each input's allocations packed next to each other
+    (16- and 32-byte redzones): how many exact violations the model reports
+    (linear overflows into a redzone) and misses (jumps past it), and the
+    throughput of each (the model runs on the interpreter path)."""
+    res = {}
+    for name, wl in (("affine1d", W.adjacent_layout(W.config1(), 16)),
+                     ("csr", W.adjacent_layout(W.config3(), 32))):
+        n = wl.n_inputs
+        dw = ckc.DeviceWorkload(ctx, wl)
+        out = out_buffers(n, dw.info["n_accesses"])
+        steps = max(2, args.steps // 2)
+        r = {}
+        for det, key in ((W.DETECT_EXACT, "exact"), (W.DETECT_TRIPWIRE, "tripwire")):
+            s, t, st = timed(ctx, dw, out, W.MODE_FULL, 1, steps, detector=det)
+            recs = np.frombuffer(out["recs"].cpu().numpy().tobytes(), ckc.RECORD_DTYPE)
+            r[key] = {"accesses_per_s": int(st["accesses_checked"].sum()) / s, "ms_per_step": s * 1e3,
+                      "violations_reported": int(recs["count"].sum()),
+                      "records_with_violation": int((recs["count"] > 0).sum()),
+                      "kernel_ms": kernel_ms(t)}
+        dw.close()
+        ex, tw = r["exact"]["violations_reported"], r["tripwire"]["violations_reported"]
+        r["caught_by_redzones"] = tw
+        r["missed_past_redzones"] = ex - tw
+        r["redzone_bytes"] = 16 if name == "affine1d" else 32
+        res[name] = r
+        progress(f"tripwire {name} done")
     return res
 
 
@@ -472,6 +503,9 @@ def main():
         if args.workload == "served":
             print(json.dumps(bench_served(args, ctx)))
             return
+        if args.workload == "tripwire":
+            print(json.dumps(bench_tripwire(args, ctx)))
+            return
         if args.workload in ("csr", "affine1d"):
             print(json.dumps(bench_plain(args, ctx, args.workload)))
             return
@@ -488,6 +522,8 @@ def main():
                     if k in r:
                         result[which][k] = r[k]
                 progress(f"{which} done")
+        if not args.no_plain:
+            result["tripwire"] = bench_tripwire(args, ctx)
         if not args.no_batched:
             b = bench_batched(args, ctx)
             progress("batched done")
