@@ -927,3 +927,236 @@ int ckco_validate(const uint8_t* ir, size_t ir_bytes, int32_t* out) {
   prog_free(&P);
   return E_OK;
 }
+
+/* ---- closed-loop fuzzing ------------------------------------------------
+ * The campaign loop of a coverage-guided fuzzer (Section 2.1): take an input
+ * from the corpus, mutate it, execute it, keep it when it reaches coverage
+ * not seen before, and note the inputs that trigger a memory bug.  Readings
+ * (listed in the design notes):
+ *   - one generation checks `batch` children; child c of generation g draws
+ *     its random numbers from SplitMix64 in counter form,
+ *     r(k) = mix(seed + (((g * batch + c) * 64 + k) + 1) * 0x9E3779B97F4A7C15);
+ *   - the child copies corpus entry r(0) mod |corpus| (corpus as at the
+ *     generation's start) and applies 1 + r(1) mod max_stack mutations, the
+ *     j-th drawing r(2+4j) .. r(5+4j);
+ *   - coverage maps are bucketed by hit count as AFL does (1, 2, 3, 4-7,
+ *     8-15, 16-31, 32-127, 128+ -> one bit each); a child is novel when its
+ *     bucketed map shares a bit with the virgin map as it was at the start of
+ *     the generation; afterwards every bit of every child's bucketed map is
+ *     cleared from the virgin map, and novel children join the corpus in child
+ *     order while it has room;
+ *   - a child "crashes" when any of its records has a violation; for each
+ *     (access, kind) the first (generation, child) that reported it is kept. */
+#define FZ_GOLDEN 0x9E3779B97F4A7C15ull
+#define MUT_LAUNCH 1u
+#define MUT_SCALAR 2u
+#define MUT_DATA 4u
+
+/* SplitMix64 (Steele, Lea and Flood, 2014): output k of the generator
+ * started at `seed`. */
+static uint64_t fz_rand(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * FZ_GOLDEN;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* the values a mutation may substitute for a scalar or an element: zero, one,
+ * minus one and the edges of power-of-two ranges */
+static const int64_t FZ_SPECIAL[28] = {
+  0, 1, -1, 2, 7, 8, 15, 16, 31, 32, 63, 64, 127, 128, 255, 256, 1023, 1024, 4095, 4096,
+  65535, 65536, 2147483647, -2147483647 - 1, 4294967295ll, 4294967296ll, INT64_MIN, INT64_MAX};
+
+/* AFL's hit-count classes */
+static uint8_t fz_class(uint8_t v) {
+  if (v == 0) return 0;
+  if (v == 1) return 1;
+  if (v == 2) return 2;
+  if (v == 3) return 4;
+  if (v <= 7) return 8;
+  if (v <= 15) return 16;
+  if (v <= 31) return 32;
+  if (v <= 127) return 64;
+  return 128;
+}
+
+typedef struct {
+  uint32_t batch, max_stack, max_block, corpus_cap, data_slot, ops, n_scalars;
+  uint64_t max_threads, seed;
+  uint64_t n_elems; /* int32 elements of the mutated data slot (0: none) */
+} fz_cfg;
+
+/* One mutation of a child (launch[6], scalars[16], data[n_elems]). */
+static void fz_mutate(const fz_cfg* C, uint32_t* L, int64_t* S, int32_t* D, uint64_t u0, uint64_t u1, uint64_t u2) {
+  uint32_t ops[3], n = 0;
+  if (C->ops & MUT_LAUNCH) ops[n++] = MUT_LAUNCH;
+  if ((C->ops & MUT_SCALAR) && C->n_scalars) ops[n++] = MUT_SCALAR;
+  if ((C->ops & MUT_DATA) && C->n_elems) ops[n++] = MUT_DATA;
+  if (n == 0) return;
+  const uint32_t op = ops[u0 % n];
+  const uint32_t kind = (uint32_t)((u1 >> 8) % 4);
+  if (op == MUT_LAUNCH) {
+    const uint32_t d = (uint32_t)(u1 % 6);
+    uint64_t v = L[d];
+    switch (kind) {
+      case 0: v = v + 1 + u2 % 8; break;
+      case 1: { uint64_t dv = 1 + u2 % 8; v = v > dv ? v - dv : 1; break; }
+      case 2: v = 1ull << (u2 % 11); break;
+      default: v = 1 + u2 % 256; break;
+    }
+    uint32_t M[6];
+    memcpy(M, L, sizeof M);
+    M[d] = (uint32_t)v;
+    const uint64_t bs = (uint64_t)M[3] * M[4] * M[5], nb = (uint64_t)M[0] * M[1] * M[2];
+    /* a child stays inside the campaign's bounds, else the mutation is void */
+    if (v >= 1 && v <= 0xFFFFFFFFull && bs <= C->max_block && nb <= 0xFFFFFFFFull &&
+        (unsigned __int128)nb * bs <= C->max_threads)
+      L[d] = (uint32_t)v;
+  } else if (op == MUT_SCALAR) {
+    const uint32_t k = (uint32_t)(u1 % C->n_scalars);
+    switch (kind) {
+      case 0: S[k] = (int64_t)((uint64_t)S[k] ^ (1ull << (u2 % 64))); break;
+      case 1: S[k] = (int64_t)((uint64_t)S[k] + (uint64_t)((int64_t)(u2 % 33) - 16)); break;
+      case 2: S[k] = FZ_SPECIAL[u2 % 28]; break;
+      default: S[k] = (int64_t)u2; break;
+    }
+  } else {
+    const uint64_t e = u1 % C->n_elems;
+    switch (kind) {
+      case 0: D[e] = (int32_t)(uint32_t)((uint32_t)D[e] + (uint32_t)((int32_t)(u2 % 33) - 16)); break;
+      case 1: D[e] = (int32_t)(uint32_t)(uint64_t)FZ_SPECIAL[u2 % 28]; break;
+      case 2: D[e] = (int32_t)(uint32_t)u2; break;
+      default: D[e] = (int32_t)((uint32_t)D[e] ^ (1u << (u2 % 32))); break;
+    }
+  }
+}
+
+/* A fuzzing campaign of `generations` generations from one seed input.
+ *   cfg      batch, max_stack, max_threads, max_block, corpus_cap, data_slot
+ *            (>= 16: none), ops (MUT_* bits), seed, generations
+ *   corpus   out: c_launch [corpus_cap][6], c_scalars [corpus_cap][16],
+ *            c_data [corpus_cap][n_elems] (when a data slot is mutated),
+ *            c_gen [corpus_cap] (generation that added it; the seed: 0 with
+ *            c_size counting it), c_size [1]
+ *   virgin   out [65536]; sigs out [n_accesses][4] (generation << 32 | child,
+ *            UINT64_MAX if never); stats out [4]: execs, novel children, crashing
+ *            children, generations
+ * Returns 0 or a negative code. */
+int ckco_fuzz(const uint8_t* ir, size_t ir_bytes, const uint32_t* seed_launch, const int64_t* seed_scalars,
+              const or_alloc* table, uint32_t table_len, uint32_t mode, uint32_t detector,
+              const uint32_t* cap_log2, const uint64_t* cfg, uint32_t* c_launch, int64_t* c_scalars,
+              int32_t* c_data, uint32_t* c_gen, uint32_t* c_size, uint8_t* virgin, uint64_t* sigs,
+              uint64_t* stats, int nthreads) {
+  or_prog P;
+  int rc = prog_decode(ir, ir_bytes, &P);
+  if (rc) return rc;
+  fz_cfg C;
+  C.batch = (uint32_t)cfg[0]; C.max_stack = (uint32_t)cfg[1]; C.max_threads = cfg[2];
+  C.max_block = (uint32_t)cfg[3]; C.corpus_cap = (uint32_t)cfg[4]; C.data_slot = (uint32_t)cfg[5];
+  C.ops = (uint32_t)cfg[6]; C.seed = cfg[7];
+  const uint64_t G = cfg[8];
+  C.n_scalars = (uint32_t)P.n_scalars;
+  C.n_elems = C.data_slot < table_len && table[C.data_slot].data ? table[C.data_slot].size_bytes / 4 : 0;
+  const int n_acc = P.n_accesses, n_sites = P.n_sites;
+  prog_free(&P);
+  if (C.batch == 0 || C.max_stack == 0 || C.corpus_cap == 0 || C.max_block == 0 || C.max_block > 1024 ||
+      table_len == 0 || table_len > 16 || mode > M_BOUNDARY)
+    return E_INVALID;
+  const uint64_t ne = C.n_elems;
+  /* corpus: the seed input */
+  memcpy(c_launch, seed_launch, 6 * sizeof(uint32_t));
+  memset(c_scalars, 0, 16 * sizeof(int64_t) * (size_t)C.corpus_cap);
+  for (uint32_t s = 0; s < C.n_scalars; s++) c_scalars[s] = seed_scalars[s];
+  if (ne) memcpy(c_data, table[C.data_slot].data, ne * 4);
+  c_gen[0] = 0;
+  uint32_t size = 1;
+  memset(virgin, 0xFF, 65536);
+  for (int k = 0; k < n_acc * 4; k++) sigs[k] = UINT64_MAX;
+  memset(stats, 0, 4 * sizeof(uint64_t));
+  /* children of one generation */
+  const uint32_t B = C.batch;
+  uint32_t* launch = (uint32_t*)malloc(sizeof(uint32_t) * 6 * B);
+  int64_t* scal = (int64_t*)calloc((size_t)B * (C.n_scalars ? C.n_scalars : 1), sizeof(int64_t));
+  int32_t* data = (int32_t*)malloc(4 * (ne ? ne : 1) * B);
+  or_alloc* tabs = (or_alloc*)malloc(sizeof(or_alloc) * table_len * B);
+  uint64_t* toff = (uint64_t*)malloc(sizeof(uint64_t) * B);
+  uint32_t* tlen = (uint32_t*)malloc(sizeof(uint32_t) * B);
+  or_record* recs = (or_record*)malloc(sizeof(or_record) * (size_t)B * (n_acc ? n_acc : 1));
+  uint64_t* counts = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)B * (n_sites ? n_sites : 1));
+  uint8_t* maps = (uint8_t*)malloc((size_t)B * 65536);
+  or_status* st = (or_status*)malloc(sizeof(or_status) * B);
+  uint8_t* novel = (uint8_t*)malloc(B);
+  uint8_t* seen = (uint8_t*)malloc(65536);
+  int64_t S[16];
+  rc = E_OK;
+  for (uint64_t g = 0; g < G && rc == E_OK; g++) {
+    for (uint32_t c = 0; c < B; c++) {
+      const uint64_t base = ((g * B + c) * 64);
+      const uint32_t p = (uint32_t)(fz_rand(C.seed, base + 0) % size);
+      uint32_t* L = launch + 6 * (size_t)c;
+      memcpy(L, c_launch + 6 * (size_t)p, 6 * sizeof(uint32_t));
+      memcpy(S, c_scalars + 16 * (size_t)p, sizeof S);
+      int32_t* D = data + ne * c;
+      if (ne) memcpy(D, c_data + ne * p, ne * 4);
+      const uint32_t m = 1 + (uint32_t)(fz_rand(C.seed, base + 1) % C.max_stack);
+      for (uint32_t j = 0; j < m; j++)
+        fz_mutate(&C, L, S, D, fz_rand(C.seed, base + 2 + 4 * j), fz_rand(C.seed, base + 3 + 4 * j),
+                  fz_rand(C.seed, base + 4 + 4 * j));
+      for (uint32_t s = 0; s < C.n_scalars; s++) scal[(size_t)c * C.n_scalars + s] = S[s];
+      memcpy(tabs + (size_t)c * table_len, table, sizeof(or_alloc) * table_len);
+      if (ne) tabs[(size_t)c * table_len + C.data_slot].data = D;
+      toff[c] = (uint64_t)c * table_len;
+      tlen[c] = table_len;
+    }
+    rc = ckco_check(ir, ir_bytes, B, launch, scal, tabs, toff, tlen, mode, detector, cap_log2, recs, counts, maps,
+                    st, nthreads);
+    if (rc) break;
+    /* novelty against the virgin map as at the generation's start */
+    memset(seen, 0, 65536);
+    for (uint32_t c = 0; c < B; c++) {
+      const uint8_t* M = maps + (size_t)c * 65536;
+      int nv = 0;
+      for (int i = 0; i < 65536; i++) {
+        const uint8_t b = fz_class(M[i]);
+        if (b & virgin[i]) nv = 1;
+        seen[i] |= b;
+      }
+      novel[c] = (uint8_t)nv;
+      int crash = 0;
+      for (int a = 0; a < n_acc; a++) {
+        const or_record* R = &recs[(size_t)c * n_acc + a];
+        if (!R->count) continue;
+        crash = 1;
+        for (int k = 0; k < 4; k++)
+          if (R->kinds & (1u << k)) {
+            const uint64_t tag = (g << 32) | c;
+            if (tag < sigs[a * 4 + k]) sigs[a * 4 + k] = tag;
+          }
+      }
+      stats[1] += nv;
+      stats[2] += crash;
+    }
+    for (int i = 0; i < 65536; i++) virgin[i] &= (uint8_t)~seen[i];
+    for (uint32_t c = 0; c < B && size < C.corpus_cap; c++) {
+      if (!novel[c]) continue;
+      memcpy(c_launch + 6 * (size_t)size, launch + 6 * (size_t)c, 6 * sizeof(uint32_t));
+      for (uint32_t s = 0; s < 16; s++)
+        c_scalars[16 * (size_t)size + s] = s < C.n_scalars ? scal[(size_t)c * C.n_scalars + s] : 0;
+      if (ne) memcpy(c_data + ne * size, data + ne * c, ne * 4);
+      c_gen[size] = (uint32_t)g;
+      size++;
+    }
+    stats[0] += B;
+    stats[3]++;
+  }
+  *c_size = size;
+  free(launch); free(scal); free(data); free(tabs); free(toff); free(tlen); free(recs); free(counts);
+  free(maps); free(st); free(novel); free(seen);
+  return rc;
+}
+
+/* Output k of the campaign's generator for `seed` (for tests). */
+uint64_t ckco_fuzz_rand(uint64_t seed, uint64_t k) { return fz_rand(seed, k); }
+
+/* The hit-count class of a map byte (for tests). */
+uint32_t ckco_fuzz_class(uint32_t v) { return fz_class((uint8_t)v); }

@@ -49,6 +49,13 @@ def _load():
             lib.ckco_check.restype = ctypes.c_int
             lib.ckco_validate.argtypes = [p, ctypes.c_size_t, p]
             lib.ckco_validate.restype = ctypes.c_int
+            lib.ckco_fuzz.argtypes = [p, ctypes.c_size_t, p, p, p, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint32, p, p, p, p, p, p, p, p, p, p, ctypes.c_int]
+            lib.ckco_fuzz.restype = ctypes.c_int
+            lib.ckco_fuzz_rand.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+            lib.ckco_fuzz_rand.restype = ctypes.c_uint64
+            lib.ckco_fuzz_class.argtypes = [ctypes.c_uint32]
+            lib.ckco_fuzz_class.restype = ctypes.c_uint32
             _lib = lib
     return _lib
 
@@ -114,3 +121,66 @@ def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: b
         raise OracleError(rc)
     del data
     return dict(records=recs, counts=counts, maps=mp, status=st)
+
+
+MUT_LAUNCH, MUT_SCALAR, MUT_DATA = 1, 2, 4
+NO_SLOT = 0xFFFFFFFF
+
+
+def fuzz_rand(seed: int, k: int) -> int:
+    """Output k of the campaign's SplitMix64 generator started at ``seed``."""
+    return int(_load().ckco_fuzz_rand(seed, k))
+
+
+def fuzz_class(v: int) -> int:
+    """The hit-count class the campaign gives a map byte."""
+    return int(_load().ckco_fuzz_class(v))
+
+
+def fuzz(wl, generations: int, batch: int, max_stack: int = 4, max_threads: int = 1 << 20,
+         max_block: int = 1024, corpus_cap: int = 256, data_slot: int = NO_SLOT,
+         ops: int = MUT_LAUNCH | MUT_SCALAR, seed: int = 0, nthreads: int = 1, mode: int | None = None,
+         detector: int | None = None):
+    """A fuzzing campaign from input 0 of workload ``wl`` (its launch,
+    scalars and table; data slots resolved to host arrays).  Returns dict(
+    launch [size, 6], scalars [size, 16], data [size, n_elems] or None, gen
+    [size], virgin [65536], sigs [n_accesses, 4], stats dict)."""
+    lib = _load()
+    n_acc, _, _, _ = validate(wl.ir)
+    mode = wl.mode if mode is None else mode
+    detector = getattr(wl, "detector", 0) if detector is None else detector
+    cap = np.asarray(wl.cap_log2, np.uint32)
+    data = [np.ascontiguousarray(d) for d in wl.data]
+    tab = np.array(wl.tables[wl.table_idx[0]], copy=True)
+    refs = tab["data"].astype(np.int64)
+    addr = np.zeros_like(tab["data"])
+    for k, d in enumerate(data):
+        addr[refs == k + 1] = d.ctypes.data
+    tab["data"] = addr
+    tab = np.ascontiguousarray(tab)
+    launch = np.ascontiguousarray(wl.launch[0], np.uint32)
+    sc = np.zeros(16, np.int64)
+    sc[: wl.scalars.shape[1]] = wl.scalars[0]
+    n_elems = int(tab[data_slot]["size_bytes"]) // 4 if data_slot < len(tab) else 0
+    cfg = np.array([batch, max_stack, max_threads, max_block, corpus_cap, data_slot, ops, seed, generations],
+                   np.uint64)
+    c_launch = np.zeros((corpus_cap, 6), np.uint32)
+    c_scalars = np.zeros((corpus_cap, 16), np.int64)
+    c_data = np.zeros((corpus_cap, max(1, n_elems)), np.int32)
+    c_gen = np.zeros(corpus_cap, np.uint32)
+    c_size = np.zeros(1, np.uint32)
+    virgin = np.zeros(65536, np.uint8)
+    sigs = np.zeros((max(1, n_acc), 4), np.uint64)
+    stats = np.zeros(4, np.uint64)
+    buf = ctypes.create_string_buffer(wl.ir, len(wl.ir))
+    rc = lib.ckco_fuzz(buf, len(wl.ir), _ptr(launch), _ptr(sc), _ptr(tab), len(tab), int(mode), int(detector),
+                       _ptr(cap), _ptr(cfg), _ptr(c_launch), _ptr(c_scalars), _ptr(c_data), _ptr(c_gen),
+                       _ptr(c_size), _ptr(virgin), _ptr(sigs), _ptr(stats), int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    n = int(c_size[0])
+    del data
+    return dict(launch=c_launch[:n], scalars=c_scalars[:n], data=c_data[:n] if n_elems else None,
+                gen=c_gen[:n], virgin=virgin, sigs=sigs[:n_acc],
+                stats=dict(execs=int(stats[0]), novel=int(stats[1]), crashes=int(stats[2]),
+                           generations=int(stats[3])))
