@@ -110,7 +110,7 @@ def parse(argv=None):
     ap.add_argument("--no-plain", action="store_true", help="skip the CSR and 1-D sub-results")
     ap.add_argument("--served-seconds", type=float, default=35.0,
                     help="length of the served stream (the first 5 s are warm-up)")
-    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d", "batched", "served", "tripwire"],
+    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d", "batched", "served", "tripwire", "fuzz"],
                     help="stencil: the benchmark line (with every sub-result unless switched off); "
                          "csr / affine1d / batched / served: that form alone")
     return ap.parse_args(argv)
@@ -300,6 +300,74 @@ def bench_tripwire(args, ctx):
         r["redzone_bytes"] = 16 if name == "affine1d" else 32
         res[name] = r
         progress(f"tripwire {name} done")
+    return res
+
+
+def fuzz_campaigns():
+    """(name, seed workload, campaign options) of the fuzzing sub-results:
+    the stencil (whole grid, launch and scalar mutation), the CSR gather
+    (col_idx elements mutated, 2^14 rows) and Listing 3's guarded kernel
+    (many small executions)."""
+    sten = W.config2(n_inputs=1, g0=32, hw0=512)
+    csr = W.config3(n_inputs=1, log2_rows=14)
+    l3 = W.Workload("listing3", _listing3_ir(), np.array([[1, 1, 1, 64, 1, 1]], np.uint32),
+                    np.array([[100]], np.int64),
+                    np.array([[W.alloc(800), W.alloc(800, base=W.LOGICAL_BASE + (1 << 36)),
+                               W.alloc(800, base=W.LOGICAL_BASE + (2 << 36))]], W.ALLOC_DTYPE),
+                    np.zeros(1, np.uint32), [], W.MODE_FULL)
+    return [("stencil_32x32_blocks", sten, dict(batch=256, ops=ckc.MUT_LAUNCH | ckc.MUT_SCALAR,
+                                               max_threads=1 << 20, max_block=1024)),
+            ("csr_2e14_rows_col_idx", csr, dict(batch=256, ops=ckc.MUT_DATA, data_slot=1,
+                                                max_threads=1 << 14, max_block=256)),
+            ("listing3_guarded", l3, dict(batch=4096, ops=ckc.MUT_LAUNCH | ckc.MUT_SCALAR,
+                                          max_threads=1 << 12, max_block=256))]
+
+
+def _listing3_ir():
+    """Listing 3's guarded vecAdd: if (id < N) c[id+1] = a[id+1] + b[id+1]."""
+    from paper_2601_01048_amd.gen.ir import Program
+    p = Program(n_scalars=1, n_slots=3)
+    idv = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), 32), p.special("tid.x"), 32)
+    with p.if_(p.cmplts(idv, p.scalar(0, 32), 32)):
+        i1 = p.add(idv, p.const(1, 32), 32)
+        p.access(0, i1)
+        p.access(1, i1)
+        p.access(2, i1, write=True)
+    return p.to_bytes()
+
+
+def bench_fuzz(args, ctx, with_cpu=True):
+    """Closed-loop fuzzing campaigns on the device: fuzz inputs (children
+    checked) per second over whole generations (mutation, check, novelty,
+    corpus update), against the oracle's campaign loop on the host cores."""
+    res = {}
+    gens = max(4, args.steps)
+    for name, wl, kw in fuzz_campaigns():
+        dw = ckc.DeviceWorkload(ctx, wl)
+        with ckc.Fuzz(ctx, dw, seed=5, corpus_cap=4096, **kw) as fz:
+            fz.run(1)
+            st0 = fz.stats()
+            t0 = time.perf_counter()
+            fz.run(gens)
+            st1 = fz.stats()
+            t1 = time.perf_counter()
+        dw.close()
+        ex = st1["execs"] - st0["execs"]
+        r = {"fuzz_inputs_per_s": ex / (t1 - t0), "ms_per_generation": (t1 - t0) / gens * 1e3,
+             "batch": kw["batch"], "generations": st1["generations"], "corpus": st1["corpus"],
+             "novel": st1["novel"], "crashing_children": st1["crashes"], "map_bits": st1["map_bits"]}
+        if with_cpu:
+            from oracle import oracle as O
+            cores = min(16, os.cpu_count() or 1)
+            okw = {k: v for k, v in kw.items() if k != "batch"}
+            b = min(kw["batch"], 256)
+            c0 = time.perf_counter()
+            O.fuzz(wl, generations=1, batch=b, seed=5, corpus_cap=4096, nthreads=cores, **okw)
+            c1 = time.perf_counter()
+            r["cpu_oracle"] = {"fuzz_inputs_per_s": b / (c1 - c0), "threads": cores,
+                               "sample": f"one generation of {b} children"}
+        res[name] = r
+        progress(f"fuzz {name} done")
     return res
 
 
@@ -503,6 +571,9 @@ def main():
         if args.workload == "served":
             print(json.dumps(bench_served(args, ctx)))
             return
+        if args.workload == "fuzz":
+            print(json.dumps(bench_fuzz(args, ctx)))
+            return
         if args.workload == "tripwire":
             print(json.dumps(bench_tripwire(args, ctx)))
             return
@@ -524,6 +595,7 @@ def main():
                 progress(f"{which} done")
         if not args.no_plain:
             result["tripwire"] = bench_tripwire(args, ctx)
+            result["fuzz"] = bench_fuzz(args, ctx, with_cpu=not args.no_cpu_baseline)
         if not args.no_batched:
             b = bench_batched(args, ctx)
             progress("batched done")

@@ -358,6 +358,96 @@ int ckc_job_elapsed(ckc_ctx ctx, uint64_t job, float* ms);
 int ckc_check_batch_noalloc(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_descs, const ckc_launch_opts* opts,
                             ckc_record* recs, uint8_t* maps, ckc_input_status* st);
 
+/* ---- closed-loop fuzzing on the device ---------------------------------------
+ * The loop the paper's fuzzer runs around every execution (Section 2.1, the
+ * AFL++ campaign of Section 7.1): take an input from the corpus, mutate it,
+ * execute it under the sanitizer with coverage, keep it when it reaches
+ * coverage not seen before, note it when it triggers a memory bug.  Here a
+ * generation is a batch of children checked together, and the whole loop
+ * stays on the device: corpus, virgin map and crash signatures never leave it
+ * between generations.
+ *
+ * Generation g, child c (both sides of every test compute exactly this):
+ *   r(k) = SplitMix64 output (g * batch + c) * 64 + k of the seed, the
+ *          counter form mix(seed + (n + 1) * 0x9E3779B97F4A7C15) (Steele,
+ *          Lea and Flood, 2014);
+ *   the child copies corpus entry r(0) mod |corpus| (corpus as at the start of
+ *   the generation) and applies 1 + r(1) mod max_stack mutations, mutation j
+ *   drawing u0, u1, u2 = r(2+4j), r(3+4j), r(4+4j): an operator among the
+ *   enabled ones (launch, scalar, data, in that order, each only if it has
+ *   something to mutate) by u0, a target (launch dimension u1 mod 6, scalar
+ *   u1 mod n_scalars, element u1 mod n_elems) and a kind ((u1 >> 8) mod 4) by
+ *   u1, a value by u2:
+ *     launch: +1..8, -1..8 (at least 1), 2^(u2 mod 11), 1 + u2 mod 256; void
+ *             when the child would leave max_block or max_threads;
+ *     scalar: flip bit u2 mod 64, add -16..16, a special value (0, 1, -1, 2,
+ *             7, 8, 15, 16, ..., 2^31-1, -2^31, 2^32-1, 2^32, -2^63, 2^63-1),
+ *             the 64 bits of u2;
+ *     data (int32 elements): add -16..16, a special value (low 32 bits), the
+ *             low 32 bits of u2, flip bit u2 mod 32;
+ *   the children are checked as one job (mode, detector and caps of the
+ *   campaign); a child is novel when its coverage map, bucketed by hit count
+ *   as AFL buckets it (1, 2, 3, 4-7, 8-15, 16-31, 32-127, 128+: one bit each),
+ *   shares a bit with the virgin map as at the start of the generation; then
+ *   every child's buckets are cleared from the virgin map, novel children
+ *   join the corpus in child order while it has room, and every violated
+ *   (access, kind) keeps its least (generation << 32 | child). */
+enum ckc_mutation_ops { CKC_MUT_LAUNCH = 1, CKC_MUT_SCALAR = 2, CKC_MUT_DATA = 4 };
+#define CKC_FUZZ_NO_SLOT 0xFFFFFFFFu
+
+typedef struct ckc_fuzz_config {
+  uint32_t prog_id;
+  uint32_t table_id;        /* allocation table of the seed input (resident) */
+  uint32_t launch[6];       /* seed input: gx gy gz bx by bz */
+  int64_t scalars[16];      /* seed input: the program's scalars (the rest ignored) */
+  uint32_t mode;            /* CKC_FULL, CKC_REP_CORNERS or CKC_REP_BOUNDARY */
+  uint32_t flags;           /* 0 or CKC_TRIPWIRE */
+  uint32_t loop_cap_log2[2];/* as in ckc_batch */
+  uint32_t batch;           /* children per generation, 1..65536 */
+  uint32_t max_stack;       /* mutations per child drawn from 1..max_stack, max_stack 1..15 */
+  uint32_t max_block;       /* bound on a child's block, 1..1024 */
+  uint32_t corpus_cap;      /* corpus entries kept, 1..2^20 */
+  uint64_t max_threads;     /* bound on a child's threads (grid x block) */
+  uint32_t data_slot;       /* slot whose data is mutated as int32 elements (each child and
+                               corpus entry gets its own copy), or CKC_FUZZ_NO_SLOT */
+  uint32_t ops;             /* ckc_mutation_ops bits */
+  uint64_t seed;            /* generator seed */
+} ckc_fuzz_config;
+
+typedef struct ckc_fuzz_stats {
+  uint64_t generations, execs;  /* generations run, children checked */
+  uint64_t novel;               /* novel children (kept or not: the corpus may be full) */
+  uint64_t crashes;             /* children with a reported violation */
+  uint64_t corpus;              /* corpus entries, the seed included */
+  uint64_t map_bits;            /* bucket bits cleared from the virgin map */
+} ckc_fuzz_stats;
+
+typedef struct ckc_fuzz_s* ckc_fuzz;
+
+/* Creates a campaign whose corpus holds the seed input: validates it like a
+ * one-input batch (errors as ckc_check_batch), stages the children's job once
+ * (buffers for batch inputs of up to max_threads threads each) and places the
+ * corpus, virgin map and signatures in device memory.  The program and table
+ * stay in use until ckc_fuzz_destroy.  The campaign runs on the context's
+ * stream; while it exists, use the context from one thread.
+ * Errors: CKC_E_INVALID (limits, the seed outside the bounds, a data slot
+ * without data), CKC_E_RANGE (key bits of max_threads), CKC_E_NOMEM, CKC_E_HIP. */
+int ckc_fuzz_create(ckc_ctx ctx, const ckc_fuzz_config* cfg, ckc_fuzz* out);
+/* Queues `generations` generations and returns without waiting. */
+int ckc_fuzz_run(ckc_fuzz f, uint32_t generations);
+/* Waits for the queued generations; the campaign's counters. */
+int ckc_fuzz_get_stats(ckc_fuzz f, ckc_fuzz_stats* st);
+/* Waits; copies the campaign out to host memory (any pointer may be NULL):
+ * launch [corpus_cap][6], scalars [corpus_cap][16], data [corpus_cap][n_elems]
+ * (n_elems = size_bytes / 4 of the data slot), gen [corpus_cap] (generation
+ * that added each entry; 0 for the seed), virgin [65536], sigs
+ * [n_accesses][4] (kinds OVER, UNDER, FREED, NULL in bit order; UINT64_MAX if
+ * never).  Entries past the corpus size are unspecified. */
+int ckc_fuzz_read(ckc_fuzz f, uint32_t* launch, int64_t* scalars, int32_t* data, uint32_t* gen,
+                  uint8_t* virgin, uint64_t* sigs);
+/* Waits, frees the campaign and releases its program and table. */
+void ckc_fuzz_destroy(ckc_fuzz f);
+
 /* ---- autotuning of the persistent launch ---------------------------------- */
 typedef struct ckc_tune_entry {
   ckc_launch_opts opts;   /* candidate (hip_stream as passed in base) */

@@ -1062,6 +1062,12 @@ int ckco_fuzz(const uint8_t* ir, size_t ir_bytes, const uint32_t* seed_launch, c
   if (C.batch == 0 || C.max_stack == 0 || C.corpus_cap == 0 || C.max_block == 0 || C.max_block > 1024 ||
       table_len == 0 || table_len > 16 || mode > M_BOUNDARY)
     return E_INVALID;
+  {
+    const uint64_t bs = (uint64_t)seed_launch[3] * seed_launch[4] * seed_launch[5];
+    const uint64_t nb = (uint64_t)seed_launch[0] * seed_launch[1] * seed_launch[2];
+    if (C.max_stack > 15 || bs == 0 || nb == 0 || bs > C.max_block || (unsigned __int128)nb * bs > C.max_threads)
+      return E_INVALID; /* the seed itself must respect the campaign's bounds */
+  }
   const uint64_t ne = C.n_elems;
   /* corpus: the seed input */
   memcpy(c_launch, seed_launch, 6 * sizeof(uint32_t));

@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src, device in (("kernels.hip", True), ("loader.cpp", False), ("runtime.cpp", False),
-                        ("server.cpp", False)):
+                        ("server.cpp", False), ("fuzz.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [hipcc] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
         if device:

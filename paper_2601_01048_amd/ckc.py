@@ -83,6 +83,22 @@ class ServerStats(ctypes.Structure):
                                                 "max_inflight_bytes", "max_inflight_jobs")]
 
 
+MUT_LAUNCH, MUT_SCALAR, MUT_DATA = 1, 2, 4
+FUZZ_NO_SLOT = 0xFFFFFFFF
+
+
+class FuzzConfig(ctypes.Structure):
+    _fields_ = [("prog_id", ctypes.c_uint32), ("table_id", ctypes.c_uint32), ("launch", ctypes.c_uint32 * 6),
+                ("scalars", ctypes.c_int64 * 16), ("mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("loop_cap_log2", ctypes.c_uint32 * 2), ("batch", ctypes.c_uint32), ("max_stack", ctypes.c_uint32),
+                ("max_block", ctypes.c_uint32), ("corpus_cap", ctypes.c_uint32), ("max_threads", ctypes.c_uint64),
+                ("data_slot", ctypes.c_uint32), ("ops", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class FuzzStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("generations", "execs", "novel", "crashes", "corpus", "map_bits")]
+
+
 def launch_opts(schedule=0, chunk=0, wg_per_cu=0, force_generic=False, use_graph=False, stream=None):
     return LaunchOpts(schedule, chunk, wg_per_cu, 1 if force_generic else 0, 1 if use_graph else 0, 0, stream)
 
@@ -125,11 +141,18 @@ def lib():
         L.ckc_server_submit.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
         L.ckc_server_result.argtypes = [vp, u64, vp, vp, vp, vp, u32]
         L.ckc_server_get_stats.argtypes = [vp, vp]
+        L.ckc_fuzz_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.ckc_fuzz_run.argtypes = [vp, u32]
+        L.ckc_fuzz_get_stats.argtypes = [vp, vp]
+        L.ckc_fuzz_read.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.ckc_fuzz_destroy.argtypes = [vp]
+        L.ckc_fuzz_destroy.restype = None
         for f in ("ckc_init", "ckc_analyze_ir", "ckc_load_program", "ckc_unload_program",
                   "ckc_put_alloc_table", "ckc_free_alloc_table", "ckc_check_batch", "ckc_check_batch_noalloc",
                   "ckc_read_results", "ckc_job_sizes", "ckc_job_timing", "ckc_job_elapsed",
                   "ckc_autotune", "ckc_server_create", "ckc_server_submit", "ckc_server_result",
-                  "ckc_server_get_stats"):
+                  "ckc_server_get_stats", "ckc_fuzz_create", "ckc_fuzz_run", "ckc_fuzz_get_stats",
+                  "ckc_fuzz_read"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -500,3 +523,70 @@ class DeviceStream:
         for pid in self.progs.values():
             self.ctx.unload_program(pid)
         self.table_ids, self.progs, self.buf = [], {}, None
+
+
+class Fuzz:
+    """A fuzzing campaign on the device (ckc_fuzz_*) seeded with input
+    ``idx`` of a DeviceWorkload."""
+
+    def __init__(self, ctx: Context, dw: DeviceWorkload, batch: int, max_stack: int = 4,
+                 max_threads: int = 1 << 20, max_block: int = 1024, corpus_cap: int = 256,
+                 data_slot: int = FUZZ_NO_SLOT, ops: int = MUT_LAUNCH | MUT_SCALAR, seed: int = 0,
+                 mode=None, idx: int = 0):
+        wl = dw.wl
+        cfg = FuzzConfig()
+        cfg.prog_id = dw.prog
+        cfg.table_id = int(dw.table_ids[wl.table_idx[idx]])
+        for q in range(6):
+            cfg.launch[q] = int(wl.launch[idx][q])
+        for q in range(wl.scalars.shape[1]):
+            cfg.scalars[q] = int(wl.scalars[idx][q])
+        cfg.mode = wl.mode if mode is None else mode
+        cfg.flags = TRIPWIRE if getattr(wl, "detector", 0) else 0
+        cfg.loop_cap_log2[0], cfg.loop_cap_log2[1] = wl.cap_log2
+        cfg.batch, cfg.max_stack, cfg.max_block, cfg.corpus_cap = batch, max_stack, max_block, corpus_cap
+        cfg.max_threads, cfg.data_slot, cfg.ops, cfg.seed = max_threads, data_slot, ops, seed
+        self.cfg, self.dw = cfg, dw
+        self.n_elems = 0
+        tab = wl.tables[wl.table_idx[idx]]
+        if data_slot != FUZZ_NO_SLOT and data_slot < len(tab):
+            self.n_elems = int(tab[data_slot]["size_bytes"]) // 4
+        h = ctypes.c_void_p()
+        _check(lib().ckc_fuzz_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    def run(self, generations: int):
+        _check(lib().ckc_fuzz_run(self.h, generations))
+
+    def stats(self):
+        st = FuzzStats()
+        _check(lib().ckc_fuzz_get_stats(self.h, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in FuzzStats._fields_}
+
+    def read(self):
+        """dict(launch [size, 6], scalars [size, 16], data [size, n_elems] or
+        None, gen [size], virgin [65536], sigs [n_accesses, 4], stats)."""
+        st = self.stats()
+        cap, n = self.cfg.corpus_cap, st["corpus"]
+        n_acc = self.dw.info["n_accesses"]
+        launch = np.zeros((cap, 6), np.uint32)
+        scal = np.zeros((cap, 16), np.int64)
+        data = np.zeros((cap, max(1, self.n_elems)), np.int32)
+        gen = np.zeros(cap, np.uint32)
+        virgin = np.zeros(65536, np.uint8)
+        sigs = np.zeros((max(1, n_acc), 4), np.uint64)
+        _check(lib().ckc_fuzz_read(self.h, _p(launch), _p(scal), _p(data) if self.n_elems else None, _p(gen),
+                                   _p(virgin), _p(sigs)))
+        return dict(launch=launch[:n], scalars=scal[:n], data=data[:n] if self.n_elems else None, gen=gen[:n],
+                    virgin=virgin, sigs=sigs[:n_acc], stats=st)
+
+    def close(self):
+        if self.h:
+            lib().ckc_fuzz_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

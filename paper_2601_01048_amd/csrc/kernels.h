@@ -104,6 +104,37 @@ hipError_t launch_finish(const KArgs& a, hipStream_t s);
 // branches) -> first-violation replay -> finishing.
 hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uint64_t n_records);
 
+// A fuzzing campaign on the device: its counters, and the buffers its
+// generation kernels use (the children are the inputs of a staged job).
+struct FzState {
+  uint32_t size, pad;         // corpus entries
+  uint64_t execs, novel, crashes, generations;
+};
+struct FzArgs {
+  dinput* in;                 // the job's inputs: one per child
+  int64_t* sc;                // the job's scalars [batch][MAX_SCALARS]
+  const ckc_record* recs;     // the job's records
+  const uint32_t* counts;     // the job's per-site counts
+  uint32_t batch, n_scalars, max_stack, max_block, cap, ops;
+  uint64_t max_threads, seed, n_elems;
+  int32_t* child_data;        // [batch][n_elems]: the children's mutated elements
+  uint32_t* c_launch;         // corpus [cap][6]
+  int64_t* c_scalars;         // corpus [cap][MAX_SCALARS]
+  int32_t* c_data;            // corpus [cap][n_elems]
+  uint32_t* c_gen;            // corpus [cap]: generation that added the entry
+  uint8_t* virgin;            // [65536]: bucket bits not yet seen
+  uint32_t* seen;             // [65536 / 4]: buckets seen by the current generation
+  unsigned long long* sigs;   // [n_accesses][4]: least (generation << 32 | child) per kind
+  uint32_t* novel;            // [batch]
+  uint32_t* pos;              // [batch]: corpus position of an appended child, or ~0
+  FzState* st;
+};
+// Builds the children of generation g from the corpus.
+hipError_t launch_fuzz_mutate(const FzArgs& f, uint64_t g, hipStream_t s);
+// Classifies the checked children of generation g, updates the virgin map,
+// appends novel children to the corpus.
+hipError_t launch_fuzz_update(const FzArgs& f, uint64_t g, hipStream_t s);
+
 // Device address of the static scratch array (CKC_NOALLOC_SCRATCH_BYTES) on
 // device dev, which must be the current device; looked up once per device.
 hipError_t scratch_address(int dev, void** out);

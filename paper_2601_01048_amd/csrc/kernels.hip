@@ -42,6 +42,7 @@
 #include "dev_plan.h"
 #include "dev_trace.h"
 #include "dev_interp.h"
+#include "dev_fuzz.h"
 
 // Buffers of ckc_check_batch_noalloc: one static array per device, held until
 // the process ends.  Host code never passes `scratch` itself to a kernel (on
@@ -163,6 +164,18 @@ hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_fuzz_mutate(const FzArgs& f, uint64_t g, hipStream_t s) {
+  hipLaunchKernelGGL(fuzz_mutate_kernel, dim3(f.batch), dim3(256), 0, s, f, g);
+  return hipGetLastError();
+}
+hipError_t launch_fuzz_update(const FzArgs& f, uint64_t g, hipStream_t s) {
+  hipLaunchKernelGGL(fuzz_classify_kernel, dim3(f.batch), dim3(256), 0, s, f, g);
+  hipLaunchKernelGGL(fuzz_virgin_kernel, dim3(65536 / 4 / 256), dim3(256), 0, s, f);
+  hipLaunchKernelGGL(fuzz_append_kernel, dim3(1), dim3(1024), 0, s, f, g);
+  hipLaunchKernelGGL(fuzz_copy_kernel, dim3(f.batch), dim3(256), 0, s, f);
+  return hipGetLastError();
 }
 
 hipError_t launch_fixup(const KArgs& a, uint64_t n_records, hipStream_t s) {

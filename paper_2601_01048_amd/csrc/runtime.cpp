@@ -606,6 +606,20 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
 
 }  // namespace
 
+int ckc::rt::stage_new_job(ckc_ctx c, Job& J, Stage& S, bool dense, KArgs& a, EvalGrid& eg) {
+  ckc_launch_opts O;
+  std::memset(&O, 0, sizeof O);
+  return stage_job(c, J, S, O, dense, a, eg);
+}
+dinput ckc::rt::make_input(const Program& P, const Table& T, const ckc_batch& B, uint32_t i) {
+  return input_of(P, T, B, i);
+}
+hipError_t ckc::rt::run_evaluation(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
+  return launch_evaluation(a, eg, s, nullptr);
+}
+void ckc::rt::release_job(ckc_ctx c, Job& J) { free_job(c, J); }
+unsigned ckc::rt::index_bits(uint64_t n) { return bits_of(n); }
+
 extern "C" {
 
 const char* ckc_last_error(void) { return g_err.c_str(); }

@@ -150,5 +150,15 @@ int fail(int code, const std::string& msg);
 int validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force_generic, uint64_t* ws_bytes);
 // Completion event of an unread job (nullptr if unknown).
 hipEvent_t job_done_event(ckc_ctx c, uint64_t job);
+// Device buffers of a staged input list (default launch options), in J.
+int stage_new_job(ckc_ctx c, Job& J, Stage& S, bool dense, KArgs& a, EvalGrid& eg);
+// The job input of input i of descriptor B (program, table, launch, caps).
+dinput make_input(const Program& P, const Table& T, const ckc_batch& B, uint32_t i);
+// Planning and every evaluator of a staged job, queued on s.
+hipError_t run_evaluation(const KArgs& a, const EvalGrid& eg, hipStream_t s);
+// Returns a job's buffers to the context's pool.
+void release_job(ckc_ctx c, Job& J);
+// Bits needed for the values 0..n-1.
+unsigned index_bits(uint64_t n);
 }  // namespace rt
 }  // namespace ckc

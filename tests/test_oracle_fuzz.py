@@ -132,3 +132,7 @@ def test_corpus_cap_and_invalid_campaigns():
         O.fuzz(wl, generations=1, batch=0)
     with pytest.raises(O.OracleError):
         O.fuzz(wl, generations=1, batch=4, mode=W.MODE_PREX)
+    with pytest.raises(O.OracleError):  # the seed's block above max_block
+        O.fuzz(wl, generations=1, batch=4, max_block=32)
+    with pytest.raises(O.OracleError):
+        O.fuzz(wl, generations=1, batch=4, max_stack=16)
