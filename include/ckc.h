@@ -104,9 +104,12 @@ enum ckc_prog_class {
   CKC_CLS_UNIFORM = 16,   /* control flow is thread-invariant and every index is
                              affine: evaluated as a per-input access trace */
   CKC_CLS_EXPANDED = 32,  /* one loop is evaluated one lane per iteration */
-  CKC_CLS_GATHER = 64     /* that loop's body is straight-line with indices affine in
+  CKC_CLS_GATHER = 64,    /* that loop's body is straight-line with indices affine in
                              the counter or in one loaded value (an indirect gather),
                              evaluated from per-input entries rather than interpreted */
+  CKC_CLS_BARRIER = 128   /* some index depends on a value loaded from shared memory (an
+                             index-related shared variable of Algorithm 2): BARRIERs are
+                             kept and each block runs phase by phase */
 };
 
 typedef struct ckc_ctx_s* ckc_ctx;
@@ -162,6 +165,15 @@ int ckc_analyze_ir(const void* ir, size_t ir_bytes, ckc_prog_info* info, ckc_acc
  * nonzero id.  info may be NULL.  Errors: CKC_E_IR, CKC_E_NOMEM, CKC_E_HIP. */
 int ckc_load_program(ckc_ctx ctx, const void* ir, size_t ir_bytes, uint32_t* prog_id,
                      ckc_prog_info* info);
+/* ckc_load_program with flags: CKC_LOAD_NO_PRUNE keeps every instruction of
+ * the program as written (the data math, every BARRIER, every STORE value):
+ * the unpruned baseline of the paper's AXIPrune measurement (Section 7.4.2);
+ * results are identical, only the work differs.  Such a program always runs
+ * on the interpreter.  Errors as ckc_load_program, CKC_E_INVALID for unknown
+ * flags. */
+enum ckc_load_flags { CKC_LOAD_NO_PRUNE = 1 };
+int ckc_load_program_ex(ckc_ctx ctx, const void* ir, size_t ir_bytes, uint32_t flags, uint32_t* prog_id,
+                        ckc_prog_info* info);
 /* CKC_E_BUSY while an unread job uses the program. */
 int ckc_unload_program(ckc_ctx ctx, uint32_t prog_id);
 

@@ -70,7 +70,33 @@
  * LOAD then reads the element (4 bytes sign-extended, or 8 bytes) from the
  * slot's data; a LOAD outside those bounds reads 0 and the lane continues.
  * Slots live in a memory space declared in the header (global, per-block
- * shared, per-thread local); LOAD reads global slots only.
+ * shared, per-thread local); LOAD reads global and shared slots.
+ *
+ * STORE is a checked write like ACCESS that also carries a value register.
+ * A STORE of 4-byte elements to a shared slot, within bounds, writes the
+ * value's low 32 bits into the block's instance of the slot; every other
+ * STORE only checks (global memory holds the host's data; local memory is
+ * not modelled).  Shared memory works in phases: BARRIER (the kernel's
+ * __syncthreads, written at the top level only) ends a phase.  Every element
+ * of a shared instance starts at 0; a LOAD from a shared slot (4-byte
+ * elements) reads the element as it was at the start of the phase; at the end
+ * of a phase each element written in it takes the largest (signed) value
+ * stored to it in the phase.  For a kernel without racing writes this is the
+ * value of its one write.
+ *
+ * Non-index arithmetic (the data math of a kernel, what the paper's
+ * MathElimination removes when their values reach no index): FADD FSUB FMUL on
+ * IEEE binary64 bit patterns in 64-bit registers (round to nearest even);
+ * FEXP e^x by one fixed method, so that every implementation gives the same
+ * bits: k = floor(x * (1/ln 2) + 1/2), r = (x - k * ln2_hi) - k * ln2_lo with
+ * ln2_hi = 0x1.62e42ffp-1 (ln 2 rounded to 29 significant bits) and ln2_lo =
+ * -0x1.718432a1b0e26p-35, the Taylor polynomial sum r^i / i! (i = 0..13,
+ * coefficients rounded to binary64) in Horner form, times 2^k (for k below
+ * -1022: times 2^(k+1000), then 2^-1000; for k = 1024: 2^1023, then 2);
+ * NaN stays NaN, x > 709.782712893384 gives +inf, x < -745.1332191019412
+ * gives 0; every operation rounded on its own (no fused multiply-add).  ITOF
+ * converts an int32 (w = 32) exactly; FTOI truncates toward zero to width w,
+ * NaN giving 0 and values out of range the nearest representable one.
  *
  * ------------------------------------------------------------------------
  * Control flow (structured; matching is by nesting, not by stored targets)
@@ -140,7 +166,7 @@ typedef struct ckc_ir_header {
  * per block of the launch; local memory one per thread.  Bounds are the same
  * for every instance (the slot's size); under the tripwire detector each
  * space is its own address window (see ckc.h, CKC_TRIPWIRE).  Only global
- * slots may be read by LOAD. */
+ * and shared slots may be read by LOAD. */
 enum ckc_ir_space { CKC_SPACE_GLOBAL = 0, CKC_SPACE_SHARED = 1, CKC_SPACE_LOCAL = 2 };
 
 typedef struct ckc_ir_instr {
@@ -160,6 +186,11 @@ typedef struct ckc_ir_instr {
  *   SELECT   dst, a = condition, b = value if true, c = value if false
  *   ACCESS   a = index reg, b = access id, c = slot, d = log2_elem (bits 0..1) | write (bit 2), s0 = site
  *   LOAD     dst, a = index reg, b = access id, c = slot, d = log2_elem (2 or 3), s0 = site
+ *   STORE    dst = VALUE register (read, not defined), a = index reg, b = access id, c = slot,
+ *            d = log2_elem (0..3), s0 = site
+ *   FADD FSUB FMUL  dst, a, b (w = 64);  FEXP  dst, a (w = 64)
+ *   ITOF     dst, a (w = 32: the operand's width);  FTOI  dst, a (w: the result's width)
+ *   BARRIER  no operands; top level only
  *   IF       a = predicate, s0 = true-site, s1 = false-site
  *   LOOP     dst = counter, a = start, b = end, c = step, s0 = iteration site, s1 = exit site
  *   ELSE ENDIF ENDLOOP   no operands */
@@ -195,13 +226,21 @@ enum ckc_ir_op {
   CKC_OP_SEXT = 32,
   CKC_OP_ZEXT = 33,
   CKC_OP_TRUNC = 34,
+  CKC_OP_FADD = 40,
+  CKC_OP_FSUB = 41,
+  CKC_OP_FMUL = 42,
+  CKC_OP_FEXP = 43,
+  CKC_OP_ITOF = 44,
+  CKC_OP_FTOI = 45,
   CKC_OP_ACCESS = 48,
   CKC_OP_LOAD = 49,
+  CKC_OP_STORE = 50,
   CKC_OP_IF = 56,
   CKC_OP_ELSE = 57,
   CKC_OP_ENDIF = 58,
   CKC_OP_LOOP = 59,
-  CKC_OP_ENDLOOP = 60
+  CKC_OP_ENDLOOP = 60,
+  CKC_OP_BARRIER = 61
 };
 
 enum ckc_special {

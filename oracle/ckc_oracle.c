@@ -41,6 +41,7 @@
  * Build: gcc -O2 -shared -fPIC -pthread ckc_oracle.c -o libckc_oracle.so
  */
 #include <limits.h>
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -53,8 +54,9 @@ enum {
   O_SHL, O_SHRA, O_SHRL, O_MINS, O_MAXS, O_MINU, O_MAXU,
   O_CMPEQ, O_CMPNE, O_CMPLTS, O_CMPLES, O_CMPLTU, O_CMPLEU,
   O_SELECT = 31, O_SEXT = 32, O_ZEXT = 33, O_TRUNC = 34,
-  O_ACCESS = 48, O_LOAD = 49,
-  O_IF = 56, O_ELSE = 57, O_ENDIF = 58, O_LOOP = 59, O_ENDLOOP = 60
+  O_FADD = 40, O_FSUB = 41, O_FMUL = 42, O_FEXP = 43, O_ITOF = 44, O_FTOI = 45,
+  O_ACCESS = 48, O_LOAD = 49, O_STORE = 50,
+  O_IF = 56, O_ELSE = 57, O_ENDIF = 58, O_LOOP = 59, O_ENDLOOP = 60, O_BARRIER = 61
 };
 #define NOSITE 0xFFFFu
 #define NOREG 0xFFFFu
@@ -108,6 +110,13 @@ typedef struct {
   int64_t* const_copy;
   uint8_t* in_slice;  /* [n_instr]: an index, IF predicate or loop bound depends on it */
   uint8_t space[16];  /* memory space of each slot */
+  int has_barrier;     /* some BARRIER */
+  int block_sync;      /* some LOAD reads shared memory: blocks run phase by phase */
+  uint32_t shared_idx; /* shared slots some LOAD of which feeds the slice (bit per slot):
+                          the index-related shared variables of the paper's Algorithm 2 */
+  uint32_t shared_live; /* shared slots read back into the pruned program (indices,
+                           control or divisions): BARRIERs are kept when nonzero */
+  uint8_t* kept;       /* [n_instr]: what the pruned program keeps (for counting) */
 } or_prog;
 
 static uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
@@ -115,11 +124,18 @@ static uint32_t rd32(const uint8_t* p) { return (uint32_t)rd16(p) | ((uint32_t)r
 static int64_t rd64(const uint8_t* p) { return (int64_t)((uint64_t)rd32(p) | ((uint64_t)rd32(p + 4) << 32)); }
 
 static void prog_free(or_prog* P) {
-  free(P->site_ids); free(P->ins); free(P->load_slot); free(P->const_copy); free(P->in_slice);
+  free(P->site_ids); free(P->ins); free(P->load_slot); free(P->const_copy); free(P->in_slice); free(P->kept);
   memset(P, 0, sizeof *P);
 }
 
 static int is_binary(int op) { return op >= O_ADD && op <= O_CMPLEU; }
+static int is_fbinary(int op) { return op == O_FADD || op == O_FSUB || op == O_FMUL; }
+static int is_funary(int op) { return op == O_FEXP || op == O_ITOF || op == O_FTOI; }
+/* ops that define no register */
+static int defines_nothing(int op) {
+  return op == O_ACCESS || op == O_STORE || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP ||
+         op == O_BARRIER;
+}
 
 /* The live-register rule of the IR description: a register lives from its
  * definition to its last use, a use inside a loop that does not contain the
@@ -136,7 +152,7 @@ static int pressure_ok(const or_prog* P) {
   for (int i = 0; i < n; i++) {
     const or_ins* I = &P->ins[i];
     int op = I->op;
-    if (!(op == O_ACCESS || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP)) def_at[I->dst] = i;
+    if (!defines_nothing(op)) def_at[I->dst] = i;
   }
   int loops[4], nl = 0; /* open LOOPs, outermost first */
   for (int u = 0; u < n; u++) {
@@ -144,8 +160,10 @@ static int pressure_ok(const or_prog* P) {
     int op = I->op, uses[3], nu = 0;
     if (op == O_ENDLOOP) { nl--; continue; }
     if (op == O_SELECT || op == O_LOOP) { uses[nu++] = I->a; uses[nu++] = I->b; uses[nu++] = I->c; }
-    else if (op == O_SEXT || op == O_ZEXT || op == O_TRUNC || op == O_ACCESS || op == O_LOAD || op == O_IF) uses[nu++] = I->a;
-    else if (is_binary(op)) { uses[nu++] = I->a; uses[nu++] = I->b; }
+    else if (op == O_SEXT || op == O_ZEXT || op == O_TRUNC || op == O_ACCESS || op == O_LOAD || op == O_IF ||
+             is_funary(op)) uses[nu++] = I->a;
+    else if (op == O_STORE) { uses[nu++] = I->a; uses[nu++] = I->dst; }
+    else if (is_binary(op) || is_fbinary(op)) { uses[nu++] = I->a; uses[nu++] = I->b; }
     for (int k = 0; k < nu; k++) {
       int r = uses[k], e = u;
       for (int q = 0; q < nl; q++)
@@ -163,8 +181,7 @@ static int pressure_ok(const or_prog* P) {
   for (int i = 0; i < n && ok; i++) {
     cur += diff[i];
     int op = P->ins[i].op;
-    int defines = !(op == O_ACCESS || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP);
-    if (defines && cur + 1 > 32) ok = 0;
+    if (!defines_nothing(op) && cur + 1 > 32) ok = 0;
   }
   free(def_at); free(endr); free(diff);
   return ok;
@@ -172,6 +189,51 @@ static int pressure_ok(const or_prog* P) {
 
 /* Decode and validate the byte format (include/ckc_ir.h describes it; this is
  * an independent reading of that description). */
+/* One backward pass (every definition precedes its uses) from the roots:
+ * the accesses (a STORE's value too when its slot is in xs), IF predicates
+ * and loop bounds and, with `divs`, the divisions and remainders (they count
+ * arithmetic faults, so their operands must be exact); every instruction whose
+ * result a marked instruction reads is marked.  Returns the shared slots some
+ * LOAD of which has its result needed. */
+static uint32_t slice_pass(const or_prog* P, uint32_t xs, int divs, uint8_t* need, uint8_t* mark) {
+  memset(need, 0, P->n_regs + 1);
+  memset(mark, 0, P->n_instr + 1);
+  for (int i = P->n_instr - 1; i >= 0; i--) {
+    const or_ins* I = &P->ins[i];
+    int op = I->op;
+    int div = op == O_DIVS || op == O_DIVU || op == O_REMS || op == O_REMU;
+    int root = op == O_ACCESS || op == O_LOAD || op == O_STORE || op == O_IF || op == O_LOOP || (divs && div);
+    int keep = root || (!defines_nothing(op) && op != O_LOOP && I->dst < P->n_regs && need[I->dst]);
+    if (!keep) continue;
+    mark[i] = 1;
+    if (op == O_CONST || op == O_SCALAR || op == O_SPECIAL) continue;
+    need[I->a] = 1;
+    if (op == O_LOOP || op == O_SELECT) { need[I->b] = 1; need[I->c] = 1; }
+    else if (is_binary(op) || is_fbinary(op)) need[I->b] = 1;
+    else if (op == O_STORE && ((xs >> I->c) & 1u)) need[I->dst] = 1;
+  }
+  uint32_t nxs = 0;
+  for (int i = 0; i < P->n_instr; i++) {
+    const or_ins* I = &P->ins[i];
+    if (I->op == O_LOAD && P->space[I->c] == SP_SHARED && need[I->dst]) nxs |= 1u << I->c;
+  }
+  return nxs;
+}
+
+/* Shared slots read back into the pass's result (the index-related shared
+ * variables of Algorithm 2 when `divs` is 0): a shared slot is one when some
+ * LOAD from it has its result needed; then the values STOREd to it are
+ * needed too, which may bring in more loads.  Repeated until nothing changes
+ * (the set only grows); mark[] holds the last pass. */
+static uint32_t slice_fixpoint(const or_prog* P, int divs, uint8_t* need, uint8_t* mark) {
+  uint32_t xs = 0;
+  for (;;) {
+    uint32_t nxs = slice_pass(P, xs, divs, need, mark);
+    if (nxs == xs) return xs;
+    xs = nxs;
+  }
+}
+
 static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
   memset(P, 0, sizeof *P);
   if (!ir || n < 32) return E_IR;
@@ -248,13 +310,42 @@ static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
         if (I->c >= P->n_slots) goto out;
         if (I->op == O_ACCESS) { if (I->d > 7) goto out; }
         else {
-          /* loads read global memory only: shared and local slots hold no
-           * data the host provides */
-          if ((I->d != 2 && I->d != 3) || P->space[I->c] != SP_GLOBAL) goto out;
-          P->load_slot[I->c] = 1;
+          /* loads read global memory (the host's data) or shared memory
+           * (4-byte elements written by the block's STOREs); local memory is
+           * not modelled */
+          if ((I->d != 2 && I->d != 3) || P->space[I->c] == SP_LOCAL) goto out;
+          if (P->space[I->c] == SP_SHARED && I->d != 2) goto out;
+          if (P->space[I->c] == SP_GLOBAL) P->load_slot[I->c] = 1;
+          else P->block_sync = 1;
           DEF(I->dst);
         }
         SITE(I->s0);
+        break;
+      case O_STORE:
+        WIDTH(I->w); USE(I->a); USE(I->dst);
+        if (I->b >= P->n_accesses || acc_used[I->b]) goto out;
+        acc_used[I->b] = 1;
+        if (I->c >= P->n_slots || I->d > 3) goto out;
+        SITE(I->s0);
+        break;
+      case O_FADD: case O_FSUB: case O_FMUL:
+        if (I->w != 64) goto out;
+        USE(I->a); USE(I->b); DEF(I->dst);
+        break;
+      case O_FEXP:
+        if (I->w != 64) goto out;
+        USE(I->a); DEF(I->dst);
+        break;
+      case O_ITOF:
+        if (I->w != 32) goto out;
+        USE(I->a); DEF(I->dst);
+        break;
+      case O_FTOI:
+        WIDTH(I->w); USE(I->a); DEF(I->dst);
+        break;
+      case O_BARRIER:
+        if (sp != 0) goto out; /* __syncthreads at the top level only */
+        P->has_barrier = 1;
         break;
       case O_IF:
         USE(I->a); SITE(I->s0); SITE(I->s1);
@@ -301,27 +392,24 @@ static int prog_decode(const uint8_t* ir, size_t n, or_prog* P) {
   if (sp != 0) goto out;
   for (int a = 0; a < P->n_accesses; a++) if (!acc_used[a]) goto out;
   if (!pressure_ok(P)) goto out;
-  /* The slice of the indices, IF predicates and loop bounds: the accesses
-   * and control instructions themselves and, walking backwards (every
-   * definition precedes its uses), every instruction whose result a slice
-   * instruction reads. */
+  /* The slice of the indices, IF predicates and loop bounds, and the live
+   * set of the pruned program (Algorithm 2); see slice_fixpoint. */
   {
     uint8_t* need = (uint8_t*)calloc(P->n_regs + 1, 1);
+    uint8_t* live = (uint8_t*)calloc(P->n_instr + 1, 1);
     P->in_slice = (uint8_t*)calloc(P->n_instr + 1, 1);
-    for (int i = P->n_instr - 1; i >= 0; i--) {
-      const or_ins* I = &P->ins[i];
-      int op = I->op;
-      int root = op == O_ACCESS || op == O_LOAD || op == O_IF || op == O_LOOP;
-      int defines = !(op == O_ACCESS || op == O_IF || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP);
-      int keep = root || (defines && op != O_LOOP && I->dst < P->n_regs && need[I->dst]);
-      if (!keep) continue;
-      P->in_slice[i] = 1;
-      if (op == O_CONST || op == O_SCALAR || op == O_SPECIAL) continue;
-      need[I->a] = 1;
-      if (op == O_LOOP || op == O_SELECT) { need[I->b] = 1; need[I->c] = 1; }
-      else if (is_binary(op)) need[I->b] = 1;
+    P->shared_idx = slice_fixpoint(P, 0, need, P->in_slice);
+    const uint32_t xl = slice_fixpoint(P, 1, need, live);
+    P->shared_live = xl;
+    /* what the pruned program keeps (MathElimination): the live set, the
+     * structure of IF and LOOP and, when some shared variable is read back
+     * into it, every BARRIER (BarrierElimination is all or none) */
+    P->kept = (uint8_t*)calloc(P->n_instr + 1, 1);
+    for (int i = 0; i < P->n_instr; i++) {
+      int op = P->ins[i].op;
+      P->kept[i] = live[i] || op == O_ELSE || op == O_ENDIF || op == O_ENDLOOP || (op == O_BARRIER && xl != 0);
     }
-    free(need);
+    free(need); free(live);
   }
   rc = E_OK;
 out:
@@ -397,6 +485,55 @@ static uint64_t trip_count(int64_t s, int64_t e, int64_t step) {
   }
 }
 
+/* e^x as the IR defines FEXP: k = floor(x / ln 2 + 1/2), r = (x - k ln2_hi)
+ * - k ln2_lo with ln 2 split into a part of 29 significant bits (k times it
+ * is exact) and the rest, the Taylor polynomial of e^r to degree 13 in Horner
+ * form, times 2^k (in two
+ * steps below 2^-1022); NaN stays NaN, x above 709.782712893384 gives +inf,
+ * below -745.1332191019412 gives 0.  Plain IEEE binary64 operations, each
+ * rounded on its own, so that any two implementations agree bit for bit. */
+static double ir_exp(double x) {
+  static const double C[14] = {
+      0x1.0000000000000p+0, 0x1.0000000000000p+0, 0x1.0000000000000p-1, 0x1.5555555555555p-3,
+      0x1.5555555555555p-5, 0x1.1111111111111p-7, 0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13,
+      0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26,
+      0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+  if (x != x) return x;
+  if (x > 709.782712893384) return INFINITY;
+  if (x < -745.1332191019412) return 0.0;
+  volatile double t = x * 0x1.71547652b82fep+0;
+  const double k = floor(t + 0.5);
+  volatile double kh = k * 0x1.62e42ff000000p-1;
+  volatile double r0 = x - kh;
+  volatile double kl = k * -0x1.718432a1b0e26p-35;
+  const double r = r0 - kl;
+  double p = C[13];
+  for (int i = 12; i >= 0; i--) {
+    volatile double pr = p * r;
+    p = pr + C[i];
+  }
+  const int ki = (int)k;
+  uint64_t b;
+  double s;
+  if (ki > 1023) {
+    b = (uint64_t)(1023 + 1023) << 52;
+    memcpy(&s, &b, 8);
+    volatile double q = p * s;
+    return q * 2.0;
+  }
+  if (ki >= -1022) {
+    b = (uint64_t)(ki + 1023) << 52;
+    memcpy(&s, &b, 8);
+    return p * s;
+  }
+  b = (uint64_t)(ki + 1000 + 1023) << 52;
+  memcpy(&s, &b, 8);
+  volatile double q = p * s;
+  b = (uint64_t)(-1000 + 1023) << 52;
+  memcpy(&s, &b, 8);
+  return q * s;
+}
+
 /* ---- one thread --------------------------------------------------------- */
 typedef struct {
   const or_prog* P;
@@ -405,6 +542,14 @@ typedef struct {
   const or_alloc* table;
   uint32_t table_n;   /* entries of this input's table */
   uint32_t detector;  /* DET_EXACT or DET_TRIPWIRE */
+  /* shared memory of the block being run: per slot its elements as at the
+   * start of the phase, and the phase's writes (0 = none, else 2^32 | the
+   * value's bits with the sign bit flipped, so that the maximum is the
+   * largest value) */
+  int32_t* sh_cur[16];
+  uint64_t* sh_next[16];
+  uint64_t sh_n[16];
+  uint64_t* executed;  /* this input's [all, kept] instruction executions, or NULL */
   uint32_t tid[3], bid[3];
   uint64_t gtid;
   unsigned L1, L2;
@@ -563,6 +708,10 @@ static void exec_range(thr* t, int pc, int end) {
   uint64_t* R = t->regs;
   while (pc < end && !t->stopped) {
     const or_ins* I = &P->ins[pc];
+    if (t->executed && !t->dry) {
+      t->executed[0]++;
+      if (P->kept[pc]) t->executed[1]++;
+    }
     switch (I->op) {
       case O_CONST: R[I->dst] = narrow((uint64_t)P->consts[I->a], I->w); break;
       case O_SCALAR: R[I->dst] = narrow((uint64_t)t->scalars[I->a], I->w); break;
@@ -590,11 +739,48 @@ static void exec_range(thr* t, int pc, int end) {
         if (t->dry && P->in_slice[pc] && !(read32_ok(R[I->a]) && (int64_t)R[I->a] >= 0)) t->wrapped = 1;
         R[I->dst] = R[I->a] & 0xFFFFFFFFull;
         break;
+      case O_FADD: case O_FSUB: case O_FMUL: {
+        double x, y, r;
+        memcpy(&x, &R[I->a], 8);
+        memcpy(&y, &R[I->b], 8);
+        r = I->op == O_FADD ? x + y : I->op == O_FSUB ? x - y : x * y;
+        memcpy(&R[I->dst], &r, 8);
+        break;
+      }
+      case O_FEXP: {
+        double x, r;
+        memcpy(&x, &R[I->a], 8);
+        r = ir_exp(x);
+        memcpy(&R[I->dst], &r, 8);
+        break;
+      }
+      case O_ITOF: {
+        double r = (double)(int32_t)(uint32_t)R[I->a];
+        memcpy(&R[I->dst], &r, 8);
+        break;
+      }
+      case O_FTOI: {
+        double x;
+        memcpy(&x, &R[I->a], 8);
+        const int w = I->w;
+        const double lo = w == 32 ? -2147483648.0 : -9223372036854775808.0;
+        const double hi = w == 32 ? 2147483648.0 : 9223372036854775808.0; /* first value above the range */
+        int64_t v;
+        if (x != x) v = 0;
+        else if (x <= lo) v = w == 32 ? (int64_t)INT32_MIN : INT64_MIN;
+        else if (x >= hi) v = w == 32 ? (int64_t)INT32_MAX : INT64_MAX;
+        else v = (int64_t)x; /* truncation toward zero */
+        R[I->dst] = narrow((uint64_t)v, w);
+        break;
+      }
+      case O_BARRIER:
+        break; /* phases are driven by run_block */
       case O_ACCESS:
+      case O_STORE:
       case O_LOAD: {
         if (t->dry && I->w == 32 && !read32_ok(R[I->a])) t->wrapped = 1;
         int64_t idx = (int64_t)narrow(R[I->a], I->w);
-        unsigned log2e = I->op == O_ACCESS ? (I->d & 3u) : I->d;
+        unsigned log2e = I->op == O_LOAD ? I->d : (I->d & 3u);
         const or_alloc* A = &t->table[I->c];
         uint32_t kind = check_kind(A, idx, log2e);
         /* the tripwire model reports a subset of the exact violations; a
@@ -607,13 +793,23 @@ static void exec_range(thr* t, int pc, int end) {
         }
         visit(t, I->s0);
         if (reported) record(t, I->b, kind, idx);
+        const int shared = P->space[I->c] == SP_SHARED;
         if (I->op == O_LOAD) {
           uint64_t v = 0;
-          if (!kind) {
+          if (!kind && shared) {
+            /* the block's instance as at the start of the phase (0 in a
+             * vertex run, which has no block) */
+            if (!t->dry && t->sh_cur[I->c] && (uint64_t)idx < t->sh_n[I->c])
+              v = (uint64_t)(int64_t)t->sh_cur[I->c][idx];
+          } else if (!kind) {
             if (log2e == 2) v = (uint64_t)(int64_t)((const int32_t*)A->data)[idx];
             else v = (uint64_t)((const int64_t*)A->data)[idx];
           }
           R[I->dst] = v;
+        } else if (I->op == O_STORE && !kind && shared && log2e == 2 && !t->dry && t->sh_next[I->c] &&
+                   (uint64_t)idx < t->sh_n[I->c]) {
+          const uint64_t packed = (1ull << 32) | (uint32_t)((uint32_t)R[I->dst] ^ 0x80000000u);
+          if (packed > t->sh_next[I->c][idx]) t->sh_next[I->c][idx] = packed;
         }
         break;
       }
@@ -648,7 +844,8 @@ static void exec_range(thr* t, int pc, int end) {
   }
 }
 
-static void run_thread(thr* t, uint64_t blin, uint32_t tlin) {
+/* Coordinates of thread (blin, tlin) of the launch. */
+static void thread_coords(thr* t, uint64_t blin, uint32_t tlin) {
   const uint32_t* L = t->launch;
   uint32_t gx = L[0], gy = L[1], bx = L[3], by = L[4];
   uint64_t bsize = (uint64_t)L[3] * L[4] * L[5];
@@ -659,11 +856,85 @@ static void run_thread(thr* t, uint64_t blin, uint32_t tlin) {
   t->tid[1] = (tlin / bx) % by;
   t->tid[2] = tlin / (bx * by);
   t->gtid = blin * bsize + tlin;
+}
+
+/* Sets up thread (blin, tlin): coordinates, zero registers, a new lane. */
+static void thread_begin(thr* t, uint64_t blin, uint32_t tlin) {
+  thread_coords(t, blin, tlin);
   memset(t->regs, 0, sizeof(uint64_t) * (t->P->n_regs + 1));
   t->iter[0] = t->iter[1] = 0;
   t->stopped = 0;
   if (!t->dry) t->st->lanes++;
+}
+
+static void run_thread(thr* t, uint64_t blin, uint32_t tlin) {
+  thread_begin(t, blin, tlin);
   exec_range(t, 0, t->P->n_instr);
+}
+
+/* The threads tl[0..n) of block blin run together, phase by phase: every
+ * thread runs the program up to the next BARRIER (or the end), in thread
+ * order, before any thread goes on; the block's shared memory starts at 0,
+ * loads see it as at the start of the phase, and at the end of the phase each
+ * element written takes the largest value stored to it (the IR's shared
+ * memory semantics). */
+static void run_block(thr* t, uint64_t blin, const uint32_t* tl, uint32_t n) {
+  const or_prog* P = t->P;
+  const size_t nr = (size_t)P->n_regs + 1;
+  uint64_t* saved = (uint64_t*)calloc((size_t)n * nr, 8);
+  uint8_t* stopped = (uint8_t*)calloc(n, 1);
+  for (int s = 0; s < 16; s++) {
+    t->sh_cur[s] = NULL; t->sh_next[s] = NULL; t->sh_n[s] = 0;
+    if (s < P->n_slots && P->space[s] == SP_SHARED && t->table[s].base != 0) {
+      t->sh_n[s] = t->table[s].size_bytes / 4;
+      t->sh_cur[s] = (int32_t*)calloc(t->sh_n[s] + 1, 4);
+      t->sh_next[s] = (uint64_t*)calloc(t->sh_n[s] + 1, 8);
+    }
+  }
+  for (uint32_t k = 0; k < n; k++) thread_begin(t, blin, tl[k]); /* lanes; registers start at 0 */
+  int pc = 0;
+  for (;;) {
+    int end = pc;
+    while (end < P->n_instr && P->ins[end].op != O_BARRIER) end++;
+    for (uint32_t k = 0; k < n; k++) {
+      thread_coords(t, blin, tl[k]);
+      memcpy(t->regs, saved + k * nr, nr * 8);
+      t->iter[0] = t->iter[1] = 0;
+      t->stopped = stopped[k];
+      exec_range(t, pc, end);
+      if (end < P->n_instr && !t->stopped && t->executed) { /* the BARRIER itself */
+        t->executed[0]++;
+        if (P->kept[end]) t->executed[1]++;
+      }
+      memcpy(saved + k * nr, t->regs, nr * 8);
+      stopped[k] = (uint8_t)t->stopped;
+    }
+    for (int s = 0; s < 16; s++)
+      for (uint64_t e = 0; e < t->sh_n[s]; e++)
+        if (t->sh_next[s][e]) {
+          t->sh_cur[s][e] = (int32_t)((uint32_t)t->sh_next[s][e] ^ 0x80000000u);
+          t->sh_next[s][e] = 0;
+        }
+    if (end >= P->n_instr) break;
+    pc = end + 1;
+  }
+  for (int s = 0; s < 16; s++) {
+    free(t->sh_cur[s]); free(t->sh_next[s]);
+    t->sh_cur[s] = NULL; t->sh_next[s] = NULL; t->sh_n[s] = 0;
+  }
+  free(saved); free(stopped);
+}
+
+/* All threads of block blin. */
+static void run_whole_block(thr* t, uint64_t blin, uint32_t bsize) {
+  if (!t->P->block_sync) {
+    for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, blin, tl);
+    return;
+  }
+  uint32_t* tl = (uint32_t*)malloc(sizeof(uint32_t) * bsize);
+  for (uint32_t k = 0; k < bsize; k++) tl[k] = k;
+  run_block(t, blin, tl, bsize);
+  free(tl);
 }
 
 /* A block is a boundary block when, along some grid dimension of extent at
@@ -713,6 +984,9 @@ static void vertex(const uint32_t* L, int tot, int v, uint64_t* blin, uint32_t* 
 static uint32_t vertex_exact(thr* t) {
   const uint32_t* L = t->launch;
   if ((uint64_t)L[0] * L[1] * L[2] == 0 || (uint64_t)L[3] * L[4] * L[5] == 0) return 0;
+  /* indices that depend on other threads' shared-memory writes: no vertex
+   * argument applies */
+  if (t->P->shared_idx) return 0;
   int tot = n_vertices(L);
   t->dry = 1; t->wrapped = 0; t->abort_run = 0;
   t->dec = (uint64_t*)malloc(sizeof(uint64_t) * (VERTEX_BUDGET + 1));
@@ -741,17 +1015,31 @@ static void run_input(thr* t, uint32_t mode) {
   if (mode == M_FULL) {
     /* The whole grid: what the paper executes for kernels that are not
      * affine-access (Section 5.1, fall-back to all blocks and threads). */
-    for (uint64_t b = 0; b < nblocks; b++)
-      for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, b, tl);
+    for (uint64_t b = 0; b < nblocks; b++) run_whole_block(t, b, bsize);
   } else if (mode == M_CORNERS) {
     /* The PREX Theorem's representative threads {first, last thread} x
      * {first, last block} (Section 5.1.1), taken per dimension: every vertex
      * of the box of block and thread coordinates. */
     int tot = n_vertices(L);
-    for (int v = 0; v < tot; v++) {
-      uint64_t blin; uint32_t tlin;
-      vertex(L, tot, v, &blin, &tlin);
-      run_thread(t, blin, tlin);
+    if (!t->P->block_sync) {
+      for (int v = 0; v < tot; v++) {
+        uint64_t blin; uint32_t tlin;
+        vertex(L, tot, v, &blin, &tlin);
+        run_thread(t, blin, tlin);
+      }
+    } else {
+      /* vertices of one block are consecutive: they run together */
+      uint32_t tl[64];
+      uint64_t cur = 0;
+      uint32_t n = 0;
+      for (int v = 0; v < tot; v++) {
+        uint64_t blin; uint32_t tlin;
+        vertex(L, tot, v, &blin, &tlin);
+        if (n && blin != cur) { run_block(t, cur, tl, n); n = 0; }
+        cur = blin;
+        tl[n++] = tlin;
+      }
+      if (n) run_block(t, cur, tl, n);
     }
   } else if (mode == M_BOUNDARY) {
     /* Every block on the faces of the grid plus the middle block, all of
@@ -759,8 +1047,7 @@ static void run_input(thr* t, uint32_t mode) {
      * plus one interior representative). */
     uint64_t centre = (uint64_t)(L[0] / 2) + (uint64_t)L[0] * ((L[1] / 2) + (uint64_t)L[1] * (L[2] / 2));
     for (uint64_t b = 0; b < nblocks; b++)
-      if (is_boundary_block(L, b) || b == centre)
-        for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, b, tl);
+      if (is_boundary_block(L, b) || b == centre) run_whole_block(t, b, bsize);
   } else if (mode == M_PREX) {
     /* Algorithm 1 (PREX runtime): blocks are taken from both ends of the
      * block order inward, head then tail, and the sweep stops before a new
@@ -774,9 +1061,8 @@ static void run_input(thr* t, uint32_t mode) {
       for (int a = 0; a < t->P->n_accesses; a++) if (!t->acc_seen[a]) { covered = 0; break; }
       for (int a = 0; a < t->P->n_accesses; a++) if (t->rec[a].count) { bug = 1; break; }
       if (covered || bug) break;
-      for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, head, tl);
-      if (tail != head)
-        for (uint32_t tl = 0; tl < bsize; tl++) run_thread(t, tail, tl);
+      run_whole_block(t, head, bsize);
+      if (tail != head) run_whole_block(t, tail, bsize);
       head++;
       if (tail == 0) break;
       tail--;
@@ -799,6 +1085,7 @@ typedef struct {
   or_record* recs;
   uint64_t* counts;
   or_status* st;
+  uint64_t* executed; /* [n_inputs][2] or NULL */
   int nthreads, me;
 } job_t;
 
@@ -817,6 +1104,7 @@ static void* worker(void* arg) {
     t.scalars = P->n_scalars ? J->scalars + (size_t)P->n_scalars * i : zero_scalars;
     t.table = J->tables + J->table_off[i];
     t.table_n = J->table_len[i];
+    t.executed = J->executed ? J->executed + 2 * (size_t)i : NULL;
     t.detector = J->detector;
     t.rec = J->recs + (size_t)P->n_accesses * i;
     t.cnt = J->counts + (size_t)P->n_sites * i;
@@ -844,7 +1132,8 @@ static void* worker(void* arg) {
 int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint32_t* launch,
                const int64_t* scalars, const or_alloc* tables, const uint64_t* table_off,
                const uint32_t* table_len, uint32_t mode, uint32_t detector, const uint32_t* cap_log2,
-               or_record* recs, uint64_t* counts, uint8_t* maps, or_status* st, int nthreads) {
+               or_record* recs, uint64_t* counts, uint8_t* maps, or_status* st, int nthreads,
+               uint64_t* executed) {
   or_prog P;
   int rc = prog_decode(ir, ir_bytes, &P);
   if (rc) return rc;
@@ -887,6 +1176,7 @@ int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint
   }
   memset(counts, 0, sizeof(uint64_t) * (size_t)n_inputs * P.n_sites);
   memset(st, 0, sizeof(or_status) * n_inputs);
+  if (executed) memset(executed, 0, sizeof(uint64_t) * 2 * n_inputs);
   if (nthreads < 1) nthreads = 1;
   if ((uint32_t)nthreads > n_inputs && n_inputs > 0) nthreads = (int)n_inputs;
   job_t* jobs = (job_t*)calloc(nthreads, sizeof(job_t));
@@ -895,7 +1185,7 @@ int ckco_check(const uint8_t* ir, size_t ir_bytes, uint32_t n_inputs, const uint
     job_t* J = &jobs[k];
     J->P = &P; J->n_inputs = n_inputs; J->launch = launch; J->scalars = scalars;
     J->tables = tables; J->table_off = table_off; J->table_len = table_len; J->mode = mode;
-    J->detector = detector; J->L1 = L1; J->L2 = L2;
+    J->detector = detector; J->L1 = L1; J->L2 = L2; J->executed = executed;
     J->cap[0] = 1ull << cap_log2[0]; J->cap[1] = 1ull << cap_log2[1];
     J->recs = recs; J->counts = counts; J->st = st; J->nthreads = nthreads; J->me = k;
   }
@@ -1115,7 +1405,7 @@ int ckco_fuzz(const uint8_t* ir, size_t ir_bytes, const uint32_t* seed_launch, c
       tlen[c] = table_len;
     }
     rc = ckco_check(ir, ir_bytes, B, launch, scal, tabs, toff, tlen, mode, detector, cap_log2, recs, counts, maps,
-                    st, nthreads);
+                    st, nthreads, NULL);
     if (rc) break;
     /* novelty against the virgin map as at the generation's start */
     memset(seen, 0, 65536);
@@ -1166,3 +1456,6 @@ uint64_t ckco_fuzz_rand(uint64_t seed, uint64_t k) { return fz_rand(seed, k); }
 
 /* The hit-count class of a map byte (for tests). */
 uint32_t ckco_fuzz_class(uint32_t v) { return fz_class((uint8_t)v); }
+
+/* FEXP as the IR defines it (for tests). */
+double ckco_ir_exp(double x) { return ir_exp(x); }

@@ -32,7 +32,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC", "-pthread",
-                               SRC, "-o", tmp])
+                               SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -45,7 +45,7 @@ def _load():
             lib = ctypes.CDLL(LIB)
             p = ctypes.c_void_p
             lib.ckco_check.argtypes = [p, ctypes.c_size_t, ctypes.c_uint32, p, p, p, p, p,
-                                       ctypes.c_uint32, ctypes.c_uint32, p, p, p, p, p, ctypes.c_int]
+                                       ctypes.c_uint32, ctypes.c_uint32, p, p, p, p, p, ctypes.c_int, p]
             lib.ckco_check.restype = ctypes.c_int
             lib.ckco_validate.argtypes = [p, ctypes.c_size_t, p]
             lib.ckco_validate.restype = ctypes.c_int
@@ -54,6 +54,8 @@ def _load():
             lib.ckco_fuzz.restype = ctypes.c_int
             lib.ckco_fuzz_rand.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
             lib.ckco_fuzz_rand.restype = ctypes.c_uint64
+            lib.ckco_ir_exp.argtypes = [ctypes.c_double]
+            lib.ckco_ir_exp.restype = ctypes.c_double
             lib.ckco_fuzz_class.argtypes = [ctypes.c_uint32]
             lib.ckco_fuzz_class.restype = ctypes.c_uint32
             _lib = lib
@@ -82,7 +84,7 @@ def validate(ir: bytes):
 
 
 def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: bool = True,
-          detector: int | None = None):
+          detector: int | None = None, executed: bool = False):
     """Run the oracle over every input of workload ``wl`` (``detector``: 0
     exact bounds, 1 the tripwire model; default the workload's).
 
@@ -112,15 +114,19 @@ def check(wl, mode: int | None = None, cap_log2=None, nthreads: int = 1, maps: b
     counts = np.zeros((n, n_sites), np.uint64)
     mp = np.zeros((n, 65536), np.uint8) if maps else None
     st = np.zeros(n, STATUS_DTYPE)
+    ex = np.zeros((n, 2), np.uint64) if executed else None
     buf = ctypes.create_string_buffer(wl.ir, len(wl.ir))
     rc = lib.ckco_check(buf, len(wl.ir), n, _ptr(launch), _ptr(scalars), _ptr(flat),
                         _ptr(table_off), _ptr(table_len), int(mode), int(detector), _ptr(cap),
                         _ptr(recs), _ptr(counts), _ptr(mp) if maps else None, _ptr(st),
-                        int(nthreads))
+                        int(nthreads), _ptr(ex) if executed else None)
     if rc:
         raise OracleError(rc)
     del data
-    return dict(records=recs, counts=counts, maps=mp, status=st)
+    out = dict(records=recs, counts=counts, maps=mp, status=st)
+    if executed:
+        out["executed"] = ex  # [n, 2]: instruction executions of the program as written / as pruned
+    return out
 
 
 MUT_LAUNCH, MUT_SCALAR, MUT_DATA = 1, 2, 4
@@ -130,6 +136,11 @@ NO_SLOT = 0xFFFFFFFF
 def fuzz_rand(seed: int, k: int) -> int:
     """Output k of the campaign's SplitMix64 generator started at ``seed``."""
     return int(_load().ckco_fuzz_rand(seed, k))
+
+
+def ir_exp(x: float) -> float:
+    """e^x by the IR's fixed method (the FEXP operation)."""
+    return float(_load().ckco_ir_exp(x))
 
 
 def fuzz_class(v: int) -> int:

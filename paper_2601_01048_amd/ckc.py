@@ -21,10 +21,11 @@ ST_VERTEX_EXACT = 1
 SCHED_DEFAULT, SCHED_BLOCKED, SCHED_CYCLIC, SCHED_DYNAMIC, SCHED_LPT = 0, 1, 2, 3, 4
 SCHED_NAMES = {0: "default", 1: "blocked", 2: "cyclic", 3: "dynamic", 4: "lpt"}
 DENSE_MAP = 2
+LOAD_NO_PRUNE = 1
 TRIPWIRE = 4
 SPACE_GLOBAL, SPACE_SHARED, SPACE_LOCAL = 0, 1, 2
 WAIT, DST_DEVICE, ENQUEUE = 1, 2, 4
-CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32, GATHER=64)
+CLS = dict(AFFINE=1, GUARDED=2, INDIRECT=4, I64=8, UNIFORM=16, EXPANDED=32, GATHER=64, BARRIER=128)
 
 RECORD_DTYPE = np.dtype([("first_key", "<u8"), ("index", "<i8"), ("count", "<u8"),
                          ("kinds", "<u4"), ("first_kind", "<u4")])
@@ -125,6 +126,7 @@ def lib():
         L.ckc_shutdown.restype = None
         L.ckc_analyze_ir.argtypes = [vp, sz, vp, vp, u32]
         L.ckc_load_program.argtypes = [vp, vp, sz, ctypes.POINTER(u32), vp]
+        L.ckc_load_program_ex.argtypes = [vp, vp, sz, u32, ctypes.POINTER(u32), vp]
         L.ckc_unload_program.argtypes = [vp, u32]
         L.ckc_put_alloc_table.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         L.ckc_free_alloc_table.argtypes = [vp, u32]
@@ -147,7 +149,7 @@ def lib():
         L.ckc_fuzz_read.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.ckc_fuzz_destroy.argtypes = [vp]
         L.ckc_fuzz_destroy.restype = None
-        for f in ("ckc_init", "ckc_analyze_ir", "ckc_load_program", "ckc_unload_program",
+        for f in ("ckc_init", "ckc_analyze_ir", "ckc_load_program", "ckc_load_program_ex", "ckc_unload_program",
                   "ckc_put_alloc_table", "ckc_free_alloc_table", "ckc_check_batch", "ckc_check_batch_noalloc",
                   "ckc_read_results", "ckc_job_sizes", "ckc_job_timing", "ckc_job_elapsed",
                   "ckc_autotune", "ckc_server_create", "ckc_server_submit", "ckc_server_result",
@@ -202,11 +204,14 @@ class Context:
     def __exit__(self, *a):
         self.close()
 
-    def load_program(self, ir: bytes):
+    def load_program(self, ir: bytes, no_prune: bool = False):
+        """(program id, info dict); ``no_prune`` keeps every instruction (the
+        unpruned baseline of the pruning measurement)."""
         pid = ctypes.c_uint32()
         info = ProgInfo()
         buf = ctypes.create_string_buffer(ir, len(ir))
-        _check(lib().ckc_load_program(self.h, buf, len(ir), ctypes.byref(pid), ctypes.byref(info)))
+        _check(lib().ckc_load_program_ex(self.h, buf, len(ir), LOAD_NO_PRUNE if no_prune else 0,
+                                         ctypes.byref(pid), ctypes.byref(info)))
         return pid.value, {f: getattr(info, f) for f, _ in ProgInfo._fields_}
 
     def unload_program(self, pid: int):
@@ -318,11 +323,11 @@ class DeviceWorkload:
     """A workload's data arrays, allocation tables and program placed on the
     device once (kept resident across checks)."""
 
-    def __init__(self, ctx: Context, wl, device: str = "cuda"):
+    def __init__(self, ctx: Context, wl, device: str = "cuda", no_prune: bool = False):
         import torch
         self.ctx, self.wl = ctx, wl
         self.tensors = [torch.from_numpy(np.ascontiguousarray(d)).to(device) for d in wl.data]
-        self.prog, self.info = ctx.load_program(wl.ir)
+        self.prog, self.info = ctx.load_program(wl.ir, no_prune=no_prune)
         self.table_ids = []
         for t in wl.tables:
             e = np.array(t, ALLOC_DTYPE)
@@ -352,11 +357,11 @@ class DeviceWorkload:
 
 
 def run_workload(ctx: Context, wl, mode=None, force_generic=False, maps=True, cap_log2=None,
-                 opts: LaunchOpts | None = None):
+                 opts: LaunchOpts | None = None, no_prune: bool = False):
     """Check every input of a workload; returns the oracle-shaped result dict
     (records [n, n_acc], maps [n, 65536] or None, status [n]).  ``opts``
     (launch_opts) overrides force_generic."""
-    dw = DeviceWorkload(ctx, wl)
+    dw = DeviceWorkload(ctx, wl, no_prune=no_prune)
     try:
         job = ctx.check([dw.desc(mode, maps, cap_log2)], force_generic=force_generic, opts=opts)
         recs, mp, st = ctx.read(job, maps=maps)

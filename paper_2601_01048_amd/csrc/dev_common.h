@@ -126,6 +126,57 @@ __device__ __forceinline__ uint32_t kind_of(uint64_t base, uint64_t size, uint32
   return (uint64_t)idx >= (size >> lg) ? CKC_KIND_OVER : 0u;
 }
 
+// e^x by the IR's definition of FEXP: reduction by ln 2 split into a part
+// of 29 significant bits (k times it is exact) and the rest (k = floor(x /
+// ln 2 + 1/2)), the degree-13 Taylor polynomial of e^r in Horner form,
+// scaling by 2^k (two steps below 2^-1022); each operation rounded on its own (no fused multiply-add), so
+// the result is the same bit pattern on any IEEE binary64 machine.
+__device__ __noinline__ double ir_exp(double x) {
+#pragma clang fp contract(off)
+  const double C[14] = {
+      0x1.0000000000000p+0, 0x1.0000000000000p+0, 0x1.0000000000000p-1, 0x1.5555555555555p-3,
+      0x1.5555555555555p-5, 0x1.1111111111111p-7, 0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13,
+      0x1.a01a01a01a01ap-16, 0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26,
+      0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+  if (x != x) return x;
+  if (x > 709.782712893384) return __longlong_as_double(0x7FF0000000000000ll);
+  if (x < -745.1332191019412) return 0.0;
+  const double k = floor(x * 0x1.71547652b82fep+0 + 0.5);
+  const double r = (x - k * 0x1.62e42ff000000p-1) - k * -0x1.718432a1b0e26p-35;
+  double p = C[13];
+  for (int i = 12; i >= 0; i--) p = p * r + C[i];
+  const int ki = (int)k;
+  if (ki > 1023) return (p * __longlong_as_double((long long)(1023 + 1023) << 52)) * 2.0;
+  if (ki >= -1022) return p * __longlong_as_double((long long)(ki + 1023) << 52);
+  return (p * __longlong_as_double((long long)(ki + 1000 + 1023) << 52)) *
+         __longlong_as_double((long long)(-1000 + 1023) << 52);
+}
+
+// Non-index arithmetic: FADD FSUB FMUL FEXP on IEEE binary64 bit patterns
+// (round to nearest even; FEXP as ir_exp), ITOF of
+// a width-32 value (exact), FTOI truncating toward zero to width w (NaN 0,
+// out-of-range values saturated).
+__device__ __forceinline__ uint64_t float_op(uint32_t op, uint32_t w, uint64_t x, uint64_t y) {
+  const double a = __longlong_as_double((long long)x), b = __longlong_as_double((long long)y);
+  switch (op) {
+    case CKC_OP_FADD: return (uint64_t)__double_as_longlong(a + b);
+    case CKC_OP_FSUB: return (uint64_t)__double_as_longlong(a - b);
+    case CKC_OP_FMUL: return (uint64_t)__double_as_longlong(a * b);
+    case CKC_OP_FEXP: return (uint64_t)__double_as_longlong(ir_exp(a));
+    case CKC_OP_ITOF: return (uint64_t)__double_as_longlong((double)(int32_t)(uint32_t)x);
+    default: {  // FTOI
+      const double lo = w == 32 ? -2147483648.0 : -9223372036854775808.0;
+      const double hi = w == 32 ? 2147483648.0 : 9223372036854775808.0;
+      int64_t v;
+      if (a != a) v = 0;
+      else if (a <= lo) v = w == 32 ? (int64_t)INT32_MIN : INT64_MIN;
+      else if (a >= hi) v = w == 32 ? (int64_t)INT32_MAX : INT64_MAX;
+      else v = (int64_t)a;
+      return w == 32 ? (uint64_t)(int64_t)(int32_t)(uint32_t)v : (uint64_t)v;
+    }
+  }
+}
+
 // The tripwire (redzone) detector model (CKC_TRIPWIRE), for an access out of
 // its slot's exact bounds on a non-NULL slot: caught when one of its bytes
 // falls in a redzone of a live allocation or in a freed allocation (with its

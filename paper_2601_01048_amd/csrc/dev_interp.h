@@ -84,6 +84,9 @@ struct GenLds {
   unsigned long long rstart[RUN_TILES + 1];
   unsigned long long rend, rpend;
   uint32_t rn;
+  // shared memory of the tile's blocks: words per block instance, blocks per
+  // tile, offset of each shared slot within an instance
+  uint32_t sh_w, sh_nbt, sh_off[MAX_SLOTS];
 };
 
 // Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
@@ -125,6 +128,13 @@ struct Ctx {
   uint32_t input;
   uint32_t tw;              // the input runs under the tripwire detector model
   uint32_t spaces;          // memory space of each slot (2 bits per slot)
+  uint32_t capture;         // capture pass: only the first violation's index and kind
+  // shared memory of the tile's blocks (blockwise programs in the whole-thread
+  // pass; null elsewhere): the instances as at the phase start and the
+  // phase's writes, the lane's instance offset and each slot's offset in it
+  int32_t* shcur;
+  unsigned long long* shnext;
+  uint32_t sh_q;
   // fix-up target
   uint32_t tacc;
   uint64_t tk0, tk1;
@@ -136,7 +146,7 @@ struct Ctx {
 // (wavefront-uniform) marks sites below 64 whose workgroup count has reached
 // the saturation value 255, after which counting them changes nothing.
 __device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint64_t& sat, uint32_t s, uint64_t mask) {
-  if (s == NOSITE || mask == 0) return;
+  if (s == NOSITE || mask == 0 || C.capture) return;
   if (s < 64 && ((sat >> s) & 1u)) return;
   const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
   const uint32_t c = (uint32_t)__popcll(mask);
@@ -184,7 +194,8 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
     // operands: a for every op that reads registers, b for binary ops, SELECT
     // and LOOP, c for SELECT and LOOP (uniform tests, no lane reads otherwise)
     const bool rd_a = op >= CKC_OP_ADD && op != CKC_OP_ELSE && op != CKC_OP_ENDIF && op != CKC_OP_ENDLOOP;
-    const bool rd_b = (op >= CKC_OP_ADD && op <= CKC_OP_SELECT) || op == CKC_OP_LOOP;
+    const bool rd_b = (op >= CKC_OP_ADD && op <= CKC_OP_SELECT) || op == CKC_OP_LOOP || op == CKC_OP_FADD ||
+                      op == CKC_OP_FSUB || op == CKC_OP_FMUL || op == CKC_OP_STORE;
     const bool rd_c = op == CKC_OP_SELECT || op == CKC_OP_LOOP;
     const uint64_t va = rd_a ? RGET(da) : 0, vb = rd_b ? RGET(db) : 0, vc = rd_c ? RGET(dc) : 0;
     const bool act = ln.dis == 0;
@@ -213,22 +224,51 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
       case CKC_OP_SELECT: r = narrow(va != 0 ? vb : vc, w); wreg = dd; break;
       case CKC_OP_SEXT: case CKC_OP_TRUNC: r = narrow(va, 32); wreg = dd; break;
       case CKC_OP_ZEXT: r = va & 0xFFFFFFFFull; wreg = dd; break;
+      case CKC_OP_FADD: case CKC_OP_FSUB: case CKC_OP_FMUL: case CKC_OP_FEXP: case CKC_OP_ITOF:
+      case CKC_OP_FTOI:
+        r = float_op(op, w, va, vb);
+        wreg = dd;
+        break;
+      case CKC_OP_BARRIER:
+        // end of a phase: every wavefront of the workgroup is here (top
+        // level); the phase's writes become the blocks' shared memory
+        if (MODE == M_MAIN && C.shcur) {
+          __syncthreads();
+          const uint32_t tot = S.sh_nbt * S.sh_w;
+          for (uint32_t e = threadIdx.x; e < tot; e += TILE) {
+            const unsigned long long nx = C.shnext[e];
+            if (nx) {
+              C.shcur[e] = (int32_t)((uint32_t)nx ^ 0x80000000u);
+              C.shnext[e] = 0;
+            }
+          }
+          __syncthreads();
+        }
+        break;
       case CKC_OP_ACCESS:
+      case CKC_OP_STORE:
       case CKC_OP_LOAD: {
         const uint32_t slot = D.slot, lg = D.fl & 3u, acc = D.x;
         const int64_t idx = (int64_t)narrow(va, w);
         c_alloc& A = C.tab[slot];
-        // kx: exact kind (decides what a LOAD reads); kd: the kind reported
-        // under the input's detector model
+        // kx: exact kind (decides what a LOAD reads and a STORE writes); kd:
+        // the kind reported under the input's detector model
         const uint32_t kx = act ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
         uint32_t kd = kx;
         if (C.tw && kx != 0 && kx != CKC_KIND_NULL && !tripwire_catches(C.tab, C.spaces, slot, idx, lg)) kd = 0;
+        const bool shared = ((C.spaces >> (2 * slot)) & 3u) == CKC_SPACE_SHARED;
         if (MODE != M_FIX) {
-          ln.acc += act ? 1u : 0u;
-          count_site(S, C, sat, D.s0, __ballot(act));
-          if (__ballot(kd != 0)) {
-            const uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2) | ln.k1;
-            merge_violation(C.rec + acc, kd, key);
+          const uint64_t key = (ln.gtid << C.Lsum) | (ln.k0 << C.L2) | ln.k1;
+          if (C.capture) {
+            // keys are unique per access: one lane writes
+            if (kd != 0 && key == C.rec[acc].first_key) {
+              C.rec[acc].index = idx;
+              C.rec[acc].first_kind = kd;
+            }
+          } else {
+            ln.acc += act ? 1u : 0u;
+            count_site(S, C, sat, D.s0, __ballot(act));
+            if (__ballot(kd != 0)) merge_violation(C.rec + acc, kd, key);
           }
         } else if (acc == C.tacc) {
           if (lane_id() == 0) { C.trec->index = idx; C.trec->first_kind = kd; }
@@ -236,10 +276,19 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
         }
         if (op == CKC_OP_LOAD) {
           uint64_t v = 0;
-          if (act && kx == 0)
-            v = lg == 2 ? (uint64_t)(int64_t)((g_i32*)A.data)[idx] : (uint64_t)((g_i64*)A.data)[idx];
+          if (act && kx == 0) {
+            if (shared)  // the block's instance as at the phase start (0 outside the whole-thread pass)
+              v = C.shcur ? (uint64_t)(int64_t)C.shcur[C.sh_q + S.sh_off[slot] + (uint64_t)idx] : 0ull;
+            else
+              v = lg == 2 ? (uint64_t)(int64_t)((g_i32*)A.data)[idx] : (uint64_t)((g_i64*)A.data)[idx];
+          }
           r = v;
           wreg = dd;
+        } else if (op == CKC_OP_STORE && act && kx == 0 && shared && lg == 2 && C.shnext) {
+          // racing writes of a phase keep the largest value: compare as
+          // unsigned with the sign bit flipped, bit 32 marks "written"
+          const unsigned long long packed = (1ull << 32) | (uint32_t)((uint32_t)vb ^ 0x80000000u);
+          atomicMax(&C.shnext[C.sh_q + S.sh_off[slot] + (uint64_t)idx], packed);
         }
         break;
       }
@@ -445,6 +494,10 @@ __device__ __forceinline__ void ctx_init(Ctx& C, const KArgs& a, c_input& in, ui
   C.xt = 0;
   C.tw = in.detector;
   C.spaces = C.P->slot_spaces;
+  C.capture = a.capture;
+  C.shcur = nullptr;
+  C.shnext = nullptr;
+  C.sh_q = 0;
 }
 
 // Per-thread state of a lane (its totals are kept).
@@ -500,7 +553,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
     if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
       pos = pos_of_tile(ins, order, a.n_inputs, PATH_GENERIC, pos, cur_end, t);
       const uint32_t i = order[pos];
-      if (cur != 0xFFFFFFFFu) {
+      if (cur != 0xFFFFFFFFu && !a.capture) {  // the capture pass counts nothing
         add_lane_totals(S, ln);
         flush_input(S, a, cur, cur_sites);
       }
@@ -519,6 +572,9 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
     c_input& in = ins[i];
     const uint64_t l = (t - tb) * TILE + tid;
     const bool act = l < cur_lanes;
+    c_dprog* Pi = (c_dprog*)in.prog;
+    const uint32_t pfl = Pi->pflags;
+    if (a.capture && !(pfl & PF_CAPTURE)) continue;  // the capture pass runs only these inputs
     Thr T;
     if (cur_mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
     else decode_lane(cur_mode, cur_L, cur_L[6], act ? l : 0, T);
@@ -526,10 +582,39 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
     C.xt = in.xt_begin + (t - tb);
+    if (pfl & PF_BLOCKWISE) {
+      // the tile holds whole blocks (block size divides TILE, checked at
+      // submission): block tid / bs of the tile gets its own shared instance,
+      // all zero at the start
+      const uint32_t bs = cur_L[3] * cur_L[4] * cur_L[5];
+      if (tid == 0) {
+        uint32_t wsum = 0;
+        c_alloc* tab = (c_alloc*)in.table;
+        for (uint32_t s = 0; s < (uint32_t)MAX_SLOTS; s++) {
+          S.sh_off[s] = wsum;
+          if (s < Pi->n_slots && ((Pi->slot_spaces >> (2 * s)) & 3u) == CKC_SPACE_SHARED && tab[s].base != 0)
+            wsum += (uint32_t)(tab[s].size_bytes / 4);
+        }
+        S.sh_w = wsum;
+        S.sh_nbt = TILE / bs;
+      }
+      __syncthreads();
+      const uint32_t rows = a.max_regs > 8u ? a.max_regs : 8u;
+      unsigned long long* nx = (unsigned long long*)(R + (size_t)rows * TILE);
+      int32_t* cu = (int32_t*)(nx + (size_t)S.sh_nbt * S.sh_w);
+      for (uint32_t e = tid; e < S.sh_nbt * S.sh_w; e += TILE) {
+        nx[e] = 0;
+        cu[e] = 0;
+      }
+      __syncthreads();
+      C.shcur = cu;
+      C.shnext = nx;
+      C.sh_q = (tid / bs) * S.sh_w;
+    }
     lane_init(ln, act, T.gtid);
     run_program<M_MAIN>(S, R, C, ln, sat, 0, C.P->n_instr);
   }
-  if (cur != 0xFFFFFFFFu) {
+  if (cur != 0xFFFFFFFFu && !a.capture) {
     add_lane_totals(S, ln);
     flush_input(S, a, cur, cur_sites);
   }
@@ -1595,6 +1680,7 @@ __global__ void __launch_bounds__(64) fixup_kernel(KArgs a, uint64_t n_records) 
   }
   c_input& in = ((c_input*)a.inputs)[lo_i];
   const dprog* P = (const dprog*)in.prog;
+  if (P->pflags & PF_CAPTURE) return;  // filled by the capture pass
   const uint32_t acc = (uint32_t)(r - in.rec_base);
   const uint64_t key = rec->first_key;
   const uint32_t Lsum = in.L1 + in.L2;

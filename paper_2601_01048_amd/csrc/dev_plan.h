@@ -289,6 +289,9 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
   uint32_t nv = 1;
   for (int d = 0; d < 6; d++) nv *= L[d] >= 2 ? 2u : 1u;
   if ((uint64_t)L[0] * L[1] * L[2] == 0 || (uint64_t)L[3] * L[4] * L[5] == 0) return 0;
+  // indices that depend on other threads' shared-memory writes: no vertex
+  // argument applies
+  if (P->pflags & PF_CAPTURE) return 0;
   // lanes past the vertex count run vertex 0 again (a duplicate changes
   // nothing and keeps every lane's control decisions equal)
   // coordinates of vertex j: tid.xyz then bid.xyz, each first or last
@@ -349,10 +352,18 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
         RSET(D.dst, narrow(v, w));
         break;
       }
-      case CKC_OP_ACCESS: case CKC_OP_LOAD: {
+      case CKC_OP_FADD: case CKC_OP_FSUB: case CKC_OP_FMUL: case CKC_OP_FEXP: case CKC_OP_ITOF:
+      case CKC_OP_FTOI:
+        RSET(D.dst, float_op(op, w, RGET64(D.a), RGET64(D.b)));
+        break;
+      case CKC_OP_BARRIER: break;
+      case CKC_OP_ACCESS: case CKC_OP_LOAD: case CKC_OP_STORE: {
         const uint64_t x = RGET64(D.a);
         if (w == 32 && !fits32(x)) wrapped = true;
-        if (op == CKC_OP_LOAD) {
+        // shared memory holds nothing in a vertex run (no block runs)
+        if (op == CKC_OP_LOAD && ((P->slot_spaces >> (2 * D.slot)) & 3u) == CKC_SPACE_SHARED) {
+          RSET(D.dst, 0ull);
+        } else if (op == CKC_OP_LOAD) {
           const ckc_alloc A = tab[D.slot];
           const uint32_t lg = D.fl & 3u;
           const int64_t idx = (int64_t)narrow(x, w);

@@ -29,6 +29,13 @@ struct dins {
 };
 static_assert(sizeof(dins) == 16, "dins layout");
 
+// Program flags (dprog.pflags).
+enum : uint8_t {
+  PF_BLOCKWISE = 1,  // blocks run together: BARRIERs executed, shared memory read back
+  PF_CAPTURE = 2     // indices depend on shared memory: the first-violation index and
+                     // kind come from a second evaluation pass (no one-thread replay)
+};
+
 enum : uint8_t {
   DI_NOSKIP = 1,    // IF/LOOP: never skip the region (holds the expanded loop)
   DI_EXPAND = 2,    // LOOP: evaluated one lane per iteration
@@ -53,7 +60,7 @@ struct dprog {
   uint32_t n_livein;
   uint32_t trace_cap;         // entries reserved per input for the trace path (0 = none)
   uint8_t livein[MAX_LIVEIN]; // physical registers read by the expanded body
-  uint8_t load_slots;         // unused
+  uint8_t pflags;             // PF_* bits
   uint8_t body_special;       // the expanded body reads tid or bid
   uint32_t off_instr, off_consts, off_access, off_sites;  // byte offsets from the header
   uint32_t total_bytes;

@@ -24,6 +24,7 @@ struct ckc_fuzz_s {
   uint32_t n_acc = 0;
   uint64_t n_records = 0;
   uint64_t gen = 0;  // generations queued so far
+  bool capture = false;  // the children's program needs the capture pass
   rt::Job J;         // the children's job buffers (from the context's pool)
   KArgs a{};
   EvalGrid eg{};
@@ -153,7 +154,9 @@ int ckc_fuzz_create(ckc_ctx c, const ckc_fuzz_config* cfg, ckc_fuzz* out) {
     d.mode = C.mode;
     d.detector = tripwire ? 1u : 0u;
     S.add(h, d, C.scalars, lanes_max, tripwire);
+    S.note_blockwise(h, T.host.data(), (uint32_t)T.host.size(), d.launch);
   }
+  F->capture = S.capture;
   if ((rc = rt::stage_new_job(c, F->J, S, false, F->a, F->eg))) return bail(rc);
   F->n_records = S.n_records;
   f.in = F->a.inputs;
@@ -204,6 +207,7 @@ int ckc_fuzz_run(ckc_fuzz F, uint32_t generations) {
     const uint64_t g = F->gen;
     hipError_t e = launch_fuzz_mutate(F->f, g, s);
     if (e == hipSuccess) e = rt::run_evaluation(F->a, F->eg, s);
+    if (e == hipSuccess && F->capture) e = launch_capture(F->a, F->eg, s);
     if (e == hipSuccess) e = launch_fixup(F->a, F->n_records, s);
     if (e == hipSuccess) e = launch_finish(F->a, s);
     if (e == hipSuccess) e = launch_fuzz_update(F->f, g, s);

@@ -9,6 +9,8 @@
 namespace ckc {
 
 constexpr int TILE = 256;  // lanes per tile = threads per evaluation workgroup
+// LDS for the shared-memory instances of one tile's blocks (blockwise programs)
+constexpr uint64_t SHARED_LDS_MAX = 48 * 1024;
 
 struct jobstate {
   unsigned long long total_tiles[3];  // tile space of each evaluator (dinput.path)
@@ -40,6 +42,8 @@ struct KArgs {
   unsigned long long* xbsum;  // [2][blocks]
   uint64_t n_xtiles;
   uint32_t max_regs;        // interpreter registers (LDS rows of TILE lanes) of the job's programs
+  uint32_t capture;         // this launch of the interpreter is the capture pass
+  uint32_t sh_bytes;        // LDS of the tile's shared-memory instances (blockwise programs)
   uint32_t pad;
 };
 // LDS bytes of the interpreter's register file for a job.
@@ -89,6 +93,11 @@ struct PrexArgs {
 hipError_t launch_prex_init(const PrexArgs& p, hipStream_t s);
 // Folds one window into the inputs' results (one workgroup per item).
 hipError_t launch_prex_merge(const PrexArgs& p, hipStream_t s);
+
+// Capture pass of programs whose indices depend on shared memory: the
+// interpreter runs their inputs again, and the lane whose key is a record's
+// first key writes the record's index and kind.
+hipError_t launch_capture(const KArgs& a, const EvalGrid& eg, hipStream_t s);
 
 hipError_t launch_plan(const KArgs& a, hipStream_t s);
 hipError_t launch_scan(const KArgs& a, hipStream_t s);

@@ -119,7 +119,7 @@ hipError_t launch_eval(const KArgs& a, const EvalGrid& eg, uint32_t path, hipStr
   KArgs k = with_sched(a, eg, path);
   void* args[] = {&k};
   return hipLaunchKernel(eval_fn(path, eg.sched[path]), dim3(eg.n_wg[path]), dim3(TILE), args,
-                         path == PATH_GENERIC ? regfile_bytes(a) : 0, s);
+                         path == PATH_GENERIC ? regfile_bytes(a) + a.sh_bytes : 0, s);
 }
 }  // namespace
 
@@ -131,6 +131,15 @@ hipError_t launch_eval_trace_lanes(const KArgs& a, const EvalGrid& eg, hipStream
 }
 hipError_t launch_eval_generic(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
   return launch_eval(a, eg, PATH_GENERIC, s);
+}
+hipError_t launch_capture(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
+  KArgs k = a;
+  k.capture = 1;
+  k.sched = CKC_SCHED_BLOCKED;  // no schedule counter to reset
+  k.chunk = 1;
+  void* args[] = {&k};
+  return hipLaunchKernel((void*)eval_generic_kernel<CKC_SCHED_BLOCKED>, dim3(eg.n_wg[PATH_GENERIC]), dim3(TILE),
+                         args, regfile_bytes(a) + a.sh_bytes, s);
 }
 static void* body_fn(uint32_t sk, uint32_t which, uint32_t big) {
   const uint32_t s = sched_impl(sk);
@@ -218,7 +227,7 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
                  argsp[PATH_BLOCKS]);
   if (e == hipSuccess)
     e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC]), eg.n_wg[PATH_GENERIC], TILE,
-                 argsp[PATH_GENERIC], regfile_bytes(a));
+                 argsp[PATH_GENERIC], regfile_bytes(a) + a.sh_bytes);
   if (e == hipSuccess)
     e = add_node(g, &ev[2], &scan, 1, eval_fn(PATH_LANES, eg.sched[PATH_LANES]), eg.n_wg[PATH_LANES], TILE,
                  argsp[PATH_LANES]);

@@ -28,9 +28,34 @@ struct Ins {
   int alt = -1, end = -1, depth = 0;  // IF: ELSE; IF/ELSE: ENDIF; LOOP<->ENDLOOP
   int parent = -1;                    // innermost enclosing IF/ELSE/LOOP pc
   bool live = false;
+  bool store_val = false;             // STORE: its value is kept (shared memory read back)
 };
 
 bool is_binary(int op) { return op >= CKC_OP_ADD && op <= CKC_OP_CMPLEU; }
+bool is_float(int op) { return op >= CKC_OP_FADD && op <= CKC_OP_FTOI; }
+// The instruction defines its dst register.
+bool defines_op(int op) {
+  return !(op == CKC_OP_ACCESS || op == CKC_OP_STORE || op == CKC_OP_IF || op == CKC_OP_ELSE ||
+           op == CKC_OP_ENDIF || op == CKC_OP_ENDLOOP || op == CKC_OP_BARRIER);
+}
+// Registers an instruction reads (a STORE's value only when `with_value`).
+int reads(const Ins& I, uint16_t r[3], bool with_value) {
+  switch (I.op) {
+    case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE: case CKC_OP_ENDIF:
+    case CKC_OP_ENDLOOP: case CKC_OP_BARRIER:
+      return 0;
+    case CKC_OP_SELECT: case CKC_OP_LOOP: r[0] = I.a; r[1] = I.b; r[2] = I.c; return 3;
+    case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS: case CKC_OP_LOAD:
+    case CKC_OP_IF: case CKC_OP_FEXP: case CKC_OP_ITOF: case CKC_OP_FTOI:
+      r[0] = I.a; return 1;
+    case CKC_OP_STORE:
+      r[0] = I.a;
+      if (!with_value) return 1;
+      r[1] = I.dst;
+      return 2;
+    default: r[0] = I.a; r[1] = I.b; return 2;  // integer and floating-point binary ops
+  }
+}
 bool is_divrem(int op) {
   return op == CKC_OP_DIVS || op == CKC_OP_DIVU || op == CKC_OP_REMS || op == CKC_OP_REMU;
 }
@@ -84,6 +109,12 @@ struct Analyzer {
   std::vector<Form> form;
   std::vector<char> indirect;
   int max_depth = 0;
+  bool no_prune = false;     // keep every instruction (the unpruned program)
+  bool has_barrier = false;  // some BARRIER
+  uint32_t shared_idx = 0;   // shared slots some LOAD of which feeds the slice
+  uint32_t shared_live = 0;  // shared slots read back into the pruned program
+
+  uint32_t space_of(int slot) const { return slot < 16 ? (slot_spaces >> (2 * slot)) & 3u : 0u; }
 
   bool fail(int pc, const char* what) {
     err = pc >= 0 ? ("instruction " + std::to_string(pc) + ": " + what) : std::string(what);
@@ -196,20 +227,43 @@ struct Analyzer {
           if (!use(i, I.a) || !def(i, I.dst)) return false;
           break;
         case CKC_OP_ACCESS:
+        case CKC_OP_STORE:
         case CKC_OP_LOAD:
           if (!width(i, I.w) || !use(i, I.a)) return false;
+          if (I.op == CKC_OP_STORE && !use(i, I.dst)) return false;
           if (I.b >= n_accesses || acc_used[I.b]) return fail(i, "access id out of range or reused");
           acc_used[I.b] = 1;
           if (I.c >= n_slots) return fail(i, "allocation slot out of range");
           if (I.op == CKC_OP_ACCESS) {
             if (I.d > 7) return fail(i, "bad ACCESS flags");
+          } else if (I.op == CKC_OP_STORE) {
+            if (I.d > 3) return fail(i, "bad STORE element size");
           } else {
             if (I.d != 2 && I.d != 3) return fail(i, "LOAD element must be 4 or 8 bytes");
-            if (((slot_spaces >> (2 * I.c)) & 3u) != CKC_SPACE_GLOBAL)
-              return fail(i, "LOAD reads a global slot only");
+            if (space_of(I.c) == CKC_SPACE_LOCAL) return fail(i, "LOAD reads global or shared slots only");
+            if (space_of(I.c) == CKC_SPACE_SHARED && I.d != 2) return fail(i, "shared LOAD element must be 4 bytes");
             if (!def(i, I.dst)) return false;
           }
           if (!site(i, I.s0)) return false;
+          break;
+        case CKC_OP_FADD: case CKC_OP_FSUB: case CKC_OP_FMUL:
+          if (I.w != 64) return fail(i, "floating-point operations have width 64");
+          if (!use(i, I.a) || !use(i, I.b) || !def(i, I.dst)) return false;
+          break;
+        case CKC_OP_FEXP:
+          if (I.w != 64) return fail(i, "floating-point operations have width 64");
+          if (!use(i, I.a) || !def(i, I.dst)) return false;
+          break;
+        case CKC_OP_ITOF:
+          if (I.w != 32) return fail(i, "ITOF converts a width-32 value");
+          if (!use(i, I.a) || !def(i, I.dst)) return false;
+          break;
+        case CKC_OP_FTOI:
+          if (!width(i, I.w) || !use(i, I.a) || !def(i, I.dst)) return false;
+          break;
+        case CKC_OP_BARRIER:
+          if (!ctl.empty()) return fail(i, "BARRIER inside IF or LOOP");
+          has_barrier = true;
           break;
         case CKC_OP_IF:
           if (!use(i, I.a) || !site(i, I.s0) || !site(i, I.s1)) return false;
@@ -286,14 +340,9 @@ struct Analyzer {
     };
     for (int i = 0; i < n_instr; i++) {
       const Ins& I = ins[i];
-      switch (I.op) {
-        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
-        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
-        case CKC_OP_SELECT: case CKC_OP_LOOP: touch(I.a, i); touch(I.b, i); touch(I.c, i); break;
-        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
-        case CKC_OP_LOAD: case CKC_OP_IF: touch(I.a, i); break;
-        default: touch(I.a, i); touch(I.b, i); break;
-      }
+      uint16_t rr[3];
+      const int nr = reads(I, rr, true);
+      for (int q = 0; q < nr; q++) touch(rr[q], i);
       if (I.op == CKC_OP_LOOP) end[I.dst] = std::max(end[I.dst], I.end);
     }
     // live after instruction i: registers r with def_pc[r] < i < end[r]
@@ -307,77 +356,91 @@ struct Analyzer {
     for (int i = 0; i < n_instr; i++) {
       cur += diff[i];
       const Ins& I = ins[i];
-      const bool defines = (I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF) || I.op == CKC_OP_LOOP;
-      if (defines && cur + 1 > (int)CKC_IR_MAX_LIVE_REGS)
+      if (defines_op(I.op) && cur + 1 > (int)CKC_IR_MAX_LIVE_REGS)
         return fail(i, "more than CKC_IR_MAX_LIVE_REGS (32) registers live");
     }
     return true;
   }
 
-  // Pruning: keep accesses, control flow, divisions (they count faults) and
-  // everything that feeds them; one backward pass suffices because every
-  // definition precedes its uses.
-  // The slice of the indices, IF predicates and loop bounds (the same walk
-  // without the division roots): the instructions whose wraps at the vertex
-  // threads clear the vertex-exact flag.
+  // Pruning, the paper's AXIPrune (Algorithm 2).  slice_pass walks
+  // backwards (every definition precedes its uses) from the accesses, IF
+  // predicates and loop bounds and, with `divs`, the divisions (they count
+  // arithmetic faults, so their operands stay exact), marking every
+  // instruction whose result a marked one reads; a STORE's value is read
+  // when its slot is in xs.  It returns the shared slots some LOAD of which
+  // has its result needed.  The fixpoint over xs (the set only grows) gives
+  // without divisions the index-related shared variables and the slice, whose
+  // wraps at the vertex threads clear the vertex-exact flag; with divisions
+  // the shared slots read back into the pruned program.  MathElimination keeps
+  // only that live set and the control structure; BarrierElimination removes
+  // every BARRIER unless some shared slot is read back (all or none, as the
+  // algorithm is written).  With no_prune everything is kept.
   std::vector<char> slice;
-  void prune() {
-    slice.assign(n_instr, 0);
-    {
-      std::vector<char> need(n_regs, 0);
-      for (int i = n_instr - 1; i >= 0; i--) {
-        const Ins& I = ins[i];
-        const bool root = I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD || I.op == CKC_OP_IF || I.op == CKC_OP_LOOP;
-        const bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF;
-        if (!(root || (defines && I.dst < n_regs && need[I.dst]))) continue;
-        slice[i] = 1;
-        auto mark = [&](uint16_t r) { if (r < n_regs) need[r] = 1; };
-        switch (I.op) {
-          case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: break;
-          case CKC_OP_SELECT: case CKC_OP_LOOP: mark(I.a); mark(I.b); mark(I.c); break;
-          case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
-          case CKC_OP_LOAD: case CKC_OP_IF: mark(I.a); break;
-          default: mark(I.a); mark(I.b); break;
-        }
-      }
-    }
-    std::vector<char> reg_live(n_regs, 0);
+  uint32_t slice_pass(uint32_t xs, bool divs, std::vector<char>& need, std::vector<char>& mark) const {
+    std::fill(need.begin(), need.end(), 0);
+    mark.assign(n_instr, 0);
     for (int i = n_instr - 1; i >= 0; i--) {
-      Ins& I = ins[i];
-      bool root = I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD || I.op >= CKC_OP_IF || is_divrem(I.op);
-      bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF;
-      I.live = root || (defines && I.dst < n_regs && reg_live[I.dst]);
-      if (!I.live) continue;
-      auto mark = [&](uint16_t r) { if (r < n_regs) reg_live[r] = 1; };
-      switch (I.op) {
-        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
-        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP:
-          break;
-        case CKC_OP_SELECT: case CKC_OP_LOOP: mark(I.a); mark(I.b); mark(I.c); break;
-        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
-        case CKC_OP_LOAD: case CKC_OP_IF: mark(I.a); break;
-        default: mark(I.a); mark(I.b); break;
-      }
+      const Ins& I = ins[i];
+      const bool root = I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD || I.op == CKC_OP_STORE ||
+                        I.op == CKC_OP_IF || I.op == CKC_OP_LOOP || (divs && is_divrem(I.op));
+      if (!(root || (defines_op(I.op) && I.op != CKC_OP_LOOP && I.dst < n_regs && need[I.dst]))) continue;
+      mark[i] = 1;
+      uint16_t rr[3];
+      const int nr = reads(I, rr, I.op == CKC_OP_STORE && ((xs >> I.c) & 1u));
+      for (int q = 0; q < nr; q++)
+        if (rr[q] < n_regs) need[rr[q]] = 1;
     }
+    uint32_t nxs = 0;
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (I.op == CKC_OP_LOAD && space_of(I.c) == CKC_SPACE_SHARED && need[I.dst]) nxs |= 1u << I.c;
+    }
+    return nxs;
+  }
+  uint32_t slice_fixpoint(bool divs, std::vector<char>& mark) const {
+    std::vector<char> need(n_regs, 0);
+    uint32_t xs = 0;
+    for (;;) {
+      const uint32_t nxs = slice_pass(xs, divs, need, mark);
+      if (nxs == xs) return xs;
+      xs = nxs;
+    }
+  }
+  bool prune() {
+    shared_idx = slice_fixpoint(false, slice);
+    std::vector<char> live;
+    shared_live = slice_fixpoint(true, live);
+    for (int i = 0; i < n_instr; i++) {
+      Ins& I = ins[i];
+      const bool structure = I.op == CKC_OP_ELSE || I.op == CKC_OP_ENDIF || I.op == CKC_OP_ENDLOOP;
+      I.live = no_prune || live[i] || structure || (I.op == CKC_OP_BARRIER && shared_live != 0);
+      I.store_val = I.op == CKC_OP_STORE && (no_prune || ((shared_live >> I.c) & 1u));
+    }
+    return true;
+  }
+
+  // The program needs its blocks run together (shared memory read back, or
+  // barriers executed).
+  bool blockwise() const {
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live) continue;
+      if (I.op == CKC_OP_BARRIER) return true;
+      // a shared LOAD whose result nothing kept reads may return anything
+      if (I.op == CKC_OP_LOAD && space_of(I.c) == CKC_SPACE_SHARED && (no_prune || ((shared_live >> I.c) & 1u)))
+        return true;
+    }
+    return false;
   }
 
   bool reg_used(int r) const {
     for (int i = def_pc[r] + 1; i < n_instr; i++) {
       const Ins& I = ins[i];
       if (!I.live) continue;
-      switch (I.op) {
-        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
-        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
-        case CKC_OP_SELECT: case CKC_OP_LOOP:
-          if (I.a == r || I.b == r || I.c == r) return true;
-          break;
-        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
-        case CKC_OP_LOAD: case CKC_OP_IF:
-          if (I.a == r) return true;
-          break;
-        default:
-          if (I.a == r || I.b == r) return true;
-      }
+      uint16_t rr[3];
+      const int nr = reads(I, rr, I.store_val);
+      for (int q = 0; q < nr; q++)
+        if (rr[q] == r) return true;
     }
     return false;
   }
@@ -418,6 +481,7 @@ struct Analyzer {
         cvar_stack.push_back(cvar_stack.back() || !uni[I.a]);
         continue;
       }
+      if (I.op == CKC_OP_STORE || I.op == CKC_OP_BARRIER) continue;
       int r = I.dst;
       switch (I.op) {
         case CKC_OP_CONST: case CKC_OP_SCALAR:
@@ -431,10 +495,19 @@ struct Analyzer {
           }
           break;
         case CKC_OP_LOAD:
-          uni[r] = uni[I.a];
+          // shared memory differs from block to block and phase to phase
+          uni[r] = uni[I.a] && space_of(I.c) != CKC_SPACE_SHARED;
           if (uni[r]) form[r] = uform(r, i);
           else indirect[r] = 1;
           break;
+        case CKC_OP_FADD: case CKC_OP_FSUB: case CKC_OP_FMUL: case CKC_OP_FEXP: case CKC_OP_ITOF:
+        case CKC_OP_FTOI: {
+          const bool unary = I.op == CKC_OP_FEXP || I.op == CKC_OP_ITOF || I.op == CKC_OP_FTOI;
+          uni[r] = uni[I.a] && (unary || uni[I.b]);
+          indirect[r] = indirect[I.a] || (!unary && indirect[I.b]);
+          form[r] = Form{};  // never affine (not modular integer arithmetic)
+          break;
+        }
         case CKC_OP_LOOP: {
           bool u = uni[I.a] && uni[I.b] && uni[I.c];
           uni[r] = u;
@@ -499,14 +572,9 @@ struct Analyzer {
     for (int i = 0; i < n_instr; i++) {
       const Ins& I = ins[i];
       if (!I.live) continue;
-      switch (I.op) {
-        case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
-        case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
-        case CKC_OP_SELECT: case CKC_OP_LOOP: touch(I.a, i); touch(I.b, i); touch(I.c, i); break;
-        case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
-        case CKC_OP_LOAD: case CKC_OP_IF: touch(I.a, i); break;
-        default: touch(I.a, i); touch(I.b, i); break;
-      }
+      uint16_t rr[3];
+      const int nr = reads(I, rr, I.store_val);
+      for (int q = 0; q < nr; q++) touch(rr[q], i);
     }
     // a loop counter lives through its whole body
     for (int i = 0; i < n_instr; i++)
@@ -516,8 +584,7 @@ struct Analyzer {
     for (int i = 0; i < n_instr; i++) {
       const Ins& I = ins[i];
       if (!I.live) continue;
-      bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF ? true : I.op == CKC_OP_LOOP;
-      if (!defines || I.dst >= n_regs) continue;
+      if (!defines_op(I.op) || I.dst >= n_regs) continue;
       int r = I.dst;
       int end = last[r] < 0 ? i : last[r];
       int got = -1;
@@ -548,7 +615,7 @@ struct Analyzer {
   }
 
   void choose_expansion(bool uniform_prog) {
-    if (uniform_prog) return;
+    if (uniform_prog || blockwise()) return;  // a blockwise program's threads stay in their block
     for (int i = 0; i < n_instr; i++) {
       const Ins& I = ins[i];
       if (!I.live || I.op != CKC_OP_LOOP || I.depth != 0) continue;
@@ -560,14 +627,7 @@ struct Analyzer {
         const Ins& J = ins[j];
         if (!J.live) continue;
         uint16_t ops[3] = {CKC_IR_NO_REG, CKC_IR_NO_REG, CKC_IR_NO_REG};
-        switch (J.op) {
-          case CKC_OP_CONST: case CKC_OP_SCALAR: case CKC_OP_SPECIAL: case CKC_OP_ELSE:
-          case CKC_OP_ENDIF: case CKC_OP_ENDLOOP: break;
-          case CKC_OP_SELECT: ops[0] = J.a; ops[1] = J.b; ops[2] = J.c; break;
-          case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: case CKC_OP_ACCESS:
-          case CKC_OP_LOAD: case CKC_OP_IF: ops[0] = J.a; break;
-          default: ops[0] = J.a; ops[1] = J.b; break;
-        }
+        reads(J, ops, J.store_val);
         for (uint16_t r : ops) {
           if (r >= n_regs || r == I.dst || def_pc[r] >= i) continue;
           int p = phys[r];
@@ -614,6 +674,9 @@ struct Analyzer {
           if (I.a < 6) return;  // thread coordinates: keep the interpreter
           var[I.dst] = -1;
           break;
+        case CKC_OP_STORE:
+          if (I.store_val) return;  // a value written back: keep the interpreter
+          [[fallthrough]];
         case CKC_OP_ACCESS: case CKC_OP_LOAD: {
           if (!operand_ok(I.a)) return;
           if (v_of(I.a) >= 0 && k_of(I.a) < w) return;
@@ -690,7 +753,7 @@ struct Analyzer {
       D.op = I.op;
       D.w = I.w;
       D.s0 = I.s0; D.s1 = I.s1;
-      if ((I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD) && I.s0 == CKC_IR_NO_SITE)
+      if ((I.op == CKC_OP_ACCESS || I.op == CKC_OP_LOAD || I.op == CKC_OP_STORE) && I.s0 == CKC_IR_NO_SITE)
         D.s0 = (uint16_t)(n_sites + n_internal++);  // internal site: counted, never mapped
       auto P = [&](uint16_t r) -> uint8_t { return r < n_regs && phys[r] >= 0 ? (uint8_t)phys[r] : 0; };
       switch (I.op) {
@@ -702,10 +765,15 @@ struct Analyzer {
         case CKC_OP_SCALAR: case CKC_OP_SPECIAL: D.dst = P(I.dst); D.x = I.a; D.w = I.op == CKC_OP_SPECIAL ? 64 : I.w; break;
         case CKC_OP_SELECT: D.dst = P(I.dst); D.a = P(I.a); D.b = P(I.b); D.c = P(I.c); break;
         case CKC_OP_SEXT: case CKC_OP_ZEXT: case CKC_OP_TRUNC: D.dst = P(I.dst); D.a = P(I.a); break;
-        case CKC_OP_ACCESS: case CKC_OP_LOAD: {
+        case CKC_OP_ACCESS: case CKC_OP_LOAD: case CKC_OP_STORE: {
           D.a = P(I.a); D.slot = (uint8_t)I.c; D.x = I.b;
-          D.fl = (uint8_t)(I.op == CKC_OP_ACCESS ? (I.d & 3) : I.d);
+          D.fl = (uint8_t)(I.op == CKC_OP_LOAD ? I.d : (I.d & 3));
           D.dst = I.op == CKC_OP_LOAD ? P(I.dst) : 0;
+          // a STORE whose value nothing reads back is a checked write
+          if (I.op == CKC_OP_STORE) {
+            if (I.store_val) D.b = P(I.dst);
+            else D.op = CKC_OP_ACCESS;
+          }
           daccess& A = acc[I.b];
           A.pc = (uint16_t)newpc[i];
           A.depth = (uint16_t)I.depth;
@@ -729,6 +797,8 @@ struct Analyzer {
           D.fl = (uint8_t)(i == expand_pc ? (DI_EXPAND | DI_NOSKIP) : 0);
           break;
         case CKC_OP_ENDLOOP: D.jmp = (uint16_t)newpc[I.end]; D.x = (uint16_t)ins[I.end].depth; break;
+        case CKC_OP_BARRIER: break;
+        case CKC_OP_FEXP: case CKC_OP_ITOF: case CKC_OP_FTOI: D.dst = P(I.dst); D.a = P(I.a); break;
         default: D.dst = P(I.dst); D.a = P(I.a); D.b = P(I.b); break;
       }
       if (slice[i] && I.op < CKC_OP_ACCESS) D.fl |= DI_SLICE;
@@ -754,6 +824,7 @@ struct Analyzer {
         if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
     h.body_gather = body_gather ? 1u : 0u;
     h.slot_spaces = slot_spaces;
+    h.pflags = (uint8_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0));
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
     h.off_instr = al(sizeof(dprog));
@@ -805,15 +876,15 @@ struct Analyzer {
 
 }  // namespace
 
-int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
+int analyze_program(const void* ir, size_t ir_bytes, Loaded* out, bool no_prune) {
   Analyzer A;
   A.ir = (const uint8_t*)ir;
   A.n = ir_bytes;
-  if (!A.decode() || !A.validate()) {
+  A.no_prune = no_prune;
+  if (!A.decode() || !A.validate() || !A.prune()) {
     out->err = A.err;
     return CKC_E_IR;
   }
-  A.prune();
   A.classify();
   if (!A.allocate()) {
     out->err = A.err;
@@ -824,11 +895,11 @@ int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
   bool all_affine = true, any_guard = false, any_ind = false, any64 = false;
   for (int i = 0; i < A.n_instr; i++) {
     const Ins& I = A.ins[i];
-    if (I.op != CKC_OP_ACCESS && I.op != CKC_OP_LOAD) continue;
+    if (I.op != CKC_OP_ACCESS && I.op != CKC_OP_LOAD && I.op != CKC_OP_STORE) continue;
     ckc_access_info& ai = out->acc[I.b];
     ai.access_id = I.b;
     ai.slot = I.c;
-    ai.log2_elem = I.op == CKC_OP_ACCESS ? (I.d & 3u) : I.d;
+    ai.log2_elem = I.op == CKC_OP_LOAD ? I.d : (I.d & 3u);
     ai.width = I.w;
     const Form& f = A.form[I.a];
     bool aff = f.affine && (A.uni[I.a] || f.k == 0 || f.k >= I.w);
@@ -851,16 +922,16 @@ int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
     if (!I.live) continue;
     if (I.op == CKC_OP_IF && !A.uni[I.a]) any_var_ctrl = true;
     if (I.op == CKC_OP_LOOP && !A.uni[I.dst]) any_var_ctrl = true;
-    bool defines = I.op != CKC_OP_ACCESS && I.op < CKC_OP_IF;
-    if (defines && I.dst < A.n_regs && !A.uni[I.dst]) {
+    if (is_float(I.op) || I.store_val || I.op == CKC_OP_BARRIER) var_ok = false;  // not on the trace path
+    if (defines_op(I.op) && I.op != CKC_OP_LOOP && I.dst < A.n_regs && !A.uni[I.dst]) {
       if (is_divrem(I.op)) var_ok = false;
       else if (!A.form[I.dst].affine && A.reg_used(I.dst)) var_ok = false;
     }
   }
-  bool uniform_prog = all_affine && !any_var_ctrl && var_ok;
+  bool uniform_prog = all_affine && !any_var_ctrl && var_ok && !A.blockwise() && !no_prune;
   uint32_t cls = (all_affine ? CKC_CLS_AFFINE : 0) | (any_guard ? CKC_CLS_GUARDED : 0) |
                  (any_ind ? CKC_CLS_INDIRECT : 0) | (any64 ? CKC_CLS_I64 : 0) |
-                 (uniform_prog ? CKC_CLS_UNIFORM : 0);
+                 (uniform_prog ? CKC_CLS_UNIFORM : 0) | (A.shared_idx ? CKC_CLS_BARRIER : 0);
   A.choose_expansion(uniform_prog);
   A.check_gather();
   if (A.expand_pc >= 0) cls |= CKC_CLS_EXPANDED;
@@ -884,7 +955,8 @@ int analyze_program(const void* ir, size_t ir_bytes, Loaded* out) {
   out->info.n_regs_phys = A.n_phys;
   out->load_slots = 0;
   for (int i = 0; i < A.n_instr; i++)
-    if (A.ins[i].op == CKC_OP_LOAD) out->load_slots |= 1u << A.ins[i].c;
+    if (A.ins[i].op == CKC_OP_LOAD && A.space_of(A.ins[i].c) == CKC_SPACE_GLOBAL)
+      out->load_slots |= 1u << A.ins[i].c;
   return CKC_OK;
 }
 

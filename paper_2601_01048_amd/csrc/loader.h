@@ -17,7 +17,8 @@ struct Loaded {
   std::string err;
 };
 
-// Validates, prunes, classifies and lowers.  CKC_OK or CKC_E_IR (out->err).
-int analyze_program(const void* ir, size_t ir_bytes, Loaded* out);
+// Validates, prunes (unless no_prune), classifies and lowers.  CKC_OK or
+// CKC_E_IR (out->err).
+int analyze_program(const void* ir, size_t ir_bytes, Loaded* out, bool no_prune = false);
 
 }  // namespace ckc

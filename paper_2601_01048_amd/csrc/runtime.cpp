@@ -186,6 +186,21 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
     if (tit == c->tables.end()) return fail(CKC_E_INVALID, di() + "unknown table");
     const Table& T = tit->second;
     if (T.host.size() < h->n_slots) return fail(CKC_E_INVALID, di() + "table has fewer slots than the program");
+    if (h->pflags & PF_BLOCKWISE) {
+      // a tile of the interpreter holds whole blocks, whose shared memory fits in LDS
+      if (bs > (uint64_t)TILE || TILE % bs != 0)
+        return fail(CKC_E_INVALID, di() + "blocks of a program with barriers or shared loads must divide 256 threads");
+      if (B.mode == CKC_REP_CORNERS)
+        return fail(CKC_E_INVALID, di() + "the corner thread set splits blocks that share memory");
+      if ((h->pflags & PF_CAPTURE) && B.mode == CKC_REP_PREX)
+        return fail(CKC_E_INVALID, di() + "PREX sweep of a program with index-related shared memory");
+      uint64_t words = 0;  // each slot capped, so that the sum cannot wrap
+      for (uint32_t s = 0; s < h->n_slots; s++)
+        if (((h->slot_spaces >> (2 * s)) & 3u) == CKC_SPACE_SHARED && T.host[s].base != 0)
+          words += std::min<uint64_t>(T.host[s].size_bytes / 4, SHARED_LDS_MAX);
+      if ((TILE / bs) * words * 12 > SHARED_LDS_MAX)
+        return fail(CKC_E_INVALID, di() + "shared memory of the blocks of one tile above 48 KiB");
+    }
     if (tripwire)  // every allocation with its redzones inside [0, 2^63]
       for (size_t s = 0; s < T.host.size(); s++) {
         const ckc_alloc& A = T.host[s];
@@ -327,6 +342,8 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   a.xbsum = xbsum;
   a.n_xtiles = nx;
   a.max_regs = S.max_regs;
+  a.capture = 0;
+  a.sh_bytes = S.sh_bytes;
   a.pad = 0;
   a.sched = CKC_SCHED_DYNAMIC;
   a.chunk = O.chunk ? O.chunk : 1u;
@@ -421,6 +438,7 @@ void stage_inputs(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc
       // tripwire inputs take the interpreter: no trace of their own
       S.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, lanes_max,
             O.force_generic != 0 || d.detector != 0);
+      S.note_blockwise(h, T.host.data(), (uint32_t)T.host.size(), d.launch);
     }
   }
 }
@@ -449,6 +467,8 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
   Stage R;  // the inputs themselves
   std::vector<uint32_t> rounds;  // ceil(nblocks / 2) per input (0: empty grid)
   std::vector<const dprog*> heads;
+  std::vector<const ckc_alloc*> tabs_host;  // each input's table (host copy) and its entries
+  std::vector<uint32_t> tabs_n;
   for (uint32_t k = 0; k < n_descs; k++) {
     const ckc_batch& B = descs[k];
     const Program& P = c->progs.find(B.prog_id)->second;
@@ -463,6 +483,8 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
       const uint64_t nb = (uint64_t)L[0] * L[1] * L[2], bs = (uint64_t)L[3] * L[4] * L[5];
       rounds.push_back(nb == 0 || bs == 0 ? 0u : (uint32_t)((nb + 1) / 2));
       heads.push_back(h);
+      tabs_host.push_back(T.host.data());
+      tabs_n.push_back((uint32_t)T.host.size());
       // the inputs need no trace or loop state of their own
       R.add(h, d, B.scalars ? B.scalars + (size_t)i * h->n_scalars : nullptr, 0, true);
     }
@@ -547,6 +569,7 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
         v.aux = next[i] + (uint32_t)r;
         v.path = 0;
         W.add(heads[i], v, sc, bs2, O.force_generic != 0 || v.detector != 0);
+        W.note_blockwise(heads[i], (const ckc_alloc*)tabs_host[i], tabs_n[i], v.launch);
         lanes += bs2;
       }
     }
@@ -709,6 +732,28 @@ int ckc_load_program(ckc_ctx c, const void* ir, size_t ir_bytes, uint32_t* prog_
   return CKC_OK;
 }
 
+int ckc_load_program_ex(ckc_ctx c, const void* ir, size_t ir_bytes, uint32_t flags, uint32_t* prog_id,
+                        ckc_prog_info* info) {
+  if (!c || !prog_id) return fail(CKC_E_INVALID, "NULL argument");
+  if (flags & ~(uint32_t)CKC_LOAD_NO_PRUNE) return fail(CKC_E_INVALID, "unknown load flags");
+  Program P;
+  int rc = analyze_program(ir, ir_bytes, &P.L, (flags & CKC_LOAD_NO_PRUNE) != 0);
+  if (rc != CKC_OK) return fail(rc, P.L.err);
+  if ((rc = set_device(c))) return rc;
+  hipError_t e = hipMalloc(&P.dblob, P.L.blob.size());
+  if (e != hipSuccess) return fail(CKC_E_NOMEM, "program upload");
+  e = hipMemcpy(P.dblob, P.L.blob.data(), P.L.blob.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(P.dblob);
+    return fail(CKC_E_HIP, std::string("program upload: ") + hipGetErrorString(e));
+  }
+  uint32_t id = c->next_prog++;
+  if (info) *info = P.L.info;
+  c->progs.emplace(id, std::move(P));
+  *prog_id = id;
+  return CKC_OK;
+}
+
 int ckc_unload_program(ckc_ctx c, uint32_t prog_id) {
   if (!c) return fail(CKC_E_INVALID, "NULL context");
   auto it = c->progs.find(prog_id);
@@ -799,13 +844,14 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   hipError_t e = hipSuccess;
   for (int q = 0; q < ckc::rt::NEV && e == hipSuccess; q++) e = hipEventCreate(&J.ev[q]);
   if (e != hipSuccess) return bail(fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e)));
-  J.graph = O.use_graph != 0;
+  J.graph = O.use_graph != 0 && !S.capture;  // the capture pass runs outside graphs
   e = hipEventRecord(J.ev[0], J.stream);
   if (J.graph) {
     if (e == hipSuccess) e = launch_graph(c, a, eg, S.n_records, J.stream);
     for (int q = 1; q < ckc::rt::NEV - 1 && e == hipSuccess; q++) e = hipEventRecord(J.ev[q], J.stream);
   } else {
     if (e == hipSuccess) e = launch_evaluation(a, eg, J.stream, J.ev);
+    if (e == hipSuccess && S.capture) e = launch_capture(a, eg, J.stream);
     if (e == hipSuccess) e = hipEventRecord(J.ev[4], J.stream);
     if (e == hipSuccess) e = launch_fixup(a, S.n_records, J.stream);
     if (e == hipSuccess) e = launch_finish(a, J.stream);
@@ -863,6 +909,7 @@ int ckc_check_batch_noalloc(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs,
   EvalGrid eg;
   if ((rc = stage_upload(c, B, s, S, O, dense, ext, a, eg))) return rc;
   hipError_t e = launch_evaluation(a, eg, s, nullptr);
+  if (e == hipSuccess && S.capture) e = launch_capture(a, eg, s);
   if (e == hipSuccess) e = launch_fixup(a, S.n_records, s);
   if (e == hipSuccess) e = launch_finish(a, s);
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("launch: ") + hipGetErrorString(e));

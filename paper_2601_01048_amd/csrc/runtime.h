@@ -58,6 +58,22 @@ struct Stage {
   uint32_t max_regs = 1;                               // interpreter register file rows
   uint64_t gen_tiles = 0;  // interpreter tiles (estimate from the launch shapes)
   uint64_t n_records = 0, n_counts = 0, trace_bytes = 0;
+  uint32_t sh_bytes = 0;  // LDS of the shared-memory instances of a tile (blockwise programs)
+  bool capture = false;   // some input needs the capture pass
+
+  // Notes an input of a blockwise program (PF_BLOCKWISE): each tile holds
+  // TILE / bs of its blocks, each with one instance of every shared slot (a
+  // 32-bit current word and a 64-bit phase-write word per element).
+  void note_blockwise(const dprog* h, const ckc_alloc* tab, uint32_t n_tab, const uint32_t* L) {
+    if (!(h->pflags & PF_BLOCKWISE)) return;
+    const uint64_t bs = (uint64_t)L[3] * L[4] * L[5];
+    uint64_t words = 0;
+    for (uint32_t s = 0; s < h->n_slots && s < n_tab; s++)
+      if (((h->slot_spaces >> (2 * s)) & 3u) == CKC_SPACE_SHARED && tab[s].base != 0) words += tab[s].size_bytes / 4;
+    const uint64_t need = bs ? (TILE / bs) * words * 12 : 0;
+    if (need > sh_bytes) sh_bytes = (uint32_t)need;
+    capture |= (h->pflags & PF_CAPTURE) != 0;
+  }
 
   // Room for n inputs, so that staging up to n allocates no host memory.
   void reserve(size_t n) {
@@ -76,6 +92,8 @@ struct Stage {
     max_regs = 1;
     gen_tiles = 0;
     n_records = n_counts = trace_bytes = 0;
+    sh_bytes = 0;
+    capture = false;
   }
 
   // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;

@@ -28,7 +28,8 @@ OP = dict(
     MINS=21, MAXS=22, MINU=23, MAXU=24,
     CMPEQ=25, CMPNE=26, CMPLTS=27, CMPLES=28, CMPLTU=29, CMPLEU=30,
     SELECT=31, SEXT=32, ZEXT=33, TRUNC=34,
-    ACCESS=48, LOAD=49, IF=56, ELSE=57, ENDIF=58, LOOP=59, ENDLOOP=60,
+    FADD=40, FSUB=41, FMUL=42, FEXP=43, ITOF=44, FTOI=45,
+    ACCESS=48, LOAD=49, STORE=50, IF=56, ELSE=57, ENDIF=58, LOOP=59, ENDLOOP=60, BARRIER=61,
 )
 BINARY = ("ADD SUB MUL DIVS DIVU REMS REMU AND OR XOR SHL SHRA SHRL MINS MAXS "
           "MINU MAXU CMPEQ CMPNE CMPLTS CMPLES CMPLTU CMPLEU").split()
@@ -154,6 +155,36 @@ class Program:
         flags = (elem.bit_length() - 1) | (4 if write else 0)
         self._emit("ACCESS", w, NO_REG, idx.idx, acc, slot, flags, self._site_arg(site))
         return acc
+
+    def store(self, slot: int, idx: Reg, value: Reg, elem: int = 4, w: int | None = None,
+              site=True) -> int:
+        """Checked write of ``value`` (a STORE: kept as data only for shared
+        slots read back by a LOAD)."""
+        w = idx.w if w is None else w
+        acc = self.n_accesses
+        self.n_accesses += 1
+        self._emit("STORE", w, value.idx, idx.idx, acc, slot, elem.bit_length() - 1, self._site_arg(site))
+        return acc
+
+    def barrier(self):
+        """__syncthreads (top level only)."""
+        self._emit("BARRIER")
+
+    def fop(self, name: str, a: Reg, b: Reg | None = None) -> Reg:
+        """FADD / FSUB / FMUL (a, b) or FEXP (a): binary64 bit patterns."""
+        r = self._new(64)
+        self._emit(name, 64, r.idx, a.idx, 0 if b is None else b.idx)
+        return r
+
+    def itof(self, a: Reg) -> Reg:
+        r = self._new(64)
+        self._emit("ITOF", 32, r.idx, a.idx)
+        return r
+
+    def ftoi(self, a: Reg, w: int = 32) -> Reg:
+        r = self._new(w)
+        self._emit("FTOI", w, r.idx, a.idx)
+        return r
 
     def load(self, slot: int, idx: Reg, elem: int = 4, w: int | None = None,
              site=True) -> Reg:

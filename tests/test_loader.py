@@ -195,8 +195,9 @@ def test_gather_classification():
 
 def test_slot_spaces_agree_with_oracle():
     """The header's slot-space word (2 bits per slot: global, shared, local):
-    every value of each field, fields beyond n_slots, and LOADs from non-global
-    slots, accepted or refused alike by the loader and the oracle's decoder."""
+    every value of each field, fields beyond n_slots, and LOADs from global,
+    shared (allowed: shared memory is read back) and local slots (refused),
+    accepted or refused alike by the loader and the oracle's decoder."""
     from paper_2601_01048_amd.gen.ir import Program
     cases = []
     for spaces in ([0, 0], [1, 2], [2, 0], [3, 0], [0, 3], [1, 1, 1], [0, 0, 2]):
@@ -223,4 +224,4 @@ def test_slot_spaces_agree_with_oracle():
             ok_lib = False
         assert ok_oracle == ok_lib, b[:32].hex()
         results.append(ok_lib)
-    assert results == [True, True, True, False, False, False, False, True, False, False]
+    assert results == [True, True, True, False, False, False, False, True, True, False]

@@ -193,7 +193,8 @@ def test_tripwire_layout_and_space_validation():
     """A live allocation whose left redzone would start below address 0 is
     refused under the tripwire model (and accepted under exact bounds);
     slot spaces other than global/shared/local, spaces on slots the program
-    does not have, and LOADs from shared or local slots are malformed IR."""
+    does not have, and LOADs from local slots are malformed IR (LOADs from
+    shared slots read shared memory back)."""
     ir = W.f1_program(32)
     tab = [[(16, 64, 0, 0, 32), (LB, 64, 0, 0, 0)]]
     wl = K.simple_workload(ir, [[1, 1, 1, 8, 1, 1]], tab)
@@ -206,10 +207,13 @@ def test_tripwire_layout_and_space_validation():
         p.access(0, p.const(0, 32), elem=4)
         with pytest.raises(O.OracleError):
             O.validate(p.to_bytes())
-    p = Program(n_slots=2, spaces=[0, 1])
+    p = Program(n_slots=2, spaces=[0, 2])
     p.load(1, p.const(0, 32), elem=4)
     with pytest.raises(O.OracleError):
         O.validate(p.to_bytes())
+    p = Program(n_slots=2, spaces=[0, 1])
+    p.load(1, p.const(0, 32), elem=4)
+    O.validate(p.to_bytes())
     p = Program(n_slots=2, spaces=[2, 1])
     p.access(0, p.const(0, 32), elem=4)
     p.access(1, p.const(0, 32), elem=4)
