@@ -12,8 +12,10 @@ allocation tables are resident before the timed region.
 Prints one JSON line: checked thread-accesses/s (value), inputs/s, the
 roofline of the dominant kernel (timed with HIP events on the job's stream),
 the same batch in the other thread-set modes (inputs/s), the other plain
-workloads (1-D affine, CSR gather), the batched and served forms, and the
-oracle's throughput on bounded samples of the same workload.
+workloads (1-D affine, CSR gather), the tripwire detector model, the
+closed-loop fuzzing campaigns, the pruning measurement (programs as written
+against pruned), the batched and served forms, and the oracle's throughput on
+bounded samples of the same workload.
 """
 from __future__ import annotations
 
@@ -110,9 +112,10 @@ def parse(argv=None):
     ap.add_argument("--no-plain", action="store_true", help="skip the CSR and 1-D sub-results")
     ap.add_argument("--served-seconds", type=float, default=35.0,
                     help="length of the served stream (the first 5 s are warm-up)")
-    ap.add_argument("--workload", default="stencil", choices=["stencil", "csr", "affine1d", "batched", "served", "tripwire", "fuzz"],
+    ap.add_argument("--workload", default="stencil",
+                    choices=["stencil", "csr", "affine1d", "batched", "served", "tripwire", "fuzz", "pruning"],
                     help="stencil: the benchmark line (with every sub-result unless switched off); "
-                         "csr / affine1d / batched / served: that form alone")
+                         "any other: that sub-result alone")
     return ap.parse_args(argv)
 
 
@@ -300,6 +303,52 @@ def bench_tripwire(args, ctx):
         r["redzone_bytes"] = 16 if name == "affine1d" else 32
         res[name] = r
         progress(f"tripwire {name} done")
+    return res
+
+
+def bench_pruning(args, ctx):
+    """The paper's AXIPrune measurement (Section 7.4: ep, hist) on the three
+    pruning kernels: each loaded as written (nothing removed: the data math
+    runs, the barriers split the blocks into phases) and pruned, checked over
+    the whole grid and under the PREX sweep; inputs/s of each, the gain, and
+    the instructions executed per thread as written and pruned (counted by
+    the oracle on a sample of the same inputs).  Both loads give the same
+    records (the parity tests compare both with the oracle)."""
+    from oracle import oracle as O
+    res = {}
+    steps = max(4, args.steps)
+    for kind in ("ep", "hist", "tile"):
+        wl = W.pruning_config(kind)
+        n = wl.n_inputs
+        r = {"inputs": n, "threads_per_step": int((wl.launch[:, 0].astype(np.int64) * wl.launch[:, 3]).sum())}
+        for mode, mkey in ((W.MODE_FULL, "full"), (W.MODE_PREX, "prex")):
+            per = {}
+            for no_prune, key in ((True, "as_written"), (False, "pruned")):
+                dw = ckc.DeviceWorkload(ctx, wl, no_prune=no_prune)
+                try:
+                    out = out_buffers(n, dw.info["n_accesses"])
+                    # two warm-up steps: jobs overlap, so two jobs' buffers are made before timing
+                    s, t, st = timed(ctx, dw, out, mode, 2, steps)
+                except ckc.CkcError as e:
+                    per[key] = {"refused": str(e)}
+                    continue
+                finally:
+                    dw.close()
+                per[key] = {"inputs_per_s": n / s, "ms_per_step": s * 1e3,
+                            "accesses_per_s": int(st["accesses_checked"].sum()) / s,
+                            "n_instr_live": int(dw.info["n_instr_live"]), "cls": int(dw.info["cls"]),
+                            "kernel_ms": kernel_ms(t)}
+            if "inputs_per_s" in per.get("pruned", {}) and "inputs_per_s" in per.get("as_written", {}):
+                per["gain"] = per["pruned"]["inputs_per_s"] / per["as_written"]["inputs_per_s"]
+            r[mkey] = per
+        ex = O.check(wl.subset(np.arange(8)), executed=True, nthreads=min(16, os.cpu_count() or 1))["executed"]
+        lanes = float((wl.launch[:8, 0].astype(np.int64) * wl.launch[:8, 3]).sum())
+        r["executed_per_thread"] = {"as_written": float(ex[:, 0].sum()) / lanes,
+                                    "pruned": float(ex[:, 1].sum()) / lanes,
+                                    "reduction": 1.0 - float(ex[:, 1].sum()) / float(ex[:, 0].sum()),
+                                    "sample": "first 8 inputs, counted by the oracle"}
+        res[kind] = r
+        progress(f"pruning {kind} done")
     return res
 
 
@@ -577,6 +626,9 @@ def main():
         if args.workload == "tripwire":
             print(json.dumps(bench_tripwire(args, ctx)))
             return
+        if args.workload == "pruning":
+            print(json.dumps(bench_pruning(args, ctx)))
+            return
         if args.workload in ("csr", "affine1d"):
             print(json.dumps(bench_plain(args, ctx, args.workload)))
             return
@@ -596,6 +648,7 @@ def main():
         if not args.no_plain:
             result["tripwire"] = bench_tripwire(args, ctx)
             result["fuzz"] = bench_fuzz(args, ctx, with_cpu=not args.no_cpu_baseline)
+            result["pruning"] = bench_pruning(args, ctx)
         if not args.no_batched:
             b = bench_batched(args, ctx)
             progress("batched done")

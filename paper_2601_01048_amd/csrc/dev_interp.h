@@ -574,7 +574,26 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
     const bool act = l < cur_lanes;
     c_dprog* Pi = (c_dprog*)in.prog;
     const uint32_t pfl = Pi->pflags;
-    if (a.capture && !(pfl & PF_CAPTURE)) continue;  // the capture pass runs only these inputs
+    if (a.capture) {
+      // the capture pass runs only the tiles that hold the thread of some
+      // first violation (lanes are in thread order in every thread set, and
+      // a tile holds whole blocks); every lane decides alike
+      if (!(pfl & PF_CAPTURE)) continue;
+      const uint64_t l0 = (t - tb) * TILE;
+      const uint64_t l1 = (l0 + TILE < cur_lanes ? l0 + TILE : cur_lanes) - 1;
+      Thr T0, T1;
+      if (cur_mode == CKC_FULL) { decode_full(dec, l0, T0); decode_full(dec, l1, T1); }
+      else { decode_lane(cur_mode, cur_L, cur_L[6], l0, T0); decode_lane(cur_mode, cur_L, cur_L[6], l1, T1); }
+      const ckc_record* rec = a.recs + in.rec_base;
+      const uint32_t ls = in.L1 + in.L2;
+      bool hit = false;
+      for (uint32_t q = 0; q < Pi->n_accesses && !hit; q++) {
+        if (rec[q].count == 0) continue;
+        const uint64_t g = rec[q].first_key >> ls;
+        hit = g >= T0.gtid && g <= T1.gtid;
+      }
+      if (!hit) continue;
+    }
     Thr T;
     if (cur_mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
     else decode_lane(cur_mode, cur_L, cur_L[6], act ? l : 0, T);

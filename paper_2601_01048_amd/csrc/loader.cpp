@@ -853,7 +853,8 @@ struct Analyzer {
     uint64_t total = 0;
     for (int i = 0; i < n_instr; i++) {
       const Ins& I = ins[i];
-      if (!I.live || (I.op != CKC_OP_ACCESS && I.op != CKC_OP_LOAD)) continue;
+      // every checked access is a trace entry: a STORE too (lowered to an ACCESS)
+      if (!I.live || (I.op != CKC_OP_ACCESS && I.op != CKC_OP_LOAD && I.op != CKC_OP_STORE)) continue;
       uint64_t mult = 1;
       for (int p = I.parent; p >= 0; p = ins[p].parent) {
         const Ins& L = ins[p];

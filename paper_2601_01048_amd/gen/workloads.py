@@ -15,6 +15,12 @@ Families (each in an int32 and an int64 form):
   F3  CSR SpMV gather: guarded row, two row_ptr loads, a loop over the row's
       nonzeros loading col_idx[j] and touching val[j] and x[col], then y[row]
 
+and three kernels with data math, shared memory and barriers, the shapes the
+paper's pruning (Section 5.2; Section 7.4's ep and hist) is measured on: an
+EP-like kernel (a chain of exponentials no index reads), a block histogram
+(shared counts no index reads, a barrier) and a tile gather (a data tile in
+shared memory read back as indices: the barrier stays).
+
 Only numpy's PCG64 generator is used; nothing here performs the checking
 arithmetic.  A workload is a plain record of arrays that both the oracle
 wrapper and the GPU binding consume.
@@ -283,6 +289,87 @@ def config3(seed: int = 1003, n_inputs: int = 64, log2_rows: int = 20, mean: int
     return Workload(f"config3_f3_i{w}", f3_program(w), launch, scalars, tables,
                     np.arange(n_inputs, dtype=np.uint32), data, MODE_FULL,
                     meta=dict(seed=seed, nrows=nrows, ncols=ncols, nnz=nnz))
+
+
+def _f2bits(x: float) -> int:
+    import struct
+    return struct.unpack("<q", struct.pack("<d", x))[0]
+
+
+def ep_program(n_exp: int = 8) -> bytes:
+    """EP-like: i = bid*bs + tid; A[i] is read; a chain of n_exp rounds of
+    x = e^(-x/2) * 1.0001 + 0.25 starting from x = i * 2^-20 (the kernel's
+    data math) ends in a write of FTOI(1000 x) to B[i].  No index reads x."""
+    p = Program(n_slots=2)
+    t = p.trunc(p.special("tid.x"))
+    i = p.add(p.mul(p.trunc(p.special("bid.x")), p.trunc(p.special("bdim.x"))), t)
+    p.access(0, i)
+    x = p.fop("FMUL", p.itof(i), p.const(_f2bits(2.0 ** -20), 64))
+    for _ in range(n_exp):
+        x = p.fop("FEXP", p.fop("FMUL", x, p.const(_f2bits(-0.5), 64)))
+        x = p.fop("FADD", p.fop("FMUL", x, p.const(_f2bits(1.0001), 64)), p.const(_f2bits(0.25), 64))
+    p.store(1, i, p.ftoi(p.fop("FMUL", x, p.const(_f2bits(1000.0), 64))))
+    return p.to_bytes()
+
+
+def hist_program(nbins: int = 256) -> bytes:
+    """Block histogram: x = G[bid*bs + tid]; the count of bin x mod nbins in
+    shared memory is read and written back incremented; a barrier; threads
+    below nbins write their bin's count to H[bid*nbins + tid].  The counts
+    reach no index (slots: 0 G data, 1 bins shared, 2 H)."""
+    p = Program(n_slots=3, spaces=[0, 1, 0])
+    t = p.trunc(p.special("tid.x"))
+    b = p.trunc(p.special("bid.x"))
+    g = p.add(p.mul(b, p.trunc(p.special("bdim.x"))), t)
+    k = p.remu(p.load(0, g), nbins)
+    p.store(1, k, p.add(p.load(1, k), 1))
+    p.barrier()
+    with p.if_(p.cmpltu(t, nbins)):
+        p.store(2, p.add(p.mul(b, nbins), t), p.load(1, t))
+    return p.to_bytes()
+
+
+def tile_gather_program() -> bytes:
+    """Tile gather: sh[tid] = G[bid*bs + tid]; a barrier; A[sh[bs - 1 - tid]]:
+    indices read back from shared memory, so the barrier stays (slots: 0 A,
+    1 tile shared, 2 G data)."""
+    p = Program(n_slots=3, spaces=[0, 1, 0])
+    t = p.trunc(p.special("tid.x"))
+    bs = p.trunc(p.special("bdim.x"))
+    g = p.add(p.mul(p.trunc(p.special("bid.x")), bs), t)
+    p.store(1, t, p.load(2, g))
+    p.barrier()
+    p.access(0, p.load(1, p.sub(p.sub(bs, 1), t)))
+    return p.to_bytes()
+
+
+def pruning_config(kind: str, seed: int = 1010, n_inputs: int = 256, g_range=(48, 80), block: int = 256,
+                   n_range=(12000, 20000)) -> Workload:
+    """Inputs of one of the three pruning kernels ("ep", "hist", "tile"):
+    G ~ U{g_range} blocks of ``block`` threads; arrays of n ~ U{n_range}
+    int32 elements (so the last blocks run past some of them); G's data are
+    seeded values in [-64, 40000) shared by every input."""
+    rng = np.random.default_rng(seed)
+    G = rng.integers(g_range[0], g_range[1] + 1, size=n_inputs)
+    n = rng.integers(n_range[0], n_range[1] + 1, size=n_inputs)
+    launch = np.zeros((n_inputs, 6), np.uint32)
+    launch[:, 0], launch[:, 1:3], launch[:, 3], launch[:, 4:6] = G, 1, block, 1
+    nd = int(g_range[1]) * block
+    data = [rng.integers(-64, 40000, size=nd).astype(np.int32)]
+    tables = np.zeros((n_inputs, 3 if kind != "ep" else 2), ALLOC_DTYPE)
+    for i in range(n_inputs):
+        a = alloc(4 * int(n[i]))
+        if kind == "ep":
+            tables[i] = [a, alloc(4 * int(n[i]), base=LOGICAL_BASE + (1 << 36))]
+        elif kind == "hist":
+            tables[i] = [alloc(4 * nd, 1, base=LOGICAL_BASE + (1 << 40)), alloc(4 * 256, base=0x100),
+                         alloc(4 * 256 * int(G[i]) - 4 * int(rng.integers(0, 512)), base=LOGICAL_BASE)]
+        else:
+            tables[i] = [a, alloc(4 * block, base=0x100), alloc(4 * nd, 1, base=LOGICAL_BASE + (1 << 40))]
+    ir = {"ep": ep_program, "hist": hist_program, "tile": tile_gather_program}[kind]()
+    return Workload(f"pruning_{kind}", ir, launch, np.zeros((n_inputs, 0), np.int64), tables,
+                    np.arange(n_inputs, dtype=np.uint32), data, MODE_FULL,
+                    meta=dict(seed=seed, G=G, n=n, block=block))
 
 
 def adjacent_layout(wl: Workload, redzone: int, gap: int = 0) -> Workload:
