@@ -390,13 +390,18 @@ int ckc_check_batch_noalloc(ckc_ctx ctx, const ckc_batch* descs, uint32_t n_desc
  *   something to mutate) by u0, a target (launch dimension u1 mod 6, scalar
  *   u1 mod n_scalars, element u1 mod n_elems) and a kind ((u1 >> 8) mod 4) by
  *   u1, a value by u2:
- *     launch: +1..8, -1..8 (at least 1), 2^(u2 mod 11), 1 + u2 mod 256; void
- *             when the child would leave max_block or max_threads;
- *     scalar: flip bit u2 mod 64, add -16..16, a special value (0, 1, -1, 2,
- *             7, 8, 15, 16, ..., 2^31-1, -2^31, 2^32-1, 2^32, -2^63, 2^63-1),
- *             the 64 bits of u2;
- *     data (int32 elements): add -16..16, a special value (low 32 bits), the
- *             low 32 bits of u2, flip bit u2 mod 32;
+ *     launch: + (1 + u2 mod 8), - (1 + u2 mod 8) (at least 1), 2^(u2 mod 11),
+ *             1 + u2 mod 256; void when the dimension would exceed 2^32 - 1,
+ *             the child's block max_block, its grid 2^32 - 1 blocks or grid x
+ *             block max_threads;
+ *     scalar: flip bit u2 mod 64, add (u2 mod 33) - 16, special value
+ *             number u2 mod 28, the 64 bits of u2;
+ *     data (int32 elements): add (u2 mod 33) - 16, the low 32 bits of special
+ *             value number u2 mod 28, the low 32 bits of u2, flip bit u2 mod 32;
+ *   (kinds in the order listed, all arithmetic wrapping at the element's
+ *   width; the 28 special values in order: 0, 1, -1, 2, 7, 8, 15, 16, 31, 32,
+ *   63, 64, 127, 128, 255, 256, 1023, 1024, 4095, 4096, 65535, 65536,
+ *   2^31-1, -2^31, 2^32-1, 2^32, -2^63, 2^63-1);
  *   the children are checked as one job (mode, detector and caps of the
  *   campaign); a child is novel when its coverage map, bucketed by hit count
  *   as AFL buckets it (1, 2, 3, 4-7, 8-15, 16-31, 32-127, 128+: one bit each),

@@ -43,11 +43,12 @@ def run_both(ir, launches, tables, model, n_acc, n_sites, spaces=(), scalars=Non
 
 @pytest.mark.parametrize("rz_a,rz_b,gap,b_flags", [
     (0, 0, 0, 0), (4, 0, 0, 0), (8, 8, 0, 0), (16, 4, 12, 0), (64, 64, 0, 0),
-    (3, 5, 1, 0), (8, 0, 0, W.ALLOC_FREED), (0, 0, 40, W.ALLOC_FREED)])
+    (3, 5, 1, 0), (8, 0, 0, W.ALLOC_FREED), (0, 0, 40, W.ALLOC_FREED), (0, 8, 0, W.ALLOC_FREED)])
 def test_f1_shadow_brute_force(rz_a, rz_b, gap, b_flags):
     """A[gid-1], A[gid], B[gid+1], B[gid+2] over grids past the arrays' ends:
     underflow of A at gid 0, overflows of A into its redzone, B's redzone and
-    B itself, overflows of B past its own redzone; B freed in two layouts."""
+    B itself, overflows of B past its own redzone; B freed in three layouts
+    (in the last, A's overflow lands in the freed B's redzone)."""
     ir = W.f1_program(32)
     launches, tables = [], []
     for G, bs, n in ((1, 32, 20), (2, 32, 50), (3, 64, 100), (4, 16, 30)):
