@@ -87,7 +87,10 @@ enum ckc_status_flags {
    * condition under which the Section 5.1.1 Theorem makes a representative set
    * flag exactly the (access, kind) pairs of the whole grid for affine,
    * unguarded programs.  Never set in CKC_FULL / CKC_FULL_ENDPOINTS. */
-  CKC_ST_VERTEX_EXACT = 1
+  CKC_ST_VERTEX_EXACT = 1,
+  /* The library skipped part of this input's evaluation (an internal
+   * inconsistency; never expected): its results are incomplete. */
+  CKC_ST_INTERNAL = 0x80000000u
 };
 
 /* violation kinds (ckc_record.kinds / first_kind) */

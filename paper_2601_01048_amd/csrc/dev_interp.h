@@ -26,6 +26,10 @@ __device__ __forceinline__ dins ld_ins(c_dins* I, uint32_t pc) {
 }
 
 typedef const __attribute__((address_space(4))) ckc_alloc c_alloc;
+// The rows form of an input, read through scalar loads.
+typedef const __attribute__((address_space(4))) drows c_drows;
+typedef const __attribute__((address_space(4))) REnt c_rent;
+typedef const __attribute__((address_space(4))) RForm c_rform;
 // Loaded data through the global address space (global rather than flat loads).
 typedef const __attribute__((address_space(1))) int32_t g_i32;
 typedef const __attribute__((address_space(1))) int64_t g_i64;
@@ -58,20 +62,27 @@ struct GBody {
   uint8_t var[NREG];       // symbolic walk: variable of each register (0xFF uniform)
 };
 
-struct GenLds {
+// LDS of the whole-thread pass (and what every pass counts into): coverage
+// counters of the current input, its status totals, the expanded loop's
+// per-wavefront sums and contiguity (the least and greatest start minus prefix
+// of the wavefront's threads with iterations, flags 1: some thread has
+// iterations, 2: some step is not 1), the tile's shared-memory layout (words
+// per block instance, blocks per tile, offset of each shared slot).
+struct WtLds {
   uint32_t sites[MAX_SITES_LDS];
   unsigned long long wsum[TILE / 64];
   unsigned long long acc_checked, hangs, faults;
+  unsigned long long wemin[TILE / 64], wemax[TILE / 64];
+  uint32_t wflag[TILE / 64];
+  uint32_t sh_w, sh_nbt, sh_off[MAX_SLOTS];
+};
+// The interpreter's passes add the state of the expanded loops' body passes.
+struct GenLds : WtLds {
   unsigned long long pref[TILE + 1];  // trip-count prefix of the tile's threads (expanded loop)
   GBody gb;                           // gather entries of the current input (body pass)
   unsigned long long xstart[TILE], xstep[TILE];  // loop start and step of the tile's threads (gather pass)
   uint16_t own[PIECE_LDS];            // owner thread of each iteration of the current piece
   uint16_t omax[TILE / 64];           // owner-map scan: per-wavefront maxima
-  // whole-thread pass: per wavefront, the least and greatest start minus
-  // prefix of its threads with iterations, and flags (1: some thread has
-  // iterations, 2: some step is not 1), for the tile's contiguity
-  unsigned long long wemin[TILE / 64], wemax[TILE / 64];
-  uint32_t wflag[TILE / 64];
   // gather pass: the violations of the current input's gather entries,
   // merged here and flushed per input
   unsigned long long vfk[MAX_GENT], vcnt[MAX_GENT];
@@ -84,9 +95,6 @@ struct GenLds {
   unsigned long long rstart[RUN_TILES + 1];
   unsigned long long rend, rpend;
   uint32_t rn;
-  // shared memory of the tile's blocks: words per block instance, blocks per
-  // tile, offset of each shared slot within an instance
-  uint32_t sh_w, sh_nbt, sh_off[MAX_SLOTS];
 };
 
 // Modes of the interpreter: M_MAIN runs whole threads (an expanded loop is
@@ -145,7 +153,7 @@ struct Ctx {
 // Coverage of site s by the lanes of `mask`: one LDS add per wavefront.  `sat`
 // (wavefront-uniform) marks sites below 64 whose workgroup count has reached
 // the saturation value 255, after which counting them changes nothing.
-__device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint64_t& sat, uint32_t s, uint64_t mask) {
+__device__ __forceinline__ void count_site(WtLds& S, const Ctx& C, uint64_t& sat, uint32_t s, uint64_t mask) {
   if (s == NOSITE || mask == 0 || C.capture) return;
   if (s < 64 && ((sat >> s) & 1u)) return;
   const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
@@ -166,6 +174,74 @@ __device__ __forceinline__ void count_site(GenLds& S, const Ctx& C, uint64_t& sa
 #define RPUT(i, v) (R[(uint32_t)(i) * TILE + threadIdx.x] = (v))
 
 constexpr uint32_t PIECE = PIECE_LDS;
+
+// The whole-thread pass at an expanded loop: every thread of the workgroup
+// calls this exactly once per tile, with its capped trip count (0 for lanes
+// that do not reach the loop), start and step.  Stores the prefix of the trip
+// counts over the tile and the thread's loop state, and per tile the total,
+// the pieces, the input and whether the tile is contiguous (every thread with
+// iterations has step 1 and the same start minus prefix d: iteration g of the
+// tile then has counter d + g).  `liv(q)` gives the thread's live-in q.
+template <class LIV>
+__device__ __forceinline__ void expand_record(WtLds& S, const Ctx& C, uint64_t cnt, uint64_t s0, uint64_t stp,
+                                              LIV liv) {
+  c_dprog* P = C.P;
+  const uint32_t tid = threadIdx.x, wv = tid / 64;
+  uint64_t incl = cnt;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
+    if ((int)lane_id() >= o) incl += u;
+  }
+  // per wavefront, start minus the prefix within the wavefront
+  const uint64_t e = s0 - (incl - cnt);
+  const uint64_t emin = wave_min64(cnt ? e : ~0ull), emax = ~wave_min64(cnt ? ~e : ~0ull);
+  const uint64_t has = __ballot(cnt != 0), nonunit = __ballot(cnt != 0 && stp != 1);
+  if (lane_id() == 63) {
+    S.wsum[wv] = incl;
+    S.wemin[wv] = emin;
+    S.wemax[wv] = emax;
+    S.wflag[wv] = (has ? 1u : 0u) | (nonunit ? 2u : 0u);
+  }
+  __syncthreads();
+  uint64_t wpre = 0;
+  for (uint32_t q = 0; q < wv; q++) wpre += S.wsum[q];
+  const uint64_t pre = wpre + incl - cnt;
+  bool contig = true, any = false;
+  uint64_t dref = 0, sum = 0;
+  for (uint32_t q = 0; q < TILE / 64; q++) {
+    const uint32_t f = S.wflag[q];
+    if (f & 1u) {
+      const uint64_t dq = S.wemin[q] - sum;
+      if ((f & 2u) || S.wemin[q] != S.wemax[q] || (any && dq != dref)) contig = false;
+      dref = dq;
+      any = true;
+    }
+    sum += S.wsum[q];
+  }
+  contig = contig && any;
+  const uint64_t l = C.lane0 + tid;
+  C.xs[l] = pre;
+  if (cnt) {
+    // gather bodies of contiguous tiles keep no start and step (the gather
+    // pass forms them from d)
+    if (!(contig && P->body_gather && !C.tw)) {
+      C.xs[C.xn + l] = s0;
+      C.xs[2 * C.xn + l] = stp;
+    }
+    const uint32_t nl = P->n_livein;
+    for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = liv(q);
+  }
+  if (tid == TILE - 1) {
+    const uint64_t tot = pre + cnt;
+    C.xtot[C.xt] = tot;
+    // the tripwire model is checked by the interpreted body form
+    (P->body_gather && !C.tw ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
+    C.xin[C.xt] = C.input;
+    C.xd[2 * C.xt] = dref;
+    C.xd[2 * C.xt + 1] = contig ? 1ull : 0ull;
+  }
+  __syncthreads();
+}
 
 // Runs the program for the wavefront from pc0 until pc_end (exclusive) or the
 // end.  M_MAIN: whole threads; at the expanded loop each lane's trip count,
@@ -324,66 +400,8 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
         const uint64_t rn = nt < cap ? nt : cap;
         const bool hg = act && nt > cap;
         if (MODE == M_MAIN && (fl & DI_EXPAND) && C.xs != nullptr) {
-          // every wavefront of the workgroup arrives here exactly once per tile:
-          // prefix of the trip counts over the tile, thread state to memory
-          const uint32_t tid = threadIdx.x, wv = tid / 64;
-          const uint64_t cnt = act ? rn : 0;
-          uint64_t incl = cnt;
-          for (int o = 1; o < 64; o <<= 1) {
-            const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
-            if ((int)lane_id() >= o) incl += u;
-          }
-          // contiguous tile: every thread with iterations has step 1 and the
-          // same start - prefix d (iteration g of the tile has counter d + g);
-          // per wavefront, start minus the prefix within the wavefront
-          const uint64_t e = (uint64_t)s0 - (incl - cnt);
-          const uint64_t emin = wave_min64(cnt ? e : ~0ull), emax = ~wave_min64(cnt ? ~e : ~0ull);
-          const uint64_t has = __ballot(cnt != 0), nonunit = __ballot(cnt != 0 && (uint64_t)stp != 1);
-          if (lane_id() == 63) {
-            S.wsum[wv] = incl;
-            S.wemin[wv] = emin;
-            S.wemax[wv] = emax;
-            S.wflag[wv] = (has ? 1u : 0u) | (nonunit ? 2u : 0u);
-          }
-          __syncthreads();
-          uint64_t wpre = 0;
-          for (uint32_t q = 0; q < wv; q++) wpre += S.wsum[q];
-          const uint64_t pre = wpre + incl - cnt;
-          bool contig = true, any = false;
-          uint64_t dref = 0, sum = 0;
-          for (uint32_t q = 0; q < TILE / 64; q++) {
-            const uint32_t f = S.wflag[q];
-            if (f & 1u) {
-              const uint64_t dq = S.wemin[q] - sum;
-              if ((f & 2u) || S.wemin[q] != S.wemax[q] || (any && dq != dref)) contig = false;
-              dref = dq;
-              any = true;
-            }
-            sum += S.wsum[q];
-          }
-          contig = contig && any;
-          const uint64_t l = C.lane0 + tid;
-          C.xs[l] = pre;
-          if (cnt) {
-            // gather bodies of contiguous tiles keep no start and step (the
-            // gather pass forms them from d)
-            if (!(contig && P->body_gather && !C.tw)) {
-              C.xs[C.xn + l] = (uint64_t)s0;
-              C.xs[2 * C.xn + l] = (uint64_t)stp;
-            }
-            const uint32_t nl = P->n_livein;
-            for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = RGET(ufirst(P->livein[q]));
-          }
-          if (tid == TILE - 1) {
-            const uint64_t tot = pre + cnt;
-            C.xtot[C.xt] = tot;
-            // the tripwire model is checked by the interpreted body form
-            (P->body_gather && !C.tw ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
-            C.xin[C.xt] = C.input;
-            C.xd[2 * C.xt] = dref;
-            C.xd[2 * C.xt + 1] = contig ? 1ull : 0ull;
-          }
-          __syncthreads();
+          expand_record(S, C, act ? rn : 0, (uint64_t)s0, (uint64_t)stp,
+                        [&](uint32_t q) { return RGET(ufirst(C.P->livein[q])); });
           // the loop is left at once: lanes that run it to the end pass its
           // exit, lanes over the cap stop
           count_site(S, C, sat, D.s1, __ballot(act && !hg));
@@ -446,7 +464,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
   }
 }
 
-__device__ void flush_input(GenLds& S, const KArgs& a, uint32_t input, uint32_t n_sites) {
+__device__ void flush_input(WtLds& S, const KArgs& a, uint32_t input, uint32_t n_sites) {
   __syncthreads();
   const dinput& in = a.inputs[input];
   uint32_t* cnt = a.counts + in.cnt_base;
@@ -514,7 +532,7 @@ __device__ __forceinline__ void lane_zero_totals(Lane& ln) {
 }
 // Adds the wavefront's totals to the workgroup's and clears them (called by
 // the whole workgroup before a flush).
-__device__ __forceinline__ void add_lane_totals(GenLds& S, Lane& ln) {
+__device__ __forceinline__ void add_lane_totals(WtLds& S, Lane& ln) {
   const uint64_t f = wave_sum64(ln.faults), h = wave_sum64(ln.hangs), n = wave_sum64(ln.acc);
   if (lane_id() == 0) {
     if (f) atomicAdd(&S.faults, (unsigned long long)f);
@@ -637,6 +655,325 @@ __global__ void __launch_bounds__(TILE, 4) eval_generic_kernel(KArgs a) {
     add_lane_totals(S, ln);
     flush_input(S, a, cur, cur_sites);
   }
+}
+
+// ---------------------------------------------------------------------------
+// The rows-form kernel: the whole-thread pass of jobs whose programs all take
+// the rows form (PF_ROWS; the plan kernel has reduced each input's part
+// outside the expanded loop's body to a list of entries, read here through
+// scalar loads).  One lane per thread, tiles of 256 threads as in the
+// interpreter, with no register file and no instruction dispatch.
+struct RowsLds {
+  uint32_t sites[MAX_SITES_LDS];       // coverage of the current input
+  unsigned long long wsum[TILE / 64];  // expanded loop: per wavefront, its trip-count total,
+  unsigned long long wd[TILE / 64];    // the start minus prefix d of its threads with iterations,
+  uint32_t wflag[TILE / 64];           // 1: some thread has iterations, 2: they are not contiguous
+  unsigned long long acc_checked, hangs;
+  unsigned long long item_slot;
+};
+
+// Per-thread values: the coordinate-class sums and the loaded values X[1..4].
+struct RSlice {
+  uint64_t base[MAX_RCLS];
+  uint64_t x[RV_MAXLOAD];
+};
+__device__ __forceinline__ uint64_t rsel4(const uint64_t* v, uint32_t k) {
+  return k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
+}
+__device__ __forceinline__ void rset4(uint64_t* v, uint32_t k, uint64_t x) {
+  if (k == 0) v[0] = x;
+  else if (k == 1) v[1] = x;
+  else if (k == 2) v[2] = x;
+  else v[3] = x;
+}
+__device__ __forceinline__ uint64_t coord(const Thr& T, int d) {
+  return d < 3 ? (uint64_t)T.t[d] : (uint64_t)T.b[d - 3];
+}
+
+// A form of the rows form for one thread at width w (fields uniform: scalar
+// loads); a coordinate form outside the classes (more distinct coefficient
+// vectors than classes) is summed from the thread's coordinates.
+__device__ __forceinline__ uint64_t rform(c_rform& f, const RSlice& X, const Thr& T, uint32_t w) {
+  const uint32_t var = f.var;
+  uint64_t v = (uint64_t)f.off;
+  if (var == RV_COORD) {
+    const uint32_t cls = f.cls;
+    if (cls != RCLS_NONE) {
+      v += rsel4(X.base, cls);
+    } else {
+      for (int d = 0; d < 6; d++) v += (uint64_t)f.c[d] * coord(T, d);
+    }
+  } else if (var != RV_UNI) {
+    v += (uint64_t)f.c[0] * rsel4(X.x, var - 1);
+  }
+  return narrow(v, w);
+}
+
+// The comparisons a rows-form guard takes (CMPEQ..CMPLEU at width w).
+__device__ __forceinline__ bool rcmp(uint32_t op, uint32_t w, uint64_t x, uint64_t y) {
+  x = narrow(x, w);
+  y = narrow(y, w);
+  const uint64_t m = w == 32 ? 0xFFFFFFFFull : ~0ull;
+  const uint64_t ux = x & m, uy = y & m;
+  const int64_t sx = (int64_t)x, sy = (int64_t)y;
+  switch (op) {
+    case CKC_OP_CMPEQ: return ux == uy;
+    case CKC_OP_CMPNE: return ux != uy;
+    case CKC_OP_CMPLTS: return sx < sy;
+    case CKC_OP_CMPLES: return sx <= sy;
+    case CKC_OP_CMPLTU: return ux < uy;
+    default: return ux <= uy;  // CMPLEU
+  }
+}
+// Trip counts of steps other than 1 (64-bit division, out of line).
+__device__ __noinline__ uint64_t trip_count_div(int64_t s, int64_t e, int64_t st) { return trip_count(s, e, st); }
+__device__ __forceinline__ uint64_t rtrips(int64_t s, int64_t e, int64_t st) {
+  if (st == 1) return s < e ? (uint64_t)e - (uint64_t)s : 0;
+  return trip_count_div(s, e, st);
+}
+
+// Adds the visits of the lanes of `mask` to site s (one LDS add per wavefront).
+__device__ __forceinline__ void rsite(RowsLds& S, const Ctx& C, uint32_t s, uint64_t mask) {
+  if (s == NOSITE || mask == 0) return;
+  const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+  if (lane_id() == leader) {
+    const uint32_t c = (uint32_t)__popcll(mask);
+    if (s < MAX_SITES_LDS) atomicAdd(&S.sites[s], c);
+    else if (C.gcnt[s] < 255u) atomicAdd(&C.gcnt[s], c);
+  }
+}
+
+// Inclusive prefix sum over the wavefront (32-bit values).
+__device__ __forceinline__ uint32_t wave_incl32(uint32_t v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(v, o, 64);
+    if ((int)lane_id() >= o) v += u;
+  }
+  return v;
+}
+
+// The expanded loop of one tile (every thread of the workgroup, once): the
+// tile's prefix of the capped trip counts, the threads' loop state, and per
+// tile the total, the pieces, the input and whether the tile is contiguous
+// (every thread with iterations has step 1 and the same start minus prefix d:
+// iteration g of the tile then has counter d + g).  Caps below 2^24 keep the
+// tile's sums in 32 bits.
+__device__ __forceinline__ void rows_expand(RowsLds& S, const Ctx& C, c_drows& G, uint64_t cnt, uint64_t s0,
+                                            uint64_t stp) {
+  c_dprog* P = C.P;
+  const uint32_t tid = threadIdx.x, wv = tid / 64;
+  uint64_t incl;
+  if (C.cap0 < (1ull << 24)) incl = wave_incl32((uint32_t)cnt);
+  else {
+    incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t u = __shfl_up((unsigned long long)incl, o, 64);
+      if ((int)lane_id() >= o) incl += u;
+    }
+  }
+  const uint64_t has = __ballot(cnt != 0);
+  // d of the wavefront: its first thread with iterations; every other one
+  // must agree
+  const uint64_t e = s0 - (incl - cnt);
+  uint64_t dw = 0;
+  bool split = stp != 1;
+  if (has) {
+    dw = readlane64(e, (int)(__ffsll((unsigned long long)has) - 1));
+    split = split || __ballot(cnt != 0 && e != dw) != 0;
+  }
+  if (lane_id() == 63) {
+    S.wsum[wv] = incl;
+    S.wd[wv] = dw;
+    S.wflag[wv] = (has ? 1u : 0u) | (split ? 2u : 0u);
+  }
+  __syncthreads();
+  uint64_t wpre = 0, tot = 0, dref = 0;
+  bool contig = true, any = false;
+  for (uint32_t q = 0; q < TILE / 64; q++) {
+    const uint32_t f = S.wflag[q];
+    if (q == wv) wpre = tot;
+    if (f & 1u) {
+      const uint64_t dq = S.wd[q] - tot;
+      if ((f & 2u) || (any && dq != dref)) contig = false;
+      dref = dq;
+      any = true;
+    }
+    tot += S.wsum[q];
+  }
+  contig = contig && any;
+  const uint64_t pre = wpre + incl - cnt;
+  const uint64_t l = C.lane0 + tid;
+  C.xs[l] = pre;
+  if (cnt) {
+    if (!(contig && P->body_gather)) {
+      C.xs[C.xn + l] = s0;
+      C.xs[2 * C.xn + l] = stp;
+    }
+    const uint32_t nl = P->n_livein;
+    for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = G.livein[q];
+  }
+  if (tid == TILE - 1) {
+    C.xtot[C.xt] = tot;
+    (P->body_gather ? C.xpg : C.xpb)[C.xt] = (tot + PIECE - 1) / PIECE;
+    C.xin[C.xt] = C.input;
+    C.xd[2 * C.xt] = dref;
+    C.xd[2 * C.xt + 1] = contig ? 1ull : 0ull;
+  }
+  __syncthreads();
+}
+
+// One thread in the rows form: the same sites, records, status and
+// expanded-loop state as the interpreter's whole-thread pass.
+__device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G, const Thr& T, bool act,
+                                            uint64_t& acc, uint64_t& hangs) {
+  RSlice X;
+  const uint32_t ncls = G.ncls;
+#pragma unroll
+  for (uint32_t c = 0; c < MAX_RCLS; c++) {
+    uint64_t v = 0;
+    if (c < ncls)
+#pragma unroll
+      for (int d = 0; d < 6; d++) {
+        const uint64_t cf = (uint64_t)G.cc[c][d];
+        if (cf) v += cf * coord(T, d);
+      }
+    X.base[c] = v;
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < RV_MAXLOAD; q++) X.x[q] = 0;
+  const uint64_t key = T.gtid << C.Lsum;
+  bool on = act, alive = act;
+  const uint32_t n = G.n;
+  for (uint32_t q = 0; q < n; q++) {
+    c_rent& E = G.e[q];
+    const uint32_t kind = E.kind, w = E.w;
+    if (kind == RE_GUARD) {
+      const bool p = on && rcmp(E.op, w, rform(E.a, X, T, w), rform(E.b, X, T, w));
+      rsite(S, C, E.s0, __ballot(p));
+      rsite(S, C, E.s1, __ballot(on && !p));
+      on = p;
+    } else if (kind == RE_ENDG) {
+      on = alive;
+    } else if (kind == RE_LOOP) {
+      const uint64_t stp = E.step;
+      const uint64_t s0 = rform(E.a, X, T, w);
+      const int64_t e0 = (int64_t)rform(E.b, X, T, w);
+      const uint64_t nt = on ? rtrips((int64_t)s0, e0, (int64_t)stp) : 0;
+      const bool hg = on && nt > C.cap0;
+      rows_expand(S, C, G, on ? (nt < C.cap0 ? nt : C.cap0) : 0, s0, stp);
+      rsite(S, C, E.s1, __ballot(on && !hg));
+      if (hg) {
+        on = alive = false;
+        hangs++;
+      }
+    } else {  // ACCESS, LOAD
+      const uint32_t lg = E.lg, dst = E.dst;
+      c_alloc& A = C.tab[E.slot];
+      const int64_t idx = (int64_t)rform(E.a, X, T, w);
+      const uint32_t kd = on ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
+      acc += on ? 1u : 0u;
+      rsite(S, C, E.s0, __ballot(on));
+      if (__ballot(kd != 0)) merge_violation(C.rec + E.acc, kd, key);
+      if (dst) {
+        uint64_t v = 0;
+        if (on && kd == 0)
+          v = lg == 2 ? (uint64_t)(int64_t)((g_i32*)A.data)[idx] : (uint64_t)((g_i64*)A.data)[idx];
+        rset4(X.x, dst - 1, v);
+      }
+    }
+  }
+}
+
+// Coverage and status of the current input into its global counters (the
+// whole workgroup).
+__device__ void flush_rows(RowsLds& S, const KArgs& a, uint32_t input, uint32_t n_sites, uint64_t& acc,
+                           uint64_t& hangs) {
+  const uint64_t n = wave_sum64(acc), h = wave_sum64(hangs);
+  if (lane_id() == 0) {
+    if (n) atomicAdd(&S.acc_checked, (unsigned long long)n);
+    if (h) atomicAdd(&S.hangs, (unsigned long long)h);
+  }
+  acc = 0;
+  hangs = 0;
+  __syncthreads();
+  const dinput& in = a.inputs[input];
+  uint32_t* cnt = a.counts + in.cnt_base;
+  const uint32_t ns = n_sites < (uint32_t)MAX_SITES_LDS ? n_sites : (uint32_t)MAX_SITES_LDS;
+  for (uint32_t s = threadIdx.x; s < ns; s += TILE) {
+    const uint32_t c = S.sites[s];
+    if (c) {
+      if (cnt[s] < 255u) atomicAdd(&cnt[s], c < 255u ? c : 255u);
+      S.sites[s] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    ckc_input_status* st = a.status + input;
+    if (S.acc_checked) atomicAdd((unsigned long long*)&st->accesses_checked, S.acc_checked);
+    if (S.hangs) atomicAdd((unsigned long long*)&st->hang_lanes, S.hangs);
+    S.acc_checked = 0;
+    S.hangs = 0;
+  }
+  __syncthreads();
+}
+
+template <uint32_t SK>
+__global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
+  __shared__ RowsLds S;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t total = a.js->total_tiles[PATH_GENERIC];
+  if (total == 0) return;
+  Sched<SK> sc;
+  sched_init(sc, a, total);
+  if (SK == CKC_SCHED_BLOCKED && sc.cur >= sc.end) return;
+  c_input* ins = (c_input*)a.inputs;
+  c_u32* order = (c_u32*)a.order;
+  for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
+  if (tid == 0) { S.acc_checked = 0; S.hangs = 0; }
+  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0;
+  uint64_t tb = 0, cur_end = 0, cur_lanes = 0, acc = 0, hangs = 0;
+  uint32_t cur_L[7] = {0, 0, 0, 0, 0, 0, 0};
+  Dec dec;
+  for (;;) {
+    __syncthreads();
+    const uint64_t t = sched_next(sc, &a.js->next_tile[PATH_GENERIC], &S.item_slot);
+    if (t == ~0ull) break;
+    if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
+      pos = pos_of_tile(ins, order, a.n_inputs, PATH_GENERIC, pos, cur_end, t);
+      const uint32_t i = order[pos];
+      if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs);
+      cur = i;
+      cur_sites = ((c_dprog*)a.inputs[i].prog)->n_sites;
+      tb = ins[i].tile_begin[PATH_GENERIC];
+      cur_end = tb + ins[i].n_tiles[PATH_GENERIC];
+      for (int q = 0; q < 6; q++) cur_L[q] = ins[i].launch[q];
+      cur_L[6] = ins[i].aux;
+      cur_mode = ins[i].mode;
+      cur_lanes = ins[i].lanes;
+      dec_make(dec, cur_L);
+    }
+    const uint32_t i = cur;
+    c_input& in = ins[i];
+    c_dprog* Pi = (c_dprog*)in.prog;
+    c_drows* G = (c_drows*)in.trace;
+    if (!(Pi->pflags & PF_ROWS) || in.detector || in.xstate == 0 || in.trace == 0 || !G->ok) {
+      // not reached: the host takes this kernel only when every program passes
+      // the walk; the input's status says so rather than a silent gap
+      if (tid == 0) atomicOr(&a.status[i].flags, (uint32_t)CKC_ST_INTERNAL);
+      continue;
+    }
+    const uint64_t l = (t - tb) * TILE + tid;
+    const bool act = l < cur_lanes;
+    Thr T;
+    if (cur_mode == CKC_FULL) decode_full(dec, act ? l : 0, T);
+    else decode_lane(cur_mode, cur_L, cur_L[6], act ? l : 0, T);
+    Ctx C;
+    ctx_init(C, a, in, i, T);
+    C.lane0 = (t - tb) * TILE;
+    C.xt = in.xt_begin + (t - tb);
+    rows_thread(S, C, *G, T, act, acc, hangs);
+  }
+  if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs);
 }
 
 // Exclusive scan, in place, of the per-tile piece counts of expanded loops

@@ -437,8 +437,241 @@ __device__ uint32_t vertex_flag(const dprog* P, const dinput& in, const int64_t*
   return bad ? 0u : 1u;
 }
 
+__device__ __forceinline__ bool is_div_op(uint32_t op) {
+  return op == CKC_OP_DIVS || op == CKC_OP_DIVU || op == CKC_OP_REMS || op == CKC_OP_REMU;
+}
+
+// State of the rows form's symbolic walk: each register's form (lane j < 7
+// of the wavefront holds component j: the constant part, then the
+// coefficients), the kind of its form and the width it is exact at, the last
+// comparison of varying forms.
+struct RowWalk {
+  uint64_t sym[NREG][8];
+  uint8_t var[NREG], wd[NREG];
+  RForm pa, pb;
+  uint32_t pop, pw;
+};
+
+// The symbolic walk of the rows form (one wavefront, once per input): lane 0
+// holds a register's constant part, lanes 1..6 its coordinate coefficients
+// (or lane 1 the coefficient of its loaded value).  A form is exact modulo
+// 2^wd of the width of the operation that made it; it may feed operations
+// and accesses of width at most wd.  G.ok is cleared when the part outside
+// the loop body takes anything else (the loader flags PF_ROWS only for
+// programs whose walk succeeds).
+__device__ void build_rows(drows& G, RowWalk& Wk, const dprog* P, const int64_t* sc, const uint32_t* launch) {
+  const uint32_t j = lane_id();
+  const dins* I = prog_ins(P);
+  const int64_t* K = prog_consts(P);
+  auto rg = [&](uint32_t r) -> uint64_t& { return Wk.sym[r][j]; };  // lanes j < 7 only
+  for (uint32_t r = j; r < NREG; r += 64) { Wk.var[r] = RV_UNI; Wk.wd[r] = 64; }
+  uint32_t n = 0, n_load = 0, ok = P->expand_pc >= 0 ? 1u : 0u, preg = 0xFFu;
+  auto form_of = [&](RForm& f, uint32_t r) {  // copy register r's form (lanes 0..6 write)
+    const uint64_t v = j < 7 ? rg(r) : 0ull;
+    if (j == 0) { f.off = (int64_t)v; f.var = Wk.var[r]; }
+    else if (j < 7) f.c[j - 1] = (int64_t)v;
+  };
+  // a varying form may feed an operation of width w only if exact at w
+  auto fits = [&](uint32_t r, uint32_t w) { return Wk.var[r] == RV_UNI || (Wk.var[r] != RV_PRED && Wk.wd[r] >= w); };
+  const uint32_t npc = P->n_instr;
+  for (uint32_t pc = 0; pc < npc && ok; pc++) {
+    const dins D = I[pc];
+    const uint32_t op = D.op, w = D.w;
+    const uint32_t da = ufirst(D.a), db = ufirst(D.b), dc = ufirst(D.c), dd = ufirst(D.dst);
+    const uint64_t a = j < 7 ? rg(da) : 0, b = j < 7 ? rg(db) : 0;
+    const uint32_t va = Wk.var[da], vb = Wk.var[db];
+    uint64_t r = 0;
+    uint32_t rv = RV_UNI, rw = 64;
+    bool wr = true;
+    switch (op) {
+      case CKC_OP_CONST: r = j == 0 ? narrow((uint64_t)K[D.x], w) : 0; break;
+      case CKC_OP_SCALAR: r = j == 0 ? narrow((uint64_t)sc[D.x], w) : 0; break;
+      case CKC_OP_SPECIAL:
+        if (D.x < 6) {
+          r = j == 1u + D.x ? 1ull : 0ull;
+          rv = RV_COORD;
+        } else {
+          r = j == 0 ? (uint64_t)(D.x < 9 ? launch[3 + D.x - 6] : launch[D.x - 9]) : 0;
+        }
+        break;
+      case CKC_OP_ADD: case CKC_OP_SUB:
+        if ((va != RV_UNI && vb != RV_UNI && va != vb) || !fits(da, w) || !fits(db, w)) { ok = 0; break; }
+        r = narrow(op == CKC_OP_ADD ? a + b : a - b, w);
+        rv = va != RV_UNI ? va : vb;
+        rw = rv == RV_UNI ? 64 : w;
+        if (rv == RV_UNI && j != 0) r = 0;
+        break;
+      case CKC_OP_MUL:
+        if ((va != RV_UNI && vb != RV_UNI) || !fits(da, w) || !fits(db, w)) { ok = 0; break; }
+        r = narrow(va != RV_UNI ? a * readlane64(b, 0) : b * readlane64(a, 0), w);
+        rv = va != RV_UNI ? va : vb;
+        rw = rv == RV_UNI ? 64 : w;
+        if (rv == RV_UNI) r = j == 0 ? narrow(readlane64(a, 0) * readlane64(b, 0), w) : 0;
+        break;
+      case CKC_OP_SHL:
+        if (vb != RV_UNI || !fits(da, w)) { ok = 0; break; }
+        r = narrow(a << (readlane64(b, 0) & (uint64_t)(w - 1)), w);
+        rv = va;
+        rw = rv == RV_UNI ? 64 : w;
+        if (rv == RV_UNI && j != 0) r = 0;
+        break;
+      case CKC_OP_TRUNC:
+        if (!fits(da, 32)) { ok = 0; break; }
+        r = narrow(a, 32);
+        rv = va;
+        rw = rv == RV_UNI ? 64 : 32;
+        if (rv == RV_UNI && j != 0) r = 0;
+        break;
+      case CKC_OP_SEXT:
+        if (va != RV_UNI) { ok = 0; break; }
+        r = j == 0 ? narrow(readlane64(a, 0), 32) : 0;
+        break;
+      case CKC_OP_ZEXT:
+        if (va != RV_UNI) { ok = 0; break; }
+        r = j == 0 ? (readlane64(a, 0) & 0xFFFFFFFFull) : 0;
+        break;
+      case CKC_OP_SELECT:
+        if (va != RV_UNI || vb != RV_UNI || Wk.var[dc] != RV_UNI) { ok = 0; break; }
+        r = j == 0 ? narrow(readlane64(a, 0) != 0 ? readlane64(b, 0) : readlane64(rg(dc), 0), w) : 0;
+        break;
+      case CKC_OP_ACCESS:
+      case CKC_OP_LOAD: {
+        if (n >= MAX_RENT || !fits(da, w) || (op == CKC_OP_LOAD && n_load >= RV_MAXLOAD)) { ok = 0; break; }
+        REnt& E = G.e[n];
+        form_of(E.a, da);
+        if (j == 0) {
+          E.kind = op == CKC_OP_LOAD ? RE_LOAD : RE_ACCESS;
+          E.w = (uint8_t)w;
+          E.acc = D.x;
+          E.s0 = D.s0;
+          E.slot = D.slot;
+          E.lg = D.fl & 3u;
+          E.dst = op == CKC_OP_LOAD ? (uint8_t)(n_load + 1) : 0;
+        }
+        n++;
+        if (op == CKC_OP_LOAD) {
+          n_load++;
+          r = j == 1 ? 1ull : 0ull;
+          rv = n_load;
+        } else {
+          wr = false;
+        }
+        break;
+      }
+      case CKC_OP_IF: {
+        if (n >= MAX_RENT) { ok = 0; break; }
+        REnt& E = G.e[n];
+        if (va == RV_PRED) {
+          if (da != preg) { ok = 0; break; }
+          if (j == 0) { E.a = Wk.pa; E.b = Wk.pb; E.op = (uint8_t)Wk.pop; E.w = (uint8_t)Wk.pw; }
+        } else {
+          // IF tests the register's 64-bit value: a form exact at wd is
+          // nonzero exactly when its value modulo 2^wd is
+          form_of(E.a, da);
+          if (j == 0) {
+            E.b.off = 0;
+            E.b.var = RV_UNI;
+            E.op = CKC_OP_CMPNE;
+            E.w = (uint8_t)(va == RV_UNI ? 64u : Wk.wd[da]);
+          }
+        }
+        if (j == 0) { E.kind = RE_GUARD; E.s0 = D.s0; E.s1 = D.s1; }
+        n++;
+        wr = false;
+        break;
+      }
+      case CKC_OP_ENDIF:
+        if (n >= MAX_RENT) { ok = 0; break; }
+        if (j == 0) G.e[n].kind = RE_ENDG;
+        n++;
+        wr = false;
+        break;
+      case CKC_OP_LOOP: {
+        const uint32_t nl = P->n_livein;
+        if (n >= MAX_RENT || (int32_t)pc != P->expand_pc || !fits(da, w) || !fits(db, w) ||
+            Wk.var[dc] != RV_UNI) { ok = 0; break; }
+        for (uint32_t q = 0; q < nl; q++)
+          if (Wk.var[ufirst(P->livein[q])] != RV_UNI) ok = 0;
+        if (!ok) break;
+        REnt& E = G.e[n];
+        form_of(E.a, da);
+        form_of(E.b, db);
+        const uint64_t stp = narrow(readlane64(rg(dc), 0), w);
+        for (uint32_t q = 0; q < nl; q++) {
+          const uint64_t v = readlane64(rg(ufirst(P->livein[q])), 0);
+          if (j == 0) G.livein[q] = v;
+        }
+        if (j == 0) {
+          E.kind = RE_LOOP;
+          E.w = (uint8_t)w;
+          E.step = stp;
+          E.s1 = D.s1;
+        }
+        n++;
+        wr = false;
+        pc = D.jmp;  // the body is the gather pass's; continue after ENDLOOP
+        break;
+      }
+      default: {
+        if (op >= CKC_OP_CMPEQ && op <= CKC_OP_CMPLEU && (va != RV_UNI || vb != RV_UNI)) {
+          // a comparison of varying forms: only an IF may read it
+          if (!fits(da, w) || !fits(db, w)) { ok = 0; break; }
+          form_of(Wk.pa, da);
+          form_of(Wk.pb, db);
+          if (j == 0) { Wk.pop = op; Wk.pw = w; }
+          preg = dd;
+          rv = RV_PRED;
+          r = 0;
+          break;
+        }
+        if (op < CKC_OP_ADD || op > CKC_OP_CMPLEU || is_div_op(op) || va != RV_UNI || vb != RV_UNI) {
+          ok = 0;
+          break;
+        }
+        uint32_t f = 0;
+        const uint64_t v = alu(op, w, readlane64(a, 0), readlane64(b, 0), f);
+        r = j == 0 ? v : 0;
+        break;
+      }
+    }
+    if (ok && wr) {
+      if (j < 7) rg(dd) = r;
+      if (j == 0) { Wk.var[dd] = (uint8_t)rv; Wk.wd[dd] = (uint8_t)rw; }
+    }
+    // lanes exchange values through LDS: keep the order of the iterations
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (j == 0) {
+    // coordinate classes: equal coefficient vectors share one per-lane sum
+    uint32_t ncls = 0;
+    for (uint32_t q = 0; q < n; q++) {
+      RForm* fs[2] = {&G.e[q].a, &G.e[q].b};
+      const uint32_t nf = G.e[q].kind == RE_GUARD || G.e[q].kind == RE_LOOP ? 2u : 1u;
+      for (uint32_t h = 0; h < nf; h++) {
+        RForm& f = *fs[h];
+        f.cls = RCLS_NONE;
+        if (f.var != RV_COORD) continue;
+        for (uint32_t k = 0; k < ncls && f.cls == RCLS_NONE; k++) {
+          bool same = true;
+          for (int d = 0; d < 6; d++) same = same && G.cc[k][d] == f.c[d];
+          if (same) f.cls = (uint8_t)k;
+        }
+        if (f.cls == RCLS_NONE && ncls < MAX_RCLS) {
+          for (int d = 0; d < 6; d++) G.cc[ncls][d] = f.c[d];
+          f.cls = (uint8_t)ncls++;
+        }
+      }
+    }
+    G.ncls = ncls;
+    G.n = n;
+    G.ok = ok;
+  }
+}
+
 __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
   extern __shared__ uint64_t RG[];  // [max_regs][64]: symbolic registers of build_trace
+  __shared__ RowWalk rw;            // the rows form's walk
+  __shared__ drows rf;
   const uint32_t i = blockIdx.x;
   if (i >= a.n_inputs) return;
   dinput& in = a.inputs[i];
@@ -486,6 +719,14 @@ __global__ void __launch_bounds__(64, 4) plan_kernel(KArgs a) {
       for (uint32_t s = j; s < P->n_sites; s += 64) cnt[s] = 0;
       if (j == 0) { st->accesses_checked = 0; st->arith_faults = 0; st->hang_lanes = 0; }
     }
+  }
+  if ((P->pflags & PF_ROWS) && !(P->cls & CKC_CLS_UNIFORM) && in.trace != 0 && !in.detector && lanes > 0) {
+    // the rows form of the input's whole-thread part, once for all its tiles
+    build_rows(rf, rw, P, a.scalars + (size_t)i * MAX_SCALARS, in.launch);
+    __syncthreads();
+    uint4* dst = (uint4*)in.trace;
+    const uint4* src = (const uint4*)&rf;
+    for (uint32_t q = j; q < sizeof(drows) / 16; q += 64) dst[q] = src[q];
   }
   if (j == 0) {
     uint64_t tiles = (lanes + TILE - 1) / TILE;

@@ -32,8 +32,10 @@ static_assert(sizeof(dins) == 16, "dins layout");
 // Program flags (dprog.pflags).
 enum : uint8_t {
   PF_BLOCKWISE = 1,  // blocks run together: BARRIERs executed, shared memory read back
-  PF_CAPTURE = 2     // indices depend on shared memory: the first-violation index and
+  PF_CAPTURE = 2,    // indices depend on shared memory: the first-violation index and
                      // kind come from a second evaluation pass (no one-thread replay)
+  PF_ROWS = 4        // the whole-thread part around an expanded gather loop may run
+                     // in the rows form (no instruction dispatch; decided per input)
 };
 
 enum : uint8_t {
@@ -108,6 +110,42 @@ constexpr uint32_t MODE_PAIR = 8;
 // Evaluators of an input: the trace evaluator in block-major wavefront jobs,
 // the general interpreter, or the trace evaluator over lane tiles.
 enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };
+
+// Rows form of the whole-thread part of a program (PF_ROWS): per input, the
+// plan kernel reduces every value outside the expanded loop's body to an
+// affine form over the thread coordinates, or over one loaded value (the
+// symbolic walk), and the whole-thread pass runs a short list of entries with
+// no instruction dispatch.  A form: off + sum c[d] * coord[d] (var RV_COORD;
+// the coefficient vector is one of the input's classes, whose per-lane sums
+// are formed once per tile), off + c[0] * X[var] (var 1..RV_MAXLOAD: the value
+// of the var-th LOAD), or off (RV_UNI); it is evaluated modulo 2^w at its
+// entry's width w.
+constexpr uint32_t RV_UNI = 0xFF, RV_COORD = 0xFE, RV_PRED = 0xFD, RV_MAXLOAD = 4;
+constexpr uint32_t MAX_RENT = 16, MAX_RCLS = 4, RCLS_NONE = 0xFF;
+struct RForm {
+  int64_t off;
+  int64_t c[6];
+  uint8_t var, cls;  // cls: coordinate class of a RV_COORD form (RCLS_NONE: evaluate c directly)
+  uint8_t pad[6];
+};
+enum : uint8_t { RE_GUARD = 0, RE_ENDG = 1, RE_ACCESS = 2, RE_LOAD = 3, RE_LOOP = 4 };
+struct REnt {
+  RForm a, b;           // GUARD: the compared forms; ACCESS/LOAD: a = index; LOOP: start, end
+  uint64_t step;        // LOOP: the (uniform) step
+  uint32_t acc;         // ACCESS/LOAD: access id
+  uint16_t s0, s1;      // sites: access / IF taken, IF not taken / loop exit
+  uint8_t kind, w, op;  // op: GUARD comparison opcode
+  uint8_t slot, lg, dst, pad[2];
+};
+// One input's rows form (in the input's `trace` buffer, which programs with
+// an expanded loop never use for a trace).
+struct drows {
+  REnt e[MAX_RENT];
+  int64_t cc[MAX_RCLS][6];      // coefficient vectors of the coordinate classes
+  uint64_t livein[MAX_LIVEIN];  // the loop's live-ins (uniform)
+  uint32_t n, ok, ncls, pad;
+};
+static_assert(sizeof(drows) % 16 == 0, "rows form alignment");
 
 constexpr int MAX_SCALARS = 16;
 constexpr uint32_t LPB = 16;  // blocks per group of the block-major trace path

@@ -100,8 +100,9 @@ KArgs with_sched(const KArgs& a, const EvalGrid& eg, uint32_t path) {
   k.chunk = eg.chunk[path];
   return k;
 }
-// Kernel of evaluator `path` compiled for schedule `sk`.
-void* eval_fn(uint32_t path, uint32_t sk) {
+// Kernel of evaluator `path` compiled for schedule `sk` (the whole-thread
+// pass: the rows-form kernel when `rows`).
+void* eval_fn(uint32_t path, uint32_t sk, bool rows = false) {
   const uint32_t s = sched_impl(sk);
   if (path == PATH_BLOCKS)
     return s == CKC_SCHED_BLOCKED ? (void*)eval_trace_kernel<CKC_SCHED_BLOCKED>
@@ -111,15 +112,25 @@ void* eval_fn(uint32_t path, uint32_t sk) {
     return s == CKC_SCHED_BLOCKED ? (void*)eval_trace_lanes_kernel<CKC_SCHED_BLOCKED>
          : s == CKC_SCHED_CYCLIC  ? (void*)eval_trace_lanes_kernel<CKC_SCHED_CYCLIC>
                                   : (void*)eval_trace_lanes_kernel<CKC_SCHED_DYNAMIC>;
+  if (rows)
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_rows_kernel<CKC_SCHED_BLOCKED>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_rows_kernel<CKC_SCHED_CYCLIC>
+                                  : (void*)eval_rows_kernel<CKC_SCHED_DYNAMIC>;
   return s == CKC_SCHED_BLOCKED ? (void*)eval_generic_kernel<CKC_SCHED_BLOCKED>
        : s == CKC_SCHED_CYCLIC  ? (void*)eval_generic_kernel<CKC_SCHED_CYCLIC>
                                 : (void*)eval_generic_kernel<CKC_SCHED_DYNAMIC>;
 }
+// Dynamic LDS of evaluator `path` (the interpreter's register file and
+// shared-memory instances; the rows-form kernel has none).
+uint32_t eval_lds(const KArgs& a, uint32_t path) {
+  return path == PATH_GENERIC && !a.rows_only ? regfile_bytes(a) + a.sh_bytes : 0u;
+}
 hipError_t launch_eval(const KArgs& a, const EvalGrid& eg, uint32_t path, hipStream_t s) {
   KArgs k = with_sched(a, eg, path);
   void* args[] = {&k};
-  return hipLaunchKernel(eval_fn(path, eg.sched[path]), dim3(eg.n_wg[path]), dim3(TILE), args,
-                         path == PATH_GENERIC ? regfile_bytes(a) + a.sh_bytes : 0, s);
+  const bool rows = path == PATH_GENERIC && a.rows_only;
+  return hipLaunchKernel(eval_fn(path, eg.sched[path], rows), dim3(eg.n_wg[path]), dim3(TILE), args,
+                         eval_lds(a, path), s);
 }
 }  // namespace
 
@@ -226,8 +237,8 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
     e = add_node(g, &ev[0], &scan, 1, eval_fn(PATH_BLOCKS, eg.sched[PATH_BLOCKS]), eg.n_wg[PATH_BLOCKS], TILE,
                  argsp[PATH_BLOCKS]);
   if (e == hipSuccess)
-    e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC]), eg.n_wg[PATH_GENERIC], TILE,
-                 argsp[PATH_GENERIC], regfile_bytes(a) + a.sh_bytes);
+    e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC], a.rows_only != 0),
+                 eg.n_wg[PATH_GENERIC], TILE, argsp[PATH_GENERIC], eval_lds(a, PATH_GENERIC));
   if (e == hipSuccess)
     e = add_node(g, &ev[2], &scan, 1, eval_fn(PATH_LANES, eg.sched[PATH_LANES]), eg.n_wg[PATH_LANES], TILE,
                  argsp[PATH_LANES]);

@@ -433,6 +433,92 @@ struct Analyzer {
     return false;
   }
 
+  // The whole-thread part of a program whose expanded loop has a gather body
+  // (everything outside that body) runs without instruction dispatch, in the
+  // rows form, when the device's symbolic walk (build_rows) reduces it to
+  // affine forms: every value a constant, an affine form of the thread
+  // coordinates or of one loaded value (at most 4 loads), exact at the width
+  // it is used at; IF regions without ELSE, not nested, whose predicate is a
+  // comparison just before or a value; the loop's bounds forms, its step and
+  // live-ins uniform; at most 16 entries.  The walk's decisions depend only on
+  // kinds and widths, not on values, so they are replayed here: a program
+  // flagged PF_ROWS always passes the walk.
+  bool rows_form() const {
+    if (expand_pc < 0 || !body_gather || blockwise()) return false;
+    const int body_end = ins[expand_pc].end;
+    enum { UNI = 0, COORD = 1, PRED = 2, LOAD0 = 3 };  // LOAD0 + k: the k-th load
+    std::vector<int> kind(n_regs, UNI), wd(n_regs, 64);
+    auto fits = [&](int r, int w) { return kind[r] == UNI || (kind[r] != PRED && wd[r] >= w); };
+    int n = 0, n_load = 0, preg = -1, open_if = 0;
+    for (int i = 0; i < n_instr; i++) {
+      const Ins& I = ins[i];
+      if (!I.live || (i > expand_pc && i < body_end)) continue;
+      const int op = I.op, w = I.w;
+      switch (op) {
+        case CKC_OP_CONST: case CKC_OP_SCALAR: kind[I.dst] = UNI; wd[I.dst] = 64; break;
+        case CKC_OP_SPECIAL: kind[I.dst] = I.a < 6 ? COORD : UNI; wd[I.dst] = 64; break;
+        case CKC_OP_ADD: case CKC_OP_SUB: case CKC_OP_MUL: case CKC_OP_SHL: {
+          const int ka = kind[I.a], kb = kind[I.b];
+          if (!fits(I.a, w) || !fits(I.b, w)) return false;
+          if (op == CKC_OP_SHL && kb != UNI) return false;
+          if (op == CKC_OP_MUL && ka != UNI && kb != UNI) return false;
+          if ((op == CKC_OP_ADD || op == CKC_OP_SUB) && ka != UNI && kb != UNI && ka != kb) return false;
+          kind[I.dst] = ka != UNI ? ka : kb;
+          wd[I.dst] = kind[I.dst] == UNI ? 64 : w;
+          break;
+        }
+        case CKC_OP_TRUNC:
+          if (!fits(I.a, 32)) return false;
+          kind[I.dst] = kind[I.a];
+          wd[I.dst] = kind[I.dst] == UNI ? 64 : 32;
+          break;
+        case CKC_OP_SEXT: case CKC_OP_ZEXT:
+          if (kind[I.a] != UNI) return false;
+          kind[I.dst] = UNI; wd[I.dst] = 64;
+          break;
+        case CKC_OP_SELECT:
+          if (kind[I.a] != UNI || kind[I.b] != UNI || kind[I.c] != UNI) return false;
+          kind[I.dst] = UNI; wd[I.dst] = 64;
+          break;
+        case CKC_OP_ACCESS: case CKC_OP_STORE: case CKC_OP_LOAD:
+          if (op == CKC_OP_STORE && I.store_val) return false;
+          if (op == CKC_OP_LOAD && (space_of(I.c) != CKC_SPACE_GLOBAL || n_load >= 4)) return false;
+          if (n >= 16 || !fits(I.a, w)) return false;
+          n++;
+          if (op == CKC_OP_LOAD) { kind[I.dst] = LOAD0 + n_load++; wd[I.dst] = 64; }
+          break;
+        case CKC_OP_IF:
+          if (open_if++ || n >= 16 || (kind[I.a] == PRED && I.a != preg)) return false;
+          n++;
+          break;
+        case CKC_OP_ENDIF:
+          open_if--;
+          if (n >= 16) return false;
+          n++;
+          break;
+        case CKC_OP_LOOP:
+          if (i != expand_pc || n >= 16 || !fits(I.a, w) || !fits(I.b, w) || kind[I.c] != UNI) return false;
+          for (int r : livein)
+            if (kind[r] != UNI) return false;
+          n++;
+          i = body_end;  // continue after ENDLOOP
+          break;
+        default:
+          if (op >= CKC_OP_CMPEQ && op <= CKC_OP_CMPLEU && (kind[I.a] != UNI || kind[I.b] != UNI)) {
+            if (!fits(I.a, w) || !fits(I.b, w)) return false;
+            kind[I.dst] = PRED;
+            preg = I.dst;
+            break;
+          }
+          if (op < CKC_OP_ADD || op > CKC_OP_CMPLEU || is_divrem(op)) return false;
+          if (kind[I.a] != UNI || kind[I.b] != UNI) return false;
+          kind[I.dst] = UNI; wd[I.dst] = 64;
+          break;
+      }
+    }
+    return true;
+  }
+
   bool reg_used(int r) const {
     for (int i = def_pc[r] + 1; i < n_instr; i++) {
       const Ins& I = ins[i];
@@ -824,7 +910,8 @@ struct Analyzer {
         if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
     h.body_gather = body_gather ? 1u : 0u;
     h.slot_spaces = slot_spaces;
-    h.pflags = (uint8_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0));
+    h.pflags = (uint8_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0) |
+                         (rows_form() ? PF_ROWS : 0));
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
     h.off_instr = al(sizeof(dprog));

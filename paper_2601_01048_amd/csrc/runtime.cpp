@@ -221,6 +221,7 @@ int ckc::rt::validate_desc(ckc_ctx c, const ckc_batch& B, uint32_t k, bool force
     ws += sizeof(dinput) + 8 * MAX_SCALARS + 4 + sizeof(ckc_input_status) + (uint64_t)h->n_accesses * sizeof(ckc_record) +
           (uint64_t)h->n_sites * 4;
     if ((h->cls & CKC_CLS_UNIFORM) && !force_generic && !tripwire) ws += ckc::trace_bytes(h->trace_cap);
+    else if ((h->pflags & PF_ROWS) && !tripwire) ws += sizeof(drows);
     if (B.flags & CKC_DENSE_MAP) ws += 65536;
   }
   if (ws_bytes) *ws_bytes = ws;
@@ -344,10 +345,12 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   a.max_regs = S.max_regs;
   a.capture = 0;
   a.sh_bytes = S.sh_bytes;
-  a.pad = 0;
+  a.rows_only = S.all_rows && !S.hin.empty() ? 1u : 0u;
   a.sched = CKC_SCHED_DYNAMIC;
   a.chunk = O.chunk ? O.chunk : 1u;
-  const uint32_t defwg[3] = {8, 4, 2};  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES
+  // PATH_BLOCKS, PATH_GENERIC, PATH_LANES; the rows-form kernel keeps 6
+  // wavefronts per SIMD
+  const uint32_t defwg[3] = {8, a.rows_only ? 6u : 4u, 2};
   for (int p = 0; p < 3; p++) {
     eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
     eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);

@@ -60,6 +60,7 @@ struct Stage {
   uint64_t n_records = 0, n_counts = 0, trace_bytes = 0;
   uint32_t sh_bytes = 0;  // LDS of the shared-memory instances of a tile (blockwise programs)
   bool capture = false;   // some input needs the capture pass
+  bool all_rows = true;   // every input's program takes the rows form (PF_ROWS, exact bounds)
 
   // Notes an input of a blockwise program (PF_BLOCKWISE): each tile holds
   // TILE / bs of its blocks, each with one instance of every shared slot (a
@@ -94,6 +95,7 @@ struct Stage {
     n_records = n_counts = trace_bytes = 0;
     sh_bytes = 0;
     capture = false;
+    all_rows = true;
   }
 
   // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;
@@ -108,6 +110,9 @@ struct Stage {
     if (uniform) {
       d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
       trace_bytes += ckc::trace_bytes(h->trace_cap);
+    } else if ((h->pflags & PF_ROWS) && !d.detector && lanes_max > 0) {
+      d.trace = trace_bytes + 1;  // the input's rows form
+      trace_bytes += sizeof(drows);
     }
     if (h->expand_pc >= 0 && !uniform && lanes_max > 0) {
       // expanded loop: thread-state arrays over at most lanes_max lanes
@@ -120,6 +125,7 @@ struct Stage {
       n_xin++;
       xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
     }
+    if (!(h->pflags & PF_ROWS) || d.detector) all_rows = false;
     hin.push_back(d);
     est.push_back(lanes_max * (1 + h->n_accesses));
     if (!uniform) gen_tiles += (lanes_max + TILE - 1) / TILE;

@@ -1,0 +1,62 @@
+"""The whole-thread pass's rows form (the part of a program around an
+expanded gather loop reduced per input to affine forms and run with no
+instruction dispatch) against the oracle on random programs of that shape:
+affine thread-coordinate forms at both widths, one level of IF guards with
+every comparison, loads feeding the loop bounds and other indices, steps of
+1, 2 and -1, loops over the trip cap (hangs), accesses before and after the
+loop, two-dimensional blocks, and near misses the device walk hands back to
+the interpreter.  Records, dense maps and status byte for byte, in the whole
+grid, the boundary set and the corner set."""
+import os
+
+import numpy as np
+import pytest
+
+import rowsprog as RP
+from oracle import oracle as O
+from paper_2601_01048_amd import ckc
+from paper_2601_01048_amd.gen import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NCPU = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = ckc.Context(0)
+    yield c
+    c.close()
+
+
+def check_same(ctx, wl, mode=None, what=""):
+    print(f"[case] rows {what} mode={wl.mode if mode is None else mode} inputs={wl.n_inputs}", flush=True)
+    g = ckc.run_workload(ctx, wl, mode=mode)
+    o = O.check(wl, mode=mode, nthreads=NCPU)
+    for f in ("first_key", "index", "count", "kinds", "first_kind"):
+        assert np.array_equal(g["records"][f], o["records"][f]), (what, f)
+    assert np.array_equal(g["maps"], o["maps"]), what
+    for f in ("lanes", "accesses_checked", "hang_lanes", "arith_faults", "flags"):
+        assert np.array_equal(g["status"][f], o["status"][f]), (what, f)
+    return g, o
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_rows_programs(ctx, seed):
+    rng = np.random.default_rng(4000 + seed)
+    for k in range(4):
+        near = k == 3
+        ir = RP.rows_program(rng, near_miss=near)
+        cap = (2, 12) if (seed + k) % 3 == 0 else (20, 12)
+        wl = RP.rows_workload(rng, ir, cap=cap)
+        for mode in (W.MODE_FULL, W.MODE_BOUNDARY, W.MODE_CORNERS):
+            check_same(ctx, wl, mode=mode, what=f"{seed}.{k}{' near' if near else ''} cap={cap[0]}")
+
+
+def test_csr_batch_rows_form(ctx):
+    """The CSR configuration's program (guard, two row-pointer loads, the
+    gather loop, y[r]) at both widths, whole grid."""
+    for w in (32, 64):
+        check_same(ctx, W.mini("config3", w=w), what=f"csr i{w}")
