@@ -464,7 +464,7 @@ __device__ void run_program(GenLds& S, uint64_t* R, Ctx& C, Lane& ln, uint64_t& 
   }
 }
 
-__device__ void flush_input(WtLds& S, const KArgs& a, uint32_t input, uint32_t n_sites) {
+__device__ __forceinline__ void flush_input(WtLds& S, const KArgs& a, uint32_t input, uint32_t n_sites) {
   __syncthreads();
   const dinput& in = a.inputs[input];
   uint32_t* cnt = a.counts + in.cnt_base;
@@ -1066,7 +1066,7 @@ __device__ __forceinline__ uint64_t find_xtile(const unsigned long long* xpb, ui
 // (wavefront 0; lane 0 holds the constant part of each register, lane 1 its
 // coefficient of the register's variable).  `live` is the owner thread's lane
 // whose stored live-ins are used (they are uniform over the input).
-__device__ void build_gather(GenLds& S, uint64_t* R, const Ctx& C, uint32_t lpc, uint32_t endpc, uint64_t live) {
+__device__ __forceinline__ void build_gather(GenLds& S, uint64_t* R, const Ctx& C, uint32_t lpc, uint32_t endpc, uint64_t live) {
   const uint32_t j = lane_id();
   c_dprog* P = C.P;
   c_dins* I = C.I;
@@ -1627,7 +1627,7 @@ __device__ __forceinline__ void end_run(GenLds& S, const Ctx& C, const uint64_t*
 // range starts inside the piece marks its start; a workgroup max-scan over the
 // marks (owners increase with the iteration) fills the rest, the piece's
 // first iteration taking the owner found by one binary search.
-__device__ void build_owner_map(GenLds& S, uint64_t it0, uint64_t it1) {
+__device__ __forceinline__ void build_owner_map(GenLds& S, uint64_t it0, uint64_t it1) {
   const uint32_t tid = threadIdx.x;
   constexpr uint32_t PER = PIECE_LDS / TILE;  // entries per thread
   for (uint32_t q = 0; q < PER; q++) S.own[tid * PER + q] = 0;
@@ -1793,7 +1793,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
 // in LDS with the tile's prefix, so an iteration costs one memory round trip
 // per dependent load of the body.
 template <uint32_t SK, bool BIG>
-__global__ void __launch_bounds__(TILE, 3) eval_gather_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, BIG ? 4 : 3) eval_gather_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
   __shared__ unsigned long long item_slot;
