@@ -810,8 +810,12 @@ __device__ __forceinline__ void rows_expand(RowsLds& S, const Ctx& C, c_drows& G
       C.xs[C.xn + l] = s0;
       C.xs[2 * C.xn + l] = stp;
     }
-    const uint32_t nl = P->n_livein;
-    for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = G.livein[q];
+    // the live-ins are uniform over the input: the gather pass reads them
+    // from the tile's first thread with iterations only
+    if (pre == 0) {
+      const uint32_t nl = P->n_livein;
+      for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = G.livein[q];
+    }
   }
   if (tid == TILE - 1) {
     C.xtot[C.xt] = tot;
@@ -1910,8 +1914,9 @@ __global__ void __launch_bounds__(TILE, BIG ? 4 : 3) eval_gather_kernel(KArgs a)
     Ctx C;
     ctx_init(C, a, in, i, T0);
     if (!built) {
-      // live-ins are uniform over the input: take the owner of this piece's first iteration
-      const uint32_t o0 = ufirst(owner_of(S, it0));
+      // live-ins are uniform over the input: take them from the tile's first
+      // thread with iterations (the one thread the rows form stores them for)
+      const uint32_t o0 = ufirst(owner_of(S, 0));
       if (tid < 64) build_gather(S, R, C, lpc, Lx.jmp, lane0 + o0);
       __syncthreads();
       built = 1;

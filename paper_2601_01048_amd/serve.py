@@ -5,6 +5,7 @@ per-job stats (arrival, admission, results readable) give the latency
 distribution.  Marshalling and timing only; the checking runs in libckc."""
 from __future__ import annotations
 
+import gc
 import threading
 import time
 
@@ -35,6 +36,13 @@ def replay(server: ckc.Server, ds: ckc.DeviceStream, jobs=None, time_scale: floa
                 d.update(records=recs, maps=None if mp is None else mp[0], status=st[0])
             out[q] = d
 
+    # the load generator must not pause: Python's cyclic garbage collector
+    # (a full collection over the replay's objects takes hundreds of ms) is
+    # off while jobs are submitted, and the objects made so far are frozen
+    gc_was = gc.isenabled()
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     th = threading.Thread(target=collect)
     th.start()
     t0 = time.monotonic_ns() + 20_000_000  # start 20 ms from now
@@ -53,9 +61,16 @@ def replay(server: ckc.Server, ds: ckc.DeviceStream, jobs=None, time_scale: floa
             ready.release()
     finally:
         th.join()
+        gc.unfreeze()
+        if gc_was:
+            gc.enable()
     lags = np.array(lags) / 1e3
+    for q, d in enumerate(out):
+        d["submit_lag_us"] = float(lags[q])
     return out, dict(submit_lag_us_p50=float(np.percentile(lags, 50)),
-                     submit_lag_us_p99=float(np.percentile(lags, 99)), t0_ns=t0)
+                     submit_lag_us_p99=float(np.percentile(lags, 99)),
+                     submit_lag_us_max=float(lags.max()) if len(lags) else 0.0,
+                     late_over_1ms=int((lags > 1000).sum()), t0_ns=t0)
 
 
 def summarize(res, t_from_s: float = 0.0, t0_ns: int = 0, arrivals=None):
