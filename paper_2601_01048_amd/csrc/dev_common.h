@@ -308,8 +308,10 @@ __device__ __forceinline__ void thr_from(const uint32_t* L, uint64_t blin, uint3
 struct Dec {
   UDiv dbs, dgxy, dgx, dbxy, dbx;
   uint32_t bs, gxy, gx, bxy, bx;
+  uint32_t one_d;  // one-dimensional grid of one-dimensional blocks
 };
 __device__ __forceinline__ void dec_make(Dec& d, const uint32_t* L) {
+  d.one_d = L[1] == 1 && L[2] == 1 && L[4] == 1 && L[5] == 1;
   d.gx = L[0];
   d.gxy = L[0] * L[1];
   d.bx = L[3];
@@ -323,6 +325,14 @@ __device__ __forceinline__ void dec_make(Dec& d, const uint32_t* L) {
 }
 // Whole-grid lane l: the lane index is the global thread id.
 __device__ __forceinline__ void decode_full(const Dec& d, uint64_t l, Thr& th) {
+  if (d.one_d && l < (1ull << 32)) {  // block and thread x only: one division
+    const uint32_t b = udiv((uint32_t)l, d.dbs);
+    th.b[0] = b;
+    th.t[0] = (uint32_t)l - b * d.bs;
+    th.b[1] = th.b[2] = th.t[1] = th.t[2] = 0;
+    th.gtid = l;
+    return;
+  }
   uint32_t blin, tlin;
   if (l < (1ull << 32)) {
     blin = udiv((uint32_t)l, d.dbs);

@@ -732,15 +732,23 @@ __device__ __forceinline__ uint64_t rtrips(int64_t s, int64_t e, int64_t st) {
   return trip_count_div(s, e, st);
 }
 
-// Adds the visits of the lanes of `mask` to site s (one LDS add per wavefront).
-__device__ __forceinline__ void rsite(RowsLds& S, const Ctx& C, uint32_t s, uint64_t mask) {
-  if (s == NOSITE || mask == 0) return;
-  const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
-  if (lane_id() == leader) {
-    const uint32_t c = (uint32_t)__popcll(mask);
-    if (s < MAX_SITES_LDS) atomicAdd(&S.sites[s], c);
-    else if (C.gcnt[s] < 255u) atomicAdd(&C.gcnt[s], c);
+// Visits of the entries' sites are counted per wavefront in one register
+// (lane 2q: site s0 of entry q, lane 2q + 1: its s1) and moved to the
+// workgroup's counters when the input changes.
+__device__ __forceinline__ void rsite(uint32_t& sv, uint32_t slot, uint64_t mask) {
+  const uint32_t c = (uint32_t)__popcll(mask);
+  if (lane_id() == slot) sv += c;
+}
+__device__ __forceinline__ void rsite_flush(RowsLds& S, uint32_t& sv, c_drows& G, uint32_t* gcnt) {
+  const uint32_t j = lane_id();
+  if (sv != 0 && j < 2 * MAX_RENT) {
+    const uint32_t s = (j & 1u) ? G.e[j >> 1].s1 : G.e[j >> 1].s0;
+    if (s != NOSITE) {
+      if (s < MAX_SITES_LDS) atomicAdd(&S.sites[s], sv);
+      else if (gcnt[s] < 255u) atomicAdd(&gcnt[s], sv < 255u ? sv : 255u);
+    }
   }
+  sv = 0;
 }
 
 // Inclusive prefix sum over the wavefront (32-bit values).
@@ -830,7 +838,7 @@ __device__ __forceinline__ void rows_expand(RowsLds& S, const Ctx& C, c_drows& G
 // One thread in the rows form: the same sites, records, status and
 // expanded-loop state as the interpreter's whole-thread pass.
 __device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G, const Thr& T, bool act,
-                                            uint64_t& acc, uint64_t& hangs) {
+                                            uint64_t& acc, uint64_t& hangs, uint32_t& sv) {
   RSlice X;
   const uint32_t ncls = G.ncls;
 #pragma unroll
@@ -854,8 +862,8 @@ __device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G
     const uint32_t kind = E.kind, w = E.w;
     if (kind == RE_GUARD) {
       const bool p = on && rcmp(E.op, w, rform(E.a, X, T, w), rform(E.b, X, T, w));
-      rsite(S, C, E.s0, __ballot(p));
-      rsite(S, C, E.s1, __ballot(on && !p));
+      rsite(sv, 2 * q, __ballot(p));
+      rsite(sv, 2 * q + 1, __ballot(on && !p));
       on = p;
     } else if (kind == RE_ENDG) {
       on = alive;
@@ -866,7 +874,7 @@ __device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G
       const uint64_t nt = on ? rtrips((int64_t)s0, e0, (int64_t)stp) : 0;
       const bool hg = on && nt > C.cap0;
       rows_expand(S, C, G, on ? (nt < C.cap0 ? nt : C.cap0) : 0, s0, stp);
-      rsite(S, C, E.s1, __ballot(on && !hg));
+      rsite(sv, 2 * q + 1, __ballot(on && !hg));
       if (hg) {
         on = alive = false;
         hangs++;
@@ -877,7 +885,7 @@ __device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G
       const int64_t idx = (int64_t)rform(E.a, X, T, w);
       const uint32_t kd = on ? kind_of(A.base, A.size_bytes, A.flags, idx, lg) : 0u;
       acc += on ? 1u : 0u;
-      rsite(S, C, E.s0, __ballot(on));
+      rsite(sv, 2 * q, __ballot(on));
       if (__ballot(kd != 0)) merge_violation(C.rec + E.acc, kd, key);
       if (dst) {
         uint64_t v = 0;
@@ -892,7 +900,10 @@ __device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G
 // Coverage and status of the current input into its global counters (the
 // whole workgroup).
 __device__ void flush_rows(RowsLds& S, const KArgs& a, uint32_t input, uint32_t n_sites, uint64_t& acc,
-                           uint64_t& hangs) {
+                           uint64_t& hangs, uint32_t& sv) {
+  const dinput& in = a.inputs[input];
+  uint32_t* cnt = a.counts + in.cnt_base;
+  rsite_flush(S, sv, *(c_drows*)in.trace, cnt);
   const uint64_t n = wave_sum64(acc), h = wave_sum64(hangs);
   if (lane_id() == 0) {
     if (n) atomicAdd(&S.acc_checked, (unsigned long long)n);
@@ -901,8 +912,6 @@ __device__ void flush_rows(RowsLds& S, const KArgs& a, uint32_t input, uint32_t 
   acc = 0;
   hangs = 0;
   __syncthreads();
-  const dinput& in = a.inputs[input];
-  uint32_t* cnt = a.counts + in.cnt_base;
   const uint32_t ns = n_sites < (uint32_t)MAX_SITES_LDS ? n_sites : (uint32_t)MAX_SITES_LDS;
   for (uint32_t s = threadIdx.x; s < ns; s += TILE) {
     const uint32_t c = S.sites[s];
@@ -934,7 +943,7 @@ __global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
   c_u32* order = (c_u32*)a.order;
   for (uint32_t s = tid; s < MAX_SITES_LDS; s += TILE) S.sites[s] = 0;
   if (tid == 0) { S.acc_checked = 0; S.hangs = 0; }
-  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0;
+  uint32_t pos = 0xFFFFFFFFu, cur = 0xFFFFFFFFu, cur_sites = 0, cur_mode = 0, sv = 0;
   uint64_t tb = 0, cur_end = 0, cur_lanes = 0, acc = 0, hangs = 0;
   uint32_t cur_L[7] = {0, 0, 0, 0, 0, 0, 0};
   Dec dec;
@@ -945,7 +954,7 @@ __global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
     if (pos == 0xFFFFFFFFu || t < tb || t >= cur_end) {
       pos = pos_of_tile(ins, order, a.n_inputs, PATH_GENERIC, pos, cur_end, t);
       const uint32_t i = order[pos];
-      if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs);
+      if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs, sv);
       cur = i;
       cur_sites = ((c_dprog*)a.inputs[i].prog)->n_sites;
       tb = ins[i].tile_begin[PATH_GENERIC];
@@ -975,9 +984,9 @@ __global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
     C.xt = in.xt_begin + (t - tb);
-    rows_thread(S, C, *G, T, act, acc, hangs);
+    rows_thread(S, C, *G, T, act, acc, hangs, sv);
   }
-  if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs);
+  if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs, sv);
 }
 
 // Exclusive scan, in place, of the per-tile piece counts of expanded loops

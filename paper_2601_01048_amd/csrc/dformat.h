@@ -62,8 +62,10 @@ struct dprog {
   uint32_t n_livein;
   uint32_t trace_cap;         // entries reserved per input for the trace path (0 = none)
   uint8_t livein[MAX_LIVEIN]; // physical registers read by the expanded body
-  uint8_t pflags;             // PF_* bits
-  uint8_t body_special;       // the expanded body reads tid or bid
+  uint8_t pad[2];
+  // flags the kernels test per work item are whole dwords (scalar loads)
+  uint32_t pflags;            // PF_* bits
+  uint32_t body_special;      // the expanded body reads tid or bid
   uint32_t off_instr, off_consts, off_access, off_sites;  // byte offsets from the header
   uint32_t total_bytes;
   uint32_t body_gather;       // the expanded body is evaluated as a gather (entries)
@@ -122,21 +124,24 @@ enum : uint32_t { PATH_BLOCKS = 0, PATH_GENERIC = 1, PATH_LANES = 2 };
 // entry's width w.
 constexpr uint32_t RV_UNI = 0xFF, RV_COORD = 0xFE, RV_PRED = 0xFD, RV_MAXLOAD = 4;
 constexpr uint32_t MAX_RENT = 16, MAX_RCLS = 4, RCLS_NONE = 0xFF;
+// Every field of the rows form is at least 32 bits wide: the kernels read
+// them as uniform values through scalar loads, which move whole dwords
+// (narrower fields would be read by vector loads, each a memory round trip).
 struct RForm {
   int64_t off;
   int64_t c[6];
-  uint8_t var, cls;  // cls: coordinate class of a RV_COORD form (RCLS_NONE: evaluate c directly)
-  uint8_t pad[6];
+  uint32_t var, cls;  // cls: coordinate class of a RV_COORD form (RCLS_NONE: evaluate c directly)
 };
-enum : uint8_t { RE_GUARD = 0, RE_ENDG = 1, RE_ACCESS = 2, RE_LOAD = 3, RE_LOOP = 4 };
+enum : uint32_t { RE_GUARD = 0, RE_ENDG = 1, RE_ACCESS = 2, RE_LOAD = 3, RE_LOOP = 4 };
 struct REnt {
   RForm a, b;           // GUARD: the compared forms; ACCESS/LOAD: a = index; LOOP: start, end
   uint64_t step;        // LOOP: the (uniform) step
   uint32_t acc;         // ACCESS/LOAD: access id
-  uint16_t s0, s1;      // sites: access / IF taken, IF not taken / loop exit
-  uint8_t kind, w, op;  // op: GUARD comparison opcode
-  uint8_t slot, lg, dst, pad[2];
+  uint32_t s0, s1;      // sites: access / IF taken, IF not taken / loop exit
+  uint32_t kind, w, op; // op: GUARD comparison opcode
+  uint32_t slot, lg, dst, pad;
 };
+static_assert(sizeof(RForm) == 64 && sizeof(REnt) % 16 == 0, "rows form layout");
 // One input's rows form (in the input's `trace` buffer, which programs with
 // an expanded loop never use for a trace).
 struct drows {

@@ -910,7 +910,7 @@ struct Analyzer {
         if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
     h.body_gather = body_gather ? 1u : 0u;
     h.slot_spaces = slot_spaces;
-    h.pflags = (uint8_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0) |
+    h.pflags = (uint32_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0) |
                          (rows_form() ? PF_ROWS : 0));
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
