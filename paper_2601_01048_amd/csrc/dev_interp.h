@@ -897,6 +897,113 @@ __device__ __forceinline__ void rows_thread(RowsLds& S, const Ctx& C, c_drows& G
   }
 }
 
+// The rows form of an input whose entries are all 32 bits wide, in 32-bit
+// arithmetic: a form at width 32 is its value modulo 2^32 (sign-extended
+// where a 64-bit value is needed), and the low 32 bits of sums and products
+// depend only on the low 32 bits of their operands.  An index is in bounds iff
+// its unsigned value is below the slot's element count clamped to 2^31.
+struct RSlice32 {
+  uint32_t base[MAX_RCLS];
+  uint32_t x[RV_MAXLOAD];
+};
+__device__ __forceinline__ uint32_t rsel4_32(const uint32_t* v, uint32_t k) {
+  return k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
+}
+__device__ __forceinline__ void rset4_32(uint32_t* v, uint32_t k, uint32_t x) {
+  if (k == 0) v[0] = x;
+  else if (k == 1) v[1] = x;
+  else if (k == 2) v[2] = x;
+  else v[3] = x;
+}
+__device__ __forceinline__ uint32_t rform32(c_rform& f, const RSlice32& X, const Thr& T) {
+  const uint32_t var = f.var;
+  uint32_t v = (uint32_t)f.off;
+  if (var == RV_COORD) {
+    const uint32_t cls = f.cls;
+    if (cls != RCLS_NONE) {
+      v += rsel4_32(X.base, cls);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 6; d++) v += (uint32_t)f.c[d] * (uint32_t)coord(T, d);
+    }
+  } else if (var != RV_UNI) {
+    v += (uint32_t)f.c[0] * rsel4_32(X.x, var - 1);
+  }
+  return v;
+}
+__device__ __forceinline__ bool rcmp32(uint32_t op, uint32_t x, uint32_t y) {
+  switch (op) {
+    case CKC_OP_CMPEQ: return x == y;
+    case CKC_OP_CMPNE: return x != y;
+    case CKC_OP_CMPLTS: return (int32_t)x < (int32_t)y;
+    case CKC_OP_CMPLES: return (int32_t)x <= (int32_t)y;
+    case CKC_OP_CMPLTU: return x < y;
+    default: return x <= y;  // CMPLEU
+  }
+}
+__device__ __forceinline__ void rows_thread32(RowsLds& S, const Ctx& C, c_drows& G, const Thr& T, bool act,
+                                              uint64_t& acc, uint64_t& hangs, uint32_t& sv) {
+  RSlice32 X;
+  const uint32_t ncls = G.ncls;
+#pragma unroll
+  for (uint32_t c = 0; c < MAX_RCLS; c++) {
+    uint32_t v = 0;
+    if (c < ncls)
+#pragma unroll
+      for (int d = 0; d < 6; d++) {
+        const uint32_t cf = (uint32_t)G.cc[c][d];
+        if (cf) v += cf * (uint32_t)coord(T, d);
+      }
+    X.base[c] = v;
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < RV_MAXLOAD; q++) X.x[q] = 0;
+  const uint64_t key = T.gtid << C.Lsum;
+  bool on = act, alive = act;
+  const uint32_t n = G.n;
+  for (uint32_t q = 0; q < n; q++) {
+    c_rent& E = G.e[q];
+    const uint32_t kind = E.kind;
+    if (kind == RE_GUARD) {
+      const bool p = on && rcmp32(E.op, rform32(E.a, X, T), rform32(E.b, X, T));
+      rsite(sv, 2 * q, __ballot(p));
+      rsite(sv, 2 * q + 1, __ballot(on && !p));
+      on = p;
+    } else if (kind == RE_ENDG) {
+      on = alive;
+    } else if (kind == RE_LOOP) {
+      const uint64_t stp = E.step;
+      const int32_t s0 = (int32_t)rform32(E.a, X, T), e0 = (int32_t)rform32(E.b, X, T);
+      uint64_t nt = 0;
+      if (on)
+        nt = stp == 1 ? (s0 < e0 ? (uint64_t)((uint32_t)e0 - (uint32_t)s0) : 0) : trip_count_div(s0, e0, (int64_t)stp);
+      const bool hg = on && nt > C.cap0;
+      rows_expand(S, C, G, on ? (nt < C.cap0 ? nt : C.cap0) : 0, (uint64_t)(int64_t)s0, stp);
+      rsite(sv, 2 * q + 1, __ballot(on && !hg));
+      if (hg) {
+        on = alive = false;
+        hangs++;
+      }
+    } else {  // ACCESS, LOAD
+      const uint32_t lg = E.lg, dst = E.dst;
+      c_alloc& A = C.tab[E.slot];
+      const uint64_t ne = A.size_bytes >> lg;
+      const uint32_t bnd = ne > 0x80000000ull ? 0x80000000u : (uint32_t)ne;
+      const uint32_t dk = A.base == 0 ? CKC_KIND_NULL : (A.flags & CKC_ALLOC_FREED) ? CKC_KIND_FREED : 0u;
+      const uint32_t v = rform32(E.a, X, T);
+      const uint32_t kd = !on ? 0u : dk ? dk : (int32_t)v < 0 ? CKC_KIND_UNDER : v >= bnd ? CKC_KIND_OVER : 0u;
+      acc += on ? 1u : 0u;
+      rsite(sv, 2 * q, __ballot(on));
+      if (__ballot(kd != 0)) merge_violation(C.rec + E.acc, kd, key);
+      if (dst) {
+        uint32_t x = 0;
+        if (on && kd == 0) x = lg == 2 ? (uint32_t)((g_i32*)A.data)[v] : (uint32_t)((g_i64*)A.data)[v];
+        rset4_32(X.x, dst - 1, x);
+      }
+    }
+  }
+}
+
 // Coverage and status of the current input into its global counters (the
 // whole workgroup).
 __device__ void flush_rows(RowsLds& S, const KArgs& a, uint32_t input, uint32_t n_sites, uint64_t& acc,
@@ -984,7 +1091,8 @@ __global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
     C.xt = in.xt_begin + (t - tb);
-    rows_thread(S, C, *G, T, act, acc, hangs, sv);
+    if (G->all32) rows_thread32(S, C, *G, T, act, acc, hangs, sv);
+    else rows_thread(S, C, *G, T, act, acc, hangs, sv);
   }
   if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs, sv);
 }
@@ -1478,11 +1586,14 @@ __device__ __forceinline__ void c32_stream(uint32_t* l, const void* data, uint32
 // One round of the contiguous form: U chunks of TILE iterations from base.
 // FULL: the whole round lies before it1.  An entry indexed by the counter with
 // coefficient 1 whose round of indices lies inside its allocation (one
-// uniform comparison) takes no per-iteration check.
-template <uint32_t U, bool FULL>
+// uniform comparison) takes no per-iteration check.  NL: the body's loads
+// (one or two; with one, the second loaded value's registers do not exist).
+// PRE: entry 0 is the body's one load, streamed by the caller into pre.
+template <uint32_t U, bool FULL, uint32_t NL, bool PRE = false>
 __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C, uint64_t base, uint64_t it0,
                                           uint64_t it1, uint32_t d32, uint32_t n, uint64_t lane0, uint32_t mode,
-                                          const uint32_t* TS, bool run, uint32_t& mine, uint64_t& visits) {
+                                          const uint32_t* TS, bool run, uint32_t& mine, uint64_t& visits,
+                                          const uint32_t* pre = nullptr) {
   const uint32_t tid = threadIdx.x;
   uint32_t l1[U], l2[U];
   bool act[U];
@@ -1490,7 +1601,7 @@ __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C
 #pragma unroll
   for (uint32_t q = 0; q < U; q++) {
     act[q] = FULL || base + q * TILE + tid < it1;
-    l1[q] = 0;
+    l1[q] = PRE ? pre[q] : 0u;
     l2[q] = 0;
     if (!FULL) {
       mine += act[q] ? 1u : 0u;
@@ -1501,7 +1612,7 @@ __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C
     mine += U;
     visits += (uint64_t)U * 64;
   }
-  for (uint32_t e = 0; e < n; e++) {
+  for (uint32_t e = PRE ? 1u : 0u; e < n; e++) {
     const GEnt& E = S.gb.e[e];
     const uint32_t meta = ufirst((uint32_t)E.var | ((uint32_t)E.dst << 8) | ((uint32_t)E.lg << 16) |
                                  ((uint32_t)(E.coef == 1) << 24) | ((uint32_t)(E.dead != 0) << 25));
@@ -1528,11 +1639,11 @@ __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C
   vio = c32_entry<U, XV, DV, FULL>(c0, l1, l2, act, off, coef, c1, bnd, dead, lg2 ? 2u : 3u, data, R32, tid)
 #define C32D(XV)                  \
   if (dst == 0 || none) C32E(XV, 0); \
-  else if (dst == 1) C32E(XV, 1);   \
+  else if (NL == 1 || dst == 1) C32E(XV, 1); \
   else C32E(XV, 2)
     if (var == 0xFF) { C32D(-1); }
     else if (var == 0) { C32D(0); }
-    else if (var == 1) { C32D(1); }
+    else if (NL == 1 || var == 1) { C32D(1); }
     else { C32D(2); }
 #undef C32D
 #undef C32E
@@ -1574,7 +1685,7 @@ __device__ __forceinline__ void c32_round(GenLds& S, uint32_t* R32, const Ctx& C
 // spans a run of chained tiles (full thread set only): a violation's owner is
 // not looked up here, merge_vio_run keeps the least violating iteration per
 // entry instead.
-template <bool BIG>
+template <bool BIG, uint32_t NL>
 __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
                                            uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
                                            const uint32_t* TS, uint32_t site_iter, uint32_t d32, bool run) {
@@ -1583,12 +1694,35 @@ __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& 
   uint64_t visits = 0;
   uint32_t mine = 0;
   uint64_t base = it0;
+  if (BIG && NL == 1 && it1 - it0 >= 2ull * TILE * UL) {
+    // entry 0 the body's only load, of 32-bit elements at the counter, every
+    // index of the whole rounds in bounds: the next round's loads are issued
+    // before the current round is checked (twice the loads in flight)
+    const GEnt& E0 = S.gb.e[0];
+    const uint32_t m0 = ufirst((uint32_t)E0.var | ((uint32_t)E0.dst << 8) | ((uint32_t)E0.lg << 16) |
+                               ((uint32_t)(E0.coef == 1) << 24) | ((uint32_t)(E0.dead != 0) << 25));
+    const uint64_t nr = (it1 - it0) / ((uint64_t)TILE * UL);  // whole rounds
+    const uint32_t i0 = ufirst((uint32_t)E0.off + d32 + (uint32_t)it0);
+    const uint64_t b64 = ufirst64(E0.bound);
+    const uint64_t bnd = b64 > 0x80000000ull ? 0x80000000ull : b64;
+    if (m0 == ((0u) | (1u << 8) | (2u << 16) | (1u << 24)) && (uint64_t)i0 + nr * TILE * UL <= bnd) {
+      const void* data0 = (const void*)ufirst64((uint64_t)E0.data);
+      uint32_t la[UL], lb[UL];
+      c32_stream<UL, true>(la, data0, i0, threadIdx.x);
+      for (uint64_t r = 0; r < nr; r++, base += (uint64_t)TILE * UL) {
+        if (r + 1 < nr) c32_stream<UL, true>(lb, data0, i0 + (uint32_t)((r + 1) * TILE * UL), threadIdx.x);
+        c32_round<UL, true, NL, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits, la);
+#pragma unroll
+        for (uint32_t q = 0; q < UL; q++) la[q] = lb[q];
+      }
+    }
+  }
   if (BIG)
     for (; base + (uint64_t)TILE * UL <= it1; base += (uint64_t)TILE * UL)
-      c32_round<UL, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
+      c32_round<UL, true, NL>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
   for (; base + (uint64_t)TILE * US <= it1; base += (uint64_t)TILE * US)
-    c32_round<US, true>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
-  if (base < it1) c32_round<US, false>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
+    c32_round<US, true, NL>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
+  if (base < it1) c32_round<US, false, NL>(S, R32, C, base, it0, it1, d32, n, lane0, mode, TS, run, mine, visits);
   // visits of the counter's site and of every entry's site
   const uint32_t vc = (uint32_t)(visits < 0xFFFFFFFFull ? visits : 0xFFFFFFFFull);
   count_site_n(S, C, sat, site_iter, vc);
@@ -1931,12 +2065,15 @@ __global__ void __launch_bounds__(TILE, BIG ? 4 : 3) eval_gather_kernel(KArgs a)
       built = 1;
       ok = S.gb.ok;
       // all-32-bit bodies with at most two loads take the contiguous form
+      // fast: 1 or 2 for bodies of at most one or two loads, 0 otherwise
       fast = S.gb.n >= 1 && S.gb.n <= GREG && Lx.w == 32;
+      uint32_t nl = 1;
       for (uint32_t e = 0; e < S.gb.n && e < GREG; e++) {
         const GEnt& E = S.gb.e[e];
         if (E.w != 32 || (E.var != 0xFF && E.var > 2) || E.dst > 2) fast = 0;
+        nl = E.dst > nl ? E.dst : nl;
       }
-      fast = ufirst(fast);
+      fast = ufirst(fast ? nl : 0u);
     }
     if (!ok) continue;  // cannot happen for a body the loader accepted
     if (fast && cont) {
@@ -1994,7 +2131,10 @@ __global__ void __launch_bounds__(TILE, BIG ? 4 : 3) eval_gather_kernel(KArgs a)
           run = true;
         }
       }
-      gather_c32<BIG>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd, run);
+      if (fast == 1)
+        gather_c32<BIG, 1>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd, run);
+      else
+        gather_c32<BIG, 2>(S, (uint32_t*)R, C, ln, sat, it0, iend, lane0, cur_mode, cur_L, Lx.s0, (uint32_t)xd, run);
       if (run) {
         end_run(S, C, xs, lane0, S.gb.n);
         cur_xt = ~0ull;  // the next piece sets its tile up afresh

@@ -663,6 +663,10 @@ __device__ void build_rows(drows& G, RowWalk& Wk, const dprog* P, const int64_t*
       }
     }
     G.ncls = ncls;
+    uint32_t all32 = 1;
+    for (uint32_t q = 0; q < n; q++)
+      if (G.e[q].kind != RE_ENDG && G.e[q].w != 32) all32 = 0;
+    G.all32 = all32;
     G.n = n;
     G.ok = ok;
   }

@@ -148,7 +148,8 @@ struct drows {
   REnt e[MAX_RENT];
   int64_t cc[MAX_RCLS][6];      // coefficient vectors of the coordinate classes
   uint64_t livein[MAX_LIVEIN];  // the loop's live-ins (uniform)
-  uint32_t n, ok, ncls, pad;
+  uint32_t n, ok, ncls;
+  uint32_t all32;  // every entry is 32 bits wide: the rows kernel evaluates in 32-bit arithmetic
 };
 static_assert(sizeof(drows) % 16 == 0, "rows form alignment");
 

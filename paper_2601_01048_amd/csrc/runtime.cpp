@@ -356,7 +356,9 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
     eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);
     // interpreter tiles: by default several per work item when there are
     // plenty (each item costs a schedule step and a lookup of its input)
-    eg.chunk[p] = O.chunk ? O.chunk : (p == PATH_GENERIC && S.gen_tiles >= 16ull * eg.n_wg[p] ? 4u : 1u);
+    // (16 for the rows-form kernel, whose tiles cost less)
+    eg.chunk[p] = O.chunk ? O.chunk
+                          : (p == PATH_GENERIC && S.gen_tiles >= 16ull * eg.n_wg[p] ? (a.rows_only ? 16u : 4u) : 1u);
   }
   eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
   // body passes: pieces are near-equal work, and a workgroup walking one
