@@ -360,13 +360,14 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
     eg.chunk[p] = O.chunk ? O.chunk
                           : (p == PATH_GENERIC && S.gen_tiles >= 16ull * eg.n_wg[p] ? (a.rows_only ? 16u : 4u) : 1u);
   }
-  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
   // body passes: pieces are near-equal work, and a workgroup walking one
   // contiguous range of them finds each piece's tile by a step from the last
   eg.sched_body = O.schedule ? O.schedule : CKC_SCHED_BLOCKED;
   // long gather ranges (inputs of 64 tiles or more on average) take the
-  // variant with larger rounds
+  // variant with larger rounds, one workgroup per resident slot (4 per CU:
+  // a second wave of workgroups costs more than it balances)
   eg.big_body = S.n_xin != 0 && S.n_xtiles >= 64 * S.n_xin ? 1u : 0u;
+  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : eg.big_body ? 4u : 8u);
   return CKC_OK;
 }
 
