@@ -1689,7 +1689,8 @@ template <bool BIG, uint32_t NL>
 __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& C, Lane& ln, uint64_t& sat,
                                            uint64_t it0, uint64_t it1, uint64_t lane0, uint32_t mode,
                                            const uint32_t* TS, uint32_t site_iter, uint32_t d32, bool run) {
-  constexpr uint32_t UL = 16, US = 8;  // R32 rows: at most 16
+  // R32 rows: UL (the launch gives large-round jobs at least 32 rows)
+  constexpr uint32_t UL = NL == 1 ? 32 : 16, US = 8;
   const uint32_t n = S.gb.n, faults = S.gb.faults;
   uint64_t visits = 0;
   uint32_t mine = 0;
@@ -1940,7 +1941,7 @@ __global__ void __launch_bounds__(TILE, 4) eval_body_kernel(KArgs a) {
 // in LDS with the tile's prefix, so an iteration costs one memory round trip
 // per dependent load of the body.
 template <uint32_t SK, bool BIG>
-__global__ void __launch_bounds__(TILE, BIG ? 4 : 3) eval_gather_kernel(KArgs a) {
+__global__ void __launch_bounds__(TILE, BIG ? 2 : 3) eval_gather_kernel(KArgs a) {
   __shared__ GenLds S;
   extern __shared__ uint64_t R[];  // rows: counter and loaded values per lane; the build uses [n_regs]
   __shared__ unsigned long long item_slot;

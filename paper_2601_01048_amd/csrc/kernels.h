@@ -50,6 +50,12 @@ struct KArgs {
 // At least 8 rows: the gather evaluation of expanded bodies keeps the counter
 // and up to 7 loaded values there.
 inline uint32_t regfile_bytes(const KArgs& a) { return (a.max_regs > 8u ? a.max_regs : 8u) * TILE * 8u; }
+// Dynamic LDS of the gather pass: the register file, and for the variant with
+// large rounds at least 32 rows of TILE 32-bit index values.
+inline uint32_t body_lds_bytes(const KArgs& a, uint32_t big) {
+  const uint32_t r = regfile_bytes(a);
+  return big && r < 32u * TILE * 4u ? 32u * TILE * 4u : r;
+}
 // LDS bytes of the planning wavefront's symbolic register file.
 inline uint32_t plan_lds_bytes(const KArgs& a) { return (a.max_regs > 1u ? a.max_regs : 1u) * 64u * 8u; }
 

@@ -180,7 +180,7 @@ hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
       e = hipLaunchKernel(body_fn(eg.sched_body, which, eg.big_body), dim3(eg.n_wg_body), dim3(TILE), args,
-                          regfile_bytes(a), s);
+                          body_lds_bytes(a, which == 1 && eg.big_body), s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -256,7 +256,7 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
       if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, argsw[which]);
       if (e == hipSuccess)
         e = add_node(g, &xb[which], &x3, 1, body_fn(eg.sched_body, which, eg.big_body), eg.n_wg_body, TILE,
-                     argsp[PATH_GENERIC], regfile_bytes(a));
+                     argsp[PATH_GENERIC], body_lds_bytes(a, which == 1 && eg.big_body));
     }
     if (e != hipSuccess) return e;
     // the replay waits for both body passes

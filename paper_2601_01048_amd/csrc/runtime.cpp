@@ -364,10 +364,11 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   // contiguous range of them finds each piece's tile by a step from the last
   eg.sched_body = O.schedule ? O.schedule : CKC_SCHED_BLOCKED;
   // long gather ranges (inputs of 64 tiles or more on average) take the
-  // variant with larger rounds, one workgroup per resident slot (4 per CU:
-  // a second wave of workgroups costs more than it balances)
+  // variant with larger rounds (2 wavefronts per SIMD: the registers hold a
+  // round's loads and the next round's), one workgroup per resident slot (a
+  // second wave of workgroups costs more than it balances)
   eg.big_body = S.n_xin != 0 && S.n_xtiles >= 64 * S.n_xin ? 1u : 0u;
-  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : eg.big_body ? 4u : 8u);
+  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : eg.big_body ? 2u : 8u);
   return CKC_OK;
 }
 
