@@ -66,7 +66,8 @@ struct EvalGrid {
   uint32_t chunk[3];
   uint32_t n_wg_body;   // workgroups of the body passes of expanded loops
   uint32_t sched_body;  // schedule of the body passes
-  uint32_t big_body;    // gather pass with 16-chunk rounds (inputs of many tiles)
+  uint32_t big_body;    // gather pass with large rounds (inputs of many tiles)
+  uint32_t body_kinds;  // body passes with work: bit 0 interpreted bodies, bit 1 gather bodies
 };
 
 // The PREX sweep (Algorithm 1) runs in windows of rounds.  A window is an

@@ -174,6 +174,7 @@ hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
   KArgs k = with_sched(a, eg, PATH_GENERIC);
   void* args[] = {&k};
   for (uint32_t which = 0; which < 2; which++) {
+    if (!((eg.body_kinds >> which) & 1u)) continue;  // no body of this kind in the job
     hipLaunchKernelGGL(xscan_sums_kernel, dim3(nb), dim3(256), 0, s, a, which);
     hipLaunchKernelGGL(xscan_blocks_kernel, dim3(1), dim3(1024), 0, s, a, nb, which);
     hipLaunchKernelGGL(xscan_apply_kernel, dim3(nb), dim3(256), 0, s, a, which);
@@ -249,19 +250,21 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
     void* argsw[2][2] = {{&ka, &wh[0]}, {&ka, &wh[1]}};
     void* argsb[2][3] = {{&ka, &nb, &wh[0]}, {&ka, &nb, &wh[1]}};
     hipGraphNode_t xb[2];
+    uint32_t nxb = 0;
     for (uint32_t which = 0; which < 2 && e == hipSuccess; which++) {
+      if (!((eg.body_kinds >> which) & 1u)) continue;  // no body of this kind in the job
       hipGraphNode_t x1, x2, x3;
       e = add_node(g, &x1, &ev[1], 1, (void*)xscan_sums_kernel, nb, 256, argsw[which]);
       if (e == hipSuccess) e = add_node(g, &x2, &x1, 1, (void*)xscan_blocks_kernel, 1, 1024, argsb[which]);
       if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, argsw[which]);
       if (e == hipSuccess)
-        e = add_node(g, &xb[which], &x3, 1, body_fn(eg.sched_body, which, eg.big_body), eg.n_wg_body, TILE,
+        e = add_node(g, &xb[nxb++], &x3, 1, body_fn(eg.sched_body, which, eg.big_body), eg.n_wg_body, TILE,
                      argsp[PATH_GENERIC], body_lds_bytes(a, which == 1 && eg.big_body));
     }
     if (e != hipSuccess) return e;
     // the replay waits for both body passes
     hipGraphNode_t join;
-    e = hipGraphAddEmptyNode(&join, g, xb, 2);
+    e = hipGraphAddEmptyNode(&join, g, xb, nxb);
     if (e != hipSuccess) return e;
     ev[1] = join;
   }

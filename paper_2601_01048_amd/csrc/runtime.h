@@ -61,6 +61,7 @@ struct Stage {
   uint32_t sh_bytes = 0;  // LDS of the shared-memory instances of a tile (blockwise programs)
   bool capture = false;   // some input needs the capture pass
   bool all_rows = true;   // every input's program takes the rows form (PF_ROWS, exact bounds)
+  uint32_t body_kinds = 0;  // expanded loops: bit 0 some interpreted body, bit 1 some gather body
 
   // Notes an input of a blockwise program (PF_BLOCKWISE): each tile holds
   // TILE / bs of its blocks, each with one instance of every shared slot (a
@@ -96,6 +97,7 @@ struct Stage {
     sh_bytes = 0;
     capture = false;
     all_rows = true;
+    body_kinds = 0;
   }
 
   // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;
@@ -124,6 +126,7 @@ struct Stage {
       n_xtiles += n_xt;
       n_xin++;
       xstate_bytes += d.xn * 8 * (3 + (uint64_t)h->n_livein);
+      body_kinds |= h->body_gather && !d.detector ? 2u : 1u;
     }
     if (!(h->pflags & PF_ROWS) || d.detector) all_rows = false;
     hin.push_back(d);
