@@ -64,7 +64,8 @@ struct EvalGrid {
   uint32_t n_wg[3];
   uint32_t sched[3];
   uint32_t chunk[3];
-  uint32_t n_wg_body;   // workgroups of the body passes of expanded loops
+  uint32_t n_wg_body;   // workgroups of the body passes of expanded loops (the gather pass: n_wg_gather)
+  uint32_t n_wg_gather;
   uint32_t sched_body;  // schedule of the body passes
   uint32_t big_body;    // gather pass with large rounds (inputs of many tiles)
   uint32_t body_kinds;  // body passes with work: bit 0 interpreted bodies, bit 1 gather bodies

@@ -180,8 +180,8 @@ hipError_t launch_expand(const KArgs& a, const EvalGrid& eg, hipStream_t s) {
     hipLaunchKernelGGL(xscan_apply_kernel, dim3(nb), dim3(256), 0, s, a, which);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
-      e = hipLaunchKernel(body_fn(eg.sched_body, which, eg.big_body), dim3(eg.n_wg_body), dim3(TILE), args,
-                          body_lds_bytes(a, which == 1 && eg.big_body), s);
+      e = hipLaunchKernel(body_fn(eg.sched_body, which, eg.big_body), dim3(which ? eg.n_wg_gather : eg.n_wg_body),
+                          dim3(TILE), args, body_lds_bytes(a, which == 1 && eg.big_body), s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -258,8 +258,9 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
       if (e == hipSuccess) e = add_node(g, &x2, &x1, 1, (void*)xscan_blocks_kernel, 1, 1024, argsb[which]);
       if (e == hipSuccess) e = add_node(g, &x3, &x2, 1, (void*)xscan_apply_kernel, nb, 256, argsw[which]);
       if (e == hipSuccess)
-        e = add_node(g, &xb[nxb++], &x3, 1, body_fn(eg.sched_body, which, eg.big_body), eg.n_wg_body, TILE,
-                     argsp[PATH_GENERIC], body_lds_bytes(a, which == 1 && eg.big_body));
+        e = add_node(g, &xb[nxb++], &x3, 1, body_fn(eg.sched_body, which, eg.big_body),
+                     which ? eg.n_wg_gather : eg.n_wg_body, TILE, argsp[PATH_GENERIC],
+                     body_lds_bytes(a, which == 1 && eg.big_body));
     }
     if (e != hipSuccess) return e;
     // the replay waits for both body passes

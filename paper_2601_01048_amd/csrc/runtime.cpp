@@ -369,7 +369,8 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   // second wave of workgroups costs more than it balances)
   eg.big_body = S.n_xin != 0 && S.n_xtiles >= 64 * S.n_xin ? 1u : 0u;
   eg.body_kinds = S.body_kinds;
-  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : eg.big_body ? 2u : 8u);
+  eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
+  eg.n_wg_gather = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : eg.big_body ? 2u : 8u);
   return CKC_OK;
 }
 
