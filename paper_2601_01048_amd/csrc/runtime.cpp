@@ -60,12 +60,12 @@ void free_job(ckc_ctx c, Job& J) {
       c->pool.emplace(b.first, b.second);
       c->pool_bytes += b.first;
     } else {
-      hipFree(b.second);
+      (void)hipFree(b.second);
     }
   }
   J.bufs.clear();
   for (auto& e : J.ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (uint32_t p : J.progs) {
     auto it = c->progs.find(p);
     if (it != c->progs.end()) it->second.busy--;
@@ -83,9 +83,9 @@ void reap(ckc_ctx c, bool wait) {
   size_t k = 0;
   for (size_t q = 0; q < R.size(); q++) {
     hipEvent_t ev = R[q].first;
-    const bool done = wait ? (hipEventSynchronize(ev), true) : hipEventQuery(ev) != hipErrorNotReady;
+    const bool done = wait ? ((void)hipEventSynchronize(ev), true) : hipEventQuery(ev) != hipErrorNotReady;
     if (done) {
-      hipEventDestroy(ev);
+      (void)hipEventDestroy(ev);
       free_job(c, R[q].second);
     } else {
       if (k != q) R[k] = std::move(R[q]);
@@ -110,7 +110,7 @@ int dalloc(ckc_ctx c, Job& J, T** out, size_t count) {
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {  // release retiring jobs and pooled buffers, retry once
       reap(c, true);
-      for (auto& kv : c->pool) hipFree(kv.second);
+      for (auto& kv : c->pool) (void)hipFree(kv.second);
       c->pool.clear();
       c->pool_bytes = 0;
       e = hipMalloc(&p, bytes);
@@ -143,10 +143,10 @@ hipError_t launch_graph(ckc_ctx c, const KArgs& a, const EvalGrid& eg, uint64_t 
     e = build_job_graph(g, a, eg, n_records);
     hipGraphExec_t x = nullptr;
     if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return e;
     if (c->graphs.size() >= 32) {  // keep the cache small
-      hipGraphExecDestroy(c->graphs.begin()->second);
+      (void)hipGraphExecDestroy(c->graphs.begin()->second);
       c->graphs.erase(c->graphs.begin());
     }
     it = c->graphs.emplace(key, x).first;
@@ -511,7 +511,7 @@ int check_prex(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const ckc_la
   J.dense = false;
   for (uint32_t k = 0; k < n_descs; k++) J.dense |= (descs[k].flags & CKC_DENSE_MAP) != 0;
   auto bail = [&](int code) {
-    hipStreamSynchronize(J.stream);
+    (void)hipStreamSynchronize(J.stream);
     free_job(c, J);
     return code;
   };
@@ -676,14 +676,14 @@ int ckc_init(int hip_device, ckc_ctx* out) {
   // device is current) and host staging room for its largest call
   e = ckc::scratch_address(hip_device, &c->scratch);
   if (e != hipSuccess) {
-    hipStreamDestroy(c->stream);
+    (void)hipStreamDestroy(c->stream);
     delete c;
     return fail(CKC_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
   }
   try {
     c->na_stage.reserve(CKC_NOALLOC_MAX_INPUTS);
   } catch (const std::bad_alloc&) {
-    hipStreamDestroy(c->stream);
+    (void)hipStreamDestroy(c->stream);
     delete c;
     return fail(CKC_E_NOMEM, "context staging arrays");
   }
@@ -693,18 +693,18 @@ int ckc_init(int hip_device, ckc_ctx* out) {
 
 void ckc_shutdown(ckc_ctx c) {
   if (!c) return;
-  hipSetDevice(c->dev);
+  (void)hipSetDevice(c->dev);
   reap(c, true);
   for (auto& kv : c->jobs) {
-    if (kv.second.stream) hipStreamSynchronize(kv.second.stream);
+    if (kv.second.stream) (void)hipStreamSynchronize(kv.second.stream);
     free_job(c, kv.second);
   }
   c->jobs.clear();
-  for (auto& kv : c->progs) hipFree(kv.second.dblob);
-  for (auto& kv : c->tables) hipFree(kv.second.dptr);
-  for (auto& kv : c->pool) hipFree(kv.second);
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
-  if (c->stream) hipStreamDestroy(c->stream);
+  for (auto& kv : c->progs) (void)hipFree(kv.second.dblob);
+  for (auto& kv : c->tables) (void)hipFree(kv.second.dptr);
+  for (auto& kv : c->pool) (void)hipFree(kv.second);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -731,7 +731,7 @@ int ckc_load_program(ckc_ctx c, const void* ir, size_t ir_bytes, uint32_t* prog_
   if (e != hipSuccess) return fail(CKC_E_NOMEM, "program upload");
   e = hipMemcpy(P.dblob, P.L.blob.data(), P.L.blob.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(P.dblob);
+    (void)hipFree(P.dblob);
     return fail(CKC_E_HIP, std::string("program upload: ") + hipGetErrorString(e));
   }
   uint32_t id = c->next_prog++;
@@ -770,7 +770,7 @@ int ckc_unload_program(ckc_ctx c, uint32_t prog_id) {
   if (it->second.busy) reap(c, true);
   if (it->second.busy) return fail(CKC_E_BUSY, "program used by an unread job");
   set_device(c);
-  hipFree(it->second.dblob);
+  (void)hipFree(it->second.dblob);
   c->progs.erase(it);
   return CKC_OK;
 }
@@ -787,7 +787,7 @@ int ckc_put_alloc_table(ckc_ctx c, const ckc_alloc* entries, uint32_t n, uint32_
   if (e != hipSuccess) return fail(CKC_E_NOMEM, "table");
   e = hipMemcpy(T.dptr, T.host.data(), sizeof(ckc_alloc) * MAX_SLOTS, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(T.dptr);
+    (void)hipFree(T.dptr);
     return fail(CKC_E_HIP, std::string("table upload: ") + hipGetErrorString(e));
   }
   T.host.resize(n);
@@ -804,7 +804,7 @@ int ckc_free_alloc_table(ckc_ctx c, uint32_t table_id) {
   if (it->second.busy) reap(c, true);
   if (it->second.busy) return fail(CKC_E_BUSY, "table used by an unread job");
   set_device(c);
-  hipFree(it->second.dptr);
+  (void)hipFree(it->second.dptr);
   c->tables.erase(it);
   return CKC_OK;
 }
@@ -843,7 +843,7 @@ int ckc_check_batch(ckc_ctx c, const ckc_batch* descs, uint32_t n_descs, const c
   J.dense = false;
   for (uint32_t k = 0; k < n_descs; k++) J.dense |= (descs[k].flags & CKC_DENSE_MAP) != 0;
   auto bail = [&](int code) {
-    hipStreamSynchronize(J.stream);
+    (void)hipStreamSynchronize(J.stream);
     free_job(c, J);
     return code;
   };
@@ -990,7 +990,7 @@ int ckc_read_results(ckc_ctx c, uint64_t job, ckc_record* recs, uint8_t* maps, c
       c->jobs.erase(it);
       return CKC_OK;
     }
-    if (done) hipEventDestroy(done);
+    if (done) (void)hipEventDestroy(done);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(J.stream);
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("readback: ") + hipGetErrorString(e));
