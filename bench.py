@@ -663,7 +663,7 @@ def main():
             progress("served done")
             result["served"] = {k: sv[k] for k in ("value", "unit", "p50_ms", "p99_ms", "p999_ms", "mean_ms",
                                                     "max_ms", "jobs_per_s", "offered_accesses_per_s", "roofline",
-                                                    "config", "server")}
+                                                    "config", "server", "submit_lag")}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args)
         progress("cpu baseline done")
