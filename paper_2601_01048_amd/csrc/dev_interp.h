@@ -1709,6 +1709,8 @@ __device__ __forceinline__ void gather_c32(GenLds& S, uint32_t* R32, const Ctx& 
     if (m0 == ((0u) | (1u << 8) | (2u << 16) | (1u << 24)) && (uint64_t)i0 + nr * TILE * UL <= bnd) {
       const void* data0 = (const void*)ufirst64((uint64_t)E0.data);
       uint32_t la[UL], lb[UL];
+#pragma unroll
+      for (uint32_t q = 0; q < UL; q++) lb[q] = 0;  // the last round loads no next one
       c32_stream<UL, true>(la, data0, i0, threadIdx.x);
       for (uint64_t r = 0; r < nr; r++, base += (uint64_t)TILE * UL) {
         if (r + 1 < nr) c32_stream<UL, true>(lb, data0, i0 + (uint32_t)((r + 1) * TILE * UL), threadIdx.x);
