@@ -115,3 +115,64 @@ def rows_workload(rng, ir, n_inputs=6, mode=W.MODE_FULL, cap=(20, 12)):
         tables[i] = tabs[i]
     return W.Workload("rows", ir, launches, np.array(scal, np.int64), tables,
                       np.arange(n_inputs, dtype=np.uint32), [P, C], mode, cap)
+
+
+def extreme_rows_program():
+    """A 32-bit rows-form program whose loop bounds come from loaded values
+    near the ends of the int32 range and whose last index is the row times a
+    scalar (wrapping modulo 2^32): r = bid.x * bdim.x + tid.x; if r < s0:
+    [s, e) = P[r], P[r + 1]; for j in [s, e): X[C[j]]; Y[r * s1]."""
+    p = Program(n_scalars=2, n_slots=4)
+    w = 32
+    r = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), w), p.special("tid.x"), w)
+    pred = p.op("CMPLTS", r, p.scalar(0, w), w)
+    p._emit("IF", 0, 0xFFFF, pred.idx, 0, 0, 0, p._site_arg(True), p._site_arg(True))
+    p._open.append("IF")
+    s = p.load(0, r, elem=4, w=w)
+    e = p.load(0, p.add(r, p.const(1, w), w), elem=4, w=w)
+    with p.loop(s, e, p.const(1, w), w=w, site_iter=True, site_exit=True) as j:
+        c = p.load(1, j, elem=4, w=w)
+        p.access(2, c, w=w)
+    p.access(3, p.mul(r, p.scalar(1, w), w), w=w)
+    assert p._open.pop() == "IF"
+    p._emit("ENDIF")
+    return p.to_bytes()
+
+
+def extreme_rows_workload(rng, ir, n_inputs=4):
+    """Row pointers with ordinary rows and rows whose bounds sit near
+    INT32_MIN and INT32_MAX (spans of a few iterations there, spans over the
+    trip cap across the range, bounds in both orders); multipliers of the last
+    index that wrap it to either sign."""
+    n_rows = 2000
+    lens = rng.integers(0, 5, size=n_rows)
+    P = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    i32min, i32max = -(1 << 31), (1 << 31) - 1
+    for r in rng.choice(n_rows - 1, size=40, replace=False):
+        k = int(rng.integers(5))
+        if k == 0:
+            P[r], P[r + 1] = i32max - int(rng.integers(1, 9)), i32max
+        elif k == 1:
+            P[r], P[r + 1] = i32min, i32min + int(rng.integers(1, 9))
+        elif k == 2:
+            P[r], P[r + 1] = i32min + int(rng.integers(0, 9)), i32max - int(rng.integers(0, 9))
+        elif k == 3:
+            P[r], P[r + 1] = i32max, i32min
+        else:
+            P[r], P[r + 1] = -int(rng.integers(1, 50)), int(rng.integers(1, 50))
+    P = P.astype(np.int32)
+    nnz = int(lens.sum()) + 64
+    C = rng.integers(-5, 1200, size=nnz).astype(np.int32)
+    launches, tabs, scal = [], [], []
+    mults = [0x40000003, -0x3FFFFFFD, 7, 0x7FFFFFFF]
+    for i in range(n_inputs):
+        bs = int(rng.choice([64, 256]))
+        launches.append([(n_rows + bs - 1) // bs, 1, 1, bs, 1, 1])
+        tabs.append([(LB, 4 * (n_rows + 1), 1, 0, 0), (LB + (1 << 30), 4 * nnz, 2, 0, 0),
+                     (LB + (2 << 30), 4 * 1024, 0, 0, 0), (LB + (3 << 30), 4 * 4096, 0, 0, 0)])
+        scal.append([n_rows - int(rng.integers(0, 3)), mults[i % len(mults)]])
+    tables = np.zeros((n_inputs, 4), W.ALLOC_DTYPE)
+    for i in range(n_inputs):
+        tables[i] = tabs[i]
+    return W.Workload("rows_extreme", ir, np.array(launches, np.uint32), np.array(scal, np.int64), tables,
+                      np.arange(n_inputs, dtype=np.uint32), [P, C], W.MODE_FULL, (20, 12))

@@ -60,3 +60,21 @@ def test_csr_batch_rows_form(ctx):
     gather loop, y[r]) at both widths, whole grid."""
     for w in (32, 64):
         check_same(ctx, W.mini("config3", w=w), what=f"csr i{w}")
+
+
+@pytest.mark.parametrize("cap", [(20, 12), (4, 12)])
+def test_rows_32bit_extremes(ctx, cap):
+    """The 32-bit evaluation of the rows form at the ends of the int32 range:
+    loop bounds loaded near INT32_MIN and INT32_MAX (short spans there, spans
+    across the whole range that exceed the trip cap, reversed bounds), and an
+    index that wraps modulo 2^32 to either sign.  The program is all 32-bit,
+    so the rows kernel takes its 32-bit path; checked against the oracle in the
+    whole grid and the boundary set."""
+    rng = np.random.default_rng(77 + cap[0])
+    ir = RP.extreme_rows_program()
+    wl = RP.extreme_rows_workload(rng, ir)
+    wl.cap_log2 = cap
+    for mode in (W.MODE_FULL, W.MODE_BOUNDARY):
+        g, o = check_same(ctx, wl, mode=mode, what=f"extremes cap={cap[0]}")
+        assert int(o["status"]["hang_lanes"].sum()) > 0
+        assert int(o["records"]["count"].sum()) > 0
