@@ -95,7 +95,7 @@ def gather_workload(rng, ir, n_inputs=4):
                       np.arange(n_inputs, dtype=np.uint32), [D, E], W.MODE_FULL, (20, 12))
 
 
-def csr_runs_workload(seed: int, log2_rows: int = 15, n_inputs: int = 4):
+def csr_runs_workload(seed: int, log2_rows: int = 15, n_inputs: int = 4, col_short: int = 0):
     """CSR gathers (the F3 program) whose row pointers exercise how the gather
     pass joins consecutive contiguous tiles of 256 rows into one run:
     input 0 a plain matrix (every tile continues the one before); input 1
@@ -105,7 +105,9 @@ def csr_runs_workload(seed: int, log2_rows: int = 15, n_inputs: int = 4):
     rows running backwards inside tiles (tiles not contiguous).  Every input
     has its own corrupted col_idx, a val allocation that ends before the last
     nonzeros (violations in late tiles of long runs) and an x allocation short
-    of ncols (violations spread over every tile)."""
+    of ncols (violations spread over every tile).  col_short > 0 also ends the
+    col_idx allocation that many elements before the last nonzero (the loaded
+    index runs out of bounds inside the last run)."""
     rng = np.random.default_rng(seed)
     data, tables, launch, scalars = [], [], [], []
     for i in range(n_inputs):
@@ -129,7 +131,7 @@ def csr_runs_workload(seed: int, log2_rows: int = 15, n_inputs: int = 4):
         data += [rp.astype(np.int32), col]
         val_len = nnz - int(rng.integers(1, 2000))
         tables.append([W.alloc((nrows + 1) * 4, len(data) - 1, W.LOGICAL_BASE),
-                       W.alloc(nnz * 4, len(data), W.LOGICAL_BASE + (1 << 36)),
+                       W.alloc((nnz - col_short) * 4, len(data), W.LOGICAL_BASE + (1 << 36)),
                        W.alloc(val_len * 4, 0, W.LOGICAL_BASE + (2 << 36)),
                        W.alloc((ncols - int(rng.integers(100, 1000))) * 4, 0, W.LOGICAL_BASE + (3 << 36)),
                        W.alloc(nrows * 4, 0, W.LOGICAL_BASE + (4 << 36))])

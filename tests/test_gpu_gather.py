@@ -54,6 +54,22 @@ def test_gather_tile_runs(ctx, schedule, wg, log2_rows):
     assert (o["records"]["count"][:, 3] > 0).all() and (o["records"]["count"][:, 4] > 100).all()
 
 
+@pytest.mark.parametrize("col_short", [1, 5000])
+def test_gather_runs_loaded_index_out_of_bounds(ctx, col_short):
+    """Runs of chained tiles whose loaded array (col_idx) ends before the last
+    nonzeros: the rounds that reach its end cannot stream it unchecked (the
+    next round's loads are issued early only while every index of the run's
+    whole rounds is in bounds), and its out-of-bounds indices are violations
+    with nothing loaded."""
+    from test_gpu_parity import compare
+    wl = G.csr_runs_workload(13, log2_rows=15, col_short=col_short)
+    print(f"[case] csr runs col_short {col_short}", flush=True)
+    g = ckc.run_workload(ctx, wl)
+    o = O.check(wl, nthreads=4)
+    compare(g, o, what=f"csr runs col_short {col_short}")
+    assert (o["records"]["count"][:, 2] == col_short).all()  # the last col_short nonzeros
+
+
 @pytest.mark.parametrize("big", [False, True])
 @pytest.mark.parametrize("seed", range(3))
 def test_long_gather_rounds(ctx, seed, big):
