@@ -69,6 +69,7 @@ struct EvalGrid {
   uint32_t sched_body;  // schedule of the body passes
   uint32_t big_body;    // gather pass with large rounds (inputs of many tiles)
   uint32_t body_kinds;  // body passes with work: bit 0 interpreted bodies, bit 1 gather bodies
+  uint32_t no_trace;    // 1: no input can take a trace path (the trace evaluators are not launched)
 };
 
 // The PREX sweep (Algorithm 1) runs in windows of rounds.  A window is an

@@ -306,7 +306,13 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   ckc_record* recs = ext.recs;
   ckc_input_status* st = ext.st;
   uint8_t* maps = ext.maps;
-  if ((rc = take(B, &d_in, n_inputs)) || (rc = take(B, &sc, S.hsc.size())) || (rc = take(B, &order, n_inputs)) ||
+  // inputs, scalars and order: one buffer, each part at a 256-byte offset,
+  // filled by one copy
+  auto part = [](size_t bytes) { return (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255; };
+  const size_t b_in = part(sizeof(dinput) * n_inputs), b_sc = part(sizeof(int64_t) * S.hsc.size()),
+               b_ord = part(sizeof(uint32_t) * n_inputs);
+  uint8_t* up = nullptr;
+  if ((rc = take(B, &up, b_in + b_sc + b_ord)) ||
       (nx && ((rc = take(B, &xs, S.xstate_bytes)) || (rc = take(B, &xtot, nx)) || (rc = take(B, &xpb, nx)) ||
               (rc = take(B, &xpg, nx)) || (rc = take(B, &xin, nx)) || (rc = take(B, &xd, 2 * nx)) ||
               (rc = take(B, &xbsum, 2 * ((nx + 4095) / 4096))))) ||
@@ -314,16 +320,20 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
       (!st && (rc = take(B, &st, n_inputs))) || (rc = take(B, &js, 1)) || (rc = take(B, &tr, S.trace_bytes)) ||
       (dense && !maps && (rc = take(B, &maps, n_inputs * 65536))))
     return rc;
+  d_in = (dinput*)up;
+  sc = (int64_t*)(up + b_in);
+  order = (uint32_t*)(up + b_in + b_sc);
   for (auto& d : S.hin) {
     if (d.trace) d.trace = (uint64_t)(uintptr_t)(tr + (d.trace - 1));
     if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(xs + (d.xstate - 1));
   }
+  S.hup.assign(b_in + b_sc + b_ord, 0);
+  std::memcpy(S.hup.data(), S.hin.data(), sizeof(dinput) * n_inputs);
+  std::memcpy(S.hup.data() + b_in, S.hsc.data(), sizeof(int64_t) * S.hsc.size());
+  std::memcpy(S.hup.data() + b_in + b_sc, S.order.data(), sizeof(uint32_t) * n_inputs);
   // pageable copies are staged before hipMemcpyAsync returns, so S may be
   // reused afterwards
-  hipError_t e = hipMemcpyAsync(d_in, S.hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(sc, S.hsc.data(), sizeof(int64_t) * S.hsc.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(order, S.order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(up, S.hup.data(), S.hup.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e));
   a.inputs = d_in;
   a.scalars = sc;
@@ -369,6 +379,8 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   // second wave of workgroups costs more than it balances)
   eg.big_body = S.n_xin != 0 && S.n_xtiles >= 64 * S.n_xin ? 1u : 0u;
   eg.body_kinds = S.body_kinds;
+  // the planner sends only uniform programs to the trace paths
+  eg.no_trace = S.any_uniform ? 0u : 1u;
   eg.n_wg_body = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : 8u);
   eg.n_wg_gather = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : eg.big_body ? 2u : 8u);
   return CKC_OK;
@@ -393,8 +405,8 @@ hipError_t launch_evaluation(const KArgs& a, const EvalGrid& eg, hipStream_t s, 
   hipError_t e = launch_plan(a, s);
   if (e == hipSuccess) e = launch_scan(a, s);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
-  if (e == hipSuccess) e = launch_eval_trace(a, eg, s);
-  if (e == hipSuccess) e = launch_eval_trace_lanes(a, eg, s);
+  if (e == hipSuccess && !eg.no_trace) e = launch_eval_trace(a, eg, s);
+  if (e == hipSuccess && !eg.no_trace) e = launch_eval_trace_lanes(a, eg, s);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
   if (e == hipSuccess) e = launch_eval_generic(a, eg, s);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);

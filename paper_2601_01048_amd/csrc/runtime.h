@@ -54,6 +54,7 @@ struct Stage {
   std::vector<int64_t> hsc;
   std::vector<uint64_t> est;     // estimated work per input (LPT order)
   std::vector<uint32_t> order;   // tile-space position -> input (filled when uploaded)
+  std::vector<uint8_t> hup;      // inputs, scalars and order packed for one upload
   uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
   uint32_t max_regs = 1;                               // interpreter register file rows
   uint64_t gen_tiles = 0;  // interpreter tiles (estimate from the launch shapes)
@@ -62,6 +63,7 @@ struct Stage {
   bool capture = false;   // some input needs the capture pass
   bool all_rows = true;   // every input's program takes the rows form (PF_ROWS, exact bounds)
   uint32_t body_kinds = 0;  // expanded loops: bit 0 some interpreted body, bit 1 some gather body
+  bool any_uniform = false;  // some input's program may take a trace path (uniform, not forced generic)
 
   // Notes an input of a blockwise program (PF_BLOCKWISE): each tile holds
   // TILE / bs of its blocks, each with one instance of every shared slot (a
@@ -83,6 +85,7 @@ struct Stage {
     hsc.reserve(n * MAX_SCALARS);
     est.reserve(n);
     order.reserve(n);
+    hup.reserve(n * (sizeof(dinput) + MAX_SCALARS * sizeof(int64_t) + sizeof(uint32_t)) + 3 * 256);
   }
   // Empties the stage and keeps the reserved room.
   void clear() {
@@ -90,6 +93,7 @@ struct Stage {
     hsc.clear();
     est.clear();
     order.clear();
+    hup.clear();
     n_xtiles = xstate_bytes = n_xin = 0;
     max_regs = 1;
     gen_tiles = 0;
@@ -98,6 +102,7 @@ struct Stage {
     capture = false;
     all_rows = true;
     body_kinds = 0;
+    any_uniform = false;
   }
 
   // d: prog, table, launch, mode, aux, L1, L2 and caps set by the caller;
@@ -109,6 +114,7 @@ struct Stage {
     n_records += h->n_accesses;
     n_counts += h->n_sites;
     const bool uniform = (h->cls & CKC_CLS_UNIFORM) && !force_generic;
+    any_uniform |= uniform;
     if (uniform) {
       d.trace = trace_bytes + 1;  // offset + 1 for now; rebased after allocation
       trace_bytes += ckc::trace_bytes(h->trace_cap);
