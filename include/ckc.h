@@ -135,6 +135,10 @@ typedef struct ckc_prog_info {
   uint32_t n_instr_live;   /* instructions left after removing those that feed no
                               index, guard or loop bound */
   uint32_t n_regs_phys;    /* registers after allocation */
+  uint32_t rows_form;      /* 1: the whole-thread part around an expanded gather loop
+                              may run in the rows form (affine forms, no instruction
+                              dispatch; the plan decides per input); 2: and every entry
+                              of that form is 32 bits wide (32-bit evaluation); 0: no */
 } ckc_prog_info;
 
 /* Per-access result of the load-time analysis.  coef[] describes the index

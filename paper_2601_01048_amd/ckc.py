@@ -38,7 +38,7 @@ ALLOC_DTYPE = np.dtype([("base", "<u8"), ("size_bytes", "<u8"), ("data", "<u8"),
 class ProgInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in
                 ("n_accesses", "n_sites", "n_slots", "n_scalars", "max_loop_depth", "cls",
-                 "n_instr_live", "n_regs_phys")]
+                 "n_instr_live", "n_regs_phys", "rows_form")]
 
 
 class AccessInfo(ctypes.Structure):

@@ -33,6 +33,7 @@ typedef const __attribute__((address_space(4))) RForm c_rform;
 // Loaded data through the global address space (global rather than flat loads).
 typedef const __attribute__((address_space(1))) int32_t g_i32;
 typedef const __attribute__((address_space(1))) int64_t g_i64;
+typedef __attribute__((address_space(1))) uint64_t g_u64w;  // written global memory
 
 // Iterations of an expanded loop per work item of the body pass (also the
 // length of the owner map staged in LDS).
@@ -811,18 +812,20 @@ __device__ __forceinline__ void rows_expand(RowsLds& S, const Ctx& C, c_drows& G
   }
   contig = contig && any;
   const uint64_t pre = wpre + incl - cnt;
-  const uint64_t l = C.lane0 + tid;
-  C.xs[l] = pre;
+  // the tile's rows of the state arrays (workgroup-uniform bases, indexed by
+  // the thread)
+  g_u64w* x0 = (g_u64w*)ufirst64((uint64_t)(uintptr_t)(C.xs + C.lane0));
+  x0[tid] = pre;
   if (cnt) {
     if (!(contig && P->body_gather)) {
-      C.xs[C.xn + l] = s0;
-      C.xs[2 * C.xn + l] = stp;
+      x0[C.xn + tid] = s0;
+      x0[2 * C.xn + tid] = stp;
     }
     // the live-ins are uniform over the input: the gather pass reads them
     // from the tile's first thread with iterations only
     if (pre == 0) {
       const uint32_t nl = P->n_livein;
-      for (uint32_t q = 0; q < nl; q++) C.xs[(3 + q) * C.xn + l] = G.livein[q];
+      for (uint32_t q = 0; q < nl; q++) x0[(3 + q) * C.xn + tid] = G.livein[q];
     }
   }
   if (tid == TILE - 1) {
@@ -1037,8 +1040,10 @@ __device__ void flush_rows(RowsLds& S, const KArgs& a, uint32_t input, uint32_t 
   __syncthreads();
 }
 
-template <uint32_t SK>
-__global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
+// W32: the instantiation for batches whose rows forms are all 32 bits wide
+// (the loader's PF_ROWS32), without the 64-bit evaluation and its registers.
+template <uint32_t SK, bool W32>
+__global__ void __launch_bounds__(TILE, W32 ? 7 : 6) eval_rows_kernel(KArgs a) {
   __shared__ RowsLds S;
   const uint32_t tid = threadIdx.x;
   const uint64_t total = a.js->total_tiles[PATH_GENERIC];
@@ -1091,8 +1096,15 @@ __global__ void __launch_bounds__(TILE, 6) eval_rows_kernel(KArgs a) {
     ctx_init(C, a, in, i, T);
     C.lane0 = (t - tb) * TILE;
     C.xt = in.xt_begin + (t - tb);
-    if (G->all32) rows_thread32(S, C, *G, T, act, acc, hangs, sv);
-    else rows_thread(S, C, *G, T, act, acc, hangs, sv);
+    if (W32 || G->all32) {
+      // W32 with a form wider than 32 bits is not reached (the loader's flag
+      // and the plan kernel's walk agree): every thread of the tile would be
+      // inactive, the tile empty, and the input's status says so
+      if (!G->all32 && tid == 0) atomicOr(&a.status[i].flags, (uint32_t)CKC_ST_INTERNAL);
+      rows_thread32(S, C, *G, T, act && G->all32, acc, hangs, sv);
+    } else {
+      rows_thread(S, C, *G, T, act, acc, hangs, sv);
+    }
   }
   if (cur != 0xFFFFFFFFu) flush_rows(S, a, cur, cur_sites, acc, hangs, sv);
 }

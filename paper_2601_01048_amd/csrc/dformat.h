@@ -34,8 +34,10 @@ enum : uint8_t {
   PF_BLOCKWISE = 1,  // blocks run together: BARRIERs executed, shared memory read back
   PF_CAPTURE = 2,    // indices depend on shared memory: the first-violation index and
                      // kind come from a second evaluation pass (no one-thread replay)
-  PF_ROWS = 4        // the whole-thread part around an expanded gather loop may run
+  PF_ROWS = 4,       // the whole-thread part around an expanded gather loop may run
                      // in the rows form (no instruction dispatch; decided per input)
+  PF_ROWS32 = 8      // PF_ROWS, and every entry of that form is 32 bits wide (decided,
+                     // like PF_ROWS, from the kinds and widths alone)
 };
 
 enum : uint8_t {

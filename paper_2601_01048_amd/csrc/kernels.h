@@ -44,7 +44,8 @@ struct KArgs {
   uint32_t max_regs;        // interpreter registers (LDS rows of TILE lanes) of the job's programs
   uint32_t capture;         // this launch of the interpreter is the capture pass
   uint32_t sh_bytes;        // LDS of the tile's shared-memory instances (blockwise programs)
-  uint32_t rows_only;       // every input's program takes the rows form: the lean whole-thread kernel
+  uint32_t rows_only;       // 1: every input's program takes the rows form (the lean whole-thread
+                            // kernel); 2: and every rows form is 32 bits wide (its 32-bit instantiation)
 };
 // LDS bytes of the interpreter's register file for a job.
 // At least 8 rows: the gather evaluation of expanded bodies keeps the counter

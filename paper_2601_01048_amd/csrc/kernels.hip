@@ -101,8 +101,8 @@ KArgs with_sched(const KArgs& a, const EvalGrid& eg, uint32_t path) {
   return k;
 }
 // Kernel of evaluator `path` compiled for schedule `sk` (the whole-thread
-// pass: the rows-form kernel when `rows`).
-void* eval_fn(uint32_t path, uint32_t sk, bool rows = false) {
+// pass: the rows-form kernel when `rows` is 1, its 32-bit instantiation when 2).
+void* eval_fn(uint32_t path, uint32_t sk, uint32_t rows = 0) {
   const uint32_t s = sched_impl(sk);
   if (path == PATH_BLOCKS)
     return s == CKC_SCHED_BLOCKED ? (void*)eval_trace_kernel<CKC_SCHED_BLOCKED>
@@ -112,10 +112,14 @@ void* eval_fn(uint32_t path, uint32_t sk, bool rows = false) {
     return s == CKC_SCHED_BLOCKED ? (void*)eval_trace_lanes_kernel<CKC_SCHED_BLOCKED>
          : s == CKC_SCHED_CYCLIC  ? (void*)eval_trace_lanes_kernel<CKC_SCHED_CYCLIC>
                                   : (void*)eval_trace_lanes_kernel<CKC_SCHED_DYNAMIC>;
+  if (rows == 2)
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_rows_kernel<CKC_SCHED_BLOCKED, true>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_rows_kernel<CKC_SCHED_CYCLIC, true>
+                                  : (void*)eval_rows_kernel<CKC_SCHED_DYNAMIC, true>;
   if (rows)
-    return s == CKC_SCHED_BLOCKED ? (void*)eval_rows_kernel<CKC_SCHED_BLOCKED>
-         : s == CKC_SCHED_CYCLIC  ? (void*)eval_rows_kernel<CKC_SCHED_CYCLIC>
-                                  : (void*)eval_rows_kernel<CKC_SCHED_DYNAMIC>;
+    return s == CKC_SCHED_BLOCKED ? (void*)eval_rows_kernel<CKC_SCHED_BLOCKED, false>
+         : s == CKC_SCHED_CYCLIC  ? (void*)eval_rows_kernel<CKC_SCHED_CYCLIC, false>
+                                  : (void*)eval_rows_kernel<CKC_SCHED_DYNAMIC, false>;
   return s == CKC_SCHED_BLOCKED ? (void*)eval_generic_kernel<CKC_SCHED_BLOCKED>
        : s == CKC_SCHED_CYCLIC  ? (void*)eval_generic_kernel<CKC_SCHED_CYCLIC>
                                 : (void*)eval_generic_kernel<CKC_SCHED_DYNAMIC>;
@@ -128,7 +132,7 @@ uint32_t eval_lds(const KArgs& a, uint32_t path) {
 hipError_t launch_eval(const KArgs& a, const EvalGrid& eg, uint32_t path, hipStream_t s) {
   KArgs k = with_sched(a, eg, path);
   void* args[] = {&k};
-  const bool rows = path == PATH_GENERIC && a.rows_only;
+  const uint32_t rows = path == PATH_GENERIC ? a.rows_only : 0u;
   return hipLaunchKernel(eval_fn(path, eg.sched[path], rows), dim3(eg.n_wg[path]), dim3(TILE), args,
                          eval_lds(a, path), s);
 }
@@ -238,7 +242,7 @@ hipError_t build_job_graph(hipGraph_t g, const KArgs& a, const EvalGrid& eg, uin
     e = add_node(g, &ev[0], &scan, 1, eval_fn(PATH_BLOCKS, eg.sched[PATH_BLOCKS]), eg.n_wg[PATH_BLOCKS], TILE,
                  argsp[PATH_BLOCKS]);
   if (e == hipSuccess)
-    e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC], a.rows_only != 0),
+    e = add_node(g, &ev[1], &scan, 1, eval_fn(PATH_GENERIC, eg.sched[PATH_GENERIC], a.rows_only),
                  eg.n_wg[PATH_GENERIC], TILE, argsp[PATH_GENERIC], eval_lds(a, PATH_GENERIC));
   if (e == hipSuccess)
     e = add_node(g, &ev[2], &scan, 1, eval_fn(PATH_LANES, eg.sched[PATH_LANES]), eg.n_wg[PATH_LANES], TILE,

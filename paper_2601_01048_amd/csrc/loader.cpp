@@ -442,14 +442,16 @@ struct Analyzer {
   // comparison just before or a value; the loop's bounds forms, its step and
   // live-ins uniform; at most 16 entries.  The walk's decisions depend only on
   // kinds and widths, not on values, so they are replayed here: a program
-  // flagged PF_ROWS always passes the walk.
-  bool rows_form() const {
+  // flagged PF_ROWS always passes the walk.  *w32 (when given): every entry
+  // the walk makes, ENDIF's aside, is 32 bits wide.
+  bool rows_form(bool* w32 = nullptr) const {
     if (expand_pc < 0 || !body_gather || blockwise()) return false;
     const int body_end = ins[expand_pc].end;
     enum { UNI = 0, COORD = 1, PRED = 2, LOAD0 = 3 };  // LOAD0 + k: the k-th load
     std::vector<int> kind(n_regs, UNI), wd(n_regs, 64);
     auto fits = [&](int r, int w) { return kind[r] == UNI || (kind[r] != PRED && wd[r] >= w); };
-    int n = 0, n_load = 0, preg = -1, open_if = 0;
+    int n = 0, n_load = 0, preg = -1, open_if = 0, pw = 64;
+    bool all32 = true;
     for (int i = 0; i < n_instr; i++) {
       const Ins& I = ins[i];
       if (!I.live || (i > expand_pc && i < body_end)) continue;
@@ -485,11 +487,14 @@ struct Analyzer {
           if (op == CKC_OP_LOAD && (space_of(I.c) != CKC_SPACE_GLOBAL || n_load >= 4)) return false;
           if (n >= 16 || !fits(I.a, w)) return false;
           n++;
+          all32 &= w == 32;
           if (op == CKC_OP_LOAD) { kind[I.dst] = LOAD0 + n_load++; wd[I.dst] = 64; }
           break;
         case CKC_OP_IF:
           if (open_if++ || n >= 16 || (kind[I.a] == PRED && I.a != preg)) return false;
           n++;
+          // a comparison's guard has its width; a value's tests the width its form is exact at
+          all32 &= (kind[I.a] == PRED ? pw : kind[I.a] == UNI ? 64 : wd[I.a]) == 32;
           break;
         case CKC_OP_ENDIF:
           open_if--;
@@ -501,6 +506,7 @@ struct Analyzer {
           for (int r : livein)
             if (kind[r] != UNI) return false;
           n++;
+          all32 &= w == 32;
           i = body_end;  // continue after ENDLOOP
           break;
         default:
@@ -508,6 +514,7 @@ struct Analyzer {
             if (!fits(I.a, w) || !fits(I.b, w)) return false;
             kind[I.dst] = PRED;
             preg = I.dst;
+            pw = w;
             break;
           }
           if (op < CKC_OP_ADD || op > CKC_OP_CMPLEU || is_divrem(op)) return false;
@@ -516,6 +523,7 @@ struct Analyzer {
           break;
       }
     }
+    if (w32) *w32 = all32;
     return true;
   }
 
@@ -910,8 +918,10 @@ struct Analyzer {
         if (ins[i].live && ins[i].op == CKC_OP_SPECIAL && ins[i].a < 6) h.body_special = 1;
     h.body_gather = body_gather ? 1u : 0u;
     h.slot_spaces = slot_spaces;
-    h.pflags = (uint32_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0) |
-                         (rows_form() ? PF_ROWS : 0));
+    bool w32 = false;
+    const bool rows = rows_form(&w32);
+    h.pflags = (uint32_t)((blockwise() ? PF_BLOCKWISE : 0) | (shared_idx ? PF_CAPTURE : 0) | (rows ? PF_ROWS : 0) |
+                          (rows && w32 ? PF_ROWS32 : 0));
     for (size_t k = 0; k < livein.size(); k++) h.livein[k] = (uint8_t)livein[k];
     h.trace_cap = trace_cap;
     h.off_instr = al(sizeof(dprog));
@@ -1041,6 +1051,8 @@ int analyze_program(const void* ir, size_t ir_bytes, Loaded* out, bool no_prune)
   out->info.cls = cls;
   out->info.n_instr_live = n_live;
   out->info.n_regs_phys = A.n_phys;
+  const uint32_t pf = ((const dprog*)out->blob.data())->pflags;
+  out->info.rows_form = (pf & PF_ROWS32) ? 2u : (pf & PF_ROWS) ? 1u : 0u;
   out->load_slots = 0;
   for (int i = 0; i < A.n_instr; i++)
     if (A.ins[i].op == CKC_OP_LOAD && A.space_of(A.ins[i].c) == CKC_SPACE_GLOBAL)

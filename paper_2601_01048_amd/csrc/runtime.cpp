@@ -306,13 +306,7 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   ckc_record* recs = ext.recs;
   ckc_input_status* st = ext.st;
   uint8_t* maps = ext.maps;
-  // inputs, scalars and order: one buffer, each part at a 256-byte offset,
-  // filled by one copy
-  auto part = [](size_t bytes) { return (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255; };
-  const size_t b_in = part(sizeof(dinput) * n_inputs), b_sc = part(sizeof(int64_t) * S.hsc.size()),
-               b_ord = part(sizeof(uint32_t) * n_inputs);
-  uint8_t* up = nullptr;
-  if ((rc = take(B, &up, b_in + b_sc + b_ord)) ||
+  if ((rc = take(B, &d_in, n_inputs)) || (rc = take(B, &sc, S.hsc.size())) || (rc = take(B, &order, n_inputs)) ||
       (nx && ((rc = take(B, &xs, S.xstate_bytes)) || (rc = take(B, &xtot, nx)) || (rc = take(B, &xpb, nx)) ||
               (rc = take(B, &xpg, nx)) || (rc = take(B, &xin, nx)) || (rc = take(B, &xd, 2 * nx)) ||
               (rc = take(B, &xbsum, 2 * ((nx + 4095) / 4096))))) ||
@@ -320,20 +314,16 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
       (!st && (rc = take(B, &st, n_inputs))) || (rc = take(B, &js, 1)) || (rc = take(B, &tr, S.trace_bytes)) ||
       (dense && !maps && (rc = take(B, &maps, n_inputs * 65536))))
     return rc;
-  d_in = (dinput*)up;
-  sc = (int64_t*)(up + b_in);
-  order = (uint32_t*)(up + b_in + b_sc);
   for (auto& d : S.hin) {
     if (d.trace) d.trace = (uint64_t)(uintptr_t)(tr + (d.trace - 1));
     if (d.xstate) d.xstate = (uint64_t)(uintptr_t)(xs + (d.xstate - 1));
   }
-  S.hup.assign(b_in + b_sc + b_ord, 0);
-  std::memcpy(S.hup.data(), S.hin.data(), sizeof(dinput) * n_inputs);
-  std::memcpy(S.hup.data() + b_in, S.hsc.data(), sizeof(int64_t) * S.hsc.size());
-  std::memcpy(S.hup.data() + b_in + b_sc, S.order.data(), sizeof(uint32_t) * n_inputs);
   // pageable copies are staged before hipMemcpyAsync returns, so S may be
   // reused afterwards
-  hipError_t e = hipMemcpyAsync(up, S.hup.data(), S.hup.size(), hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(d_in, S.hin.data(), sizeof(dinput) * n_inputs, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(sc, S.hsc.data(), sizeof(int64_t) * S.hsc.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(order, S.order.data(), sizeof(uint32_t) * n_inputs, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(CKC_E_HIP, std::string("staging: ") + hipGetErrorString(e));
   a.inputs = d_in;
   a.scalars = sc;
@@ -355,12 +345,12 @@ int stage_upload(ckc_ctx c, BufSource& B, hipStream_t s, Stage& S, const ckc_lau
   a.max_regs = S.max_regs;
   a.capture = 0;
   a.sh_bytes = S.sh_bytes;
-  a.rows_only = S.all_rows && !S.hin.empty() ? 1u : 0u;
+  a.rows_only = S.all_rows && !S.hin.empty() ? (S.all_rows32 ? 2u : 1u) : 0u;
   a.sched = CKC_SCHED_DYNAMIC;
   a.chunk = O.chunk ? O.chunk : 1u;
   // PATH_BLOCKS, PATH_GENERIC, PATH_LANES; the rows-form kernel keeps 6
-  // wavefronts per SIMD
-  const uint32_t defwg[3] = {8, a.rows_only ? 6u : 4u, 2};
+  // wavefronts per SIMD, 7 in its 32-bit instantiation
+  const uint32_t defwg[3] = {8, a.rows_only == 2 ? 7u : a.rows_only ? 6u : 4u, 2};
   for (int p = 0; p < 3; p++) {
     eg.n_wg[p] = (uint32_t)c->n_cu * (O.wg_per_cu ? O.wg_per_cu : defwg[p]);
     eg.sched[p] = O.schedule ? O.schedule : (p == PATH_GENERIC ? CKC_SCHED_DYNAMIC : CKC_SCHED_BLOCKED);

@@ -54,7 +54,6 @@ struct Stage {
   std::vector<int64_t> hsc;
   std::vector<uint64_t> est;     // estimated work per input (LPT order)
   std::vector<uint32_t> order;   // tile-space position -> input (filled when uploaded)
-  std::vector<uint8_t> hup;      // inputs, scalars and order packed for one upload
   uint64_t n_xtiles = 0, xstate_bytes = 0, n_xin = 0;  // expanded loops: tiles, bytes, inputs
   uint32_t max_regs = 1;                               // interpreter register file rows
   uint64_t gen_tiles = 0;  // interpreter tiles (estimate from the launch shapes)
@@ -62,6 +61,7 @@ struct Stage {
   uint32_t sh_bytes = 0;  // LDS of the shared-memory instances of a tile (blockwise programs)
   bool capture = false;   // some input needs the capture pass
   bool all_rows = true;   // every input's program takes the rows form (PF_ROWS, exact bounds)
+  bool all_rows32 = true;  // ... and every rows form is 32 bits wide (PF_ROWS32)
   uint32_t body_kinds = 0;  // expanded loops: bit 0 some interpreted body, bit 1 some gather body
   bool any_uniform = false;  // some input's program may take a trace path (uniform, not forced generic)
 
@@ -85,7 +85,6 @@ struct Stage {
     hsc.reserve(n * MAX_SCALARS);
     est.reserve(n);
     order.reserve(n);
-    hup.reserve(n * (sizeof(dinput) + MAX_SCALARS * sizeof(int64_t) + sizeof(uint32_t)) + 3 * 256);
   }
   // Empties the stage and keeps the reserved room.
   void clear() {
@@ -93,7 +92,6 @@ struct Stage {
     hsc.clear();
     est.clear();
     order.clear();
-    hup.clear();
     n_xtiles = xstate_bytes = n_xin = 0;
     max_regs = 1;
     gen_tiles = 0;
@@ -101,6 +99,7 @@ struct Stage {
     sh_bytes = 0;
     capture = false;
     all_rows = true;
+    all_rows32 = true;
     body_kinds = 0;
     any_uniform = false;
   }
@@ -135,6 +134,7 @@ struct Stage {
       body_kinds |= h->body_gather && !d.detector ? 2u : 1u;
     }
     if (!(h->pflags & PF_ROWS) || d.detector) all_rows = false;
+    if (!(h->pflags & PF_ROWS32) || d.detector) all_rows32 = false;
     hin.push_back(d);
     est.push_back(lanes_max * (1 + h->n_accesses));
     if (!uniform) gen_tiles += (lanes_max + TILE - 1) / TILE;

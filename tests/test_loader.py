@@ -225,3 +225,29 @@ def test_slot_spaces_agree_with_oracle():
         assert ok_oracle == ok_lib, b[:32].hex()
         results.append(ok_lib)
     assert results == [True, True, True, False, False, False, False, True, True, False]
+
+
+def test_rows_form_flag():
+    """The loader's rows-form decision, which picks the whole-thread kernel:
+    the CSR program (guard, two row-pointer loads, the gather loop, y[r]) is
+    all 32-bit at width 32 (2), and its int64 form is not a rows form (0);
+    the all-32-bit program of the int32-range test is 2; the CSR shape at
+    width 32 with one 64-bit access after the loop is 1; a program with no
+    expanded loop (F1) is 0."""
+    import rowsprog as RP
+    assert ckc.analyze(W.f3_program(32))[0]["rows_form"] == 2
+    assert ckc.analyze(W.f3_program(64))[0]["rows_form"] == 0
+    assert ckc.analyze(RP.extreme_rows_program())[0]["rows_form"] == 2
+    assert ckc.analyze(W.f1_program(32))[0]["rows_form"] == 0
+    p = Program(n_scalars=1, n_slots=5)
+    r = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), 32), p.special("tid.x"), 32)
+    r64 = p.add(p.mul(p.special("bid.x"), p.special("bdim.x"), 64), p.special("tid.x"), 64)
+    with p.if_(p.cmplts(r, p.scalar(0, 32), 32)):
+        rp0 = p.load(0, r, elem=4, w=32)
+        rp1 = p.load(0, p.add(r, p.const(1, 32), 32), elem=4, w=32)
+        with p.loop(rp0, rp1, 1, w=32) as j:
+            c = p.load(1, j, elem=4, w=32)
+            p.access(2, j, elem=4, w=32)
+            p.access(3, c, elem=4, w=32)
+        p.access(4, r64, elem=4, write=True, w=64)
+    assert ckc.analyze(p.to_bytes())[0]["rows_form"] == 1
