@@ -78,3 +78,42 @@ def test_rows_32bit_extremes(ctx, cap):
         g, o = check_same(ctx, wl, mode=mode, what=f"extremes cap={cap[0]}")
         assert int(o["status"]["hang_lanes"].sum()) > 0
         assert int(o["records"]["count"].sum()) > 0
+
+
+def test_mixed_width_rows_batch(ctx):
+    """One job of two programs that both take the rows form, one all 32-bit
+    (the CSR program) and one with 64-bit entries: the job runs the general
+    rows kernel, which evaluates the first in 32-bit arithmetic and the
+    second in 64-bit.  Each workload's records, maps and status against the
+    oracle."""
+    rng = np.random.default_rng(4100)
+    ir64 = None
+    for _ in range(400):
+        ir = RP.rows_program(rng)
+        if ckc.analyze(ir)[0]["rows_form"] == 1:
+            ir64 = ir
+            break
+    assert ir64 is not None
+    wls = [W.mini("config3", w=32), RP.rows_workload(rng, ir64)]
+    assert ckc.analyze(wls[0].ir)[0]["rows_form"] == 2
+    print(f"[case] rows mixed widths inputs={[wl.n_inputs for wl in wls]}", flush=True)
+    dws = [ckc.DeviceWorkload(ctx, wl) for wl in wls]
+    try:
+        job = ctx.check([dw.desc() for dw in dws])
+        recs, mp, st = ctx.read(job)
+        n_acc = [dw.info["n_accesses"] for dw in dws]
+    finally:
+        for dw in dws:
+            dw.close()
+    r0 = i0 = 0
+    for k, (wl, na) in enumerate(zip(wls, n_acc)):
+        n = wl.n_inputs
+        o = O.check(wl, nthreads=NCPU)
+        g = recs[r0:r0 + n * na].reshape(n, na)
+        for f in ("first_key", "index", "count", "kinds", "first_kind"):
+            assert np.array_equal(g[f], o["records"][f]), (k, f)
+        assert np.array_equal(mp[i0:i0 + n], o["maps"]), k
+        for f in ("lanes", "accesses_checked", "hang_lanes", "arith_faults", "flags"):
+            assert np.array_equal(st[i0:i0 + n][f], o["status"][f]), (k, f)
+        r0 += n * na
+        i0 += n
